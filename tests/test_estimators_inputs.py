@@ -1,0 +1,126 @@
+"""The reduction formulas (oracle side), the DA closed form and the input generators."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import oracle
+from oracle import estimators as est
+from paper_2604_13929_amd import inputs
+
+
+# -- the paper's printed numbers ------------------------------------------------
+def test_dilution_identity_reproduces_printed_ratios():
+    """Sec. 2.8 (b) / Table S2: r = 0.5142 (phi = 0.70) and 0.5152 (phi = 0.90) give
+    <Phi>_3D/<Phi>_1D = 1.5153 and 1.7739 through Eq. dilution."""
+    for phi, r, ratio in [(0.70, 0.5142, 1.5153), (0.90, 0.5152, 1.7739)]:
+        pred = 1.0 / (phi * r + (1.0 - phi))
+        # r and the ratio are printed to 4 decimals: allow half a unit of each
+        tol = pred ** 2 * phi * 0.5e-4 + 0.5e-4
+        assert abs(pred - ratio) <= tol
+
+
+def test_pore_average_reproduces_printed_values():
+    """Table S2: <Phi>_pore from <Phi>_1D = phi <Phi>_pore + (1 - phi) <Phi>_3D."""
+    for phi, p3, p1, pore in [(0.70, 6.17e19, 4.07e19, 3.170e19), (0.90, 1.238e20, 6.98e19, 6.381e19)]:
+        assert (p1 - (1 - phi) * p3) / phi == pytest.approx(pore, rel=2e-3)
+
+
+def test_da_worked_values():
+    """Sec. 2.4 with Table 1 / Table S2 parameters: L_opt = 521 / 852 um and
+    <Phi>_DA = 7.73e19 / 1.266e20 photon m^-2 s^-1 at S0 = 8.27e19, L = 557 um."""
+    L, S0 = 557e-6, 8.27e19
+    assert cf.da_lopt(1548.0, 6035.0, L) == pytest.approx(521e-6, rel=1e-3)
+    assert cf.da_mean(1548.0, 6035.0, L, S0) == pytest.approx(7.73e19, rel=1e-3)
+    assert cf.da_lopt(516.0, 2012.0, L) == pytest.approx(852e-6, rel=1e-3)
+    assert cf.da_mean(516.0, 2012.0, L, S0) == pytest.approx(1.266e20, rel=1e-3)
+
+
+def test_da_parameters_table1():
+    """Table 1: D = 4.40e-5 m, kappa = 5934 m^-1, kappa L = 3.30, z_b = 110.5 um."""
+    p = cf.da_params(1548.0, 6035.0)
+    assert p["D"] == pytest.approx(4.40e-5, rel=2e-3)
+    assert p["kappa"] == pytest.approx(5934.0, rel=2e-4)
+    assert p["kappa"] * 557e-6 == pytest.approx(3.30, abs=6e-3)
+    assert p["z_b"] == pytest.approx(110.5e-6, rel=1e-3)
+
+
+def test_da_boundary_conditions():
+    """The diffuse part vanishes on both extrapolated boundaries."""
+    mua, musr, L = 0.003, 0.045, 256.0
+    p = cf.da_params(mua, musr)
+    full = lambda z: cf.da_profile(z, mua, musr, L) - np.exp(-p["mu_t"] * np.asarray(z))  # noqa: E731
+    assert abs(float(full(-p["z_b"]))) < 1e-12
+    assert abs(float(full(L + p["z_b"]))) < 1e-12
+
+
+# -- reduction on real tallies ------------------------------------------------------
+def test_identity_holds_on_tallies(mask_m1):
+    n = 20000
+    r = oracle.run(mask_m1, 0.5, 0.01, 0.7, n, seed=3)
+    e = est.estimators(r["fluence"][0], mask_m1, n)
+    assert e["porosity"] == 22938 / 32768
+    assert e["ratio"] == pytest.approx(e["identity_rhs"], rel=1e-12)
+    # decomposition of the volume average
+    por = e["porosity"]
+    assert e["phi1d"] == pytest.approx(por * e["phi_pore"] + (1 - por) * e["phi3d"], rel=1e-12)
+    assert np.nansum(e["depth"]) / mask_m1.shape[0] == pytest.approx(e["phi1d"], rel=1e-12)
+
+
+def test_rms_w_definition():
+    q = np.array([4.0, 2.0, 1.0])
+    p = q * np.array([1.1, 0.8, 1.0])
+    want = math.sqrt((4 * 0.01 + 2 * 0.04 + 0) / 7.0)
+    assert est.rms_w(p, q) == pytest.approx(want, rel=1e-14)
+
+
+# -- input generators ----------------------------------------------------------------
+def test_mask_exact_porosity_and_determinism():
+    for shape, lam, phi in [((32, 32, 32), 8.0, 0.70), ((17, 23, 9), 5.0, 0.5), ((40, 24, 16), 12.0, 0.9)]:
+        nx, ny, nz = shape
+        a = inputs.spinodal_mask(nx, ny, nz, lam, phi, seed=0)
+        b = inputs.spinodal_mask(nx, ny, nz, lam, phi, seed=0)
+        assert a.shape == (nz, ny, nx) and a.dtype == np.uint8
+        assert np.array_equal(a, b)
+        assert int(a.sum()) == int(round(phi * a.size))
+    c = inputs.spinodal_mask(32, 32, 32, 8.0, 0.70, seed=1)
+    assert not np.array_equal(c, inputs.spinodal_mask(32, 32, 32, 8.0, 0.70, seed=0))
+
+
+def test_masks_from_one_field_are_nested():
+    f = inputs.cahn_field(24, 24, 24, 8.0, seed=0)
+    m7, m9 = inputs.rank_threshold(f, 0.7), inputs.rank_threshold(f, 0.9)
+    assert np.all(m9[m7 == 1] == 1)
+
+
+def test_field_matches_direct_sum():
+    """The separable evaluation equals the plain sum of cosines."""
+    nx, ny, nz, lam = 6, 5, 4, 7.0
+    k, ph = inputs.wave_vectors(lam, 3, 256)
+    f = inputs.cahn_field(nx, ny, nz, lam, 3)
+    z, y, x = np.meshgrid(np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    direct = np.zeros_like(f)
+    for i in range(256):
+        direct += np.cos(k[i, 0] * x + k[i, 1] * y + k[i, 2] * z + ph[i])
+    assert np.allclose(f, direct, atol=1e-10)
+    assert np.allclose(np.linalg.norm(k, axis=1), 2 * math.pi / lam)
+
+
+def test_rank_threshold_tie_break():
+    f = np.array([[[1.0, 2.0, 2.0, 2.0, 0.0]]])
+    m = inputs.rank_threshold(f, 0.4)      # two pores: the tie goes to the lower index
+    assert m.reshape(-1).tolist() == [0, 1, 1, 0, 0]
+
+
+def test_batch_jobs_ranges():
+    jobs = inputs.batch_jobs(seed=0)
+    assert len(jobs) == 64
+    for j in jobs:
+        assert 64 <= j["nx"] <= 256 and j["nx"] == j["ny"] == j["nz"]
+        assert j["porosity"] in (0.5, 0.6, 0.7, 0.8, 0.9)
+        assert 0.2 <= j["mu_s"] <= 1.0 and 0.005 <= j["mu_a"] <= 0.05 and 0.5 <= j["g"] <= 0.9
+        assert 10 ** 6 <= j["n_photons"] <= 10 ** 7
+    assert jobs == inputs.batch_jobs(seed=0)
