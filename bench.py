@@ -1,0 +1,165 @@
+"""Benchmark of the photon-migration hot path on one MI355X.
+
+Workload: the 256^3 bicontinuous Cahn-wave mask at porosity 0.70 (|k| = 2 pi/24
+per voxel, mask seed 0), solid mu_s = 0.5, mu_a = 0.01, g = 0.7 per voxel,
+pores transparent, 1e8 photons per step, transport seed 20260809.  One step is
+one full pass of the hot path: mc_run (zero tallies, pack the mask, persistent
+walk) and mc_reduce (per-depth integer sums, FP64 estimators), with the mask
+already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "photon-steps/sec and photons/sec at 256^3 phi=0.70; batched vs plain"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_STEP = 8  # one int64 track-length deposit per photon-step
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--photons", type=int, default=100_000_000)
+    ap.add_argument("--cpu-photons", type=int, default=1_000_000, help="oracle sample size (first ids)")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is not built",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2604_13929_amd import inputs
+    from paper_2604_13929_amd import photonmc as pm
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    pm.load()
+    dev = torch.device("cuda:0")
+    wl = inputs.WORKLOADS["M2a"]
+    t0 = time.time()
+    mask_np = inputs.spinodal_mask(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], wl["porosity"],
+                                   seed=inputs.PAPER_MASK_SEED)
+    log(f"mask {mask_np.shape} porosity {mask_np.mean():.6f} built in {time.time() - t0:.1f}s")
+    mask = torch.from_numpy(mask_np).to(dev)
+    opt = pm.Optics(**inputs.SOLID_OPTICS)
+    seed = inputs.PAPER_TRANSPORT_SEED
+    n = args.photons
+
+    def one_step(timed):
+        res = pm.run(mask, opt, n, seed, timed=timed)
+        summ, depth, ws = pm.reduce_async(mask, res)
+        return res, summ
+
+    for i in range(args.warmup):
+        res, summ = one_step(False)
+        torch.cuda.synchronize()
+        log(f"warmup {i} done")
+    torch.cuda.synchronize()
+    walk_ms = []
+    steps_total = 0
+    t_start = time.perf_counter()
+    outs = []
+    for i in range(args.steps):
+        res, summ = one_step(True)
+        walk_ms.append(res.walk_ms)   # waits for this step's walk (events on the run's stream)
+        outs.append((res.scalars, summ))
+        log(f"step {i}: walk {res.walk_ms:.1f} ms")
+    torch.cuda.synchronize()
+    t_el = time.perf_counter() - t_start
+    ms_per_step = 1e3 * t_el / args.steps
+    sc = outs[-1][0].cpu().numpy()
+    steps_per_run = int(sc[pm.SCALARS.index("steps")])
+    for s, _ in outs:
+        assert torch.equal(s, outs[0][0]), "runs are not bitwise identical"
+    q = outs[-1][1].cpu().numpy()
+    summary = {k: float(q[i]) for i, k in enumerate(pm.SUMMARY)}
+    assert summary["closure_exact"] == 1.0
+    steps_per_s = steps_per_run * args.steps / t_el
+    photons_per_s = n * args.steps / t_el
+    walk_avg_ms = float(np.mean(walk_ms))
+    achieved_gbs = steps_per_run * BYTES_PER_STEP / (walk_avg_ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "photon-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain: 256^3 Cahn-wave mask phi=0.70 (lambda 24), mu_s 0.5 mu_a 0.01 g 0.7, "
+                               "1e8 photons per step, seed 20260809",
+                   "photons_per_step": n, "photon_steps_per_step": steps_per_run, "tallies": "int64 fixed point"},
+        "photons_per_s": photons_per_s,
+        "walk_ms_avg": walk_avg_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_walk", "algorithmic_bytes_per_step": BYTES_PER_STEP},
+        "results": {k: summary[k] for k in ("phi3d", "phi1d", "r", "ratio", "identity_rhs", "R", "T", "A",
+                                             "steps_per_photon", "Pw_void_gtL", "mean_void_path")},
+    }
+
+    if not args.no_cpu:
+        import oracle
+        from oracle import estimators as est
+        ncpu = len(os.sched_getaffinity(0))
+        m = args.cpu_photons
+        log(f"oracle: {m} photons on {ncpu} threads")
+        t1 = time.perf_counter()
+        ref = oracle.run(mask_np, opt.mu_s, opt.mu_a, opt.g, m, seed, nthreads=ncpu)
+        t_cpu = time.perf_counter() - t1
+        tot = oracle.totals(ref)
+        # the same photons on the GPU, for the error against the oracle
+        sub = pm.run(mask, opt, m, seed)
+        ssum = pm.reduce(mask, sub)
+        e = est.estimators(ref["fluence"][0], mask_np, m)
+        err = {k: abs(ssum[k] - e[k]) / abs(e[k]) for k in ("phi3d", "phi1d", "r")}
+        gsc = sub.scalar_dict()
+        for k in ("R", "T", "A"):
+            err[k] = abs(gsc[k] - tot[k]) / (m * pm.W1)
+        err["steps"] = abs(gsc["steps"] - tot["steps"]) / tot["steps"]
+        line["cpu_baseline"] = {"value": tot["steps"] / t_cpu, "unit": "photon-steps/s", "cores": ncpu,
+                                "kind": "oracle", "photons_per_s": m / t_cpu,
+                                "sample": f"first {m} photon ids of the same workload (same mask, optics, seed), "
+                                          f"FP64, {ncpu} threads, {cpu_model()}",
+                                "seconds": t_cpu}
+        line["oracle_error"] = err
+        line["gpu_over_cpu"] = steps_per_s / (tot["steps"] / t_cpu)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

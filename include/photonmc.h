@@ -1,0 +1,227 @@
+/*
+ * photonmc.h -- C ABI of the MI355X (gfx950) photon-migration library.
+ *
+ * The library simulates weighted photon packets through a voxelised binary
+ * solid/pore mask, as in "Three-dimensional photon transport in spinodal
+ * photocatalytic aerogels":
+ *   - Sec. 2.5 (Three-dimensional Monte Carlo simulation) and App. B: pores are
+ *     transparent (mu_a = mu_s = 0), solid voxels absorb and scatter; a planar
+ *     collimated source covers the z = 0 face and points along +z; the axial
+ *     faces are open; weighted photons with implicit capture and Russian
+ *     roulette; absorptance from an absorbed-energy counter and reflectance /
+ *     transmittance from escape records (Eq. RTA, Eq. closure);
+ *   - Sec. 2.6 (Fluence estimators): solid-weighted <Phi>_3D (Eq. Phi_MC3D),
+ *     volume average <Phi>_1D (Eq. Phi_MC1D), pore average and the contrast
+ *     ratio r (Eq. r_def), and the identity of Eq. dilution;
+ *   - Sec. 2.8 (c): in-pore path length of every escaping photon.
+ * Boundaries here: lateral faces periodic, refractive index 1 everywhere.
+ *
+ * Conventions
+ *   - All buffers named "device" are HIP device pointers owned by the caller.
+ *     The library never allocates device memory; scratch space is passed in
+ *     as a workspace whose size a *_workspace_bytes() query returns.
+ *   - Every entry point is asynchronous on the given HIP stream (NULL: the
+ *     legacy default stream) and returns after enqueueing, except where noted.
+ *     Pointers must stay valid until the enqueued work has finished.
+ *   - Status: 0 ok, > 0 warning, < 0 error.  No entry point throws.  On error
+ *     nothing is enqueued and mc_last_error() (thread-local) explains why.
+ *   - Weights are integers in units of 2^-31 of a launched photon (Q31).  The
+ *     fluence tally is int64, in Q31 weight x voxel length.  Integer atomics
+ *     make every result independent of scheduling: a run is bitwise
+ *     reproducible and a run split into photon ranges sums to the whole.
+ *   - Coordinates: voxel (x, y, z), x fastest; z = 0 is the illuminated face.
+ */
+#ifndef PHOTONMC_H
+#define PHOTONMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_ABI_VERSION 1
+
+/* status codes */
+#define MC_OK 0
+#define MC_WARN_LOST 1      /* some weight hit the step / path cap (scalar MC_S_LOST > 0) */
+#define MC_EINVAL (-1)      /* invalid argument */
+#define MC_EOVERFLOW (-2)   /* a voxel tally reached 2^62 (reported by the reduction) */
+#define MC_EHIP (-3)        /* a HIP runtime call failed */
+#define MC_ENOSPACE (-4)    /* workspace too small */
+
+/* flags */
+#define MC_ACCUMULATE 1     /* add to the tallies instead of zeroing them first */
+#define MC_TIMED 2          /* time the walk kernel with HIP events on the run's stream (mc_walk_elapsed_ms) */
+
+/* Scalar tally channels: int64 words in a caller-owned device array of
+ * MC_NSCALARS entries.  Weight channels are Q31.  For every run
+ * R + T + A + RR + LOST == LAUNCHED * 2^31 exactly. */
+enum {
+    MC_S_R = 0,            /* weight escaped through z = 0 (reflectance) */
+    MC_S_T,                /* weight escaped through z = Nz (transmittance) */
+    MC_S_A,                /* weight absorbed at interaction sites */
+    MC_S_RR,               /* net weight removed by Russian roulette (signed) */
+    MC_S_LOST,             /* weight of photons stopped by the step / path cap */
+    MC_S_ESC_W,            /* escaped weight, both faces */
+    MC_S_ESC_W_GTL,        /* escaped weight whose in-pore path exceeds Nz */
+    MC_S_ESC_W_VOID_PATH,  /* sum of escaped weight x in-pore path (Q31 x voxel) */
+    MC_S_ESC_N,            /* escaped photons */
+    MC_S_ESC_N_GTL,        /* escaped photons whose in-pore path exceeds Nz */
+    MC_S_STEPS,            /* photon-steps (one segment inside one voxel) */
+    MC_S_INTERACTIONS,     /* interaction events */
+    MC_S_LAUNCHED,         /* photons launched */
+    MC_NSCALARS = 16
+};
+
+/* Reduced results (doubles, caller-owned device array of MC_NSUMMARY). Phi is
+ * reported as Phi/S0, dimensionless (Eq. Phi_norm without the physical units). */
+enum {
+    MC_Q_PHI3D = 0,        /* <Phi>_3D, solid-weighted (Eq. Phi_MC3D) */
+    MC_Q_PHI1D,            /* <Phi>_1D, volume average (Eq. Phi_MC1D) */
+    MC_Q_PHI_PORE,         /* pore average */
+    MC_Q_R_CONTRAST,       /* r = <Phi>_pore / <Phi>_3D (Eq. r_def) */
+    MC_Q_POROSITY,         /* achieved porosity N_pore / N_vox */
+    MC_Q_RATIO,            /* <Phi>_3D / <Phi>_1D */
+    MC_Q_IDENTITY_RHS,     /* 1 / [phi r + (1 - phi)] (Eq. dilution) */
+    MC_Q_R,                /* reflectance R */
+    MC_Q_T,                /* transmittance T */
+    MC_Q_A,                /* absorptance A */
+    MC_Q_RR,               /* roulette balance */
+    MC_Q_LOST,             /* lost fraction */
+    MC_Q_CLOSURE_EXACT,    /* 1.0 if R+T+A+RR+LOST == LAUNCHED * 2^31 exactly, else 0.0 */
+    MC_Q_FRONT_BACK,       /* Phi(z = 0) / Phi(z = Nz - 1) */
+    MC_Q_L_OPT,            /* <Phi>_1D * Nz, in voxels */
+    MC_Q_ESC_FRAC,         /* escaped weight / launched weight */
+    MC_Q_PW_VOID_GTL,      /* escaped-weight fraction with in-pore path > Nz */
+    MC_Q_PN_VOID_GTL,      /* escaped-photon fraction with in-pore path > Nz */
+    MC_Q_MEAN_VOID_PATH,   /* escaped-weight-weighted mean in-pore path, voxels */
+    MC_Q_STEPS_PER_PHOTON,
+    MC_Q_INTERACTIONS_PER_PHOTON,
+    MC_Q_STATUS,           /* 0, or MC_EOVERFLOW if a voxel tally reached 2^62 */
+    MC_Q_N_SOLID,          /* solid voxel count */
+    MC_Q_LAUNCHED,         /* photons the tallies hold */
+    MC_NSUMMARY = 32
+};
+
+/* The volume: a binary mask in device memory, uint8[nz][ny][nx], 1 = pore,
+ * 0 = solid (the paper's m; s = 1 - m).  Limits: 1 <= nx, ny, nz <= 65535,
+ * nx*ny*nz < 2^34. */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t reserved;
+    const uint8_t *mask;
+} mc_volume;
+
+/* Optical properties of the solid phase (per voxel length); pores are 0. */
+typedef struct {
+    float mu_s;            /* scattering coefficient, >= 0 */
+    float mu_a;            /* absorption coefficient, >= 0 */
+    float g;               /* Henyey-Greenstein anisotropy, |g| < 1 */
+    float w_roulette;      /* roulette threshold as a fraction of a launched photon (1e-4) */
+    uint32_t roulette_m;   /* roulette survival 1/m, m >= 2 (10); w_roulette * m <= 1 */
+    float path_cap;        /* stop a photon after this total path, voxels (<= 0: none) */
+    int32_t source;        /* 0: collimated normal incidence (the paper's); 1: Lambertian (test) */
+    uint32_t max_steps;    /* stop a photon after this many steps (0: 2^24) */
+} mc_optics;
+
+/* Launch shape of the persistent walk.  Any value <= 0 selects the default.
+ * Results do not depend on it. */
+typedef struct {
+    int32_t block;         /* threads per workgroup: 64, 128, 256, 512 */
+    int32_t waves_per_cu;  /* resident waves per compute unit the grid is sized for */
+    int32_t chunk;         /* photons a wavefront takes from the queue at once */
+    int32_t refill;        /* refill a wavefront once this many of its lanes are idle */
+} mc_tune;
+
+/* Fill *t with the library defaults. */
+void mc_tune_default(mc_tune *t);
+
+/* Workspace (device bytes) an mc_run on this volume needs. */
+size_t mc_run_workspace_bytes(const mc_volume *vol);
+
+/*
+ * Run photons [photon_begin, photon_begin + n_photons) of the stream
+ * (seed, stream_id) through the volume (Sec. 2.5, App. B).
+ *   fluence  device int64[nz][ny][nx], Q31 weight x voxel (track-length estimator)
+ *   scalars  device int64[MC_NSCALARS]
+ *   workspace, workspace_bytes  device scratch of >= mc_run_workspace_bytes(vol)
+ *   tune     launch shape, or NULL for defaults
+ * Tallies are zeroed first unless flags has MC_ACCUMULATE.  Photon p draws
+ * Philox4x32-10 block k (k = 0 launch, k >= 1 its k-th interaction) with
+ * key (seed lo, seed hi) and counter (k, p, stream_id, 0); photon ids must be
+ * < 2^32.  Errors: MC_EINVAL for a bad volume or optics, n_photons == 0,
+ * photon_begin + n_photons > 2^32; MC_ENOSPACE; MC_EHIP.
+ */
+int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons,
+           uint64_t seed, uint32_t stream_id, int flags, int64_t *fluence, int64_t *scalars,
+           void *workspace, size_t workspace_bytes, const mc_tune *tune, void *hip_stream);
+
+/* Duration in milliseconds of the walk kernel of the last mc_run on this thread
+ * that carried MC_TIMED (two HIP events recorded on its stream around the walk
+ * launch only).  Waits for that walk to finish.  MC_EINVAL if none. */
+int mc_walk_elapsed_ms(float *ms);
+
+/* Workspace (device bytes) an mc_reduce on this volume needs. */
+size_t mc_reduce_workspace_bytes(const mc_volume *vol);
+
+/*
+ * Reduce the tallies of a run (Sec. 2.6): per-depth, per-phase integer sums of
+ * the fluence (exact, two 64-bit halves), then the estimators in FP64.
+ *   summary  device double[MC_NSUMMARY]
+ *   depth    device double[3][nz]: Phi/S0 lateral mean, solid mean, pore mean per
+ *            depth (NaN where a layer has no voxel of that phase); may be NULL
+ * The photon count is the tallies' own MC_S_LAUNCHED.  A voxel tally >= 2^62
+ * sets summary[MC_Q_STATUS] = MC_EOVERFLOW.
+ */
+int mc_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scalars, double *summary,
+              double *depth, void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* One trace record per step of a traced photon: the state at the start of the
+ * step and how the step ended. */
+typedef struct {
+    int32_t ix, iy, iz;
+    int32_t event;         /* 0/1/2 face crossing on x/y/z, 3 scatter, 4 escape z<0, 5 escape z>Nz,
+                              6 weight absorbed to zero, 7 roulette kill, 8 cap; -1 unused */
+    float fx, fy, fz;      /* offsets inside the voxel, [0, 1] */
+    float ux, uy, uz;      /* direction */
+    float d;               /* segment length */
+    uint32_t w;            /* weight, Q31 */
+    uint32_t k;            /* interactions so far */
+    uint32_t reserved;
+} mc_trace_rec;
+
+/* Per-photon outcome of a traced photon. */
+typedef struct {
+    int64_t R, T, A, RR, lost;     /* this photon's share of each weight channel */
+    uint32_t w_final, fate;        /* final weight and final event */
+    uint32_t steps, interactions;
+    float path_void, path_solid;
+} mc_photon_rec;
+
+/*
+ * Trace photons one per lane through the same walk as mc_run (no tallies):
+ *   photon_ids  device uint64[n] (each < 2^32)
+ *   recs        device mc_trace_rec[n][max_steps] (all records written; unused ones event -1)
+ *   outcome     device mc_photon_rec[n], or NULL
+ */
+int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_ids, int32_t n,
+             int32_t max_steps, uint64_t seed, uint32_t stream_id, mc_trace_rec *recs,
+             mc_photon_rec *outcome, void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Text for a status code. */
+const char *mc_strerror(int status);
+/* Message of the last error on this thread ("" if none). */
+const char *mc_last_error(void);
+/* Library ABI version (MC_ABI_VERSION). */
+int mc_abi_version(void);
+/* sizeof one of the ABI structs by name ("mc_volume", "mc_optics", "mc_tune",
+ * "mc_trace_rec", "mc_photon_rec"), 0 for an unknown name; lets a binding check
+ * its layouts. */
+size_t mc_sizeof(const char *type_name);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHOTONMC_H */

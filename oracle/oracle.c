@@ -137,6 +137,7 @@ typedef struct {
     int64_t w_final;
     uint64_t steps, interactions;
     double path_void, path_solid;
+    double min_gap;              /* smallest tie gap over the whole walk (see orc_rec) */
     int32_t fate;                /* final event */
     int32_t pad;
 } orc_photon;
@@ -212,6 +213,7 @@ static void walk(const orc_problem *P, uint64_t photon, orc_sink *S)
     double score_s = 0.0, score_a = 0.0, score_g = 0.0; /* LR scores */
     orc_photon me;
     memset(&me, 0, sizeof me);
+    me.min_gap = INFINITY;
     int fate = -1;
 
     for (;;) {
@@ -236,18 +238,20 @@ static void walk(const orc_problem *P, uint64_t photon, orc_sink *S)
         const int interact = (s_int <= d_face);
         const double d = interact ? s_int : d_face;
 
+        /* how close the step came to a different decision */
+        double gap = fabs(s_int - d_face);
+        for (int a = 0; a < 3; ++a)
+            if (a != axis && isfinite(dist[a])) {
+                double ga = fabs(dist[a] - d_face);
+                if (ga < gap) gap = ga;
+            }
+        if (gap < me.min_gap) me.min_gap = gap;
         if (S->trace && (int64_t)steps < S->max_rec) {
             orc_rec *rec = &S->trace[steps];
             rec->ix = (int32_t)ix; rec->iy = (int32_t)iy; rec->iz = (int32_t)iz;
             rec->fx = fx; rec->fy = fy; rec->fz = fz;
             rec->ux = ux; rec->uy = uy; rec->uz = uz;
             rec->w = w; rec->k = k; rec->d = d;
-            double gap = fabs(s_int - d_face);
-            for (int a = 0; a < 3; ++a)
-                if (a != axis && isfinite(dist[a])) {
-                    double ga = fabs(dist[a] - d_face);
-                    if (ga < gap) gap = ga;
-                }
             rec->tie_gap = gap;
             rec->event = -1;
         }

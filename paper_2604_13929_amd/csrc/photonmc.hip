@@ -1,0 +1,674 @@
+// photonmc.hip -- MI355X (gfx950) kernels and the C ABI declared in photonmc.h.
+//
+// Kernels
+//   k_fill_i64     zero the tallies and the queue counter (a fill kernel, so the
+//                  sequence stays capturable in a HIP graph without memset nodes)
+//   k_pack         uint8 mask -> 4x4x4 bit bricks (one uint64 per brick)
+//   k_walk         persistent photon walk: one photon per lane, wavefronts take
+//                  photon ids from a global queue in chunks and refill idle lanes
+//   k_trace        one traced photon per lane, same step function, records
+//   k_reduce       per-depth, per-phase exact integer sums of the fluence tally
+//   k_finalize     the estimators in FP64 from those sums and the scalar channels
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "photonmc.h"
+#include "walk.hpp"
+
+using namespace pmc;
+
+// ---------------------------------------------------------------------------
+// Error reporting
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512] = "";
+
+static int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int status, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(MC_EHIP, "%s: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i64(int64_t *__restrict__ p, uint64_t n, int64_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// One thread per 4x4x4 brick; bit (dz*16 + dy*4 + dx) is 1 for a pore voxel.
+// Voxels outside the volume (ragged edges) stay 0 and are never addressed.
+__global__ void k_pack(const uint8_t *__restrict__ mask, int32_t nx, int32_t ny, int32_t nz, int32_t nxb,
+                       int32_t nyb, uint64_t nbricks, uint64_t *__restrict__ bricks)
+{
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbricks) return;
+    const int32_t bx = (int32_t)(b % (uint64_t)nxb);
+    const int32_t by = (int32_t)((b / (uint64_t)nxb) % (uint64_t)nyb);
+    const int32_t bz = (int32_t)(b / ((uint64_t)nxb * (uint64_t)nyb));
+    uint64_t bits = 0;
+    for (int dz = 0; dz < 4; ++dz) {
+        const int32_t z = bz * 4 + dz;
+        if (z >= nz) break;
+        for (int dy = 0; dy < 4; ++dy) {
+            const int32_t y = by * 4 + dy;
+            if (y >= ny) break;
+            const uint8_t *row = mask + ((uint64_t)z * ny + y) * (uint64_t)nx;
+            for (int dx = 0; dx < 4; ++dx) {
+                const int32_t x = bx * 4 + dx;
+                if (x >= nx) break;
+                if (row[x]) bits |= 1ull << ((dz << 4) | (dy << 2) | dx);
+            }
+        }
+    }
+    bricks[b] = bits;
+}
+
+// ---------------------------------------------------------------------------
+// Sinks: where a step's side effects go
+// ---------------------------------------------------------------------------
+struct TallySink {
+    __device__ __forceinline__ void segment(const Photon &, const Job &, float, bool) {}
+    __device__ __forceinline__ void flush(const Job &J, uint64_t v, uint64_t acc)
+    {
+        if (acc != 0ull)
+            __hip_atomic_fetch_add((unsigned long long *)(J.fluence + v), (unsigned long long)acc,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+// Terminal outcome of one photon into the block's channel accumulators (LDS).
+__device__ __forceinline__ void account(unsigned long long *acc, const Photon &p, int32_t ev, int32_t nz)
+{
+    if (ev == EV_ESC_R || ev == EV_ESC_T) {
+        atomicAdd(&acc[ev == EV_ESC_R ? MC_S_R : MC_S_T], (unsigned long long)p.w);
+        atomicAdd(&acc[MC_S_ESC_W], (unsigned long long)p.w);
+        atomicAdd(&acc[MC_S_ESC_N], 1ull);
+        if (p.l_void > (float)nz) {
+            atomicAdd(&acc[MC_S_ESC_W_GTL], (unsigned long long)p.w);
+            atomicAdd(&acc[MC_S_ESC_N_GTL], 1ull);
+        }
+        atomicAdd(&acc[MC_S_ESC_W_VOID_PATH], __float2ull_rn((float)p.w * p.l_void));
+    } else if (ev == EV_LOST) {
+        atomicAdd(&acc[MC_S_LOST], (unsigned long long)p.w);
+    }
+    if (p.absorbed) atomicAdd(&acc[MC_S_A], (unsigned long long)p.absorbed);
+    if (p.rr) atomicAdd(&acc[MC_S_RR], (unsigned long long)p.rr);  // two's complement: signed sum
+    atomicAdd(&acc[MC_S_STEPS], (unsigned long long)p.steps);
+    atomicAdd(&acc[MC_S_INTERACTIONS], (unsigned long long)p.k);
+    atomicAdd(&acc[MC_S_LAUNCHED], 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent walk
+// ---------------------------------------------------------------------------
+// Each wavefront owns a private range [q_next, q_end) of queue positions and
+// takes `chunk` more with one atomic when it runs dry.  Idle lanes are refilled
+// together once at least `refill` of them are idle (or all are), so launches
+// run converged.  A wavefront exits when the queue is exhausted, its range is
+// empty and none of its lanes is alive; every photon terminates (escape,
+// weight 0, roulette, or the step cap), so every wavefront exits.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long *__restrict__ queue, int32_t chunk,
+                                                int32_t refill)
+{
+    __shared__ unsigned long long acc[MC_NSCALARS];
+    if (threadIdx.x < MC_NSCALARS) acc[threadIdx.x] = 0ull;
+    __syncthreads();
+
+    TallySink sink;
+    Photon p;
+    bool alive = false;
+    uint64_t q_next = 0, q_end = 0;
+    bool exhausted = false;
+    const uint64_t total = J.n_photons;
+    const uint32_t lane = __lane_id();
+
+    for (;;) {
+        const uint64_t idle = __ballot(!alive);
+        if (idle != 0ull) {
+            const int32_t nidle = __popcll(idle);
+            if (!exhausted && (nidle >= refill || idle == ~0ull)) {
+                if (q_next >= q_end) {
+                    unsigned long long base = 0ull;
+                    if (lane == 0) base = atomicAdd(queue, (unsigned long long)chunk);
+                    base = __shfl(base, 0);
+                    if (base >= total) {
+                        exhausted = true;
+                    } else {
+                        q_next = base;
+                        q_end = base + (uint64_t)chunk < total ? base + (uint64_t)chunk : total;
+                    }
+                }
+                if (q_next < q_end) {
+                    const uint64_t avail = q_end - q_next;
+                    const uint32_t rank = (uint32_t)__popcll(idle & __lanemask_lt());
+                    if (!alive && rank < avail) {
+                        launch(p, J, (uint32_t)(J.photon_begin + q_next + rank));
+                        alive = true;
+                    }
+                    q_next += (uint64_t)nidle < avail ? (uint64_t)nidle : avail;
+                }
+            }
+            if (exhausted && q_next >= q_end && !__any(alive)) break;
+        }
+        if (alive) {
+            const int32_t ev = step(p, J, sink);
+            if (ev >= EV_FIRST_TERMINAL) {
+                account(acc, p, ev, J.nz);
+                alive = false;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < MC_NSCALARS) {
+        const unsigned long long v = acc[threadIdx.x];
+        if (v) atomicAdd((unsigned long long *)&J.scalars[threadIdx.x], v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Trace
+// ---------------------------------------------------------------------------
+struct TraceSink {
+    mc_trace_rec *rec;
+    int32_t max_rec, n;
+    __device__ __forceinline__ void segment(const Photon &p, const Job &, float d, bool)
+    {
+        if (n < max_rec) {
+            mc_trace_rec &r = rec[n];
+            r.ix = p.ix; r.iy = p.iy; r.iz = p.iz; r.event = -1;
+            r.fx = p.fx; r.fy = p.fy; r.fz = p.fz;
+            r.ux = p.ux; r.uy = p.uy; r.uz = p.uz;
+            r.d = d; r.w = p.w; r.k = p.k; r.reserved = 0u;
+        }
+    }
+    __device__ __forceinline__ void flush(const Job &, uint64_t, uint64_t) {}
+    __device__ __forceinline__ void post(int32_t ev)
+    {
+        if (n < max_rec) rec[n].event = ev;
+        ++n;
+    }
+};
+
+__global__ void k_trace(const Job J, const uint64_t *__restrict__ ids, int32_t n, int32_t max_rec,
+                        mc_trace_rec *__restrict__ recs, mc_photon_rec *__restrict__ out)
+{
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    TraceSink sink{recs + (int64_t)i * max_rec, max_rec, 0};
+    for (int32_t j = 0; j < max_rec; ++j) sink.rec[j].event = -1;
+    Photon p;
+    launch(p, J, (uint32_t)ids[i]);
+    int32_t ev;
+    for (;;) {
+        ev = step(p, J, sink);
+        sink.post(ev);
+        if (ev >= EV_FIRST_TERMINAL) break;
+    }
+    if (out) {
+        mc_photon_rec o;
+        o.R = ev == EV_ESC_R ? (int64_t)p.w : 0;
+        o.T = ev == EV_ESC_T ? (int64_t)p.w : 0;
+        o.A = (int64_t)p.absorbed;
+        o.RR = p.rr;
+        o.lost = ev == EV_LOST ? (int64_t)p.w : 0;
+        o.w_final = p.w;
+        o.fate = (uint32_t)ev;
+        o.steps = p.steps;
+        o.interactions = p.k;
+        o.path_void = p.l_void;
+        o.path_solid = p.l_tot - p.l_void;
+        out[i] = o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduction
+// ---------------------------------------------------------------------------
+// bins[z][8]: solid (hi, lo), pore (hi, lo), n_solid, n_pore, max, unused.
+// A voxel value v >= 0 is split as v = hi * 2^32 + lo; the halves are summed
+// separately, so no partial sum overflows and the totals are exact.
+constexpr int kBinW = 8;
+constexpr int kReduceBlock = 256;
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kReduceBlock) void k_reduce(const int64_t *__restrict__ F, const uint8_t *__restrict__ mask,
+                                                         uint64_t layer, uint64_t per_block,
+                                                         unsigned long long *__restrict__ bins)
+{
+    const uint64_t z = blockIdx.y;
+    const uint64_t begin = (uint64_t)blockIdx.x * per_block;
+    const uint64_t end = begin + per_block < layer ? begin + per_block : layer;
+    const int64_t *f = F + z * layer;
+    const uint8_t *m = mask + z * layer;
+    unsigned long long s_hi = 0, s_lo = 0, p_hi = 0, p_lo = 0, n_s = 0, n_p = 0, mx = 0;
+    for (uint64_t i = begin + threadIdx.x; i < end; i += kReduceBlock) {
+        const unsigned long long v = (unsigned long long)f[i];
+        const unsigned long long hi = v >> 32, lo = v & 0xFFFFFFFFull;
+        if (m[i]) { p_hi += hi; p_lo += lo; ++n_p; }
+        else      { s_hi += hi; s_lo += lo; ++n_s; }
+        mx = v > mx ? v : mx;
+    }
+    __shared__ unsigned long long part[kReduceBlock / 64][7];
+    const int w = threadIdx.x >> 6;
+    unsigned long long vals[7] = {s_hi, s_lo, p_hi, p_lo, n_s, n_p, mx};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) vals[c] = wave_sum(vals[c]);
+    vals[6] = wave_max(vals[6]);
+    if (__lane_id() == 0)
+        for (int c = 0; c < 7; ++c) part[w][c] = vals[c];
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kReduceBlock / 64; ++i)
+            t = threadIdx.x == 6 ? (part[i][6] > t ? part[i][6] : t) : t + part[i][threadIdx.x];
+        unsigned long long *dst = bins + z * kBinW + threadIdx.x;
+        if (threadIdx.x == 6) atomicMax(dst, t);
+        else if (t) atomicAdd(dst, t);
+    }
+}
+
+__device__ __forceinline__ double join(unsigned long long hi, unsigned long long lo)
+{
+    return (double)hi * 4294967296.0 + (double)lo;
+}
+
+// One block: per-depth profiles in parallel, totals by thread 0 in z order.
+__global__ void k_finalize(const unsigned long long *__restrict__ bins, const int64_t *__restrict__ S, int32_t nx,
+                           int32_t ny, int32_t nz, double *__restrict__ q, double *__restrict__ depth)
+{
+    const double n_ph = (double)S[MC_S_LAUNCHED];
+    const double launched_w = n_ph * 2147483648.0;
+    const double face = (double)nx * (double)ny;
+    const double norm = face / launched_w;  // Phi/S0 per unit of F
+    const double nan = __builtin_nan("");
+    if (depth) {
+        for (int32_t z = threadIdx.x; z < nz; z += blockDim.x) {
+            const unsigned long long *b = bins + (uint64_t)z * kBinW;
+            const double fs = join(b[0], b[1]), fp = join(b[2], b[3]);
+            depth[z] = (fs + fp) * norm / face;
+            depth[nz + z] = b[4] ? fs * norm / (double)b[4] : nan;
+            depth[2 * nz + z] = b[5] ? fp * norm / (double)b[5] : nan;
+        }
+    }
+    if (threadIdx.x != 0) return;
+    unsigned long long s_hi = 0, s_lo = 0, p_hi = 0, p_lo = 0, n_s = 0, n_p = 0, mx = 0;
+    for (int32_t z = 0; z < nz; ++z) {
+        const unsigned long long *b = bins + (uint64_t)z * kBinW;
+        s_hi += b[0]; s_lo += b[1]; p_hi += b[2]; p_lo += b[3]; n_s += b[4]; n_p += b[5];
+        mx = b[6] > mx ? b[6] : mx;
+    }
+    const double fs = join(s_hi, s_lo), fp = join(p_hi, p_lo);
+    const double nvox = (double)(n_s + n_p);
+    for (int i = 0; i < MC_NSUMMARY; ++i) q[i] = 0.0;
+    q[MC_Q_PHI3D] = n_s ? fs * norm / (double)n_s : nan;
+    q[MC_Q_PHI1D] = (fs + fp) * norm / nvox;
+    q[MC_Q_PHI_PORE] = n_p ? fp * norm / (double)n_p : nan;
+    q[MC_Q_R_CONTRAST] = q[MC_Q_PHI_PORE] / q[MC_Q_PHI3D];
+    q[MC_Q_POROSITY] = (double)n_p / nvox;
+    q[MC_Q_RATIO] = q[MC_Q_PHI3D] / q[MC_Q_PHI1D];
+    q[MC_Q_IDENTITY_RHS] = 1.0 / (q[MC_Q_POROSITY] * q[MC_Q_R_CONTRAST] + (1.0 - q[MC_Q_POROSITY]));
+    q[MC_Q_R] = (double)S[MC_S_R] / launched_w;
+    q[MC_Q_T] = (double)S[MC_S_T] / launched_w;
+    q[MC_Q_A] = (double)S[MC_S_A] / launched_w;
+    q[MC_Q_RR] = (double)S[MC_S_RR] / launched_w;
+    q[MC_Q_LOST] = (double)S[MC_S_LOST] / launched_w;
+    const int64_t sum = S[MC_S_R] + S[MC_S_T] + S[MC_S_A] + S[MC_S_RR] + S[MC_S_LOST];
+    q[MC_Q_CLOSURE_EXACT] = (sum == S[MC_S_LAUNCHED] * (int64_t)2147483648ll) ? 1.0 : 0.0;
+    const unsigned long long *b0 = bins, *bl = bins + (uint64_t)(nz - 1) * kBinW;
+    const double f0 = join(b0[0], b0[1]) + join(b0[2], b0[3]);
+    const double fl = join(bl[0], bl[1]) + join(bl[2], bl[3]);
+    q[MC_Q_FRONT_BACK] = fl > 0.0 ? f0 / fl : __builtin_inf();
+    q[MC_Q_L_OPT] = q[MC_Q_PHI1D] * (double)nz;
+    q[MC_Q_ESC_FRAC] = (double)S[MC_S_ESC_W] / launched_w;
+    q[MC_Q_PW_VOID_GTL] = S[MC_S_ESC_W] ? (double)S[MC_S_ESC_W_GTL] / (double)S[MC_S_ESC_W] : nan;
+    q[MC_Q_PN_VOID_GTL] = S[MC_S_ESC_N] ? (double)S[MC_S_ESC_N_GTL] / (double)S[MC_S_ESC_N] : nan;
+    q[MC_Q_MEAN_VOID_PATH] = S[MC_S_ESC_W] ? (double)S[MC_S_ESC_W_VOID_PATH] / (double)S[MC_S_ESC_W] : nan;
+    q[MC_Q_STEPS_PER_PHOTON] = (double)S[MC_S_STEPS] / n_ph;
+    q[MC_Q_INTERACTIONS_PER_PHOTON] = (double)S[MC_S_INTERACTIONS] / n_ph;
+    q[MC_Q_STATUS] = mx >= (1ull << 62) ? (double)MC_EOVERFLOW : 0.0;
+    q[MC_Q_N_SOLID] = (double)n_s;
+    q[MC_Q_LAUNCHED] = n_ph;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kHeaderBytes = 256;  // queue counter(s) at the start of a run workspace
+
+struct Dims {
+    int32_t nxb, nyb, nzb;
+    uint64_t nbricks, nvox;
+};
+
+Dims dims_of(const mc_volume *v)
+{
+    Dims d;
+    d.nxb = (v->nx + 3) / 4;
+    d.nyb = (v->ny + 3) / 4;
+    d.nzb = (v->nz + 3) / 4;
+    d.nbricks = (uint64_t)d.nxb * d.nyb * d.nzb;
+    d.nvox = (uint64_t)v->nx * v->ny * v->nz;
+    return d;
+}
+
+int check_volume(const mc_volume *v)
+{
+    if (!v) return fail(MC_EINVAL, "volume is NULL");
+    if (v->nx < 1 || v->ny < 1 || v->nz < 1 || v->nx > 65535 || v->ny > 65535 || v->nz > 65535)
+        return fail(MC_EINVAL, "volume dimensions %d x %d x %d outside [1, 65535]", v->nx, v->ny, v->nz);
+    if ((uint64_t)v->nx * v->ny * v->nz >= (1ull << 34))
+        return fail(MC_EINVAL, "volume has 2^34 or more voxels");
+    if (!v->mask) return fail(MC_EINVAL, "mask pointer is NULL");
+    return MC_OK;
+}
+
+int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons, uint64_t seed,
+             uint32_t stream_id, Job *J)
+{
+    int rc = check_volume(vol);
+    if (rc) return rc;
+    if (!opt) return fail(MC_EINVAL, "optics is NULL");
+    if (!(opt->mu_s >= 0.0f) || !(opt->mu_a >= 0.0f) || !isfinite(opt->mu_s) || !isfinite(opt->mu_a))
+        return fail(MC_EINVAL, "mu_s and mu_a must be finite and >= 0");
+    if (!(fabsf(opt->g) < 1.0f)) return fail(MC_EINVAL, "|g| must be < 1");
+    if (opt->roulette_m < 2) return fail(MC_EINVAL, "roulette_m must be >= 2");
+    if (!(opt->w_roulette >= 0.0f) || !(opt->w_roulette <= 1.0f)) return fail(MC_EINVAL, "w_roulette must be in [0, 1]");
+    const double w_th = floor((double)opt->w_roulette * 2147483648.0);
+    if (w_th * (double)opt->roulette_m > 2147483648.0)
+        return fail(MC_EINVAL, "w_roulette * roulette_m must not exceed 1 (a survivor would outweigh a launched photon)");
+    if (opt->source != 0 && opt->source != 1) return fail(MC_EINVAL, "source must be 0 or 1");
+    if (n_photons == 0) return fail(MC_EINVAL, "n_photons is 0");
+    if (photon_begin >= (1ull << 32) || n_photons > (1ull << 32) - photon_begin)
+        return fail(MC_EINVAL, "photon ids must be < 2^32");
+    memset(J, 0, sizeof *J);
+    const Dims d = dims_of(vol);
+    J->nx = vol->nx;
+    J->ny = vol->ny;
+    J->nz = vol->nz;
+    J->nxb = d.nxb;
+    J->nyb = d.nyb;
+    const double mu_s = opt->mu_s, mu_a = opt->mu_a, mu_t = mu_s + mu_a;
+    J->mu_t = opt->mu_s + opt->mu_a;
+    J->g = opt->g;
+    J->path_cap = opt->path_cap > 0.0f ? opt->path_cap : kInf;
+    J->s_q = mu_t > 0.0 ? (uint64_t)llround(mu_s / mu_t * 4294967296.0) : 0ull;
+    J->w_th = (uint32_t)w_th;
+    J->t_m = (uint32_t)llround(16777216.0 / (double)opt->roulette_m);
+    J->m = opt->roulette_m;
+    J->key0 = (uint32_t)seed;
+    J->key1 = (uint32_t)(seed >> 32);
+    J->stream_id = stream_id;
+    J->source = opt->source;
+    J->max_steps = opt->max_steps ? opt->max_steps : (1u << 24);
+    J->photon_begin = photon_begin;
+    J->n_photons = n_photons;
+    J->queue_begin = 0;
+    return MC_OK;
+}
+
+struct DeviceInfo {
+    int cus = 0;
+};
+
+int device_info(DeviceInfo *out)
+{
+    static std::mutex mu;
+    static DeviceInfo cache[64];
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if (dev < 0 || dev >= 64) return fail(MC_EHIP, "device index %d out of range", dev);
+    if (cache[dev].cus == 0) HIP_TRY(hipDeviceGetAttribute(&cache[dev].cus, hipDeviceAttributeMultiprocessorCount, dev));
+    *out = cache[dev];
+    return MC_OK;
+}
+
+mc_tune resolve_tune(const mc_tune *t)
+{
+    mc_tune r;
+    mc_tune_default(&r);
+    if (t) {
+        if (t->block > 0) r.block = t->block;
+        if (t->waves_per_cu > 0) r.waves_per_cu = t->waves_per_cu;
+        if (t->chunk > 0) r.chunk = t->chunk;
+        if (t->refill > 0) r.refill = t->refill;
+    }
+    return r;
+}
+
+int fill(int64_t *p, uint64_t n, hipStream_t s)
+{
+    if (n == 0) return MC_OK;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)blocks), dim3(256), 0, s, p, n, (int64_t)0);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+int pack(const mc_volume *vol, uint64_t *bricks, hipStream_t s)
+{
+    const Dims d = dims_of(vol);
+    const uint64_t blocks = (d.nbricks + 255) / 256;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)blocks), dim3(256), 0, s, vol->mask, vol->nx, vol->ny, vol->nz, d.nxb,
+                       d.nyb, d.nbricks, bricks);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+struct Timing {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool armed = false;
+};
+thread_local Timing g_timing;
+
+int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s, bool timed)
+{
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc) return rc;
+    const int waves_per_block = t.block / 64;
+    const int blocks = std::max(1, di.cus * t.waves_per_cu / waves_per_block);
+    if (timed) {
+        if (!g_timing.start) {
+            HIP_TRY(hipEventCreate(&g_timing.start));
+            HIP_TRY(hipEventCreate(&g_timing.stop));
+        }
+        HIP_TRY(hipEventRecord(g_timing.start, s));
+    }
+    switch (t.block) {
+    case 64: hipLaunchKernelGGL(k_walk<64>, dim3(blocks), dim3(64), 0, s, J, queue, t.chunk, t.refill); break;
+    case 128: hipLaunchKernelGGL(k_walk<128>, dim3(blocks), dim3(128), 0, s, J, queue, t.chunk, t.refill); break;
+    case 256: hipLaunchKernelGGL(k_walk<256>, dim3(blocks), dim3(256), 0, s, J, queue, t.chunk, t.refill); break;
+    case 512: hipLaunchKernelGGL(k_walk<512>, dim3(blocks), dim3(512), 0, s, J, queue, t.chunk, t.refill); break;
+    default: return fail(MC_EINVAL, "block size %d not one of 64, 128, 256, 512", t.block);
+    }
+    HIP_TRY(hipGetLastError());
+    if (timed) {
+        HIP_TRY(hipEventRecord(g_timing.stop, s));
+        g_timing.armed = true;
+    }
+    return MC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int mc_abi_version(void) { return MC_ABI_VERSION; }
+
+size_t mc_sizeof(const char *type_name)
+{
+    if (!type_name) return 0;
+    if (!strcmp(type_name, "mc_volume")) return sizeof(mc_volume);
+    if (!strcmp(type_name, "mc_optics")) return sizeof(mc_optics);
+    if (!strcmp(type_name, "mc_tune")) return sizeof(mc_tune);
+    if (!strcmp(type_name, "mc_trace_rec")) return sizeof(mc_trace_rec);
+    if (!strcmp(type_name, "mc_photon_rec")) return sizeof(mc_photon_rec);
+    return 0;
+}
+
+const char *mc_last_error(void) { return g_err; }
+
+const char *mc_strerror(int status)
+{
+    switch (status) {
+    case MC_OK: return "ok";
+    case MC_WARN_LOST: return "warning: weight stopped by the step or path cap";
+    case MC_EINVAL: return "invalid argument";
+    case MC_EOVERFLOW: return "a voxel tally reached 2^62";
+    case MC_EHIP: return "HIP runtime error";
+    case MC_ENOSPACE: return "workspace too small";
+    default: return "unknown status";
+    }
+}
+
+void mc_tune_default(mc_tune *t)
+{
+    if (!t) return;
+    t->block = 256;
+    t->waves_per_cu = 16;
+    t->chunk = 256;
+    t->refill = 16;
+}
+
+size_t mc_run_workspace_bytes(const mc_volume *vol)
+{
+    if (check_volume(vol)) return 0;
+    return kHeaderBytes + dims_of(vol).nbricks * sizeof(uint64_t);
+}
+
+int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons, uint64_t seed,
+           uint32_t stream_id, int flags, int64_t *fluence, int64_t *scalars, void *workspace, size_t workspace_bytes,
+           const mc_tune *tune, void *hip_stream)
+{
+    g_err[0] = 0;
+    Job J;
+    int rc = make_job(vol, opt, photon_begin, n_photons, seed, stream_id, &J);
+    if (rc) return rc;
+    if (!fluence || !scalars || !workspace) return fail(MC_EINVAL, "fluence, scalars and workspace must be non-NULL");
+    const size_t need = mc_run_workspace_bytes(vol);
+    if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    const mc_tune t = resolve_tune(tune);
+    if (t.block != 64 && t.block != 128 && t.block != 256 && t.block != 512)
+        return fail(MC_EINVAL, "tune: block size %d not one of 64, 128, 256, 512", t.block);
+    if (t.chunk < 1 || t.refill < 1 || t.refill > 64 || t.waves_per_cu < 1 || t.waves_per_cu > 32)
+        return fail(MC_EINVAL, "tune out of range (chunk >= 1, refill in [1, 64], waves_per_cu in [1, 32])");
+    hipStream_t s = (hipStream_t)hip_stream;
+    unsigned long long *queue = (unsigned long long *)workspace;
+    uint64_t *bricks = (uint64_t *)((char *)workspace + kHeaderBytes);
+    J.bricks = bricks;
+    J.fluence = fluence;
+    J.scalars = scalars;
+    if (!(flags & MC_ACCUMULATE)) {
+        if ((rc = fill(fluence, dims_of(vol).nvox, s))) return rc;
+        if ((rc = fill(scalars, MC_NSCALARS, s))) return rc;
+    }
+    if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
+    if ((rc = pack(vol, bricks, s))) return rc;
+    return launch_walk(J, queue, t, s, (flags & MC_TIMED) != 0);
+}
+
+int mc_walk_elapsed_ms(float *ms)
+{
+    if (!ms) return fail(MC_EINVAL, "ms is NULL");
+    if (!g_timing.armed) return fail(MC_EINVAL, "no timed walk has been enqueued on this thread");
+    HIP_TRY(hipEventSynchronize(g_timing.stop));
+    HIP_TRY(hipEventElapsedTime(ms, g_timing.start, g_timing.stop));
+    return MC_OK;
+}
+
+size_t mc_reduce_workspace_bytes(const mc_volume *vol)
+{
+    if (check_volume(vol)) return 0;
+    return (size_t)vol->nz * kBinW * sizeof(uint64_t);
+}
+
+int mc_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scalars, double *summary, double *depth,
+              void *workspace, size_t workspace_bytes, void *hip_stream)
+{
+    g_err[0] = 0;
+    int rc = check_volume(vol);
+    if (rc) return rc;
+    if (!fluence || !scalars || !summary || !workspace) return fail(MC_EINVAL, "NULL argument");
+    const size_t need = mc_reduce_workspace_bytes(vol);
+    if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    hipStream_t s = (hipStream_t)hip_stream;
+    unsigned long long *bins = (unsigned long long *)workspace;
+    if ((rc = fill((int64_t *)bins, (uint64_t)vol->nz * kBinW, s))) return rc;
+    const uint64_t layer = (uint64_t)vol->nx * vol->ny;
+    const uint64_t per_block = 8192;
+    const uint64_t gx = (layer + per_block - 1) / per_block;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)gx, (unsigned)vol->nz), dim3(kReduceBlock), 0, s, fluence, vol->mask,
+                       layer, per_block, bins);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, bins, scalars, vol->nx, vol->ny, vol->nz, summary, depth);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_ids, int32_t n, int32_t max_steps,
+             uint64_t seed, uint32_t stream_id, mc_trace_rec *recs, mc_photon_rec *outcome, void *workspace,
+             size_t workspace_bytes, void *hip_stream)
+{
+    g_err[0] = 0;
+    Job J;
+    int rc = make_job(vol, opt, 0, 1, seed, stream_id, &J);
+    if (rc) return rc;
+    if (n < 0 || max_steps < 0) return fail(MC_EINVAL, "n and max_steps must be >= 0");
+    if (n == 0) return MC_OK;
+    if (!photon_ids || !workspace || (max_steps > 0 && !recs)) return fail(MC_EINVAL, "NULL argument");
+    const size_t need = mc_run_workspace_bytes(vol);
+    if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    hipStream_t s = (hipStream_t)hip_stream;
+    uint64_t *bricks = (uint64_t *)((char *)workspace + kHeaderBytes);
+    J.bricks = bricks;
+    if ((rc = pack(vol, bricks, s))) return rc;
+    hipLaunchKernelGGL(k_trace, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, J, photon_ids, n, max_steps, recs,
+                       outcome);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+}  // extern "C"

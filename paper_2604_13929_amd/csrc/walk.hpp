@@ -1,0 +1,277 @@
+// Photon state and one step of the voxel walk, device side (gfx950, wave64).
+//
+// Physics (paper, Sec. 2.5 and App. B): transparent pores, absorbing and
+// scattering solid, planar collimated source on z = 0 along +z, open axial
+// faces, weighted photons with implicit capture and Russian roulette.  The
+// readings fixed here where the paper is silent: periodic lateral faces,
+// index 1 everywhere, track-length fluence per voxel, absorption at
+// interaction sites on an integer Q31 weight, HG deflection by inverse CDF,
+// the MCML direction update (Wang, Jacques & Zheng 1995), one Philox block per
+// event, the face axis taken as the first minimum in x, y, z order, an
+// interaction winning a tie against a face, in-voxel offsets clamped to [0,1].
+//
+// Position is an integer voxel index plus an FP32 offset in [0,1] per axis,
+// so FP32 keeps ~1e-7 voxel resolution anywhere in the volume.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "philox.hpp"
+
+namespace pmc {
+
+constexpr float kInf = __builtin_inff();
+constexpr uint32_t kW1 = 0x80000000u;  // launched weight, 2^31
+
+// events (same codes as the trace records of the public header)
+enum : int32_t {
+    EV_FACE_X = 0, EV_FACE_Y = 1, EV_FACE_Z = 2, EV_SCATTER = 3,
+    EV_ESC_R = 4, EV_ESC_T = 5, EV_DEAD_ABSORB = 6, EV_DEAD_ROULETTE = 7, EV_LOST = 8,
+    EV_FIRST_TERMINAL = 4
+};
+
+// Per-job constants.  Everything integer that decides an outcome is computed
+// on the host in FP64 (survival factor, roulette threshold and odds).
+struct Job {
+    const uint64_t *bricks;   // 4x4x4 bit bricks, 1 = pore
+    int64_t *fluence;         // [nz][ny][nx]
+    int64_t *scalars;         // [MC_NSCALARS]
+    int32_t nx, ny, nz;
+    int32_t nxb, nyb;         // bricks along x and y
+    float mu_t;               // mu_s + mu_a of the solid
+    float g;
+    float path_cap;           // +inf when off
+    uint64_t s_q;             // round(mu_s / mu_t * 2^32), <= 2^32
+    uint32_t w_th;            // roulette threshold (Q31)
+    uint32_t t_m;             // survive roulette iff (r >> 8) < t_m
+    uint32_t m;               // roulette multiplier
+    uint32_t key0, key1;      // Philox key = seed
+    uint32_t stream_id;
+    int32_t source;           // 0 collimated, 1 Lambertian
+    uint32_t max_steps;
+    uint64_t photon_begin;    // first photon id
+    uint64_t n_photons;
+    uint64_t queue_begin;     // this job's offset in the launch-wide queue
+};
+
+struct Photon {
+    int32_t ix, iy, iz;
+    float fx, fy, fz;
+    float ux, uy, uz;
+    float s_rem;              // remaining free path, in solid path length
+    float l_void, l_tot;
+    uint32_t w, k, steps, pid;
+    uint64_t absorbed;        // weight absorbed by this photon so far
+    int64_t rr;               // roulette balance of this photon
+    uint64_t acc;             // deposit in the current voxel not yet flushed
+    uint32_t brick;           // index of the cached brick
+    uint32_t solid;           // current voxel is solid
+    uint64_t bits;            // cached brick
+};
+
+__device__ __forceinline__ uint32_t brick_of(const Job &J, int32_t ix, int32_t iy, int32_t iz)
+{
+    return ((uint32_t)(iz >> 2) * (uint32_t)J.nyb + (uint32_t)(iy >> 2)) * (uint32_t)J.nxb + (uint32_t)(ix >> 2);
+}
+
+__device__ __forceinline__ uint32_t bit_of(int32_t ix, int32_t iy, int32_t iz)
+{
+    return ((uint32_t)(iz & 3) << 4) | ((uint32_t)(iy & 3) << 2) | (uint32_t)(ix & 3);
+}
+
+// Refresh the solid flag of the current voxel, reloading the brick only when
+// the photon has left the cached one.
+__device__ __forceinline__ void lookup(Photon &p, const Job &J)
+{
+    const uint32_t b = brick_of(J, p.ix, p.iy, p.iz);
+    if (b != p.brick) {
+        p.bits = J.bricks[b];
+        p.brick = b;
+    }
+    p.solid = (uint32_t)((p.bits >> bit_of(p.ix, p.iy, p.iz)) & 1ull) ^ 1u;
+}
+
+__device__ __forceinline__ uint64_t voxel_index(const Job &J, const Photon &p)
+{
+    return ((uint64_t)p.iz * (uint64_t)J.ny + (uint64_t)p.iy) * (uint64_t)J.nx + (uint64_t)p.ix;
+}
+
+__device__ __forceinline__ float free_path(const Job &J, uint32_t r)
+{
+    // tau = -ln U, U in (0,1]; the interaction lies tau / mu_t into the solid
+    return J.mu_t > 0.0f ? -logf(u01_oc(r)) / J.mu_t : kInf;
+}
+
+__device__ __forceinline__ float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+
+// 1/|u| per axis, +inf on an axis the photon does not move along.
+__device__ __forceinline__ float inv_abs(float u) { return u != 0.0f ? 1.0f / fabsf(u) : kInf; }
+
+// Launch photon `pid` (Philox block k = 0): uniform position on the z = 0 face
+// from 24-bit uniforms scaled by the face size in integer arithmetic, normal
+// incidence (or Lambertian for the test source), first free path.
+__device__ __forceinline__ void launch(Photon &p, const Job &J, uint32_t pid)
+{
+    const U4 r = philox4x32_10(U4{0u, pid, J.stream_id, 0u}, J.key0, J.key1);
+    const uint64_t X = (uint64_t)(r.x >> 8) * (uint64_t)J.nx;
+    const uint64_t Y = (uint64_t)(r.y >> 8) * (uint64_t)J.ny;
+    p.ix = (int32_t)(X >> 24);
+    p.iy = (int32_t)(Y >> 24);
+    p.iz = 0;
+    p.fx = (float)(uint32_t)(X & 0xFFFFFFu) * 0x1.0p-24f;
+    p.fy = (float)(uint32_t)(Y & 0xFFFFFFu) * 0x1.0p-24f;
+    p.fz = 0.0f;
+    p.ux = 0.0f;
+    p.uy = 0.0f;
+    p.uz = 1.0f;
+    if (J.source == 1) {
+        const U4 s = philox4x32_10(U4{0u, pid, J.stream_id, 1u}, J.key0, J.key1);
+        const float ct = sqrtf(u01_co(s.x));
+        const float st = sqrtf(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
+        float sp, cp;
+        sincospif(2.0f * u01_co(s.y), &sp, &cp);
+        p.ux = st * cp;
+        p.uy = st * sp;
+        p.uz = ct;
+    }
+    p.s_rem = free_path(J, r.z);
+    p.l_void = 0.0f;
+    p.l_tot = 0.0f;
+    p.w = kW1;
+    p.k = 0u;
+    p.steps = 0u;
+    p.pid = pid;
+    p.absorbed = 0ull;
+    p.rr = 0;
+    p.acc = 0ull;
+    p.brick = 0xFFFFFFFFu;
+    lookup(p, J);
+}
+
+// Henyey-Greenstein deflection and the MCML direction update.  sin(theta) is
+// formed from (1 - cos)(1 + cos), each factor written without cancellation:
+//   1 - cos = (1-g)(1-xi)(t+1-g)/den,  1 + cos = (1+g) xi (1+g+t)/den,
+// with den = 1 - g + 2 g xi and t = (1 - g^2)/den.  The transverse norm of the
+// old direction is sqrt(ux^2 + uy^2) (= sqrt(1 - uz^2) for a unit vector).
+__device__ __forceinline__ void scatter(Photon &p, const Job &J, uint32_t r0, uint32_t r1)
+{
+    const float g = J.g, xi = u01_co(r0);
+    float ct, st2;
+    if (g != 0.0f) {
+        const float den = 1.0f - g + 2.0f * g * xi;
+        const float t = (1.0f - g * g) / den;
+        ct = (1.0f + g * g - t * t) / (2.0f * g);
+        const float om = (1.0f - g) * (1.0f - xi) * (t + 1.0f - g) / den;
+        const float op = (1.0f + g) * xi * (1.0f + g + t) / den;
+        st2 = om * op;
+    } else {
+        ct = 2.0f * xi - 1.0f;
+        st2 = 4.0f * xi * (1.0f - xi);
+    }
+    ct = fminf(fmaxf(ct, -1.0f), 1.0f);
+    const float st = sqrtf(fmaxf(st2, 0.0f));
+    float sp, cp;
+    sincospif(2.0f * u01_co(r1), &sp, &cp);
+    const float ux = p.ux, uy = p.uy, uz = p.uz;
+    const float tn = sqrtf(ux * ux + uy * uy);
+    float nx, ny, nz;
+    if (tn == 0.0f) {
+        nx = st * cp;
+        ny = st * sp;
+        nz = (uz >= 0.0f ? ct : -ct);
+    } else {
+        const float it = 1.0f / tn;
+        nx = st * (ux * uz * cp - uy * sp) * it + ux * ct;
+        ny = st * (uy * uz * cp + ux * sp) * it + uy * ct;
+        nz = -st * cp * tn + uz * ct;
+    }
+    const float inrm = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
+    p.ux = nx * inrm;
+    p.uy = ny * inrm;
+    p.uz = nz * inrm;
+}
+
+// One photon-step: a segment inside the current voxel that ends at a face, an
+// interaction or an escape.  Returns the event.  The Sink receives the
+// segment, the flushed per-voxel deposits and the terminal outcomes.
+template <class Sink>
+__device__ __forceinline__ int32_t step(Photon &p, const Job &J, Sink &sink)
+{
+    const float ivx = inv_abs(p.ux), ivy = inv_abs(p.uy), ivz = inv_abs(p.uz);
+    const float dx = p.ux != 0.0f ? (p.ux > 0.0f ? 1.0f - p.fx : p.fx) * ivx : kInf;
+    const float dy = p.uy != 0.0f ? (p.uy > 0.0f ? 1.0f - p.fy : p.fy) * ivy : kInf;
+    const float dz = p.uz != 0.0f ? (p.uz > 0.0f ? 1.0f - p.fz : p.fz) * ivz : kInf;
+    int32_t axis = 0;
+    float d_face = dx;
+    if (dy < d_face) { axis = 1; d_face = dy; }
+    if (dz < d_face) { axis = 2; d_face = dz; }
+    const bool solid = p.solid != 0u;
+    const bool interact = solid && (p.s_rem <= d_face);
+    const float d = interact ? p.s_rem : d_face;
+
+    sink.segment(p, J, d, solid);
+    // track-length deposit, quantised per segment, accumulated while in this voxel
+    p.acc += (uint64_t)__float2ull_rn((float)p.w * d);
+    if (solid) p.s_rem = fmaxf(p.s_rem - d, 0.0f);
+    else p.l_void += d;
+    p.l_tot += d;
+    p.steps += 1u;
+
+    int32_t ev;
+    if (interact) {
+        p.fx = clamp01(p.fx + p.ux * d);
+        p.fy = clamp01(p.fy + p.uy * d);
+        p.fz = clamp01(p.fz + p.uz * d);
+        p.k += 1u;
+        const U4 r = philox4x32_10(U4{p.k, p.pid, J.stream_id, 0u}, J.key0, J.key1);
+        // implicit capture on the integer weight, round half up
+        const uint32_t w_new = (uint32_t)(((uint64_t)p.w * J.s_q + 0x80000000ull) >> 32);
+        p.absorbed += (uint64_t)(p.w - w_new);
+        p.w = w_new;
+        if (w_new == 0u) {
+            ev = EV_DEAD_ABSORB;
+        } else {
+            scatter(p, J, r.x, r.y);
+            ev = EV_SCATTER;
+            if (p.w < J.w_th) {
+                if ((r.w >> 8) < J.t_m) {
+                    p.rr -= (int64_t)(J.m - 1u) * (int64_t)p.w;
+                    p.w *= J.m;
+                } else {
+                    p.rr += (int64_t)p.w;
+                    ev = EV_DEAD_ROULETTE;
+                }
+            }
+            p.s_rem = free_path(J, r.z);
+        }
+    } else {
+        if (axis != 0) p.fx = clamp01(p.fx + p.ux * d);
+        if (axis != 1) p.fy = clamp01(p.fy + p.uy * d);
+        if (axis != 2) p.fz = clamp01(p.fz + p.uz * d);
+        sink.flush(J, voxel_index(J, p), p.acc);
+        p.acc = 0ull;
+        ev = axis;
+        if (axis == 0) {
+            if (p.ux > 0.0f) { p.fx = 0.0f; p.ix = (p.ix + 1 == J.nx) ? 0 : p.ix + 1; }
+            else             { p.fx = 1.0f; p.ix = (p.ix == 0) ? J.nx - 1 : p.ix - 1; }
+        } else if (axis == 1) {
+            if (p.uy > 0.0f) { p.fy = 0.0f; p.iy = (p.iy + 1 == J.ny) ? 0 : p.iy + 1; }
+            else             { p.fy = 1.0f; p.iy = (p.iy == 0) ? J.ny - 1 : p.iy - 1; }
+        } else {
+            if (p.uz > 0.0f) { p.fz = 0.0f; p.iz += 1; }
+            else             { p.fz = 1.0f; p.iz -= 1; }
+            if (p.iz < 0) ev = EV_ESC_R;
+            else if (p.iz >= J.nz) ev = EV_ESC_T;
+        }
+        if (ev < EV_FIRST_TERMINAL) lookup(p, J);
+    }
+    if (ev < EV_FIRST_TERMINAL && (p.steps >= J.max_steps || p.l_tot > J.path_cap)) ev = EV_LOST;
+    if (ev >= EV_FIRST_TERMINAL && p.acc != 0ull) {
+        // photon ends inside a voxel (absorbed, roulette, cap): flush what it left there
+        sink.flush(J, voxel_index(J, p), p.acc);
+        p.acc = 0ull;
+    }
+    return ev;
+}
+
+}  // namespace pmc

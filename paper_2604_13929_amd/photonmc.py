@@ -1,0 +1,249 @@
+"""Python binding of libphotonmc.so (argument marshalling only).
+
+Torch provides device memory and the current HIP stream; every step of the
+walk and of the reduction runs in the library's HIP kernels.  If the library
+is missing the calls raise: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import build as _build
+
+LIB_PATH = _build.LIB
+
+MC_ACCUMULATE = 1
+MC_TIMED = 2
+NSCALARS = 16
+NSUMMARY = 32
+SCALARS = ["R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_w_void_path", "esc_n", "esc_n_gtL",
+           "steps", "interactions", "launched"]
+SUMMARY = ["phi3d", "phi1d", "phi_pore", "r", "porosity", "ratio", "identity_rhs", "R", "T", "A", "RR", "lost",
+           "closure_exact", "front_back", "L_opt", "esc_frac", "Pw_void_gtL", "Pn_void_gtL", "mean_void_path",
+           "steps_per_photon", "interactions_per_photon", "status", "n_solid", "launched"]
+W1 = 2 ** 31
+
+
+class McVolume(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("mask", ctypes.c_void_p)]
+
+
+class McOptics(ctypes.Structure):
+    _fields_ = [("mu_s", ctypes.c_float), ("mu_a", ctypes.c_float), ("g", ctypes.c_float),
+                ("w_roulette", ctypes.c_float), ("roulette_m", ctypes.c_uint32), ("path_cap", ctypes.c_float),
+                ("source", ctypes.c_int32), ("max_steps", ctypes.c_uint32)]
+
+
+class McTune(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("refill", ctypes.c_int32)]
+
+
+TRACE_DTYPE = np.dtype([("ix", "<i4"), ("iy", "<i4"), ("iz", "<i4"), ("event", "<i4"),
+                        ("fx", "<f4"), ("fy", "<f4"), ("fz", "<f4"), ("ux", "<f4"), ("uy", "<f4"), ("uz", "<f4"),
+                        ("d", "<f4"), ("w", "<u4"), ("k", "<u4"), ("reserved", "<u4")])
+PHOTON_DTYPE = np.dtype([("R", "<i8"), ("T", "<i8"), ("A", "<i8"), ("RR", "<i8"), ("lost", "<i8"),
+                         ("w_final", "<u4"), ("fate", "<u4"), ("steps", "<u4"), ("interactions", "<u4"),
+                         ("path_void", "<f4"), ("path_solid", "<f4")])
+
+# exported symbols and their signatures (restype, argtypes)
+_P = ctypes.c_void_p
+_SIGS = {
+    "mc_abi_version": (ctypes.c_int, []),
+    "mc_sizeof": (ctypes.c_size_t, [ctypes.c_char_p]),
+    "mc_last_error": (ctypes.c_char_p, []),
+    "mc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "mc_tune_default": (None, [_P]),
+    "mc_run_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "mc_run": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                              ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P, _P]),
+    "mc_walk_elapsed_ms": (ctypes.c_int, [_P]),
+    "mc_reduce_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "mc_reduce": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mc_trace": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
+                                _P, _P, _P, ctypes.c_size_t, _P]),
+}
+
+_lib = None
+
+
+class McError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2604_13929_amd.build.build_library() "
+                           "(or __graft_entry__.build()) first -- there is no fallback path")
+    L = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    for name, size in (("mc_volume", ctypes.sizeof(McVolume)), ("mc_optics", ctypes.sizeof(McOptics)),
+                       ("mc_tune", ctypes.sizeof(McTune)), ("mc_trace_rec", TRACE_DTYPE.itemsize),
+                       ("mc_photon_rec", PHOTON_DTYPE.itemsize)):
+        if L.mc_sizeof(name.encode()) != size:
+            raise RuntimeError(f"ABI mismatch: sizeof({name}) is {L.mc_sizeof(name.encode())}, binding has {size}")
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status: int, where: str):
+    if status < 0:
+        L = load()
+        raise McError(status, where, (L.mc_last_error() or b"").decode() or L.mc_strerror(status).decode())
+    return status
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class Optics:
+    """Solid-phase optics per voxel length; pores are transparent."""
+    mu_s: float
+    mu_a: float
+    g: float
+    w_roulette: float = 1e-4
+    roulette_m: int = 10
+    path_cap: float = 0.0
+    source: int = 0
+    max_steps: int = 0
+
+    def c(self) -> McOptics:
+        return McOptics(self.mu_s, self.mu_a, self.g, self.w_roulette, self.roulette_m, self.path_cap,
+                        self.source, self.max_steps)
+
+
+@dataclass
+class Tune:
+    block: int = 0
+    waves_per_cu: int = 0
+    chunk: int = 0
+    refill: int = 0
+
+    def c(self) -> McTune:
+        return McTune(self.block, self.waves_per_cu, self.chunk, self.refill)
+
+
+@dataclass
+class RunResult:
+    """Device tallies of a run: fluence int64[nz][ny][nx] and int64[NSCALARS]."""
+    fluence: torch.Tensor
+    scalars: torch.Tensor
+    walk_ms: float | None = None
+
+    def scalar_dict(self) -> dict:
+        s = self.scalars.cpu().tolist()
+        return {name: int(s[i]) for i, name in enumerate(SCALARS)}
+
+
+def volume(mask: torch.Tensor) -> McVolume:
+    if mask.dtype != torch.uint8 or mask.dim() != 3 or not mask.is_cuda or not mask.is_contiguous():
+        raise ValueError("mask must be a contiguous uint8 device tensor [nz, ny, nx]")
+    nz, ny, nx = mask.shape
+    return McVolume(nx, ny, nz, 0, mask.data_ptr())
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def run(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_begin: int = 0, stream_id: int = 0,
+        accumulate: RunResult | None = None, tune: Tune | None = None, timed: bool = False) -> RunResult:
+    """mc_run on the current stream of the mask's device."""
+    L = load()
+    vol = volume(mask)
+    dev = mask.device
+    if accumulate is None:
+        res = RunResult(torch.empty(tuple(mask.shape), dtype=torch.int64, device=dev),
+                        torch.empty(NSCALARS, dtype=torch.int64, device=dev))
+        flags = 0
+    else:
+        res, flags = accumulate, MC_ACCUMULATE
+    if timed:
+        flags |= MC_TIMED
+    nbytes = L.mc_run_workspace_bytes(ctypes.byref(vol))
+    ws = workspace(nbytes, dev)
+    opt = optics.c()
+    t = tune.c() if tune is not None else None
+    _check(L.mc_run(ctypes.byref(vol), ctypes.byref(opt), photon_begin, n_photons, seed, stream_id, flags,
+                    res.fluence.data_ptr(), res.scalars.data_ptr(), ws.data_ptr(), ws.numel(),
+                    ctypes.byref(t) if t is not None else None, _stream(dev)), "mc_run")
+    res._ws = ws  # keep the workspace alive with the queued work
+    if timed:
+        ms = ctypes.c_float(0.0)
+        _check(L.mc_walk_elapsed_ms(ctypes.byref(ms)), "mc_walk_elapsed_ms")
+        res.walk_ms = float(ms.value)
+    return res
+
+
+@dataclass
+class Summary:
+    values: dict
+    depth: np.ndarray = field(repr=False)        # Phi/S0 per depth
+    depth_solid: np.ndarray = field(repr=False)
+    depth_pore: np.ndarray = field(repr=False)
+
+    def __getitem__(self, k):
+        return self.values[k]
+
+
+def reduce_async(mask: torch.Tensor, res: RunResult):
+    """mc_reduce into device buffers (summary double[NSUMMARY], depth double[3][nz])."""
+    L = load()
+    vol = volume(mask)
+    dev = mask.device
+    summary = torch.empty(NSUMMARY, dtype=torch.float64, device=dev)
+    depth = torch.empty((3, mask.shape[0]), dtype=torch.float64, device=dev)
+    ws = workspace(L.mc_reduce_workspace_bytes(ctypes.byref(vol)), dev)
+    _check(L.mc_reduce(ctypes.byref(vol), res.fluence.data_ptr(), res.scalars.data_ptr(), summary.data_ptr(),
+                       depth.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)), "mc_reduce")
+    return summary, depth, ws
+
+
+def reduce(mask: torch.Tensor, res: RunResult) -> Summary:
+    summary, depth, ws = reduce_async(mask, res)
+    s = summary.cpu().numpy()
+    d = depth.cpu().numpy()
+    del ws
+    vals = {name: float(s[i]) for i, name in enumerate(SUMMARY)}
+    if vals["status"] != 0:
+        raise McError(int(vals["status"]), "mc_reduce", "a voxel tally reached 2^62")
+    return Summary(vals, d[0], d[1], d[2])
+
+
+def trace(mask: torch.Tensor, optics: Optics, photon_ids, max_steps: int, seed: int, stream_id: int = 0):
+    """Per-step records [n, max_steps] and per-photon outcomes [n] (numpy structured arrays)."""
+    L = load()
+    vol = volume(mask)
+    dev = mask.device
+    ids = torch.as_tensor(np.asarray(photon_ids, dtype=np.uint64).view(np.int64), device=dev)
+    n = int(ids.numel())
+    recs = torch.empty((n, max_steps, TRACE_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+    outc = torch.empty((n, PHOTON_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+    ws = workspace(L.mc_run_workspace_bytes(ctypes.byref(vol)), dev)
+    opt = optics.c()
+    _check(L.mc_trace(ctypes.byref(vol), ctypes.byref(opt), ids.data_ptr(), n, max_steps, seed, stream_id,
+                      recs.data_ptr(), outc.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)), "mc_trace")
+    r = recs.cpu().numpy().reshape(-1).view(TRACE_DTYPE).reshape(n, max_steps)
+    o = outc.cpu().numpy().reshape(-1).view(PHOTON_DTYPE)
+    return r, o

@@ -1,0 +1,88 @@
+"""The C-ABI library: it loads, exports every entry point the header declares,
+its struct layouts match the binding, and host-side validation rejects bad
+arguments before any device work (no GPU needed)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2604_13929_amd import photonmc as pm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "photonmc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(mc_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pm.LIB_PATH):
+        pytest.fail("libphotonmc.so is not built (run __graft_entry__.build())")
+    return pm.load()
+
+
+def test_header_parsed():
+    names = declared_functions()
+    assert {"mc_run", "mc_reduce", "mc_trace"} <= set(names)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(pm.exported_symbols())
+
+
+def test_abi_version_and_layouts(lib):
+    assert lib.mc_abi_version() == 1
+    assert lib.mc_sizeof(b"mc_volume") == 24
+    assert lib.mc_sizeof(b"mc_trace_rec") == pm.TRACE_DTYPE.itemsize == 56
+    assert lib.mc_sizeof(b"mc_photon_rec") == pm.PHOTON_DTYPE.itemsize == 64
+    assert lib.mc_sizeof(b"nonsense") == 0
+
+
+def test_strerror(lib):
+    assert lib.mc_strerror(0) == b"ok"
+    assert b"invalid" in lib.mc_strerror(-1)
+
+
+def _call_run(lib, nx=8, ny=8, nz=8, mask=1, mu_s=0.5, mu_a=0.01, g=0.7, w_r=1e-4, m=10, n=10, begin=0,
+              fluence=1, scalars=1, ws=1, ws_bytes=1 << 20, source=0, tune=None):
+    vol = pm.McVolume(nx, ny, nz, 0, mask)
+    opt = pm.McOptics(mu_s, mu_a, g, w_r, m, 0.0, source, 0)
+    return lib.mc_run(ctypes.byref(vol), ctypes.byref(opt), begin, n, 1, 0, 0, fluence, scalars, ws, ws_bytes,
+                      ctypes.byref(tune) if tune is not None else None, None)
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(nx=0), b"dimensions"), (dict(nz=-3), b"dimensions"), (dict(nx=70000), b"dimensions"),
+    (dict(mask=None), b"mask"), (dict(mu_s=-1.0), b"mu_s"), (dict(mu_a=float("nan")), b"mu_s"),
+    (dict(g=1.0), b"|g|"), (dict(m=1), b"roulette_m"), (dict(w_r=0.5, m=10), b"outweigh"),
+    (dict(n=0), b"n_photons"), (dict(begin=2 ** 32 - 5, n=10), b"2^32"), (dict(source=3), b"source"),
+    (dict(fluence=None), b"non-NULL"), (dict(ws_bytes=16), b"workspace"),
+])
+def test_run_rejects_bad_arguments(lib, kw, needle):
+    rc = _call_run(lib, **kw)
+    assert rc in (-1, -4)
+    assert needle in lib.mc_last_error()
+
+
+def test_run_rejects_bad_tune(lib):
+    assert _call_run(lib, tune=pm.McTune(96, 0, 0, 0)) == -1 and b"block" in lib.mc_last_error()
+    assert _call_run(lib, tune=pm.McTune(0, 0, 0, 65)) == -1 and b"refill" in lib.mc_last_error()
+
+
+def test_workspace_sizes(lib):
+    vol = pm.McVolume(9, 5, 7, 0, 1)
+    # header + one uint64 per 4x4x4 brick (3 x 2 x 2 bricks)
+    assert lib.mc_run_workspace_bytes(ctypes.byref(vol)) == 256 + 12 * 8
+    assert lib.mc_reduce_workspace_bytes(ctypes.byref(vol)) == 7 * 8 * 8
+    bad = pm.McVolume(0, 5, 7, 0, 1)
+    assert lib.mc_run_workspace_bytes(ctypes.byref(bad)) == 0
