@@ -54,6 +54,7 @@ extern "C" {
 /* flags */
 #define MC_ACCUMULATE 1     /* add to the tallies instead of zeroing them first */
 #define MC_TIMED 2          /* time the walk kernel with HIP events on the run's stream (mc_walk_elapsed_ms) */
+#define MC_FP64 4           /* geometry and scattering in FP64 instead of FP32 (reference transport) */
 
 /* Scalar tally channels: int64 words in a caller-owned device array of
  * MC_NSCALARS entries.  Weight channels are Q31.  For every run
@@ -179,17 +180,18 @@ int mc_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scala
               double *depth, void *workspace, size_t workspace_bytes, void *hip_stream);
 
 /* One trace record per step of a traced photon: the state at the start of the
- * step and how the step ended. */
+ * step (exact values of the transport precision, widened to double) and how the
+ * step ended. */
 typedef struct {
+    double fx, fy, fz;     /* offsets inside the voxel, [0, 1] */
+    double ux, uy, uz;     /* direction */
+    double d;              /* segment length */
+    double s_rem;          /* remaining free path (solid length) at the start of the step */
+    uint32_t w;            /* weight, Q31 */
+    uint32_t k;            /* interactions so far */
     int32_t ix, iy, iz;
     int32_t event;         /* 0/1/2 face crossing on x/y/z, 3 scatter, 4 escape z<0, 5 escape z>Nz,
                               6 weight absorbed to zero, 7 roulette kill, 8 cap; -1 unused */
-    float fx, fy, fz;      /* offsets inside the voxel, [0, 1] */
-    float ux, uy, uz;      /* direction */
-    float d;               /* segment length */
-    uint32_t w;            /* weight, Q31 */
-    uint32_t k;            /* interactions so far */
-    uint32_t reserved;
 } mc_trace_rec;
 
 /* Per-photon outcome of a traced photon. */
@@ -197,17 +199,18 @@ typedef struct {
     int64_t R, T, A, RR, lost;     /* this photon's share of each weight channel */
     uint32_t w_final, fate;        /* final weight and final event */
     uint32_t steps, interactions;
-    float path_void, path_solid;
+    double path_void, path_solid;
 } mc_photon_rec;
 
 /*
- * Trace photons one per lane through the same walk as mc_run (no tallies):
+ * Trace photons one per lane through the same walk as mc_run (no tallies); flags
+ * may hold MC_FP64:
  *   photon_ids  device uint64[n] (each < 2^32)
  *   recs        device mc_trace_rec[n][max_steps] (all records written; unused ones event -1)
  *   outcome     device mc_photon_rec[n], or NULL
  */
 int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_ids, int32_t n,
-             int32_t max_steps, uint64_t seed, uint32_t stream_id, mc_trace_rec *recs,
+             int32_t max_steps, uint64_t seed, uint32_t stream_id, int flags, mc_trace_rec *recs,
              mc_photon_rec *outcome, void *workspace, size_t workspace_bytes, void *hip_stream);
 
 /* Text for a status code. */

@@ -47,6 +47,13 @@ PHOTON_DTYPE = np.dtype([("R", "<i8"), ("T", "<i8"), ("A", "<i8"), ("RR", "<i8")
                          ("fate", "<i4"), ("pad", "<i4")])
 
 
+STATE_DTYPE = np.dtype([("ix", "<i8"), ("iy", "<i8"), ("iz", "<i8"),
+                        ("fx", "<f8"), ("fy", "<f8"), ("fz", "<f8"), ("ux", "<f8"), ("uy", "<f8"), ("uz", "<f8"),
+                        ("tau", "<f8"), ("w", "<i8"), ("k", "<u4"), ("pad", "<u4"), ("steps", "<u8"),
+                        ("l_void", "<f8"), ("l_solid", "<f8"), ("score_s", "<f8"), ("score_a", "<f8"),
+                        ("score_g", "<f8")])
+
+
 def build(force: bool = False) -> str:
     """Compile oracle.c into liboracle.so with gcc (plain C11, no fast-math, no contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -70,11 +77,14 @@ def lib():
         L.orc_trace.restype = ctypes.c_int
         L.orc_trace.argtypes = [ctypes.POINTER(Problem), ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_step.restype = ctypes.c_int
+        L.orc_step.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_philox.restype = None
         L.orc_philox.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         assert L.orc_sizeof_rec() == REC_DTYPE.itemsize
         assert L.orc_sizeof_photon() == PHOTON_DTYPE.itemsize
         assert L.orc_sizeof_problem() == ctypes.sizeof(Problem)
+        assert L.orc_sizeof_state() == STATE_DTYPE.itemsize
         _lib = L
     return _lib
 
@@ -161,3 +171,16 @@ def trace(mask, mu_s, mu_a, g, photon_ids, seed, max_rec=64, stream_id=0, **kw):
     if rc != 0:
         raise ValueError("oracle rejected the problem")
     return recs, summ
+
+
+def step_from(mask, mu_s, mu_a, g, photon_id, state, seed, stream_id=0, **kw):
+    """One oracle step of photon ``photon_id`` from ``state`` (a STATE_DTYPE record).
+
+    Returns (event, new_state, tie_gap)."""
+    P, m = make_problem(mask, mu_s, mu_a, g, seed, stream_id, **kw)
+    st = np.array(state, dtype=STATE_DTYPE).reshape(1).copy()
+    gap = ctypes.c_double(0.0)
+    ev = lib().orc_step(ctypes.byref(P), int(photon_id), st.ctypes.data, ctypes.byref(gap))
+    if ev < 0:
+        raise ValueError("oracle rejected the problem")
+    return ev, st[0], gap.value

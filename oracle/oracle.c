@@ -173,8 +173,58 @@ static double hg_score(double mu, double g)
     return -2.0 * g / (1.0 - g * g) + 3.0 * (mu - g) / (1.0 + g * g - 2.0 * g * mu);
 }
 
-/* Walk one photon from launch to termination. */
-static void walk(const orc_problem *P, uint64_t photon, orc_sink *S)
+/* State of one photon between steps. */
+typedef struct {
+    int64_t ix, iy, iz;
+    double fx, fy, fz;
+    double ux, uy, uz;
+    double tau;              /* optical depth left to the next interaction */
+    int64_t w;               /* weight, units of 2^-31 */
+    uint32_t k;              /* interactions so far */
+    uint32_t pad;
+    uint64_t steps;
+    double l_void, l_solid;
+    double score_s, score_a, score_g;   /* LR scores (see the header comment) */
+} orc_state;
+
+/* Launch: uniform position over the z = 0 face (integer voxel + offset from 24-bit
+ * uniforms), direction +z (or Lambertian for the test source), weight 2^31, and the
+ * optical depth of the first flight. */
+static void launch(const orc_problem *P, uint64_t photon, orc_state *st)
+{
+    uint32_t r[4];
+    draw(P, photon, 0, 0, r);
+    memset(st, 0, sizeof *st);
+    uint64_t X = (uint64_t)(r[0] >> 8) * (uint64_t)P->nx;
+    uint64_t Y = (uint64_t)(r[1] >> 8) * (uint64_t)P->ny;
+    st->ix = (int64_t)(X >> 24);
+    st->iy = (int64_t)(Y >> 24);
+    st->iz = 0;
+    st->fx = (double)(X & 0xFFFFFFu) / 16777216.0;
+    st->fy = (double)(Y & 0xFFFFFFu) / 16777216.0;
+    st->fz = 0.0;
+    st->ux = 0.0; st->uy = 0.0; st->uz = 1.0;
+    if (P->source == 1) {
+        uint32_t s[4];
+        draw(P, photon, 0, 1, s);
+        double ct = sqrt(u_closed_open(s[0]));
+        double stt = sqrt(1.0 - ct * ct);
+        double psi = 2.0 * ORC_PI * u_closed_open(s[1]);
+        st->ux = stt * cos(psi);
+        st->uy = stt * sin(psi);
+        st->uz = ct;
+    }
+    st->tau = -log(u_open_closed(r[2]));
+    st->w = (int64_t)ORC_W1;
+}
+
+/*
+ * One step from state st: the segment inside the current voxel up to a face, an
+ * interaction or an escape.  Updates st, the sink and the photon's own shares me;
+ * returns the event, and sets *gap to how close the step came to a different
+ * decision (|s_int - d_face| and the gaps between face distances).
+ */
+static int step(const orc_problem *P, uint64_t photon, orc_state *st, orc_sink *S, orc_photon *me, double *gap_out)
 {
     const int64_t nx = P->nx, ny = P->ny, nz = P->nz;
     const double mu_t_solid = P->mu_s + P->mu_a;
@@ -184,227 +234,211 @@ static void walk(const orc_problem *P, uint64_t photon, orc_sink *S)
     const int64_t w_th = (int64_t)floor(P->w_roulette * ORC_W1);
     const uint32_t T_m = (uint32_t)llround(16777216.0 / (double)P->roulette_m);
 
-    uint32_t r[4];
-    draw(P, photon, 0, 0, r);
+    const int64_t v = (st->iz * ny + st->iy) * nx + st->ix;
+    const int solid = (P->mask[v] == 0);
+    const double mu_t = solid ? mu_t_solid : 0.0;
 
-    /* launch: uniform position over the z = 0 face, integer voxel + offset */
-    uint64_t X = (uint64_t)(r[0] >> 8) * (uint64_t)nx;
-    uint64_t Y = (uint64_t)(r[1] >> 8) * (uint64_t)ny;
-    int64_t ix = (int64_t)(X >> 24), iy = (int64_t)(Y >> 24), iz = 0;
-    double fx = (double)(X & 0xFFFFFFu) / 16777216.0;
-    double fy = (double)(Y & 0xFFFFFFu) / 16777216.0;
-    double fz = 0.0;
-    double ux = 0.0, uy = 0.0, uz = 1.0;
-    if (P->source == 1) {
-        uint32_t s[4];
-        draw(P, photon, 0, 1, s);
-        double ct = sqrt(u_closed_open(s[0]));
-        double st = sqrt(1.0 - ct * ct);
-        double psi = 2.0 * ORC_PI * u_closed_open(s[1]);
-        ux = st * cos(psi);
-        uy = st * sin(psi);
-        uz = ct;
+    /* distance to each face along the direction of travel */
+    double dist[3];
+    const double f[3] = {st->fx, st->fy, st->fz};
+    const double u[3] = {st->ux, st->uy, st->uz};
+    for (int a = 0; a < 3; ++a) {
+        if (u[a] > 0.0) dist[a] = (1.0 - f[a]) / u[a];
+        else if (u[a] < 0.0) dist[a] = f[a] / (-u[a]);
+        else dist[a] = INFINITY;
     }
-    double tau = -log(u_open_closed(r[2]));
-    int64_t w = (int64_t)ORC_W1;
-    uint32_t k = 0;
-    uint64_t steps = 0;
-    double l_void = 0.0, l_solid = 0.0;
-    double score_s = 0.0, score_a = 0.0, score_g = 0.0; /* LR scores */
+    int axis = 0;
+    if (dist[1] < dist[axis]) axis = 1;
+    if (dist[2] < dist[axis]) axis = 2;
+    const double d_face = dist[axis];
+    const double s_int = (mu_t > 0.0) ? st->tau / mu_t : INFINITY;
+    const int interact = (s_int <= d_face);
+    const double d = interact ? s_int : d_face;
+
+    double gap = fabs(s_int - d_face);
+    for (int a = 0; a < 3; ++a)
+        if (a != axis && isfinite(dist[a])) {
+            double ga = fabs(dist[a] - d_face);
+            if (ga < gap) gap = ga;
+        }
+    if (gap_out) *gap_out = gap;
+    if (S->trace && (int64_t)st->steps < S->max_rec) {
+        orc_rec *rec = &S->trace[st->steps];
+        rec->ix = (int32_t)st->ix; rec->iy = (int32_t)st->iy; rec->iz = (int32_t)st->iz;
+        rec->fx = st->fx; rec->fy = st->fy; rec->fz = st->fz;
+        rec->ux = st->ux; rec->uy = st->uy; rec->uz = st->uz;
+        rec->w = st->w; rec->k = st->k; rec->d = d;
+        rec->tie_gap = gap;
+        rec->event = -1;
+    }
+
+    /* track-length deposit */
+    const int64_t w = st->w;
+    if (S->fluence) S->fluence[v] += (double)w * d;
+    if (S->depth) S->depth[(solid ? 0 : 1) * nz + st->iz] += (double)w * d;
+    if (S->grad) {
+        const int ph = solid ? 0 : 1;
+        const double sq = solid ? 0.5 * d * d : 0.0;
+        S->grad[(0 * 2 + ph) * nz + st->iz] += (double)w * (st->score_s * d - sq);
+        S->grad[(1 * 2 + ph) * nz + st->iz] += (double)w * (st->score_a * d - sq);
+        S->grad[(2 * 2 + ph) * nz + st->iz] += (double)w * (st->score_g * d);
+    }
+    if (solid) {
+        st->l_solid += d;
+        st->score_s -= d;
+        st->score_a -= d;
+    } else {
+        st->l_void += d;
+    }
+
+    int event;
+    int done = 0;
+    if (interact) {
+        st->fx = clamp01(st->fx + st->ux * d);
+        st->fy = clamp01(st->fy + st->uy * d);
+        st->fz = clamp01(st->fz + st->uz * d);
+        st->tau = 0.0;
+        event = EV_SCATTER;
+    } else {
+        if (axis != 0) st->fx = clamp01(st->fx + st->ux * d);
+        if (axis != 1) st->fy = clamp01(st->fy + st->uy * d);
+        if (axis != 2) st->fz = clamp01(st->fz + st->uz * d);
+        st->tau -= mu_t * d;
+        if (st->tau < 0.0) st->tau = 0.0;
+        event = axis;
+    }
+    st->steps += 1;
+
+    if (!interact) {
+        /* cross the face */
+        if (axis == 0) {
+            if (st->ux > 0.0) { st->ix += 1; st->fx = 0.0; if (st->ix == nx) st->ix = 0; }
+            else              { st->ix -= 1; st->fx = 1.0; if (st->ix < 0) st->ix = nx - 1; }
+        } else if (axis == 1) {
+            if (st->uy > 0.0) { st->iy += 1; st->fy = 0.0; if (st->iy == ny) st->iy = 0; }
+            else              { st->iy -= 1; st->fy = 1.0; if (st->iy < 0) st->iy = ny - 1; }
+        } else {
+            if (st->uz > 0.0) { st->iz += 1; st->fz = 0.0; }
+            else              { st->iz -= 1; st->fz = 1.0; }
+            if (st->iz < 0 || st->iz >= nz) {
+                /* escape through an open axial face */
+                const int top = (st->iz < 0);
+                if (top) { S->sums->ich[ORC_R] += w; me->R += w; event = EV_ESC_R; }
+                else     { S->sums->ich[ORC_T] += w; me->T += w; event = EV_ESC_T; }
+                S->sums->ich[ORC_ESC_W] += w;
+                S->sums->ich[ORC_ESC_N] += 1;
+                if (st->l_void > (double)nz) {
+                    S->sums->ich[ORC_ESC_W_GTL] += w;
+                    S->sums->ich[ORC_ESC_N_GTL] += 1;
+                }
+                S->sums->dch[ORC_ESC_W_VOID_PATH] += (double)w * st->l_void;
+                done = 1;
+            }
+        }
+    } else {
+        /* interaction: absorb, scatter, roulette, new free path */
+        st->k += 1;
+        uint32_t r[4];
+        draw(P, photon, st->k, 0, r);
+        const int64_t w_new = (int64_t)(((uint64_t)st->w * S_q + 2147483648ull) >> 32);
+        S->sums->ich[ORC_A] += st->w - w_new;
+        me->A += st->w - w_new;
+        st->w = w_new;
+        if (w_new == 0) {
+            event = EV_DEAD_ABSORB;
+            done = 1;
+        } else {
+            /* Henyey-Greenstein polar angle, inverse CDF */
+            const double g = P->g, xi = u_closed_open(r[0]);
+            double ct;
+            if (g != 0.0) {
+                const double t = (1.0 - g * g) / (1.0 - g + 2.0 * g * xi);
+                ct = (1.0 + g * g - t * t) / (2.0 * g);
+            } else {
+                ct = 2.0 * xi - 1.0;
+            }
+            if (ct < -1.0) ct = -1.0;
+            if (ct > 1.0) ct = 1.0;
+            const double stt = sqrt(1.0 - ct * ct);
+            const double psi = 2.0 * ORC_PI * u_closed_open(r[1]);
+            const double cp = cos(psi), sp = sin(psi);
+            st->score_g += hg_score(ct, g);
+            if (P->mu_s > 0.0) st->score_s += 1.0 / P->mu_s;
+            /* rotate the direction (MCML).  The transverse norm is
+             * sqrt(1 - uz^2) = sqrt(ux^2 + uy^2) for a unit vector; the
+             * axis-aligned form is used only when the direction lies on the
+             * z axis. */
+            const double ux = st->ux, uy = st->uy, uz = st->uz;
+            const double tn = sqrt(ux * ux + uy * uy);
+            double nux, nuy, nuz;
+            if (tn == 0.0) {
+                nux = stt * cp;
+                nuy = stt * sp;
+                nuz = (uz >= 0.0 ? 1.0 : -1.0) * ct;
+            } else {
+                nux = stt * (ux * uz * cp - uy * sp) / tn + ux * ct;
+                nuy = stt * (uy * uz * cp + ux * sp) / tn + uy * ct;
+                nuz = -stt * cp * tn + uz * ct;
+            }
+            const double nrm = sqrt(nux * nux + nuy * nuy + nuz * nuz);
+            st->ux = nux / nrm; st->uy = nuy / nrm; st->uz = nuz / nrm;
+            /* Russian roulette on the integer weight */
+            if (st->w < w_th) {
+                if ((r[3] >> 8) < T_m) {
+                    const int64_t m = (int64_t)P->roulette_m;
+                    S->sums->ich[ORC_RR] -= (m - 1) * st->w;
+                    me->RR -= (m - 1) * st->w;
+                    st->w *= m;
+                } else {
+                    S->sums->ich[ORC_RR] += st->w;
+                    me->RR += st->w;
+                    event = EV_DEAD_ROULETTE;
+                    done = 1;
+                }
+            }
+            st->tau = -log(u_open_closed(r[2]));
+        }
+    }
+
+    if (!done) {
+        const double path = st->l_void + st->l_solid;
+        if (st->steps >= P->max_steps || (P->path_cap > 0.0 && path > P->path_cap)) {
+            S->sums->ich[ORC_LOST] += st->w;
+            me->lost += st->w;
+            event = EV_LOST;
+        }
+    }
+    if (S->trace && (int64_t)st->steps - 1 < S->max_rec) S->trace[st->steps - 1].event = event;
+    return event;
+}
+
+/* Walk one photon from launch to termination. */
+static void walk(const orc_problem *P, uint64_t photon, orc_sink *S)
+{
+    orc_state st;
+    launch(P, photon, &st);
     orc_photon me;
     memset(&me, 0, sizeof me);
     me.min_gap = INFINITY;
-    int fate = -1;
-
+    int event;
     for (;;) {
-        const int64_t v = (iz * ny + iy) * nx + ix;
-        const int solid = (P->mask[v] == 0);
-        const double mu_t = solid ? mu_t_solid : 0.0;
-
-        /* distance to each face along the direction of travel */
-        double dist[3];
-        const double f[3] = {fx, fy, fz};
-        const double u[3] = {ux, uy, uz};
-        for (int a = 0; a < 3; ++a) {
-            if (u[a] > 0.0) dist[a] = (1.0 - f[a]) / u[a];
-            else if (u[a] < 0.0) dist[a] = f[a] / (-u[a]);
-            else dist[a] = INFINITY;
-        }
-        int axis = 0;
-        if (dist[1] < dist[axis]) axis = 1;
-        if (dist[2] < dist[axis]) axis = 2;
-        const double d_face = dist[axis];
-        const double s_int = (mu_t > 0.0) ? tau / mu_t : INFINITY;
-        const int interact = (s_int <= d_face);
-        const double d = interact ? s_int : d_face;
-
-        /* how close the step came to a different decision */
-        double gap = fabs(s_int - d_face);
-        for (int a = 0; a < 3; ++a)
-            if (a != axis && isfinite(dist[a])) {
-                double ga = fabs(dist[a] - d_face);
-                if (ga < gap) gap = ga;
-            }
+        double gap;
+        event = step(P, photon, &st, S, &me, &gap);
         if (gap < me.min_gap) me.min_gap = gap;
-        if (S->trace && (int64_t)steps < S->max_rec) {
-            orc_rec *rec = &S->trace[steps];
-            rec->ix = (int32_t)ix; rec->iy = (int32_t)iy; rec->iz = (int32_t)iz;
-            rec->fx = fx; rec->fy = fy; rec->fz = fz;
-            rec->ux = ux; rec->uy = uy; rec->uz = uz;
-            rec->w = w; rec->k = k; rec->d = d;
-            rec->tie_gap = gap;
-            rec->event = -1;
-        }
-
-        /* track-length deposit */
-        if (S->fluence) S->fluence[v] += (double)w * d;
-        if (S->depth) S->depth[(solid ? 0 : 1) * nz + iz] += (double)w * d;
-        if (S->grad) {
-            const int ph = solid ? 0 : 1;
-            const double sq = solid ? 0.5 * d * d : 0.0;
-            S->grad[(0 * 2 + ph) * nz + iz] += (double)w * (score_s * d - sq);
-            S->grad[(1 * 2 + ph) * nz + iz] += (double)w * (score_a * d - sq);
-            S->grad[(2 * 2 + ph) * nz + iz] += (double)w * (score_g * d);
-        }
-        if (solid) {
-            l_solid += d;
-            score_s -= d;
-            score_a -= d;
-        } else {
-            l_void += d;
-        }
-
-        int event;
-        if (interact) {
-            fx = clamp01(fx + ux * d);
-            fy = clamp01(fy + uy * d);
-            fz = clamp01(fz + uz * d);
-            tau = 0.0;
-            event = EV_SCATTER;
-        } else {
-            if (axis != 0) fx = clamp01(fx + ux * d);
-            if (axis != 1) fy = clamp01(fy + uy * d);
-            if (axis != 2) fz = clamp01(fz + uz * d);
-            tau -= mu_t * d;
-            if (tau < 0.0) tau = 0.0;
-            event = axis;
-        }
-        ++steps;
-
-        if (!interact) {
-            /* cross the face */
-            if (axis == 0) {
-                if (ux > 0.0) { ix += 1; fx = 0.0; if (ix == nx) ix = 0; }
-                else          { ix -= 1; fx = 1.0; if (ix < 0) ix = nx - 1; }
-            } else if (axis == 1) {
-                if (uy > 0.0) { iy += 1; fy = 0.0; if (iy == ny) iy = 0; }
-                else          { iy -= 1; fy = 1.0; if (iy < 0) iy = ny - 1; }
-            } else {
-                if (uz > 0.0) { iz += 1; fz = 0.0; }
-                else          { iz -= 1; fz = 1.0; }
-                if (iz < 0 || iz >= nz) {
-                    /* escape through an open axial face */
-                    const int top = (iz < 0);
-                    if (top) { S->sums->ich[ORC_R] += w; me.R += w; event = EV_ESC_R; }
-                    else     { S->sums->ich[ORC_T] += w; me.T += w; event = EV_ESC_T; }
-                    S->sums->ich[ORC_ESC_W] += w;
-                    S->sums->ich[ORC_ESC_N] += 1;
-                    if (l_void > (double)nz) {
-                        S->sums->ich[ORC_ESC_W_GTL] += w;
-                        S->sums->ich[ORC_ESC_N_GTL] += 1;
-                    }
-                    S->sums->dch[ORC_ESC_W_VOID_PATH] += (double)w * l_void;
-                    fate = event;
-                }
-            }
-        } else {
-            /* interaction: absorb, scatter, roulette, new free path */
-            ++k;
-            draw(P, photon, k, 0, r);
-            const int64_t w_new = (int64_t)(((uint64_t)w * S_q + 2147483648ull) >> 32);
-            S->sums->ich[ORC_A] += w - w_new;
-            me.A += w - w_new;
-            w = w_new;
-            if (w == 0) {
-                event = EV_DEAD_ABSORB;
-                fate = event;
-            } else {
-                /* Henyey-Greenstein polar angle, inverse CDF */
-                const double g = P->g, xi = u_closed_open(r[0]);
-                double ct;
-                if (g != 0.0) {
-                    const double t = (1.0 - g * g) / (1.0 - g + 2.0 * g * xi);
-                    ct = (1.0 + g * g - t * t) / (2.0 * g);
-                } else {
-                    ct = 2.0 * xi - 1.0;
-                }
-                if (ct < -1.0) ct = -1.0;
-                if (ct > 1.0) ct = 1.0;
-                const double st = sqrt(1.0 - ct * ct);
-                const double psi = 2.0 * ORC_PI * u_closed_open(r[1]);
-                const double cp = cos(psi), sp = sin(psi);
-                score_g += hg_score(ct, g);
-                if (P->mu_s > 0.0) score_s += 1.0 / P->mu_s;
-                /* rotate the direction (MCML).  The transverse norm is
-                 * sqrt(1 - uz^2) = sqrt(ux^2 + uy^2) for a unit vector; the
-                 * axis-aligned form is used only when the direction lies on the
-                 * z axis. */
-                const double tn = sqrt(ux * ux + uy * uy);
-                double nux, nuy, nuz;
-                if (tn == 0.0) {
-                    nux = st * cp;
-                    nuy = st * sp;
-                    nuz = (uz >= 0.0 ? 1.0 : -1.0) * ct;
-                } else {
-                    nux = st * (ux * uz * cp - uy * sp) / tn + ux * ct;
-                    nuy = st * (uy * uz * cp + ux * sp) / tn + uy * ct;
-                    nuz = -st * cp * tn + uz * ct;
-                }
-                const double nrm = sqrt(nux * nux + nuy * nuy + nuz * nuz);
-                ux = nux / nrm; uy = nuy / nrm; uz = nuz / nrm;
-                /* Russian roulette on the integer weight */
-                if (w < w_th) {
-                    if ((r[3] >> 8) < T_m) {
-                        const int64_t m = (int64_t)P->roulette_m;
-                        S->sums->ich[ORC_RR] -= (m - 1) * w;
-                        me.RR -= (m - 1) * w;
-                        w *= m;
-                    } else {
-                        S->sums->ich[ORC_RR] += w;
-                        me.RR += w;
-                        event = EV_DEAD_ROULETTE;
-                        fate = event;
-                    }
-                }
-                tau = -log(u_open_closed(r[2]));
-            }
-        }
-
-        if (fate < 0) {
-            const double path = l_void + l_solid;
-            if (steps >= P->max_steps || (P->path_cap > 0.0 && path > P->path_cap)) {
-                S->sums->ich[ORC_LOST] += w;
-                me.lost += w;
-                event = EV_LOST;
-                fate = event;
-            }
-        }
-        if (S->trace && (int64_t)steps - 1 < S->max_rec) S->trace[steps - 1].event = event;
-        if (fate >= 0) break;
+        if (event >= EV_ESC_R) break;
     }
-
-    S->sums->ich[ORC_STEPS] += (int64_t)steps;
-    S->sums->ich[ORC_INTERACTIONS] += (int64_t)k;
-    S->sums->dch[ORC_PATH_TOTAL] += l_void + l_solid;
-    S->sums->dch[ORC_PATH_SOLID] += l_solid;
-    S->sums->dch[ORC_PATH_VOID] += l_void;
+    S->sums->ich[ORC_STEPS] += (int64_t)st.steps;
+    S->sums->ich[ORC_INTERACTIONS] += (int64_t)st.k;
+    S->sums->dch[ORC_PATH_TOTAL] += st.l_void + st.l_solid;
+    S->sums->dch[ORC_PATH_SOLID] += st.l_solid;
+    S->sums->dch[ORC_PATH_VOID] += st.l_void;
     if (S->summary) {
-        me.w_final = w;
-        me.steps = steps;
-        me.interactions = k;
-        me.path_void = l_void;
-        me.path_solid = l_solid;
-        me.fate = fate;
+        me.w_final = st.w;
+        me.steps = st.steps;
+        me.interactions = st.k;
+        me.path_void = st.l_void;
+        me.path_solid = st.l_solid;
+        me.fate = event;
         *S->summary = me;
     }
 }
@@ -534,6 +568,25 @@ int orc_trace(const orc_problem *P, const uint64_t *ids, int32_t n, int32_t max_
     return 0;
 }
 
+/*
+ * One step of photon `photon` from the state *st (updated in place); returns the
+ * event and the step's tie gap.  Lets a test restart the reference walk from any
+ * state another implementation reports.  Tallies of the step are discarded.
+ */
+int orc_step(const orc_problem *P, uint64_t photon, orc_state *st, double *gap)
+{
+    if (!valid(P) || !st) return -1;
+    orc_sums sums;
+    memset(&sums, 0, sizeof sums);
+    orc_sink S;
+    memset(&S, 0, sizeof S);
+    S.sums = &sums;
+    orc_photon me;
+    memset(&me, 0, sizeof me);
+    return step(P, photon, st, &S, &me, gap);
+}
+
+int orc_sizeof_state(void) { return (int)sizeof(orc_state); }
 int orc_sizeof_rec(void) { return (int)sizeof(orc_rec); }
 int orc_sizeof_photon(void) { return (int)sizeof(orc_photon); }
 int orc_sizeof_problem(void) { return (int)sizeof(orc_problem); }

@@ -87,7 +87,8 @@ __global__ void k_pack(const uint8_t *__restrict__ mask, int32_t nx, int32_t ny,
 // Sinks: where a step's side effects go
 // ---------------------------------------------------------------------------
 struct TallySink {
-    __device__ __forceinline__ void segment(const Photon &, const Job &, float, bool) {}
+    template <typename R> __device__ __forceinline__ void segment(const Photon<R> &, const Job &, R, bool) {}
+    template <typename R> __device__ __forceinline__ void deflect(const Photon<R> &, const Job &, R) {}
     __device__ __forceinline__ void flush(const Job &J, uint64_t v, uint64_t acc)
     {
         if (acc != 0ull)
@@ -97,17 +98,18 @@ struct TallySink {
 };
 
 // Terminal outcome of one photon into the block's channel accumulators (LDS).
-__device__ __forceinline__ void account(unsigned long long *acc, const Photon &p, int32_t ev, int32_t nz)
+template <typename R>
+__device__ __forceinline__ void account(unsigned long long *acc, const Photon<R> &p, int32_t ev, int32_t nz)
 {
     if (ev == EV_ESC_R || ev == EV_ESC_T) {
         atomicAdd(&acc[ev == EV_ESC_R ? MC_S_R : MC_S_T], (unsigned long long)p.w);
         atomicAdd(&acc[MC_S_ESC_W], (unsigned long long)p.w);
         atomicAdd(&acc[MC_S_ESC_N], 1ull);
-        if (p.l_void > (float)nz) {
+        if (p.l_void > (double)nz) {
             atomicAdd(&acc[MC_S_ESC_W_GTL], (unsigned long long)p.w);
             atomicAdd(&acc[MC_S_ESC_N_GTL], 1ull);
         }
-        atomicAdd(&acc[MC_S_ESC_W_VOID_PATH], __float2ull_rn((float)p.w * p.l_void));
+        atomicAdd(&acc[MC_S_ESC_W_VOID_PATH], (unsigned long long)__double2ll_rn((double)p.w * p.l_void));
     } else if (ev == EV_LOST) {
         atomicAdd(&acc[MC_S_LOST], (unsigned long long)p.w);
     }
@@ -127,7 +129,7 @@ __device__ __forceinline__ void account(unsigned long long *acc, const Photon &p
 // run converged.  A wavefront exits when the queue is exhausted, its range is
 // empty and none of its lanes is alive; every photon terminates (escape,
 // weight 0, roulette, or the step cap), so every wavefront exits.
-template <int BLOCK>
+template <int BLOCK, typename R>
 __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long *__restrict__ queue, int32_t chunk,
                                                 int32_t refill)
 {
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
     __syncthreads();
 
     TallySink sink;
-    Photon p;
+    Photon<R> p;
     bool alive = false;
     uint64_t q_next = 0, q_end = 0;
     bool exhausted = false;
@@ -192,16 +194,18 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
 struct TraceSink {
     mc_trace_rec *rec;
     int32_t max_rec, n;
-    __device__ __forceinline__ void segment(const Photon &p, const Job &, float d, bool)
+    template <typename R>
+    __device__ __forceinline__ void segment(const Photon<R> &p, const Job &, R d, bool)
     {
         if (n < max_rec) {
             mc_trace_rec &r = rec[n];
             r.ix = p.ix; r.iy = p.iy; r.iz = p.iz; r.event = -1;
             r.fx = p.fx; r.fy = p.fy; r.fz = p.fz;
             r.ux = p.ux; r.uy = p.uy; r.uz = p.uz;
-            r.d = d; r.w = p.w; r.k = p.k; r.reserved = 0u;
+            r.d = d; r.s_rem = p.s_rem; r.w = p.w; r.k = p.k;
         }
     }
+    template <typename R> __device__ __forceinline__ void deflect(const Photon<R> &, const Job &, R) {}
     __device__ __forceinline__ void flush(const Job &, uint64_t, uint64_t) {}
     __device__ __forceinline__ void post(int32_t ev)
     {
@@ -210,6 +214,7 @@ struct TraceSink {
     }
 };
 
+template <typename R>
 __global__ void k_trace(const Job J, const uint64_t *__restrict__ ids, int32_t n, int32_t max_rec,
                         mc_trace_rec *__restrict__ recs, mc_photon_rec *__restrict__ out)
 {
@@ -217,7 +222,7 @@ __global__ void k_trace(const Job J, const uint64_t *__restrict__ ids, int32_t n
     if (i >= n) return;
     TraceSink sink{recs + (int64_t)i * max_rec, max_rec, 0};
     for (int32_t j = 0; j < max_rec; ++j) sink.rec[j].event = -1;
-    Photon p;
+    Photon<R> p;
     launch(p, J, (uint32_t)ids[i]);
     int32_t ev;
     for (;;) {
@@ -427,7 +432,7 @@ int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, 
     J->nxb = d.nxb;
     J->nyb = d.nyb;
     const double mu_s = opt->mu_s, mu_a = opt->mu_a, mu_t = mu_s + mu_a;
-    J->mu_t = opt->mu_s + opt->mu_a;
+    J->mu_t = mu_t;
     J->g = opt->g;
     J->path_cap = opt->path_cap > 0.0f ? opt->path_cap : kInf;
     J->s_q = mu_t > 0.0 ? (uint64_t)llround(mu_s / mu_t * 4294967296.0) : 0ull;
@@ -500,13 +505,25 @@ struct Timing {
 };
 thread_local Timing g_timing;
 
-int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s, bool timed)
+template <typename R>
+void enqueue_walk(int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s)
+{
+    switch (block) {
+    case 64: hipLaunchKernelGGL((k_walk<64, R>), dim3(blocks), dim3(64), 0, s, J, queue, t.chunk, t.refill); break;
+    case 128: hipLaunchKernelGGL((k_walk<128, R>), dim3(blocks), dim3(128), 0, s, J, queue, t.chunk, t.refill); break;
+    case 256: hipLaunchKernelGGL((k_walk<256, R>), dim3(blocks), dim3(256), 0, s, J, queue, t.chunk, t.refill); break;
+    default: hipLaunchKernelGGL((k_walk<512, R>), dim3(blocks), dim3(512), 0, s, J, queue, t.chunk, t.refill); break;
+    }
+}
+
+int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s, int flags)
 {
     DeviceInfo di;
     int rc = device_info(&di);
     if (rc) return rc;
     const int waves_per_block = t.block / 64;
     const int blocks = std::max(1, di.cus * t.waves_per_cu / waves_per_block);
+    const bool timed = (flags & MC_TIMED) != 0;
     if (timed) {
         if (!g_timing.start) {
             HIP_TRY(hipEventCreate(&g_timing.start));
@@ -514,13 +531,8 @@ int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipSt
         }
         HIP_TRY(hipEventRecord(g_timing.start, s));
     }
-    switch (t.block) {
-    case 64: hipLaunchKernelGGL(k_walk<64>, dim3(blocks), dim3(64), 0, s, J, queue, t.chunk, t.refill); break;
-    case 128: hipLaunchKernelGGL(k_walk<128>, dim3(blocks), dim3(128), 0, s, J, queue, t.chunk, t.refill); break;
-    case 256: hipLaunchKernelGGL(k_walk<256>, dim3(blocks), dim3(256), 0, s, J, queue, t.chunk, t.refill); break;
-    case 512: hipLaunchKernelGGL(k_walk<512>, dim3(blocks), dim3(512), 0, s, J, queue, t.chunk, t.refill); break;
-    default: return fail(MC_EINVAL, "block size %d not one of 64, 128, 256, 512", t.block);
-    }
+    if (flags & MC_FP64) enqueue_walk<double>(t.block, blocks, J, queue, t, s);
+    else enqueue_walk<float>(t.block, blocks, J, queue, t, s);
     HIP_TRY(hipGetLastError());
     if (timed) {
         HIP_TRY(hipEventRecord(g_timing.stop, s));
@@ -607,7 +619,7 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
     }
     if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
     if ((rc = pack(vol, bricks, s))) return rc;
-    return launch_walk(J, queue, t, s, (flags & MC_TIMED) != 0);
+    return launch_walk(J, queue, t, s, flags);
 }
 
 int mc_walk_elapsed_ms(float *ms)
@@ -649,8 +661,8 @@ int mc_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scala
 }
 
 int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_ids, int32_t n, int32_t max_steps,
-             uint64_t seed, uint32_t stream_id, mc_trace_rec *recs, mc_photon_rec *outcome, void *workspace,
-             size_t workspace_bytes, void *hip_stream)
+             uint64_t seed, uint32_t stream_id, int flags, mc_trace_rec *recs, mc_photon_rec *outcome,
+             void *workspace, size_t workspace_bytes, void *hip_stream)
 {
     g_err[0] = 0;
     Job J;
@@ -665,8 +677,12 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
     uint64_t *bricks = (uint64_t *)((char *)workspace + kHeaderBytes);
     J.bricks = bricks;
     if ((rc = pack(vol, bricks, s))) return rc;
-    hipLaunchKernelGGL(k_trace, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, J, photon_ids, n, max_steps, recs,
-                       outcome);
+    if (flags & MC_FP64)
+        hipLaunchKernelGGL(k_trace<double>, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, J, photon_ids, n,
+                           max_steps, recs, outcome);
+    else
+        hipLaunchKernelGGL(k_trace<float>, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, J, photon_ids, n,
+                           max_steps, recs, outcome);
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }

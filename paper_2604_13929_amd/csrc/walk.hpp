@@ -10,8 +10,11 @@
 // event, the face axis taken as the first minimum in x, y, z order, an
 // interaction winning a tie against a face, in-voxel offsets clamped to [0,1].
 //
-// Position is an integer voxel index plus an FP32 offset in [0,1] per axis,
-// so FP32 keeps ~1e-7 voxel resolution anywhere in the volume.
+// Position is an integer voxel index plus an offset in [0,1] per axis.  The
+// geometry and scattering arithmetic is templated on R: float (the default
+// transport) or double (a reference transport whose trajectories follow an
+// FP64 evaluation of the same steps).  The remaining free path and the path
+// sums are FP64 in both, since they accumulate over many segments.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -38,7 +41,7 @@ struct Job {
     int64_t *scalars;         // [MC_NSCALARS]
     int32_t nx, ny, nz;
     int32_t nxb, nyb;         // bricks along x and y
-    float mu_t;               // mu_s + mu_a of the solid
+    double mu_t;              // mu_s + mu_a of the solid, summed in FP64 on the host
     float g;
     float path_cap;           // +inf when off
     uint64_t s_q;             // round(mu_s / mu_t * 2^32), <= 2^32
@@ -54,12 +57,13 @@ struct Job {
     uint64_t queue_begin;     // this job's offset in the launch-wide queue
 };
 
+template <typename R>
 struct Photon {
     int32_t ix, iy, iz;
-    float fx, fy, fz;
-    float ux, uy, uz;
-    float s_rem;              // remaining free path, in solid path length
-    float l_void, l_tot;
+    R fx, fy, fz;
+    R ux, uy, uz;
+    double s_rem;             // remaining free path, in solid path length
+    double l_void, l_tot;     // path inside pores, total path
     uint32_t w, k, steps, pid;
     uint64_t absorbed;        // weight absorbed by this photon so far
     int64_t rr;               // roulette balance of this photon
@@ -68,6 +72,19 @@ struct Photon {
     uint32_t solid;           // current voxel is solid
     uint64_t bits;            // cached brick
 };
+
+// precision-generic helpers
+__device__ __forceinline__ float r_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double r_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ void r_sincospi(float x, float *s, float *c) { sincospif(x, s, c); }
+__device__ __forceinline__ void r_sincospi(double x, double *s, double *c) { sincospi(x, s, c); }
+__device__ __forceinline__ uint64_t r_to_u64(float x) { return __float2ull_rn(x); }
+__device__ __forceinline__ uint64_t r_to_u64(double x) { return __double2ull_rn(x); }
+template <typename R> __device__ __forceinline__ R r_inf() { return (R)kInf; }
+template <typename R> __device__ __forceinline__ R clamp01(R x) { return fmin(fmax(x, (R)0), (R)1); }
+template <typename R> __device__ __forceinline__ R u01(uint32_t r) { return (R)(r >> 8) * (R)0x1.0p-24; }
+// 1/|u| per axis, +inf on an axis the photon does not move along
+template <typename R> __device__ __forceinline__ R inv_abs(R u) { return u != (R)0 ? (R)1 / fabs(u) : r_inf<R>(); }
 
 __device__ __forceinline__ uint32_t brick_of(const Job &J, int32_t ix, int32_t iy, int32_t iz)
 {
@@ -81,7 +98,8 @@ __device__ __forceinline__ uint32_t bit_of(int32_t ix, int32_t iy, int32_t iz)
 
 // Refresh the solid flag of the current voxel, reloading the brick only when
 // the photon has left the cached one.
-__device__ __forceinline__ void lookup(Photon &p, const Job &J)
+template <typename R>
+__device__ __forceinline__ void lookup(Photon<R> &p, const Job &J)
 {
     const uint32_t b = brick_of(J, p.ix, p.iy, p.iz);
     if (b != p.brick) {
@@ -91,26 +109,24 @@ __device__ __forceinline__ void lookup(Photon &p, const Job &J)
     p.solid = (uint32_t)((p.bits >> bit_of(p.ix, p.iy, p.iz)) & 1ull) ^ 1u;
 }
 
-__device__ __forceinline__ uint64_t voxel_index(const Job &J, const Photon &p)
+template <typename R>
+__device__ __forceinline__ uint64_t voxel_index(const Job &J, const Photon<R> &p)
 {
     return ((uint64_t)p.iz * (uint64_t)J.ny + (uint64_t)p.iy) * (uint64_t)J.nx + (uint64_t)p.ix;
 }
 
-__device__ __forceinline__ float free_path(const Job &J, uint32_t r)
+__device__ __forceinline__ double free_path(const Job &J, uint32_t r)
 {
     // tau = -ln U, U in (0,1]; the interaction lies tau / mu_t into the solid
-    return J.mu_t > 0.0f ? -logf(u01_oc(r)) / J.mu_t : kInf;
+    const double u = (double)((r >> 8) + 1u) * 0x1.0p-24;
+    return J.mu_t > 0.0 ? -log(u) / J.mu_t : (double)kInf;
 }
-
-__device__ __forceinline__ float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
-
-// 1/|u| per axis, +inf on an axis the photon does not move along.
-__device__ __forceinline__ float inv_abs(float u) { return u != 0.0f ? 1.0f / fabsf(u) : kInf; }
 
 // Launch photon `pid` (Philox block k = 0): uniform position on the z = 0 face
 // from 24-bit uniforms scaled by the face size in integer arithmetic, normal
 // incidence (or Lambertian for the test source), first free path.
-__device__ __forceinline__ void launch(Photon &p, const Job &J, uint32_t pid)
+template <typename R>
+__device__ __forceinline__ void launch(Photon<R> &p, const Job &J, uint32_t pid)
 {
     const U4 r = philox4x32_10(U4{0u, pid, J.stream_id, 0u}, J.key0, J.key1);
     const uint64_t X = (uint64_t)(r.x >> 8) * (uint64_t)J.nx;
@@ -118,25 +134,25 @@ __device__ __forceinline__ void launch(Photon &p, const Job &J, uint32_t pid)
     p.ix = (int32_t)(X >> 24);
     p.iy = (int32_t)(Y >> 24);
     p.iz = 0;
-    p.fx = (float)(uint32_t)(X & 0xFFFFFFu) * 0x1.0p-24f;
-    p.fy = (float)(uint32_t)(Y & 0xFFFFFFu) * 0x1.0p-24f;
-    p.fz = 0.0f;
-    p.ux = 0.0f;
-    p.uy = 0.0f;
-    p.uz = 1.0f;
+    p.fx = (R)(uint32_t)(X & 0xFFFFFFu) * (R)0x1.0p-24;
+    p.fy = (R)(uint32_t)(Y & 0xFFFFFFu) * (R)0x1.0p-24;
+    p.fz = (R)0;
+    p.ux = (R)0;
+    p.uy = (R)0;
+    p.uz = (R)1;
     if (J.source == 1) {
         const U4 s = philox4x32_10(U4{0u, pid, J.stream_id, 1u}, J.key0, J.key1);
-        const float ct = sqrtf(u01_co(s.x));
-        const float st = sqrtf(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
-        float sp, cp;
-        sincospif(2.0f * u01_co(s.y), &sp, &cp);
+        const R ct = r_sqrt(u01<R>(s.x));
+        const R st = r_sqrt(fmax((R)0, ((R)1 - ct) * ((R)1 + ct)));
+        R sp, cp;
+        r_sincospi((R)2 * u01<R>(s.y), &sp, &cp);
         p.ux = st * cp;
         p.uy = st * sp;
         p.uz = ct;
     }
     p.s_rem = free_path(J, r.z);
-    p.l_void = 0.0f;
-    p.l_tot = 0.0f;
+    p.l_void = 0.0;
+    p.l_tot = 0.0;
     p.w = kW1;
     p.k = 0u;
     p.steps = 0u;
@@ -153,68 +169,70 @@ __device__ __forceinline__ void launch(Photon &p, const Job &J, uint32_t pid)
 //   1 - cos = (1-g)(1-xi)(t+1-g)/den,  1 + cos = (1+g) xi (1+g+t)/den,
 // with den = 1 - g + 2 g xi and t = (1 - g^2)/den.  The transverse norm of the
 // old direction is sqrt(ux^2 + uy^2) (= sqrt(1 - uz^2) for a unit vector).
-__device__ __forceinline__ void scatter(Photon &p, const Job &J, uint32_t r0, uint32_t r1)
+// Returns cos(theta) (the gradient walk scores it).
+template <typename R>
+__device__ __forceinline__ R scatter(Photon<R> &p, const Job &J, uint32_t r0, uint32_t r1)
 {
-    const float g = J.g, xi = u01_co(r0);
-    float ct, st2;
-    if (g != 0.0f) {
-        const float den = 1.0f - g + 2.0f * g * xi;
-        const float t = (1.0f - g * g) / den;
-        ct = (1.0f + g * g - t * t) / (2.0f * g);
-        const float om = (1.0f - g) * (1.0f - xi) * (t + 1.0f - g) / den;
-        const float op = (1.0f + g) * xi * (1.0f + g + t) / den;
+    const R g = (R)J.g, xi = u01<R>(r0);
+    R ct, st2;
+    if (g != (R)0) {
+        const R den = (R)1 - g + (R)2 * g * xi;
+        const R t = ((R)1 - g * g) / den;
+        ct = ((R)1 + g * g - t * t) / ((R)2 * g);
+        const R om = ((R)1 - g) * ((R)1 - xi) * (t + (R)1 - g) / den;
+        const R op = ((R)1 + g) * xi * ((R)1 + g + t) / den;
         st2 = om * op;
     } else {
-        ct = 2.0f * xi - 1.0f;
-        st2 = 4.0f * xi * (1.0f - xi);
+        ct = (R)2 * xi - (R)1;
+        st2 = (R)4 * xi * ((R)1 - xi);
     }
-    ct = fminf(fmaxf(ct, -1.0f), 1.0f);
-    const float st = sqrtf(fmaxf(st2, 0.0f));
-    float sp, cp;
-    sincospif(2.0f * u01_co(r1), &sp, &cp);
-    const float ux = p.ux, uy = p.uy, uz = p.uz;
-    const float tn = sqrtf(ux * ux + uy * uy);
-    float nx, ny, nz;
-    if (tn == 0.0f) {
+    ct = fmin(fmax(ct, (R)-1), (R)1);
+    const R st = r_sqrt(fmax(st2, (R)0));
+    R sp, cp;
+    r_sincospi((R)2 * u01<R>(r1), &sp, &cp);
+    const R ux = p.ux, uy = p.uy, uz = p.uz;
+    const R tn = r_sqrt(ux * ux + uy * uy);
+    R nx, ny, nz;
+    if (tn == (R)0) {
         nx = st * cp;
         ny = st * sp;
-        nz = (uz >= 0.0f ? ct : -ct);
+        nz = (uz >= (R)0 ? ct : -ct);
     } else {
-        const float it = 1.0f / tn;
+        const R it = (R)1 / tn;
         nx = st * (ux * uz * cp - uy * sp) * it + ux * ct;
         ny = st * (uy * uz * cp + ux * sp) * it + uy * ct;
         nz = -st * cp * tn + uz * ct;
     }
-    const float inrm = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
+    const R inrm = (R)1 / r_sqrt(nx * nx + ny * ny + nz * nz);
     p.ux = nx * inrm;
     p.uy = ny * inrm;
     p.uz = nz * inrm;
+    return ct;
 }
 
 // One photon-step: a segment inside the current voxel that ends at a face, an
 // interaction or an escape.  Returns the event.  The Sink receives the
-// segment, the flushed per-voxel deposits and the terminal outcomes.
-template <class Sink>
-__device__ __forceinline__ int32_t step(Photon &p, const Job &J, Sink &sink)
+// segment, the flushed per-voxel deposits and the deflection cosines.
+template <typename R, class Sink>
+__device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
 {
-    const float ivx = inv_abs(p.ux), ivy = inv_abs(p.uy), ivz = inv_abs(p.uz);
-    const float dx = p.ux != 0.0f ? (p.ux > 0.0f ? 1.0f - p.fx : p.fx) * ivx : kInf;
-    const float dy = p.uy != 0.0f ? (p.uy > 0.0f ? 1.0f - p.fy : p.fy) * ivy : kInf;
-    const float dz = p.uz != 0.0f ? (p.uz > 0.0f ? 1.0f - p.fz : p.fz) * ivz : kInf;
+    const R dx = p.ux != (R)0 ? (p.ux > (R)0 ? (R)1 - p.fx : p.fx) * inv_abs(p.ux) : r_inf<R>();
+    const R dy = p.uy != (R)0 ? (p.uy > (R)0 ? (R)1 - p.fy : p.fy) * inv_abs(p.uy) : r_inf<R>();
+    const R dz = p.uz != (R)0 ? (p.uz > (R)0 ? (R)1 - p.fz : p.fz) * inv_abs(p.uz) : r_inf<R>();
     int32_t axis = 0;
-    float d_face = dx;
+    R d_face = dx;
     if (dy < d_face) { axis = 1; d_face = dy; }
     if (dz < d_face) { axis = 2; d_face = dz; }
     const bool solid = p.solid != 0u;
-    const bool interact = solid && (p.s_rem <= d_face);
-    const float d = interact ? p.s_rem : d_face;
+    const bool interact = solid && (p.s_rem <= (double)d_face);
+    const R d = interact ? (R)p.s_rem : d_face;
 
     sink.segment(p, J, d, solid);
     // track-length deposit, quantised per segment, accumulated while in this voxel
-    p.acc += (uint64_t)__float2ull_rn((float)p.w * d);
-    if (solid) p.s_rem = fmaxf(p.s_rem - d, 0.0f);
-    else p.l_void += d;
-    p.l_tot += d;
+    p.acc += r_to_u64((R)p.w * d);
+    if (solid) p.s_rem = fmax(p.s_rem - (double)d, 0.0);
+    else p.l_void += (double)d;
+    p.l_tot += (double)d;
     p.steps += 1u;
 
     int32_t ev;
@@ -231,7 +249,8 @@ __device__ __forceinline__ int32_t step(Photon &p, const Job &J, Sink &sink)
         if (w_new == 0u) {
             ev = EV_DEAD_ABSORB;
         } else {
-            scatter(p, J, r.x, r.y);
+            const R ct = scatter(p, J, r.x, r.y);
+            sink.deflect(p, J, ct);
             ev = EV_SCATTER;
             if (p.w < J.w_th) {
                 if ((r.w >> 8) < J.t_m) {
@@ -252,20 +271,20 @@ __device__ __forceinline__ int32_t step(Photon &p, const Job &J, Sink &sink)
         p.acc = 0ull;
         ev = axis;
         if (axis == 0) {
-            if (p.ux > 0.0f) { p.fx = 0.0f; p.ix = (p.ix + 1 == J.nx) ? 0 : p.ix + 1; }
-            else             { p.fx = 1.0f; p.ix = (p.ix == 0) ? J.nx - 1 : p.ix - 1; }
+            if (p.ux > (R)0) { p.fx = (R)0; p.ix = (p.ix + 1 == J.nx) ? 0 : p.ix + 1; }
+            else             { p.fx = (R)1; p.ix = (p.ix == 0) ? J.nx - 1 : p.ix - 1; }
         } else if (axis == 1) {
-            if (p.uy > 0.0f) { p.fy = 0.0f; p.iy = (p.iy + 1 == J.ny) ? 0 : p.iy + 1; }
-            else             { p.fy = 1.0f; p.iy = (p.iy == 0) ? J.ny - 1 : p.iy - 1; }
+            if (p.uy > (R)0) { p.fy = (R)0; p.iy = (p.iy + 1 == J.ny) ? 0 : p.iy + 1; }
+            else             { p.fy = (R)1; p.iy = (p.iy == 0) ? J.ny - 1 : p.iy - 1; }
         } else {
-            if (p.uz > 0.0f) { p.fz = 0.0f; p.iz += 1; }
-            else             { p.fz = 1.0f; p.iz -= 1; }
+            if (p.uz > (R)0) { p.fz = (R)0; p.iz += 1; }
+            else             { p.fz = (R)1; p.iz -= 1; }
             if (p.iz < 0) ev = EV_ESC_R;
             else if (p.iz >= J.nz) ev = EV_ESC_T;
         }
         if (ev < EV_FIRST_TERMINAL) lookup(p, J);
     }
-    if (ev < EV_FIRST_TERMINAL && (p.steps >= J.max_steps || p.l_tot > J.path_cap)) ev = EV_LOST;
+    if (ev < EV_FIRST_TERMINAL && (p.steps >= J.max_steps || p.l_tot > (double)J.path_cap)) ev = EV_LOST;
     if (ev >= EV_FIRST_TERMINAL && p.acc != 0ull) {
         // photon ends inside a voxel (absorbed, roulette, cap): flush what it left there
         sink.flush(J, voxel_index(J, p), p.acc);

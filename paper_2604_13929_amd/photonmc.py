@@ -19,6 +19,7 @@ LIB_PATH = _build.LIB
 
 MC_ACCUMULATE = 1
 MC_TIMED = 2
+MC_FP64 = 4
 NSCALARS = 16
 NSUMMARY = 32
 SCALARS = ["R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_w_void_path", "esc_n", "esc_n_gtL",
@@ -45,12 +46,12 @@ class McTune(ctypes.Structure):
                 ("refill", ctypes.c_int32)]
 
 
-TRACE_DTYPE = np.dtype([("ix", "<i4"), ("iy", "<i4"), ("iz", "<i4"), ("event", "<i4"),
-                        ("fx", "<f4"), ("fy", "<f4"), ("fz", "<f4"), ("ux", "<f4"), ("uy", "<f4"), ("uz", "<f4"),
-                        ("d", "<f4"), ("w", "<u4"), ("k", "<u4"), ("reserved", "<u4")])
+TRACE_DTYPE = np.dtype([("fx", "<f8"), ("fy", "<f8"), ("fz", "<f8"), ("ux", "<f8"), ("uy", "<f8"), ("uz", "<f8"),
+                        ("d", "<f8"), ("s_rem", "<f8"), ("w", "<u4"), ("k", "<u4"),
+                        ("ix", "<i4"), ("iy", "<i4"), ("iz", "<i4"), ("event", "<i4")])
 PHOTON_DTYPE = np.dtype([("R", "<i8"), ("T", "<i8"), ("A", "<i8"), ("RR", "<i8"), ("lost", "<i8"),
                          ("w_final", "<u4"), ("fate", "<u4"), ("steps", "<u4"), ("interactions", "<u4"),
-                         ("path_void", "<f4"), ("path_solid", "<f4")])
+                         ("path_void", "<f8"), ("path_solid", "<f8")])
 
 # exported symbols and their signatures (restype, argtypes)
 _P = ctypes.c_void_p
@@ -67,7 +68,7 @@ _SIGS = {
     "mc_reduce_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_reduce": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mc_trace": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
-                                _P, _P, _P, ctypes.c_size_t, _P]),
+                                ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P]),
 }
 
 _lib = None
@@ -168,8 +169,9 @@ def workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def run(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_begin: int = 0, stream_id: int = 0,
-        accumulate: RunResult | None = None, tune: Tune | None = None, timed: bool = False) -> RunResult:
-    """mc_run on the current stream of the mask's device."""
+        accumulate: RunResult | None = None, tune: Tune | None = None, timed: bool = False,
+        fp64: bool = False) -> RunResult:
+    """mc_run on the current stream of the mask's device (fp64: the FP64 reference transport)."""
     L = load()
     vol = volume(mask)
     dev = mask.device
@@ -181,6 +183,8 @@ def run(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_be
         res, flags = accumulate, MC_ACCUMULATE
     if timed:
         flags |= MC_TIMED
+    if fp64:
+        flags |= MC_FP64
     nbytes = L.mc_run_workspace_bytes(ctypes.byref(vol))
     ws = workspace(nbytes, dev)
     opt = optics.c()
@@ -231,7 +235,8 @@ def reduce(mask: torch.Tensor, res: RunResult) -> Summary:
     return Summary(vals, d[0], d[1], d[2])
 
 
-def trace(mask: torch.Tensor, optics: Optics, photon_ids, max_steps: int, seed: int, stream_id: int = 0):
+def trace(mask: torch.Tensor, optics: Optics, photon_ids, max_steps: int, seed: int, stream_id: int = 0,
+          fp64: bool = False):
     """Per-step records [n, max_steps] and per-photon outcomes [n] (numpy structured arrays)."""
     L = load()
     vol = volume(mask)
@@ -243,7 +248,7 @@ def trace(mask: torch.Tensor, optics: Optics, photon_ids, max_steps: int, seed: 
     ws = workspace(L.mc_run_workspace_bytes(ctypes.byref(vol)), dev)
     opt = optics.c()
     _check(L.mc_trace(ctypes.byref(vol), ctypes.byref(opt), ids.data_ptr(), n, max_steps, seed, stream_id,
-                      recs.data_ptr(), outc.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)), "mc_trace")
+                      MC_FP64 if fp64 else 0, recs.data_ptr(), outc.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)), "mc_trace")
     r = recs.cpu().numpy().reshape(-1).view(TRACE_DTYPE).reshape(n, max_steps)
     o = outc.cpu().numpy().reshape(-1).view(PHOTON_DTYPE)
     return r, o

@@ -43,8 +43,8 @@ def test_every_declared_symbol_is_exported(lib):
 def test_abi_version_and_layouts(lib):
     assert lib.mc_abi_version() == 1
     assert lib.mc_sizeof(b"mc_volume") == 24
-    assert lib.mc_sizeof(b"mc_trace_rec") == pm.TRACE_DTYPE.itemsize == 56
-    assert lib.mc_sizeof(b"mc_photon_rec") == pm.PHOTON_DTYPE.itemsize == 64
+    assert lib.mc_sizeof(b"mc_trace_rec") == pm.TRACE_DTYPE.itemsize == 88
+    assert lib.mc_sizeof(b"mc_photon_rec") == pm.PHOTON_DTYPE.itemsize == 72
     assert lib.mc_sizeof(b"nonsense") == 0
 
 
