@@ -58,7 +58,8 @@ extern "C" {
 
 /* Scalar tally channels: int64 words in a caller-owned device array of
  * MC_NSCALARS entries.  Weight channels are Q31.  For every run
- * R + T + A + RR + LOST == LAUNCHED * 2^31 exactly. */
+ * R + T + A + RR + LOST == LAUNCHED * 2^31 exactly.  One set of tallies holds
+ * fewer than 2^32 photons (so LAUNCHED * 2^31 < 2^63). */
 enum {
     MC_S_R = 0,            /* weight escaped through z = 0 (reflectance) */
     MC_S_T,                /* weight escaped through z = Nz (transmittance) */
@@ -67,12 +68,14 @@ enum {
     MC_S_LOST,             /* weight of photons stopped by the step / path cap */
     MC_S_ESC_W,            /* escaped weight, both faces */
     MC_S_ESC_W_GTL,        /* escaped weight whose in-pore path exceeds Nz */
-    MC_S_ESC_W_VOID_PATH,  /* sum of escaped weight x in-pore path (Q31 x voxel) */
+    MC_S_ESC_W_VOID_PATH,  /* sum of escaped weight x in-pore path (Q31 x voxel), low 32 bits of each
+                              photon's term (summed as unsigned) */
     MC_S_ESC_N,            /* escaped photons */
     MC_S_ESC_N_GTL,        /* escaped photons whose in-pore path exceeds Nz */
     MC_S_STEPS,            /* photon-steps (one segment inside one voxel) */
     MC_S_INTERACTIONS,     /* interaction events */
     MC_S_LAUNCHED,         /* photons launched */
+    MC_S_ESC_W_VOID_PATH_HI, /* high parts (term >> 32) of the same sum: total = HI * 2^32 + LO */
     MC_NSCALARS = 16
 };
 

@@ -43,7 +43,8 @@ def estimators(F: np.ndarray, mask: np.ndarray, n_photons: int) -> dict:
     out["phi_pore"] = (phi * m).sum() / m.sum() if m.sum() > 0 else float("nan")
     out["r"] = out["phi_pore"] / out["phi3d"]
     por = out["porosity"]
-    out["identity_rhs"] = 1.0 / (por * out["r"] + (1.0 - por))
+    # with no pore voxel the pore term of the identity is absent
+    out["identity_rhs"] = 1.0 / (por * out["r"] + (1.0 - por)) if m.sum() > 0 else 1.0
     out["ratio"] = out["phi3d"] / out["phi1d"]
     depth = phi.sum(axis=(1, 2)) / (nx * ny)
     n_s = s.sum(axis=(1, 2))

@@ -109,7 +109,10 @@ __device__ __forceinline__ void account(unsigned long long *acc, const Photon<R>
             atomicAdd(&acc[MC_S_ESC_W_GTL], (unsigned long long)p.w);
             atomicAdd(&acc[MC_S_ESC_N_GTL], 1ull);
         }
-        atomicAdd(&acc[MC_S_ESC_W_VOID_PATH], (unsigned long long)__double2ll_rn((double)p.w * p.l_void));
+        // w * l_void can reach 2^51 per photon: sum the two 32-bit halves separately
+        const unsigned long long vp = __double2ull_rn((double)p.w * p.l_void);
+        atomicAdd(&acc[MC_S_ESC_W_VOID_PATH], vp & 0xFFFFFFFFull);
+        if (vp >> 32) atomicAdd(&acc[MC_S_ESC_W_VOID_PATH_HI], vp >> 32);
     } else if (ev == EV_LOST) {
         atomicAdd(&acc[MC_S_LOST], (unsigned long long)p.w);
     }
@@ -348,7 +351,9 @@ __global__ void k_finalize(const unsigned long long *__restrict__ bins, const in
     q[MC_Q_R_CONTRAST] = q[MC_Q_PHI_PORE] / q[MC_Q_PHI3D];
     q[MC_Q_POROSITY] = (double)n_p / nvox;
     q[MC_Q_RATIO] = q[MC_Q_PHI3D] / q[MC_Q_PHI1D];
-    q[MC_Q_IDENTITY_RHS] = 1.0 / (q[MC_Q_POROSITY] * q[MC_Q_R_CONTRAST] + (1.0 - q[MC_Q_POROSITY]));
+    // with no pore voxel the pore term of the identity is absent
+    q[MC_Q_IDENTITY_RHS] =
+        n_p ? 1.0 / (q[MC_Q_POROSITY] * q[MC_Q_R_CONTRAST] + (1.0 - q[MC_Q_POROSITY])) : 1.0;
     q[MC_Q_R] = (double)S[MC_S_R] / launched_w;
     q[MC_Q_T] = (double)S[MC_S_T] / launched_w;
     q[MC_Q_A] = (double)S[MC_S_A] / launched_w;
@@ -364,7 +369,9 @@ __global__ void k_finalize(const unsigned long long *__restrict__ bins, const in
     q[MC_Q_ESC_FRAC] = (double)S[MC_S_ESC_W] / launched_w;
     q[MC_Q_PW_VOID_GTL] = S[MC_S_ESC_W] ? (double)S[MC_S_ESC_W_GTL] / (double)S[MC_S_ESC_W] : nan;
     q[MC_Q_PN_VOID_GTL] = S[MC_S_ESC_N] ? (double)S[MC_S_ESC_N_GTL] / (double)S[MC_S_ESC_N] : nan;
-    q[MC_Q_MEAN_VOID_PATH] = S[MC_S_ESC_W] ? (double)S[MC_S_ESC_W_VOID_PATH] / (double)S[MC_S_ESC_W] : nan;
+    const double void_path = join((unsigned long long)S[MC_S_ESC_W_VOID_PATH_HI],
+                                  (unsigned long long)S[MC_S_ESC_W_VOID_PATH]);
+    q[MC_Q_MEAN_VOID_PATH] = S[MC_S_ESC_W] ? void_path / (double)S[MC_S_ESC_W] : nan;
     q[MC_Q_STEPS_PER_PHOTON] = (double)S[MC_S_STEPS] / n_ph;
     q[MC_Q_INTERACTIONS_PER_PHOTON] = (double)S[MC_S_INTERACTIONS] / n_ph;
     q[MC_Q_STATUS] = mx >= (1ull << 62) ? (double)MC_EOVERFLOW : 0.0;

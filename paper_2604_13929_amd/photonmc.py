@@ -22,8 +22,8 @@ MC_TIMED = 2
 MC_FP64 = 4
 NSCALARS = 16
 NSUMMARY = 32
-SCALARS = ["R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_w_void_path", "esc_n", "esc_n_gtL",
-           "steps", "interactions", "launched"]
+SCALARS = ["R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_w_void_path_lo", "esc_n", "esc_n_gtL",
+           "steps", "interactions", "launched", "esc_w_void_path_hi"]
 SUMMARY = ["phi3d", "phi1d", "phi_pore", "r", "porosity", "ratio", "identity_rhs", "R", "T", "A", "RR", "lost",
            "closure_exact", "front_back", "L_opt", "esc_frac", "Pw_void_gtL", "Pn_void_gtL", "mean_void_path",
            "steps_per_photon", "interactions_per_photon", "status", "n_solid", "launched"]
@@ -154,7 +154,9 @@ class RunResult:
 
     def scalar_dict(self) -> dict:
         s = self.scalars.cpu().tolist()
-        return {name: int(s[i]) for i, name in enumerate(SCALARS)}
+        d = {name: int(s[i]) for i, name in enumerate(SCALARS)}
+        d["esc_w_void_path"] = (d["esc_w_void_path_hi"] << 32) + (d["esc_w_void_path_lo"] % (1 << 64))
+        return d
 
 
 def volume(mask: torch.Tensor) -> McVolume:
