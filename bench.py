@@ -49,7 +49,36 @@ def main():
     ap.add_argument("--photons", type=int, default=100_000_000)
     ap.add_argument("--cpu-photons", type=int, default=1_000_000, help="oracle sample size (first ids)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--scatter-probe", action="store_true",
+                    help="only measure random 64-bit scatter / atomic throughput (the deposit roofline)")
     args = ap.parse_args()
+    if args.scatter_probe:
+        import torch
+
+        from paper_2604_13929_amd import photonmc as pm
+        pm.load()
+        out = {}
+        names = {0: "atomic64_device", 1: "atomic64_workgroup", 2: "store64", 3: "atomic32_device",
+                 4: "atomic64_device_wave_contiguous"}
+        for mib in (2, 128, 512, 2048):
+            t = torch.zeros(mib * 1024 * 1024 // 8, dtype=torch.int64, device="cuda:0")
+            for mode in names:
+                pm.probe_scatter(t, 1 << 24, mode)
+                out[f"{names[mode]}_{mib}MiB"] = pm.probe_scatter(t, 1 << 30, mode)
+                log(f"{mib:5d} MiB {names[mode]:32s} {out[f'{names[mode]}_{mib}MiB'] / 1e9:8.2f} G ops/s")
+            del t
+        print(json.dumps({"scatter_probe_ops_per_s": out}))
+        return
+    if args.copy_probe:
+        import torch
+        x = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")   # 1 GiB
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 8}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is not built",
                           "n_gpus": args.gpus}))

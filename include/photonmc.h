@@ -216,6 +216,17 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
              int32_t max_steps, uint64_t seed, uint32_t stream_id, int flags, mc_trace_rec *recs,
              mc_photon_rec *outcome, void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/*
+ * Roofline probe (measurement only, not part of the walk): n_ops random 64-bit
+ * scatter operations over a device table of n_entries int64 (a power of two),
+ * spread over 16 waves per compute unit.  mode 0: device-scope atomic add (what
+ * the walk's fluence deposit does); 1: workgroup-scope atomic add; 2: plain
+ * store; 3: device-scope 32-bit atomic add; 4: device-scope atomic add with the
+ * 64 lanes of a wavefront on 64 consecutive entries.  The table's contents
+ * afterwards are meaningless.
+ */
+int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mode, void *hip_stream);
+
 /* Text for a status code. */
 const char *mc_strerror(int status);
 /* Message of the last error on this thread ("" if none). */

@@ -380,6 +380,45 @@ __global__ void k_finalize(const unsigned long long *__restrict__ bins, const in
 }
 
 // ---------------------------------------------------------------------------
+// Roofline probe: random 64-bit scatter-adds, the walk's deposit pattern
+// without the walk.  Addresses come from a 64-bit mixer of (thread, i); the
+// table size is a power of two.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t x)
+{
+    // SplitMix64 finaliser (Steele, Lea & Flood, OOPSLA 2014)
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_probe(unsigned long long *__restrict__ table, uint64_t mask, uint64_t per_thread)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t wave = t >> 6, lane = t & 63;
+    for (uint64_t i = 0; i < per_thread; ++i) {
+        const uint64_t a = mix64(t * per_thread + i) & mask;
+        if (MODE == 0) {
+            __hip_atomic_fetch_add(table + a, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (MODE == 1) {
+            __hip_atomic_fetch_add(table + a, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else if (MODE == 2) {
+            table[a] = i;
+        } else if (MODE == 3) {
+            // 32-bit atomic add at a random 32-bit slot
+            unsigned int *t32 = (unsigned int *)table;
+            __hip_atomic_fetch_add(t32 + ((a << 1) | (i & 1)), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // the 64 lanes of a wavefront hit 64 consecutive slots of one random block
+            const uint64_t blk = mix64(wave * per_thread + i) & (mask & ~63ull);
+            __hip_atomic_fetch_add(table + blk + lane, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 namespace {
@@ -694,4 +733,29 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
     return MC_OK;
 }
 
+int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mode, void *hip_stream)
+{
+    g_err[0] = 0;
+    if (!table || n_entries == 0 || (n_entries & (n_entries - 1)) != 0)
+        return fail(MC_EINVAL, "table must be non-NULL with a power-of-two entry count");
+    if (mode < 0 || mode > 4) return fail(MC_EINVAL, "mode must be in [0, 4]");
+    if (mode == 4 && n_entries < 64) return fail(MC_EINVAL, "mode 4 needs at least 64 entries");
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc) return rc;
+    const uint64_t threads = (uint64_t)di.cus * 16 * 64;
+    const uint64_t per_thread = std::max<uint64_t>(1, n_ops / threads);
+    const unsigned blocks = (unsigned)(threads / 256);
+    hipStream_t s = (hipStream_t)hip_stream;
+    unsigned long long *t = (unsigned long long *)table;
+    if (mode == 0) hipLaunchKernelGGL(k_probe<0>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
+    else if (mode == 1) hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
+    else if (mode == 2) hipLaunchKernelGGL(k_probe<2>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
+    else if (mode == 3) hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
+    else hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
 }  // extern "C"
+

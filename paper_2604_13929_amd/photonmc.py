@@ -67,6 +67,7 @@ _SIGS = {
     "mc_walk_elapsed_ms": (ctypes.c_int, [_P]),
     "mc_reduce_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_reduce": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mc_probe_scatter": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, _P]),
     "mc_trace": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
                                 ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P]),
 }
@@ -254,3 +255,17 @@ def trace(mask: torch.Tensor, optics: Optics, photon_ids, max_steps: int, seed: 
     r = recs.cpu().numpy().reshape(-1).view(TRACE_DTYPE).reshape(n, max_steps)
     o = outc.cpu().numpy().reshape(-1).view(PHOTON_DTYPE)
     return r, o
+
+
+def probe_scatter(table: torch.Tensor, n_ops: int, mode: int = 0) -> float:
+    """Time mc_probe_scatter on the current stream; returns operations per second."""
+    L = load()
+    dev = table.device
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    _check(L.mc_probe_scatter(table.data_ptr(), table.numel(), n_ops, mode, _stream(dev)), "mc_probe_scatter")
+    stop.record()
+    stop.synchronize()
+    threads = torch.cuda.get_device_properties(dev).multi_processor_count * 16 * 64
+    done = max(1, n_ops // threads) * threads
+    return done / (start.elapsed_time(stop) * 1e-3)
