@@ -227,6 +227,63 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
  */
 int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mode, void *hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched runs: many volumes of uneven size, porosity and optics in one
+ * persistent launch.  Every job draws its own Philox streams (seed, stream_id),
+ * so job k of a batch is bitwise identical to mc_run of that job alone, for any
+ * launch shape.
+ * ------------------------------------------------------------------------- */
+#define MC_MAX_BATCH_JOBS 64
+
+typedef struct {
+    mc_volume vol;
+    mc_optics opt;
+    uint64_t photon_begin, n_photons, seed;
+    uint32_t stream_id;
+    int32_t accumulate;    /* nonzero: add to this job's tallies instead of zeroing them */
+    int64_t *fluence;      /* device int64[nz][ny][nx] */
+    int64_t *scalars;      /* device int64[MC_NSCALARS] */
+    double *summary;       /* device double[MC_NSUMMARY]: also reduce this job; NULL: no reduction */
+    double *depth;         /* device double[3][nz] or NULL (as mc_reduce) */
+} mc_job;
+
+/* Workspace (device bytes) a batch of these jobs needs; 0 for an invalid batch. */
+size_t mc_batch_workspace_bytes(const mc_job *jobs, int32_t n_jobs);
+
+/*
+ * Run 1..MC_MAX_BATCH_JOBS jobs: zero (unless accumulate) and pack every job,
+ * one persistent walk over all photons of all jobs (queued longest job first),
+ * then the reduction of every job that has a summary buffer.  flags: MC_FP64,
+ * MC_TIMED (times the walk kernel).  tune NULL: the launch shape cached for
+ * this batch's shape class (device, precision, job count, total voxels and
+ * photons, each rounded to a power of two) is used, or found by
+ * mc_autotune_batch first and cached (file $PHOTONMC_TUNE_CACHE, else
+ * ~/.cache/photonmc_tune.txt; MC_EINVAL if a job accumulates then, as the
+ * tuning trials write to the tallies).  Errors: MC_EINVAL (a job is invalid;
+ * the message names it), MC_ENOSPACE, MC_EHIP.
+ */
+int mc_run_batch(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune, void *workspace,
+                 size_t workspace_bytes, void *hip_stream);
+
+/*
+ * Find a fast launch shape for this batch by timed trials on a scaled-down copy
+ * of it (about 2^22 photons per trial; coordinate descent over waves per CU,
+ * block size, chunk and refill), store it in the tune cache and return it.
+ * Synchronises the stream.  Overwrites the jobs' tallies with meaningless
+ * values (MC_EINVAL if a job accumulates).
+ */
+int mc_autotune_batch(const mc_job *jobs, int32_t n_jobs, int flags, void *workspace, size_t workspace_bytes,
+                      mc_tune *out, void *hip_stream);
+
+/* A captured HIP graph of a whole batched step (what mc_run_batch enqueues, with
+ * a fixed tune), replayable with one launch.  All buffers named by the jobs and
+ * the workspace are baked in and must outlive the graph. */
+typedef struct mc_graph_s *mc_graph;
+int mc_batch_graph_create(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune, void *workspace,
+                          size_t workspace_bytes, mc_graph *out);
+int mc_graph_launch(mc_graph graph, void *hip_stream);
+int mc_graph_destroy(mc_graph graph);
+
 /* Text for a status code. */
 const char *mc_strerror(int status);
 /* Message of the last error on this thread ("" if none). */
@@ -234,8 +291,8 @@ const char *mc_last_error(void);
 /* Library ABI version (MC_ABI_VERSION). */
 int mc_abi_version(void);
 /* sizeof one of the ABI structs by name ("mc_volume", "mc_optics", "mc_tune",
- * "mc_trace_rec", "mc_photon_rec"), 0 for an unknown name; lets a binding check
- * its layouts. */
+ * "mc_trace_rec", "mc_photon_rec", "mc_job"), 0 for an unknown name; lets a
+ * binding check its layouts. */
 size_t mc_sizeof(const char *type_name);
 
 #ifdef __cplusplus

@@ -1,0 +1,595 @@
+// batch.hip -- many masks of uneven size, porosity and optics in one
+// persistent launch; a captured HIP graph of the whole batched step; and the
+// launch-shape autotuner with its on-disk cache.
+//
+// The job table is ordered longest-first (photons x depth as the cost
+// estimate) and concatenated into one photon queue; a wavefront's chunk may
+// straddle two jobs, so every lane carries its own job index and reads that
+// job's constants from a copy of the table staged in LDS.  Each job draws its
+// own Philox streams (seed, stream id), so job k of a batch is bitwise the same
+// as a plain run of that job.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <sys/stat.h>
+
+#include <algorithm>
+#include <functional>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace pmc;
+using namespace pmc::host;
+
+static_assert(sizeof(Job) % 8 == 0, "job table is staged in 8-byte words");
+
+namespace {
+
+// Writes up to 8 job descriptors, passed by value, into the device table.
+struct JobPack {
+    Job j[8];
+};
+
+__global__ void k_write_jobs(JobPack pack, Job *__restrict__ dst, int32_t count)
+{
+    const int32_t w = (int32_t)(sizeof(Job) / 8);
+    const uint64_t *src = (const uint64_t *)pack.j;
+    uint64_t *d = (uint64_t *)dst;
+    for (int32_t i = threadIdx.x; i < count * w; i += blockDim.x) d[i] = src[i];
+}
+
+struct BatchTallySink {
+    template <typename R> __device__ __forceinline__ void segment(const Photon<R> &, const Job &, R, bool) {}
+    template <typename R> __device__ __forceinline__ void deflect(const Photon<R> &, const Job &, R) {}
+    __device__ __forceinline__ void flush(const Job &J, uint64_t v, uint64_t a)
+    {
+        if (a != 0ull)
+            __hip_atomic_fetch_add((unsigned long long *)(J.fluence + v), (unsigned long long)a, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ void account_job(unsigned long long *acc, const Photon<R> &p, int32_t ev, int32_t nz)
+{
+    if (ev == EV_ESC_R || ev == EV_ESC_T) {
+        atomicAdd(&acc[ev == EV_ESC_R ? MC_S_R : MC_S_T], (unsigned long long)p.w);
+        atomicAdd(&acc[MC_S_ESC_W], (unsigned long long)p.w);
+        atomicAdd(&acc[MC_S_ESC_N], 1ull);
+        if (p.l_void > (double)nz) {
+            atomicAdd(&acc[MC_S_ESC_W_GTL], (unsigned long long)p.w);
+            atomicAdd(&acc[MC_S_ESC_N_GTL], 1ull);
+        }
+        const unsigned long long vp = __double2ull_rn((double)p.w * p.l_void);
+        atomicAdd(&acc[MC_S_ESC_W_VOID_PATH], vp & 0xFFFFFFFFull);
+        if (vp >> 32) atomicAdd(&acc[MC_S_ESC_W_VOID_PATH_HI], vp >> 32);
+    } else if (ev == EV_LOST) {
+        atomicAdd(&acc[MC_S_LOST], (unsigned long long)p.w);
+    }
+    if (p.absorbed) atomicAdd(&acc[MC_S_A], (unsigned long long)p.absorbed);
+    if (p.rr) atomicAdd(&acc[MC_S_RR], (unsigned long long)p.rr);
+    atomicAdd(&acc[MC_S_STEPS], (unsigned long long)p.steps);
+    atomicAdd(&acc[MC_S_INTERACTIONS], (unsigned long long)p.k);
+    atomicAdd(&acc[MC_S_LAUNCHED], 1ull);
+}
+
+// Same queue discipline as the plain walk: a wavefront-private range of queue
+// positions refilled by one atomic, idle lanes refilled together, exit once
+// the queue is exhausted and no lane is alive.
+template <int BLOCK, typename R>
+__global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jobs, int32_t n_jobs,
+                                                      unsigned long long *__restrict__ queue, int32_t chunk,
+                                                      int32_t refill)
+{
+    __shared__ Job s_jobs[MC_MAX_BATCH_JOBS];
+    __shared__ unsigned long long acc[MC_MAX_BATCH_JOBS][MC_NSCALARS];
+    {
+        const uint64_t *src = (const uint64_t *)jobs;
+        uint64_t *dst = (uint64_t *)s_jobs;
+        const int32_t words = n_jobs * (int32_t)(sizeof(Job) / 8);
+        for (int32_t i = threadIdx.x; i < words; i += BLOCK) dst[i] = src[i];
+        unsigned long long *a = &acc[0][0];
+        for (int32_t i = threadIdx.x; i < n_jobs * MC_NSCALARS; i += BLOCK) a[i] = 0ull;
+    }
+    __syncthreads();
+
+    const uint64_t total = s_jobs[n_jobs - 1].queue_begin + s_jobs[n_jobs - 1].n_photons;
+    BatchTallySink sink;
+    Photon<R> p;
+    int32_t job = 0;
+    bool alive = false;
+    uint64_t q_next = 0, q_end = 0;
+    bool exhausted = false;
+    const uint32_t lane = __lane_id();
+
+    for (;;) {
+        const uint64_t idle = __ballot(!alive);
+        if (idle != 0ull) {
+            const int32_t nidle = __popcll(idle);
+            if (!exhausted && (nidle >= refill || idle == ~0ull)) {
+                if (q_next >= q_end) {
+                    unsigned long long base = 0ull;
+                    if (lane == 0) base = atomicAdd(queue, (unsigned long long)chunk);
+                    base = __shfl(base, 0);
+                    if (base >= total) {
+                        exhausted = true;
+                    } else {
+                        q_next = base;
+                        q_end = base + (uint64_t)chunk < total ? base + (uint64_t)chunk : total;
+                    }
+                }
+                if (q_next < q_end) {
+                    const uint64_t avail = q_end - q_next;
+                    const uint32_t rank = (uint32_t)__popcll(idle & __lanemask_lt());
+                    if (!alive && rank < avail) {
+                        const uint64_t q = q_next + rank;
+                        int32_t lo = 0, hi = n_jobs - 1;  // last job whose range starts at or before q
+                        while (lo < hi) {
+                            const int32_t mid = (lo + hi + 1) >> 1;
+                            if (s_jobs[mid].queue_begin <= q) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        job = lo;
+                        const Job &J = s_jobs[job];
+                        launch(p, J, (uint32_t)(J.photon_begin + (q - J.queue_begin)));
+                        alive = true;
+                    }
+                    q_next += (uint64_t)nidle < avail ? (uint64_t)nidle : avail;
+                }
+            }
+            if (exhausted && q_next >= q_end && !__any(alive)) break;
+        }
+        if (alive) {
+            const Job &J = s_jobs[job];
+            const int32_t ev = step(p, J, sink);
+            if (ev >= EV_FIRST_TERMINAL) {
+                account_job(acc[job], p, ev, J.nz);
+                alive = false;
+            }
+        }
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n_jobs * MC_NSCALARS; i += BLOCK) {
+        const unsigned long long v = acc[i / MC_NSCALARS][i % MC_NSCALARS];
+        if (v) atomicAdd((unsigned long long *)&s_jobs[i / MC_NSCALARS].scalars[i % MC_NSCALARS], v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t jobs_off, bricks_off[MC_MAX_BATCH_JOBS], bins_off[MC_MAX_BATCH_JOBS], total;
+};
+
+Layout layout_of(const mc_job *jobs, int32_t n)
+{
+    Layout L;
+    size_t off = kHeaderBytes;
+    L.jobs_off = off;
+    off += align_up(sizeof(Job) * MC_MAX_BATCH_JOBS);
+    for (int32_t i = 0; i < n; ++i) {
+        L.bricks_off[i] = off;
+        off += align_up(dims_of(&jobs[i].vol).nbricks * sizeof(uint64_t));
+        L.bins_off[i] = off;
+        off += align_up((size_t)jobs[i].vol.nz * kBinW * sizeof(uint64_t));
+    }
+    L.total = off;
+    return L;
+}
+
+// A validated batch: device job descriptors in queue (longest-first) order.
+struct Prepared {
+    std::vector<Job> table;       // queue order
+    std::vector<int32_t> order;   // table index -> caller's job index
+    Layout L;
+    uint64_t total_photons = 0;
+};
+
+int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, Prepared *P)
+{
+    if (!jobs || n < 1 || n > MC_MAX_BATCH_JOBS)
+        return fail(MC_EINVAL, "a batch holds 1 to %d jobs (got %d)", MC_MAX_BATCH_JOBS, n);
+    if (!ws) return fail(MC_EINVAL, "workspace is NULL");
+    char msg[512];
+    for (int32_t i = 0; i < n; ++i) {
+        int rc = check_volume(&jobs[i].vol);
+        if (rc) {
+            snprintf(msg, sizeof msg, "%s", mc_last_error());
+            return fail(rc, "job %d: %s", i, msg);
+        }
+    }
+    P->L = layout_of(jobs, n);
+    if (ws_bytes < P->L.total) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, P->L.total);
+    P->order.resize(n);
+    for (int32_t i = 0; i < n; ++i) P->order[i] = i;
+    // longest first; ties keep the caller's order
+    std::stable_sort(P->order.begin(), P->order.end(), [&](int32_t a, int32_t b) {
+        const double ca = (double)jobs[a].n_photons * jobs[a].vol.nz, cb = (double)jobs[b].n_photons * jobs[b].vol.nz;
+        return ca > cb;
+    });
+    P->table.resize(n);
+    uint64_t q = 0;
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t i = P->order[t];
+        const mc_job &jb = jobs[i];
+        Job &J = P->table[t];
+        int rc = make_job(&jb.vol, &jb.opt, jb.photon_begin, jb.n_photons, jb.seed, jb.stream_id, &J);
+        if (rc) {
+            snprintf(msg, sizeof msg, "%s", mc_last_error());
+            return fail(rc, "job %d: %s", i, msg);
+        }
+        if (!jb.fluence || !jb.scalars) return fail(MC_EINVAL, "job %d: fluence and scalars must be non-NULL", i);
+        J.bricks = (const uint64_t *)(ws + P->L.bricks_off[i]);
+        J.fluence = jb.fluence;
+        J.scalars = jb.scalars;
+        J.queue_begin = q;
+        q += jb.n_photons;
+    }
+    P->total_photons = q;
+    return MC_OK;
+}
+
+template <typename R>
+void enqueue_batch_walk(int block, int blocks, const Job *table, int32_t n, unsigned long long *queue,
+                        const mc_tune &t, hipStream_t s)
+{
+    switch (block) {
+    case 64:
+        hipLaunchKernelGGL((k_walk_batch<64, R>), dim3(blocks), dim3(64), 0, s, table, n, queue, t.chunk, t.refill);
+        break;
+    case 128:
+        hipLaunchKernelGGL((k_walk_batch<128, R>), dim3(blocks), dim3(128), 0, s, table, n, queue, t.chunk, t.refill);
+        break;
+    case 256:
+        hipLaunchKernelGGL((k_walk_batch<256, R>), dim3(blocks), dim3(256), 0, s, table, n, queue, t.chunk, t.refill);
+        break;
+    default:
+        hipLaunchKernelGGL((k_walk_batch<512, R>), dim3(blocks), dim3(512), 0, s, table, n, queue, t.chunk, t.refill);
+        break;
+    }
+}
+
+int enqueue_table(const Prepared &P, char *ws, hipStream_t s)
+{
+    Job *dst = (Job *)(ws + P.L.jobs_off);
+    const int32_t n = (int32_t)P.table.size();
+    for (int32_t i = 0; i < n; i += 8) {
+        JobPack pack;
+        memset(&pack, 0, sizeof pack);
+        const int32_t c = std::min(8, n - i);
+        for (int32_t k = 0; k < c; ++k) pack.j[k] = P.table[i + k];
+        hipLaunchKernelGGL(k_write_jobs, dim3(1), dim3(256), 0, s, pack, dst + i, c);
+        HIP_TRY(hipGetLastError());
+    }
+    return MC_OK;
+}
+
+// The walk alone (table written, tallies zeroed and masks packed beforehand).
+int enqueue_walk_only(const Prepared &P, char *ws, const mc_tune &t, int flags, hipStream_t s)
+{
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc) return rc;
+    if ((rc = fill((int64_t *)ws, kHeaderBytes / 8, s))) return rc;
+    const int blocks = std::max(1, di.cus * t.waves_per_cu / (t.block / 64));
+    const Job *table = (const Job *)(ws + P.L.jobs_off);
+    unsigned long long *queue = (unsigned long long *)ws;
+    const int32_t n = (int32_t)P.table.size();
+    if (flags & MC_FP64) enqueue_batch_walk<double>(t.block, blocks, table, n, queue, t, s);
+    else enqueue_batch_walk<float>(t.block, blocks, table, n, queue, t, s);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+// The whole batched step: table, zeroed tallies, packed masks, one walk, reductions.
+int enqueue_batch(const mc_job *jobs, const Prepared &P, char *ws, const mc_tune &t, int flags, hipStream_t s)
+{
+    int rc = enqueue_table(P, ws, s);
+    if (rc) return rc;
+    const int32_t n = (int32_t)P.table.size();
+    for (int32_t i = 0; i < n; ++i) {
+        const mc_job &jb = jobs[i];
+        if (!jb.accumulate) {
+            if ((rc = fill(jb.fluence, dims_of(&jb.vol).nvox, s))) return rc;
+            if ((rc = fill(jb.scalars, MC_NSCALARS, s))) return rc;
+        }
+        if ((rc = pack(&jb.vol, (uint64_t *)(ws + P.L.bricks_off[i]), s))) return rc;
+    }
+    const bool timed = (flags & MC_TIMED) != 0;
+    if (timed && (rc = time_begin(s))) return rc;
+    if ((rc = enqueue_walk_only(P, ws, t, flags, s))) return rc;
+    if (timed && (rc = time_end(s))) return rc;
+    for (int32_t i = 0; i < n; ++i) {
+        const mc_job &jb = jobs[i];
+        if (!jb.summary) continue;
+        if ((rc = enqueue_reduce(&jb.vol, jb.fluence, jb.scalars, jb.summary, jb.depth,
+                                 (unsigned long long *)(ws + P.L.bins_off[i]), s)))
+            return rc;
+    }
+    return MC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: coordinate descent over waves per CU, block size, chunk and
+// refill threshold, each trial a timed walk over a scaled-down copy of the
+// batch (every job keeps at least one photon).  Results never depend on the
+// launch shape, so tuning only changes speed.
+// ---------------------------------------------------------------------------
+std::mutex g_cache_mu;
+
+std::string cache_path()
+{
+    const char *env = getenv("PHOTONMC_TUNE_CACHE");
+    if (env && *env) return env;
+    const char *home = getenv("HOME");
+    if (!home || !*home) return "";
+    std::string dir = std::string(home) + "/.cache";
+    mkdir(dir.c_str(), 0755);
+    return dir + "/photonmc_tune.txt";
+}
+
+bool cache_get(const std::string &key, mc_tune *t)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    const std::string path = cache_path();
+    if (path.empty()) return false;
+    FILE *f = fopen(path.c_str(), "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char k[400];
+        mc_tune r;
+        if (sscanf(line, "%399s %d %d %d %d", k, &r.block, &r.waves_per_cu, &r.chunk, &r.refill) == 5 && key == k &&
+            check_tune(r) == MC_OK) {
+            *t = r;  // the last entry for a key wins
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_put(const std::string &key, const mc_tune &t)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    const std::string path = cache_path();
+    if (path.empty()) return;
+    FILE *f = fopen(path.c_str(), "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d %d\n", key.c_str(), t.block, t.waves_per_cu, t.chunk, t.refill);
+    fclose(f);
+}
+
+std::string shape_key(const char *kind, const Prepared &P, int flags)
+{
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    memset(&prop, 0, sizeof prop);
+    hipGetDeviceProperties(&prop, dev);
+    uint64_t vox = 0;
+    for (const Job &J : P.table) vox += (uint64_t)J.nx * J.ny * J.nz;
+    char buf[400];
+    snprintf(buf, sizeof buf, "%s|%s|cu%d|%s|jobs%zu|vox2^%d|ph2^%d", kind, prop.gcnArchName, prop.multiProcessorCount,
+             (flags & MC_FP64) ? "f64" : "f32", P.table.size(), (int)log2((double)vox + 1.0),
+             (int)log2((double)P.total_photons + 1.0));
+    for (char *c = buf; *c; ++c)
+        if (*c == ' ') *c = '_';
+    return buf;
+}
+
+int time_trial(const std::function<int(const mc_tune &)> &enqueue, const mc_tune &t, hipStream_t s, float *ms)
+{
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    int rc = MC_OK;
+    if (hipEventRecord(a, s) != hipSuccess) rc = fail(MC_EHIP, "event record failed");
+    if (!rc) rc = enqueue(t);
+    if (!rc && hipEventRecord(b, s) != hipSuccess) rc = fail(MC_EHIP, "event record failed");
+    if (!rc && hipEventSynchronize(b) != hipSuccess) rc = fail(MC_EHIP, "event sync failed");
+    if (!rc && hipEventElapsedTime(ms, a, b) != hipSuccess) rc = fail(MC_EHIP, "elapsed time failed");
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return rc;
+}
+
+int tune_descent(const std::function<int(const mc_tune &)> &enqueue, hipStream_t s, mc_tune *best_out)
+{
+    mc_tune best;
+    mc_tune_default(&best);
+    float best_ms = 0.0f;
+    int rc = time_trial(enqueue, best, s, &best_ms);  // also warms the code objects
+    if (rc) return rc;
+    if ((rc = time_trial(enqueue, best, s, &best_ms))) return rc;
+    auto consider = [&](mc_tune cand) -> int {
+        if (check_tune(cand) != MC_OK) return MC_OK;
+        float ms = 0.0f;
+        int r = time_trial(enqueue, cand, s, &ms);
+        if (r) return r;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+        }
+        return MC_OK;
+    };
+    for (int w : {4, 8, 12, 16, 24, 32}) {
+        mc_tune c = best;
+        c.waves_per_cu = w;
+        if ((rc = consider(c))) return rc;
+    }
+    for (int b : {64, 128, 256, 512}) {
+        mc_tune c = best;
+        c.block = b;
+        if ((rc = consider(c))) return rc;
+    }
+    for (int ch : {32, 128, 256, 1024, 4096}) {
+        mc_tune c = best;
+        c.chunk = ch;
+        if ((rc = consider(c))) return rc;
+    }
+    for (int rf : {1, 8, 16, 32, 48}) {
+        mc_tune c = best;
+        c.refill = rf;
+        if ((rc = consider(c))) return rc;
+    }
+    clear_error();
+    *best_out = best;
+    return MC_OK;
+}
+
+// Scaled-down copy of a prepared batch for tuning trials.
+Prepared scaled(const Prepared &P, double fraction)
+{
+    Prepared S = P;
+    uint64_t q = 0;
+    for (Job &J : S.table) {
+        J.n_photons = std::max<uint64_t>(1, (uint64_t)((double)J.n_photons * fraction));
+        J.queue_begin = q;
+        q += J.n_photons;
+    }
+    S.total_photons = q;
+    return S;
+}
+
+int autotune_prepared(const mc_job *jobs, const Prepared &P, char *ws, int flags, hipStream_t s, mc_tune *out)
+{
+    for (size_t i = 0; i < P.table.size(); ++i)
+        if (jobs[i].accumulate)
+            return fail(MC_EINVAL, "job %zu accumulates: tuning trials would add to its tallies; pass a tune", i);
+    // trials of about 2^22 photons in total
+    const double fraction = std::min(1.0, 4194304.0 / (double)P.total_photons);
+    Prepared S = scaled(P, fraction);
+    int rc = enqueue_table(S, ws, s);
+    if (rc) return rc;
+    for (size_t i = 0; i < S.table.size(); ++i)
+        if ((rc = pack(&jobs[S.order[i]].vol, (uint64_t *)(ws + S.L.bricks_off[S.order[i]]), s))) return rc;
+    auto trial = [&](const mc_tune &t) { return enqueue_walk_only(S, ws, t, flags & MC_FP64, s); };
+    return tune_descent(trial, s, out);
+}
+
+struct GraphHandle {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t mc_batch_workspace_bytes(const mc_job *jobs, int32_t n_jobs)
+{
+    if (!jobs || n_jobs < 1 || n_jobs > MC_MAX_BATCH_JOBS) return 0;
+    for (int32_t i = 0; i < n_jobs; ++i)
+        if (check_volume(&jobs[i].vol)) return 0;
+    return layout_of(jobs, n_jobs).total;
+}
+
+int mc_autotune_batch(const mc_job *jobs, int32_t n_jobs, int flags, void *workspace, size_t workspace_bytes,
+                      mc_tune *out, void *hip_stream)
+{
+    clear_error();
+    if (!out) return fail(MC_EINVAL, "out is NULL");
+    Prepared P;
+    int rc = prepare(jobs, n_jobs, (char *)workspace, workspace_bytes, &P);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const std::string key = shape_key("batch", P, flags);
+    if ((rc = autotune_prepared(jobs, P, (char *)workspace, flags, s, out))) return rc;
+    cache_put(key, *out);
+    return MC_OK;
+}
+
+int mc_run_batch(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune, void *workspace,
+                 size_t workspace_bytes, void *hip_stream)
+{
+    clear_error();
+    Prepared P;
+    int rc = prepare(jobs, n_jobs, (char *)workspace, workspace_bytes, &P);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    mc_tune t;
+    if (tune) {
+        t = resolve_tune(tune);
+    } else {
+        const std::string key = shape_key("batch", P, flags);
+        if (!cache_get(key, &t)) {
+            if ((rc = autotune_prepared(jobs, P, (char *)workspace, flags, s, &t))) return rc;
+            cache_put(key, t);
+        }
+    }
+    if ((rc = check_tune(t))) return rc;
+    return enqueue_batch(jobs, P, (char *)workspace, t, flags, s);
+}
+
+int mc_batch_graph_create(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune, void *workspace,
+                          size_t workspace_bytes, mc_graph *out)
+{
+    clear_error();
+    if (!out) return fail(MC_EINVAL, "out is NULL");
+    if (flags & MC_TIMED) return fail(MC_EINVAL, "MC_TIMED cannot be captured; time the graph launch instead");
+    Prepared P;
+    int rc = prepare(jobs, n_jobs, (char *)workspace, workspace_bytes, &P);
+    if (rc) return rc;
+    const mc_tune t = resolve_tune(tune);
+    if ((rc = check_tune(t))) return rc;
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    GraphHandle *h = new GraphHandle;
+    rc = MC_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = fail(MC_EHIP, "hipStreamBeginCapture failed");
+    } else {
+        const int erc = enqueue_batch(jobs, P, (char *)workspace, t, flags, cs);
+        const hipError_t e = hipStreamEndCapture(cs, &h->graph);
+        if (erc) rc = erc;
+        else if (e != hipSuccess) rc = fail(MC_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        else if (hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0) != hipSuccess)
+            rc = fail(MC_EHIP, "hipGraphInstantiate failed");
+    }
+    hipStreamDestroy(cs);
+    if (rc) {
+        if (h->exec) hipGraphExecDestroy(h->exec);
+        if (h->graph) hipGraphDestroy(h->graph);
+        delete h;
+        return rc;
+    }
+    *out = (mc_graph)h;
+    return MC_OK;
+}
+
+int mc_graph_launch(mc_graph g, void *hip_stream)
+{
+    clear_error();
+    if (!g) return fail(MC_EINVAL, "graph is NULL");
+    HIP_TRY(hipGraphLaunch(((GraphHandle *)g)->exec, (hipStream_t)hip_stream));
+    return MC_OK;
+}
+
+int mc_graph_destroy(mc_graph g)
+{
+    clear_error();
+    if (!g) return MC_OK;
+    GraphHandle *h = (GraphHandle *)g;
+    if (h->exec) hipGraphExecDestroy(h->exec);
+    if (h->graph) hipGraphDestroy(h->graph);
+    delete h;
+    return MC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// Host-side helpers shared by the translation units of the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "photonmc.h"
+#include "walk.hpp"
+
+namespace pmc {
+namespace host {
+
+int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define HIP_TRY(expr)                                                                                    \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return ::pmc::host::fail(MC_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kHeaderBytes = 256;  // queue counter(s) at the start of a run workspace
+constexpr int kBinW = 8;              // int64 words per depth bin of the reduction
+
+struct Dims {
+    int32_t nxb, nyb, nzb;
+    uint64_t nbricks, nvox;
+};
+Dims dims_of(const mc_volume *v);
+int check_volume(const mc_volume *v);
+int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons, uint64_t seed,
+             uint32_t stream_id, Job *J);
+
+struct DeviceInfo {
+    int cus = 0;
+};
+int device_info(DeviceInfo *out);
+
+mc_tune resolve_tune(const mc_tune *t);
+int check_tune(const mc_tune &t);
+
+// asynchronous building blocks on a stream
+int fill(int64_t *p, uint64_t n, hipStream_t s);
+int pack(const mc_volume *vol, uint64_t *bricks, hipStream_t s);
+int enqueue_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scalars, double *summary,
+                   double *depth, unsigned long long *bins, hipStream_t s);
+
+// the walk-kernel timer (MC_TIMED)
+struct Timing {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool armed = false;
+};
+Timing &timing();
+int time_begin(hipStream_t s);
+int time_end(hipStream_t s);
+
+}  // namespace host
+}  // namespace pmc

@@ -20,8 +20,7 @@
 #include <algorithm>
 #include <mutex>
 
-#include "photonmc.h"
-#include "walk.hpp"
+#include "internal.hpp"
 
 using namespace pmc;
 
@@ -30,8 +29,10 @@ using namespace pmc;
 // ---------------------------------------------------------------------------
 static thread_local char g_err[512] = "";
 
-static int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-static int fail(int status, const char *fmt, ...)
+namespace pmc {
+namespace host {
+
+int fail(int status, const char *fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
@@ -40,11 +41,12 @@ static int fail(int status, const char *fmt, ...)
     return status;
 }
 
-#define HIP_TRY(expr)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) return fail(MC_EHIP, "%s: %s", #expr, hipGetErrorString(e_));  \
-    } while (0)
+void clear_error() { g_err[0] = 0; }
+
+}  // namespace host
+}  // namespace pmc
+
+using namespace pmc::host;
 
 // ---------------------------------------------------------------------------
 // Small kernels
@@ -256,7 +258,6 @@ __global__ void k_trace(const Job J, const uint64_t *__restrict__ ids, int32_t n
 // bins[z][8]: solid (hi, lo), pore (hi, lo), n_solid, n_pore, max, unused.
 // A voxel value v >= 0 is split as v = hi * 2^32 + lo; the halves are summed
 // separately, so no partial sum overflows and the totals are exact.
-constexpr int kBinW = 8;
 constexpr int kReduceBlock = 256;
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
@@ -421,14 +422,8 @@ __global__ __launch_bounds__(256) void k_probe(unsigned long long *__restrict__ 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-namespace {
-
-constexpr size_t kHeaderBytes = 256;  // queue counter(s) at the start of a run workspace
-
-struct Dims {
-    int32_t nxb, nyb, nzb;
-    uint64_t nbricks, nvox;
-};
+namespace pmc {
+namespace host {
 
 Dims dims_of(const mc_volume *v)
 {
@@ -496,10 +491,6 @@ int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, 
     return MC_OK;
 }
 
-struct DeviceInfo {
-    int cus = 0;
-};
-
 int device_info(DeviceInfo *out)
 {
     static std::mutex mu;
@@ -526,6 +517,15 @@ mc_tune resolve_tune(const mc_tune *t)
     return r;
 }
 
+int check_tune(const mc_tune &t)
+{
+    if (t.block != 64 && t.block != 128 && t.block != 256 && t.block != 512)
+        return fail(MC_EINVAL, "tune: block size %d not one of 64, 128, 256, 512", t.block);
+    if (t.chunk < 1 || t.refill < 1 || t.refill > 64 || t.waves_per_cu < 1 || t.waves_per_cu > 32)
+        return fail(MC_EINVAL, "tune out of range (chunk >= 1, refill in [1, 64], waves_per_cu in [1, 32])");
+    return MC_OK;
+}
+
 int fill(int64_t *p, uint64_t n, hipStream_t s)
 {
     if (n == 0) return MC_OK;
@@ -545,11 +545,42 @@ int pack(const mc_volume *vol, uint64_t *bricks, hipStream_t s)
     return MC_OK;
 }
 
-struct Timing {
-    hipEvent_t start = nullptr, stop = nullptr;
-    bool armed = false;
-};
 thread_local Timing g_timing;
+
+Timing &timing() { return g_timing; }
+
+int time_begin(hipStream_t s)
+{
+    if (!g_timing.start) {
+        HIP_TRY(hipEventCreate(&g_timing.start));
+        HIP_TRY(hipEventCreate(&g_timing.stop));
+    }
+    HIP_TRY(hipEventRecord(g_timing.start, s));
+    return MC_OK;
+}
+
+int time_end(hipStream_t s)
+{
+    HIP_TRY(hipEventRecord(g_timing.stop, s));
+    g_timing.armed = true;
+    return MC_OK;
+}
+
+int enqueue_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scalars, double *summary,
+                   double *depth, unsigned long long *bins, hipStream_t s)
+{
+    int rc = fill((int64_t *)bins, (uint64_t)vol->nz * kBinW, s);
+    if (rc) return rc;
+    const uint64_t layer = (uint64_t)vol->nx * vol->ny;
+    const uint64_t per_block = 8192;
+    const uint64_t gx = (layer + per_block - 1) / per_block;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)gx, (unsigned)vol->nz), dim3(kReduceBlock), 0, s, fluence, vol->mask,
+                       layer, per_block, bins);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, bins, scalars, vol->nx, vol->ny, vol->nz, summary, depth);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
 
 template <typename R>
 void enqueue_walk(int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s)
@@ -570,24 +601,16 @@ int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipSt
     const int waves_per_block = t.block / 64;
     const int blocks = std::max(1, di.cus * t.waves_per_cu / waves_per_block);
     const bool timed = (flags & MC_TIMED) != 0;
-    if (timed) {
-        if (!g_timing.start) {
-            HIP_TRY(hipEventCreate(&g_timing.start));
-            HIP_TRY(hipEventCreate(&g_timing.stop));
-        }
-        HIP_TRY(hipEventRecord(g_timing.start, s));
-    }
+    if (timed && (rc = time_begin(s))) return rc;
     if (flags & MC_FP64) enqueue_walk<double>(t.block, blocks, J, queue, t, s);
     else enqueue_walk<float>(t.block, blocks, J, queue, t, s);
     HIP_TRY(hipGetLastError());
-    if (timed) {
-        HIP_TRY(hipEventRecord(g_timing.stop, s));
-        g_timing.armed = true;
-    }
+    if (timed && (rc = time_end(s))) return rc;
     return MC_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace pmc
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -604,6 +627,7 @@ size_t mc_sizeof(const char *type_name)
     if (!strcmp(type_name, "mc_tune")) return sizeof(mc_tune);
     if (!strcmp(type_name, "mc_trace_rec")) return sizeof(mc_trace_rec);
     if (!strcmp(type_name, "mc_photon_rec")) return sizeof(mc_photon_rec);
+    if (!strcmp(type_name, "mc_job")) return sizeof(mc_job);
     return 0;
 }
 
@@ -641,7 +665,7 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
            uint32_t stream_id, int flags, int64_t *fluence, int64_t *scalars, void *workspace, size_t workspace_bytes,
            const mc_tune *tune, void *hip_stream)
 {
-    g_err[0] = 0;
+    clear_error();
     Job J;
     int rc = make_job(vol, opt, photon_begin, n_photons, seed, stream_id, &J);
     if (rc) return rc;
@@ -649,10 +673,7 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
     const size_t need = mc_run_workspace_bytes(vol);
     if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
     const mc_tune t = resolve_tune(tune);
-    if (t.block != 64 && t.block != 128 && t.block != 256 && t.block != 512)
-        return fail(MC_EINVAL, "tune: block size %d not one of 64, 128, 256, 512", t.block);
-    if (t.chunk < 1 || t.refill < 1 || t.refill > 64 || t.waves_per_cu < 1 || t.waves_per_cu > 32)
-        return fail(MC_EINVAL, "tune out of range (chunk >= 1, refill in [1, 64], waves_per_cu in [1, 32])");
+    if ((rc = check_tune(t))) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     unsigned long long *queue = (unsigned long long *)workspace;
     uint64_t *bricks = (uint64_t *)((char *)workspace + kHeaderBytes);
@@ -686,31 +707,21 @@ size_t mc_reduce_workspace_bytes(const mc_volume *vol)
 int mc_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scalars, double *summary, double *depth,
               void *workspace, size_t workspace_bytes, void *hip_stream)
 {
-    g_err[0] = 0;
+    clear_error();
     int rc = check_volume(vol);
     if (rc) return rc;
     if (!fluence || !scalars || !summary || !workspace) return fail(MC_EINVAL, "NULL argument");
     const size_t need = mc_reduce_workspace_bytes(vol);
     if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    hipStream_t s = (hipStream_t)hip_stream;
-    unsigned long long *bins = (unsigned long long *)workspace;
-    if ((rc = fill((int64_t *)bins, (uint64_t)vol->nz * kBinW, s))) return rc;
-    const uint64_t layer = (uint64_t)vol->nx * vol->ny;
-    const uint64_t per_block = 8192;
-    const uint64_t gx = (layer + per_block - 1) / per_block;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)gx, (unsigned)vol->nz), dim3(kReduceBlock), 0, s, fluence, vol->mask,
-                       layer, per_block, bins);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, bins, scalars, vol->nx, vol->ny, vol->nz, summary, depth);
-    HIP_TRY(hipGetLastError());
-    return MC_OK;
+    return enqueue_reduce(vol, fluence, scalars, summary, depth, (unsigned long long *)workspace,
+                          (hipStream_t)hip_stream);
 }
 
 int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_ids, int32_t n, int32_t max_steps,
              uint64_t seed, uint32_t stream_id, int flags, mc_trace_rec *recs, mc_photon_rec *outcome,
              void *workspace, size_t workspace_bytes, void *hip_stream)
 {
-    g_err[0] = 0;
+    clear_error();
     Job J;
     int rc = make_job(vol, opt, 0, 1, seed, stream_id, &J);
     if (rc) return rc;
@@ -735,7 +746,7 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
 
 int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mode, void *hip_stream)
 {
-    g_err[0] = 0;
+    clear_error();
     if (!table || n_entries == 0 || (n_entries & (n_entries - 1)) != 0)
         return fail(MC_EINVAL, "table must be non-NULL with a power-of-two entry count");
     if (mode < 0 || mode > 4) return fail(MC_EINVAL, "mode must be in [0, 4]");

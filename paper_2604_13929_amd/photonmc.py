@@ -46,6 +46,15 @@ class McTune(ctypes.Structure):
                 ("refill", ctypes.c_int32)]
 
 
+class McJob(ctypes.Structure):
+    _fields_ = [("vol", McVolume), ("opt", McOptics), ("photon_begin", ctypes.c_uint64),
+                ("n_photons", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
+                ("accumulate", ctypes.c_int32), ("fluence", ctypes.c_void_p), ("scalars", ctypes.c_void_p),
+                ("summary", ctypes.c_void_p), ("depth", ctypes.c_void_p)]
+
+
+MAX_BATCH_JOBS = 64
+
 TRACE_DTYPE = np.dtype([("fx", "<f8"), ("fy", "<f8"), ("fz", "<f8"), ("ux", "<f8"), ("uy", "<f8"), ("uz", "<f8"),
                         ("d", "<f8"), ("s_rem", "<f8"), ("w", "<u4"), ("k", "<u4"),
                         ("ix", "<i4"), ("iy", "<i4"), ("iz", "<i4"), ("event", "<i4")])
@@ -68,6 +77,12 @@ _SIGS = {
     "mc_reduce_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_reduce": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mc_probe_scatter": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, _P]),
+    "mc_batch_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
+    "mc_run_batch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, _P, _P, ctypes.c_size_t, _P]),
+    "mc_autotune_batch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
+    "mc_batch_graph_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, _P, _P, ctypes.c_size_t, _P]),
+    "mc_graph_launch": (ctypes.c_int, [_P, _P]),
+    "mc_graph_destroy": (ctypes.c_int, [_P]),
     "mc_trace": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
                                 ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P]),
 }
@@ -95,6 +110,7 @@ def load(path: str = LIB_PATH):
         fn.restype = res
         fn.argtypes = args
     for name, size in (("mc_volume", ctypes.sizeof(McVolume)), ("mc_optics", ctypes.sizeof(McOptics)),
+                       ("mc_job", ctypes.sizeof(McJob)),
                        ("mc_tune", ctypes.sizeof(McTune)), ("mc_trace_rec", TRACE_DTYPE.itemsize),
                        ("mc_photon_rec", PHOTON_DTYPE.itemsize)):
         if L.mc_sizeof(name.encode()) != size:
@@ -269,3 +285,108 @@ def probe_scatter(table: torch.Tensor, n_ops: int, mode: int = 0) -> float:
     threads = torch.cuda.get_device_properties(dev).multi_processor_count * 16 * 64
     done = max(1, n_ops // threads) * threads
     return done / (start.elapsed_time(stop) * 1e-3)
+
+
+@dataclass
+class BatchJob:
+    """One job of a batch: a mask on the device, its optics, photons and stream."""
+    mask: torch.Tensor
+    optics: Optics
+    n_photons: int
+    seed: int
+    stream_id: int = 0
+    photon_begin: int = 0
+    reduce: bool = True
+
+
+class Batch:
+    """Device buffers and the C job table of a batch (they must outlive queued work)."""
+
+    def __init__(self, jobs: list[BatchJob], accumulate_into: "Batch | None" = None):
+        if not 1 <= len(jobs) <= MAX_BATCH_JOBS:
+            raise ValueError(f"a batch holds 1 to {MAX_BATCH_JOBS} jobs")
+        self.jobs = jobs
+        dev = jobs[0].mask.device
+        self.device = dev
+        self.results: list[RunResult] = []
+        self.summaries, self.depths = [], []
+        arr = (McJob * len(jobs))()
+        for i, j in enumerate(jobs):
+            vol = volume(j.mask)
+            if accumulate_into is None:
+                r = RunResult(torch.empty(tuple(j.mask.shape), dtype=torch.int64, device=dev),
+                              torch.empty(NSCALARS, dtype=torch.int64, device=dev))
+            else:
+                r = accumulate_into.results[i]
+            q = torch.empty(NSUMMARY, dtype=torch.float64, device=dev) if j.reduce else None
+            d = torch.empty((3, j.mask.shape[0]), dtype=torch.float64, device=dev) if j.reduce else None
+            self.results.append(r)
+            self.summaries.append(q)
+            self.depths.append(d)
+            arr[i] = McJob(vol, j.optics.c(), j.photon_begin, j.n_photons, j.seed, j.stream_id,
+                           1 if accumulate_into is not None else 0, r.fluence.data_ptr(), r.scalars.data_ptr(),
+                           q.data_ptr() if q is not None else None, d.data_ptr() if d is not None else None)
+        self.c_jobs = arr
+        L = load()
+        nbytes = L.mc_batch_workspace_bytes(ctypes.byref(arr), len(jobs))
+        if nbytes == 0:
+            raise McError(-1, "mc_batch_workspace_bytes", "invalid batch")
+        self.ws = workspace(nbytes, dev)
+
+    def summary(self, i: int) -> Summary:
+        q = self.summaries[i].cpu().numpy()
+        d = self.depths[i].cpu().numpy()
+        vals = {name: float(q[k]) for k, name in enumerate(SUMMARY)}
+        return Summary(vals, d[0], d[1], d[2])
+
+
+def run_batch(jobs: list[BatchJob], tune: Tune | None = None, fp64: bool = False, timed: bool = False,
+              accumulate_into: Batch | None = None) -> Batch:
+    """mc_run_batch on the current stream; tune None: the cached (or autotuned) launch shape."""
+    L = load()
+    b = Batch(jobs, accumulate_into)
+    flags = (MC_FP64 if fp64 else 0) | (MC_TIMED if timed else 0)
+    t = tune.c() if tune is not None else None
+    _check(L.mc_run_batch(ctypes.byref(b.c_jobs), len(jobs), flags, ctypes.byref(t) if t is not None else None,
+                          b.ws.data_ptr(), b.ws.numel(), _stream(b.device)), "mc_run_batch")
+    if timed:
+        ms = ctypes.c_float(0.0)
+        _check(L.mc_walk_elapsed_ms(ctypes.byref(ms)), "mc_walk_elapsed_ms")
+        b.walk_ms = float(ms.value)
+    return b
+
+
+def autotune_batch(jobs: list[BatchJob], fp64: bool = False) -> Tune:
+    L = load()
+    b = Batch(jobs)
+    out = McTune()
+    _check(L.mc_autotune_batch(ctypes.byref(b.c_jobs), len(jobs), MC_FP64 if fp64 else 0, b.ws.data_ptr(),
+                               b.ws.numel(), ctypes.byref(out), _stream(b.device)), "mc_autotune_batch")
+    return Tune(out.block, out.waves_per_cu, out.chunk, out.refill)
+
+
+class BatchGraph:
+    """A captured HIP graph of one batched step; replay with launch()."""
+
+    def __init__(self, jobs: list[BatchJob], tune: Tune | None = None, fp64: bool = False):
+        L = load()
+        self.batch = Batch(jobs)
+        self.handle = ctypes.c_void_p()
+        t = tune.c() if tune is not None else None
+        _check(L.mc_batch_graph_create(ctypes.byref(self.batch.c_jobs), len(jobs), MC_FP64 if fp64 else 0,
+                                       ctypes.byref(t) if t is not None else None, self.batch.ws.data_ptr(),
+                                       self.batch.ws.numel(), ctypes.byref(self.handle)), "mc_batch_graph_create")
+
+    def launch(self):
+        _check(load().mc_graph_launch(self.handle, _stream(self.batch.device)), "mc_graph_launch")
+
+    def close(self):
+        if self.handle:
+            load().mc_graph_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -86,3 +86,32 @@ def test_workspace_sizes(lib):
     assert lib.mc_reduce_workspace_bytes(ctypes.byref(vol)) == 7 * 8 * 8
     bad = pm.McVolume(0, 5, 7, 0, 1)
     assert lib.mc_run_workspace_bytes(ctypes.byref(bad)) == 0
+
+
+def _job(nx=8, ny=8, nz=8, mask=1, n=10, mu_s=0.5, g=0.7):
+    vol = pm.McVolume(nx, ny, nz, 0, mask)
+    opt = pm.McOptics(mu_s, 0.01, g, 1e-4, 10, 0.0, 0, 0)
+    return pm.McJob(vol, opt, 0, n, 1, 0, 0, 1, 1, None, None)
+
+
+def test_batch_validation_names_the_job(lib):
+    jobs = (pm.McJob * 3)(_job(), _job(g=1.5), _job())
+    ws = lib.mc_batch_workspace_bytes(ctypes.byref(jobs), 3)
+    assert ws > 0
+    rc = lib.mc_run_batch(ctypes.byref(jobs), 3, 0, ctypes.byref(pm.McTune(256, 8, 64, 8)), 1, ws, None)
+    assert rc == -1 and b"job 1" in lib.mc_last_error() and b"|g|" in lib.mc_last_error()
+    assert lib.mc_run_batch(ctypes.byref(jobs), 0, 0, None, 1, ws, None) == -1
+    many = (pm.McJob * 65)(*[_job() for _ in range(65)])
+    assert lib.mc_batch_workspace_bytes(ctypes.byref(many), 65) == 0
+    assert lib.mc_run_batch(ctypes.byref(many), 65, 0, None, 1, 1 << 30, None) == -1
+    bad = (pm.McJob * 1)(_job(nz=0))
+    assert lib.mc_batch_workspace_bytes(ctypes.byref(bad), 1) == 0
+    small = (pm.McJob * 1)(_job())
+    assert lib.mc_run_batch(ctypes.byref(small), 1, 0, None, 1, 64, None) == -4
+
+
+def test_graph_rejects_timed_capture(lib):
+    jobs = (pm.McJob * 1)(_job())
+    out = ctypes.c_void_p()
+    assert lib.mc_batch_graph_create(ctypes.byref(jobs), 1, 2, None, 1, 1 << 20, ctypes.byref(out)) == -1
+    assert lib.mc_graph_destroy(None) == 0

@@ -1,0 +1,121 @@
+"""Batched multi-mask launch: job k of a batch equals a plain run of job k, bit for
+bit, for any launch shape; the captured graph replays the same bits; the reduction
+of every job equals mc_reduce on that job; the autotuner returns a usable shape."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2604_13929_amd import inputs
+from paper_2604_13929_amd import photonmc as pm
+
+pytestmark = pytest.mark.gpu
+f32 = lambda x: float(np.float32(x))  # noqa: E731
+
+
+def banner(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pm.load()
+
+
+@pytest.fixture(scope="module")
+def small_jobs():
+    """Six jobs of uneven (ragged) size, porosity and optics."""
+    spec = [(37, 29, 23, 0.6, 0.5, 0.01, 0.7, 20000), (16, 16, 40, 0.9, 1.0, 0.05, 0.5, 5000),
+            (48, 48, 48, 0.5, 0.2, 0.005, 0.9, 30000), (8, 8, 8, 0.7, 0.7, 0.02, 0.6, 1),
+            (24, 40, 12, 0.8, 0.3, 0.03, 0.8, 12345), (32, 32, 32, 0.7, 0.5, 0.01, 0.7, 40000)]
+    jobs = []
+    for i, (nx, ny, nz, phi, mus, mua, g, n) in enumerate(spec):
+        m = torch.from_numpy(inputs.spinodal_mask(nx, ny, nz, 8.0, phi, seed=100 + i)).cuda()
+        jobs.append(pm.BatchJob(m, pm.Optics(f32(mus), f32(mua), f32(g)), n, seed=20260809, stream_id=i,
+                                photon_begin=7 * i))
+    return jobs
+
+
+def _plain(j: pm.BatchJob, fp64=False):
+    r = pm.run(j.mask, j.optics, j.n_photons, j.seed, photon_begin=j.photon_begin, stream_id=j.stream_id, fp64=fp64)
+    return r, pm.reduce(j.mask, r)
+
+
+def test_batch_equals_plain_runs(small_jobs):
+    banner("batch of 6 == 6 plain runs, bitwise, several launch shapes")
+    plains = [_plain(j) for j in small_jobs]
+    for tune in (pm.Tune(256, 16, 256, 16), pm.Tune(64, 4, 7, 1), pm.Tune(512, 32, 4096, 64)):
+        b = pm.run_batch(small_jobs, tune=tune)
+        torch.cuda.synchronize()
+        for k, (r, s) in enumerate(plains):
+            assert torch.equal(b.results[k].fluence, r.fluence), (tune, k)
+            assert torch.equal(b.results[k].scalars, r.scalars), (tune, k)
+            bs = b.summary(k)
+            for key in ("phi3d", "phi1d", "r", "R", "T", "A", "closure_exact"):
+                a, c = bs[key], s[key]
+                assert (a == c) or (np.isnan(a) and np.isnan(c)), (k, key)
+            assert np.array_equal(bs.depth, s.depth, equal_nan=True)
+
+
+def test_batch_fp64_equals_plain_fp64(small_jobs):
+    banner("batch FP64 transport == plain FP64")
+    b = pm.run_batch(small_jobs[:3], tune=pm.Tune(128, 8, 64, 8), fp64=True)
+    for k in range(3):
+        r, _ = _plain(small_jobs[k], fp64=True)
+        assert torch.equal(b.results[k].fluence, r.fluence) and torch.equal(b.results[k].scalars, r.scalars)
+
+
+def test_batch_accumulate_equals_whole(small_jobs):
+    banner("batch resume: two halves accumulate to the whole")
+    whole = pm.run_batch(small_jobs, tune=pm.Tune(256, 8, 128, 16))
+    first = [pm.BatchJob(j.mask, j.optics, max(1, j.n_photons // 2), j.seed, j.stream_id, j.photon_begin, False)
+             for j in small_jobs]
+    second = [pm.BatchJob(j.mask, j.optics, j.n_photons - f.n_photons, j.seed, j.stream_id,
+                          j.photon_begin + f.n_photons, False) for j, f in zip(small_jobs, first)]
+    keep = [i for i, s in enumerate(second) if s.n_photons > 0]
+    part = pm.run_batch(first, tune=pm.Tune(256, 8, 128, 16))
+    sub = pm.Batch.__new__(pm.Batch)
+    sub.results = [part.results[i] for i in keep]
+    pm.run_batch([second[i] for i in keep], tune=pm.Tune(64, 16, 32, 4), accumulate_into=sub)
+    torch.cuda.synchronize()
+    for k in range(len(small_jobs)):
+        assert torch.equal(part.results[k].fluence, whole.results[k].fluence), k
+        assert torch.equal(part.results[k].scalars, whole.results[k].scalars), k
+
+
+def test_graph_replays_match_eager(small_jobs):
+    banner("captured graph: 3 replays with eager work between, each == eager")
+    eager = pm.run_batch(small_jobs, tune=pm.Tune(256, 16, 256, 16))
+    torch.cuda.synchronize()
+    ref_f = [r.fluence.clone() for r in eager.results]
+    ref_s = [r.scalars.clone() for r in eager.results]
+    ref_q = [q.clone() for q in eager.summaries]
+    g = pm.BatchGraph(small_jobs, tune=pm.Tune(256, 16, 256, 16))
+    for rep in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        for k in range(len(small_jobs)):
+            assert torch.equal(g.batch.results[k].fluence, ref_f[k]), (rep, k)
+            assert torch.equal(g.batch.results[k].scalars, ref_s[k]), (rep, k)
+            assert torch.equal(g.batch.summaries[k].nan_to_num(-1), ref_q[k].nan_to_num(-1)), (rep, k)
+        # unrelated eager work in between replays
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+        pm.run(small_jobs[0].mask, small_jobs[0].optics, 1000, 1)
+        torch.cuda.synchronize()
+    g.close()
+
+
+def test_autotune_returns_usable_shape(small_jobs, tmp_path, monkeypatch):
+    banner("autotune + cache")
+    monkeypatch.setenv("PHOTONMC_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    t = pm.autotune_batch(small_jobs)
+    assert t.block in (64, 128, 256, 512) and 1 <= t.waves_per_cu <= 32 and t.chunk >= 1 and 1 <= t.refill <= 64
+    assert (tmp_path / "tune.txt").read_text().strip()
+    b = pm.run_batch(small_jobs)          # tune=None: taken from the cache
+    r, _ = _plain(small_jobs[2])
+    torch.cuda.synchronize()
+    assert torch.equal(b.results[2].fluence, r.fluence)
