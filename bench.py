@@ -41,6 +41,63 @@ def cpu_model():
     return platform.processor()
 
 
+def batched_leg(args, seed):
+    """The uneven 64-job batch: one persistent launch (autotuned, with the reductions)
+    against the same 64 jobs as sequential plain runs (mc_run + mc_reduce each)."""
+    import torch
+
+    from paper_2604_13929_amd import inputs
+    from paper_2604_13929_amd import photonmc as pm
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    specs = inputs.batch_jobs(seed=0)
+    jobs = []
+    for j in specs:
+        m = inputs.spinodal_mask_torch(j["nx"], j["ny"], j["nz"], j["wavelength"], j["porosity"],
+                                       seed=j["mask_seed"], device=dev)
+        jobs.append(pm.BatchJob(m, pm.Optics(j["mu_s"], j["mu_a"], j["g"]), j["n_photons"], seed,
+                                stream_id=j["stream_id"]))
+    torch.cuda.synchronize()
+    n_total = sum(j.n_photons for j in jobs)
+    vox = sum(j.mask.numel() for j in jobs)
+    log(f"batch: 64 masks ({vox / 1e6:.0f} Mvoxels, {n_total / 1e6:.0f} M photons) built in {time.time() - t0:.1f}s")
+    b = pm.run_batch(jobs)           # warm-up; autotunes the launch shape on a cache miss
+    torch.cuda.synchronize()
+    log("batch warm-up done")
+    times, walk = [], []
+    for i in range(args.batch_steps):
+        del b
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        b = pm.run_batch(jobs, timed=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        walk.append(b.walk_ms)
+        log(f"batch step {i}: {times[-1] * 1e3:.0f} ms (walk {b.walk_ms:.0f} ms)")
+    steps = sum(int(r.scalars[pm.SCALARS.index("steps")].item()) for r in b.results)
+    batch_scalars = [r.scalars.clone() for r in b.results]
+    del b
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    seq = []
+    for j in jobs:
+        r = pm.run(j.mask, j.optics, j.n_photons, j.seed, stream_id=j.stream_id)
+        q, d, ws = pm.reduce_async(j.mask, r)
+        seq.append(r.scalars)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t2
+    log(f"sequential plain runs: {t_seq * 1e3:.0f} ms")
+    identical = all(torch.equal(a, c) for a, c in zip(batch_scalars, seq))
+    t_b = min(times)
+    return {"workload": "64 Cahn-wave cubes, side U{64..256}, phi in {0.5..0.9}, mu_s [0.2,1], mu_a [0.005,0.05], "
+                        "g [0.5,0.9], 1e6..1e7 photons each (seed 0)",
+            "photons": n_total, "photon_steps": steps, "voxels": vox,
+            "ms": t_b * 1e3, "walk_ms": min(walk), "photon_steps_per_s": steps / t_b, "photons_per_s": n_total / t_b,
+            "sequential_plain_ms": t_seq * 1e3, "sequential_photon_steps_per_s": steps / t_seq,
+            "speedup_vs_sequential": t_seq / t_b, "jobs_bitwise_equal_to_plain": identical}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +106,8 @@ def main():
     ap.add_argument("--photons", type=int, default=100_000_000)
     ap.add_argument("--cpu-photons", type=int, default=1_000_000, help="oracle sample size (first ids)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--scatter-probe", action="store_true",
@@ -160,6 +219,9 @@ def main():
         "results": {k: summary[k] for k in ("phi3d", "phi1d", "r", "ratio", "identity_rhs", "R", "T", "A",
                                              "steps_per_photon", "Pw_void_gtL", "mean_void_path")},
     }
+
+    if not args.no_batch:
+        line["batched"] = batched_leg(args, seed)
 
     if not args.no_cpu:
         import oracle

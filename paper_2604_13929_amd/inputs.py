@@ -91,6 +91,36 @@ def spinodal_mask(nx: int, ny: int, nz: int, wavelength: float, porosity: float,
     return rank_threshold(cahn_field(nx, ny, nz, wavelength, seed, n_waves), porosity)
 
 
+def spinodal_mask_torch(nx: int, ny: int, nz: int, wavelength: float, porosity: float, seed: int = PAPER_MASK_SEED,
+                        n_waves: int = 256, device="cuda"):
+    """The same construction evaluated with torch (FP64, complex matmul) on ``device``.
+
+    Returns a contiguous uint8 tensor [nz, ny, nx] on that device.  It differs from
+    ``spinodal_mask`` only where two field values lie within rounding of the
+    threshold; use one generator per experiment.
+    """
+    import torch
+
+    k, phase = wave_vectors(wavelength, seed, n_waves)
+    kt = torch.as_tensor(k, dtype=torch.float64, device=device)
+    ph = torch.as_tensor(phase, dtype=torch.float64, device=device)
+    xs = torch.arange(nx, dtype=torch.float64, device=device) + 0.5
+    ys = torch.arange(ny, dtype=torch.float64, device=device) + 0.5
+    zs = torch.arange(nz, dtype=torch.float64, device=device) + 0.5
+    ex = torch.polar(torch.ones(n_waves, nx, dtype=torch.float64, device=device), torch.outer(kt[:, 0], xs))
+    ey = torch.polar(torch.ones(n_waves, ny, dtype=torch.float64, device=device), torch.outer(kt[:, 1], ys))
+    ez = torch.polar(torch.ones(nz, n_waves, dtype=torch.float64, device=device), torch.outer(zs, kt[:, 2]) + ph)
+    plane = (ey[:, :, None] * ex[:, None, :]).reshape(n_waves, ny * nx)
+    field = torch.matmul(ez, plane).real.reshape(-1)
+    n = field.numel()
+    n_pore = int(round(porosity * n))
+    mask = torch.zeros(n, dtype=torch.uint8, device=device)
+    if n_pore > 0:
+        order = torch.sort(-field, stable=True).indices   # highest first, ties by lower index
+        mask[order[:n_pore]] = 1
+    return mask.reshape(nz, ny, nx).contiguous()
+
+
 def homogeneous_mask(nx: int, ny: int, nz: int, pore: bool = False) -> np.ndarray:
     """All-solid (or all-pore) slab."""
     return np.full((nz, ny, nx), 1 if pore else 0, dtype=np.uint8)
