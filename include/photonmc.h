@@ -182,6 +182,37 @@ size_t mc_reduce_workspace_bytes(const mc_volume *vol);
 int mc_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scalars, double *summary,
               double *depth, void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Gradients by the likelihood-ratio (perturbation Monte Carlo) method; not in
+ * the paper.  The sampled path density of a photon with k interactions is
+ * mu_s^k exp(-mu_t l_solid) prod_i p_HG(cos_i; g) (implicit capture supplies
+ * the ratio to the sampling density), so the scores are S_mus = k/mu_s - l_solid,
+ * S_mua = -l_solid, S_g = sum_i d ln p_HG(cos_i; g)/dg.  A track segment of
+ * length d adds w (S d - [solid] d^2/2) to the mu_s and mu_a bins and w S_g d to
+ * the g bin of its (phase, depth).
+ * ------------------------------------------------------------------------- */
+#define MC_GRAD_MAX_NZ 2048
+
+/* Workspace (device bytes) an mc_grad on this volume needs. */
+size_t mc_grad_workspace_bytes(const mc_volume *vol);
+
+/*
+ * The walk of mc_run (same photons, same tallies) that also accumulates the
+ * score bins, then optionally the reduction and the Jacobian:
+ *   grad_bins  device int64[3][2][nz][2]: (mu_s, mu_a, g) x (solid, pore) x depth x
+ *              (hi, lo); value = hi * 2^32 + lo (lo summed as unsigned) in units of
+ *              2^-16 Q31 weight x voxel
+ *   jac        device double[3][2 + nz] or NULL: d<Phi>_3D, d<Phi>_1D, dPhi(z)/S0
+ *              with respect to mu_s, mu_a, g (per voxel units)
+ *   summary, depth  as mc_reduce, or NULL
+ * nz <= MC_GRAD_MAX_NZ.  flags: MC_ACCUMULATE (also accumulates grad_bins),
+ * MC_FP64, MC_TIMED.  Errors as mc_run.
+ */
+int mc_grad(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons, uint64_t seed,
+            uint32_t stream_id, int flags, int64_t *fluence, int64_t *scalars, int64_t *grad_bins, double *jac,
+            double *summary, double *depth, void *workspace, size_t workspace_bytes, const mc_tune *tune,
+            void *hip_stream);
+
 /* One trace record per step of a traced photon: the state at the start of the
  * step (exact values of the transport precision, widened to double) and how the
  * step ended. */

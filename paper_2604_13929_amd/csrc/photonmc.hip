@@ -90,12 +90,51 @@ __global__ void k_pack(const uint8_t *__restrict__ mask, int32_t nx, int32_t ny,
 // ---------------------------------------------------------------------------
 struct TallySink {
     template <typename R> __device__ __forceinline__ void segment(const Photon<R> &, const Job &, R, bool) {}
-    template <typename R> __device__ __forceinline__ void deflect(const Photon<R> &, const Job &, R) {}
+    template <typename R> __device__ __forceinline__ void deflect(Photon<R> &, const Job &, R) {}
     __device__ __forceinline__ void flush(const Job &J, uint64_t v, uint64_t acc)
     {
         if (acc != 0ull)
             __hip_atomic_fetch_add((unsigned long long *)(J.fluence + v), (unsigned long long)acc,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+// Likelihood-ratio (perturbation Monte Carlo) scores of the track-length
+// estimator.  The sampled path density is mu_s^k exp(-mu_t l_solid) prod p_HG;
+// its log-derivatives give the scores S_mus = k/mu_s - l_solid,
+// S_mua = -l_solid and S_g = sum_i d ln p_HG(cos_i)/dg.  A segment of length d
+// starting with those scores adds w (S d - [solid] d^2/2) to the mu_s and mu_a
+// bins (the d^2/2 is the survival inside the segment) and w S_g d to the g bin,
+// per (parameter, phase, depth), in fixed point 2^-16 of a Q31 weight x voxel.
+// Roulette decisions carry no score: survival 1/m with weight x m is unbiased.
+constexpr double kGradScale = 0x1.0p-16;
+
+__device__ __forceinline__ double hg_score(double ct, double g)
+{
+    return -2.0 * g / (1.0 - g * g) + 3.0 * (ct - g) / (1.0 + g * g - 2.0 * g * ct);
+}
+
+struct GradSink : TallySink {
+    unsigned long long *bins;  // LDS [3][2][nz]
+    int32_t nz;
+    double inv_mu_s;           // 1/mu_s, 0 when mu_s = 0
+    template <typename R>
+    __device__ __forceinline__ void segment(const Photon<R> &p, const Job &, R d, bool solid)
+    {
+        const double dd = (double)d, ls = p.l_tot - p.l_void;  // solid path before this segment
+        const double sq = solid ? 0.5 * dd * dd : 0.0;
+        const double sw = (double)p.w * kGradScale;
+        const int32_t base = (solid ? 0 : nz) + p.iz;
+        const long long vs = __double2ll_rn(sw * (((double)p.k * inv_mu_s - ls) * dd - sq));
+        const long long va = __double2ll_rn(sw * (-ls * dd - sq));
+        const long long vg = __double2ll_rn(sw * (p.score_g * dd));
+        if (vs) atomicAdd(&bins[base], (unsigned long long)vs);
+        if (va) atomicAdd(&bins[2 * nz + base], (unsigned long long)va);
+        if (vg) atomicAdd(&bins[4 * nz + base], (unsigned long long)vg);
+    }
+    template <typename R> __device__ __forceinline__ void deflect(Photon<R> &p, const Job &J, R ct)
+    {
+        p.score_g += hg_score((double)ct, (double)J.g);
     }
 };
 
@@ -134,15 +173,26 @@ __device__ __forceinline__ void account(unsigned long long *acc, const Photon<R>
 // run converged.  A wavefront exits when the queue is exhausted, its range is
 // empty and none of its lanes is alive; every photon terminates (escape,
 // weight 0, roulette, or the step cap), so every wavefront exits.
-template <int BLOCK, typename R>
+template <bool GRAD> struct SinkOf { using type = TallySink; };
+template <> struct SinkOf<true> { using type = GradSink; };
+
+template <int BLOCK, typename R, bool GRAD>
 __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long *__restrict__ queue, int32_t chunk,
-                                                int32_t refill)
+                                                int32_t refill, unsigned long long *__restrict__ grad)
 {
     __shared__ unsigned long long acc[MC_NSCALARS];
+    extern __shared__ unsigned long long s_grad[];  // GRAD: [3][2][nz]
     if (threadIdx.x < MC_NSCALARS) acc[threadIdx.x] = 0ull;
+    if (GRAD)
+        for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) s_grad[i] = 0ull;
     __syncthreads();
 
-    TallySink sink;
+    typename SinkOf<GRAD>::type sink;
+    if constexpr (GRAD) {
+        sink.bins = s_grad;
+        sink.nz = J.nz;
+        sink.inv_mu_s = J.mu_s > 0.0 ? 1.0 / J.mu_s : 0.0;
+    }
     Photon<R> p;
     bool alive = false;
     uint64_t q_next = 0, q_end = 0;
@@ -190,6 +240,16 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
     if (threadIdx.x < MC_NSCALARS) {
         const unsigned long long v = acc[threadIdx.x];
         if (v) atomicAdd((unsigned long long *)&J.scalars[threadIdx.x], v);
+    }
+    if (GRAD) {
+        // signed block sums into (hi, lo) pairs: total = sum(hi) * 2^32 + sum(lo)
+        for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) {
+            const long long v = (long long)s_grad[i];
+            if (v) {
+                atomicAdd(&grad[2 * i], (unsigned long long)(v >> 32));
+                atomicAdd(&grad[2 * i + 1], (unsigned long long)v & 0xFFFFFFFFull);
+            }
+        }
     }
 }
 
@@ -380,6 +440,39 @@ __global__ void k_finalize(const unsigned long long *__restrict__ bins, const in
     q[MC_Q_LAUNCHED] = n_ph;
 }
 
+// Jacobian of <Phi>_3D, <Phi>_1D and Phi(z) with respect to (mu_s, mu_a, g)
+// from the gradient bins, normalised as the forward estimators (Phi/S0).
+__device__ __forceinline__ double join_signed(unsigned long long hi, unsigned long long lo)
+{
+    return (double)(long long)hi * 4294967296.0 + (double)lo;
+}
+
+__global__ void k_grad_finalize(const unsigned long long *__restrict__ grad, const unsigned long long *__restrict__ bins,
+                                const int64_t *__restrict__ S, int32_t nx, int32_t ny, int32_t nz,
+                                double *__restrict__ jac)
+{
+    const double face = (double)nx * (double)ny;
+    const double norm = face / ((double)S[MC_S_LAUNCHED] * 2147483648.0) / 0x1.0p-16;
+    const int32_t row = 2 + nz;
+    for (int32_t i = threadIdx.x; i < 3 * nz; i += blockDim.x) {
+        const int32_t p = i / nz, z = i % nz;
+        const unsigned long long *gs = grad + 2 * ((2 * p) * nz + z), *gp = grad + 2 * ((2 * p + 1) * nz + z);
+        jac[p * row + 2 + z] = (join_signed(gs[0], gs[1]) + join_signed(gp[0], gp[1])) * norm / face;
+    }
+    if (threadIdx.x >= 3) return;
+    const int32_t p = threadIdx.x;
+    unsigned long long n_s = 0, n_p = 0, s_hi = 0, s_lo = 0, t_hi = 0, t_lo = 0;
+    for (int32_t z = 0; z < nz; ++z) {
+        n_s += bins[(uint64_t)z * kBinW + 4];
+        n_p += bins[(uint64_t)z * kBinW + 5];
+        const unsigned long long *gs = grad + 2 * ((2 * p) * nz + z), *gp = grad + 2 * ((2 * p + 1) * nz + z);
+        s_hi += gs[0]; s_lo += gs[1];
+        t_hi += gs[0] + gp[0]; t_lo += gs[1] + gp[1];
+    }
+    jac[p * row + 0] = n_s ? join_signed(s_hi, s_lo) * norm / (double)n_s : __builtin_nan("");
+    jac[p * row + 1] = join_signed(t_hi, t_lo) * norm / (double)(n_s + n_p);
+}
+
 // ---------------------------------------------------------------------------
 // Roofline probe: random 64-bit scatter-adds, the walk's deposit pattern
 // without the walk.  Addresses come from a 64-bit mixer of (thread, i); the
@@ -474,6 +567,7 @@ int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, 
     J->nyb = d.nyb;
     const double mu_s = opt->mu_s, mu_a = opt->mu_a, mu_t = mu_s + mu_a;
     J->mu_t = mu_t;
+    J->mu_s = mu_s;
     J->g = opt->g;
     J->path_cap = opt->path_cap > 0.0f ? opt->path_cap : kInf;
     J->s_q = mu_t > 0.0 ? (uint64_t)llround(mu_s / mu_t * 4294967296.0) : 0ull;
@@ -582,18 +676,29 @@ int enqueue_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *
     return MC_OK;
 }
 
-template <typename R>
-void enqueue_walk(int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s)
+template <typename R, bool GRAD>
+void enqueue_walk(int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t,
+                  unsigned long long *grad, hipStream_t s)
 {
+    const size_t lds = GRAD ? (size_t)6 * J.nz * sizeof(unsigned long long) : 0;
     switch (block) {
-    case 64: hipLaunchKernelGGL((k_walk<64, R>), dim3(blocks), dim3(64), 0, s, J, queue, t.chunk, t.refill); break;
-    case 128: hipLaunchKernelGGL((k_walk<128, R>), dim3(blocks), dim3(128), 0, s, J, queue, t.chunk, t.refill); break;
-    case 256: hipLaunchKernelGGL((k_walk<256, R>), dim3(blocks), dim3(256), 0, s, J, queue, t.chunk, t.refill); break;
-    default: hipLaunchKernelGGL((k_walk<512, R>), dim3(blocks), dim3(512), 0, s, J, queue, t.chunk, t.refill); break;
+    case 64:
+        hipLaunchKernelGGL((k_walk<64, R, GRAD>), dim3(blocks), dim3(64), lds, s, J, queue, t.chunk, t.refill, grad);
+        break;
+    case 128:
+        hipLaunchKernelGGL((k_walk<128, R, GRAD>), dim3(blocks), dim3(128), lds, s, J, queue, t.chunk, t.refill, grad);
+        break;
+    case 256:
+        hipLaunchKernelGGL((k_walk<256, R, GRAD>), dim3(blocks), dim3(256), lds, s, J, queue, t.chunk, t.refill, grad);
+        break;
+    default:
+        hipLaunchKernelGGL((k_walk<512, R, GRAD>), dim3(blocks), dim3(512), lds, s, J, queue, t.chunk, t.refill, grad);
+        break;
     }
 }
 
-int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s, int flags)
+int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s, int flags,
+                unsigned long long *grad)
 {
     DeviceInfo di;
     int rc = device_info(&di);
@@ -602,8 +707,13 @@ int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipSt
     const int blocks = std::max(1, di.cus * t.waves_per_cu / waves_per_block);
     const bool timed = (flags & MC_TIMED) != 0;
     if (timed && (rc = time_begin(s))) return rc;
-    if (flags & MC_FP64) enqueue_walk<double>(t.block, blocks, J, queue, t, s);
-    else enqueue_walk<float>(t.block, blocks, J, queue, t, s);
+    if (grad) {
+        if (flags & MC_FP64) enqueue_walk<double, true>(t.block, blocks, J, queue, t, grad, s);
+        else enqueue_walk<float, true>(t.block, blocks, J, queue, t, grad, s);
+    } else {
+        if (flags & MC_FP64) enqueue_walk<double, false>(t.block, blocks, J, queue, t, nullptr, s);
+        else enqueue_walk<float, false>(t.block, blocks, J, queue, t, nullptr, s);
+    }
     HIP_TRY(hipGetLastError());
     if (timed && (rc = time_end(s))) return rc;
     return MC_OK;
@@ -686,7 +796,7 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
     }
     if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
     if ((rc = pack(vol, bricks, s))) return rc;
-    return launch_walk(J, queue, t, s, flags);
+    return launch_walk(J, queue, t, s, flags, nullptr);
 }
 
 int mc_walk_elapsed_ms(float *ms)
@@ -741,6 +851,56 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
         hipLaunchKernelGGL(k_trace<float>, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, J, photon_ids, n,
                            max_steps, recs, outcome);
     HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+size_t mc_grad_workspace_bytes(const mc_volume *vol)
+{
+    if (check_volume(vol)) return 0;
+    return mc_run_workspace_bytes(vol) + mc_reduce_workspace_bytes(vol) + MC_NSUMMARY * sizeof(double);
+}
+
+int mc_grad(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons, uint64_t seed,
+            uint32_t stream_id, int flags, int64_t *fluence, int64_t *scalars, int64_t *grad_bins, double *jac,
+            double *summary, double *depth, void *workspace, size_t workspace_bytes, const mc_tune *tune,
+            void *hip_stream)
+{
+    clear_error();
+    Job J;
+    int rc = make_job(vol, opt, photon_begin, n_photons, seed, stream_id, &J);
+    if (rc) return rc;
+    if (vol->nz > MC_GRAD_MAX_NZ) return fail(MC_EINVAL, "mc_grad supports nz <= %d (got %d)", MC_GRAD_MAX_NZ, vol->nz);
+    if (!fluence || !scalars || !grad_bins || !workspace)
+        return fail(MC_EINVAL, "fluence, scalars, grad_bins and workspace must be non-NULL");
+    const size_t need = mc_grad_workspace_bytes(vol);
+    if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    const mc_tune t = resolve_tune(tune);
+    if ((rc = check_tune(t))) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    char *ws = (char *)workspace;
+    unsigned long long *queue = (unsigned long long *)ws;
+    uint64_t *bricks = (uint64_t *)(ws + kHeaderBytes);
+    unsigned long long *bins = (unsigned long long *)(ws + mc_run_workspace_bytes(vol));
+    double *scratch_q = (double *)(ws + mc_run_workspace_bytes(vol) + mc_reduce_workspace_bytes(vol));
+    J.bricks = bricks;
+    J.fluence = fluence;
+    J.scalars = scalars;
+    if (!(flags & MC_ACCUMULATE)) {
+        if ((rc = fill(fluence, dims_of(vol).nvox, s))) return rc;
+        if ((rc = fill(scalars, MC_NSCALARS, s))) return rc;
+        if ((rc = fill(grad_bins, (uint64_t)12 * vol->nz, s))) return rc;
+    }
+    if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
+    if ((rc = pack(vol, bricks, s))) return rc;
+    if ((rc = launch_walk(J, queue, t, s, flags, (unsigned long long *)grad_bins))) return rc;
+    if (jac || summary || depth) {
+        if ((rc = enqueue_reduce(vol, fluence, scalars, summary ? summary : scratch_q, depth, bins, s))) return rc;
+    }
+    if (jac) {
+        hipLaunchKernelGGL(k_grad_finalize, dim3(1), dim3(256), 0, s, (const unsigned long long *)grad_bins, bins,
+                           scalars, vol->nx, vol->ny, vol->nz, jac);
+        HIP_TRY(hipGetLastError());
+    }
     return MC_OK;
 }
 

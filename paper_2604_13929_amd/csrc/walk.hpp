@@ -42,6 +42,7 @@ struct Job {
     int32_t nx, ny, nz;
     int32_t nxb, nyb;         // bricks along x and y
     double mu_t;              // mu_s + mu_a of the solid, summed in FP64 on the host
+    double mu_s;              // mu_s of the solid (the gradient walk's score)
     float g;
     float path_cap;           // +inf when off
     uint64_t s_q;             // round(mu_s / mu_t * 2^32), <= 2^32
@@ -64,6 +65,7 @@ struct Photon {
     R ux, uy, uz;
     double s_rem;             // remaining free path, in solid path length
     double l_void, l_tot;     // path inside pores, total path
+    double score_g;           // sum of d ln p_HG / dg over the deflections so far (gradient walk)
     uint32_t w, k, steps, pid;
     uint64_t absorbed;        // weight absorbed by this photon so far
     int64_t rr;               // roulette balance of this photon
@@ -153,6 +155,7 @@ __device__ __forceinline__ void launch(Photon<R> &p, const Job &J, uint32_t pid)
     p.s_rem = free_path(J, r.z);
     p.l_void = 0.0;
     p.l_tot = 0.0;
+    p.score_g = 0.0;
     p.w = kW1;
     p.k = 0u;
     p.steps = 0u;

@@ -77,6 +77,9 @@ _SIGS = {
     "mc_reduce_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_reduce": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mc_probe_scatter": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, _P]),
+    "mc_grad_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "mc_grad": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                               ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
     "mc_batch_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
     "mc_run_batch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, _P, _P, ctypes.c_size_t, _P]),
     "mc_autotune_batch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
@@ -390,3 +393,77 @@ class BatchGraph:
             self.close()
         except Exception:
             pass
+
+
+@dataclass
+class GradResult:
+    """Forward tallies of the gradient walk, its raw score bins and the Jacobian."""
+    run: RunResult
+    bins: torch.Tensor            # int64 [3, 2, nz, 2] (hi, lo)
+    jac: torch.Tensor             # float64 [3, 2 + nz]
+    summary: torch.Tensor         # float64 [NSUMMARY]
+    depth: torch.Tensor           # float64 [3, nz]
+
+    def bins_value(self) -> np.ndarray:
+        """Exact bin values (hi * 2^32 + lo) as float64 [3, 2, nz], units 2^-16 Q31 weight x voxel."""
+        b = self.bins.cpu().numpy()
+        hi = b[..., 0].astype(np.float64)
+        lo = b[..., 1].view(np.uint64).astype(np.float64)
+        return hi * 4294967296.0 + lo
+
+
+def grad(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_begin: int = 0, stream_id: int = 0,
+         fp64: bool = False, timed: bool = False, tune: Tune | None = None) -> GradResult:
+    """mc_grad on the current stream."""
+    L = load()
+    vol = volume(mask)
+    dev = mask.device
+    nz = mask.shape[0]
+    run_ = RunResult(torch.empty(tuple(mask.shape), dtype=torch.int64, device=dev),
+                     torch.empty(NSCALARS, dtype=torch.int64, device=dev))
+    bins = torch.empty((3, 2, nz, 2), dtype=torch.int64, device=dev)
+    jac = torch.empty((3, 2 + nz), dtype=torch.float64, device=dev)
+    summary = torch.empty(NSUMMARY, dtype=torch.float64, device=dev)
+    depth = torch.empty((3, nz), dtype=torch.float64, device=dev)
+    ws = workspace(L.mc_grad_workspace_bytes(ctypes.byref(vol)), dev)
+    opt = optics.c()
+    t = tune.c() if tune is not None else None
+    flags = (MC_FP64 if fp64 else 0) | (MC_TIMED if timed else 0)
+    _check(L.mc_grad(ctypes.byref(vol), ctypes.byref(opt), photon_begin, n_photons, seed, stream_id, flags,
+                     run_.fluence.data_ptr(), run_.scalars.data_ptr(), bins.data_ptr(), jac.data_ptr(),
+                     summary.data_ptr(), depth.data_ptr(), ws.data_ptr(), ws.numel(),
+                     ctypes.byref(t) if t is not None else None, _stream(dev)), "mc_grad")
+    res = GradResult(run_, bins, jac, summary, depth)
+    res._ws = ws
+    if timed:
+        ms = ctypes.c_float(0.0)
+        _check(L.mc_walk_elapsed_ms(ctypes.byref(ms)), "mc_walk_elapsed_ms")
+        res.walk_ms = float(ms.value)
+    return res
+
+
+class PhiFn(torch.autograd.Function):
+    """(mu_s, mu_a, g) -> (<Phi>_3D, <Phi>_1D, Phi(z)) through the HIP walk.
+
+    forward: mc_run + mc_reduce.  backward: mc_grad replays the same photons
+    (same seed, stream and ids) and returns the likelihood-ratio Jacobian, which is
+    contracted with the incoming gradients.  The coefficients enter as float32.
+    """
+
+    @staticmethod
+    def forward(ctx, mu_s, mu_a, g, mask, n_photons, seed, stream_id=0, fp64=False):
+        base = Optics(float(mu_s), float(mu_a), float(g))
+        r = run(mask, base, n_photons, seed, stream_id=stream_id, fp64=fp64)
+        q, d, ws = reduce_async(mask, r)
+        ctx.save_for_backward(mu_s, mu_a, g)
+        ctx.cfg = (mask, base, n_photons, seed, stream_id, fp64)
+        return (q[SUMMARY.index("phi3d")].clone(), q[SUMMARY.index("phi1d")].clone(), d[0].clone())
+
+    @staticmethod
+    def backward(ctx, g3, g1, gz):
+        mask, base, n_photons, seed, stream_id, fp64 = ctx.cfg
+        jac = grad(mask, base, n_photons, seed, stream_id=stream_id, fp64=fp64).jac     # [3, 2 + nz]
+        v = torch.cat([g3.reshape(1), g1.reshape(1), gz.reshape(-1)]).to(jac.dtype)
+        out = jac @ v
+        mu_s, mu_a, g = ctx.saved_tensors
+        return (out[0].to(mu_s.dtype), out[1].to(mu_a.dtype), out[2].to(g.dtype), None, None, None, None, None)

@@ -115,3 +115,12 @@ def test_graph_rejects_timed_capture(lib):
     out = ctypes.c_void_p()
     assert lib.mc_batch_graph_create(ctypes.byref(jobs), 1, 2, None, 1, 1 << 20, ctypes.byref(out)) == -1
     assert lib.mc_graph_destroy(None) == 0
+
+
+def test_grad_rejects_deep_volume(lib):
+    vol = pm.McVolume(4, 4, 4096, 0, 1)
+    opt = pm.McOptics(0.5, 0.01, 0.7, 1e-4, 10, 0.0, 0, 0)
+    rc = lib.mc_grad(ctypes.byref(vol), ctypes.byref(opt), 0, 10, 1, 0, 0, 1, 1, 1, None, None, None, 1, 1 << 30,
+                     None, None)
+    assert rc == -1 and b"nz" in lib.mc_last_error()
+    assert lib.mc_grad_workspace_bytes(ctypes.byref(vol)) > 0

@@ -1,0 +1,149 @@
+"""Likelihood-ratio gradients on the GPU: the forward tallies of the gradient walk
+equal mc_run's; the score bins match the FP64 oracle's (exactly up to fixed-point
+rounding with the FP64 transport, within 4 sigma with the FP32 one); the Jacobian
+agrees with common-random-number central differences and, for a pure absorber,
+with the Beer-Lambert derivative; the autograd Function contracts it."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import closed_forms as cf
+import oracle
+from paper_2604_13929_amd import inputs
+from paper_2604_13929_amd import photonmc as pm
+
+pytestmark = pytest.mark.gpu
+W1 = 2 ** 31
+SEED = 20260809
+f32 = lambda x: float(np.float32(x))  # noqa: E731
+OPT = pm.Optics(0.5, f32(0.01), f32(0.7))
+
+
+def banner(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pm.load()
+
+
+def dev(mask):
+    return torch.from_numpy(np.ascontiguousarray(mask)).to("cuda:0")
+
+
+def norm_bins(g: pm.GradResult, mask, n):
+    """Score bins as d(sum of Phi/S0 over the voxels of a (phase, depth) cell)."""
+    nz, ny, nx = mask.shape
+    return g.bins_value() * 2.0 ** 16 * (nx * ny) / (n * W1)
+
+
+def test_grad_walk_forward_equals_run(mask_m1):
+    banner("grad walk forward tallies == mc_run")
+    d = dev(mask_m1)
+    for fp64 in (False, True):
+        r = pm.run(d, OPT, 50_000, SEED, fp64=fp64)
+        g = pm.grad(d, OPT, 50_000, SEED, fp64=fp64)
+        assert torch.equal(g.run.fluence, r.fluence) and torch.equal(g.run.scalars, r.scalars)
+        s = pm.reduce(d, r)
+        assert g.summary[pm.SUMMARY.index("phi3d")].item() == s["phi3d"]
+
+
+def test_grad_bins_fp64_match_oracle(mask_m1):
+    banner("grad bins, FP64 transport vs oracle LR")
+    n = 100_000
+    g = pm.grad(dev(mask_m1), OPT, n, SEED, fp64=True)
+    ref = oracle.run(mask_m1, OPT.mu_s, OPT.mu_a, OPT.g, n, SEED, grad=True, fluence=False)
+    nz, ny, nx = mask_m1.shape
+    got = norm_bins(g, mask_m1, n)
+    want = ref["grad"][0] * (nx * ny) / (n * W1)
+    scale = np.abs(want).max(axis=-1, keepdims=True)
+    assert np.all(np.abs(got - want) <= 1e-6 * scale + 1e-9), np.abs(got - want).max()
+
+
+def test_grad_fp32_within_oracle_error(mask_m1):
+    banner("grad Jacobian, FP32 transport vs oracle LR (4 sigma)")
+    n, B = 200_000, 32
+    g = pm.grad(dev(mask_m1), OPT, n, SEED)
+    jac = g.jac.cpu().numpy()
+    ref = oracle.run(mask_m1, OPT.mu_s, OPT.mu_a, OPT.g, n, SEED, nbatch=B, grad=True, fluence=False)
+    nz, ny, nx = mask_m1.shape
+    solid = (mask_m1 == 0)
+    per_b = ref["grad"] * (nx * ny) / (n / B * W1)                 # [B, 3, 2, nz]
+    d3 = per_b[:, :, 0, :].sum(-1) / solid.sum()
+    d1 = per_b.sum(axis=(2, 3)) / mask_m1.size
+    for col, arr in ((0, d3), (1, d1)):
+        m, s = arr.mean(0), arr.std(0, ddof=1) / math.sqrt(B)
+        assert np.all(np.abs(jac[:, col] - m) < 4 * s + 1e-12), (col, jac[:, col], m, s)
+
+
+def test_grad_pure_absorber_closed_form(mask_m1):
+    banner("d Phi / d mu_a of a pure absorber vs Beer-Lambert")
+    m = mask_m1
+    nz, ny, nx = m.shape
+    mu_a = f32(0.05)
+    n, B = 400_000, 16
+    opt = pm.Optics(0.0, mu_a, 0.0)
+    d = dev(m)
+    per = []
+    for b in range(B):
+        g = pm.grad(d, opt, n // B, SEED, photon_begin=b * (n // B))
+        per.append(norm_bins(g, m, n // B)[1])                     # mu_a, [2, nz]
+    per = np.stack(per)
+    mean, se = per.mean(0), per.std(0, ddof=1) / math.sqrt(B)
+    dd = cf.beer_lambert_voxel_dmua(m, mu_a)
+    solid = m == 0
+    want = np.stack([(dd * solid).sum(axis=(1, 2)), (dd * ~solid).sum(axis=(1, 2))])
+    assert np.all(np.abs(mean - want) <= 4 * se + 1e-9)
+
+
+def test_grad_against_crn_finite_differences():
+    banner("LR Jacobian vs CRN central differences, 64^3 mask")
+    m = inputs.spinodal_mask(64, 64, 64, 16.0, 0.7, seed=7)
+    d = dev(m)
+    n, B, h = 2_000_000, 16, 0.02
+    chunk = n // B
+    base = dict(mu_s=f32(0.5), mu_a=f32(0.01), g=f32(0.7))
+    lr = []
+    for b in range(B):
+        lr.append(pm.grad(d, pm.Optics(**base), chunk, SEED, photon_begin=b * chunk).jac.cpu().numpy()[:, :2])
+    lr = np.stack(lr)                                             # [B, 3, 2]
+    for pi, name in enumerate(("mu_s", "mu_a", "g")):
+        plus, minus = dict(base), dict(base)
+        plus[name], minus[name] = f32(base[name] * (1 + h)), f32(base[name] * (1 - h))
+        fd = []
+        for b in range(B):
+            rp = pm.reduce(d, pm.run(d, pm.Optics(**plus), chunk, SEED, photon_begin=b * chunk))
+            rm = pm.reduce(d, pm.run(d, pm.Optics(**minus), chunk, SEED, photon_begin=b * chunk))
+            fd.append([(rp[k] - rm[k]) / (plus[name] - minus[name]) for k in ("phi3d", "phi1d")])
+        fd = np.array(fd)
+        fm, fs = fd.mean(0), fd.std(0, ddof=1) / math.sqrt(B)
+        lm, ls = lr[:, pi].mean(0), lr[:, pi].std(0, ddof=1) / math.sqrt(B)
+        print(f"{name}: LR {lm} +- {ls}, FD {fm} +- {fs}")
+        assert np.all(np.abs(fm - lm) < 4 * np.hypot(fs, ls)), name
+        assert np.all(np.sign(fm) == np.sign(lm)), name
+
+
+def test_autograd_function_contracts_jacobian(mask_m1):
+    banner("PhiFn backward == Jacobian contraction")
+    d = dev(mask_m1)
+    mu_s = torch.tensor(0.5, dtype=torch.float64, requires_grad=True)
+    mu_a = torch.tensor(f32(0.01), dtype=torch.float64, requires_grad=True)
+    g = torch.tensor(f32(0.7), dtype=torch.float64, requires_grad=True)
+    phi3d, phi1d, depth = pm.PhiFn.apply(mu_s, mu_a, g, d, 20_000, SEED)
+    w = torch.linspace(0, 1, depth.numel(), dtype=torch.float64, device=depth.device)
+    loss = 2.0 * phi3d - phi1d + (w * depth).sum()
+    loss.backward()
+    jac = pm.grad(d, OPT, 20_000, SEED).jac.cpu()
+    v = torch.cat([torch.tensor([2.0, -1.0], dtype=torch.float64), w.cpu()])
+    want = jac @ v
+    got = torch.stack([mu_s.grad, mu_a.grad, g.grad])
+    assert torch.allclose(got, want, rtol=1e-12, atol=0)
+    s = pm.reduce(d, pm.run(d, OPT, 20_000, SEED))
+    assert phi3d.item() == s["phi3d"]
