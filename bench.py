@@ -98,6 +98,92 @@ def batched_leg(args, seed):
             "speedup_vs_sequential": t_seq / t_b, "jobs_bitwise_equal_to_plain": identical}
 
 
+def morphology_leg(args, seed):
+    """512 x 512 x 256 mask at phi = 0.90 next to the homogeneous slab of the same
+    thickness with (1 - phi)-scaled coefficients: RMS_w of the depth profiles and the
+    in-void path statistics of escaping photons."""
+    import numpy as np
+    import torch
+
+    from paper_2604_13929_amd import inputs
+    from paper_2604_13929_amd import photonmc as pm
+
+    wl = inputs.WORKLOADS["M3"]
+    n = args.photons
+    d3 = inputs.spinodal_mask_torch(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], wl["porosity"], seed=0)
+    dh = torch.zeros_like(d3)
+    base = pm.Optics(**inputs.SOLID_OPTICS)
+    phi = wl["porosity"]
+    opt_h = pm.Optics(float(np.float32((1 - phi) * base.mu_s)), float(np.float32((1 - phi) * base.mu_a)), base.g)
+    out = {}
+    for name, d, opt in (("M3", d3, base), ("H3", dh, opt_h)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pm.run(d, opt, n, seed, timed=True)
+        s = pm.reduce(d, r)
+        t = time.perf_counter() - t0
+        out[name] = {"ms": t * 1e3, "walk_ms": r.walk_ms, "photon_steps_per_s": s["steps_per_photon"] * n / t,
+                     "photons_per_s": n / t, "depth": s.depth, "summary": s}
+        log(f"{name}: {t * 1e3:.0f} ms, {s['steps_per_photon']:.0f} steps/photon")
+    sm, sh = out["M3"]["summary"], out["H3"]["summary"]
+    return {"workload": "512x512x256 Cahn-wave mask phi=0.90 (lambda 32) vs homogeneous slab mu_s 0.05 mu_a 0.001 g 0.7, "
+                        f"{n:.0e} photons each",
+            "rms_w_M3_vs_H3": pm.rms_w(out["M3"]["depth"], out["H3"]["depth"]),
+            "Pw_void_gt_L": sm["Pw_void_gtL"], "Pn_void_gt_L": sm["Pn_void_gtL"],
+            "mean_void_path_escaping": sm["mean_void_path"], "escaping_weight_fraction": sm["esc_frac"],
+            "phi3d": {"M3": sm["phi3d"], "H3": sh["phi3d"]}, "phi1d": {"M3": sm["phi1d"], "H3": sh["phi1d"]},
+            "r_M3": sm["r"], "R_T_A_M3": [sm["R"], sm["T"], sm["A"]], "R_T_A_H3": [sh["R"], sh["T"], sh["A"]],
+            "photon_steps_per_s": {k: out[k]["photon_steps_per_s"] for k in out},
+            "ms": {k: out[k]["ms"] for k in out}}
+
+
+def grad_leg(args, seed, mask):
+    """Likelihood-ratio Jacobian on the plain workload and its check against
+    central finite differences with common random numbers (relative step 1e-3),
+    with the spread of 8 photon sub-ranges as the error."""
+    import numpy as np
+    import torch
+
+    from paper_2604_13929_amd import inputs
+    from paper_2604_13929_amd import photonmc as pm
+
+    n = args.photons
+    base = pm.Optics(**inputs.SOLID_OPTICS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = pm.grad(mask, base, n, seed, timed=True)
+    jac = g.jac.cpu().numpy()
+    t_lr = time.perf_counter() - t0
+    steps = int(g.run.scalars[pm.SCALARS.index("steps")].item())
+    log(f"grad: {t_lr * 1e3:.0f} ms (walk {g.walk_ms:.0f} ms)")
+    B, h = 8, 1e-3
+    chunk = n // B
+    lr = np.stack([pm.grad(mask, base, chunk, seed, photon_begin=b * chunk).jac.cpu().numpy()[:, :2]
+                   for b in range(B)])
+    res = {}
+    names = ("mu_s", "mu_a", "g")
+    for pi, name in enumerate(names):
+        vals = {"mu_s": base.mu_s, "mu_a": base.mu_a, "g": base.g}
+        plus, minus = dict(vals), dict(vals)
+        plus[name] = float(np.float32(vals[name] * (1 + h)))
+        minus[name] = float(np.float32(vals[name] * (1 - h)))
+        fd = []
+        for b in range(B):
+            rp = pm.reduce(mask, pm.run(mask, pm.Optics(**plus), chunk, seed, photon_begin=b * chunk))
+            rm = pm.reduce(mask, pm.run(mask, pm.Optics(**minus), chunk, seed, photon_begin=b * chunk))
+            fd.append([(rp[k] - rm[k]) / (plus[name] - minus[name]) for k in ("phi3d", "phi1d")])
+        fd = np.array(fd)
+        fm, fs = fd.mean(0), fd.std(0, ddof=1) / np.sqrt(B)
+        lm, ls = lr[:, pi].mean(0), lr[:, pi].std(0, ddof=1) / np.sqrt(B)
+        res[name] = {"lr": jac[pi, :2].tolist(), "lr_subrange_mean": lm.tolist(), "lr_sigma": ls.tolist(),
+                     "fd": fm.tolist(), "fd_sigma": fs.tolist(), "z": ((fm - lm) / np.hypot(fs, ls)).tolist()}
+        log(f"grad check {name}: LR {lm} FD {fm} z {res[name]['z']}")
+    return {"workload": "plain workload, d<Phi>_3D and d<Phi>_1D (and dPhi(z)) wrt solid mu_s, mu_a, g",
+            "ms": t_lr * 1e3, "walk_ms": g.walk_ms, "photon_steps_per_s": steps / t_lr, "photons_per_s": n / t_lr,
+            "check_vs_crn_fd": res, "fd_relative_step": h, "subranges": B,
+            "columns": ["d_phi3d", "d_phi1d"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +193,8 @@ def main():
     ap.add_argument("--cpu-photons", type=int, default=1_000_000, help="oracle sample size (first ids)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-morph", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
@@ -222,6 +310,10 @@ def main():
 
     if not args.no_batch:
         line["batched"] = batched_leg(args, seed)
+    if not args.no_morph:
+        line["morphology_control"] = morphology_leg(args, seed)
+    if not args.no_grad:
+        line["differentiated"] = grad_leg(args, seed, mask)
 
     if not args.no_cpu:
         import oracle

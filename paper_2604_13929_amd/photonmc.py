@@ -467,3 +467,11 @@ class PhiFn(torch.autograd.Function):
         out = jac @ v
         mu_s, mu_a, g = ctx.saved_tensors
         return (out[0].to(mu_s.dtype), out[1].to(mu_a.dtype), out[2].to(g.dtype), None, None, None, None, None)
+
+
+def rms_w(profile, reference) -> float:
+    """Fluence-weighted relative RMS deviation of a depth profile from a reference
+    (the paper's discrepancy metric, Sec. 2.7): host FP64 on two short profiles."""
+    p = np.asarray(profile, dtype=np.float64)
+    q = np.asarray(reference, dtype=np.float64)
+    return float(np.sqrt(np.sum(q * ((p - q) / q) ** 2) / np.sum(q)))
