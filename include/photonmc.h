@@ -55,6 +55,8 @@ extern "C" {
 #define MC_ACCUMULATE 1     /* add to the tallies instead of zeroing them first */
 #define MC_TIMED 2          /* time the walk kernel with HIP events on the run's stream (mc_walk_elapsed_ms) */
 #define MC_FP64 4           /* geometry and scattering in FP64 instead of FP32 (reference transport) */
+#define MC_DIRECT_DEPOSIT 8 /* one atomic per voxel visit into the caller's tally, not the line-coalesced
+                               deposit log (the log is used when the bricked tally has <= 2^32 words) */
 
 /* Scalar tally channels: int64 words in a caller-owned device array of
  * MC_NSCALARS entries.  Weight channels are Q31.  For every run

@@ -47,12 +47,12 @@ __global__ void k_write_jobs(JobPack pack, Job *__restrict__ dst, int32_t count)
 
 struct BatchTallySink {
     template <typename R> __device__ __forceinline__ void segment(const Photon<R> &, const Job &, R, bool) {}
-    template <typename R> __device__ __forceinline__ void deflect(const Photon<R> &, const Job &, R) {}
-    __device__ __forceinline__ void flush(const Job &J, uint64_t v, uint64_t a)
+    template <typename R> __device__ __forceinline__ void deflect(Photon<R> &, const Job &, R) {}
+    template <typename R> __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
     {
         if (a != 0ull)
-            __hip_atomic_fetch_add((unsigned long long *)(J.fluence + v), (unsigned long long)a, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add((unsigned long long *)(J.fluence + voxel_index(J, p)), (unsigned long long)a,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
 

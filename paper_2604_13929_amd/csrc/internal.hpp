@@ -22,9 +22,14 @@ constexpr size_t kHeaderBytes = 256;  // queue counter(s) at the start of a run 
 constexpr int kBinW = 8;              // int64 words per depth bin of the reduction
 
 struct Dims {
-    int32_t nxb, nyb, nzb;
+    int32_t nxb, nyb, nzb;       // 4x4x4 mask bricks
     uint64_t nbricks, nvox;
+    int32_t tnxb, tnyb, tnzb;    // 2x2x2 tally bricks
+    uint64_t tally_words;        // int64 words of the bricked tally
+    bool logged;                 // the bricked tally fits 32-bit indices
 };
+size_t run_workspace_bytes(const Dims &d);
+size_t tally_offset(const Dims &d);
 Dims dims_of(const mc_volume *v);
 int check_volume(const mc_volume *v);
 int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons, uint64_t seed,

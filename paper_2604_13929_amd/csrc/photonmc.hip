@@ -85,18 +85,80 @@ __global__ void k_pack(const uint8_t *__restrict__ mask, int32_t nx, int32_t ny,
     bricks[b] = bits;
 }
 
+// Bricked tally -> the caller's [nz][ny][nx] tally (assign, or add when accumulating).
+__global__ void k_unbrick(const int64_t *__restrict__ T, int64_t *__restrict__ F, int32_t nx, int32_t ny, int32_t nz,
+                          int32_t tnxb, int32_t tnyb, int32_t accumulate)
+{
+    const uint64_t n = (uint64_t)nx * ny * nz;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x) {
+        const int32_t x = (int32_t)(v % (uint64_t)nx);
+        const int32_t y = (int32_t)((v / (uint64_t)nx) % (uint64_t)ny);
+        const int32_t z = (int32_t)(v / ((uint64_t)nx * ny));
+        const int64_t t = T[tally_brick_index(tnxb, tnyb, x, y, z)];
+        F[v] = accumulate ? F[v] + t : t;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Sinks: where a step's side effects go
 // ---------------------------------------------------------------------------
-struct TallySink {
-    template <typename R> __device__ __forceinline__ void segment(const Photon<R> &, const Job &, R, bool) {}
-    template <typename R> __device__ __forceinline__ void deflect(Photon<R> &, const Job &, R) {}
-    __device__ __forceinline__ void flush(const Job &J, uint64_t v, uint64_t acc)
+// Fluence deposits straight to the caller's [nz][ny][nx] tally, one device-scope
+// atomic per voxel visit.
+struct DirectDeposit {
+    template <typename R>
+    __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
     {
-        if (acc != 0ull)
-            __hip_atomic_fetch_add((unsigned long long *)(J.fluence + v), (unsigned long long)acc,
+        if (a != 0ull)
+            __hip_atomic_fetch_add((unsigned long long *)(J.fluence + voxel_index(J, p)), (unsigned long long)a,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+};
+
+// Fluence deposits logged in LDS, one slot per lane and iteration, into a tally
+// of 2x2x2 bricks; every kLogK iterations the wavefront issues the log with
+// lanes transposed so that one atomic instruction carries kLogK successive
+// deposits of each of 64/kLogK lanes: deposits of one photon that fall in the
+// same brick (the same 64-byte line) then travel as one memory-side request.
+constexpr int kLogK = 8;
+constexpr int kLogStride = 65;  // 64 lanes + 1: the transposed reads hit distinct banks
+
+struct LoggedDeposit {
+    uint32_t *lidx;             // this wavefront's log: [kLogK][kLogStride]
+    unsigned long long *lval;
+    uint32_t slot;              // (iteration % kLogK) * kLogStride + lane
+    template <typename R>
+    __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
+    {
+        if (a != 0ull) {
+            lidx[slot] = tally_brick_index(J.tnxb, J.tnyb, p.ix, p.iy, p.iz);
+            lval[slot] = a;
+        }
+    }
+};
+
+__device__ __forceinline__ void flush_log(uint32_t *lidx, unsigned long long *lval, int64_t *tally, uint32_t lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = 0; i < kLogK; ++i) {
+        const uint32_t src = (uint32_t)i * (64 / kLogK) + lane / kLogK;
+        const uint32_t e = (lane % kLogK) * kLogStride + src;
+        const unsigned long long v = lval[e];
+        if (v) {
+            __hip_atomic_fetch_add((unsigned long long *)(tally + lidx[e]), v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            lval[e] = 0ull;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <class Deposit>
+struct TallySink : Deposit {
+    template <typename R> __device__ __forceinline__ void segment(const Photon<R> &, const Job &, R, bool) {}
+    template <typename R> __device__ __forceinline__ void deflect(Photon<R> &, const Job &, R) {}
 };
 
 // Likelihood-ratio (perturbation Monte Carlo) scores of the track-length
@@ -114,7 +176,8 @@ __device__ __forceinline__ double hg_score(double ct, double g)
     return -2.0 * g / (1.0 - g * g) + 3.0 * (ct - g) / (1.0 + g * g - 2.0 * g * ct);
 }
 
-struct GradSink : TallySink {
+template <class Deposit>
+struct GradSink : Deposit {
     unsigned long long *bins;  // LDS [3][2][nz]
     int32_t nz;
     double inv_mu_s;           // 1/mu_s, 0 when mu_s = 0
@@ -173,21 +236,36 @@ __device__ __forceinline__ void account(unsigned long long *acc, const Photon<R>
 // run converged.  A wavefront exits when the queue is exhausted, its range is
 // empty and none of its lanes is alive; every photon terminates (escape,
 // weight 0, roulette, or the step cap), so every wavefront exits.
-template <bool GRAD> struct SinkOf { using type = TallySink; };
-template <> struct SinkOf<true> { using type = GradSink; };
+template <bool GRAD, bool LOGGED> struct SinkOf {
+    using Deposit = typename std::conditional<LOGGED, LoggedDeposit, DirectDeposit>::type;
+    using type = typename std::conditional<GRAD, GradSink<Deposit>, TallySink<Deposit>>::type;
+};
 
-template <int BLOCK, typename R, bool GRAD>
+// LOGGED: J.fluence is the bricked tally (see LoggedDeposit).
+template <int BLOCK, typename R, bool GRAD, bool LOGGED>
 __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long *__restrict__ queue, int32_t chunk,
                                                 int32_t refill, unsigned long long *__restrict__ grad)
 {
+    constexpr int kWaves = BLOCK / 64;
     __shared__ unsigned long long acc[MC_NSCALARS];
+    __shared__ uint32_t s_lidx[LOGGED ? kWaves * kLogK * kLogStride : 1];
+    __shared__ unsigned long long s_lval[LOGGED ? kWaves * kLogK * kLogStride : 1];
     extern __shared__ unsigned long long s_grad[];  // GRAD: [3][2][nz]
+    const uint32_t lane = __lane_id();
+    uint32_t *lidx = s_lidx + (threadIdx.x >> 6) * (LOGGED ? kLogK * kLogStride : 0);
+    unsigned long long *lval = s_lval + (threadIdx.x >> 6) * (LOGGED ? kLogK * kLogStride : 0);
     if (threadIdx.x < MC_NSCALARS) acc[threadIdx.x] = 0ull;
     if (GRAD)
         for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) s_grad[i] = 0ull;
+    if (LOGGED)
+        for (int i = 0; i < kLogK; ++i) lval[i * kLogStride + lane] = 0ull;
     __syncthreads();
 
-    typename SinkOf<GRAD>::type sink;
+    typename SinkOf<GRAD, LOGGED>::type sink;
+    if constexpr (LOGGED) {
+        sink.lidx = lidx;
+        sink.lval = lval;
+    }
     if constexpr (GRAD) {
         sink.bins = s_grad;
         sink.nz = J.nz;
@@ -198,7 +276,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
     uint64_t q_next = 0, q_end = 0;
     bool exhausted = false;
     const uint64_t total = J.n_photons;
-    const uint32_t lane = __lane_id();
+    uint32_t iter = 0;
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -229,13 +307,18 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
             if (exhausted && q_next >= q_end && !__any(alive)) break;
         }
         if (alive) {
+            if constexpr (LOGGED) sink.slot = (iter % kLogK) * kLogStride + lane;
             const int32_t ev = step(p, J, sink);
             if (ev >= EV_FIRST_TERMINAL) {
                 account(acc, p, ev, J.nz);
                 alive = false;
             }
         }
+        if constexpr (LOGGED) {
+            if (++iter % kLogK == 0) flush_log(lidx, lval, J.fluence, lane);
+        }
     }
+    if constexpr (LOGGED) flush_log(lidx, lval, J.fluence, lane);
     __syncthreads();
     if (threadIdx.x < MC_NSCALARS) {
         const unsigned long long v = acc[threadIdx.x];
@@ -271,7 +354,7 @@ struct TraceSink {
         }
     }
     template <typename R> __device__ __forceinline__ void deflect(const Photon<R> &, const Job &, R) {}
-    __device__ __forceinline__ void flush(const Job &, uint64_t, uint64_t) {}
+    template <typename R> __device__ __forceinline__ void flush(const Job &, const Photon<R> &, uint64_t) {}
     __device__ __forceinline__ void post(int32_t ev)
     {
         if (n < max_rec) rec[n].event = ev;
@@ -526,7 +609,21 @@ Dims dims_of(const mc_volume *v)
     d.nzb = (v->nz + 3) / 4;
     d.nbricks = (uint64_t)d.nxb * d.nyb * d.nzb;
     d.nvox = (uint64_t)v->nx * v->ny * v->nz;
+    d.tnxb = (v->nx + 1) / 2;
+    d.tnyb = (v->ny + 1) / 2;
+    d.tnzb = (v->nz + 1) / 2;
+    d.tally_words = (uint64_t)d.tnxb * d.tnyb * d.tnzb * 8;
+    d.logged = d.tally_words <= (1ull << 32);
     return d;
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t tally_offset(const Dims &d) { return kHeaderBytes + align256(d.nbricks * sizeof(uint64_t)); }
+
+size_t run_workspace_bytes(const Dims &d)
+{
+    return tally_offset(d) + (d.logged ? align256(d.tally_words * sizeof(int64_t)) : 0);
 }
 
 int check_volume(const mc_volume *v)
@@ -565,6 +662,8 @@ int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, 
     J->nz = vol->nz;
     J->nxb = d.nxb;
     J->nyb = d.nyb;
+    J->tnxb = d.tnxb;
+    J->tnyb = d.tnyb;
     const double mu_s = opt->mu_s, mu_a = opt->mu_a, mu_t = mu_s + mu_a;
     J->mu_t = mu_t;
     J->mu_s = mu_s;
@@ -676,29 +775,41 @@ int enqueue_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *
     return MC_OK;
 }
 
-template <typename R, bool GRAD>
+template <typename R, bool GRAD, bool LOGGED>
 void enqueue_walk(int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t,
                   unsigned long long *grad, hipStream_t s)
 {
     const size_t lds = GRAD ? (size_t)6 * J.nz * sizeof(unsigned long long) : 0;
     switch (block) {
     case 64:
-        hipLaunchKernelGGL((k_walk<64, R, GRAD>), dim3(blocks), dim3(64), lds, s, J, queue, t.chunk, t.refill, grad);
+        hipLaunchKernelGGL((k_walk<64, R, GRAD, LOGGED>), dim3(blocks), dim3(64), lds, s, J, queue, t.chunk, t.refill,
+                           grad);
         break;
     case 128:
-        hipLaunchKernelGGL((k_walk<128, R, GRAD>), dim3(blocks), dim3(128), lds, s, J, queue, t.chunk, t.refill, grad);
+        hipLaunchKernelGGL((k_walk<128, R, GRAD, LOGGED>), dim3(blocks), dim3(128), lds, s, J, queue, t.chunk,
+                           t.refill, grad);
         break;
     case 256:
-        hipLaunchKernelGGL((k_walk<256, R, GRAD>), dim3(blocks), dim3(256), lds, s, J, queue, t.chunk, t.refill, grad);
+        hipLaunchKernelGGL((k_walk<256, R, GRAD, LOGGED>), dim3(blocks), dim3(256), lds, s, J, queue, t.chunk,
+                           t.refill, grad);
         break;
     default:
-        hipLaunchKernelGGL((k_walk<512, R, GRAD>), dim3(blocks), dim3(512), lds, s, J, queue, t.chunk, t.refill, grad);
+        hipLaunchKernelGGL((k_walk<512, R, GRAD, LOGGED>), dim3(blocks), dim3(512), lds, s, J, queue, t.chunk,
+                           t.refill, grad);
         break;
     }
 }
 
+template <typename R, bool GRAD>
+void enqueue_walk_dep(bool logged, int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t,
+                      unsigned long long *grad, hipStream_t s)
+{
+    if (logged) enqueue_walk<R, GRAD, true>(block, blocks, J, queue, t, grad, s);
+    else enqueue_walk<R, GRAD, false>(block, blocks, J, queue, t, grad, s);
+}
+
 int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s, int flags,
-                unsigned long long *grad)
+                unsigned long long *grad, bool logged)
 {
     DeviceInfo di;
     int rc = device_info(&di);
@@ -708,14 +819,46 @@ int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipSt
     const bool timed = (flags & MC_TIMED) != 0;
     if (timed && (rc = time_begin(s))) return rc;
     if (grad) {
-        if (flags & MC_FP64) enqueue_walk<double, true>(t.block, blocks, J, queue, t, grad, s);
-        else enqueue_walk<float, true>(t.block, blocks, J, queue, t, grad, s);
+        if (flags & MC_FP64) enqueue_walk_dep<double, true>(logged, t.block, blocks, J, queue, t, grad, s);
+        else enqueue_walk_dep<float, true>(logged, t.block, blocks, J, queue, t, grad, s);
     } else {
-        if (flags & MC_FP64) enqueue_walk<double, false>(t.block, blocks, J, queue, t, nullptr, s);
-        else enqueue_walk<float, false>(t.block, blocks, J, queue, t, nullptr, s);
+        if (flags & MC_FP64) enqueue_walk_dep<double, false>(logged, t.block, blocks, J, queue, t, nullptr, s);
+        else enqueue_walk_dep<float, false>(logged, t.block, blocks, J, queue, t, nullptr, s);
     }
     HIP_TRY(hipGetLastError());
     if (timed && (rc = time_end(s))) return rc;
+    return MC_OK;
+}
+
+// Zero the tallies (unless accumulating), pack the mask, walk, and for the
+// logged deposit path move the bricked tally into the caller's layout.
+int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws, unsigned long long *grad_bins,
+             hipStream_t s)
+{
+    const Dims d = dims_of(vol);
+    const bool logged = d.logged && !(flags & MC_DIRECT_DEPOSIT);
+    unsigned long long *queue = (unsigned long long *)ws;
+    uint64_t *bricks = (uint64_t *)(ws + kHeaderBytes);
+    int64_t *tally = (int64_t *)(ws + tally_offset(d));
+    int64_t *fluence = J.fluence;
+    int rc;
+    if (!(flags & MC_ACCUMULATE)) {
+        if (!logged && (rc = fill(fluence, d.nvox, s))) return rc;
+        if ((rc = fill(J.scalars, MC_NSCALARS, s))) return rc;
+        if (grad_bins && (rc = fill((int64_t *)grad_bins, (uint64_t)12 * vol->nz, s))) return rc;
+    }
+    if (logged && (rc = fill(tally, d.tally_words, s))) return rc;
+    if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
+    if ((rc = pack(vol, bricks, s))) return rc;
+    J.bricks = bricks;
+    if (logged) J.fluence = tally;
+    if ((rc = launch_walk(J, queue, t, s, flags, grad_bins, logged))) return rc;
+    if (logged) {
+        const uint64_t blocks = std::min<uint64_t>((d.nvox + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_unbrick, dim3((unsigned)blocks), dim3(256), 0, s, tally, fluence, vol->nx, vol->ny,
+                           vol->nz, d.tnxb, d.tnyb, (flags & MC_ACCUMULATE) ? 1 : 0);
+        HIP_TRY(hipGetLastError());
+    }
     return MC_OK;
 }
 
@@ -768,7 +911,7 @@ void mc_tune_default(mc_tune *t)
 size_t mc_run_workspace_bytes(const mc_volume *vol)
 {
     if (check_volume(vol)) return 0;
-    return kHeaderBytes + dims_of(vol).nbricks * sizeof(uint64_t);
+    return run_workspace_bytes(dims_of(vol));
 }
 
 int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons, uint64_t seed,
@@ -784,19 +927,9 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
     if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
     const mc_tune t = resolve_tune(tune);
     if ((rc = check_tune(t))) return rc;
-    hipStream_t s = (hipStream_t)hip_stream;
-    unsigned long long *queue = (unsigned long long *)workspace;
-    uint64_t *bricks = (uint64_t *)((char *)workspace + kHeaderBytes);
-    J.bricks = bricks;
     J.fluence = fluence;
     J.scalars = scalars;
-    if (!(flags & MC_ACCUMULATE)) {
-        if ((rc = fill(fluence, dims_of(vol).nvox, s))) return rc;
-        if ((rc = fill(scalars, MC_NSCALARS, s))) return rc;
-    }
-    if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
-    if ((rc = pack(vol, bricks, s))) return rc;
-    return launch_walk(J, queue, t, s, flags, nullptr);
+    return run_walk(vol, J, flags, t, (char *)workspace, nullptr, (hipStream_t)hip_stream);
 }
 
 int mc_walk_elapsed_ms(float *ms)
@@ -878,21 +1011,11 @@ int mc_grad(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, u
     if ((rc = check_tune(t))) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     char *ws = (char *)workspace;
-    unsigned long long *queue = (unsigned long long *)ws;
-    uint64_t *bricks = (uint64_t *)(ws + kHeaderBytes);
     unsigned long long *bins = (unsigned long long *)(ws + mc_run_workspace_bytes(vol));
     double *scratch_q = (double *)(ws + mc_run_workspace_bytes(vol) + mc_reduce_workspace_bytes(vol));
-    J.bricks = bricks;
     J.fluence = fluence;
     J.scalars = scalars;
-    if (!(flags & MC_ACCUMULATE)) {
-        if ((rc = fill(fluence, dims_of(vol).nvox, s))) return rc;
-        if ((rc = fill(scalars, MC_NSCALARS, s))) return rc;
-        if ((rc = fill(grad_bins, (uint64_t)12 * vol->nz, s))) return rc;
-    }
-    if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
-    if ((rc = pack(vol, bricks, s))) return rc;
-    if ((rc = launch_walk(J, queue, t, s, flags, (unsigned long long *)grad_bins))) return rc;
+    if ((rc = run_walk(vol, J, flags, t, ws, (unsigned long long *)grad_bins, s))) return rc;
     if (jac || summary || depth) {
         if ((rc = enqueue_reduce(vol, fluence, scalars, summary ? summary : scratch_q, depth, bins, s))) return rc;
     }

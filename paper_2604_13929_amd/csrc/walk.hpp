@@ -41,6 +41,7 @@ struct Job {
     int64_t *scalars;         // [MC_NSCALARS]
     int32_t nx, ny, nz;
     int32_t nxb, nyb;         // bricks along x and y
+    int32_t tnxb, tnyb;       // 2x2x2 tally bricks along x and y (logged deposits)
     double mu_t;              // mu_s + mu_a of the solid, summed in FP64 on the host
     double mu_s;              // mu_s of the solid (the gradient walk's score)
     float g;
@@ -115,6 +116,14 @@ template <typename R>
 __device__ __forceinline__ uint64_t voxel_index(const Job &J, const Photon<R> &p)
 {
     return ((uint64_t)p.iz * (uint64_t)J.ny + (uint64_t)p.iy) * (uint64_t)J.nx + (uint64_t)p.ix;
+}
+
+// Index in a tally stored as 2x2x2 bricks of int64, one brick per 64-byte line,
+// so that successive deposits of a photon tend to share a line.
+__device__ __forceinline__ uint32_t tally_brick_index(int32_t tnxb, int32_t tnyb, int32_t ix, int32_t iy, int32_t iz)
+{
+    const uint32_t b = ((uint32_t)(iz >> 1) * (uint32_t)tnyb + (uint32_t)(iy >> 1)) * (uint32_t)tnxb + (uint32_t)(ix >> 1);
+    return (b << 3) | ((uint32_t)(iz & 1) << 2) | ((uint32_t)(iy & 1) << 1) | (uint32_t)(ix & 1);
 }
 
 __device__ __forceinline__ double free_path(const Job &J, uint32_t r)
@@ -270,7 +279,7 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
         if (axis != 0) p.fx = clamp01(p.fx + p.ux * d);
         if (axis != 1) p.fy = clamp01(p.fy + p.uy * d);
         if (axis != 2) p.fz = clamp01(p.fz + p.uz * d);
-        sink.flush(J, voxel_index(J, p), p.acc);
+        sink.flush(J, p, p.acc);
         p.acc = 0ull;
         ev = axis;
         if (axis == 0) {
@@ -290,7 +299,7 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
     if (ev < EV_FIRST_TERMINAL && (p.steps >= J.max_steps || p.l_tot > (double)J.path_cap)) ev = EV_LOST;
     if (ev >= EV_FIRST_TERMINAL && p.acc != 0ull) {
         // photon ends inside a voxel (absorbed, roulette, cap): flush what it left there
-        sink.flush(J, voxel_index(J, p), p.acc);
+        sink.flush(J, p, p.acc);
         p.acc = 0ull;
     }
     return ev;

@@ -20,6 +20,7 @@ LIB_PATH = _build.LIB
 MC_ACCUMULATE = 1
 MC_TIMED = 2
 MC_FP64 = 4
+MC_DIRECT_DEPOSIT = 8
 NSCALARS = 16
 NSUMMARY = 32
 SCALARS = ["R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_w_void_path_lo", "esc_n", "esc_n_gtL",
@@ -192,7 +193,7 @@ def workspace(nbytes: int, device) -> torch.Tensor:
 
 def run(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_begin: int = 0, stream_id: int = 0,
         accumulate: RunResult | None = None, tune: Tune | None = None, timed: bool = False,
-        fp64: bool = False) -> RunResult:
+        fp64: bool = False, direct: bool = False) -> RunResult:
     """mc_run on the current stream of the mask's device (fp64: the FP64 reference transport)."""
     L = load()
     vol = volume(mask)
@@ -207,6 +208,8 @@ def run(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_be
         flags |= MC_TIMED
     if fp64:
         flags |= MC_FP64
+    if direct:
+        flags |= MC_DIRECT_DEPOSIT
     nbytes = L.mc_run_workspace_bytes(ctypes.byref(vol))
     ws = workspace(nbytes, dev)
     opt = optics.c()
