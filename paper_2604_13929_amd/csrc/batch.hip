@@ -56,6 +56,51 @@ struct BatchTallySink {
     }
 };
 
+// Line-coalesced deposits for the batch: as the plain walk's log, with the job
+// index in the top 6 bits of each logged value (a per-visit deposit stays below
+// 2^58 Q31 units because batch jobs cap a photon at 2^26 steps).
+constexpr int kBLogK = 8;
+constexpr int kBLogStride = 65;
+constexpr int kJobShift = 58;
+constexpr unsigned long long kValMask = (1ull << kJobShift) - 1ull;
+
+struct BatchLoggedSink {
+    uint32_t *lidx;
+    unsigned long long *lval;
+    uint32_t slot;
+    unsigned long long tag;     // job << kJobShift
+    template <typename R> __device__ __forceinline__ void segment(const Photon<R> &, const Job &, R, bool) {}
+    template <typename R> __device__ __forceinline__ void deflect(Photon<R> &, const Job &, R) {}
+    template <typename R> __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
+    {
+        if (a != 0ull) {
+            lidx[slot] = tally_brick_index(J.tnxb, J.tnyb, p.ix, p.iy, p.iz);
+            lval[slot] = a | tag;
+        }
+    }
+};
+
+__device__ __forceinline__ void flush_batch_log(uint32_t *lidx, unsigned long long *lval, const Job *jobs,
+                                                uint32_t lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = 0; i < kBLogK; ++i) {
+        const uint32_t src = (uint32_t)i * (64 / kBLogK) + lane / kBLogK;
+        const uint32_t e = (lane % kBLogK) * kBLogStride + src;
+        const unsigned long long v = lval[e];
+        if (v) {
+            int64_t *tally = jobs[v >> kJobShift].fluence;
+            __hip_atomic_fetch_add((unsigned long long *)(tally + lidx[e]), v & kValMask, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            lval[e] = 0ull;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <typename R>
 __device__ __forceinline__ void account_job(unsigned long long *acc, const Photon<R> &p, int32_t ev, int32_t nz)
 {
@@ -83,13 +128,22 @@ __device__ __forceinline__ void account_job(unsigned long long *acc, const Photo
 // Same queue discipline as the plain walk: a wavefront-private range of queue
 // positions refilled by one atomic, idle lanes refilled together, exit once
 // the queue is exhausted and no lane is alive.
-template <int BLOCK, typename R>
+// LOGGED: every job's fluence pointer is its bricked tally.
+template <int BLOCK, typename R, bool LOGGED>
 __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jobs, int32_t n_jobs,
                                                       unsigned long long *__restrict__ queue, int32_t chunk,
                                                       int32_t refill)
 {
+    constexpr int kWaves = BLOCK / 64;
     __shared__ Job s_jobs[MC_MAX_BATCH_JOBS];
     __shared__ unsigned long long acc[MC_MAX_BATCH_JOBS][MC_NSCALARS];
+    __shared__ uint32_t s_lidx[LOGGED ? kWaves * kBLogK * kBLogStride : 1];
+    __shared__ unsigned long long s_lval[LOGGED ? kWaves * kBLogK * kBLogStride : 1];
+    const uint32_t lane = __lane_id();
+    uint32_t *lidx = s_lidx + (threadIdx.x >> 6) * (LOGGED ? kBLogK * kBLogStride : 0);
+    unsigned long long *lval = s_lval + (threadIdx.x >> 6) * (LOGGED ? kBLogK * kBLogStride : 0);
+    if (LOGGED)
+        for (int i = 0; i < kBLogK; ++i) lval[i * kBLogStride + lane] = 0ull;
     {
         const uint64_t *src = (const uint64_t *)jobs;
         uint64_t *dst = (uint64_t *)s_jobs;
@@ -101,13 +155,17 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
     __syncthreads();
 
     const uint64_t total = s_jobs[n_jobs - 1].queue_begin + s_jobs[n_jobs - 1].n_photons;
-    BatchTallySink sink;
+    typename std::conditional<LOGGED, BatchLoggedSink, BatchTallySink>::type sink;
+    if constexpr (LOGGED) {
+        sink.lidx = lidx;
+        sink.lval = lval;
+    }
     Photon<R> p;
     int32_t job = 0;
     bool alive = false;
     uint64_t q_next = 0, q_end = 0;
     bool exhausted = false;
-    const uint32_t lane = __lane_id();
+    uint32_t iter = 0;
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -148,13 +206,21 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
         }
         if (alive) {
             const Job &J = s_jobs[job];
+            if constexpr (LOGGED) {
+                sink.slot = (iter % kBLogK) * kBLogStride + lane;
+                sink.tag = (unsigned long long)job << kJobShift;
+            }
             const int32_t ev = step(p, J, sink);
             if (ev >= EV_FIRST_TERMINAL) {
                 account_job(acc[job], p, ev, J.nz);
                 alive = false;
             }
         }
+        if constexpr (LOGGED) {
+            if (++iter % kBLogK == 0) flush_batch_log(lidx, lval, s_jobs, lane);
+        }
     }
+    if constexpr (LOGGED) flush_batch_log(lidx, lval, s_jobs, lane);
     __syncthreads();
     for (int32_t i = threadIdx.x; i < n_jobs * MC_NSCALARS; i += BLOCK) {
         const unsigned long long v = acc[i / MC_NSCALARS][i % MC_NSCALARS];
@@ -169,7 +235,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t jobs_off, bricks_off[MC_MAX_BATCH_JOBS], bins_off[MC_MAX_BATCH_JOBS], total;
+    size_t jobs_off, bricks_off[MC_MAX_BATCH_JOBS], bins_off[MC_MAX_BATCH_JOBS], tally_off[MC_MAX_BATCH_JOBS], total;
+    bool logged;   // every job's bricked tally fits 32-bit indices
 };
 
 Layout layout_of(const mc_job *jobs, int32_t n)
@@ -178,11 +245,16 @@ Layout layout_of(const mc_job *jobs, int32_t n)
     size_t off = kHeaderBytes;
     L.jobs_off = off;
     off += align_up(sizeof(Job) * MC_MAX_BATCH_JOBS);
+    L.logged = true;
+    for (int32_t i = 0; i < n; ++i) L.logged = L.logged && dims_of(&jobs[i].vol).logged;
     for (int32_t i = 0; i < n; ++i) {
+        const Dims d = dims_of(&jobs[i].vol);
         L.bricks_off[i] = off;
-        off += align_up(dims_of(&jobs[i].vol).nbricks * sizeof(uint64_t));
+        off += align_up(d.nbricks * sizeof(uint64_t));
         L.bins_off[i] = off;
         off += align_up((size_t)jobs[i].vol.nz * kBinW * sizeof(uint64_t));
+        L.tally_off[i] = off;
+        if (L.logged) off += align_up(d.tally_words * sizeof(int64_t));
     }
     L.total = off;
     return L;
@@ -230,8 +302,9 @@ int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, Prepared *
             return fail(rc, "job %d: %s", i, msg);
         }
         if (!jb.fluence || !jb.scalars) return fail(MC_EINVAL, "job %d: fluence and scalars must be non-NULL", i);
+        if (J.max_steps > (1u << 26)) return fail(MC_EINVAL, "job %d: batch jobs allow max_steps <= 2^26", i);
         J.bricks = (const uint64_t *)(ws + P->L.bricks_off[i]);
-        J.fluence = jb.fluence;
+        J.fluence = P->L.logged ? (int64_t *)(ws + P->L.tally_off[i]) : jb.fluence;
         J.scalars = jb.scalars;
         J.queue_begin = q;
         q += jb.n_photons;
@@ -240,22 +313,26 @@ int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, Prepared *
     return MC_OK;
 }
 
-template <typename R>
+template <typename R, bool LOGGED>
 void enqueue_batch_walk(int block, int blocks, const Job *table, int32_t n, unsigned long long *queue,
                         const mc_tune &t, hipStream_t s)
 {
     switch (block) {
     case 64:
-        hipLaunchKernelGGL((k_walk_batch<64, R>), dim3(blocks), dim3(64), 0, s, table, n, queue, t.chunk, t.refill);
+        hipLaunchKernelGGL((k_walk_batch<64, R, LOGGED>), dim3(blocks), dim3(64), 0, s, table, n, queue, t.chunk,
+                           t.refill);
         break;
     case 128:
-        hipLaunchKernelGGL((k_walk_batch<128, R>), dim3(blocks), dim3(128), 0, s, table, n, queue, t.chunk, t.refill);
+        hipLaunchKernelGGL((k_walk_batch<128, R, LOGGED>), dim3(blocks), dim3(128), 0, s, table, n, queue, t.chunk,
+                           t.refill);
         break;
     case 256:
-        hipLaunchKernelGGL((k_walk_batch<256, R>), dim3(blocks), dim3(256), 0, s, table, n, queue, t.chunk, t.refill);
+        hipLaunchKernelGGL((k_walk_batch<256, R, LOGGED>), dim3(blocks), dim3(256), 0, s, table, n, queue, t.chunk,
+                           t.refill);
         break;
     default:
-        hipLaunchKernelGGL((k_walk_batch<512, R>), dim3(blocks), dim3(512), 0, s, table, n, queue, t.chunk, t.refill);
+        hipLaunchKernelGGL((k_walk_batch<512, R, LOGGED>), dim3(blocks), dim3(512), 0, s, table, n, queue, t.chunk,
+                           t.refill);
         break;
     }
 }
@@ -286,8 +363,13 @@ int enqueue_walk_only(const Prepared &P, char *ws, const mc_tune &t, int flags, 
     const Job *table = (const Job *)(ws + P.L.jobs_off);
     unsigned long long *queue = (unsigned long long *)ws;
     const int32_t n = (int32_t)P.table.size();
-    if (flags & MC_FP64) enqueue_batch_walk<double>(t.block, blocks, table, n, queue, t, s);
-    else enqueue_batch_walk<float>(t.block, blocks, table, n, queue, t, s);
+    if (P.L.logged) {
+        if (flags & MC_FP64) enqueue_batch_walk<double, true>(t.block, blocks, table, n, queue, t, s);
+        else enqueue_batch_walk<float, true>(t.block, blocks, table, n, queue, t, s);
+    } else {
+        if (flags & MC_FP64) enqueue_batch_walk<double, false>(t.block, blocks, table, n, queue, t, s);
+        else enqueue_batch_walk<float, false>(t.block, blocks, table, n, queue, t, s);
+    }
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }
@@ -300,16 +382,25 @@ int enqueue_batch(const mc_job *jobs, const Prepared &P, char *ws, const mc_tune
     const int32_t n = (int32_t)P.table.size();
     for (int32_t i = 0; i < n; ++i) {
         const mc_job &jb = jobs[i];
+        const Dims d = dims_of(&jb.vol);
         if (!jb.accumulate) {
-            if ((rc = fill(jb.fluence, dims_of(&jb.vol).nvox, s))) return rc;
+            if (!P.L.logged && (rc = fill(jb.fluence, d.nvox, s))) return rc;
             if ((rc = fill(jb.scalars, MC_NSCALARS, s))) return rc;
         }
+        if (P.L.logged && (rc = fill((int64_t *)(ws + P.L.tally_off[i]), d.tally_words, s))) return rc;
         if ((rc = pack(&jb.vol, (uint64_t *)(ws + P.L.bricks_off[i]), s))) return rc;
     }
     const bool timed = (flags & MC_TIMED) != 0;
     if (timed && (rc = time_begin(s))) return rc;
     if ((rc = enqueue_walk_only(P, ws, t, flags, s))) return rc;
     if (timed && (rc = time_end(s))) return rc;
+    if (P.L.logged) {
+        for (int32_t i = 0; i < n; ++i) {
+            const mc_job &jb = jobs[i];
+            if ((rc = unbrick((const int64_t *)(ws + P.L.tally_off[i]), jb.fluence, &jb.vol, jb.accumulate != 0, s)))
+                return rc;
+        }
+    }
     for (int32_t i = 0; i < n; ++i) {
         const mc_job &jb = jobs[i];
         if (!jb.summary) continue;

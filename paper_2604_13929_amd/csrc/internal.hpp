@@ -46,6 +46,7 @@ int check_tune(const mc_tune &t);
 // asynchronous building blocks on a stream
 int fill(int64_t *p, uint64_t n, hipStream_t s);
 int pack(const mc_volume *vol, uint64_t *bricks, hipStream_t s);
+int unbrick(const int64_t *tally, int64_t *fluence, const mc_volume *vol, bool accumulate, hipStream_t s);
 int enqueue_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scalars, double *summary,
                    double *depth, unsigned long long *bins, hipStream_t s);
 

@@ -853,12 +853,17 @@ int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws,
     J.bricks = bricks;
     if (logged) J.fluence = tally;
     if ((rc = launch_walk(J, queue, t, s, flags, grad_bins, logged))) return rc;
-    if (logged) {
-        const uint64_t blocks = std::min<uint64_t>((d.nvox + 255) / 256, 16384);
-        hipLaunchKernelGGL(k_unbrick, dim3((unsigned)blocks), dim3(256), 0, s, tally, fluence, vol->nx, vol->ny,
-                           vol->nz, d.tnxb, d.tnyb, (flags & MC_ACCUMULATE) ? 1 : 0);
-        HIP_TRY(hipGetLastError());
-    }
+    if (logged) return unbrick(tally, fluence, vol, (flags & MC_ACCUMULATE) != 0, s);
+    return MC_OK;
+}
+
+int unbrick(const int64_t *tally, int64_t *fluence, const mc_volume *vol, bool accumulate, hipStream_t s)
+{
+    const Dims d = dims_of(vol);
+    const uint64_t blocks = std::min<uint64_t>((d.nvox + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_unbrick, dim3((unsigned)blocks), dim3(256), 0, s, tally, fluence, vol->nx, vol->ny, vol->nz,
+                       d.tnxb, d.tnyb, accumulate ? 1 : 0);
+    HIP_TRY(hipGetLastError());
     return MC_OK;
 }
 

@@ -254,6 +254,9 @@ def test_bitwise_reproducible_and_tune_invariant(mask_m1):
     for t in (None, pm.Tune(64, 8, 32, 1), pm.Tune(512, 4, 1024, 64), pm.Tune(128, 32, 7, 33)):
         r = pm.run(d, OPT, n, SEED, tune=t)
         assert torch.equal(r.fluence, F0) and torch.equal(r.scalars, S0), t
+        # the deposit path (line-coalesced log or one atomic per visit) changes nothing either
+        r = pm.run(d, OPT, n, SEED, tune=t, direct=True)
+        assert torch.equal(r.fluence, F0) and torch.equal(r.scalars, S0), t
 
 
 def test_resume_split_equals_whole(mask_m1):
