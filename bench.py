@@ -25,6 +25,34 @@ if ROOT not in sys.path:
 METRIC = "photon-steps/sec and photons/sec at 256^3 phi=0.70; batched vs plain"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_STEP = 8  # one int64 track-length deposit per photon-step
+# the device sources the walk kernel is built from; counter summaries under profiles/ record their hash
+SOURCES = ["include/photonmc.h", "paper_2604_13929_amd/csrc/batch.hip", "paper_2604_13929_amd/csrc/internal.hpp",
+           "paper_2604_13929_amd/csrc/philox.hpp", "paper_2604_13929_amd/csrc/photonmc.hip",
+           "paper_2604_13929_amd/csrc/walk.hpp"]
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_walk_plain_256cube_phi070_traffic.json")
+
+
+def source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(photons: int):
+    """HBM bytes per walk launch from the committed counter summary, scaled to this
+    launch's photon count, or None when the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_sha256():
+        return None
+    return rec, rec["traffic_bytes_per_launch"] * photons / rec["photons"]
 
 
 def log(msg):
@@ -208,7 +236,8 @@ def main():
         pm.load()
         out = {}
         names = {0: "atomic64_device", 1: "atomic64_workgroup", 2: "store64", 3: "atomic32_device",
-                 4: "atomic64_device_wave_contiguous"}
+                 4: "atomic64_device_wave_contiguous", 5: "atomic64_device_16lane_128B",
+                 6: "atomic64_device_8lane_64B", 7: "atomic64_device_4lane_32B"}
         for mib in (2, 128, 512, 2048):
             t = torch.zeros(mib * 1024 * 1024 // 8, dtype=torch.int64, device="cuda:0")
             for mode in names:
@@ -307,6 +336,19 @@ def main():
         "results": {k: summary[k] for k in ("phi3d", "phi1d", "r", "ratio", "identity_rhs", "R", "T", "A",
                                              "steps_per_photon", "Pw_void_gtL", "mean_void_path")},
     }
+
+    tr = recorded_traffic(n)
+    if tr is not None:
+        rec, traffic = tr
+        line["roofline"]["traffic"] = traffic
+        # the binding limit: memory-side atomic requests (64-byte granules), measured by the scatter probe
+        req = rec["atomic_requests_per_launch"] * n / rec["photons"]
+        line["atomic_request_roof"] = {
+            "requests_per_launch": req, "requests_per_step": req / steps_per_run,
+            "achieved_requests_per_s": req / (walk_avg_ms * 1e-3),
+            "probe_requests_per_s": rec["probe_random_atomic64_128MiB_per_s"],
+            "frac": req / (walk_avg_ms * 1e-3) / rec["probe_random_atomic64_128MiB_per_s"],
+            "source": os.path.relpath(TRAFFIC_RECORD, ROOT)}
 
     if not args.no_batch:
         line["batched"] = batched_leg(args, seed)

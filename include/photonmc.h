@@ -255,8 +255,10 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
  * spread over 16 waves per compute unit.  mode 0: device-scope atomic add (what
  * the walk's fluence deposit does); 1: workgroup-scope atomic add; 2: plain
  * store; 3: device-scope 32-bit atomic add; 4: device-scope atomic add with the
- * 64 lanes of a wavefront on 64 consecutive entries.  The table's contents
- * afterwards are meaningless.
+ * 64 lanes of a wavefront on 64 consecutive entries; 5, 6, 7: device-scope atomic
+ * add with groups of 16, 8, 4 lanes on 16, 8, 4 consecutive entries of a random
+ * aligned block (128, 64, 32 bytes).  The table's contents afterwards are
+ * meaningless.
  */
 int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mode, void *hip_stream);
 

@@ -587,10 +587,16 @@ __global__ __launch_bounds__(256) void k_probe(unsigned long long *__restrict__ 
             // 32-bit atomic add at a random 32-bit slot
             unsigned int *t32 = (unsigned int *)table;
             __hip_atomic_fetch_add(t32 + ((a << 1) | (i & 1)), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        } else if (MODE == 4) {
             // the 64 lanes of a wavefront hit 64 consecutive slots of one random block
             const uint64_t blk = mix64(wave * per_thread + i) & (mask & ~63ull);
             __hip_atomic_fetch_add(table + blk + lane, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // groups of G lanes hit G consecutive slots (G * 8 bytes) of a random aligned block
+            constexpr uint64_t G = MODE == 5 ? 16 : (MODE == 6 ? 8 : 4);
+            const uint64_t grp = (t >> (MODE == 5 ? 4 : (MODE == 6 ? 3 : 2)));
+            const uint64_t blk = mix64(grp * per_thread + i) & (mask & ~(G - 1));
+            __hip_atomic_fetch_add(table + blk + (lane & (G - 1)), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -1037,7 +1043,7 @@ int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mod
     clear_error();
     if (!table || n_entries == 0 || (n_entries & (n_entries - 1)) != 0)
         return fail(MC_EINVAL, "table must be non-NULL with a power-of-two entry count");
-    if (mode < 0 || mode > 4) return fail(MC_EINVAL, "mode must be in [0, 4]");
+    if (mode < 0 || mode > 7) return fail(MC_EINVAL, "mode must be in [0, 7]");
     if (mode == 4 && n_entries < 64) return fail(MC_EINVAL, "mode 4 needs at least 64 entries");
     DeviceInfo di;
     int rc = device_info(&di);
@@ -1051,7 +1057,10 @@ int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mod
     else if (mode == 1) hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
     else if (mode == 2) hipLaunchKernelGGL(k_probe<2>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
     else if (mode == 3) hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
-    else hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
+    else if (mode == 4) hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
+    else if (mode == 5) hipLaunchKernelGGL(k_probe<5>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
+    else if (mode == 6) hipLaunchKernelGGL(k_probe<6>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
+    else hipLaunchKernelGGL(k_probe<7>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }
