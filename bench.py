@@ -218,7 +218,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--photons", type=int, default=100_000_000)
-    ap.add_argument("--cpu-photons", type=int, default=1_000_000, help="oracle sample size (first ids)")
+    ap.add_argument("--cpu-photons", type=int, default=3_000_000, help="oracle sample size (first ids)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-morph", action="store_true")

@@ -465,11 +465,14 @@ void cache_put(const std::string &key, const mc_tune &t)
 
 std::string shape_key(const char *kind, const Prepared &P, int flags)
 {
+    // a failed query only weakens the cache key (unknown arch / 0 CUs)
     int dev = 0;
-    hipGetDevice(&dev);
     hipDeviceProp_t prop;
     memset(&prop, 0, sizeof prop);
-    hipGetDeviceProperties(&prop, dev);
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        memset(&prop, 0, sizeof prop);
+        snprintf(prop.gcnArchName, sizeof prop.gcnArchName, "unknown");
+    }
     uint64_t vox = 0;
     for (const Job &J : P.table) vox += (uint64_t)J.nx * J.ny * J.nz;
     char buf[400];
@@ -492,8 +495,8 @@ int time_trial(const std::function<int(const mc_tune &)> &enqueue, const mc_tune
     if (!rc && hipEventRecord(b, s) != hipSuccess) rc = fail(MC_EHIP, "event record failed");
     if (!rc && hipEventSynchronize(b) != hipSuccess) rc = fail(MC_EHIP, "event sync failed");
     if (!rc && hipEventElapsedTime(ms, a, b) != hipSuccess) rc = fail(MC_EHIP, "elapsed time failed");
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    if (hipEventDestroy(a) != hipSuccess && !rc) rc = fail(MC_EHIP, "event destroy failed");
+    if (hipEventDestroy(b) != hipSuccess && !rc) rc = fail(MC_EHIP, "event destroy failed");
     return rc;
 }
 
@@ -653,10 +656,11 @@ int mc_batch_graph_create(const mc_job *jobs, int32_t n_jobs, int flags, const m
         else if (hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0) != hipSuccess)
             rc = fail(MC_EHIP, "hipGraphInstantiate failed");
     }
-    hipStreamDestroy(cs);
+    if (hipStreamDestroy(cs) != hipSuccess && !rc) rc = fail(MC_EHIP, "hipStreamDestroy failed");
     if (rc) {
-        if (h->exec) hipGraphExecDestroy(h->exec);
-        if (h->graph) hipGraphDestroy(h->graph);
+        // already failing: the first error is the one reported
+        if (h->exec) (void)hipGraphExecDestroy(h->exec);
+        if (h->graph) (void)hipGraphDestroy(h->graph);
         delete h;
         return rc;
     }
@@ -677,10 +681,11 @@ int mc_graph_destroy(mc_graph g)
     clear_error();
     if (!g) return MC_OK;
     GraphHandle *h = (GraphHandle *)g;
-    if (h->exec) hipGraphExecDestroy(h->exec);
-    if (h->graph) hipGraphDestroy(h->graph);
+    int rc = MC_OK;
+    if (h->exec && hipGraphExecDestroy(h->exec) != hipSuccess) rc = fail(MC_EHIP, "hipGraphExecDestroy failed");
+    if (h->graph && hipGraphDestroy(h->graph) != hipSuccess && !rc) rc = fail(MC_EHIP, "hipGraphDestroy failed");
     delete h;
-    return MC_OK;
+    return rc;
 }
 
 }  // extern "C"

@@ -119,7 +119,7 @@ struct DirectDeposit {
 // lanes transposed so that one atomic instruction carries kLogK successive
 // deposits of each of 64/kLogK lanes: deposits of one photon that fall in the
 // same brick (the same 64-byte line) then travel as one memory-side request.
-constexpr int kLogK = 8;
+constexpr int kLogK = 16;
 constexpr int kLogStride = 65;  // 64 lanes + 1: the transposed reads hit distinct banks
 
 struct LoggedDeposit {
