@@ -154,7 +154,13 @@ def morphology_leg(args, seed):
                      "photons_per_s": n / t, "depth": s.depth, "summary": s}
         log(f"{name}: {t * 1e3:.0f} ms, {s['steps_per_photon']:.0f} steps/photon")
     sm, sh = out["M3"]["summary"], out["H3"]["summary"]
-    return {"workload": "512x512x256 Cahn-wave mask phi=0.90 (lambda 32) vs homogeneous slab mu_s 0.05 mu_a 0.001 g 0.7, "
+    checks = {}
+    if not args.no_cpu:
+        ncpu = len(os.sched_getaffinity(0))
+        checks = {"M3": oracle_check(d3.cpu().numpy(), d3, base, 100_000, seed, ncpu),
+                  "H3": oracle_check(dh.cpu().numpy(), dh, opt_h, 100_000, seed, ncpu)}
+    return {"oracle": checks,
+            "workload": "512x512x256 Cahn-wave mask phi=0.90 (lambda 32) vs homogeneous slab mu_s 0.05 mu_a 0.001 g 0.7, "
                         f"{n:.0e} photons each",
             "rms_w_M3_vs_H3": pm.rms_w(out["M3"]["depth"], out["H3"]["depth"]),
             "Pw_void_gt_L": sm["Pw_void_gtL"], "Pn_void_gt_L": sm["Pn_void_gtL"],
@@ -163,6 +169,98 @@ def morphology_leg(args, seed):
             "r_M3": sm["r"], "R_T_A_M3": [sm["R"], sm["T"], sm["A"]], "R_T_A_H3": [sh["R"], sh["T"], sh["A"]],
             "photon_steps_per_s": {k: out[k]["photon_steps_per_s"] for k in out},
             "ms": {k: out[k]["ms"] for k in out}}
+
+
+def oracle_check(mask_np, dmask, opt, m, seed, ncpu):
+    """The oracle on the first ``m`` photon ids of a workload and the GPU on the same
+    ids: relative errors of the estimators, and the oracle's time."""
+    import math
+
+    import oracle
+    from oracle import estimators as est
+    from paper_2604_13929_amd import photonmc as pm
+
+    t0 = time.perf_counter()
+    ref = oracle.run(mask_np, opt.mu_s, opt.mu_a, opt.g, m, seed, nthreads=ncpu)
+    t_cpu = time.perf_counter() - t0
+    tot = oracle.totals(ref)
+    sub = pm.run(dmask, opt, m, seed)
+    ssum = pm.reduce(dmask, sub)
+    e = est.estimators(ref["fluence"][0], mask_np, m)
+    err = {k: abs(ssum[k] - e[k]) / abs(e[k]) for k in ("phi3d", "phi1d", "r")
+           if math.isfinite(e[k]) and e[k] != 0}
+    gsc = sub.scalar_dict()
+    for k in ("R", "T", "A"):
+        err[k] = abs(gsc[k] - tot[k]) / (m * pm.W1)
+    err["steps"] = abs(gsc["steps"] - tot["steps"]) / tot["steps"]
+    return {"photons": m, "relative_error": err, "oracle_s": t_cpu,
+            "oracle_photon_steps_per_s": tot["steps"] / t_cpu}
+
+
+def rows_leg(args, seed, field):
+    """The other workloads of the survey's measurement list, each timed on the GPU and
+    (unless --no-cpu) checked against the oracle on its first photon ids: 32^3
+    phi = 0.70 (all 1e5 photons) and 256^3 phi = 0.90 thresholded from the plain
+    workload's field (1e8 photons)."""
+    import torch
+
+    from paper_2604_13929_amd import inputs
+    from paper_2604_13929_amd import photonmc as pm
+
+    ncpu = len(os.sched_getaffinity(0))
+    opt = pm.Optics(**inputs.SOLID_OPTICS)
+    w1 = inputs.WORKLOADS["M1"]
+    m1 = inputs.spinodal_mask(w1["nx"], w1["ny"], w1["nz"], w1["wavelength"], w1["porosity"],
+                              seed=inputs.PAPER_MASK_SEED)
+    m2b = inputs.rank_threshold(field, inputs.WORKLOADS["M2b"]["porosity"])
+    rows = {}
+    for name, mask_np, n, m_cpu in (("M1_32cube_phi070", m1, w1["n_photons"], w1["n_photons"]),
+                                    ("M2b_256cube_phi090", m2b, args.photons, 200_000)):
+        d = torch.from_numpy(mask_np).cuda()
+        pm.run(d, opt, min(n, 1 << 20), seed)          # warm the code path and the allocator
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pm.run(d, opt, n, seed, timed=True)
+        s = pm.reduce(d, r)
+        t = time.perf_counter() - t0
+        steps = s["steps_per_photon"] * n
+        row = {"photons": n, "ms": t * 1e3, "walk_ms": r.walk_ms, "photon_steps_per_s": steps / t,
+               "photons_per_s": n / t, "phi3d": s["phi3d"], "phi1d": s["phi1d"], "r": s["r"],
+               "R_T_A": [s["R"], s["T"], s["A"]], "steps_per_photon": s["steps_per_photon"]}
+        if not args.no_cpu:
+            row["oracle"] = oracle_check(mask_np, d, opt, m_cpu, seed, ncpu)
+        log(f"{name}: {t * 1e3:.1f} ms, {steps / t:.3e} steps/s")
+        rows[name] = row
+    return rows
+
+
+def grad_oracle_check(seed, n=100_000, B=32):
+    """GPU likelihood-ratio Jacobian (FP32 transport) on the 32^3 workload against the
+    oracle's FP64 likelihood-ratio bins on the same photons: z-scores with the
+    oracle's spread over B photon batches."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2604_13929_amd import inputs
+    from paper_2604_13929_amd import photonmc as pm
+
+    w1 = inputs.WORKLOADS["M1"]
+    m1 = inputs.spinodal_mask(w1["nx"], w1["ny"], w1["nz"], w1["wavelength"], w1["porosity"],
+                              seed=inputs.PAPER_MASK_SEED)
+    opt = pm.Optics(**inputs.SOLID_OPTICS)
+    g = pm.grad(torch.from_numpy(m1).cuda(), opt, n, seed)
+    jac = g.jac.cpu().numpy()[:, :2]
+    ref = oracle.run(m1, opt.mu_s, opt.mu_a, opt.g, n, seed, nbatch=B, grad=True, fluence=False,
+                     nthreads=len(os.sched_getaffinity(0)))
+    nz, ny, nx = m1.shape
+    per_b = ref["grad"] * (nx * ny) / (n / B * pm.W1)            # [B, 3, 2, nz]
+    d3 = per_b[:, :, 0, :].sum(-1) / (m1 == 0).sum()
+    d1 = per_b.sum(axis=(2, 3)) / m1.size
+    want = np.stack([d3.mean(0), d1.mean(0)], 1)                 # [3, 2]
+    sig = np.stack([d3.std(0, ddof=1), d1.std(0, ddof=1)], 1) / np.sqrt(B)
+    return {"photons": n, "gpu": jac.tolist(), "oracle": want.tolist(),
+            "z": ((jac - want) / sig).tolist(), "rows": ["mu_s", "mu_a", "g"], "columns": ["d_phi3d", "d_phi1d"]}
 
 
 def grad_leg(args, seed, mask):
@@ -206,7 +304,11 @@ def grad_leg(args, seed, mask):
         res[name] = {"lr": jac[pi, :2].tolist(), "lr_subrange_mean": lm.tolist(), "lr_sigma": ls.tolist(),
                      "fd": fm.tolist(), "fd_sigma": fs.tolist(), "z": ((fm - lm) / np.hypot(fs, ls)).tolist()}
         log(f"grad check {name}: LR {lm} FD {fm} z {res[name]['z']}")
-    return {"workload": "plain workload, d<Phi>_3D and d<Phi>_1D (and dPhi(z)) wrt solid mu_s, mu_a, g",
+    check = None
+    if not args.no_cpu:
+        check = grad_oracle_check(seed)
+    return {"oracle_lr_32cube": check,
+            "workload": "plain workload, d<Phi>_3D and d<Phi>_1D (and dPhi(z)) wrt solid mu_s, mu_a, g",
             "ms": t_lr * 1e3, "walk_ms": g.walk_ms, "photon_steps_per_s": steps / t_lr, "photons_per_s": n / t_lr,
             "check_vs_crn_fd": res, "fd_relative_step": h, "subranges": B,
             "columns": ["d_phi3d", "d_phi1d"]}
@@ -223,6 +325,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-morph", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-rows", action="store_true", help="skip the 32^3 and phi = 0.90 rows")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
@@ -271,8 +374,8 @@ def main():
     dev = torch.device("cuda:0")
     wl = inputs.WORKLOADS["M2a"]
     t0 = time.time()
-    mask_np = inputs.spinodal_mask(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], wl["porosity"],
-                                   seed=inputs.PAPER_MASK_SEED)
+    field = inputs.cahn_field(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], inputs.PAPER_MASK_SEED)
+    mask_np = inputs.rank_threshold(field, wl["porosity"])
     log(f"mask {mask_np.shape} porosity {mask_np.mean():.6f} built in {time.time() - t0:.1f}s")
     mask = torch.from_numpy(mask_np).to(dev)
     opt = pm.Optics(**inputs.SOLID_OPTICS)
@@ -330,6 +433,7 @@ def main():
                    "photons_per_step": n, "photon_steps_per_step": steps_per_run, "tallies": "int64 fixed point"},
         "photons_per_s": photons_per_s,
         "walk_ms_avg": walk_avg_ms,
+        "walk_ms_median": float(np.median(walk_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_walk", "algorithmic_bytes_per_step": BYTES_PER_STEP},
@@ -350,6 +454,9 @@ def main():
             "frac": req / (walk_avg_ms * 1e-3) / rec["probe_random_atomic64_128MiB_per_s"],
             "source": os.path.relpath(TRAFFIC_RECORD, ROOT)}
 
+    if not args.no_rows:
+        line["rows"] = rows_leg(args, seed, field)
+    del field
     if not args.no_batch:
         line["batched"] = batched_leg(args, seed)
     if not args.no_morph:
@@ -383,6 +490,13 @@ def main():
                                 "seconds": t_cpu}
         line["oracle_error"] = err
         line["gpu_over_cpu"] = steps_per_s / (tot["steps"] / t_cpu)
+        # the same oracle on one host thread, over a smaller sample of the same ids
+        m1 = max(1, m // 60)
+        t1 = time.perf_counter()
+        ref1 = oracle.run(mask_np, opt.mu_s, opt.mu_a, opt.g, m1, seed, nthreads=1, fluence=False)
+        t_one = time.perf_counter() - t1
+        line["cpu_baseline"]["one_core"] = {"value": oracle.totals(ref1)["steps"] / t_one, "photons": m1,
+                                            "seconds": t_one}
     print(json.dumps(line), flush=True)
 
 
