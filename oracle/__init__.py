@@ -18,12 +18,17 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # integer channels (units of 2^-31 launch weight unless a count)
-ICH = ["R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_n", "esc_n_gtL", "steps", "interactions"]
+ICH = ["R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_n", "esc_n_gtL", "steps", "interactions",
+       "gated"]
 # floating channels
 DCH = ["esc_w_void_path", "path_total", "path_solid", "path_void"]
 
 EVENTS = {0: "face_x", 1: "face_y", 2: "face_z", 3: "scatter", 4: "esc_R", 5: "esc_T",
-          6: "dead_absorb", 7: "dead_roulette", 8: "lost"}
+          6: "dead_absorb", 7: "dead_roulette", 8: "lost", 9: "gated",
+          10: "reflect_x", 11: "reflect_y", 12: "reflect_z"}
+#: boundary models: the plain one (periodic laterals, index 1, no pads, no gate) and the
+#: paper's (air pads, Fresnel at index steps, mirror or periodic laterals, time gate)
+BOUNDARY_PLAIN, BOUNDARY_PAPER = 0, 1
 W1 = 2 ** 31
 
 
@@ -34,7 +39,9 @@ class Problem(ctypes.Structure):
                 ("w_roulette", ctypes.c_double), ("roulette_m", ctypes.c_uint32),
                 ("path_cap", ctypes.c_double), ("source", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32),
-                ("max_steps", ctypes.c_uint32)]
+                ("max_steps", ctypes.c_uint32),
+                ("boundary", ctypes.c_int32), ("lateral", ctypes.c_int32),
+                ("n_solid", ctypes.c_double), ("gate", ctypes.c_double)]
 
 
 REC_DTYPE = np.dtype([("ix", "<i4"), ("iy", "<i4"), ("iz", "<i4"), ("event", "<i4"),
@@ -51,7 +58,7 @@ STATE_DTYPE = np.dtype([("ix", "<i8"), ("iy", "<i8"), ("iz", "<i8"),
                         ("fx", "<f8"), ("fy", "<f8"), ("fz", "<f8"), ("ux", "<f8"), ("uy", "<f8"), ("uz", "<f8"),
                         ("tau", "<f8"), ("w", "<i8"), ("k", "<u4"), ("pad", "<u4"), ("steps", "<u8"),
                         ("l_void", "<f8"), ("l_solid", "<f8"), ("score_s", "<f8"), ("score_a", "<f8"),
-                        ("score_g", "<f8")])
+                        ("score_g", "<f8"), ("l_opt", "<f8"), ("nf", "<u4"), ("pad2", "<u4")])
 
 
 def build(force: bool = False) -> str:
@@ -79,6 +86,9 @@ def lib():
                                 ctypes.c_void_p, ctypes.c_void_p]
         L.orc_step.restype = ctypes.c_int
         L.orc_step.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_fresnel.restype = ctypes.c_double
+        L.orc_fresnel.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.POINTER(ctypes.c_double)]
         L.orc_philox.restype = None
         L.orc_philox.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         assert L.orc_sizeof_rec() == REC_DTYPE.itemsize
@@ -98,6 +108,14 @@ def philox(counter, key) -> np.ndarray:
     return out
 
 
+def fresnel(n1: float, n2: float, cos_i: float):
+    """Unpolarised Fresnel reflectance from index n1 into n2 at incidence cosine cos_i,
+    and the transmission cosine (0 under total internal reflection)."""
+    ct = ctypes.c_double(0.0)
+    r = lib().orc_fresnel(float(n1), float(n2), float(cos_i), ctypes.byref(ct))
+    return r, ct.value
+
+
 def _f32(x: float) -> float:
     """The transport sees its coefficients as float32; the oracle uses the same values."""
     return float(np.float32(x))
@@ -105,13 +123,15 @@ def _f32(x: float) -> float:
 
 def make_problem(mask: np.ndarray, mu_s: float, mu_a: float, g: float, seed: int, stream_id: int = 0,
                  w_roulette: float = 1e-4, roulette_m: int = 10, path_cap: float = 0.0, source: int = 0,
-                 max_steps: int = 1 << 24):
+                 max_steps: int = 1 << 24, boundary: int = BOUNDARY_PLAIN, lateral: int = 0,
+                 n_solid: float = 1.0, gate: float = float("inf")):
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     assert m.ndim == 3
     nz, ny, nx = m.shape
     P = Problem(nx=nx, ny=ny, nz=nz, mask=m.ctypes.data, mu_s=_f32(mu_s), mu_a=_f32(mu_a), g=_f32(g),
                 w_roulette=_f32(w_roulette), roulette_m=roulette_m, path_cap=float(path_cap),
-                source=source, seed=seed, stream_id=stream_id, max_steps=max_steps)
+                source=source, seed=seed, stream_id=stream_id, max_steps=max_steps,
+                boundary=boundary, lateral=lateral, n_solid=_f32(n_solid), gate=float(gate))
     return P, m
 
 

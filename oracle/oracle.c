@@ -41,6 +41,27 @@
  *   - ties: the face axis is the first minimum in x, y, z order; an interaction
  *     wins a tie against a face; in-voxel offsets are clamped to [0, 1].
  *
+ * The paper's own boundary model (boundary = 1; Sec. 2.5 "Source and boundary
+ * conditions" and "Photon budget, time gate and statistics", App. B):
+ *   - a one-voxel air pad (index 1, no attenuation, no tally) on each axial
+ *     face: layers iz = -1 and iz = nz.  Photons start on the outer face of the
+ *     top pad and escape when they leave through the outer face of either pad;
+ *   - lateral faces are specular mirrors (lateral = 1) or periodic (lateral = 0);
+ *   - the solid has refractive index n_solid, pores and air have 1.  At every
+ *     face between two media of different index the photon is reflected or
+ *     refracted: total internal reflection when Snell's law has no solution,
+ *     otherwise reflection with the Fresnel reflectance for unpolarised light
+ *     (mean of the s and p power coefficients).  Reading: the choice is made
+ *     against one uniform of its own Philox stream, tag 4, counter
+ *     (j >> 2, photon, stream, 4), word j & 3 for the photon's j-th Fresnel
+ *     decision.  Refraction scales the tangential direction components by
+ *     n1/n2 and sets the normal one to cos(theta_t) with its sign kept;
+ *   - time gate (Eq. tend): the photon's optical path sum(n d), pads included,
+ *     may not exceed `gate` (c t_end in voxels).  The segment that reaches it is
+ *     cut there, its part deposited, and the photon's weight goes to its own
+ *     channel (gated), so the integer closure stays exact.
+ * Path statistics (in-pore path, solid path) count slab voxels only.
+ *
  * Gradients (likelihood-ratio / perturbation Monte Carlo) are not in the
  * paper; the oracle computes them from the path density
  *   mu_s^k * exp(-mu_t * l_solid) * prod_i p_HG(cos_i; g)
@@ -103,13 +124,17 @@ typedef struct {
     uint64_t seed;
     uint32_t stream_id;
     uint32_t max_steps;      /* step cap (photon counted as lost beyond it) */
+    int32_t boundary;        /* 0: periodic laterals, index 1, no pads, no gate; 1: the paper's model */
+    int32_t lateral;         /* boundary 1: 0 periodic, 1 specular mirrors */
+    double n_solid;          /* boundary 1: refractive index of the solid (>= 1) */
+    double gate;             /* boundary 1: optical path limit c t_end in voxels (INFINITY: none) */
 } orc_problem;
 
 /* integer channels */
 enum {
     ORC_R, ORC_T, ORC_A, ORC_RR, ORC_LOST,
     ORC_ESC_W, ORC_ESC_W_GTL, ORC_ESC_N, ORC_ESC_N_GTL,
-    ORC_STEPS, ORC_INTERACTIONS, ORC_NI
+    ORC_STEPS, ORC_INTERACTIONS, ORC_GATED, ORC_NI
 };
 /* floating channels */
 enum { ORC_ESC_W_VOID_PATH, ORC_PATH_TOTAL, ORC_PATH_SOLID, ORC_PATH_VOID, ORC_ND };
@@ -129,7 +154,10 @@ typedef struct {
 
 /* events */
 enum { EV_FACE_X = 0, EV_FACE_Y = 1, EV_FACE_Z = 2, EV_SCATTER = 3, EV_ESC_R = 4,
-       EV_ESC_T = 5, EV_DEAD_ABSORB = 6, EV_DEAD_ROULETTE = 7, EV_LOST = 8 };
+       EV_ESC_T = 5, EV_DEAD_ABSORB = 6, EV_DEAD_ROULETTE = 7, EV_LOST = 8, EV_GATED = 9,
+       EV_REFLECT_X = 10, EV_REFLECT_Y = 11, EV_REFLECT_Z = 12 };
+
+static int terminal(int ev) { return ev >= EV_ESC_R && ev <= EV_GATED; }
 
 /* per-photon summary */
 typedef struct {
@@ -185,6 +213,9 @@ typedef struct {
     uint64_t steps;
     double l_void, l_solid;
     double score_s, score_a, score_g;   /* LR scores (see the header comment) */
+    double l_opt;            /* optical path sum(n d) so far, pads included (time gate) */
+    uint32_t nf;             /* Fresnel decisions drawn so far */
+    uint32_t pad2;
 } orc_state;
 
 /* Launch: uniform position over the z = 0 face (integer voxel + offset from 24-bit
@@ -199,7 +230,7 @@ static void launch(const orc_problem *P, uint64_t photon, orc_state *st)
     uint64_t Y = (uint64_t)(r[1] >> 8) * (uint64_t)P->ny;
     st->ix = (int64_t)(X >> 24);
     st->iy = (int64_t)(Y >> 24);
-    st->iz = 0;
+    st->iz = P->boundary ? -1 : 0;   /* paper model: outer face of the top air pad */
     st->fx = (double)(X & 0xFFFFFFu) / 16777216.0;
     st->fy = (double)(Y & 0xFFFFFFu) / 16777216.0;
     st->fz = 0.0;
@@ -219,14 +250,64 @@ static void launch(const orc_problem *P, uint64_t photon, orc_state *st)
 }
 
 /*
+ * Fresnel reflectance for unpolarised light going from index n1 into n2 at
+ * incidence cosine cos_i (> 0): the mean of the s and p power reflection
+ * coefficients.  Returns 1 (and *cos_t = 0) for total internal reflection.
+ */
+double orc_fresnel(double n1, double n2, double cos_i, double *cos_t)
+{
+    const double eta = n1 / n2;
+    const double sin_t2 = eta * eta * (1.0 - cos_i * cos_i);
+    if (sin_t2 >= 1.0) {
+        if (cos_t) *cos_t = 0.0;
+        return 1.0;
+    }
+    const double ct = sqrt(1.0 - sin_t2);
+    const double rs = (n1 * cos_i - n2 * ct) / (n1 * cos_i + n2 * ct);
+    const double rp = (n1 * ct - n2 * cos_i) / (n1 * ct + n2 * cos_i);
+    if (cos_t) *cos_t = ct;
+    return 0.5 * (rs * rs + rp * rp);
+}
+
+/* uniform for the photon's j-th Fresnel decision (tag-4 stream, four words per block) */
+static double fresnel_uniform(const orc_problem *P, uint64_t photon, uint32_t j)
+{
+    uint32_t r[4];
+    draw(P, photon, j >> 2, 4, r);
+    return u_closed_open(r[j & 3u]);
+}
+
+static int is_solid(const orc_problem *P, int64_t ix, int64_t iy, int64_t iz)
+{
+    if (iz < 0 || iz >= P->nz) return 0;   /* air pad */
+    return P->mask[(iz * P->ny + iy) * P->nx + ix] == 0;
+}
+
+static void escape(const orc_problem *P, orc_state *st, orc_sink *S, orc_photon *me, int top)
+{
+    const int64_t w = st->w;
+    if (top) { S->sums->ich[ORC_R] += w; me->R += w; }
+    else     { S->sums->ich[ORC_T] += w; me->T += w; }
+    S->sums->ich[ORC_ESC_W] += w;
+    S->sums->ich[ORC_ESC_N] += 1;
+    if (st->l_void > (double)P->nz) {
+        S->sums->ich[ORC_ESC_W_GTL] += w;
+        S->sums->ich[ORC_ESC_N_GTL] += 1;
+    }
+    S->sums->dch[ORC_ESC_W_VOID_PATH] += (double)w * st->l_void;
+}
+
+/*
  * One step from state st: the segment inside the current voxel up to a face, an
- * interaction or an escape.  Updates st, the sink and the photon's own shares me;
- * returns the event, and sets *gap to how close the step came to a different
- * decision (|s_int - d_face| and the gaps between face distances).
+ * interaction, the time gate or an escape.  Updates st, the sink and the photon's
+ * own shares me; returns the event, and sets *gap to how close the step came to a
+ * different decision (|s_int - d_face|, the gaps between face distances, and in the
+ * paper model the gate margin and the Fresnel uniform's distance to the reflectance).
  */
 static int step(const orc_problem *P, uint64_t photon, orc_state *st, orc_sink *S, orc_photon *me, double *gap_out)
 {
     const int64_t nx = P->nx, ny = P->ny, nz = P->nz;
+    const int paper = (P->boundary == 1);
     const double mu_t_solid = P->mu_s + P->mu_a;
     /* survival factor of one interaction, as an integer fraction of 2^32 */
     uint64_t S_q = 0;
@@ -234,14 +315,16 @@ static int step(const orc_problem *P, uint64_t photon, orc_state *st, orc_sink *
     const int64_t w_th = (int64_t)floor(P->w_roulette * ORC_W1);
     const uint32_t T_m = (uint32_t)llround(16777216.0 / (double)P->roulette_m);
 
-    const int64_t v = (st->iz * ny + st->iy) * nx + st->ix;
-    const int solid = (P->mask[v] == 0);
+    const int in_slab = (st->iz >= 0 && st->iz < nz);
+    const int64_t v = in_slab ? (st->iz * ny + st->iy) * nx + st->ix : -1;
+    const int solid = in_slab && P->mask[v] == 0;
     const double mu_t = solid ? mu_t_solid : 0.0;
+    const double n_here = (paper && solid) ? P->n_solid : 1.0;
 
     /* distance to each face along the direction of travel */
     double dist[3];
-    const double f[3] = {st->fx, st->fy, st->fz};
-    const double u[3] = {st->ux, st->uy, st->uz};
+    double f[3] = {st->fx, st->fy, st->fz};
+    double u[3] = {st->ux, st->uy, st->uz};
     for (int a = 0; a < 3; ++a) {
         if (u[a] > 0.0) dist[a] = (1.0 - f[a]) / u[a];
         else if (u[a] < 0.0) dist[a] = f[a] / (-u[a]);
@@ -252,8 +335,8 @@ static int step(const orc_problem *P, uint64_t photon, orc_state *st, orc_sink *
     if (dist[2] < dist[axis]) axis = 2;
     const double d_face = dist[axis];
     const double s_int = (mu_t > 0.0) ? st->tau / mu_t : INFINITY;
-    const int interact = (s_int <= d_face);
-    const double d = interact ? s_int : d_face;
+    int interact = (s_int <= d_face);
+    double d = interact ? s_int : d_face;
 
     double gap = fabs(s_int - d_face);
     for (int a = 0; a < 3; ++a)
@@ -261,44 +344,64 @@ static int step(const orc_problem *P, uint64_t photon, orc_state *st, orc_sink *
             double ga = fabs(dist[a] - d_face);
             if (ga < gap) gap = ga;
         }
-    if (gap_out) *gap_out = gap;
+    /* time gate: the optical path may reach, not pass, the gate */
+    int gated = 0;
+    if (paper && isfinite(P->gate)) {
+        const double t_left = (P->gate - st->l_opt) / n_here;
+        const double gg = fabs(d - t_left);
+        if (gg < gap) gap = gg;
+        if (d > t_left) {
+            gated = 1;
+            interact = 0;
+            d = t_left > 0.0 ? t_left : 0.0;
+        }
+    }
+    orc_rec *rec = NULL;
     if (S->trace && (int64_t)st->steps < S->max_rec) {
-        orc_rec *rec = &S->trace[st->steps];
+        rec = &S->trace[st->steps];
         rec->ix = (int32_t)st->ix; rec->iy = (int32_t)st->iy; rec->iz = (int32_t)st->iz;
         rec->fx = st->fx; rec->fy = st->fy; rec->fz = st->fz;
         rec->ux = st->ux; rec->uy = st->uy; rec->uz = st->uz;
         rec->w = st->w; rec->k = st->k; rec->d = d;
-        rec->tie_gap = gap;
         rec->event = -1;
     }
 
-    /* track-length deposit */
+    /* track-length deposit (slab voxels only) */
     const int64_t w = st->w;
-    if (S->fluence) S->fluence[v] += (double)w * d;
-    if (S->depth) S->depth[(solid ? 0 : 1) * nz + st->iz] += (double)w * d;
-    if (S->grad) {
-        const int ph = solid ? 0 : 1;
-        const double sq = solid ? 0.5 * d * d : 0.0;
-        S->grad[(0 * 2 + ph) * nz + st->iz] += (double)w * (st->score_s * d - sq);
-        S->grad[(1 * 2 + ph) * nz + st->iz] += (double)w * (st->score_a * d - sq);
-        S->grad[(2 * 2 + ph) * nz + st->iz] += (double)w * (st->score_g * d);
+    if (in_slab) {
+        if (S->fluence) S->fluence[v] += (double)w * d;
+        if (S->depth) S->depth[(solid ? 0 : 1) * nz + st->iz] += (double)w * d;
+        if (S->grad) {
+            const int ph = solid ? 0 : 1;
+            const double sq = solid ? 0.5 * d * d : 0.0;
+            S->grad[(0 * 2 + ph) * nz + st->iz] += (double)w * (st->score_s * d - sq);
+            S->grad[(1 * 2 + ph) * nz + st->iz] += (double)w * (st->score_a * d - sq);
+            S->grad[(2 * 2 + ph) * nz + st->iz] += (double)w * (st->score_g * d);
+        }
+        if (solid) {
+            st->l_solid += d;
+            st->score_s -= d;
+            st->score_a -= d;
+        } else {
+            st->l_void += d;
+        }
     }
-    if (solid) {
-        st->l_solid += d;
-        st->score_s -= d;
-        st->score_a -= d;
-    } else {
-        st->l_void += d;
-    }
+    st->l_opt += n_here * d;
 
     int event;
     int done = 0;
-    if (interact) {
+    if (interact || gated) {
         st->fx = clamp01(st->fx + st->ux * d);
         st->fy = clamp01(st->fy + st->uy * d);
         st->fz = clamp01(st->fz + st->uz * d);
-        st->tau = 0.0;
-        event = EV_SCATTER;
+        if (interact) {
+            st->tau = 0.0;
+            event = EV_SCATTER;
+        } else {
+            st->tau -= mu_t * d;
+            if (st->tau < 0.0) st->tau = 0.0;
+            event = EV_GATED;
+        }
     } else {
         if (axis != 0) st->fx = clamp01(st->fx + st->ux * d);
         if (axis != 1) st->fy = clamp01(st->fy + st->uy * d);
@@ -309,8 +412,11 @@ static int step(const orc_problem *P, uint64_t photon, orc_state *st, orc_sink *
     }
     st->steps += 1;
 
-    if (!interact) {
-        /* cross the face */
+    if (gated) {
+        S->sums->ich[ORC_GATED] += st->w;
+        done = 1;
+    } else if (!interact && !paper) {
+        /* cross the face: periodic laterals, open axial faces */
         if (axis == 0) {
             if (st->ux > 0.0) { st->ix += 1; st->fx = 0.0; if (st->ix == nx) st->ix = 0; }
             else              { st->ix -= 1; st->fx = 1.0; if (st->ix < 0) st->ix = nx - 1; }
@@ -323,18 +429,66 @@ static int step(const orc_problem *P, uint64_t photon, orc_state *st, orc_sink *
             if (st->iz < 0 || st->iz >= nz) {
                 /* escape through an open axial face */
                 const int top = (st->iz < 0);
-                if (top) { S->sums->ich[ORC_R] += w; me->R += w; event = EV_ESC_R; }
-                else     { S->sums->ich[ORC_T] += w; me->T += w; event = EV_ESC_T; }
-                S->sums->ich[ORC_ESC_W] += w;
-                S->sums->ich[ORC_ESC_N] += 1;
-                if (st->l_void > (double)nz) {
-                    S->sums->ich[ORC_ESC_W_GTL] += w;
-                    S->sums->ich[ORC_ESC_N_GTL] += 1;
-                }
-                S->sums->dch[ORC_ESC_W_VOID_PATH] += (double)w * st->l_void;
+                escape(P, st, S, me, top);
+                event = top ? EV_ESC_R : EV_ESC_T;
                 done = 1;
             }
         }
+    } else if (!interact) {
+        /* paper model: mirror, Fresnel reflection / refraction, or crossing */
+        int64_t j[3] = {st->ix, st->iy, st->iz};
+        const double sgn = (axis == 0 ? st->ux : axis == 1 ? st->uy : st->uz) > 0.0 ? 1.0 : -1.0;
+        j[axis] += (int64_t)sgn;
+        int reflect = 0, out = 0;
+        if (axis < 2) {
+            const int64_t n_ax = axis == 0 ? nx : ny;
+            if (j[axis] < 0 || j[axis] >= n_ax) {
+                if (P->lateral == 1) reflect = 1;                   /* specular mirror */
+                else j[axis] = (j[axis] < 0) ? n_ax - 1 : 0;        /* periodic */
+            }
+        } else if (j[2] < -1 || j[2] > nz) {
+            out = 1;                                                /* through a pad's outer face */
+        }
+        double uu[3] = {st->ux, st->uy, st->uz};
+        if (!reflect && !out) {
+            const double n_next = is_solid(P, j[0], j[1], j[2]) ? P->n_solid : 1.0;
+            if (n_next != n_here) {
+                const double cos_i = fabs(uu[axis]);
+                double cos_t;
+                const double R = orc_fresnel(n_here, n_next, cos_i, &cos_t);
+                if (R >= 1.0) {
+                    reflect = 1;                                    /* total internal reflection */
+                } else {
+                    const double U = fresnel_uniform(P, photon, st->nf);
+                    st->nf += 1;
+                    const double gf = fabs(U - R);
+                    if (gf < gap) gap = gf;
+                    if (U < R) {
+                        reflect = 1;
+                    } else {
+                        const double eta = n_here / n_next;
+                        for (int a = 0; a < 3; ++a) uu[a] = (a == axis) ? sgn * cos_t : eta * uu[a];
+                    }
+                }
+            }
+        }
+        if (reflect) {
+            uu[axis] = -uu[axis];
+            f[0] = st->fx; f[1] = st->fy; f[2] = st->fz;
+            f[axis] = sgn > 0.0 ? 1.0 : 0.0;
+            st->fx = f[0]; st->fy = f[1]; st->fz = f[2];
+            event = EV_REFLECT_X + axis;
+        } else if (out) {
+            escape(P, st, S, me, j[2] < 0);
+            event = j[2] < 0 ? EV_ESC_R : EV_ESC_T;
+            done = 1;
+        } else {
+            st->ix = j[0]; st->iy = j[1]; st->iz = j[2];
+            f[0] = st->fx; f[1] = st->fy; f[2] = st->fz;
+            f[axis] = sgn > 0.0 ? 0.0 : 1.0;
+            st->fx = f[0]; st->fy = f[1]; st->fz = f[2];
+        }
+        st->ux = uu[0]; st->uy = uu[1]; st->uz = uu[2];
     } else {
         /* interaction: absorb, scatter, roulette, new free path */
         st->k += 1;
@@ -408,7 +562,11 @@ static int step(const orc_problem *P, uint64_t photon, orc_state *st, orc_sink *
             event = EV_LOST;
         }
     }
-    if (S->trace && (int64_t)st->steps - 1 < S->max_rec) S->trace[st->steps - 1].event = event;
+    if (gap_out) *gap_out = gap;
+    if (rec) {
+        rec->event = event;
+        rec->tie_gap = gap;
+    }
     return event;
 }
 
@@ -425,7 +583,7 @@ static void walk(const orc_problem *P, uint64_t photon, orc_sink *S)
         double gap;
         event = step(P, photon, &st, S, &me, &gap);
         if (gap < me.min_gap) me.min_gap = gap;
-        if (event >= EV_ESC_R) break;
+        if (terminal(event)) break;
     }
     S->sums->ich[ORC_STEPS] += (int64_t)st.steps;
     S->sums->ich[ORC_INTERACTIONS] += (int64_t)st.k;
@@ -478,6 +636,16 @@ static int valid(const orc_problem *P)
     if (!P || !P->mask || P->nx <= 0 || P->ny <= 0 || P->nz <= 0) return 0;
     if (!(P->mu_s >= 0.0) || !(P->mu_a >= 0.0) || !(fabs(P->g) < 1.0)) return 0;
     if (P->roulette_m < 2 || P->max_steps == 0) return 0;
+    if (P->boundary == 0) {
+        /* the plain model has no index, mirrors or gate */
+        if (P->lateral != 0 || P->n_solid != 1.0 || !isinf(P->gate)) return 0;
+    } else if (P->boundary == 1) {
+        if (P->lateral != 0 && P->lateral != 1) return 0;
+        if (!(P->n_solid >= 1.0) || !isfinite(P->n_solid)) return 0;
+        if (!(P->gate > 0.0)) return 0;
+    } else {
+        return 0;
+    }
     /* a surviving photon's weight w_th * m must not exceed the launch weight, so that
      * every weight stays <= 2^31 and w * S_q fits in 64 bits */
     if (!(P->w_roulette >= 0.0) || floor(P->w_roulette * ORC_W1) * (double)P->roulette_m > ORC_W1) return 0;
