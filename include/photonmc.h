@@ -14,7 +14,18 @@
  *     volume average <Phi>_1D (Eq. Phi_MC1D), pore average and the contrast
  *     ratio r (Eq. r_def), and the identity of Eq. dilution;
  *   - Sec. 2.8 (c): in-pore path length of every escaping photon.
- * Boundaries here: lateral faces periodic, refractive index 1 everywhere.
+ * Two boundary models (mc_optics.boundary):
+ *   - MC_BOUNDARY_PLAIN: lateral faces periodic, refractive index 1 everywhere,
+ *     photons start on the z = 0 face and escape when they cross z = 0 or z = Nz;
+ *   - MC_BOUNDARY_PAPER (Sec. 2.5 "Source and boundary conditions", "Photon
+ *     budget, time gate and statistics", App. B): a one-voxel air pad (index 1,
+ *     untallied) on each axial face, photons start on the pad's outer face and
+ *     escape through the outer face of either pad; lateral faces specular
+ *     mirrors or periodic; the solid has index n_solid and every face between
+ *     media of different index reflects (total internal reflection, or with the
+ *     unpolarised Fresnel reflectance against one uniform of the photon's own
+ *     Fresnel stream) or refracts (Snell's law); optional time gate (Eq. tend)
+ *     on the optical path sum(n d), the cut weight going to its own channel.
  *
  * Conventions
  *   - All buffers named "device" are HIP device pointers owned by the caller.
@@ -41,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MC_ABI_VERSION 1
+#define MC_ABI_VERSION 2
 
 /* status codes */
 #define MC_OK 0
@@ -60,7 +71,7 @@ extern "C" {
 
 /* Scalar tally channels: int64 words in a caller-owned device array of
  * MC_NSCALARS entries.  Weight channels are Q31.  For every run
- * R + T + A + RR + LOST == LAUNCHED * 2^31 exactly.  One set of tallies holds
+ * R + T + A + RR + LOST + GATED == LAUNCHED * 2^31 exactly.  One set of tallies holds
  * fewer than 2^32 photons (so LAUNCHED * 2^31 < 2^63). */
 enum {
     MC_S_R = 0,            /* weight escaped through z = 0 (reflectance) */
@@ -78,6 +89,7 @@ enum {
     MC_S_INTERACTIONS,     /* interaction events */
     MC_S_LAUNCHED,         /* photons launched */
     MC_S_ESC_W_VOID_PATH_HI, /* high parts (term >> 32) of the same sum: total = HI * 2^32 + LO */
+    MC_S_GATED,            /* weight of photons stopped by the time gate (paper boundary model) */
     MC_NSCALARS = 16
 };
 
@@ -108,6 +120,7 @@ enum {
     MC_Q_STATUS,           /* 0, or MC_EOVERFLOW if a voxel tally reached 2^62 */
     MC_Q_N_SOLID,          /* solid voxel count */
     MC_Q_LAUNCHED,         /* photons the tallies hold */
+    MC_Q_GATED,            /* weight fraction stopped by the time gate */
     MC_NSUMMARY = 32
 };
 
@@ -120,7 +133,14 @@ typedef struct {
     const uint8_t *mask;
 } mc_volume;
 
-/* Optical properties of the solid phase (per voxel length); pores are 0. */
+/* boundary models (mc_optics.boundary) */
+#define MC_BOUNDARY_PLAIN 0
+#define MC_BOUNDARY_PAPER 1
+#define MC_LATERAL_PERIODIC 0
+#define MC_LATERAL_MIRROR 1
+
+/* Optical properties of the solid phase (per voxel length); pores are 0.  A
+ * zero-initialised tail (boundary .. gate) selects the plain model. */
 typedef struct {
     float mu_s;            /* scattering coefficient, >= 0 */
     float mu_a;            /* absorption coefficient, >= 0 */
@@ -130,6 +150,12 @@ typedef struct {
     float path_cap;        /* stop a photon after this total path, voxels (<= 0: none) */
     int32_t source;        /* 0: collimated normal incidence (the paper's); 1: Lambertian (test) */
     uint32_t max_steps;    /* stop a photon after this many steps (0: 2^24) */
+    int32_t boundary;      /* MC_BOUNDARY_PLAIN (0) or MC_BOUNDARY_PAPER (1) */
+    int32_t lateral;       /* paper model: MC_LATERAL_PERIODIC (0) or MC_LATERAL_MIRROR (1); plain: 0 */
+    float n_solid;         /* paper model: refractive index of the solid, >= 1 (0: 1); plain: 0 or 1 */
+    int32_t reserved;      /* 0 */
+    double gate;           /* paper model: optical path limit c t_end in voxels, sum of n x segment length
+                              over the walk, pads included (<= 0 or +inf: none); plain: <= 0 or +inf */
 } mc_optics;
 
 /* Launch shape of the persistent walk.  Any value <= 0 selects the default.
@@ -227,7 +253,9 @@ typedef struct {
     uint32_t k;            /* interactions so far */
     int32_t ix, iy, iz;
     int32_t event;         /* 0/1/2 face crossing on x/y/z, 3 scatter, 4 escape z<0, 5 escape z>Nz,
-                              6 weight absorbed to zero, 7 roulette kill, 8 cap; -1 unused */
+                              6 weight absorbed to zero, 7 roulette kill, 8 cap, 9 time gate,
+                              10/11/12 reflection (mirror, Fresnel or total internal) on an x/y/z face;
+                              -1 unused.  In the paper model iz = -1 and iz = Nz are the air pads. */
 } mc_trace_rec;
 
 /* Per-photon outcome of a traced photon. */

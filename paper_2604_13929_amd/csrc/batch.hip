@@ -117,6 +117,8 @@ __device__ __forceinline__ void account_job(unsigned long long *acc, const Photo
         if (vp >> 32) atomicAdd(&acc[MC_S_ESC_W_VOID_PATH_HI], vp >> 32);
     } else if (ev == EV_LOST) {
         atomicAdd(&acc[MC_S_LOST], (unsigned long long)p.w);
+    } else if (ev == EV_GATED) {
+        atomicAdd(&acc[MC_S_GATED], (unsigned long long)p.w);
     }
     if (p.absorbed) atomicAdd(&acc[MC_S_A], (unsigned long long)p.absorbed);
     if (p.rr) atomicAdd(&acc[MC_S_RR], (unsigned long long)p.rr);
@@ -128,8 +130,9 @@ __device__ __forceinline__ void account_job(unsigned long long *acc, const Photo
 // Same queue discipline as the plain walk: a wavefront-private range of queue
 // positions refilled by one atomic, idle lanes refilled together, exit once
 // the queue is exhausted and no lane is alive.
-// LOGGED: every job's fluence pointer is its bricked tally.
-template <int BLOCK, typename R, bool LOGGED>
+// LOGGED: every job's fluence pointer is its bricked tally.  GENERAL: some job
+// uses the paper's boundary model (each job's own flags select its physics).
+template <int BLOCK, typename R, bool LOGGED, bool GENERAL>
 __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jobs, int32_t n_jobs,
                                                       unsigned long long *__restrict__ queue, int32_t chunk,
                                                       int32_t refill)
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
                         }
                         job = lo;
                         const Job &J = s_jobs[job];
-                        launch(p, J, (uint32_t)(J.photon_begin + (q - J.queue_begin)));
+                        launch<GENERAL>(p, J, (uint32_t)(J.photon_begin + (q - J.queue_begin)));
                         alive = true;
                     }
                     q_next += (uint64_t)nidle < avail ? (uint64_t)nidle : avail;
@@ -210,8 +213,8 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
                 sink.slot = (iter % kBLogK) * kBLogStride + lane;
                 sink.tag = (unsigned long long)job << kJobShift;
             }
-            const int32_t ev = step(p, J, sink);
-            if (ev >= EV_FIRST_TERMINAL) {
+            const int32_t ev = step<GENERAL>(p, J, sink);
+            if (is_terminal(ev)) {
                 account_job(acc[job], p, ev, J.nz);
                 alive = false;
             }
@@ -266,6 +269,7 @@ struct Prepared {
     std::vector<int32_t> order;   // table index -> caller's job index
     Layout L;
     uint64_t total_photons = 0;
+    bool general = false;         // some job uses the paper boundary model
 };
 
 int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, Prepared *P)
@@ -308,30 +312,31 @@ int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, Prepared *
         J.scalars = jb.scalars;
         J.queue_begin = q;
         q += jb.n_photons;
+        P->general = P->general || J.paper;
     }
     P->total_photons = q;
     return MC_OK;
 }
 
-template <typename R, bool LOGGED>
+template <typename R, bool LOGGED, bool GENERAL>
 void enqueue_batch_walk(int block, int blocks, const Job *table, int32_t n, unsigned long long *queue,
                         const mc_tune &t, hipStream_t s)
 {
     switch (block) {
     case 64:
-        hipLaunchKernelGGL((k_walk_batch<64, R, LOGGED>), dim3(blocks), dim3(64), 0, s, table, n, queue, t.chunk,
+        hipLaunchKernelGGL((k_walk_batch<64, R, LOGGED, GENERAL>), dim3(blocks), dim3(64), 0, s, table, n, queue, t.chunk,
                            t.refill);
         break;
     case 128:
-        hipLaunchKernelGGL((k_walk_batch<128, R, LOGGED>), dim3(blocks), dim3(128), 0, s, table, n, queue, t.chunk,
+        hipLaunchKernelGGL((k_walk_batch<128, R, LOGGED, GENERAL>), dim3(blocks), dim3(128), 0, s, table, n, queue, t.chunk,
                            t.refill);
         break;
     case 256:
-        hipLaunchKernelGGL((k_walk_batch<256, R, LOGGED>), dim3(blocks), dim3(256), 0, s, table, n, queue, t.chunk,
+        hipLaunchKernelGGL((k_walk_batch<256, R, LOGGED, GENERAL>), dim3(blocks), dim3(256), 0, s, table, n, queue, t.chunk,
                            t.refill);
         break;
     default:
-        hipLaunchKernelGGL((k_walk_batch<512, R, LOGGED>), dim3(blocks), dim3(512), 0, s, table, n, queue, t.chunk,
+        hipLaunchKernelGGL((k_walk_batch<512, R, LOGGED, GENERAL>), dim3(blocks), dim3(512), 0, s, table, n, queue, t.chunk,
                            t.refill);
         break;
     }
@@ -363,12 +368,23 @@ int enqueue_walk_only(const Prepared &P, char *ws, const mc_tune &t, int flags, 
     const Job *table = (const Job *)(ws + P.L.jobs_off);
     unsigned long long *queue = (unsigned long long *)ws;
     const int32_t n = (int32_t)P.table.size();
-    if (P.L.logged) {
-        if (flags & MC_FP64) enqueue_batch_walk<double, true>(t.block, blocks, table, n, queue, t, s);
-        else enqueue_batch_walk<float, true>(t.block, blocks, table, n, queue, t, s);
+    const bool f64 = (flags & MC_FP64) != 0;
+    if (P.general) {
+        if (P.L.logged) {
+            if (f64) enqueue_batch_walk<double, true, true>(t.block, blocks, table, n, queue, t, s);
+            else enqueue_batch_walk<float, true, true>(t.block, blocks, table, n, queue, t, s);
+        } else {
+            if (f64) enqueue_batch_walk<double, false, true>(t.block, blocks, table, n, queue, t, s);
+            else enqueue_batch_walk<float, false, true>(t.block, blocks, table, n, queue, t, s);
+        }
     } else {
-        if (flags & MC_FP64) enqueue_batch_walk<double, false>(t.block, blocks, table, n, queue, t, s);
-        else enqueue_batch_walk<float, false>(t.block, blocks, table, n, queue, t, s);
+        if (P.L.logged) {
+            if (f64) enqueue_batch_walk<double, true, false>(t.block, blocks, table, n, queue, t, s);
+            else enqueue_batch_walk<float, true, false>(t.block, blocks, table, n, queue, t, s);
+        } else {
+            if (f64) enqueue_batch_walk<double, false, false>(t.block, blocks, table, n, queue, t, s);
+            else enqueue_batch_walk<float, false, false>(t.block, blocks, table, n, queue, t, s);
+        }
     }
     HIP_TRY(hipGetLastError());
     return MC_OK;
@@ -476,8 +492,9 @@ std::string shape_key(const char *kind, const Prepared &P, int flags)
     uint64_t vox = 0;
     for (const Job &J : P.table) vox += (uint64_t)J.nx * J.ny * J.nz;
     char buf[400];
-    snprintf(buf, sizeof buf, "%s|%s|cu%d|%s|jobs%zu|vox2^%d|ph2^%d", kind, prop.gcnArchName, prop.multiProcessorCount,
-             (flags & MC_FP64) ? "f64" : "f32", P.table.size(), (int)log2((double)vox + 1.0),
+    snprintf(buf, sizeof buf, "%s|%s|cu%d|%s%s|jobs%zu|vox2^%d|ph2^%d", kind, prop.gcnArchName,
+             prop.multiProcessorCount, (flags & MC_FP64) ? "f64" : "f32", P.general ? "|paper" : "", P.table.size(),
+             (int)log2((double)vox + 1.0),
              (int)log2((double)P.total_photons + 1.0));
     for (char *c = buf; *c; ++c)
         if (*c == ' ') *c = '_';

@@ -184,6 +184,7 @@ struct GradSink : Deposit {
     template <typename R>
     __device__ __forceinline__ void segment(const Photon<R> &p, const Job &, R d, bool solid)
     {
+        if (p.iz < 0 || p.iz >= nz) return;                  // air pads carry no bins
         const double dd = (double)d, ls = p.l_tot - p.l_void;  // solid path before this segment
         const double sq = solid ? 0.5 * dd * dd : 0.0;
         const double sw = (double)p.w * kGradScale;
@@ -219,6 +220,8 @@ __device__ __forceinline__ void account(unsigned long long *acc, const Photon<R>
         if (vp >> 32) atomicAdd(&acc[MC_S_ESC_W_VOID_PATH_HI], vp >> 32);
     } else if (ev == EV_LOST) {
         atomicAdd(&acc[MC_S_LOST], (unsigned long long)p.w);
+    } else if (ev == EV_GATED) {
+        atomicAdd(&acc[MC_S_GATED], (unsigned long long)p.w);
     }
     if (p.absorbed) atomicAdd(&acc[MC_S_A], (unsigned long long)p.absorbed);
     if (p.rr) atomicAdd(&acc[MC_S_RR], (unsigned long long)p.rr);  // two's complement: signed sum
@@ -241,8 +244,9 @@ template <bool GRAD, bool LOGGED> struct SinkOf {
     using type = typename std::conditional<GRAD, GradSink<Deposit>, TallySink<Deposit>>::type;
 };
 
-// LOGGED: J.fluence is the bricked tally (see LoggedDeposit).
-template <int BLOCK, typename R, bool GRAD, bool LOGGED>
+// LOGGED: J.fluence is the bricked tally (see LoggedDeposit).  GENERAL: the
+// step that also knows the paper's boundary model (see walk.hpp).
+template <int BLOCK, typename R, bool GRAD, bool LOGGED, bool GENERAL>
 __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long *__restrict__ queue, int32_t chunk,
                                                 int32_t refill, unsigned long long *__restrict__ grad)
 {
@@ -298,7 +302,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
                     const uint64_t avail = q_end - q_next;
                     const uint32_t rank = (uint32_t)__popcll(idle & __lanemask_lt());
                     if (!alive && rank < avail) {
-                        launch(p, J, (uint32_t)(J.photon_begin + q_next + rank));
+                        launch<GENERAL>(p, J, (uint32_t)(J.photon_begin + q_next + rank));
                         alive = true;
                     }
                     q_next += (uint64_t)nidle < avail ? (uint64_t)nidle : avail;
@@ -308,8 +312,8 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
         }
         if (alive) {
             if constexpr (LOGGED) sink.slot = (iter % kLogK) * kLogStride + lane;
-            const int32_t ev = step(p, J, sink);
-            if (ev >= EV_FIRST_TERMINAL) {
+            const int32_t ev = step<GENERAL>(p, J, sink);
+            if (is_terminal(ev)) {
                 account(acc, p, ev, J.nz);
                 alive = false;
             }
@@ -362,7 +366,7 @@ struct TraceSink {
     }
 };
 
-template <typename R>
+template <typename R, bool GENERAL>
 __global__ void k_trace(const Job J, const uint64_t *__restrict__ ids, int32_t n, int32_t max_rec,
                         mc_trace_rec *__restrict__ recs, mc_photon_rec *__restrict__ out)
 {
@@ -371,12 +375,12 @@ __global__ void k_trace(const Job J, const uint64_t *__restrict__ ids, int32_t n
     TraceSink sink{recs + (int64_t)i * max_rec, max_rec, 0};
     for (int32_t j = 0; j < max_rec; ++j) sink.rec[j].event = -1;
     Photon<R> p;
-    launch(p, J, (uint32_t)ids[i]);
+    launch<GENERAL>(p, J, (uint32_t)ids[i]);
     int32_t ev;
     for (;;) {
-        ev = step(p, J, sink);
+        ev = step<GENERAL>(p, J, sink);
         sink.post(ev);
-        if (ev >= EV_FIRST_TERMINAL) break;
+        if (is_terminal(ev)) break;
     }
     if (out) {
         mc_photon_rec o;
@@ -503,7 +507,7 @@ __global__ void k_finalize(const unsigned long long *__restrict__ bins, const in
     q[MC_Q_A] = (double)S[MC_S_A] / launched_w;
     q[MC_Q_RR] = (double)S[MC_S_RR] / launched_w;
     q[MC_Q_LOST] = (double)S[MC_S_LOST] / launched_w;
-    const int64_t sum = S[MC_S_R] + S[MC_S_T] + S[MC_S_A] + S[MC_S_RR] + S[MC_S_LOST];
+    const int64_t sum = S[MC_S_R] + S[MC_S_T] + S[MC_S_A] + S[MC_S_RR] + S[MC_S_LOST] + S[MC_S_GATED];
     q[MC_Q_CLOSURE_EXACT] = (sum == S[MC_S_LAUNCHED] * (int64_t)2147483648ll) ? 1.0 : 0.0;
     const unsigned long long *b0 = bins, *bl = bins + (uint64_t)(nz - 1) * kBinW;
     const double f0 = join(b0[0], b0[1]) + join(b0[2], b0[3]);
@@ -521,6 +525,7 @@ __global__ void k_finalize(const unsigned long long *__restrict__ bins, const in
     q[MC_Q_STATUS] = mx >= (1ull << 62) ? (double)MC_EOVERFLOW : 0.0;
     q[MC_Q_N_SOLID] = (double)n_s;
     q[MC_Q_LAUNCHED] = n_ph;
+    q[MC_Q_GATED] = (double)S[MC_S_GATED] / launched_w;
 }
 
 // Jacobian of <Phi>_3D, <Phi>_1D and Phi(z) with respect to (mu_s, mu_a, g)
@@ -658,6 +663,20 @@ int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, 
     if (w_th * (double)opt->roulette_m > 2147483648.0)
         return fail(MC_EINVAL, "w_roulette * roulette_m must not exceed 1 (a survivor would outweigh a launched photon)");
     if (opt->source != 0 && opt->source != 1) return fail(MC_EINVAL, "source must be 0 or 1");
+    const bool gate_on = opt->gate > 0.0 && !isinf(opt->gate);
+    if (isnan(opt->gate)) return fail(MC_EINVAL, "gate is NaN");
+    if (opt->reserved != 0) return fail(MC_EINVAL, "mc_optics.reserved must be 0");
+    if (opt->boundary == MC_BOUNDARY_PLAIN) {
+        if (opt->lateral != MC_LATERAL_PERIODIC || (opt->n_solid != 0.0f && opt->n_solid != 1.0f) || gate_on)
+            return fail(MC_EINVAL, "the plain boundary model has periodic laterals, index 1 and no time gate");
+    } else if (opt->boundary == MC_BOUNDARY_PAPER) {
+        if (opt->lateral != MC_LATERAL_PERIODIC && opt->lateral != MC_LATERAL_MIRROR)
+            return fail(MC_EINVAL, "lateral must be MC_LATERAL_PERIODIC or MC_LATERAL_MIRROR");
+        if (opt->n_solid != 0.0f && !(opt->n_solid >= 1.0f && isfinite(opt->n_solid)))
+            return fail(MC_EINVAL, "n_solid must be finite and >= 1 (0 selects 1)");
+    } else {
+        return fail(MC_EINVAL, "boundary must be MC_BOUNDARY_PLAIN or MC_BOUNDARY_PAPER");
+    }
     if (n_photons == 0) return fail(MC_EINVAL, "n_photons is 0");
     if (photon_begin >= (1ull << 32) || n_photons > (1ull << 32) - photon_begin)
         return fail(MC_EINVAL, "photon ids must be < 2^32");
@@ -687,6 +706,11 @@ int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, 
     J->photon_begin = photon_begin;
     J->n_photons = n_photons;
     J->queue_begin = 0;
+    J->paper = opt->boundary == MC_BOUNDARY_PAPER ? 1 : 0;
+    J->lateral = opt->lateral;
+    J->n_solid = opt->n_solid == 0.0f ? 1.0f : opt->n_solid;
+    J->fresnel = J->n_solid != 1.0f ? 1 : 0;
+    J->gate = gate_on ? opt->gate : (double)kInf;
     return MC_OK;
 }
 
@@ -781,26 +805,26 @@ int enqueue_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *
     return MC_OK;
 }
 
-template <typename R, bool GRAD, bool LOGGED>
+template <typename R, bool GRAD, bool LOGGED, bool GENERAL>
 void enqueue_walk(int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t,
                   unsigned long long *grad, hipStream_t s)
 {
     const size_t lds = GRAD ? (size_t)6 * J.nz * sizeof(unsigned long long) : 0;
     switch (block) {
     case 64:
-        hipLaunchKernelGGL((k_walk<64, R, GRAD, LOGGED>), dim3(blocks), dim3(64), lds, s, J, queue, t.chunk, t.refill,
+        hipLaunchKernelGGL((k_walk<64, R, GRAD, LOGGED, GENERAL>), dim3(blocks), dim3(64), lds, s, J, queue, t.chunk, t.refill,
                            grad);
         break;
     case 128:
-        hipLaunchKernelGGL((k_walk<128, R, GRAD, LOGGED>), dim3(blocks), dim3(128), lds, s, J, queue, t.chunk,
+        hipLaunchKernelGGL((k_walk<128, R, GRAD, LOGGED, GENERAL>), dim3(blocks), dim3(128), lds, s, J, queue, t.chunk,
                            t.refill, grad);
         break;
     case 256:
-        hipLaunchKernelGGL((k_walk<256, R, GRAD, LOGGED>), dim3(blocks), dim3(256), lds, s, J, queue, t.chunk,
+        hipLaunchKernelGGL((k_walk<256, R, GRAD, LOGGED, GENERAL>), dim3(blocks), dim3(256), lds, s, J, queue, t.chunk,
                            t.refill, grad);
         break;
     default:
-        hipLaunchKernelGGL((k_walk<512, R, GRAD, LOGGED>), dim3(blocks), dim3(512), lds, s, J, queue, t.chunk,
+        hipLaunchKernelGGL((k_walk<512, R, GRAD, LOGGED, GENERAL>), dim3(blocks), dim3(512), lds, s, J, queue, t.chunk,
                            t.refill, grad);
         break;
     }
@@ -810,8 +834,13 @@ template <typename R, bool GRAD>
 void enqueue_walk_dep(bool logged, int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t,
                       unsigned long long *grad, hipStream_t s)
 {
-    if (logged) enqueue_walk<R, GRAD, true>(block, blocks, J, queue, t, grad, s);
-    else enqueue_walk<R, GRAD, false>(block, blocks, J, queue, t, grad, s);
+    if (J.paper) {
+        if (logged) enqueue_walk<R, GRAD, true, true>(block, blocks, J, queue, t, grad, s);
+        else enqueue_walk<R, GRAD, false, true>(block, blocks, J, queue, t, grad, s);
+    } else {
+        if (logged) enqueue_walk<R, GRAD, true, false>(block, blocks, J, queue, t, grad, s);
+        else enqueue_walk<R, GRAD, false, false>(block, blocks, J, queue, t, grad, s);
+    }
 }
 
 int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s, int flags,
@@ -988,12 +1017,18 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
     uint64_t *bricks = (uint64_t *)((char *)workspace + kHeaderBytes);
     J.bricks = bricks;
     if ((rc = pack(vol, bricks, s))) return rc;
-    if (flags & MC_FP64)
-        hipLaunchKernelGGL(k_trace<double>, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, J, photon_ids, n,
-                           max_steps, recs, outcome);
-    else
-        hipLaunchKernelGGL(k_trace<float>, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, J, photon_ids, n,
-                           max_steps, recs, outcome);
+    const dim3 grid((unsigned)((n + 63) / 64));
+    if (flags & MC_FP64) {
+        if (J.paper)
+            hipLaunchKernelGGL((k_trace<double, true>), grid, dim3(64), 0, s, J, photon_ids, n, max_steps, recs, outcome);
+        else
+            hipLaunchKernelGGL((k_trace<double, false>), grid, dim3(64), 0, s, J, photon_ids, n, max_steps, recs, outcome);
+    } else {
+        if (J.paper)
+            hipLaunchKernelGGL((k_trace<float, true>), grid, dim3(64), 0, s, J, photon_ids, n, max_steps, recs, outcome);
+        else
+            hipLaunchKernelGGL((k_trace<float, false>), grid, dim3(64), 0, s, J, photon_ids, n, max_steps, recs, outcome);
+    }
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }

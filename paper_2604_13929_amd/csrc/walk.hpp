@@ -10,6 +10,17 @@
 // event, the face axis taken as the first minimum in x, y, z order, an
 // interaction winning a tie against a face, in-voxel offsets clamped to [0,1].
 //
+// The paper's own boundary model (Sec. 2.5 "Source and boundary conditions",
+// App. B) is the GENERAL step: one-voxel air pads (layers iz = -1 and iz = nz,
+// index 1, untallied) on the axial faces, specular mirrors or periodic lateral
+// faces, a solid of index n_solid with reflection or refraction at every face
+// between media of different index (total internal reflection, else the
+// unpolarised Fresnel reflectance against a uniform of the photon's Fresnel
+// stream: Philox tag 4, block j >> 2, word j & 3 for its j-th decision; Snell's
+// law scales the tangential components by n1/n2), and the time gate of
+// Eq. tend on the optical path sum(n d).  With n_solid = 1, periodic faces and
+// no gate, the general step reproduces the plain step's tallies exactly.
+//
 // Position is an integer voxel index plus an offset in [0,1] per axis.  The
 // geometry and scattering arithmetic is templated on R: float (the default
 // transport) or double (a reference transport whose trajectories follow an
@@ -29,9 +40,11 @@ constexpr uint32_t kW1 = 0x80000000u;  // launched weight, 2^31
 // events (same codes as the trace records of the public header)
 enum : int32_t {
     EV_FACE_X = 0, EV_FACE_Y = 1, EV_FACE_Z = 2, EV_SCATTER = 3,
-    EV_ESC_R = 4, EV_ESC_T = 5, EV_DEAD_ABSORB = 6, EV_DEAD_ROULETTE = 7, EV_LOST = 8,
-    EV_FIRST_TERMINAL = 4
+    EV_ESC_R = 4, EV_ESC_T = 5, EV_DEAD_ABSORB = 6, EV_DEAD_ROULETTE = 7, EV_LOST = 8, EV_GATED = 9,
+    EV_REFLECT_X = 10, EV_REFLECT_Y = 11, EV_REFLECT_Z = 12
 };
+
+__host__ __device__ __forceinline__ bool is_terminal(int32_t ev) { return ev >= EV_ESC_R && ev <= EV_GATED; }
 
 // Per-job constants.  Everything integer that decides an outcome is computed
 // on the host in FP64 (survival factor, roulette threshold and odds).
@@ -57,6 +70,11 @@ struct Job {
     uint64_t photon_begin;    // first photon id
     uint64_t n_photons;
     uint64_t queue_begin;     // this job's offset in the launch-wide queue
+    int32_t paper;            // paper boundary model: air pads, mirrors or periodic, index, gate
+    int32_t lateral;          // paper model: 1 mirrors, 0 periodic
+    float n_solid;            // refractive index of the solid (1 in the plain model)
+    int32_t fresnel;          // n_solid != 1
+    double gate;              // optical path limit (paper model), +inf when off
 };
 
 template <typename R>
@@ -74,6 +92,9 @@ struct Photon {
     uint32_t brick;           // index of the cached brick
     uint32_t solid;           // current voxel is solid
     uint64_t bits;            // cached brick
+    double l_opt;             // optical path sum(n d), pads included (paper model's gate)
+    uint32_t nf;              // Fresnel decisions drawn so far
+    U4 fr;                    // current block of the Fresnel stream
 };
 
 // precision-generic helpers
@@ -100,10 +121,15 @@ __device__ __forceinline__ uint32_t bit_of(int32_t ix, int32_t iy, int32_t iz)
 }
 
 // Refresh the solid flag of the current voxel, reloading the brick only when
-// the photon has left the cached one.
-template <typename R>
+// the photon has left the cached one.  The air pads (iz outside [0, nz)) are
+// not solid (GENERAL walks only; the plain walk never stands in a pad).
+template <bool GENERAL, typename R>
 __device__ __forceinline__ void lookup(Photon<R> &p, const Job &J)
 {
+    if (GENERAL && (p.iz < 0 || p.iz >= J.nz)) {
+        p.solid = 0u;
+        return;
+    }
     const uint32_t b = brick_of(J, p.ix, p.iy, p.iz);
     if (b != p.brick) {
         p.bits = J.bricks[b];
@@ -136,7 +162,7 @@ __device__ __forceinline__ double free_path(const Job &J, uint32_t r)
 // Launch photon `pid` (Philox block k = 0): uniform position on the z = 0 face
 // from 24-bit uniforms scaled by the face size in integer arithmetic, normal
 // incidence (or Lambertian for the test source), first free path.
-template <typename R>
+template <bool GENERAL, typename R>
 __device__ __forceinline__ void launch(Photon<R> &p, const Job &J, uint32_t pid)
 {
     const U4 r = philox4x32_10(U4{0u, pid, J.stream_id, 0u}, J.key0, J.key1);
@@ -144,7 +170,7 @@ __device__ __forceinline__ void launch(Photon<R> &p, const Job &J, uint32_t pid)
     const uint64_t Y = (uint64_t)(r.y >> 8) * (uint64_t)J.ny;
     p.ix = (int32_t)(X >> 24);
     p.iy = (int32_t)(Y >> 24);
-    p.iz = 0;
+    p.iz = (GENERAL && J.paper) ? -1 : 0;  // paper model: the outer face of the top air pad
     p.fx = (R)(uint32_t)(X & 0xFFFFFFu) * (R)0x1.0p-24;
     p.fy = (R)(uint32_t)(Y & 0xFFFFFFu) * (R)0x1.0p-24;
     p.fz = (R)0;
@@ -173,7 +199,9 @@ __device__ __forceinline__ void launch(Photon<R> &p, const Job &J, uint32_t pid)
     p.rr = 0;
     p.acc = 0ull;
     p.brick = 0xFFFFFFFFu;
-    lookup(p, J);
+    p.l_opt = 0.0;
+    p.nf = 0u;
+    lookup<GENERAL>(p, J);
 }
 
 // Henyey-Greenstein deflection and the MCML direction update.  sin(theta) is
@@ -222,10 +250,42 @@ __device__ __forceinline__ R scatter(Photon<R> &p, const Job &J, uint32_t r0, ui
     return ct;
 }
 
+// Unpolarised Fresnel reflectance from index n1 into n2 at incidence cosine ci:
+// the mean of the s and p power coefficients.  Returns 1 on total internal
+// reflection; otherwise *ct is the cosine of the refracted direction.
+template <typename R>
+__device__ __forceinline__ R fresnel(R n1, R n2, R ci, R *ct)
+{
+    const R eta = n1 / n2;
+    const R st2 = eta * eta * ((R)1 - ci * ci);
+    if (st2 >= (R)1) {
+        *ct = (R)0;
+        return (R)1;
+    }
+    const R c = r_sqrt((R)1 - st2);
+    const R rs = (n1 * ci - n2 * c) / (n1 * ci + n2 * c);
+    const R rp = (n1 * c - n2 * ci) / (n1 * c + n2 * ci);
+    *ct = c;
+    return (R)0.5 * (rs * rs + rp * rp);
+}
+
+// Uniform of the photon's next Fresnel decision: word j & 3 of block j >> 2 of
+// its tag-4 Philox stream, a block drawn once per four decisions.
+template <typename R>
+__device__ __forceinline__ R fresnel_uniform(Photon<R> &p, const Job &J)
+{
+    const uint32_t j = p.nf++;
+    if ((j & 3u) == 0u) p.fr = philox4x32_10(U4{j >> 2, p.pid, J.stream_id, 4u}, J.key0, J.key1);
+    const uint32_t w = (j & 2u) ? ((j & 1u) ? p.fr.w : p.fr.z) : ((j & 1u) ? p.fr.y : p.fr.x);
+    return u01<R>(w);
+}
+
 // One photon-step: a segment inside the current voxel that ends at a face, an
-// interaction or an escape.  Returns the event.  The Sink receives the
-// segment, the flushed per-voxel deposits and the deflection cosines.
-template <typename R, class Sink>
+// interaction or an escape (and, in the GENERAL walk, a reflection or the time
+// gate).  Returns the event.  The Sink receives every segment (deposits and
+// gradient scores are taken only inside the slab), the flushed per-voxel
+// deposits and the deflection cosines.
+template <bool GENERAL, typename R, class Sink>
 __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
 {
     const R dx = p.ux != (R)0 ? (p.ux > (R)0 ? (R)1 - p.fx : p.fx) * inv_abs(p.ux) : r_inf<R>();
@@ -236,19 +296,40 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
     if (dy < d_face) { axis = 1; d_face = dy; }
     if (dz < d_face) { axis = 2; d_face = dz; }
     const bool solid = p.solid != 0u;
-    const bool interact = solid && (p.s_rem <= (double)d_face);
-    const R d = interact ? (R)p.s_rem : d_face;
+    bool interact = solid && (p.s_rem <= (double)d_face);
+    R d = interact ? (R)p.s_rem : d_face;
+    bool in_slab = true, gated = false;
+    double n_here = 1.0;
+    if constexpr (GENERAL) {
+        in_slab = p.iz >= 0 && p.iz < J.nz;
+        n_here = solid ? (double)J.n_solid : 1.0;
+        // the optical path may reach the gate, not pass it
+        const double t_left = (J.gate - p.l_opt) / n_here;
+        if ((double)d > t_left) {
+            gated = true;
+            interact = false;
+            d = (R)fmax(t_left, 0.0);
+        }
+    }
 
     sink.segment(p, J, d, solid);
-    // track-length deposit, quantised per segment, accumulated while in this voxel
-    p.acc += r_to_u64((R)p.w * d);
-    if (solid) p.s_rem = fmax(p.s_rem - (double)d, 0.0);
-    else p.l_void += (double)d;
-    p.l_tot += (double)d;
+    if (in_slab) {
+        // track-length deposit, quantised per segment, accumulated while in this voxel
+        p.acc += r_to_u64((R)p.w * d);
+        if (solid) p.s_rem = fmax(p.s_rem - (double)d, 0.0);
+        else p.l_void += (double)d;
+        p.l_tot += (double)d;
+    }
+    if constexpr (GENERAL) p.l_opt += n_here * (double)d;
     p.steps += 1u;
 
     int32_t ev;
-    if (interact) {
+    if (GENERAL && gated) {
+        p.fx = clamp01(p.fx + p.ux * d);
+        p.fy = clamp01(p.fy + p.uy * d);
+        p.fz = clamp01(p.fz + p.uz * d);
+        ev = EV_GATED;
+    } else if (interact) {
         p.fx = clamp01(p.fx + p.ux * d);
         p.fy = clamp01(p.fy + p.uy * d);
         p.fz = clamp01(p.fz + p.uz * d);
@@ -275,7 +356,7 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
             }
             p.s_rem = free_path(J, r.z);
         }
-    } else {
+    } else if constexpr (!GENERAL) {
         if (axis != 0) p.fx = clamp01(p.fx + p.ux * d);
         if (axis != 1) p.fy = clamp01(p.fy + p.uy * d);
         if (axis != 2) p.fz = clamp01(p.fz + p.uz * d);
@@ -294,11 +375,81 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
             if (p.iz < 0) ev = EV_ESC_R;
             else if (p.iz >= J.nz) ev = EV_ESC_T;
         }
-        if (ev < EV_FIRST_TERMINAL) lookup(p, J);
+        if (!is_terminal(ev)) lookup<false>(p, J);
+    } else {
+        if (axis != 0) p.fx = clamp01(p.fx + p.ux * d);
+        if (axis != 1) p.fy = clamp01(p.fy + p.uy * d);
+        if (axis != 2) p.fz = clamp01(p.fz + p.uz * d);
+        const R ua = axis == 0 ? p.ux : (axis == 1 ? p.uy : p.uz);
+        const int32_t sgn = ua > (R)0 ? 1 : -1;
+        int32_t jx = p.ix, jy = p.iy, jz = p.iz;
+        bool reflect = false, out = false;
+        if (axis == 0) {
+            jx += sgn;
+            if (jx < 0 || jx >= J.nx) {
+                if (J.lateral) reflect = true;             // specular mirror
+                else jx = jx < 0 ? J.nx - 1 : 0;           // periodic
+            }
+        } else if (axis == 1) {
+            jy += sgn;
+            if (jy < 0 || jy >= J.ny) {
+                if (J.lateral) reflect = true;
+                else jy = jy < 0 ? J.ny - 1 : 0;
+            }
+        } else {
+            jz += sgn;
+            out = J.paper ? (jz < -1 || jz > J.nz) : (jz < 0 || jz >= J.nz);
+        }
+        // the neighbour's medium, from the cached brick when it holds it
+        uint32_t nb = p.brick;
+        uint64_t nbits = p.bits;
+        bool next_solid = false;
+        if (!reflect && !out && jz >= 0 && jz < J.nz) {
+            nb = brick_of(J, jx, jy, jz);
+            if (nb != p.brick) nbits = J.bricks[nb];
+            next_solid = ((nbits >> bit_of(jx, jy, jz)) & 1ull) == 0ull;
+        }
+        if (!reflect && !out && J.fresnel && next_solid != solid) {
+            const R n1 = solid ? (R)J.n_solid : (R)1, n2 = next_solid ? (R)J.n_solid : (R)1;
+            R ct;
+            const R rf = fresnel(n1, n2, fabs(ua), &ct);
+            if (rf >= (R)1 || fresnel_uniform(p, J) < rf) {
+                reflect = true;
+            } else {
+                const R eta = n1 / n2;
+                p.ux = axis == 0 ? (R)sgn * ct : eta * p.ux;
+                p.uy = axis == 1 ? (R)sgn * ct : eta * p.uy;
+                p.uz = axis == 2 ? (R)sgn * ct : eta * p.uz;
+            }
+        }
+        if (reflect) {
+            // stay in this voxel on the face, normal component reversed
+            if (axis == 0) { p.ux = -p.ux; p.fx = sgn > 0 ? (R)1 : (R)0; }
+            else if (axis == 1) { p.uy = -p.uy; p.fy = sgn > 0 ? (R)1 : (R)0; }
+            else { p.uz = -p.uz; p.fz = sgn > 0 ? (R)1 : (R)0; }
+            ev = EV_REFLECT_X + axis;
+        } else {
+            if (in_slab) sink.flush(J, p, p.acc);
+            p.acc = 0ull;
+            if (out) {
+                ev = jz < 0 ? EV_ESC_R : EV_ESC_T;
+            } else {
+                p.ix = jx; p.iy = jy; p.iz = jz;
+                if (axis == 0) p.fx = sgn > 0 ? (R)0 : (R)1;
+                else if (axis == 1) p.fy = sgn > 0 ? (R)0 : (R)1;
+                else p.fz = sgn > 0 ? (R)0 : (R)1;
+                if (jz >= 0 && jz < J.nz) {
+                    p.brick = nb;
+                    p.bits = nbits;
+                }
+                p.solid = next_solid ? 1u : 0u;
+                ev = axis;
+            }
+        }
     }
-    if (ev < EV_FIRST_TERMINAL && (p.steps >= J.max_steps || p.l_tot > (double)J.path_cap)) ev = EV_LOST;
-    if (ev >= EV_FIRST_TERMINAL && p.acc != 0ull) {
-        // photon ends inside a voxel (absorbed, roulette, cap): flush what it left there
+    if (!is_terminal(ev) && (p.steps >= J.max_steps || p.l_tot > (double)J.path_cap)) ev = EV_LOST;
+    if (is_terminal(ev) && p.acc != 0ull) {
+        // photon ends inside a voxel (absorbed, roulette, cap, gate): flush what it left there
         sink.flush(J, p, p.acc);
         p.acc = 0ull;
     }

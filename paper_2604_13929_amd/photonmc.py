@@ -24,10 +24,16 @@ MC_DIRECT_DEPOSIT = 8
 NSCALARS = 16
 NSUMMARY = 32
 SCALARS = ["R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_w_void_path_lo", "esc_n", "esc_n_gtL",
-           "steps", "interactions", "launched", "esc_w_void_path_hi"]
+           "steps", "interactions", "launched", "esc_w_void_path_hi", "gated"]
 SUMMARY = ["phi3d", "phi1d", "phi_pore", "r", "porosity", "ratio", "identity_rhs", "R", "T", "A", "RR", "lost",
            "closure_exact", "front_back", "L_opt", "esc_frac", "Pw_void_gtL", "Pn_void_gtL", "mean_void_path",
-           "steps_per_photon", "interactions_per_photon", "status", "n_solid", "launched"]
+           "steps_per_photon", "interactions_per_photon", "status", "n_solid", "launched", "gated"]
+BOUNDARY_PLAIN, BOUNDARY_PAPER = 0, 1
+LATERAL_PERIODIC, LATERAL_MIRROR = 0, 1
+#: trace events
+EVENTS = {0: "face_x", 1: "face_y", 2: "face_z", 3: "scatter", 4: "esc_R", 5: "esc_T", 6: "dead_absorb",
+          7: "dead_roulette", 8: "lost", 9: "gated", 10: "reflect_x", 11: "reflect_y", 12: "reflect_z"}
+SPEED_OF_LIGHT = 299_792_458.0
 W1 = 2 ** 31
 
 
@@ -39,7 +45,9 @@ class McVolume(ctypes.Structure):
 class McOptics(ctypes.Structure):
     _fields_ = [("mu_s", ctypes.c_float), ("mu_a", ctypes.c_float), ("g", ctypes.c_float),
                 ("w_roulette", ctypes.c_float), ("roulette_m", ctypes.c_uint32), ("path_cap", ctypes.c_float),
-                ("source", ctypes.c_int32), ("max_steps", ctypes.c_uint32)]
+                ("source", ctypes.c_int32), ("max_steps", ctypes.c_uint32),
+                ("boundary", ctypes.c_int32), ("lateral", ctypes.c_int32), ("n_solid", ctypes.c_float),
+                ("reserved", ctypes.c_int32), ("gate", ctypes.c_double)]
 
 
 class McTune(ctypes.Structure):
@@ -140,7 +148,10 @@ def _stream(device: torch.device):
 
 @dataclass
 class Optics:
-    """Solid-phase optics per voxel length; pores are transparent."""
+    """Solid-phase optics per voxel length; pores are transparent.  ``boundary``
+    selects the plain model (periodic laterals, index 1) or the paper's (air pads,
+    ``lateral`` mirrors or periodic faces, solid index ``n_solid`` with Fresnel
+    reflection and refraction, optional time gate ``gate`` = c t_end in voxels)."""
     mu_s: float
     mu_a: float
     g: float
@@ -149,10 +160,40 @@ class Optics:
     path_cap: float = 0.0
     source: int = 0
     max_steps: int = 0
+    boundary: int = BOUNDARY_PLAIN
+    lateral: int = LATERAL_PERIODIC
+    n_solid: float = 0.0
+    gate: float = 0.0
 
     def c(self) -> McOptics:
         return McOptics(self.mu_s, self.mu_a, self.g, self.w_roulette, self.roulette_m, self.path_cap,
-                        self.source, self.max_steps)
+                        self.source, self.max_steps, self.boundary, self.lateral, self.n_solid, 0, self.gate)
+
+
+def paper_optics(mu_s: float, mu_a: float, g: float, n_solid: float = 1.746, lateral: int = LATERAL_MIRROR,
+                 gate: float = 0.0, **kw) -> Optics:
+    """Optics under the paper's boundary model (mirrors, air pads, Fresnel at the solid's
+    index, gate in voxels of optical path or 0 for none)."""
+    return Optics(mu_s, mu_a, g, boundary=BOUNDARY_PAPER, lateral=lateral, n_solid=n_solid, gate=gate, **kw)
+
+
+def time_gate_seconds(mu_a: float, mu_s_red: float, porosity: float, thickness: float, n_eff: float,
+                      c: float = SPEED_OF_LIGHT) -> float:
+    """Eq. tend: t_end = max(5 n_eff / (mu_a c), 6 L^2 / D_phys) with
+    D_phys = (c / n_eff) / (3 (mu_a,eff + mu_s,eff')) and the effective-medium
+    scaling of Eq. EMA_scaling, mu_eff = (1 - phi) mu.  SI units (1/m, m, s);
+    mu_a and mu_s_red are the solid (shell) coefficients."""
+    mu_a_eff = mu_a * (1.0 - porosity)
+    mus_eff = mu_s_red * (1.0 - porosity)
+    d_phys = (c / n_eff) / (3.0 * (mu_a_eff + mus_eff))
+    absorb = 5.0 * n_eff / (mu_a * c) if mu_a > 0 else float("inf")
+    return max(absorb, 6.0 * thickness ** 2 / d_phys)
+
+
+def time_gate_voxels(mu_s: float, mu_a: float, g: float, porosity: float, nz: int, n_eff: float) -> float:
+    """The same gate as an optical path c t_end in voxel lengths, for coefficients per
+    voxel and a slab of nz voxels: max(5 n / mu_a, 18 n nz^2 (1 - phi)(mu_a + mu_s (1 - g)))."""
+    return time_gate_seconds(mu_a, mu_s * (1.0 - g), porosity, float(nz), n_eff, c=1.0)
 
 
 @dataclass

@@ -41,8 +41,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_layouts(lib):
-    assert lib.mc_abi_version() == 1
+    assert lib.mc_abi_version() == 2
     assert lib.mc_sizeof(b"mc_volume") == 24
+    assert lib.mc_sizeof(b"mc_optics") == ctypes.sizeof(pm.McOptics) == 56
     assert lib.mc_sizeof(b"mc_trace_rec") == pm.TRACE_DTYPE.itemsize == 88
     assert lib.mc_sizeof(b"mc_photon_rec") == pm.PHOTON_DTYPE.itemsize == 72
     assert lib.mc_sizeof(b"nonsense") == 0
@@ -54,9 +55,10 @@ def test_strerror(lib):
 
 
 def _call_run(lib, nx=8, ny=8, nz=8, mask=1, mu_s=0.5, mu_a=0.01, g=0.7, w_r=1e-4, m=10, n=10, begin=0,
-              fluence=1, scalars=1, ws=1, ws_bytes=1 << 20, source=0, tune=None):
+              fluence=1, scalars=1, ws=1, ws_bytes=1 << 20, source=0, tune=None, boundary=0, lateral=0,
+              n_solid=0.0, reserved=0, gate=0.0):
     vol = pm.McVolume(nx, ny, nz, 0, mask)
-    opt = pm.McOptics(mu_s, mu_a, g, w_r, m, 0.0, source, 0)
+    opt = pm.McOptics(mu_s, mu_a, g, w_r, m, 0.0, source, 0, boundary, lateral, n_solid, reserved, gate)
     return lib.mc_run(ctypes.byref(vol), ctypes.byref(opt), begin, n, 1, 0, 0, fluence, scalars, ws, ws_bytes,
                       ctypes.byref(tune) if tune is not None else None, None)
 
@@ -67,6 +69,11 @@ def _call_run(lib, nx=8, ny=8, nz=8, mask=1, mu_s=0.5, mu_a=0.01, g=0.7, w_r=1e-
     (dict(g=1.0), b"|g|"), (dict(m=1), b"roulette_m"), (dict(w_r=0.5, m=10), b"outweigh"),
     (dict(n=0), b"n_photons"), (dict(begin=2 ** 32 - 5, n=10), b"2^32"), (dict(source=3), b"source"),
     (dict(fluence=None), b"non-NULL"), (dict(ws_bytes=16), b"workspace"),
+    (dict(lateral=1), b"plain boundary model"), (dict(n_solid=1.5), b"plain boundary model"),
+    (dict(gate=100.0), b"plain boundary model"), (dict(boundary=2), b"boundary must"),
+    (dict(boundary=1, n_solid=0.5), b"n_solid"), (dict(boundary=1, n_solid=float("inf")), b"n_solid"),
+    (dict(boundary=1, lateral=2), b"lateral"), (dict(boundary=1, gate=float("nan")), b"NaN"),
+    (dict(reserved=1), b"reserved"),
 ])
 def test_run_rejects_bad_arguments(lib, kw, needle):
     rc = _call_run(lib, **kw)

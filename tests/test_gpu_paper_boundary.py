@@ -1,0 +1,223 @@
+"""The paper's boundary model on the GPU (air pads, Fresnel reflection and
+refraction at the solid's index, lateral mirrors, time gate) against the FP64
+oracle and against closed forms, through the C ABI:
+
+* index 1, periodic laterals, no gate: the general walk reproduces the plain
+  walk's tallies bit for bit (only the pad steps are added);
+* FP64 transport: trajectories follow the oracle to 1e-5 voxel, per-photon
+  outcomes are identical (Fresnel decisions included);
+* FP32 transport: per-voxel fluence within 4 sigma of the oracle, globals within
+  0.5 %, exact integer closure with the gated channel;
+* straight photons cut exactly at the gate; a non-scattering slab against
+  incoherent multiple reflection;
+* a batch mixing both models equals the plain runs of its jobs bit for bit;
+* likelihood-ratio bins under the paper model match the oracle's;
+* at 256^3 with the paper's per-voxel optics and gate, a sampled sub-range of the
+  id space matches the oracle.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import estimators as est
+from paper_2604_13929_amd import inputs
+from paper_2604_13929_amd import photonmc as pm
+from test_gpu_parity import _compare_trajectories
+
+pytestmark = pytest.mark.gpu
+
+W1 = 2 ** 31
+SEED = 20260809
+f32 = lambda x: float(np.float32(x))  # noqa: E731
+N_SOLID = f32(1.746)
+BASE = dict(mu_s=0.5, mu_a=f32(0.01), g=f32(0.7))
+PAPER = pm.paper_optics(**BASE, n_solid=N_SOLID, lateral=pm.LATERAL_MIRROR, gate=400.0)
+
+
+def banner(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pm.load()
+
+
+def dev(mask):
+    return torch.from_numpy(np.ascontiguousarray(mask)).to("cuda:0")
+
+
+def okw(opt: pm.Optics) -> dict:
+    """The oracle's arguments for the same optics."""
+    return dict(w_roulette=opt.w_roulette, roulette_m=opt.roulette_m, source=opt.source, boundary=opt.boundary,
+                lateral=opt.lateral, n_solid=opt.n_solid if opt.n_solid else 1.0,
+                gate=opt.gate if opt.gate > 0 else float("inf"))
+
+
+def closure(sc, n):
+    return sc["R"] + sc["T"] + sc["A"] + sc["RR"] + sc["lost"] + sc["gated"] - n * W1
+
+
+def test_index_matched_paper_model_equals_plain_bitwise(mask_m1):
+    banner("paper model, index 1, periodic, no gate == plain model (FP32 and FP64)")
+    d = dev(mask_m1)
+    n = 100_000
+    matched = pm.paper_optics(**BASE, n_solid=1.0, lateral=pm.LATERAL_PERIODIC, gate=0.0)
+    for fp64 in (False, True):
+        a = pm.run(d, pm.Optics(**BASE), n, SEED, fp64=fp64)
+        b = pm.run(d, matched, n, SEED, fp64=fp64)
+        assert torch.equal(a.fluence, b.fluence)
+        sa, sb = a.scalar_dict(), b.scalar_dict()
+        for k in pm.SCALARS:
+            if k != "steps":
+                assert sa[k] == sb[k], (fp64, k)
+        assert sb["steps"] >= sa["steps"] + 2 * n
+
+
+def test_trajectories_fp64_paper_model(mask_m1):
+    banner("paper model FP64 trajectories M1, 2000 photons x 64 steps")
+    ids = np.arange(2000, dtype=np.uint64) * 7 + 3
+    g, _ = pm.trace(dev(mask_m1), PAPER, ids, 64, SEED, fp64=True)
+    o, _ = oracle.trace(mask_m1, PAPER.mu_s, PAPER.mu_a, PAPER.g, ids, SEED, max_rec=64, **okw(PAPER))
+    worst = _compare_trajectories(g, o, tol=1e-5, tie=1e-9)
+    print("fp64 trajectory deviation quantiles 50/99/100 %:", np.quantile(worst, [0.5, 0.99, 1.0]))
+    assert np.all(worst < 1e-5)
+    ev = o["event"][o["event"] >= 0]
+    assert (ev >= 10).sum() > 1000        # reflections (mirror, Fresnel, total internal) are exercised
+
+
+def test_photon_outcomes_fp64_paper_model(mask_m1):
+    banner("paper model per-photon outcomes M1, 5000 photons, FP64 transport, gate 150")
+    opt = pm.paper_optics(**BASE, n_solid=N_SOLID, lateral=pm.LATERAL_MIRROR, gate=150.0)
+    ids = np.arange(5000, dtype=np.uint64) + 98_765
+    _, go = pm.trace(dev(mask_m1), opt, ids, 0, SEED, fp64=True)
+    _, oo = oracle.trace(mask_m1, opt.mu_s, opt.mu_a, opt.g, ids, SEED, max_rec=0, **okw(opt))
+    clean = oo["min_gap"] > 1e-9
+    assert clean.mean() > 0.995
+    for f in ("R", "T", "A", "RR", "lost", "w_final", "fate", "steps", "interactions"):
+        assert np.array_equal(go[f][clean].astype(np.int64), oo[f][clean].astype(np.int64)), f
+    assert np.allclose(go["path_void"][clean], oo["path_void"][clean], rtol=1e-9, atol=1e-9)
+    assert (oo["fate"] == 9).sum() > 100                                   # gated photons
+    assert np.all(go["steps"] > 0)
+
+
+def test_fields_and_globals_paper_model(mask_m1):
+    banner("paper model M1 1e5 photons FP32: per-voxel 4 sigma, globals 0.5 %")
+    n, B = 100_000, 32
+    d = dev(mask_m1)
+    res = pm.run(d, PAPER, n, SEED)
+    summ = pm.reduce(d, res)
+    sc = res.scalar_dict()
+    assert closure(sc, n) == 0 and summ["closure_exact"] == 1.0 and sc["lost"] == 0
+    ref = oracle.run(mask_m1, PAPER.mu_s, PAPER.mu_a, PAPER.g, n, SEED, nbatch=B, **okw(PAPER))
+    tot = oracle.totals(ref)
+    F_o = ref["fluence"].sum(axis=0)
+    F_g = res.fluence.cpu().numpy().astype(np.float64)
+    sd = ref["fluence"].std(axis=0, ddof=1) * math.sqrt(B)
+    nz_sd = sd > 0
+    chi = ((F_g - F_o)[nz_sd] / sd[nz_sd]) ** 2
+    print(f"per-voxel (dF/sigma)^2 mean {chi.mean():.3f}, max {chi.max():.2f}; gated fraction "
+          f"{sc['gated'] / (n * W1):.4f}")
+    assert np.all(np.abs(F_g - F_o)[nz_sd] <= 4 * sd[nz_sd]) and chi.mean() < 1.0
+    e = est.estimators(F_o, mask_m1, n)
+    for k in ("phi3d", "phi1d", "phi_pore"):
+        assert abs(summ[k] - e[k]) <= 5e-3 * abs(e[k]), k
+    for k in ("R", "T", "A", "gated"):
+        assert abs(sc[k] - tot[k]) <= 5e-3 * n * W1, k
+    assert tot["gated"] > 0
+    assert abs(sc["steps"] - tot["steps"]) <= 1e-3 * tot["steps"]
+    assert summ["gated"] == sc["gated"] / (n * W1)
+
+
+def test_gate_cuts_straight_photons_exactly_gpu():
+    banner("gate: straight photons through an empty slab, exact layer sums")
+    nx, ny, nz, n = 5, 3, 8, 20_000
+    m = inputs.homogeneous_mask(nx, ny, nz, pore=True)
+    for G in (5.25, 1.5, 9.75):
+        res = pm.run(dev(m), pm.paper_optics(**BASE, n_solid=N_SOLID, gate=G), n, SEED)
+        sc = res.scalar_dict()
+        assert sc["gated"] == n * W1 and sc["R"] == sc["T"] == sc["A"] == 0
+        layer = res.fluence.cpu().numpy().sum(axis=(1, 2))
+        want = (np.clip(G - 1 - np.arange(nz), 0, 1) * n * W1).astype(np.int64)
+        assert np.array_equal(layer, want), (G, layer, want)
+
+
+def test_slab_multiple_reflection_gpu():
+    banner("non-scattering solid slab between Fresnel faces vs closed form")
+    nz, n = 12, 1_000_000
+    m = inputs.homogeneous_mask(4, 4, nz)
+    mu_a = f32(0.05)
+    res = pm.run(dev(m), pm.paper_optics(0.0, mu_a, 0.0, n_solid=N_SOLID), n, SEED)
+    sc = res.scalar_dict()
+    assert closure(sc, n) == 0
+    r = ((N_SOLID - 1) / (N_SOLID + 1)) ** 2
+    t = math.exp(-mu_a * nz)
+    T = (1 - r) ** 2 * t / (1 - r * r * t * t)
+    R = r + r * (1 - r) ** 2 * t * t / (1 - r * r * t * t)
+    for key, p in (("R", R), ("T", T)):
+        got = sc[key] / (n * W1)
+        assert abs(got - p) < 4 * math.sqrt(p * (1 - p) / n), (key, got, p)
+
+
+def test_batch_mixing_models_equals_plain_runs(mask_m1):
+    banner("batch of paper and plain jobs == their own runs, bitwise")
+    m2 = inputs.spinodal_mask(24, 20, 16, 6.0, 0.8, seed=5)
+    specs = [(mask_m1, PAPER, 30_000, 0), (mask_m1, pm.Optics(**BASE), 20_000, 1),
+             (m2, pm.paper_optics(**BASE, n_solid=1.4, lateral=pm.LATERAL_PERIODIC), 25_000, 2)]
+    jobs = [pm.BatchJob(dev(m), o, n, SEED, stream_id=s) for m, o, n, s in specs]
+    b = pm.run_batch(jobs, tune=pm.Tune(256, 8, 64, 16))
+    for (m, o, n, s), r in zip(specs, b.results):
+        ref = pm.run(dev(m), o, n, SEED, stream_id=s)
+        assert torch.equal(r.fluence, ref.fluence) and torch.equal(r.scalars, ref.scalars)
+
+
+def test_grad_paper_model_matches_oracle(mask_m1):
+    banner("likelihood-ratio bins under the paper model, FP64 transport vs oracle")
+    n = 50_000
+    d = dev(mask_m1)
+    g = pm.grad(d, PAPER, n, SEED, fp64=True)
+    r = pm.run(d, PAPER, n, SEED, fp64=True)
+    assert torch.equal(g.run.fluence, r.fluence) and torch.equal(g.run.scalars, r.scalars)
+    ref = oracle.run(mask_m1, PAPER.mu_s, PAPER.mu_a, PAPER.g, n, SEED, grad=True, fluence=False, **okw(PAPER))
+    nz, ny, nx = mask_m1.shape
+    got = g.bins_value() * 2.0 ** 16 * (nx * ny) / (n * W1)
+    want = ref["grad"][0] * (nx * ny) / (n * W1)
+    scale = np.abs(want).max(axis=-1, keepdims=True)
+    assert np.all(np.abs(got - want) <= 1e-6 * scale + 1e-9), np.abs(got - want).max()
+
+
+def test_paper_configuration_256cube_sampled():
+    """The paper's per-voxel shell optics (mu_s = 20118 1/m, mu_a = 5159 1/m, g = 0 at
+    1.45 um voxels), n_eff = 1.746, mirrors, air pads and the gate of Eq. tend, on the
+    256^3 phi = 0.70 mask: 20 000 photons from the middle of the id range vs oracle."""
+    banner("paper configuration 256^3 phi 0.70: sampled sub-range vs oracle")
+    wl = inputs.WORKLOADS["M2a"]
+    m = inputs.spinodal_mask(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], wl["porosity"], seed=0)
+    a = 1.45e-6
+    mu_s, mu_a = f32(20118.0 * a), f32(5159.0 * a)
+    gate = pm.time_gate_voxels(mu_s, mu_a, 0.0, wl["porosity"], wl["nz"], 1.746)
+    opt = pm.paper_optics(mu_s, mu_a, 0.0, n_solid=N_SOLID, gate=gate)
+    d = dev(m)
+    begin, n = 40_000_000, 20_000
+    res = pm.run(d, opt, n, SEED, photon_begin=begin)
+    s = pm.reduce(d, res)
+    sc = res.scalar_dict()
+    assert closure(sc, n) == 0
+    ref = oracle.run(m, opt.mu_s, opt.mu_a, opt.g, n, SEED, photon_begin=begin, fluence=False, depth=True, **okw(opt))
+    tot = oracle.totals(ref)
+    for k in ("R", "T", "A", "gated"):
+        assert abs(sc[k] - tot[k]) <= 5e-3 * n * W1, (k, sc[k], tot[k])
+    assert abs(sc["steps"] - tot["steps"]) <= 2e-3 * tot["steps"]
+    dep = ref["depth"][0] * (wl["nx"] * wl["ny"]) / (n * W1)
+    n_s = int((m == 0).sum())
+    phi3d = dep[0].sum() / n_s
+    assert abs(s["phi3d"] - phi3d) <= 5e-3 * phi3d
+    print(f"paper configuration: R {s['R']:.4f} T {s['T']:.4f} A {s['A']:.4f} gated {s['gated']:.2e}, "
+          f"phi3d {s['phi3d']:.4f}, r {s['r']:.4f}, steps/photon {s['steps_per_photon']:.0f}")
