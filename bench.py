@@ -171,6 +171,12 @@ def morphology_leg(args, seed):
             "ms": {k: out[k]["ms"] for k in out}}
 
 
+def oracle_kw(opt) -> dict:
+    """The oracle's boundary-model arguments for the binding's optics."""
+    return dict(boundary=opt.boundary, lateral=opt.lateral, n_solid=opt.n_solid if opt.n_solid else 1.0,
+                gate=opt.gate if opt.gate > 0 else float("inf"))
+
+
 def oracle_check(mask_np, dmask, opt, m, seed, ncpu):
     """The oracle on the first ``m`` photon ids of a workload and the GPU on the same
     ids: relative errors of the estimators, and the oracle's time."""
@@ -181,7 +187,7 @@ def oracle_check(mask_np, dmask, opt, m, seed, ncpu):
     from paper_2604_13929_amd import photonmc as pm
 
     t0 = time.perf_counter()
-    ref = oracle.run(mask_np, opt.mu_s, opt.mu_a, opt.g, m, seed, nthreads=ncpu)
+    ref = oracle.run(mask_np, opt.mu_s, opt.mu_a, opt.g, m, seed, nthreads=ncpu, **oracle_kw(opt))
     t_cpu = time.perf_counter() - t0
     tot = oracle.totals(ref)
     sub = pm.run(dmask, opt, m, seed)
@@ -190,7 +196,7 @@ def oracle_check(mask_np, dmask, opt, m, seed, ncpu):
     err = {k: abs(ssum[k] - e[k]) / abs(e[k]) for k in ("phi3d", "phi1d", "r")
            if math.isfinite(e[k]) and e[k] != 0}
     gsc = sub.scalar_dict()
-    for k in ("R", "T", "A"):
+    for k in ("R", "T", "A", "gated"):
         err[k] = abs(gsc[k] - tot[k]) / (m * pm.W1)
     err["steps"] = abs(gsc["steps"] - tot["steps"]) / tot["steps"]
     return {"photons": m, "relative_error": err, "oracle_s": t_cpu,
@@ -232,6 +238,49 @@ def rows_leg(args, seed, field):
         log(f"{name}: {t * 1e3:.1f} ms, {steps / t:.3e} steps/s")
         rows[name] = row
     return rows
+
+
+def paper_leg(args, seed, mask_np, mask):
+    """The paper's own boundary model (one-voxel air pads, lateral mirrors, solid index
+    n_eff = 1.746 with Fresnel reflection and refraction, gate of Eq. tend) on the plain
+    workload's 256^3 phi = 0.70 mask: with the paper's shell optics per 1.45 um voxel
+    (mu_s = 20118 1/m, mu_a = 5159 1/m, g = 0), and with the plain workload's optics."""
+    import numpy as np
+    import torch
+
+    from paper_2604_13929_amd import inputs
+    from paper_2604_13929_amd import photonmc as pm
+
+    def f32(x):
+        return float(np.float32(x))
+
+    a_vox, nz, phi = 1.45e-6, mask_np.shape[0], float(mask_np.mean())
+    n = args.photons
+    shell = dict(mu_s=f32(20118.0 * a_vox), mu_a=f32(5159.0 * a_vox), g=0.0)
+    plain = dict(inputs.SOLID_OPTICS)
+    out = {}
+    for name, o in (("paper_optics", shell), ("plain_optics", plain)):
+        gate = pm.time_gate_voxels(o["mu_s"], o["mu_a"], o["g"], phi, nz, 1.746)
+        opt = pm.paper_optics(o["mu_s"], o["mu_a"], o["g"], n_solid=f32(1.746), lateral=pm.LATERAL_MIRROR,
+                              gate=gate)
+        pm.run(mask, opt, 1 << 20, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pm.run(mask, opt, n, seed, timed=True)
+        s = pm.reduce(mask, r)
+        t = time.perf_counter() - t0
+        steps = s["steps_per_photon"] * n
+        row = {"optics": {**o, "n_solid": 1.746, "lateral": "mirror", "gate_voxels": gate, "air_pads": 1},
+               "photons": n, "ms": t * 1e3, "walk_ms": r.walk_ms, "photon_steps_per_s": steps / t,
+               "photons_per_s": n / t, "R": s["R"], "T": s["T"], "A": s["A"], "gated": s["gated"],
+               "phi3d": s["phi3d"], "phi1d": s["phi1d"], "r": s["r"], "ratio": s["ratio"],
+               "steps_per_photon": s["steps_per_photon"], "closure_exact": s["closure_exact"]}
+        if not args.no_cpu:
+            row["oracle"] = oracle_check(mask_np, mask, opt, 100_000, seed, len(os.sched_getaffinity(0)))
+        log(f"paper model, {name}: {t * 1e3:.0f} ms, {steps / t:.3e} steps/s, r {s['r']:.4f}")
+        out[name] = row
+    return {"workload": "256^3 Cahn-wave mask phi=0.70 (lambda 24), air pads, lateral mirrors, n_solid 1.746 "
+                        "(Fresnel), gate of Eq. tend, 1e8 photons", **out}
 
 
 def grad_oracle_check(seed, n=100_000, B=32):
@@ -326,6 +375,7 @@ def main():
     ap.add_argument("--no-morph", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="skip the 32^3 and phi = 0.90 rows")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper boundary model rows")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
@@ -457,6 +507,8 @@ def main():
     if not args.no_rows:
         line["rows"] = rows_leg(args, seed, field)
     del field
+    if not args.no_paper:
+        line["paper_boundary"] = paper_leg(args, seed, mask_np, mask)
     if not args.no_batch:
         line["batched"] = batched_leg(args, seed)
     if not args.no_morph:

@@ -347,10 +347,10 @@ static int step(const orc_problem *P, uint64_t photon, orc_state *st, orc_sink *
     /* time gate: the optical path may reach, not pass, the gate */
     int gated = 0;
     if (paper && isfinite(P->gate)) {
-        const double t_left = (P->gate - st->l_opt) / n_here;
-        const double gg = fabs(d - t_left);
+        const double gg = fabs(st->l_opt + n_here * d - P->gate) / n_here;
         if (gg < gap) gap = gg;
-        if (d > t_left) {
+        if (st->l_opt + n_here * d > P->gate) {
+            const double t_left = (P->gate - st->l_opt) / n_here;
             gated = 1;
             interact = 0;
             d = t_left > 0.0 ? t_left : 0.0;

@@ -94,7 +94,7 @@ struct Photon {
     uint64_t bits;            // cached brick
     double l_opt;             // optical path sum(n d), pads included (paper model's gate)
     uint32_t nf;              // Fresnel decisions drawn so far
-    U4 fr;                    // current block of the Fresnel stream
+    U4 fr;                    // words of the current Fresnel block not drawn yet, next in fr.x
 };
 
 // precision-generic helpers
@@ -270,13 +270,18 @@ __device__ __forceinline__ R fresnel(R n1, R n2, R ci, R *ct)
 }
 
 // Uniform of the photon's next Fresnel decision: word j & 3 of block j >> 2 of
-// its tag-4 Philox stream, a block drawn once per four decisions.
+// its tag-4 Philox stream, a block drawn once per four decisions.  The unused
+// words wait in p.fr and move down one place per draw (a variable word index
+// would force the photon state out of registers).
 template <typename R>
 __device__ __forceinline__ R fresnel_uniform(Photon<R> &p, const Job &J)
 {
     const uint32_t j = p.nf++;
     if ((j & 3u) == 0u) p.fr = philox4x32_10(U4{j >> 2, p.pid, J.stream_id, 4u}, J.key0, J.key1);
-    const uint32_t w = (j & 2u) ? ((j & 1u) ? p.fr.w : p.fr.z) : ((j & 1u) ? p.fr.y : p.fr.x);
+    const uint32_t w = p.fr.x;
+    p.fr.x = p.fr.y;
+    p.fr.y = p.fr.z;
+    p.fr.z = p.fr.w;
     return u01<R>(w);
 }
 
@@ -293,8 +298,9 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
     const R dz = p.uz != (R)0 ? (p.uz > (R)0 ? (R)1 - p.fz : p.fz) * inv_abs(p.uz) : r_inf<R>();
     int32_t axis = 0;
     R d_face = dx;
-    if (dy < d_face) { axis = 1; d_face = dy; }
-    if (dz < d_face) { axis = 2; d_face = dz; }
+    R ua = p.ux;              // direction component normal to the face reached
+    if (dy < d_face) { axis = 1; d_face = dy; ua = p.uy; }
+    if (dz < d_face) { axis = 2; d_face = dz; ua = p.uz; }
     const bool solid = p.solid != 0u;
     bool interact = solid && (p.s_rem <= (double)d_face);
     R d = interact ? (R)p.s_rem : d_face;
@@ -304,11 +310,10 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
         in_slab = p.iz >= 0 && p.iz < J.nz;
         n_here = solid ? (double)J.n_solid : 1.0;
         // the optical path may reach the gate, not pass it
-        const double t_left = (J.gate - p.l_opt) / n_here;
-        if ((double)d > t_left) {
+        if (p.l_opt + n_here * (double)d > J.gate) {
             gated = true;
             interact = false;
-            d = (R)fmax(t_left, 0.0);
+            d = (R)fmax((J.gate - p.l_opt) / n_here, 0.0);
         }
     }
 
@@ -380,7 +385,6 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
         if (axis != 0) p.fx = clamp01(p.fx + p.ux * d);
         if (axis != 1) p.fy = clamp01(p.fy + p.uy * d);
         if (axis != 2) p.fz = clamp01(p.fz + p.uz * d);
-        const R ua = axis == 0 ? p.ux : (axis == 1 ? p.uy : p.uz);
         const int32_t sgn = ua > (R)0 ? 1 : -1;
         int32_t jx = p.ix, jy = p.iy, jz = p.iz;
         bool reflect = false, out = false;
@@ -422,11 +426,18 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
                 p.uz = axis == 2 ? (R)sgn * ct : eta * p.uz;
             }
         }
+        // Every component is written with a value select: stores chosen by axis would
+        // be merged into one store through a selected address, which keeps the photon
+        // state in memory.
         if (reflect) {
             // stay in this voxel on the face, normal component reversed
-            if (axis == 0) { p.ux = -p.ux; p.fx = sgn > 0 ? (R)1 : (R)0; }
-            else if (axis == 1) { p.uy = -p.uy; p.fy = sgn > 0 ? (R)1 : (R)0; }
-            else { p.uz = -p.uz; p.fz = sgn > 0 ? (R)1 : (R)0; }
+            const R face = sgn > 0 ? (R)1 : (R)0;
+            p.ux = axis == 0 ? -p.ux : p.ux;
+            p.uy = axis == 1 ? -p.uy : p.uy;
+            p.uz = axis == 2 ? -p.uz : p.uz;
+            p.fx = axis == 0 ? face : p.fx;
+            p.fy = axis == 1 ? face : p.fy;
+            p.fz = axis == 2 ? face : p.fz;
             ev = EV_REFLECT_X + axis;
         } else {
             if (in_slab) sink.flush(J, p, p.acc);
@@ -434,10 +445,11 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
             if (out) {
                 ev = jz < 0 ? EV_ESC_R : EV_ESC_T;
             } else {
+                const R face = sgn > 0 ? (R)0 : (R)1;
                 p.ix = jx; p.iy = jy; p.iz = jz;
-                if (axis == 0) p.fx = sgn > 0 ? (R)0 : (R)1;
-                else if (axis == 1) p.fy = sgn > 0 ? (R)0 : (R)1;
-                else p.fz = sgn > 0 ? (R)0 : (R)1;
+                p.fx = axis == 0 ? face : p.fx;
+                p.fy = axis == 1 ? face : p.fy;
+                p.fz = axis == 2 ? face : p.fz;
                 if (jz >= 0 && jz < J.nz) {
                     p.brick = nb;
                     p.bits = nbits;
