@@ -21,6 +21,7 @@
 #include <mutex>
 
 #include "internal.hpp"
+#include "spinodal.h"
 
 using namespace pmc;
 
@@ -917,6 +918,7 @@ size_t mc_sizeof(const char *type_name)
     if (!type_name) return 0;
     if (!strcmp(type_name, "mc_volume")) return sizeof(mc_volume);
     if (!strcmp(type_name, "mc_optics")) return sizeof(mc_optics);
+    if (!strcmp(type_name, "mc_ch_grid")) return sizeof(mc_ch_grid);
     if (!strcmp(type_name, "mc_tune")) return sizeof(mc_tune);
     if (!strcmp(type_name, "mc_trace_rec")) return sizeof(mc_trace_rec);
     if (!strcmp(type_name, "mc_photon_rec")) return sizeof(mc_photon_rec);

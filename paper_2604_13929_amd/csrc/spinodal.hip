@@ -1,0 +1,880 @@
+// spinodal.hip -- Cahn-Hilliard spinodal mask generator (Sec. 2.3, Eq. CH,
+// Eq. CH_spectral; App. A): the semi-implicit Fourier spectral step in FP64,
+// the radial power spectral density of the stopping rule, and the exact rank
+// binarisation.
+//
+// Design (gfx950): the spectrum lives in HBM as complex double [nz][ny][nx/2+1].
+// Every transform is a Stockham FFT (radices 2, 3, 4) over whole lines held in
+// LDS, 4096 complex values per 256-thread workgroup, so one line is read and
+// written once per pass.  One time step is four in-place passes over the
+// spectrum-sized work array W, with the state S touched only in the z pass:
+//   y pass   W <- inverse FFT_y(W)
+//   x pass   W <- FFT_x(f'(inverse FFT_x(W)))       (real field only in LDS)
+//   y pass   W <- FFT_y(W)
+//   z pass   S <- (S - dt k^2 FFT_z(W)) / (1 + dt kappa k^4);  W <- inverse FFT_z(S)
+// i.e. ten spectrum-sized transfers per step instead of the fifteen of two
+// separate 3-D transforms and an update.  Columns along y and z are read as
+// tiles of consecutive kx (contiguous in memory) and transformed as lines in LDS.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "internal.hpp"
+#include "spinodal.h"
+
+using namespace pmc::host;
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kLdsElems = 4096;           // complex doubles per workgroup (64 KiB)
+constexpr int kMaxStages = 12;
+constexpr int kMaxN = 1024;
+
+struct Plan {
+    int32_t n;
+    int32_t nstages;
+    int32_t radix[kMaxStages];
+};
+
+// radix-3 stages first, then radix 4, then one radix 2 if the power of two is odd
+bool make_plan(int n, Plan *p)
+{
+    memset(p, 0, sizeof *p);
+    p->n = n;
+    int m = n, threes = 0, twos = 0;
+    while (m % 3 == 0) { m /= 3; ++threes; }
+    while (m % 2 == 0) { m /= 2; ++twos; }
+    if (m != 1) return false;
+    int s = 0;
+    for (int i = 0; i < threes; ++i) p->radix[s++] = 3;
+    for (int i = 0; i < twos / 2; ++i) p->radix[s++] = 4;
+    if (twos % 2) p->radix[s++] = 2;
+    p->nstages = s;
+    return s <= kMaxStages;
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Small DFTs, forward (sign -1) or inverse (sign +1).
+template <int R> __device__ __forceinline__ void dft(double2 *v, bool inv);
+
+template <> __device__ __forceinline__ void dft<2>(double2 *v, bool)
+{
+    const double2 a = v[0], b = v[1];
+    v[0] = make_double2(a.x + b.x, a.y + b.y);
+    v[1] = make_double2(a.x - b.x, a.y - b.y);
+}
+
+template <> __device__ __forceinline__ void dft<4>(double2 *v, bool inv)
+{
+    const double2 s02 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+    const double2 d02 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+    const double2 s13 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+    const double2 d13 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+    // forward: -i d13; inverse: +i d13
+    const double2 r = inv ? make_double2(-d13.y, d13.x) : make_double2(d13.y, -d13.x);
+    v[0] = make_double2(s02.x + s13.x, s02.y + s13.y);
+    v[2] = make_double2(s02.x - s13.x, s02.y - s13.y);
+    v[1] = make_double2(d02.x + r.x, d02.y + r.y);
+    v[3] = make_double2(d02.x - r.x, d02.y - r.y);
+}
+
+template <> __device__ __forceinline__ void dft<3>(double2 *v, bool inv)
+{
+    constexpr double kS = 0.86602540378443864676;  // sqrt(3)/2
+    const double2 t = make_double2(v[1].x + v[2].x, v[1].y + v[2].y);
+    const double2 u = make_double2(v[1].x - v[2].x, v[1].y - v[2].y);
+    const double2 m = make_double2(v[0].x - 0.5 * t.x, v[0].y - 0.5 * t.y);
+    // forward: y1 = m - i s u, y2 = m + i s u; inverse swaps them
+    const double2 isu = make_double2(-kS * u.y, kS * u.x);
+    v[0] = make_double2(v[0].x + t.x, v[0].y + t.y);
+    if (!inv) {
+        v[1] = make_double2(m.x - isu.x, m.y - isu.y);
+        v[2] = make_double2(m.x + isu.x, m.y + isu.y);
+    } else {
+        v[1] = make_double2(m.x + isu.x, m.y + isu.y);
+        v[2] = make_double2(m.x - isu.x, m.y - isu.y);
+    }
+}
+
+// One Stockham stage of radix R over `nlines` lines of length n in LDS (line l
+// at buf + l * ls): butterfly j of a line reads elements j + r n/R, twiddles
+// them by w^(r (j mod ns)) with w = exp(-+ 2 pi i / (ns R)), transforms, and
+// writes them to (j / ns) ns R + (j mod ns) + r ns.  Values wait in registers
+// between the read and the write barrier, so one LDS buffer suffices.
+template <int R>
+__device__ __forceinline__ void stage(double2 *buf, int n, int ns, int nlines, int ls, bool inv, const double2 *tw)
+{
+    constexpr int kPer = (kLdsElems / R + kThreads - 1) / kThreads;
+    const int nb = n / R;
+    const int total = nlines * nb;
+    const int tstep = n / (ns * R);
+    double2 v[kPer][R];
+    int dst[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int b = (int)threadIdx.x + q * kThreads;
+        dst[q] = -1;
+        if (b < total) {
+            const int line = b / nb, j = b - line * nb;
+            const int jm = j % ns;
+            const double2 *src = buf + line * ls;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double2 x = src[j + r * nb];
+                if (r) {
+                    double2 w = tw[jm * r * tstep];
+                    if (inv) w.y = -w.y;
+                    x = cmul(x, w);
+                }
+                v[q][r] = x;
+            }
+            dft<R>(v[q], inv);
+            dst[q] = line * ls + (j - jm) * R + jm;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        if (dst[q] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[dst[q] + r * ns] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Unnormalised FFT of every line (forward: exp(-2 pi i j k / n)).
+__device__ void fft_lines(double2 *buf, int ls, int nlines, const Plan &P, const double2 *tw, bool inv)
+{
+    int ns = 1;
+    for (int s = 0; s < P.nstages; ++s) {
+        const int R = P.radix[s];
+        if (R == 4) stage<4>(buf, P.n, ns, nlines, ls, inv, tw);
+        else if (R == 2) stage<2>(buf, P.n, ns, nlines, ls, inv, tw);
+        else stage<3>(buf, P.n, ns, nlines, ls, inv, tw);
+        ns *= R;
+    }
+}
+
+// Tables: forward twiddles exp(-2 pi i m / n) and k^2 = (2 pi m' / n)^2 with m'
+// the signed frequency of index m (the rfft axis x keeps m' = m).
+__global__ void k_tables(double2 *tw, double *k2, int n, int half)
+{
+    const int m = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (m < n) {
+        double s, c;
+        sincospi(2.0 * (double)m / (double)n, &s, &c);
+        tw[m] = make_double2(c, -s);
+    }
+    const int nk = half ? n / 2 + 1 : n;
+    if (m < nk) {
+        const int ms = (!half && m >= (n + 1) / 2) ? m - n : m;
+        const double k = (2.0 * M_PI) * ((double)ms * (1.0 / (double)n));
+        k2[m] = k * k;
+    }
+}
+
+enum { X_INIT = 0, X_NONLIN = 1, X_FIELD = 2 };
+
+// Lines along x.  X_INIT: real line -> forward transform, half spectrum out.
+// X_NONLIN: half spectrum -> inverse -> f'(phi) -> forward -> half spectrum.
+// X_FIELD: half spectrum -> inverse -> real line out.  `scale` = 1/(nx ny nz).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_xpass(const double *__restrict__ rin, double2 *spec,
+                                                     double *__restrict__ rout, int nx, int nlines_total, int L,
+                                                     Plan P, const double2 *__restrict__ tw, double scale)
+{
+    __shared__ double2 buf[kLdsElems];
+    const int hx = nx / 2 + 1, ls = nx + 1;
+    const int line0 = (int)blockIdx.x * L;
+    const int nl = min(L, nlines_total - line0);
+    const int tid = (int)threadIdx.x;
+    if (MODE == X_INIT) {
+        for (int e = tid; e < nl * nx; e += kThreads) {
+            const int l = e / nx, x = e - l * nx;
+            buf[l * ls + x] = make_double2(rin[(size_t)(line0 + l) * nx + x], 0.0);
+        }
+        __syncthreads();
+    } else {
+        for (int e = tid; e < nl * hx; e += kThreads) {
+            const int l = e / hx, x = e - l * hx;
+            buf[l * ls + x] = spec[(size_t)(line0 + l) * hx + x];
+        }
+        __syncthreads();
+        // Hermitian extension: X[n - j] = conj(X[j]); the real part of the complex
+        // inverse then ignores the imaginary parts of the 0 and n/2 bins, as a
+        // real inverse transform does
+        const int ne = nx / 2 - 1;
+        for (int e = tid; e < nl * ne; e += kThreads) {
+            const int l = e / ne, j = 1 + (e - l * ne);
+            const double2 v = buf[l * ls + j];
+            buf[l * ls + nx - j] = make_double2(v.x, -v.y);
+        }
+        __syncthreads();
+        fft_lines(buf, ls, nl, P, tw, true);
+        if (MODE == X_FIELD) {
+            for (int e = tid; e < nl * nx; e += kThreads) {
+                const int l = e / nx, x = e - l * nx;
+                rout[(size_t)(line0 + l) * nx + x] = buf[l * ls + x].x * scale;
+            }
+            return;
+        }
+        for (int e = tid; e < nl * nx; e += kThreads) {
+            const int l = e / nx, x = e - l * nx;
+            const double phi = buf[l * ls + x].x * scale;
+            buf[l * ls + x] = make_double2(2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi), 0.0);
+        }
+        __syncthreads();
+    }
+    fft_lines(buf, ls, nl, P, tw, false);
+    for (int e = tid; e < nl * hx; e += kThreads) {
+        const int l = e / hx, x = e - l * hx;
+        spec[(size_t)(line0 + l) * hx + x] = buf[l * ls + x];
+    }
+}
+
+// Column addressing: element j of column (plane p, kx = x0 + c).  Along y the
+// plane is z; along z the plane is y.
+template <int AXIS>
+__device__ __forceinline__ size_t col_addr(int j, int p, int x, int ny, int hx)
+{
+    return AXIS == 1 ? ((size_t)p * ny + j) * hx + x : ((size_t)j * ny + p) * hx + x;
+}
+
+// In-place FFT along y (AXIS 1) or z (AXIS 2) of T-column tiles.
+template <int AXIS>
+__global__ __launch_bounds__(kThreads) void k_colpass(double2 *A, int ny, int hx, int n, int T, int tiles, Plan P,
+                                                       const double2 *__restrict__ tw, int inv)
+{
+    __shared__ double2 buf[kLdsElems];
+    const int p = (int)blockIdx.x / tiles, tile = (int)blockIdx.x - p * tiles;
+    const int x0 = tile * T, nc = min(T, hx - x0), ls = n + 1;
+    const int tid = (int)threadIdx.x;
+    for (int e = tid; e < n * nc; e += kThreads) {
+        const int j = e / nc, c = e - j * nc;
+        buf[c * ls + j] = A[col_addr<AXIS>(j, p, x0 + c, ny, hx)];
+    }
+    __syncthreads();
+    fft_lines(buf, ls, nc, P, tw, inv != 0);
+    for (int e = tid; e < n * nc; e += kThreads) {
+        const int j = e / nc, c = e - j * nc;
+        A[col_addr<AXIS>(j, p, x0 + c, ny, hx)] = buf[c * ls + j];
+    }
+}
+
+enum { Z_INV = 0, Z_INIT = 1, Z_UPDATE = 2 };
+
+// The z pass.  Z_INV: W = inverse FFT_z(S).  Z_INIT: S = FFT_z(W).  Z_UPDATE:
+// S = (S - dt k^2 FFT_z(W)) / (1 + dt kappa k^4) (Eq. CH_spectral, evaluated in
+// that order).  With write_w (Z_INIT, Z_UPDATE) W = inverse FFT_z(S) as well, the
+// start of the next step.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_zpass(double2 *S, double2 *W, int ny, int hx, int nz, int T, int tiles,
+                                                     Plan P, const double2 *__restrict__ tw,
+                                                     const double *__restrict__ kx2, const double *__restrict__ ky2,
+                                                     const double *__restrict__ kz2, double dt, double kappa,
+                                                     int write_w)
+{
+    __shared__ double2 buf[kLdsElems];
+    const int y = (int)blockIdx.x / tiles, tile = (int)blockIdx.x - y * tiles;
+    const int x0 = tile * T, nc = min(T, hx - x0), ls = nz + 1;
+    const int tid = (int)threadIdx.x;
+    const double2 *src = MODE == Z_INV ? S : W;
+    for (int e = tid; e < nz * nc; e += kThreads) {
+        const int j = e / nc, c = e - j * nc;
+        buf[c * ls + j] = src[col_addr<2>(j, y, x0 + c, ny, hx)];
+    }
+    __syncthreads();
+    if (MODE != Z_INV) {
+        fft_lines(buf, ls, nc, P, tw, false);
+        const double dtk = dt * kappa;
+        for (int e = tid; e < nz * nc; e += kThreads) {
+            const int j = e / nc, c = e - j * nc;
+            const size_t a = col_addr<2>(j, y, x0 + c, ny, hx);
+            double2 v = buf[c * ls + j];
+            if (MODE == Z_UPDATE) {
+                const double k2 = kz2[j] + ky2[y] + kx2[x0 + c];
+                const double den = 1.0 + dtk * k2 * k2;
+                const double g = dt * k2;
+                const double2 s = S[a];
+                v = make_double2((s.x - g * v.x) / den, (s.y - g * v.y) / den);
+            }
+            S[a] = v;
+            buf[c * ls + j] = v;
+        }
+        __syncthreads();
+        if (!write_w) return;
+    }
+    fft_lines(buf, ls, nc, P, tw, true);
+    for (int e = tid; e < nz * nc; e += kThreads) {
+        const int j = e / nc, c = e - j * nc;
+        W[col_addr<2>(j, y, x0 + c, ny, hx)] = buf[c * ls + j];
+    }
+}
+
+// Radial PSD: per-block partial shell sums in LDS, then a fixed-order sum over
+// the blocks.
+constexpr int kPsdBlocks = 512;
+
+__global__ __launch_bounds__(kThreads) void k_psd_partial(const double2 *__restrict__ S, int nx, int ny, int nz,
+                                                          const double *__restrict__ kx2,
+                                                          const double *__restrict__ ky2,
+                                                          const double *__restrict__ kz2, double *partial, int nb)
+{
+    __shared__ double bins[kMaxN / 2 + 1];
+    for (int i = (int)threadIdx.x; i < nb; i += kThreads) bins[i] = 0.0;
+    __syncthreads();
+    const int hx = nx / 2 + 1;
+    const int nmax = max(nx, max(ny, nz));
+    const size_t total = (size_t)nz * ny * hx;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < total; i += (size_t)gridDim.x * kThreads) {
+        const int x = (int)(i % hx);
+        const size_t r = i / hx;
+        const int y = (int)(r % ny), z = (int)(r / ny);
+        if (i == 0) continue;
+        const double k2 = kz2[z] + ky2[y] + kx2[x];
+        const int s = (int)floor(sqrt(k2) * (double)nmax / (2.0 * M_PI) + 0.5);
+        if (s >= nb) continue;
+        const double2 v = S[i];
+        const double w = (x == 0 || 2 * x == nx) ? 1.0 : 2.0;
+        atomicAdd(&bins[s], (v.x * v.x + v.y * v.y) * w);
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < nb; i += kThreads) partial[(size_t)blockIdx.x * nb + i] = bins[i];
+}
+
+__global__ void k_psd_sum(const double *__restrict__ partial, int nblocks, int nb, double *psd)
+{
+    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= nb) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblocks; ++b) acc += partial[(size_t)b * nb + s];
+    psd[s] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Rank binarisation: an MSB-first radix select of the n_pore-th largest key
+// (11-bit digits, six passes), then the equal keys taken in index order.
+// ---------------------------------------------------------------------------
+constexpr int kDigitBits = 11;
+constexpr int kDigits = 1 << kDigitBits;
+constexpr int kChunk = kThreads * 16;      // elements per marking block
+
+struct SelectState {
+    unsigned long long prefix;   // key bits chosen so far
+    long long k;                 // rank still to find inside the current candidates (1-based, from the top)
+    long long pad[6];
+};
+
+// order-preserving map of a double to uint64 (-0.0 and +0.0 map alike)
+__device__ __forceinline__ unsigned long long key_of(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v + 0.0);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__global__ __launch_bounds__(kThreads) void k_hist(const double *__restrict__ f, long long n,
+                                                   const SelectState *st, unsigned long long *hist, int shift,
+                                                   int bits)
+{
+    __shared__ unsigned int h[kDigits];
+    for (int i = (int)threadIdx.x; i < kDigits; i += kThreads) h[i] = 0u;
+    __syncthreads();
+    const int top = shift + bits;
+    const unsigned long long hi_mask = top >= 64 ? 0ull : (~0ull << top);
+    const unsigned long long prefix = st->prefix;
+    const unsigned long long dmask = (1ull << bits) - 1ull;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+        const unsigned long long key = key_of(f[i]);
+        if ((key & hi_mask) == prefix) atomicAdd(&h[(key >> shift) & dmask], 1u);
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < (1 << bits); i += kThreads)
+        if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
+}
+
+__global__ void k_select(SelectState *st, unsigned long long *hist, int shift, int bits)
+{
+    if (threadIdx.x == 0) {
+        long long k = st->k, above = 0;
+        int d = (1 << bits) - 1;
+        for (; d > 0; --d) {
+            if (above + (long long)hist[d] >= k) break;
+            above += (long long)hist[d];
+        }
+        st->k = k - above;
+        st->prefix |= (unsigned long long)d << shift;
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < kDigits; i += (int)blockDim.x) hist[i] = 0ull;
+}
+
+__global__ __launch_bounds__(kThreads) void k_count_eq(const double *__restrict__ f, long long n,
+                                                       const SelectState *st, long long *counts)
+{
+    __shared__ int wsum[kThreads / 64];
+    const unsigned long long T = st->prefix;
+    const long long base = (long long)blockIdx.x * kChunk;
+    int c = 0;
+    for (int it = 0; it < kChunk / kThreads; ++it) {
+        const long long i = base + it * kThreads + threadIdx.x;
+        if (i < n && key_of(f[i]) == T) ++c;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int w = 0; w < kThreads / 64; ++w) t += wsum[w];
+        counts[blockIdx.x] = t;
+    }
+}
+
+// exclusive scan of the per-chunk counts, one workgroup: each thread scans a
+// contiguous segment
+__global__ __launch_bounds__(kThreads) void k_scan(long long *counts, int nchunks)
+{
+    __shared__ long long seg[kThreads];
+    const int per = (nchunks + kThreads - 1) / kThreads;
+    const int b0 = (int)threadIdx.x * per, b1 = min(nchunks, b0 + per);
+    long long s = 0;
+    for (int b = b0; b < b1; ++b) s += counts[b];
+    seg[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long run = 0;
+        for (int t = 0; t < kThreads; ++t) {
+            const long long v = seg[t];
+            seg[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    long long run = seg[threadIdx.x];
+    for (int b = b0; b < b1; ++b) {
+        const long long v = counts[b];
+        counts[b] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_mark(const double *__restrict__ f, long long n, const SelectState *st,
+                                                   const long long *__restrict__ offsets, uint8_t *mask)
+{
+    __shared__ int wcount[kThreads / 64];
+    const unsigned long long T = st->prefix;
+    const long long need = st->k;
+    const long long base = (long long)blockIdx.x * kChunk;
+    long long run = offsets[blockIdx.x];
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    for (int it = 0; it < kChunk / kThreads; ++it) {
+        const long long i = base + it * kThreads + threadIdx.x;
+        unsigned long long key = 0ull;
+        if (i < n) key = key_of(f[i]);
+        const bool eq = i < n && key == T;
+        const unsigned long long bal = __ballot(eq);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wcount[wave] = __popcll(bal);
+        __syncthreads();
+        int woff = 0;
+        for (int w = 0; w < wave; ++w) woff += wcount[w];
+        int tot = 0;
+        for (int w = 0; w < kThreads / 64; ++w) tot += wcount[w];
+        if (i < n) mask[i] = (uint8_t)(key > T || (eq && run + woff + before < need));
+        run += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill_u8(uint8_t *p, long long n, uint8_t v)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_init_state(SelectState *st, unsigned long long *hist, long long k)
+{
+    if (threadIdx.x == 0) {
+        st->prefix = 0ull;
+        st->k = k;
+    }
+    for (int i = (int)threadIdx.x; i < kDigits; i += (int)blockDim.x) hist[i] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Geo {
+    int nx, ny, nz, hx;
+    size_t spec_elems;      // nz * ny * hx
+    Plan px, py, pz;
+    int Lx;                 // x lines per workgroup
+    int Ty, Tz, tiles_y, tiles_z;
+    // workspace offsets (bytes)
+    size_t w_off, twx, twy, twz, kx2, ky2, kz2, psd_off, total;
+};
+
+int geometry(const mc_ch_grid *g, Geo *G)
+{
+    if (!g) return fail(MC_EINVAL, "grid is NULL");
+    if (g->reserved != 0) return fail(MC_EINVAL, "mc_ch_grid.reserved must be 0");
+    if (g->nx < 2 || g->nx > kMaxN || (g->nx & 1)) return fail(MC_EINVAL, "nx must be even, 2..%d", kMaxN);
+    if (g->ny < 1 || g->ny > kMaxN || g->nz < 1 || g->nz > kMaxN) return fail(MC_EINVAL, "ny, nz must be 1..%d", kMaxN);
+    if ((long long)g->nx * g->ny * g->nz >= (1ll << 31)) return fail(MC_EINVAL, "nx*ny*nz must be < 2^31");
+    if (!(g->kappa > 0.0) || !isfinite(g->kappa) || !(g->dt > 0.0) || !isfinite(g->dt))
+        return fail(MC_EINVAL, "kappa and dt must be finite and > 0");
+    memset(G, 0, sizeof *G);
+    G->nx = g->nx;
+    G->ny = g->ny;
+    G->nz = g->nz;
+    G->hx = g->nx / 2 + 1;
+    if (!make_plan(g->nx, &G->px) || !make_plan(g->ny, &G->py) || !make_plan(g->nz, &G->pz))
+        return fail(MC_EINVAL, "every extent must be a product of powers of 2 and 3");
+    G->spec_elems = (size_t)G->nz * G->ny * G->hx;
+    G->Lx = std::max(1, kLdsElems / (G->nx + 1));
+    G->Ty = std::max(1, kLdsElems / (G->ny + 1));
+    G->Tz = std::max(1, kLdsElems / (G->nz + 1));
+    G->tiles_y = (G->hx + G->Ty - 1) / G->Ty;
+    G->tiles_z = (G->hx + G->Tz - 1) / G->Tz;
+    size_t off = 0;
+    G->w_off = off;
+    off += align_up(G->spec_elems * sizeof(double2));
+    G->twx = off;
+    off += align_up(sizeof(double2) * G->nx);
+    G->twy = off;
+    off += align_up(sizeof(double2) * G->ny);
+    G->twz = off;
+    off += align_up(sizeof(double2) * G->nz);
+    G->kx2 = off;
+    off += align_up(sizeof(double) * G->hx);
+    G->ky2 = off;
+    off += align_up(sizeof(double) * G->ny);
+    G->kz2 = off;
+    off += align_up(sizeof(double) * G->nz);
+    G->psd_off = off;
+    off += align_up(sizeof(double) * kPsdBlocks * (kMaxN / 2 + 1));
+    G->total = off;
+    return MC_OK;
+}
+
+struct Ptrs {
+    double2 *W;
+    double2 *twx, *twy, *twz;
+    double *kx2, *ky2, *kz2;
+    double *psd_partial;
+};
+
+Ptrs pointers(const Geo &G, void *ws)
+{
+    char *b = (char *)ws;
+    Ptrs p;
+    p.W = (double2 *)(b + G.w_off);
+    p.twx = (double2 *)(b + G.twx);
+    p.twy = (double2 *)(b + G.twy);
+    p.twz = (double2 *)(b + G.twz);
+    p.kx2 = (double *)(b + G.kx2);
+    p.ky2 = (double *)(b + G.ky2);
+    p.kz2 = (double *)(b + G.kz2);
+    p.psd_partial = (double *)(b + G.psd_off);
+    return p;
+}
+
+int prepare(const mc_ch_grid *g, void *ws, size_t ws_bytes, hipStream_t s, Geo *G, Ptrs *P)
+{
+    int rc = geometry(g, G);
+    if (rc) return rc;
+    if (!ws) return fail(MC_EINVAL, "workspace is NULL");
+    if (ws_bytes < G->total) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, G->total);
+    *P = pointers(*G, ws);
+    hipLaunchKernelGGL(k_tables, dim3((G->nx + 255) / 256), dim3(256), 0, s, P->twx, P->kx2, G->nx, 1);
+    hipLaunchKernelGGL(k_tables, dim3((G->ny + 255) / 256), dim3(256), 0, s, P->twy, P->ky2, G->ny, 0);
+    hipLaunchKernelGGL(k_tables, dim3((G->nz + 255) / 256), dim3(256), 0, s, P->twz, P->kz2, G->nz, 0);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+void enqueue_col(const Geo &G, int axis, double2 *A, const Ptrs &P, bool inv, hipStream_t s)
+{
+    if (axis == 1) {
+        if (G.ny == 1) return;
+        hipLaunchKernelGGL(k_colpass<1>, dim3((unsigned)(G.nz * G.tiles_y)), dim3(kThreads), 0, s, A, G.ny, G.hx,
+                           G.ny, G.Ty, G.tiles_y, G.py, P.twy, inv ? 1 : 0);
+    } else {
+        if (G.nz == 1) return;
+        hipLaunchKernelGGL(k_colpass<2>, dim3((unsigned)(G.ny * G.tiles_z)), dim3(kThreads), 0, s, A, G.ny, G.hx,
+                           G.nz, G.Tz, G.tiles_z, G.pz, P.twz, inv ? 1 : 0);
+    }
+}
+
+template <int MODE>
+void enqueue_x(const Geo &G, const double *rin, double2 *spec, double *rout, const Ptrs &P, hipStream_t s)
+{
+    const int lines = G.nz * G.ny;
+    const double scale = 1.0 / ((double)G.nx * (double)G.ny * (double)G.nz);
+    hipLaunchKernelGGL(k_xpass<MODE>, dim3((unsigned)((lines + G.Lx - 1) / G.Lx)), dim3(kThreads), 0, s, rin, spec,
+                       rout, G.nx, lines, G.Lx, G.px, P.twx, scale);
+}
+
+template <int MODE>
+void enqueue_z(const Geo &G, double2 *S, const Ptrs &P, double dt, double kappa, bool write_w, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zpass<MODE>, dim3((unsigned)(G.ny * G.tiles_z)), dim3(kThreads), 0, s, S, P.W, G.ny, G.hx,
+                       G.nz, G.Tz, G.tiles_z, G.pz, P.twz, P.kx2, P.ky2, P.kz2, dt, kappa, write_w ? 1 : 0);
+}
+
+pmc::host::Timing g_ch_timing;
+
+int ch_time(hipStream_t s, bool begin)
+{
+    Timing &t = g_ch_timing;
+    if (!t.start) {
+        HIP_TRY(hipEventCreate(&t.start));
+        HIP_TRY(hipEventCreate(&t.stop));
+    }
+    if (begin) {
+        HIP_TRY(hipEventRecord(t.start, s));
+        t.armed = false;
+    } else {
+        HIP_TRY(hipEventRecord(t.stop, s));
+        t.armed = true;
+    }
+    return MC_OK;
+}
+
+size_t rank_ws_bytes(int64_t n)
+{
+    const size_t nchunks = (size_t)((n + kChunk - 1) / kChunk);
+    return align_up(sizeof(SelectState)) + align_up(sizeof(unsigned long long) * kDigits) +
+           align_up(sizeof(long long) * nchunks);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mc_ch_workspace_bytes(const mc_ch_grid *g)
+{
+    clear_error();
+    Geo G;
+    if (geometry(g, &G)) return 0;
+    return G.total;
+}
+
+int mc_ch_init(const mc_ch_grid *g, const double *phi0, double *state, void *workspace, size_t workspace_bytes,
+               void *hip_stream)
+{
+    clear_error();
+    if (!phi0 || !state) return fail(MC_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Geo G;
+    Ptrs P;
+    int rc = prepare(g, workspace, workspace_bytes, s, &G, &P);
+    if (rc) return rc;
+    enqueue_x<X_INIT>(G, phi0, P.W, nullptr, P, s);
+    enqueue_col(G, 1, P.W, P, false, s);
+    if (G.nz == 1) {
+        HIP_TRY(hipMemcpyAsync(state, P.W, G.spec_elems * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    } else {
+        enqueue_z<Z_INIT>(G, (double2 *)state, P, g->dt, g->kappa, false, s);
+    }
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+int mc_ch_steps(const mc_ch_grid *g, int32_t n_steps, double *state, void *workspace, size_t workspace_bytes,
+                int flags, void *hip_stream)
+{
+    clear_error();
+    if (!state) return fail(MC_EINVAL, "state is NULL");
+    if (n_steps < 0) return fail(MC_EINVAL, "n_steps must be >= 0");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Geo G;
+    Ptrs P;
+    int rc = prepare(g, workspace, workspace_bytes, s, &G, &P);
+    if (rc) return rc;
+    if (G.nz == 1) return fail(MC_EINVAL, "mc_ch_steps needs nz >= 2 (the step is fused with the z transform)");
+    double2 *S = (double2 *)state;
+    const bool timed = (flags & MC_TIMED) != 0;
+    if (timed && (rc = ch_time(s, true))) return rc;
+    if (n_steps > 0) enqueue_z<Z_INV>(G, S, P, g->dt, g->kappa, true, s);
+    for (int32_t i = 0; i < n_steps; ++i) {
+        enqueue_col(G, 1, P.W, P, true, s);
+        enqueue_x<X_NONLIN>(G, nullptr, P.W, nullptr, P, s);
+        enqueue_col(G, 1, P.W, P, false, s);
+        enqueue_z<Z_UPDATE>(G, S, P, g->dt, g->kappa, i + 1 < n_steps, s);
+    }
+    HIP_TRY(hipGetLastError());
+    if (timed && (rc = ch_time(s, false))) return rc;
+    return MC_OK;
+}
+
+int mc_ch_field(const mc_ch_grid *g, const double *state, double *phi, void *workspace, size_t workspace_bytes,
+                void *hip_stream)
+{
+    clear_error();
+    if (!state || !phi) return fail(MC_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Geo G;
+    Ptrs P;
+    int rc = prepare(g, workspace, workspace_bytes, s, &G, &P);
+    if (rc) return rc;
+    if (G.nz == 1) {
+        HIP_TRY(hipMemcpyAsync(P.W, state, G.spec_elems * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    } else {
+        enqueue_z<Z_INV>(G, (double2 *)state, P, g->dt, g->kappa, true, s);
+    }
+    enqueue_col(G, 1, P.W, P, true, s);
+    enqueue_x<X_FIELD>(G, nullptr, P.W, phi, P, s);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+int mc_ch_psd(const mc_ch_grid *g, const double *state, double *psd, void *workspace, size_t workspace_bytes,
+              void *hip_stream)
+{
+    clear_error();
+    if (!state || !psd) return fail(MC_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Geo G;
+    Ptrs P;
+    int rc = prepare(g, workspace, workspace_bytes, s, &G, &P);
+    if (rc) return rc;
+    const int nb = std::max(G.nx, std::max(G.ny, G.nz)) / 2 + 1;
+    hipLaunchKernelGGL(k_psd_partial, dim3(kPsdBlocks), dim3(kThreads), 0, s, (const double2 *)state, G.nx, G.ny, G.nz,
+                       P.kx2, P.ky2, P.kz2, P.psd_partial, nb);
+    hipLaunchKernelGGL(k_psd_sum, dim3((nb + 255) / 256), dim3(256), 0, s, P.psd_partial, kPsdBlocks, nb, psd);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+double mc_ch_elapsed_ms(void)
+{
+    Timing &t = g_ch_timing;
+    if (!t.armed) return -1.0;
+    if (hipEventSynchronize(t.stop) != hipSuccess) return -1.0;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess) return -1.0;
+    return (double)ms;
+}
+
+size_t mc_rank_threshold_workspace_bytes(int64_t n)
+{
+    clear_error();
+    if (n < 1 || n >= (1ll << 40)) return 0;
+    return rank_ws_bytes(n);
+}
+
+int mc_rank_threshold(const double *field, int64_t n, int64_t n_pore, uint8_t *mask, void *workspace,
+                      size_t workspace_bytes, void *hip_stream)
+{
+    clear_error();
+    if (!field || !mask || !workspace) return fail(MC_EINVAL, "NULL argument");
+    if (n < 1 || n >= (1ll << 40)) return fail(MC_EINVAL, "n must be in [1, 2^40)");
+    if (n_pore < 0 || n_pore > n) return fail(MC_EINVAL, "n_pore must be in [0, n]");
+    const size_t need = rank_ws_bytes(n);
+    if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const unsigned grid = (unsigned)std::min<long long>(4096, (n + kThreads - 1) / kThreads);
+    if (n_pore == 0 || n_pore == n) {
+        hipLaunchKernelGGL(k_fill_u8, dim3(grid), dim3(kThreads), 0, s, mask, (long long)n,
+                           (uint8_t)(n_pore == n ? 1 : 0));
+        HIP_TRY(hipGetLastError());
+        return MC_OK;
+    }
+    char *b = (char *)workspace;
+    SelectState *st = (SelectState *)b;
+    unsigned long long *hist = (unsigned long long *)(b + align_up(sizeof(SelectState)));
+    long long *counts = (long long *)(b + align_up(sizeof(SelectState)) + align_up(sizeof(unsigned long long) * kDigits));
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(kThreads), 0, s, st, hist, (long long)n_pore);
+    // digits from the top: bits 63..53, 52..42, 41..31, 30..20, 19..9, 8..0
+    for (int shift = 64 - kDigitBits; shift > -kDigitBits; shift -= kDigitBits) {
+        const int sh = std::max(shift, 0);
+        const int bits = shift >= 0 ? kDigitBits : kDigitBits + shift;
+        hipLaunchKernelGGL(k_hist, dim3(grid), dim3(kThreads), 0, s, field, (long long)n, st, hist, sh, bits);
+        hipLaunchKernelGGL(k_select, dim3(1), dim3(kThreads), 0, s, st, hist, sh, bits);
+    }
+    const long long nchunks = (n + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_count_eq, dim3((unsigned)nchunks), dim3(kThreads), 0, s, field, (long long)n, st, counts);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kThreads), 0, s, counts, (int)nchunks);
+    hipLaunchKernelGGL(k_mark, dim3((unsigned)nchunks), dim3(kThreads), 0, s, field, (long long)n, st, counts, mask);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+size_t mc_ch_generate_workspace_bytes(const mc_ch_grid *g)
+{
+    clear_error();
+    Geo G;
+    if (geometry(g, &G)) return 0;
+    const size_t n = (size_t)G.nx * G.ny * G.nz;
+    return G.total + align_up(n * sizeof(double)) + align_up(sizeof(double) * (kMaxN / 2 + 1)) +
+           rank_ws_bytes((int64_t)n);
+}
+
+int mc_ch_generate(const mc_ch_grid *g, const double *phi0, double d_target, double sigma, int32_t check_every,
+                   int32_t max_steps, double porosity, double *state, double *phi_out, uint8_t *mask,
+                   int32_t *steps_taken, double *last_size, void *workspace, size_t workspace_bytes, void *hip_stream)
+{
+    clear_error();
+    if (!phi0 || !state || !workspace) return fail(MC_EINVAL, "NULL argument");
+    if (check_every < 1 || max_steps < 0) return fail(MC_EINVAL, "check_every must be >= 1 and max_steps >= 0");
+    if (!(porosity >= 0.0 && porosity <= 1.0)) return fail(MC_EINVAL, "porosity must be in [0, 1]");
+    if (!(d_target > 0.0) || !(sigma >= 0.0)) return fail(MC_EINVAL, "d_target must be > 0 and sigma >= 0");
+    Geo G;
+    int rc = geometry(g, &G);
+    if (rc) return rc;
+    const size_t need = mc_ch_generate_workspace_bytes(g);
+    if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t n = (size_t)G.nx * G.ny * G.nz;
+    char *b = (char *)workspace;
+    double *field = (double *)(b + G.total);
+    double *psd = (double *)(b + G.total + align_up(n * sizeof(double)));
+    void *rank_ws = b + G.total + align_up(n * sizeof(double)) + align_up(sizeof(double) * (kMaxN / 2 + 1));
+    const int nmax = std::max(G.nx, std::max(G.ny, G.nz));
+    const int nb = nmax / 2 + 1;
+    if ((rc = mc_ch_init(g, phi0, state, workspace, G.total, hip_stream))) return rc;
+    int32_t done = 0;
+    double size = 0.0;
+    double host_psd[kMaxN / 2 + 1];
+    while (done < max_steps) {
+        const int32_t m = std::min(check_every, max_steps - done);
+        if ((rc = mc_ch_steps(g, m, state, workspace, G.total, 0, hip_stream))) return rc;
+        done += m;
+        if ((rc = mc_ch_psd(g, state, psd, workspace, G.total, hip_stream))) return rc;
+        HIP_TRY(hipMemcpyAsync(host_psd, psd, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int peak = 1;
+        for (int i = 2; i < nb; ++i)
+            if (host_psd[i] > host_psd[peak]) peak = i;
+        size = (double)nmax / (2.0 * peak);
+        if (size >= d_target - 0.5 * sigma && size <= d_target + 0.5 * sigma) break;
+    }
+    if (steps_taken) *steps_taken = done;
+    if (last_size) *last_size = size;
+    if (phi_out || mask) {
+        double *f = phi_out ? phi_out : field;
+        if ((rc = mc_ch_field(g, state, f, workspace, G.total, hip_stream))) return rc;
+        if (mask) {
+            const long long n_pore = llround(porosity * (double)n);
+            if ((rc = mc_rank_threshold(f, (int64_t)n, n_pore, mask, rank_ws, rank_ws_bytes((int64_t)n), hip_stream)))
+                return rc;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return MC_OK;
+}
+
+}  // extern "C"

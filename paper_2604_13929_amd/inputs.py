@@ -121,6 +121,14 @@ def spinodal_mask_torch(nx: int, ny: int, nz: int, wavelength: float, porosity: 
     return mask.reshape(nz, ny, nx).contiguous()
 
 
+def ch_initial_field(nx: int, ny: int, nz: int, seed: int = PAPER_MASK_SEED, amplitude: float = 0.05) -> np.ndarray:
+    """Initial condition of the Cahn-Hilliard generator (App. A): 0.5 plus independent
+    Gaussian noise of standard deviation `amplitude` per voxel, clipped to [0, 1];
+    numpy.random.default_rng(seed), float64 [nz, ny, nx]."""
+    rng = np.random.default_rng(seed)
+    return np.clip(0.5 + amplitude * rng.standard_normal((nz, ny, nx)), 0.0, 1.0)
+
+
 def homogeneous_mask(nx: int, ny: int, nz: int, pore: bool = False) -> np.ndarray:
     """All-solid (or all-pore) slab."""
     return np.full((nz, ny, nx), 1 if pore else 0, dtype=np.uint8)

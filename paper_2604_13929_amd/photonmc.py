@@ -50,6 +50,11 @@ class McOptics(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("gate", ctypes.c_double)]
 
 
+class McChGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("kappa", ctypes.c_double), ("dt", ctypes.c_double)]
+
+
 class McTune(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("refill", ctypes.c_int32)]
@@ -97,6 +102,18 @@ _SIGS = {
     "mc_graph_destroy": (ctypes.c_int, [_P]),
     "mc_trace": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
                                 ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P]),
+    # spinodal.h: the Cahn-Hilliard mask generator
+    "mc_ch_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "mc_ch_init": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mc_ch_steps": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_size_t, ctypes.c_int, _P]),
+    "mc_ch_field": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mc_ch_psd": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mc_ch_elapsed_ms": (ctypes.c_double, []),
+    "mc_rank_threshold_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+    "mc_rank_threshold": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P]),
+    "mc_ch_generate_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "mc_ch_generate": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_double, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
 }
 
 _lib = None
@@ -124,7 +141,7 @@ def load(path: str = LIB_PATH):
     for name, size in (("mc_volume", ctypes.sizeof(McVolume)), ("mc_optics", ctypes.sizeof(McOptics)),
                        ("mc_job", ctypes.sizeof(McJob)),
                        ("mc_tune", ctypes.sizeof(McTune)), ("mc_trace_rec", TRACE_DTYPE.itemsize),
-                       ("mc_photon_rec", PHOTON_DTYPE.itemsize)):
+                       ("mc_photon_rec", PHOTON_DTYPE.itemsize), ("mc_ch_grid", ctypes.sizeof(McChGrid))):
         if L.mc_sizeof(name.encode()) != size:
             raise RuntimeError(f"ABI mismatch: sizeof({name}) is {L.mc_sizeof(name.encode())}, binding has {size}")
     _lib = L

@@ -12,11 +12,11 @@ import pytest
 from paper_2604_13929_amd import photonmc as pm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "photonmc.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("photonmc.h", "spinodal.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(mc_[a-z_0-9]+)\s*\(", text, flags=re.M)
     return sorted(set(names))
@@ -31,7 +31,7 @@ def lib():
 
 def test_header_parsed():
     names = declared_functions()
-    assert {"mc_run", "mc_reduce", "mc_trace"} <= set(names)
+    assert {"mc_run", "mc_reduce", "mc_trace", "mc_ch_steps", "mc_rank_threshold"} <= set(names)
 
 
 def test_every_declared_symbol_is_exported(lib):
