@@ -283,6 +283,71 @@ def paper_leg(args, seed, mask_np, mask):
                         "(Fresnel), gate of Eq. tend, 1e8 photons", **out}
 
 
+def ch_leg(args):
+    """The Cahn-Hilliard generator (Eq. CH_spectral, App. A) on the paper's domain,
+    384 x 1024 x 1024 voxels, kappa_CH = 0.1140, dt = 0.0450, from the App. A initial
+    field (0.5 + N(0, 0.05^2), clipped, seed 0): one stopping-check interval of
+    `ch_steps` steps timed with HIP events, plus the PSD check; the numpy oracle's
+    rate on a 64^3 grid as the CPU reference."""
+    import numpy as np
+    import torch
+
+    from paper_2604_13929_amd import inputs
+    from paper_2604_13929_amd import spinodal as sp
+
+    nz, ny, nx = 384, 1024, 1024
+    kappa = sp.kappa_from_target(17.4 / 1.45)
+    dt = sp.dt_from_kappa(kappa)
+    g = sp.Grid(nx, ny, nz, kappa, dt)
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    phi0 = torch.from_numpy(inputs.ch_initial_field(nx, ny, nz, seed=inputs.PAPER_MASK_SEED)).to(dev)
+    log(f"CH initial field {nz}x{ny}x{nx} built in {time.time() - t0:.1f}s")
+    ws = sp.workspace(g, dev)
+    st = sp.init(phi0, g, ws)
+    del phi0
+    sp.steps(st, g, 4, ws)
+    torch.cuda.synchronize()
+    n = args.ch_steps
+    t1 = time.perf_counter()
+    ms = sp.steps(st, g, n, ws, timed=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    p = sp.psd(st, g, ws)
+    size = sp.dominant_size(p, g)
+    torch.cuda.synchronize()
+    psd_ms = (time.perf_counter() - t2) * 1e3
+    spec_bytes = nz * ny * (nx // 2 + 1) * 16
+    bytes_per_step = 10 * spec_bytes
+    voxels = nx * ny * nz
+    log(f"CH: {n} steps in {ms:.0f} ms ({ms / n:.2f} ms/step, {bytes_per_step / (ms / n * 1e-3) / 1e9:.0f} GB/s)")
+    out = {"workload": "Cahn-Hilliard semi-implicit spectral steps, 384x1024x1024 FP64, kappa 0.1140, dt 0.0450",
+           "steps": n, "ms": ms, "wall_ms": wall * 1e3, "ms_per_step": ms / n, "steps_per_s": n / (ms * 1e-3),
+           "voxel_steps_per_s": voxels * n / (ms * 1e-3),
+           "roofline": {"bound": "hbm", "bytes_per_step": bytes_per_step,
+                        "achieved": bytes_per_step / (ms / n * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": bytes_per_step / (ms / n * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "note": "ten spectrum-sized (complex FP64 [nz][ny][nx/2+1]) transfers per step"},
+           "psd_ms": psd_ms, "dominant_size_voxels_after": size, "steps_done": n + 4}
+    if not args.no_cpu:
+        from oracle import cahn_hilliard as och
+        m = 64
+        phi_s = inputs.ch_initial_field(m, m, m, seed=1)
+        ph = och.spectrum(phi_s)
+        och.steps(ph, phi_s.shape, 2, dt, kappa)
+        t3 = time.perf_counter()
+        k = 50
+        och.steps(ph, phi_s.shape, k, dt, kappa)
+        tc = time.perf_counter() - t3
+        out["cpu_baseline"] = {"value": m ** 3 * k / tc, "unit": "voxel-steps/s", "kind": "oracle",
+                               "sample": f"{k} steps on a {m}^3 grid, numpy FFT (single thread)", "seconds": tc}
+        out["gpu_over_cpu"] = out["voxel_steps_per_s"] / out["cpu_baseline"]["value"]
+    del st, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def grad_oracle_check(seed, n=100_000, B=32):
     """GPU likelihood-ratio Jacobian (FP32 transport) on the 32^3 workload against the
     oracle's FP64 likelihood-ratio bins on the same photons: z-scores with the
@@ -376,6 +441,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="skip the 32^3 and phi = 0.90 rows")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper boundary model rows")
+    ap.add_argument("--no-ch", action="store_true", help="skip the Cahn-Hilliard generator leg")
+    ap.add_argument("--ch-steps", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
@@ -509,6 +576,8 @@ def main():
     del field
     if not args.no_paper:
         line["paper_boundary"] = paper_leg(args, seed, mask_np, mask)
+    if not args.no_ch:
+        line["spinodal_generator"] = ch_leg(args)
     if not args.no_batch:
         line["batched"] = batched_leg(args, seed)
     if not args.no_morph:

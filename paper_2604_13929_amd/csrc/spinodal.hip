@@ -22,24 +22,62 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "spinodal.h"
 
 using namespace pmc::host;
 
+// The transforms and the update may contract multiply-adds into FMAs: unlike the
+// photon walk, nothing here has to be bitwise independent of launch shape, and a
+// given binary still gives the same bits on every run.
+#pragma clang fp contract(fast)
+
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kLdsElems = 4096;           // complex doubles per workgroup (64 KiB)
+constexpr int kLdsElems = 4096;           // complex doubles transformed per workgroup (64 KiB)
+constexpr int kColElems = kLdsElems + 64; // LDS of the column passes: lines padded to n + 1
 constexpr int kMaxStages = 12;
 constexpr int kMaxN = 1024;
+constexpr int kTwElems = 768;             // LDS twiddles: n/2 for even n (w(m + n/2) = -w(m)), n for odd n <= 729
+constexpr int kPadElems = 4400;           // LDS of the compile-time lengths: lines padded by one per 16
+constexpr int kPadTw = 528;               // their twiddles: n/2 padded by one per 32
 
+// LDS index of element i of a line: the compile-time lengths insert one pad
+// element per 16 (and one per 32 in the twiddle table), which spreads the
+// strided accesses of the early and middle stages over the banks.
+template <int N> __device__ __forceinline__ int pidx(int i) { return N > 0 ? i + (i >> 4) : i; }
+template <int N> __device__ __forceinline__ int tidx(int i) { return N > 0 ? i + (i >> 5) : i; }
+
+// Host-side geometry of the LDS layouts (must match the kernels).
+constexpr bool static_length(int n) { return n == 1024 || n == 512 || n == 384 || n == 256; }
+inline int line_stride(int n, bool column)
+{
+    return static_length(n) ? n + n / 16 + (column ? 1 : 0) : n + (column ? 1 : 0);
+}
+
+// Per-stage constants, with FP32 reciprocals for the index divisions.
 struct Plan {
     int32_t n;
     int32_t nstages;
     int32_t radix[kMaxStages];
+    int32_t ns[kMaxStages];        // product of the radices before the stage
+    float inv_nb[kMaxStages];      // 1 / (n / radix)
+    float inv_ns[kMaxStages];      // 1 / ns
 };
+
+// x / d for 0 <= x < 2^22 and 1 <= d < 2^22, with inv = 1/d in FP32: the
+// product is off by at most one, which the remainder corrects.
+__device__ __forceinline__ int fdiv(int x, int d, float inv)
+{
+    int q = (int)((float)x * inv);
+    const int r = x - q * d;
+    if (r < 0) q -= 1;
+    else if (r >= d) q += 1;
+    return q;
+}
 
 // radix-3 stages first, then radix 4, then one radix 2 if the power of two is odd
 bool make_plan(int n, Plan *p)
@@ -55,6 +93,13 @@ bool make_plan(int n, Plan *p)
     for (int i = 0; i < twos / 2; ++i) p->radix[s++] = 4;
     if (twos % 2) p->radix[s++] = 2;
     p->nstages = s;
+    int ns = 1;
+    for (int i = 0; i < s; ++i) {
+        p->ns[i] = ns;
+        p->inv_nb[i] = 1.0f / (float)(n / p->radix[i]);
+        p->inv_ns[i] = 1.0f / (float)ns;
+        ns *= p->radix[i];
+    }
     return s <= kMaxStages;
 }
 
@@ -111,7 +156,8 @@ template <> __device__ __forceinline__ void dft<3>(double2 *v, bool inv)
 // writes them to (j / ns) ns R + (j mod ns) + r ns.  Values wait in registers
 // between the read and the write barrier, so one LDS buffer suffices.
 template <int R>
-__device__ __forceinline__ void stage(double2 *buf, int n, int ns, int nlines, int ls, bool inv, const double2 *tw)
+__device__ __forceinline__ void stage(double2 *buf, int n, int ns, int nlines, int ls, bool inv, const double2 *tw,
+                                      float inv_nb, float inv_ns)
 {
     constexpr int kPer = (kLdsElems / R + kThreads - 1) / kThreads;
     const int nb = n / R;
@@ -124,15 +170,22 @@ __device__ __forceinline__ void stage(double2 *buf, int n, int ns, int nlines, i
         const int b = (int)threadIdx.x + q * kThreads;
         dst[q] = -1;
         if (b < total) {
-            const int line = b / nb, j = b - line * nb;
-            const int jm = j % ns;
+            const int line = fdiv(b, nb, inv_nb), j = b - line * nb;
+            const int jm = j - fdiv(j, ns, inv_ns) * ns;
             const double2 *src = buf + line * ls;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double2 x = src[j + r * nb];
                 if (r) {
-                    double2 w = tw[jm * r * tstep];
-                    if (inv) w.y = -w.y;
+                    int m = jm * r * tstep;
+                    double sg = 1.0;
+                    if (!(n & 1) && m >= (n >> 1)) {
+                        m -= n >> 1;
+                        sg = -1.0;
+                    }
+                    double2 w = tw[m];
+                    w.x *= sg;
+                    w.y *= inv ? -sg : sg;
                     x = cmul(x, w);
                 }
                 v[q][r] = x;
@@ -152,16 +205,114 @@ __device__ __forceinline__ void stage(double2 *buf, int n, int ns, int nlines, i
     __syncthreads();
 }
 
-// Unnormalised FFT of every line (forward: exp(-2 pi i j k / n)).
+// Copy the twiddles a transform of length n reads into LDS: the first n/2 when n
+// is even, all n when n is odd.
+template <int N>
+__device__ __forceinline__ void load_twiddles(double2 *tw_s, const double2 *__restrict__ tw, int n)
+{
+    const int m = (n & 1) ? n : n >> 1;
+    for (int i = (int)threadIdx.x; i < m; i += kThreads) tw_s[tidx<N>(i)] = tw[i];
+}
+
+// Unnormalised FFT of every line (forward: exp(-2 pi i j k / n)); tw is the
+// table staged by load_twiddles.
 __device__ void fft_lines(double2 *buf, int ls, int nlines, const Plan &P, const double2 *tw, bool inv)
 {
-    int ns = 1;
     for (int s = 0; s < P.nstages; ++s) {
-        const int R = P.radix[s];
-        if (R == 4) stage<4>(buf, P.n, ns, nlines, ls, inv, tw);
-        else if (R == 2) stage<2>(buf, P.n, ns, nlines, ls, inv, tw);
-        else stage<3>(buf, P.n, ns, nlines, ls, inv, tw);
-        ns *= R;
+        const int R = P.radix[s], ns = P.ns[s];
+        if (R == 4) stage<4>(buf, P.n, ns, nlines, ls, inv, tw, P.inv_nb[s], P.inv_ns[s]);
+        else if (R == 2) stage<2>(buf, P.n, ns, nlines, ls, inv, tw, P.inv_nb[s], P.inv_ns[s]);
+        else stage<3>(buf, P.n, ns, nlines, ls, inv, tw, P.inv_nb[s], P.inv_ns[s]);
+    }
+}
+
+// Compile-time plans for the common extents: the same stages as make_plan with
+// every divisor and stride a constant.
+constexpr int c_threes(int n) { int t = 0; while (n % 3 == 0) { n /= 3; ++t; } return t; }
+constexpr int c_twos(int n) { while (n % 3 == 0) n /= 3; int t = 0; while (n % 2 == 0) { n /= 2; ++t; } return t; }
+constexpr int c_stages(int n) { return c_threes(n) + c_twos(n) / 2 + c_twos(n) % 2; }
+constexpr int c_radix(int n, int s)
+{
+    const int t3 = c_threes(n), t4 = c_twos(n) / 2;
+    return s < t3 ? 3 : (s < t3 + t4 ? 4 : 2);
+}
+constexpr int c_ns(int n, int s)
+{
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= c_radix(n, i);
+    return p;
+}
+
+template <int R, int N, int NS, bool INV>
+__device__ __forceinline__ void stage_c(double2 *buf, int ls, int nlines, const double2 *tw)
+{
+    constexpr int NB = N / R;
+    constexpr int TSTEP = N / (NS * R);
+    constexpr int kPer = (kLdsElems / R + kThreads - 1) / kThreads;
+    const int total = nlines * NB;
+    double2 v[kPer][R];
+    int dst[kPer], dst2[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int b = (int)threadIdx.x + q * kThreads;
+        dst[q] = -1;
+        dst2[q] = 0;
+        if (b < total) {
+            const int line = b / NB, j = b - line * NB;
+            const int jm = j % NS;
+            const double2 *src = buf + line * ls;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double2 x = src[pidx<N>(j + r * NB)];
+                if (r) {
+                    int m = jm * r * TSTEP;
+                    double2 w;
+                    if constexpr ((N & 1) == 0) {
+                        const bool hi = m >= N / 2;
+                        w = tw[tidx<N>(hi ? m - N / 2 : m)];
+                        if (hi) w = make_double2(-w.x, -w.y);
+                    } else {
+                        w = tw[tidx<N>(m)];
+                    }
+                    if (INV) w.y = -w.y;
+                    x = cmul(x, w);
+                }
+                v[q][r] = x;
+            }
+            dft<R>(v[q], INV);
+            dst[q] = line * ls;
+            dst2[q] = (j - jm) * R + jm;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        if (dst[q] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[dst[q] + pidx<N>(dst2[q] + r * NS)] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int S, bool INV>
+__device__ __forceinline__ void fft_c(double2 *buf, int ls, int nlines, const double2 *tw)
+{
+    if constexpr (S < c_stages(N)) {
+        stage_c<c_radix(N, S), N, c_ns(N, S), INV>(buf, ls, nlines, tw);
+        fft_c<N, S + 1, INV>(buf, ls, nlines, tw);
+    }
+}
+
+// Transform dispatch: N > 0 selects the compile-time plan for that length.
+template <int N>
+__device__ __forceinline__ void fft_any(double2 *buf, int ls, int nlines, const Plan &P, const double2 *tw, bool inv)
+{
+    if constexpr (N > 0) {
+        if (inv) fft_c<N, 0, true>(buf, ls, nlines, tw);
+        else fft_c<N, 0, false>(buf, ls, nlines, tw);
+    } else {
+        fft_lines(buf, ls, nlines, P, tw, inv);
     }
 }
 
@@ -183,62 +334,93 @@ __global__ void k_tables(double2 *tw, double *k2, int n, int half)
     }
 }
 
+// Cooperative copy of `total` elements: each thread issues U global loads before
+// it writes any of them, so U loads per thread are in flight at once.
+template <int U, class T, class Load, class Store>
+__device__ __forceinline__ void gather(int total, Load load, Store store)
+{
+    for (int e0 = (int)threadIdx.x; e0 < total; e0 += U * kThreads) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * kThreads;
+            if (e < total) v[u] = load(e);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * kThreads;
+            if (e < total) store(e, v[u]);
+        }
+    }
+}
+
 enum { X_INIT = 0, X_NONLIN = 1, X_FIELD = 2 };
 
 // Lines along x.  X_INIT: real line -> forward transform, half spectrum out.
 // X_NONLIN: half spectrum -> inverse -> f'(phi) -> forward -> half spectrum.
 // X_FIELD: half spectrum -> inverse -> real line out.  `scale` = 1/(nx ny nz).
-template <int MODE>
+template <int MODE, int N>
 __global__ __launch_bounds__(kThreads) void k_xpass(const double *__restrict__ rin, double2 *spec,
                                                      double *__restrict__ rout, int nx, int nlines_total, int L,
                                                      Plan P, const double2 *__restrict__ tw, double scale)
 {
-    __shared__ double2 buf[kLdsElems];
-    const int hx = nx / 2 + 1, ls = nx + 1;
+    __shared__ double2 buf[N > 0 ? kPadElems : kLdsElems];
+    __shared__ double2 tw_s[N > 0 ? kPadTw : kTwElems];
+    load_twiddles<N>(tw_s, tw, nx);
+    const int hx = nx / 2 + 1, ls = N > 0 ? nx + nx / 16 : nx;   // read along the lines: no extra pad
     const int line0 = (int)blockIdx.x * L;
     const int nl = min(L, nlines_total - line0);
     const int tid = (int)threadIdx.x;
+    const float inv_nx = 1.0f / (float)nx, inv_hx = 1.0f / (float)hx;
     if (MODE == X_INIT) {
-        for (int e = tid; e < nl * nx; e += kThreads) {
-            const int l = e / nx, x = e - l * nx;
-            buf[l * ls + x] = make_double2(rin[(size_t)(line0 + l) * nx + x], 0.0);
-        }
+        // the block's lines are contiguous in memory
+        const double *src = rin + (size_t)line0 * nx;
+        gather<8, double>(
+            nl * nx, [&](int e) { return src[e]; },
+            [&](int e, double v) {
+                const int l = fdiv(e, nx, inv_nx), x = e - l * nx;
+                buf[l * ls + pidx<N>(x)] = make_double2(v, 0.0);
+            });
         __syncthreads();
     } else {
-        for (int e = tid; e < nl * hx; e += kThreads) {
-            const int l = e / hx, x = e - l * hx;
-            buf[l * ls + x] = spec[(size_t)(line0 + l) * hx + x];
-        }
+        const double2 *src = spec + (size_t)line0 * hx;
+        gather<8, double2>(
+            nl * hx, [&](int e) { return src[e]; },
+            [&](int e, double2 v) {
+                const int l = fdiv(e, hx, inv_hx), x = e - l * hx;
+                buf[l * ls + pidx<N>(x)] = v;
+            });
         __syncthreads();
         // Hermitian extension: X[n - j] = conj(X[j]); the real part of the complex
         // inverse then ignores the imaginary parts of the 0 and n/2 bins, as a
         // real inverse transform does
         const int ne = nx / 2 - 1;
+        const float inv_ne = 1.0f / (float)max(ne, 1);
         for (int e = tid; e < nl * ne; e += kThreads) {
-            const int l = e / ne, j = 1 + (e - l * ne);
-            const double2 v = buf[l * ls + j];
-            buf[l * ls + nx - j] = make_double2(v.x, -v.y);
+            const int l = fdiv(e, ne, inv_ne), j = 1 + (e - l * ne);
+            const double2 v = buf[l * ls + pidx<N>(j)];
+            buf[l * ls + pidx<N>(nx - j)] = make_double2(v.x, -v.y);
         }
         __syncthreads();
-        fft_lines(buf, ls, nl, P, tw, true);
+        fft_any<N>(buf, ls, nl, P, tw_s, true);
         if (MODE == X_FIELD) {
             for (int e = tid; e < nl * nx; e += kThreads) {
-                const int l = e / nx, x = e - l * nx;
-                rout[(size_t)(line0 + l) * nx + x] = buf[l * ls + x].x * scale;
+                const int l = fdiv(e, nx, inv_nx), x = e - l * nx;
+                rout[(size_t)(line0 + l) * nx + x] = buf[l * ls + pidx<N>(x)].x * scale;
             }
             return;
         }
         for (int e = tid; e < nl * nx; e += kThreads) {
-            const int l = e / nx, x = e - l * nx;
-            const double phi = buf[l * ls + x].x * scale;
-            buf[l * ls + x] = make_double2(2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi), 0.0);
+            const int l = fdiv(e, nx, inv_nx), x = e - l * nx;
+            const double phi = buf[l * ls + pidx<N>(x)].x * scale;
+            buf[l * ls + pidx<N>(x)] = make_double2(2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi), 0.0);
         }
         __syncthreads();
     }
-    fft_lines(buf, ls, nl, P, tw, false);
+    fft_any<N>(buf, ls, nl, P, tw_s, false);
     for (int e = tid; e < nl * hx; e += kThreads) {
-        const int l = e / hx, x = e - l * hx;
-        spec[(size_t)(line0 + l) * hx + x] = buf[l * ls + x];
+        const int l = fdiv(e, hx, inv_hx), x = e - l * hx;
+        spec[(size_t)(line0 + l) * hx + x] = buf[l * ls + pidx<N>(x)];
     }
 }
 
@@ -251,23 +433,33 @@ __device__ __forceinline__ size_t col_addr(int j, int p, int x, int ny, int hx)
 }
 
 // In-place FFT along y (AXIS 1) or z (AXIS 2) of T-column tiles.
-template <int AXIS>
+template <int AXIS, int N>
 __global__ __launch_bounds__(kThreads) void k_colpass(double2 *A, int ny, int hx, int n, int T, int tiles, Plan P,
                                                        const double2 *__restrict__ tw, int inv)
 {
-    __shared__ double2 buf[kLdsElems];
+    __shared__ double2 buf[N > 0 ? kPadElems : kColElems];
+    __shared__ double2 tw_s[N > 0 ? kPadTw : kTwElems];
+    load_twiddles<N>(tw_s, tw, n);
     const int p = (int)blockIdx.x / tiles, tile = (int)blockIdx.x - p * tiles;
-    const int x0 = tile * T, nc = min(T, hx - x0), ls = n + 1;
+    // lines padded to an odd stride: the transposing loads hit distinct banks
+    const int x0 = tile * T, nc = min(T, hx - x0), ls = (N > 0 ? n + n / 16 : n) + 1;
     const int tid = (int)threadIdx.x;
-    for (int e = tid; e < n * nc; e += kThreads) {
-        const int j = e / nc, c = e - j * nc;
-        buf[c * ls + j] = A[col_addr<AXIS>(j, p, x0 + c, ny, hx)];
-    }
+    const float inv_nc = 1.0f / (float)nc;
+    gather<8, double2>(
+        n * nc,
+        [&](int e) {
+            const int j = fdiv(e, nc, inv_nc), c = e - j * nc;
+            return A[col_addr<AXIS>(j, p, x0 + c, ny, hx)];
+        },
+        [&](int e, double2 v) {
+            const int j = fdiv(e, nc, inv_nc), c = e - j * nc;
+            buf[c * ls + pidx<N>(j)] = v;
+        });
     __syncthreads();
-    fft_lines(buf, ls, nc, P, tw, inv != 0);
+    fft_any<N>(buf, ls, nc, P, tw_s, inv != 0);
     for (int e = tid; e < n * nc; e += kThreads) {
-        const int j = e / nc, c = e - j * nc;
-        A[col_addr<AXIS>(j, p, x0 + c, ny, hx)] = buf[c * ls + j];
+        const int j = fdiv(e, nc, inv_nc), c = e - j * nc;
+        A[col_addr<AXIS>(j, p, x0 + c, ny, hx)] = buf[c * ls + pidx<N>(j)];
     }
 }
 
@@ -277,47 +469,63 @@ enum { Z_INV = 0, Z_INIT = 1, Z_UPDATE = 2 };
 // S = (S - dt k^2 FFT_z(W)) / (1 + dt kappa k^4) (Eq. CH_spectral, evaluated in
 // that order).  With write_w (Z_INIT, Z_UPDATE) W = inverse FFT_z(S) as well, the
 // start of the next step.
-template <int MODE>
+template <int MODE, int N>
 __global__ __launch_bounds__(kThreads) void k_zpass(double2 *S, double2 *W, int ny, int hx, int nz, int T, int tiles,
                                                      Plan P, const double2 *__restrict__ tw,
                                                      const double *__restrict__ kx2, const double *__restrict__ ky2,
                                                      const double *__restrict__ kz2, double dt, double kappa,
                                                      int write_w)
 {
-    __shared__ double2 buf[kLdsElems];
+    __shared__ double2 buf[N > 0 ? kPadElems : kColElems];
+    __shared__ double2 tw_s[N > 0 ? kPadTw : kTwElems];
+    load_twiddles<N>(tw_s, tw, nz);
     const int y = (int)blockIdx.x / tiles, tile = (int)blockIdx.x - y * tiles;
-    const int x0 = tile * T, nc = min(T, hx - x0), ls = nz + 1;
+    const int x0 = tile * T, nc = min(T, hx - x0), ls = (N > 0 ? nz + nz / 16 : nz) + 1;
     const int tid = (int)threadIdx.x;
+    const float inv_nc = 1.0f / (float)nc;
     const double2 *src = MODE == Z_INV ? S : W;
-    for (int e = tid; e < nz * nc; e += kThreads) {
-        const int j = e / nc, c = e - j * nc;
-        buf[c * ls + j] = src[col_addr<2>(j, y, x0 + c, ny, hx)];
-    }
+    gather<8, double2>(
+        nz * nc,
+        [&](int e) {
+            const int j = fdiv(e, nc, inv_nc), c = e - j * nc;
+            return src[col_addr<2>(j, y, x0 + c, ny, hx)];
+        },
+        [&](int e, double2 v) {
+            const int j = fdiv(e, nc, inv_nc), c = e - j * nc;
+            buf[c * ls + pidx<N>(j)] = v;
+        });
     __syncthreads();
     if (MODE != Z_INV) {
-        fft_lines(buf, ls, nc, P, tw, false);
+        fft_any<N>(buf, ls, nc, P, tw_s, false);
         const double dtk = dt * kappa;
-        for (int e = tid; e < nz * nc; e += kThreads) {
-            const int j = e / nc, c = e - j * nc;
-            const size_t a = col_addr<2>(j, y, x0 + c, ny, hx);
-            double2 v = buf[c * ls + j];
-            if (MODE == Z_UPDATE) {
-                const double k2 = kz2[j] + ky2[y] + kx2[x0 + c];
-                const double den = 1.0 + dtk * k2 * k2;
-                const double g = dt * k2;
-                const double2 s = S[a];
-                v = make_double2((s.x - g * v.x) / den, (s.y - g * v.y) / den);
-            }
-            S[a] = v;
-            buf[c * ls + j] = v;
-        }
+        // the old state comes in with U loads in flight per thread (Z_UPDATE);
+        // Z_INIT stores the transform as the state
+        gather<8, double2>(
+            nz * nc,
+            [&](int e) {
+                if (MODE != Z_UPDATE) return make_double2(0.0, 0.0);
+                const int j = fdiv(e, nc, inv_nc), c = e - j * nc;
+                return S[col_addr<2>(j, y, x0 + c, ny, hx)];
+            },
+            [&](int e, double2 s) {
+                const int j = fdiv(e, nc, inv_nc), c = e - j * nc;
+                double2 v = buf[c * ls + pidx<N>(j)];
+                if (MODE == Z_UPDATE) {
+                    const double k2 = kz2[j] + ky2[y] + kx2[x0 + c];
+                    const double den = 1.0 + dtk * k2 * k2;
+                    const double g = dt * k2;
+                    v = make_double2((s.x - g * v.x) / den, (s.y - g * v.y) / den);
+                }
+                S[col_addr<2>(j, y, x0 + c, ny, hx)] = v;
+                buf[c * ls + pidx<N>(j)] = v;
+            });
         __syncthreads();
         if (!write_w) return;
     }
-    fft_lines(buf, ls, nc, P, tw, true);
+    fft_any<N>(buf, ls, nc, P, tw_s, true);
     for (int e = tid; e < nz * nc; e += kThreads) {
-        const int j = e / nc, c = e - j * nc;
-        W[col_addr<2>(j, y, x0 + c, ny, hx)] = buf[c * ls + j];
+        const int j = fdiv(e, nc, inv_nc), c = e - j * nc;
+        W[col_addr<2>(j, y, x0 + c, ny, hx)] = buf[c * ls + pidx<N>(j)];
     }
 }
 
@@ -543,9 +751,14 @@ int geometry(const mc_ch_grid *g, Geo *G)
     if (!make_plan(g->nx, &G->px) || !make_plan(g->ny, &G->py) || !make_plan(g->nz, &G->pz))
         return fail(MC_EINVAL, "every extent must be a product of powers of 2 and 3");
     G->spec_elems = (size_t)G->nz * G->ny * G->hx;
-    G->Lx = std::max(1, kLdsElems / (G->nx + 1));
-    G->Ty = std::max(1, kLdsElems / (G->ny + 1));
-    G->Tz = std::max(1, kLdsElems / (G->nz + 1));
+    G->Lx = std::max(1, kLdsElems / G->nx);
+    // column tiles: padded lines must fit the LDS buffer and the stage registers
+    auto tile = [](int n) {
+        const int lds = static_length(n) ? kPadElems : kColElems;
+        return std::max(1, std::min(lds / line_stride(n, true), kLdsElems / n));
+    };
+    G->Ty = tile(G->ny);
+    G->Tz = tile(G->nz);
     G->tiles_y = (G->hx + G->Ty - 1) / G->Ty;
     G->tiles_z = (G->hx + G->Tz - 1) / G->Tz;
     size_t off = 0;
@@ -605,16 +818,33 @@ int prepare(const mc_ch_grid *g, void *ws, size_t ws_bytes, hipStream_t s, Geo *
     return MC_OK;
 }
 
+// Lengths with a compile-time plan; any other length takes the runtime plan.
+template <class F>
+void with_length(int n, F &&f)
+{
+    switch (n) {
+    case 1024: f(std::integral_constant<int, 1024>{}); break;
+    case 512: f(std::integral_constant<int, 512>{}); break;
+    case 384: f(std::integral_constant<int, 384>{}); break;
+    case 256: f(std::integral_constant<int, 256>{}); break;
+    default: f(std::integral_constant<int, 0>{}); break;
+    }
+}
+
 void enqueue_col(const Geo &G, int axis, double2 *A, const Ptrs &P, bool inv, hipStream_t s)
 {
     if (axis == 1) {
         if (G.ny == 1) return;
-        hipLaunchKernelGGL(k_colpass<1>, dim3((unsigned)(G.nz * G.tiles_y)), dim3(kThreads), 0, s, A, G.ny, G.hx,
-                           G.ny, G.Ty, G.tiles_y, G.py, P.twy, inv ? 1 : 0);
+        with_length(G.ny, [&](auto nc) {
+            hipLaunchKernelGGL((k_colpass<1, decltype(nc)::value>), dim3((unsigned)(G.nz * G.tiles_y)), dim3(kThreads),
+                               0, s, A, G.ny, G.hx, G.ny, G.Ty, G.tiles_y, G.py, P.twy, inv ? 1 : 0);
+        });
     } else {
         if (G.nz == 1) return;
-        hipLaunchKernelGGL(k_colpass<2>, dim3((unsigned)(G.ny * G.tiles_z)), dim3(kThreads), 0, s, A, G.ny, G.hx,
-                           G.nz, G.Tz, G.tiles_z, G.pz, P.twz, inv ? 1 : 0);
+        with_length(G.nz, [&](auto nc) {
+            hipLaunchKernelGGL((k_colpass<2, decltype(nc)::value>), dim3((unsigned)(G.ny * G.tiles_z)), dim3(kThreads),
+                               0, s, A, G.ny, G.hx, G.nz, G.Tz, G.tiles_z, G.pz, P.twz, inv ? 1 : 0);
+        });
     }
 }
 
@@ -623,15 +853,20 @@ void enqueue_x(const Geo &G, const double *rin, double2 *spec, double *rout, con
 {
     const int lines = G.nz * G.ny;
     const double scale = 1.0 / ((double)G.nx * (double)G.ny * (double)G.nz);
-    hipLaunchKernelGGL(k_xpass<MODE>, dim3((unsigned)((lines + G.Lx - 1) / G.Lx)), dim3(kThreads), 0, s, rin, spec,
-                       rout, G.nx, lines, G.Lx, G.px, P.twx, scale);
+    with_length(G.nx, [&](auto nc) {
+        hipLaunchKernelGGL((k_xpass<MODE, decltype(nc)::value>), dim3((unsigned)((lines + G.Lx - 1) / G.Lx)),
+                           dim3(kThreads), 0, s, rin, spec, rout, G.nx, lines, G.Lx, G.px, P.twx, scale);
+    });
 }
 
 template <int MODE>
 void enqueue_z(const Geo &G, double2 *S, const Ptrs &P, double dt, double kappa, bool write_w, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zpass<MODE>, dim3((unsigned)(G.ny * G.tiles_z)), dim3(kThreads), 0, s, S, P.W, G.ny, G.hx,
-                       G.nz, G.Tz, G.tiles_z, G.pz, P.twz, P.kx2, P.ky2, P.kz2, dt, kappa, write_w ? 1 : 0);
+    with_length(G.nz, [&](auto nc) {
+        hipLaunchKernelGGL((k_zpass<MODE, decltype(nc)::value>), dim3((unsigned)(G.ny * G.tiles_z)), dim3(kThreads), 0,
+                           s, S, P.W, G.ny, G.hx, G.nz, G.Tz, G.tiles_z, G.pz, P.twz, P.kx2, P.ky2, P.kz2, dt, kappa,
+                           write_w ? 1 : 0);
+    });
 }
 
 pmc::host::Timing g_ch_timing;

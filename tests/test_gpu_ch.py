@@ -80,6 +80,23 @@ def test_steps_match_oracle(shape, n, tol):
     assert got[0, 0, 0] == och.spectrum(phi0)[0, 0, 0] or abs(got[0, 0, 0] - want[0, 0, 0]) <= 1e-12 * abs(want[0, 0, 0])
 
 
+@pytest.mark.parametrize("shape", [(384, 6, 256), (6, 1024, 12), (12, 6, 1024), (256, 4, 512)])
+def test_compile_time_lengths_match_oracle(shape):
+    """Extents 256, 384, 512 and 1024 take the compile-time transform plans."""
+    banner(f"30 CH steps vs oracle on compile-time lengths, shape {shape}")
+    nz, ny, nx = shape
+    g = sp.Grid(nx, ny, nz, KAPPA, DT)
+    phi0 = inputs.ch_initial_field(nx, ny, nz, seed=15)
+    st = sp.init(cuda(phi0), g)
+    assert np.abs(st.cpu().numpy() - och.spectrum(phi0)).max() <= 1e-13 * np.abs(och.spectrum(phi0)).max()
+    sp.steps(st, g, 30)
+    want = och.steps(och.spectrum(phi0), shape, 30, DT, KAPPA)
+    err = np.abs(st.cpu().numpy() - want).max() / np.abs(want).max()
+    ferr = np.abs(sp.field(st, g).cpu().numpy() - och.field(want, shape)).max()
+    print(f"relative spectrum error {err:.2e}, field error {ferr:.2e}")
+    assert err < 1e-11 and ferr < 1e-11
+
+
 def test_psd_matches_oracle():
     banner("radial PSD vs oracle")
     shape = (18, 24, 36)
