@@ -424,6 +424,15 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const double *__restrict__ r
     }
 }
 
+// Workgroup ids are dealt to the 8 XCDs in turn; give each XCD a contiguous
+// range of tiles instead, so that neighbouring tiles, which share 128-byte
+// lines, meet in the same L2.  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int xcd_order(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x * q + min(x, r) + k;
+}
+
 // Column addressing: element j of column (plane p, kx = x0 + c).  Along y the
 // plane is z; along z the plane is y.
 template <int AXIS>
@@ -440,7 +449,8 @@ __global__ __launch_bounds__(kThreads) void k_colpass(double2 *A, int ny, int hx
     __shared__ double2 buf[N > 0 ? kPadElems : kColElems];
     __shared__ double2 tw_s[N > 0 ? kPadTw : kTwElems];
     load_twiddles<N>(tw_s, tw, n);
-    const int p = (int)blockIdx.x / tiles, tile = (int)blockIdx.x - p * tiles;
+    const int bid = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    const int p = bid / tiles, tile = bid - p * tiles;
     // lines padded to an odd stride: the transposing loads hit distinct banks
     const int x0 = tile * T, nc = min(T, hx - x0), ls = (N > 0 ? n + n / 16 : n) + 1;
     const int tid = (int)threadIdx.x;
@@ -479,7 +489,8 @@ __global__ __launch_bounds__(kThreads) void k_zpass(double2 *S, double2 *W, int 
     __shared__ double2 buf[N > 0 ? kPadElems : kColElems];
     __shared__ double2 tw_s[N > 0 ? kPadTw : kTwElems];
     load_twiddles<N>(tw_s, tw, nz);
-    const int y = (int)blockIdx.x / tiles, tile = (int)blockIdx.x - y * tiles;
+    const int bid = xcd_order((int)blockIdx.x, (int)gridDim.x);
+    const int y = bid / tiles, tile = bid - y * tiles;
     const int x0 = tile * T, nc = min(T, hx - x0), ls = (N > 0 ? nz + nz / 16 : nz) + 1;
     const int tid = (int)threadIdx.x;
     const float inv_nc = 1.0f / (float)nc;
