@@ -1,0 +1,116 @@
+"""Pins of the analytics oracle (oracle/analytics.py) against facts other than
+itself: hand-counted chords and an independent run-length count, conservation of
+phase volume, the mean-chord ratio phi/(1 - phi) on lines with as many pore as
+solid chords, the exact per-depth decomposition phi(z) c_pore + (1 - phi(z)) c_solid
+= 1, the escape histograms against the walk's own escape channels, brute-force
+brightest deciles, and the distance transform against brute force."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+from oracle import analytics as an
+from oracle import estimators as est
+from paper_2604_13929_amd import inputs
+
+W1 = 2 ** 31
+f32 = lambda x: float(np.float32(x))  # noqa: E731
+
+
+def runs_by_diff(line):
+    """Independent run-length count: change points of the sequence."""
+    line = np.asarray(line)
+    edges = np.flatnonzero(np.diff(line)) + 1
+    starts = np.r_[0, edges]
+    ends = np.r_[edges, line.size]
+    return [(int(line[s]), int(e - s)) for s, e in zip(starts, ends)]
+
+
+def test_chords_hand_counted():
+    line = np.array([1, 1, 0, 1, 1, 1, 0, 0, 1, 1], dtype=np.uint8)
+    m = line.reshape(10, 1, 1)
+    h = an.chord_histogram(m, axis=0)
+    assert h[1, 2] == 2 and h[1, 3] == 1 and h[0, 1] == 1 and h[0, 2] == 1 and h.sum() == 5
+    st = an.chord_stats(h, thresholds=(2,))
+    assert st["mean_pore"] == 7 / 3 and st["mean_solid"] == 1.5
+    assert st["plen_pore_gt_2"] == 3 / 7
+
+
+def test_chords_against_run_lengths_and_volume():
+    m = inputs.spinodal_mask(12, 10, 14, 5.0, 0.6, seed=2)
+    for axis in (0, 1, 2):
+        h = an.chord_histogram(m, axis=axis)
+        ref = np.zeros_like(h)
+        lines = np.moveaxis(m, axis, -1).reshape(-1, m.shape[axis])
+        for line in lines:
+            for ph, ln in runs_by_diff(line):
+                ref[ph, ln] += 1
+        assert np.array_equal(h, ref)
+        lengths = np.arange(h.shape[1])
+        assert (lengths * h[1]).sum() == m.sum() and (lengths * h[0]).sum() == (m == 0).sum()
+
+
+def test_mean_chord_ratio_on_balanced_lines():
+    """Lines that start with one phase and end with the other hold as many chords of
+    each phase, so mean pore / mean solid chord = pore / solid voxels."""
+    rng = np.random.default_rng(3)
+    lines = []
+    while len(lines) < 200:
+        line = (rng.random(40) < 0.7).astype(np.uint8)
+        if line[0] != line[-1]:
+            lines.append(line)
+    m = np.array(lines).T.reshape(40, 200, 1)
+    st = an.chord_stats(an.chord_histogram(m, axis=0))
+    phi = m.mean()
+    assert math.isclose(st["mean_pore"] / st["mean_solid"], phi / (1 - phi), rel_tol=1e-12)
+
+
+def test_phase_contrast_decomposition(mask_m1):
+    n = 20_000
+    ref = oracle.run(mask_m1, 0.5, f32(0.01), f32(0.7), n, 31)
+    e = est.estimators(ref["fluence"][0], mask_m1, n)
+    pc = an.phase_contrast(e["depth"], e["depth_solid"], e["depth_pore"])
+    phi_z = mask_m1.mean(axis=(1, 2))
+    cs = e["depth_solid"] / e["depth"]
+    cp = e["depth_pore"] / e["depth"]
+    assert np.allclose(phi_z * cp + (1 - phi_z) * cs, 1.0, rtol=1e-12)
+    assert math.isclose(pc["solid_mean"], cs.mean(), rel_tol=1e-12) and pc["depths"] == mask_m1.shape[0]
+    h = inputs.homogeneous_mask(4, 4, 8)
+    r = oracle.run(h, 0.5, f32(0.01), f32(0.7), 2000, 31)
+    e2 = est.estimators(r["fluence"][0], h, 2000)
+    pc2 = an.phase_contrast(e2["depth"], e2["depth_solid"], e2["depth_pore"])
+    assert math.isclose(pc2["solid_mean"], 1.0, rel_tol=1e-12) and pc2["solid_sd"] < 1e-12
+
+
+def test_escape_histogram_matches_walk_channels(mask_m1):
+    ids = np.arange(3000, dtype=np.uint64)
+    _, summ = oracle.trace(mask_m1, 0.5, f32(0.01), f32(0.7), ids, 41, max_rec=0)
+    run = oracle.run(mask_m1, 0.5, f32(0.01), f32(0.7), 3000, 41, fluence=False)
+    tot = oracle.totals(run)
+    nz = mask_m1.shape[0]
+    hw, hn, aw, an_ = an.escape_path_histogram(summ["fate"], summ["w_final"], summ["path_void"], 2.0, 40,
+                                               thresholds=(float(nz), 10.0))
+    assert hw.sum() == tot["esc_w"] and hn.sum() == tot["esc_n"]
+    assert aw[0] == tot["esc_w_gtL"] and an_[0] == tot["esc_n_gtL"]
+    assert aw[1] >= aw[0]
+
+
+def test_bright_colocalization_brute_force():
+    rng = np.random.default_rng(4)
+    F = rng.integers(0, 5, size=(6, 5, 7))           # many ties
+    m = (rng.random((6, 5, 7)) < 0.6).astype(np.uint8)
+    k, s = an.bright_colocalization(F, m, z0=2, frac=0.1)
+    for i, z in enumerate(range(2, 6)):
+        f = F[z].ravel()
+        kk = math.ceil(0.1 * f.size)
+        # brute force: order by (-F, index)
+        order = sorted(range(f.size), key=lambda j: (-f[j], j))[:kk]
+        assert k[i] == kk and s[i] == sum(int(m[z].ravel()[j] == 0) for j in order)
+
+
+def test_pore_distance_brute_force():
+    for seed in (5, 6):
+        m = inputs.spinodal_mask(9, 7, 8, 4.0, 0.7, seed=seed)
+        assert np.array_equal(an.pore_distance(m), an.pore_distance_brute(m))
