@@ -14,9 +14,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libphotonmc.so")
-SOURCES = [os.path.join(CSRC, "photonmc.hip"), os.path.join(CSRC, "batch.hip"), os.path.join(CSRC, "spinodal.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("philox.hpp", "walk.hpp", "internal.hpp")] + [
-    os.path.join(INCLUDE, "photonmc.h"), os.path.join(INCLUDE, "spinodal.h")]
+SOURCES = [os.path.join(CSRC, "photonmc.hip"), os.path.join(CSRC, "batch.hip"), os.path.join(CSRC, "spinodal.hip"),
+           os.path.join(CSRC, "analytics.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("philox.hpp", "walk.hpp", "internal.hpp", "select.hpp")] + [
+    os.path.join(INCLUDE, "photonmc.h"), os.path.join(INCLUDE, "spinodal.h"), os.path.join(INCLUDE, "analytics.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

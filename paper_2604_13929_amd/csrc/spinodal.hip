@@ -25,6 +25,7 @@
 #include <type_traits>
 
 #include "internal.hpp"
+#include "select.hpp"
 #include "spinodal.h"
 
 using namespace pmc::host;
@@ -581,155 +582,6 @@ __global__ void k_psd_sum(const double *__restrict__ partial, int nblocks, int n
 }
 
 // ---------------------------------------------------------------------------
-// Rank binarisation: an MSB-first radix select of the n_pore-th largest key
-// (11-bit digits, six passes), then the equal keys taken in index order.
-// ---------------------------------------------------------------------------
-constexpr int kDigitBits = 11;
-constexpr int kDigits = 1 << kDigitBits;
-constexpr int kChunk = kThreads * 16;      // elements per marking block
-
-struct SelectState {
-    unsigned long long prefix;   // key bits chosen so far
-    long long k;                 // rank still to find inside the current candidates (1-based, from the top)
-    long long pad[6];
-};
-
-// order-preserving map of a double to uint64 (-0.0 and +0.0 map alike)
-__device__ __forceinline__ unsigned long long key_of(double v)
-{
-    const unsigned long long u = (unsigned long long)__double_as_longlong(v + 0.0);
-    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
-}
-
-__global__ __launch_bounds__(kThreads) void k_hist(const double *__restrict__ f, long long n,
-                                                   const SelectState *st, unsigned long long *hist, int shift,
-                                                   int bits)
-{
-    __shared__ unsigned int h[kDigits];
-    for (int i = (int)threadIdx.x; i < kDigits; i += kThreads) h[i] = 0u;
-    __syncthreads();
-    const int top = shift + bits;
-    const unsigned long long hi_mask = top >= 64 ? 0ull : (~0ull << top);
-    const unsigned long long prefix = st->prefix;
-    const unsigned long long dmask = (1ull << bits) - 1ull;
-    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
-        const unsigned long long key = key_of(f[i]);
-        if ((key & hi_mask) == prefix) atomicAdd(&h[(key >> shift) & dmask], 1u);
-    }
-    __syncthreads();
-    for (int i = (int)threadIdx.x; i < (1 << bits); i += kThreads)
-        if (h[i]) atomicAdd(&hist[i], (unsigned long long)h[i]);
-}
-
-__global__ void k_select(SelectState *st, unsigned long long *hist, int shift, int bits)
-{
-    if (threadIdx.x == 0) {
-        long long k = st->k, above = 0;
-        int d = (1 << bits) - 1;
-        for (; d > 0; --d) {
-            if (above + (long long)hist[d] >= k) break;
-            above += (long long)hist[d];
-        }
-        st->k = k - above;
-        st->prefix |= (unsigned long long)d << shift;
-    }
-    __syncthreads();
-    for (int i = (int)threadIdx.x; i < kDigits; i += (int)blockDim.x) hist[i] = 0ull;
-}
-
-__global__ __launch_bounds__(kThreads) void k_count_eq(const double *__restrict__ f, long long n,
-                                                       const SelectState *st, long long *counts)
-{
-    __shared__ int wsum[kThreads / 64];
-    const unsigned long long T = st->prefix;
-    const long long base = (long long)blockIdx.x * kChunk;
-    int c = 0;
-    for (int it = 0; it < kChunk / kThreads; ++it) {
-        const long long i = base + it * kThreads + threadIdx.x;
-        if (i < n && key_of(f[i]) == T) ++c;
-    }
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        long long t = 0;
-        for (int w = 0; w < kThreads / 64; ++w) t += wsum[w];
-        counts[blockIdx.x] = t;
-    }
-}
-
-// exclusive scan of the per-chunk counts, one workgroup: each thread scans a
-// contiguous segment
-__global__ __launch_bounds__(kThreads) void k_scan(long long *counts, int nchunks)
-{
-    __shared__ long long seg[kThreads];
-    const int per = (nchunks + kThreads - 1) / kThreads;
-    const int b0 = (int)threadIdx.x * per, b1 = min(nchunks, b0 + per);
-    long long s = 0;
-    for (int b = b0; b < b1; ++b) s += counts[b];
-    seg[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        long long run = 0;
-        for (int t = 0; t < kThreads; ++t) {
-            const long long v = seg[t];
-            seg[t] = run;
-            run += v;
-        }
-    }
-    __syncthreads();
-    long long run = seg[threadIdx.x];
-    for (int b = b0; b < b1; ++b) {
-        const long long v = counts[b];
-        counts[b] = run;
-        run += v;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_mark(const double *__restrict__ f, long long n, const SelectState *st,
-                                                   const long long *__restrict__ offsets, uint8_t *mask)
-{
-    __shared__ int wcount[kThreads / 64];
-    const unsigned long long T = st->prefix;
-    const long long need = st->k;
-    const long long base = (long long)blockIdx.x * kChunk;
-    long long run = offsets[blockIdx.x];
-    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
-    for (int it = 0; it < kChunk / kThreads; ++it) {
-        const long long i = base + it * kThreads + threadIdx.x;
-        unsigned long long key = 0ull;
-        if (i < n) key = key_of(f[i]);
-        const bool eq = i < n && key == T;
-        const unsigned long long bal = __ballot(eq);
-        const int before = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) wcount[wave] = __popcll(bal);
-        __syncthreads();
-        int woff = 0;
-        for (int w = 0; w < wave; ++w) woff += wcount[w];
-        int tot = 0;
-        for (int w = 0; w < kThreads / 64; ++w) tot += wcount[w];
-        if (i < n) mask[i] = (uint8_t)(key > T || (eq && run + woff + before < need));
-        run += tot;
-        __syncthreads();
-    }
-}
-
-__global__ void k_fill_u8(uint8_t *p, long long n, uint8_t v)
-{
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
-__global__ void k_init_state(SelectState *st, unsigned long long *hist, long long k)
-{
-    if (threadIdx.x == 0) {
-        st->prefix = 0ull;
-        st->k = k;
-    }
-    for (int i = (int)threadIdx.x; i < kDigits; i += (int)blockDim.x) hist[i] = 0ull;
-}
-
-// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 constexpr size_t kAlign = 256;
@@ -899,12 +751,7 @@ int ch_time(hipStream_t s, bool begin)
     return MC_OK;
 }
 
-size_t rank_ws_bytes(int64_t n)
-{
-    const size_t nchunks = (size_t)((n + kChunk - 1) / kChunk);
-    return align_up(sizeof(SelectState)) + align_up(sizeof(unsigned long long) * kDigits) +
-           align_up(sizeof(long long) * nchunks);
-}
+size_t rank_ws_bytes(int64_t n) { return pmc::sel::workspace_bytes((long long)n); }
 
 }  // namespace
 
@@ -1031,32 +878,7 @@ int mc_rank_threshold(const double *field, int64_t n, int64_t n_pore, uint8_t *m
     if (n_pore < 0 || n_pore > n) return fail(MC_EINVAL, "n_pore must be in [0, n]");
     const size_t need = rank_ws_bytes(n);
     if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    hipStream_t s = (hipStream_t)hip_stream;
-    const unsigned grid = (unsigned)std::min<long long>(4096, (n + kThreads - 1) / kThreads);
-    if (n_pore == 0 || n_pore == n) {
-        hipLaunchKernelGGL(k_fill_u8, dim3(grid), dim3(kThreads), 0, s, mask, (long long)n,
-                           (uint8_t)(n_pore == n ? 1 : 0));
-        HIP_TRY(hipGetLastError());
-        return MC_OK;
-    }
-    char *b = (char *)workspace;
-    SelectState *st = (SelectState *)b;
-    unsigned long long *hist = (unsigned long long *)(b + align_up(sizeof(SelectState)));
-    long long *counts = (long long *)(b + align_up(sizeof(SelectState)) + align_up(sizeof(unsigned long long) * kDigits));
-    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(kThreads), 0, s, st, hist, (long long)n_pore);
-    // digits from the top: bits 63..53, 52..42, 41..31, 30..20, 19..9, 8..0
-    for (int shift = 64 - kDigitBits; shift > -kDigitBits; shift -= kDigitBits) {
-        const int sh = std::max(shift, 0);
-        const int bits = shift >= 0 ? kDigitBits : kDigitBits + shift;
-        hipLaunchKernelGGL(k_hist, dim3(grid), dim3(kThreads), 0, s, field, (long long)n, st, hist, sh, bits);
-        hipLaunchKernelGGL(k_select, dim3(1), dim3(kThreads), 0, s, st, hist, sh, bits);
-    }
-    const long long nchunks = (n + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_count_eq, dim3((unsigned)nchunks), dim3(kThreads), 0, s, field, (long long)n, st, counts);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kThreads), 0, s, counts, (int)nchunks);
-    hipLaunchKernelGGL(k_mark, dim3((unsigned)nchunks), dim3(kThreads), 0, s, field, (long long)n, st, counts, mask);
-    HIP_TRY(hipGetLastError());
-    return MC_OK;
+    return pmc::sel::enqueue_top(field, (long long)n, (long long)n_pore, mask, workspace, (hipStream_t)hip_stream);
 }
 
 size_t mc_ch_generate_workspace_bytes(const mc_ch_grid *g)

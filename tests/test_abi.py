@@ -12,7 +12,7 @@ import pytest
 from paper_2604_13929_amd import photonmc as pm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("photonmc.h", "spinodal.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("photonmc.h", "spinodal.h", "analytics.h")]
 
 
 def declared_functions():

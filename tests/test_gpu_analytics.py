@@ -1,0 +1,165 @@
+"""Analytics of Sec. 3.4 on the GPU (include/analytics.h) against the oracle
+(oracle/analytics.py), through the C ABI:
+
+* chord histograms bit-exact on every axis (small masks, M1, and at 256^3 against
+  an independent vectorised count);
+* the depth-normalised phase contrast of a GPU run's depth profiles;
+* escape-path histograms: bit-exact against the oracle's binning of the same
+  per-photon records, and summing exactly to the walk's own escape channels;
+* brightest-decile co-localisation per slice bit-exact on a GPU fluence tally;
+* the pore distance transform bit-exact against scipy's (M1, ragged sizes, 256^3),
+  with the all-pore and all-solid cases.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import analytics as oan
+from paper_2604_13929_amd import analytics as an
+from paper_2604_13929_amd import inputs
+from paper_2604_13929_amd import photonmc as pm
+
+pytestmark = pytest.mark.gpu
+W1 = 2 ** 31
+SEED = 20260809
+f32 = lambda x: float(np.float32(x))  # noqa: E731
+OPT = pm.Optics(0.5, f32(0.01), f32(0.7))
+
+
+def banner(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pm.load()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def runs_vectorised(mask: np.ndarray, np_axis: int) -> np.ndarray:
+    """Chord histogram by change points, all lines at once (independent of the oracle's loop)."""
+    m = np.moveaxis(mask, np_axis, -1).reshape(-1, mask.shape[np_axis]).astype(np.int16)
+    L, n = m.shape
+    flip = np.ones((L, 1), dtype=np.int16) * 2
+    edges = np.diff(np.concatenate([flip, m, flip], axis=1), axis=1) != 0
+    hist = np.zeros((2, n + 1), dtype=np.int64)
+    for ph in (0, 1):
+        # start positions of runs of phase ph and their lengths
+        rows, cols = np.nonzero(edges[:, :-1] & (m == ph))
+        starts = cols
+        # run end: next edge after the start within the row
+        ends = np.empty_like(starts)
+        e_rows, e_cols = np.nonzero(edges[:, 1:])
+        key = e_rows.astype(np.int64) * (n + 1) + e_cols
+        q = np.searchsorted(key, rows.astype(np.int64) * (n + 1) + starts)
+        ends = key[q] - rows.astype(np.int64) * (n + 1)
+        np.add.at(hist[ph], ends - starts + 1, 1)
+    return hist
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 9), (16, 3, 11), (1, 4, 4)])
+def test_chords_small(shape):
+    banner(f"chord histograms, shape {shape}")
+    nz, ny, nx = shape
+    m = (np.random.default_rng(sum(shape)).random(shape) < 0.6).astype(np.uint8)
+    for axis in (0, 1, 2):
+        got = an.chord_histogram(dev(m), axis).cpu().numpy()
+        assert np.array_equal(got, oan.chord_histogram(m, axis=2 - axis)), axis
+
+
+def test_chords_m1_and_fullsize(mask_m1):
+    banner("chord histograms M1 (vs oracle) and 256^3 (vs vectorised count)")
+    for axis in (0, 1, 2):
+        assert np.array_equal(an.chord_histogram(dev(mask_m1), axis).cpu().numpy(),
+                              oan.chord_histogram(mask_m1, axis=2 - axis))
+    wl = inputs.WORKLOADS["M2a"]
+    m = inputs.spinodal_mask(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], wl["porosity"], seed=0)
+    h = an.chord_histogram(dev(m), 2).cpu().numpy()
+    assert np.array_equal(h, runs_vectorised(m, 0))
+    lengths = np.arange(h.shape[1])
+    assert (lengths * h[1]).sum() == m.sum() and (lengths * h[0]).sum() == (m == 0).sum()
+    st = oan.chord_stats(h, thresholds=(25, 51))
+    print(f"256^3 phi 0.70 along z: mean pore chord {st['mean_pore']:.2f}, solid {st['mean_solid']:.2f}, "
+          f"ratio {st['mean_pore'] / st['mean_solid']:.3f} (phi/(1-phi) = {0.7 / 0.3:.3f})")
+
+
+def test_phase_contrast(mask_m1):
+    banner("phase contrast of a GPU run's depth profiles")
+    d = dev(mask_m1)
+    _, depth, _ = pm.reduce_async(d, pm.run(d, OPT, 200_000, SEED))     # device double[3][nz]
+    dn = depth.cpu().numpy()
+    for z0 in (0, 10):
+        got = an.phase_contrast(depth, z0)
+        want = oan.phase_contrast(dn[0], dn[1], dn[2], z0)
+        for k in ("solid_mean", "solid_sd", "pore_mean", "pore_sd"):
+            assert abs(got[k] - want[k]) <= 1e-12 * abs(want[k]), k
+        assert got["depths"] == want["depths"]
+    phi_z = mask_m1.mean(axis=(1, 2))
+    got = an.phase_contrast(depth, 0)
+    # the exact decomposition phi c_pore + (1 - phi) c_solid = 1 holds per depth, so the means obey it on average
+    assert abs((phi_z * (dn[2] / dn[0]) + (1 - phi_z) * (dn[1] / dn[0])).mean() - 1.0) < 1e-12
+
+
+def test_escape_paths(mask_m1):
+    banner("escape path histograms vs oracle binning and the walk's channels")
+    n = 200_000
+    d = dev(mask_m1)
+    nz = mask_m1.shape[0]
+    thr = (float(nz), 25.0, 3.0)
+    res = an.escape_paths(d, OPT, n, SEED, bin_width=2.0, nbins=64, thresholds=thr)
+    rec = res["outcomes"].cpu().numpy().reshape(-1).view(pm.PHOTON_DTYPE)
+    hw, hn, aw, an_ = oan.escape_path_histogram(rec["fate"], rec["w_final"], rec["path_void"], 2.0, 64, thr)
+    assert np.array_equal(res["hist_w"].cpu().numpy(), hw) and np.array_equal(res["hist_n"].cpu().numpy(), hn)
+    assert np.array_equal(res["above_w"].cpu().numpy(), aw) and np.array_equal(res["above_n"].cpu().numpy(), an_)
+    run = pm.run(d, OPT, n, SEED).scalar_dict()
+    assert hw.sum() == run["esc_w"] and hn.sum() == run["esc_n"]
+    assert aw[0] == run["esc_w_gtL"] and an_[0] == run["esc_n_gtL"]
+
+
+def test_bright_colocalization(mask_m1):
+    banner("brightest-decile co-localisation per slice vs oracle")
+    d = dev(mask_m1)
+    F = pm.run(d, OPT, 100_000, SEED).fluence
+    for z0, frac in ((0, 0.1), (12, 0.1), (5, 0.37)):
+        k, s = an.bright_colocalization(d, F, z0, frac)
+        kw, sw = oan.bright_colocalization(F.cpu().numpy(), mask_m1, z0, frac)
+        assert np.array_equal(k.cpu().numpy(), kw) and np.array_equal(s.cpu().numpy(), sw)
+    # ties: a constant slice takes the lowest indices
+    Fc = torch.zeros_like(F)
+    k, s = an.bright_colocalization(d, Fc, 0, 0.1)
+    kw, sw = oan.bright_colocalization(Fc.cpu().numpy(), mask_m1, 0, 0.1)
+    assert np.array_equal(s.cpu().numpy(), sw)
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (17, 30, 20), (9, 1, 33), (40, 5, 1)])
+def test_pore_distance(shape, mask_m1):
+    banner(f"pore distance transform vs scipy, shape {shape}")
+    nz, ny, nx = shape
+    if shape == (32, 32, 32):
+        m = mask_m1
+    else:
+        m = (np.random.default_rng(nx + ny).random(shape) < 0.8).astype(np.uint8)
+        m.flat[0] = 0
+    got = an.pore_distance(dev(m)).cpu().numpy()
+    assert np.array_equal(got, oan.pore_distance(m))
+
+
+def test_pore_distance_degenerate_and_fullsize():
+    banner("pore distance: all solid, all pore, 256^3 vs scipy")
+    z = inputs.homogeneous_mask(6, 5, 4)
+    assert np.all(an.pore_distance(dev(z)).cpu().numpy() == 0.0)
+    p = inputs.homogeneous_mask(6, 5, 4, pore=True)
+    assert np.all(np.isinf(an.pore_distance(dev(p)).cpu().numpy()))
+    wl = inputs.WORKLOADS["M2a"]
+    m = inputs.spinodal_mask(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], wl["porosity"], seed=0)
+    got = an.pore_distance(dev(m)).cpu().numpy()
+    want = oan.pore_distance(m)
+    assert np.array_equal(got, want)
+    print(f"256^3 phi 0.70: mean pore distance {want[m == 1].mean():.3f} voxels, max {want.max():.2f}")
