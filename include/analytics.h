@@ -60,6 +60,23 @@ size_t mc_pore_distance_workspace_bytes(const mc_volume *vol);
 int mc_pore_distance(const mc_volume *vol, double *dist, void *workspace, size_t workspace_bytes,
                      void *hip_stream);
 
+/* Sec. 3.4, co-localisation: Spearman rank correlation, per slice z0 <= z < nz, between
+ * the fluence and the local pore size (the distance of mc_pore_distance) over the
+ * pore voxels of that slice.  Ties take the average of their ranks; rho is the
+ * Pearson correlation of the two rank vectors, NaN where a slice has fewer than two
+ * pore voxels or either rank vector is constant.
+ *   fluence      device int64[nz][ny][nx] (mc_run's tally)
+ *   rho          device double[nz - z0] (written)
+ *   n_pore       device int64[nz - z0]: pore voxels per slice (written)
+ * Needs nx * ny * (nz - z0) < 2^31.  Unlike the other calls this one synchronises
+ * the stream once: the number of pore voxels sizes the sorts.  The workspace query
+ * asks the HIP runtime for the current device's sort configuration and returns 0
+ * (with mc_last_error) for invalid arguments or when no device answers; the
+ * workspace it sizes is for the current device. */
+size_t mc_pore_spearman_workspace_bytes(const mc_volume *vol, int32_t z0);
+int mc_pore_spearman(const mc_volume *vol, const int64_t *fluence, int32_t z0, double *rho, int64_t *n_pore,
+                     void *workspace, size_t workspace_bytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

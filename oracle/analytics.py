@@ -16,14 +16,18 @@ photocatalytic aerogels", Sec. 3.4):
       distribution of the in-pore path, and the fractions above thresholds;
   co-localisation: on each deep slice z >= z0, the brightest decile of voxels by
       fluence and the fraction of it that is solid; the local pore size by a
-      Euclidean distance transform of the pore phase.
+      Euclidean distance transform of the pore phase, and, inside the pore phase of
+      each deep slice, the Spearman rank correlation of fluence with that size.
 Readings where the paper is silent (listed with their reasons in the design
 notes): chords cut by the slab faces count with their in-slab length; the
 brightest decile of a slice is its ceil(0.1 N) voxels of highest fluence with
 ties to the lower linear index (ranking inside one slice is what removing the
 depth trend amounts to); the distance transform is the distance from a pore voxel
 to the nearest solid voxel centre inside the volume (no periodic images), as
-scipy.ndimage.distance_transform_edt computes it.
+scipy.ndimage.distance_transform_edt computes it; the Spearman correlation takes
+tied values at their average rank (scipy.stats.spearmanr), is computed per slice
+z >= z0 over that slice's pore voxels, and is NaN where a slice has fewer than two
+pore voxels or a constant rank vector.
 """
 from __future__ import annotations
 
@@ -125,3 +129,31 @@ def pore_distance_brute(mask: np.ndarray) -> np.ndarray:
         else:
             out[tuple(idx)] = math.inf
     return out
+
+
+def pore_spearman(fluence: np.ndarray, mask: np.ndarray, z0: int):
+    """For each slice z >= z0: (rho, n_pore), the Spearman correlation between the
+    fluence and the pore distance transform over the pore voxels of the slice
+    (scipy.stats.spearmanr as one library step), NaN where undefined."""
+    from scipy import stats
+
+    m = np.asarray(mask, dtype=np.uint8)
+    dist = pore_distance(m)
+    nz = m.shape[0]
+    rho, npore = [], []
+    for z in range(z0, nz):
+        sel = m[z].ravel() == 1
+        f = np.asarray(fluence[z], dtype=np.float64).ravel()[sel]
+        d = dist[z].ravel()[sel]
+        npore.append(int(sel.sum()))
+        if f.size < 2 or np.all(f == f[0]) or np.all(d == d[0]):
+            rho.append(math.nan)
+        else:
+            rho.append(float(stats.spearmanr(f, d).statistic))
+    return np.array(rho, dtype=np.float64), np.array(npore, dtype=np.int64)
+
+
+def average_ranks_brute(x: np.ndarray) -> np.ndarray:
+    """1-based ranks with ties averaged, by counting: rank_i = #{x_j < x_i} + (#{x_j == x_i} + 1) / 2."""
+    x = np.asarray(x)
+    return np.array([(x < v).sum() + ((x == v).sum() + 1) / 2 for v in x], dtype=np.float64)

@@ -92,3 +92,21 @@ def pore_distance(mask: torch.Tensor) -> torch.Tensor:
     pm._check(L.mc_pore_distance(ctypes.byref(vol), _ptr(out), _ptr(ws), ws.numel(), pm._stream(dev)),
               "mc_pore_distance")
     return out
+
+
+def pore_spearman(mask: torch.Tensor, fluence: torch.Tensor, z0: int):
+    """Per slice z >= z0: (Spearman rho of fluence vs pore size over the pore voxels
+    as float64, pore voxel count as int64)."""
+    L = pm.load()
+    vol = pm.volume(mask)
+    dev = mask.device
+    nz = mask.shape[0]
+    rho = torch.empty(nz - z0, dtype=torch.float64, device=dev)
+    n = torch.empty(nz - z0, dtype=torch.int64, device=dev)
+    need = L.mc_pore_spearman_workspace_bytes(ctypes.byref(vol), int(z0))
+    if need == 0:
+        raise ValueError(f"mc_pore_spearman: no workspace size for z0={z0} and mask {tuple(mask.shape)}")
+    ws = pm.workspace(need, dev)
+    pm._check(L.mc_pore_spearman(ctypes.byref(vol), _ptr(fluence.contiguous()), int(z0), _ptr(rho), _ptr(n),
+                                 _ptr(ws), ws.numel(), pm._stream(dev)), "mc_pore_spearman")
+    return rho, n

@@ -9,14 +9,20 @@
 // neighbouring bytes), global 64-bit atomics for the histograms, the shared radix
 // select for the per-slice deciles, and the separable distance transform of
 // Felzenszwalb & Huttenlocher (2012): a two-sided scan along x, then the lower
-// envelope of parabolas along y and along z.
+// envelope of parabolas along y and along z.  The per-slice Spearman correlation
+// of fluence and pore size compacts each slice's pore voxels, sorts both keys per
+// slice with rocPRIM's segmented radix sort, and averages tied ranks by binary
+// search in the sorted segment.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+
+#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "analytics.h"
 #include "internal.hpp"
@@ -220,6 +226,223 @@ unsigned blocks_for(long long n) { return (unsigned)std::max<long long>(1, std::
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Pore-phase Spearman correlation (one workgroup per slice where noted).
+// Compaction of the pore voxels of slice z0 + s in index order: keys of fluence
+// and squared distance, segment offsets from a scan of the per-slice counts.
+__global__ void k_slice_pore_count(const uint8_t *__restrict__ mask, long long n_slice, int z0, long long *counts)
+{
+    const uint8_t *m = mask + (size_t)(z0 + blockIdx.x) * n_slice;
+    long long c = 0;
+    for (long long i = threadIdx.x; i < n_slice; i += blockDim.x) c += m[i] ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    __shared__ long long w[4];
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) counts[blockIdx.x] = w[0] + w[1] + w[2] + w[3];
+}
+
+__global__ void k_offsets(const long long *counts, int nseg, int *begin, int *end)
+{
+    if (threadIdx.x != 0) return;
+    long long run = 0;
+    for (int i = 0; i < nseg; ++i) {
+        begin[i] = (int)run;
+        run += counts[i];
+        end[i] = (int)run;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_compact(const uint8_t *__restrict__ mask, const long long *__restrict__ F,
+                                                 const int *__restrict__ g, long long n_slice, int z0,
+                                                 const int *__restrict__ begin, long long *kf, int *kd, int *pos)
+{
+    __shared__ int wcount[4];
+    const size_t base = (size_t)(z0 + blockIdx.x) * n_slice;
+    int run = begin[blockIdx.x];
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    for (long long i0 = 0; i0 < n_slice; i0 += 256) {
+        const long long i = i0 + threadIdx.x;
+        const bool p = i < n_slice && mask[base + i] != 0;
+        const unsigned long long bal = __ballot(p);
+        if (lane == 0) wcount[wave] = __popcll(bal);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < wave) off += wcount[w];
+            tot += wcount[w];
+        }
+        if (p) {
+            const int at = run + off + __popcll(bal & ((1ull << lane) - 1ull));
+            kf[at] = F[base + i];
+            kd[at] = g[base + i];
+            pos[at] = at;
+        }
+        run += tot;
+        __syncthreads();
+    }
+}
+
+// average rank (1-based; ties share the mean of their positions) of every element of
+// a sorted segment, written at its compact position
+template <typename K>
+__global__ void k_avg_rank(const K *__restrict__ sorted, const int *__restrict__ perm, const int *__restrict__ begin,
+                           const int *__restrict__ end, int nseg, int total, double *rank)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+        // the segment holding i
+        int lo_s = 0, hi_s = nseg - 1;
+        while (lo_s < hi_s) {
+            const int mid = (lo_s + hi_s + 1) >> 1;
+            if (begin[mid] <= i) lo_s = mid;
+            else hi_s = mid - 1;
+        }
+        const int b = begin[lo_s], e = end[lo_s];
+        const K v = sorted[i];
+        int lo = b, hi = (int)i;                 // first position with key == v
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sorted[mid] < v) lo = mid + 1;
+            else hi = mid;
+        }
+        int lo2 = (int)i, hi2 = e - 1;           // last position with key == v
+        while (lo2 < hi2) {
+            const int mid = (lo2 + hi2 + 1) >> 1;
+            if (sorted[mid] > v) hi2 = mid - 1;
+            else lo2 = mid;
+        }
+        rank[perm[i]] = 0.5 * (double)((lo - b) + (lo2 - b)) + 1.0;
+    }
+}
+
+// Pearson correlation of the two rank vectors of each segment, centred on the exact
+// mean rank (n + 1)/2; fixed summation order per workgroup
+__global__ __launch_bounds__(256) void k_rank_corr(const double *__restrict__ rf, const double *__restrict__ rd,
+                                                   const int *__restrict__ begin, const int *__restrict__ end,
+                                                   double *rho, long long *npore)
+{
+    __shared__ double sh[3][256];
+    const int b = begin[blockIdx.x], e = end[blockIdx.x];
+    const double m = 0.5 * (double)(e - b + 1);
+    double sxy = 0.0, sxx = 0.0, syy = 0.0;
+    for (int i = b + (int)threadIdx.x; i < e; i += 256) {
+        const double x = rf[i] - m, y = rd[i] - m;
+        sxy += x * y;
+        sxx += x * x;
+        syy += y * y;
+    }
+    sh[0][threadIdx.x] = sxy;
+    sh[1][threadIdx.x] = sxx;
+    sh[2][threadIdx.x] = syy;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        npore[blockIdx.x] = e - b;
+        rho[blockIdx.x] = (sh[1][0] > 0.0 && sh[2][0] > 0.0) ? sh[0][0] / sqrt(sh[1][0] * sh[2][0]) : NAN;
+    }
+}
+
+struct EdtScratch {
+    int *g, *sv, *sf;
+    double *sz;
+    long long C;
+};
+
+EdtScratch edt_layout(const mc_volume *vol, void *ws)
+{
+    const size_t nvox = (size_t)vol->nx * vol->ny * vol->nz;
+    const int nmax = std::max(vol->ny, vol->nz);
+    const long long lines = std::max((long long)vol->nx * vol->nz, (long long)vol->nx * vol->ny);
+    EdtScratch e;
+    e.C = std::min<long long>(kEdtChunk, lines);
+    char *b = (char *)ws;
+    e.g = (int *)b;
+    e.sv = (int *)(b + align256(nvox * sizeof(int)));
+    e.sf = (int *)((char *)e.sv + align256((size_t)e.C * (nmax + 1) * sizeof(int)));
+    e.sz = (double *)((char *)e.sf + align256((size_t)e.C * (nmax + 1) * sizeof(int)));
+    return e;
+}
+
+size_t edt_bytes(const mc_volume *vol)
+{
+    const size_t nvox = (size_t)vol->nx * vol->ny * vol->nz;
+    const int nmax = std::max(vol->ny, vol->nz);
+    const long long lines = std::max((long long)vol->nx * vol->nz, (long long)vol->nx * vol->ny);
+    const size_t C = (size_t)std::min<long long>(kEdtChunk, lines);
+    return align256(nvox * sizeof(int)) + align256(C * (nmax + 1) * sizeof(int)) * 2 +
+           align256(C * (nmax + 2) * sizeof(double));
+}
+
+// squared distances (int, kInf where no solid voxel exists) into e.g
+int enqueue_sqdist(const mc_volume *vol, const EdtScratch &e, hipStream_t s)
+{
+    const int nx = vol->nx, ny = vol->ny, nz = vol->nz;
+    const long long xl = (long long)ny * nz;
+    hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((xl + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, vol->mask, nx, xl,
+                       e.g);
+    for (int axis = 1; axis <= 2; ++axis) {
+        const int n = axis == 1 ? ny : nz;
+        if (n == 1) continue;
+        const long long lines = (long long)nx * (axis == 1 ? nz : ny);
+        for (long long l0 = 0; l0 < lines; l0 += e.C) {
+            const long long cl = std::min(e.C, lines - l0);
+            hipLaunchKernelGGL(k_edt_env, dim3((unsigned)((cl + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, e.g, axis,
+                               n, l0, cl, nx, ny, e.sv, e.sf, e.sz);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+bool too_large(const mc_volume *vol)
+{
+    return (long long)vol->nx * vol->nx + (long long)vol->ny * vol->ny + (long long)vol->nz * vol->nz >= kInf;
+}
+
+// Spearman workspace layout after the distance transform's
+struct SpLayout {
+    size_t edt, counts, begin, end, kf, kd, pos, kf_s, kd_s, perm_f, perm_d, rf, rd, tmp, total;
+    size_t tmp_bytes;
+    hipError_t status;   // of rocPRIM's storage query (it asks the runtime for the device)
+};
+
+SpLayout sp_layout(const mc_volume *vol, int z0, long long npore_max, hipStream_t stream)
+{
+    SpLayout L;
+    const int nseg = vol->nz - z0;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t at = off; off += align256(bytes); return at; };
+    L.edt = take(edt_bytes(vol));
+    L.counts = take(sizeof(long long) * nseg);
+    L.begin = take(sizeof(int) * nseg);
+    L.end = take(sizeof(int) * nseg);
+    L.kf = take(sizeof(long long) * npore_max);
+    L.kd = take(sizeof(int) * npore_max);
+    L.pos = take(sizeof(int) * npore_max);
+    L.kf_s = take(sizeof(long long) * npore_max);
+    L.kd_s = take(sizeof(int) * npore_max);
+    L.perm_f = take(sizeof(int) * npore_max);
+    L.perm_d = take(sizeof(int) * npore_max);
+    L.rf = take(sizeof(double) * npore_max);
+    L.rd = take(sizeof(double) * npore_max);
+    // rocPRIM's temporary storage for the larger of the two sorts
+    size_t t1 = 0, t2 = 0;
+    L.status = rocprim::segmented_radix_sort_pairs(nullptr, t1, (const long long *)nullptr, (long long *)nullptr,
+                                        (const int *)nullptr, (int *)nullptr, (unsigned)npore_max, (unsigned)nseg,
+                                        (const int *)nullptr, (const int *)nullptr, 0, 64, stream);
+    if (L.status == hipSuccess)
+        L.status = rocprim::segmented_radix_sort_pairs(nullptr, t2, (const int *)nullptr, (int *)nullptr, (const int *)nullptr,
+                                        (int *)nullptr, (unsigned)npore_max, (unsigned)nseg, (const int *)nullptr,
+                                        (const int *)nullptr, 0, 32, stream);
+    L.tmp_bytes = std::max(t1, t2);
+    L.tmp = take(L.tmp_bytes);
+    L.total = off;
+    return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -324,12 +547,7 @@ size_t mc_pore_distance_workspace_bytes(const mc_volume *vol)
 {
     clear_error();
     if (check_volume(vol)) return 0;
-    const size_t nvox = (size_t)vol->nx * vol->ny * vol->nz;
-    const int nmax = std::max(vol->ny, vol->nz);
-    const long long lines = std::max((long long)vol->nx * vol->nz, (long long)vol->nx * vol->ny);
-    const size_t C = (size_t)std::min<long long>(kEdtChunk, lines);
-    return align256(nvox * sizeof(int)) + align256(C * (nmax + 1) * sizeof(int)) * 2 +
-           align256(C * (nmax + 2) * sizeof(double));
+    return edt_bytes(vol);
 }
 
 int mc_pore_distance(const mc_volume *vol, double *dist, void *workspace, size_t workspace_bytes, void *hip_stream)
@@ -340,33 +558,92 @@ int mc_pore_distance(const mc_volume *vol, double *dist, void *workspace, size_t
     if (!dist || !workspace) return fail(MC_EINVAL, "NULL argument");
     const size_t need = mc_pore_distance_workspace_bytes(vol);
     if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    if ((long long)vol->nx * vol->nx + (long long)vol->ny * vol->ny + (long long)vol->nz * vol->nz >= kInf)
-        return fail(MC_EINVAL, "volume too large for 32-bit squared distances");
+    if (too_large(vol)) return fail(MC_EINVAL, "volume too large for 32-bit squared distances");
     hipStream_t s = (hipStream_t)hip_stream;
-    const int nx = vol->nx, ny = vol->ny, nz = vol->nz;
-    const size_t nvox = (size_t)nx * ny * nz;
-    const int nmax = std::max(ny, nz);
-    const long long max_lines = std::max((long long)nx * nz, (long long)nx * ny);
-    const long long C = std::min<long long>(kEdtChunk, max_lines);
-    char *b = (char *)workspace;
-    int *g = (int *)b;
-    int *sv = (int *)(b + align256(nvox * sizeof(int)));
-    int *sf = (int *)((char *)sv + align256((size_t)C * (nmax + 1) * sizeof(int)));
-    double *sz = (double *)((char *)sf + align256((size_t)C * (nmax + 1) * sizeof(int)));
-    const long long xl = (long long)ny * nz;
-    hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((xl + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, vol->mask, nx, xl,
-                       g);
-    for (int axis = 1; axis <= 2; ++axis) {
-        const int n = axis == 1 ? ny : nz;
-        if (n == 1) continue;
-        const long long lines = (long long)nx * (axis == 1 ? nz : ny);
-        for (long long l0 = 0; l0 < lines; l0 += C) {
-            const long long cl = std::min(C, lines - l0);
-            hipLaunchKernelGGL(k_edt_env, dim3((unsigned)((cl + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, g, axis,
-                               n, l0, cl, nx, ny, sv, sf, sz);
-        }
-    }
+    const size_t nvox = (size_t)vol->nx * vol->ny * vol->nz;
+    const EdtScratch e = edt_layout(vol, workspace);
+    if ((rc = enqueue_sqdist(vol, e, s))) return rc;
+    int *g = e.g;
     hipLaunchKernelGGL(k_edt_out, dim3(blocks_for((long long)nvox)), dim3(kThreads), 0, s, g, (long long)nvox, dist);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+size_t mc_pore_spearman_workspace_bytes(const mc_volume *vol, int32_t z0)
+{
+    clear_error();
+    if (check_volume(vol) || z0 < 0 || z0 >= vol->nz) return 0;
+    const long long npore_max = (long long)vol->nx * vol->ny * (vol->nz - z0);
+    if (npore_max >= 0x7fffffffLL) return 0;
+    const SpLayout L = sp_layout(vol, z0, npore_max, (hipStream_t)0);
+    if (L.status != hipSuccess) {
+        fail(MC_EHIP, "sizing the segmented sort: %s", hipGetErrorString(L.status));
+        return 0;
+    }
+    return L.total;
+}
+
+int mc_pore_spearman(const mc_volume *vol, const int64_t *fluence, int32_t z0, double *rho, int64_t *n_pore,
+                     void *workspace, size_t workspace_bytes, void *hip_stream)
+{
+    clear_error();
+    int rc = check_volume(vol);
+    if (rc) return rc;
+    if (!fluence || !rho || !n_pore || !workspace) return fail(MC_EINVAL, "NULL argument");
+    if (z0 < 0 || z0 >= vol->nz) return fail(MC_EINVAL, "need 0 <= z0 < nz");
+    if (too_large(vol)) return fail(MC_EINVAL, "volume too large for 32-bit squared distances");
+    const long long n_slice = (long long)vol->nx * vol->ny;
+    const long long npore_max = n_slice * (vol->nz - z0);
+    if (npore_max >= 0x7fffffffLL) return fail(MC_EINVAL, "nx * ny * (nz - z0) must stay below 2^31");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const SpLayout L = sp_layout(vol, z0, npore_max, s);
+    if (L.status != hipSuccess) return fail(MC_EHIP, "sizing the segmented sort: %s", hipGetErrorString(L.status));
+    if (workspace_bytes < L.total) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    char *b = (char *)workspace;
+    const EdtScratch e = edt_layout(vol, b + L.edt);
+    if ((rc = enqueue_sqdist(vol, e, s))) return rc;
+    const int nseg = vol->nz - z0;
+    long long *counts = (long long *)(b + L.counts);
+    int *begin = (int *)(b + L.begin), *end = (int *)(b + L.end);
+    long long *kf = (long long *)(b + L.kf), *kf_s = (long long *)(b + L.kf_s);
+    int *kd = (int *)(b + L.kd), *kd_s = (int *)(b + L.kd_s), *pos = (int *)(b + L.pos);
+    int *perm_f = (int *)(b + L.perm_f), *perm_d = (int *)(b + L.perm_d);
+    double *rf = (double *)(b + L.rf), *rd = (double *)(b + L.rd);
+    hipLaunchKernelGGL(k_slice_pore_count, dim3(nseg), dim3(256), 0, s, vol->mask, n_slice, z0, counts);
+    hipLaunchKernelGGL(k_offsets, dim3(1), dim3(64), 0, s, counts, nseg, begin, end);
+    hipLaunchKernelGGL(k_compact, dim3(nseg), dim3(256), 0, s, vol->mask, (const long long *)fluence, e.g, n_slice, z0,
+                       begin, kf, kd, pos);
+    HIP_TRY(hipGetLastError());
+    // the total number of pore voxels decides the sort sizes: bring it to the host
+    long long total = 0;
+    {
+        long long *h = (long long *)malloc(sizeof(long long) * nseg);
+        if (!h) return fail(MC_EINVAL, "host allocation failed");
+        const hipError_t err = hipMemcpyAsync(h, counts, sizeof(long long) * nseg, hipMemcpyDeviceToHost, s);
+        const hipError_t err2 = err == hipSuccess ? hipStreamSynchronize(s) : err;
+        if (err2 != hipSuccess) {
+            free(h);
+            return fail(MC_EHIP, "reading the pore counts: %s", hipGetErrorString(err2));
+        }
+        for (int i = 0; i < nseg; ++i) total += h[i];
+        free(h);
+    }
+    if (total > 0) {
+        size_t tmp = L.tmp_bytes;
+        HIP_TRY(rocprim::segmented_radix_sort_pairs(b + L.tmp, tmp, (const long long *)kf, kf_s, (const int *)pos, perm_f,
+                                                    (unsigned)total, (unsigned)nseg, (const int *)begin,
+                                                    (const int *)end, 0, 64, s));
+        tmp = L.tmp_bytes;
+        HIP_TRY(rocprim::segmented_radix_sort_pairs(b + L.tmp, tmp, (const int *)kd, kd_s, (const int *)pos, perm_d,
+                                                    (unsigned)total, (unsigned)nseg, (const int *)begin,
+                                                    (const int *)end, 0, 32, s));
+        hipLaunchKernelGGL(k_avg_rank<long long>, dim3(blocks_for(total)), dim3(256), 0, s, (const long long *)kf_s,
+                           (const int *)perm_f, (const int *)begin, (const int *)end, nseg, (int)total, rf);
+        hipLaunchKernelGGL(k_avg_rank<int>, dim3(blocks_for(total)), dim3(256), 0, s, (const int *)kd_s,
+                           (const int *)perm_d, (const int *)begin, (const int *)end, nseg, (int)total, rd);
+    }
+    hipLaunchKernelGGL(k_rank_corr, dim3(nseg), dim3(256), 0, s, (const double *)rf, (const double *)rd,
+                       (const int *)begin, (const int *)end, rho, (long long *)n_pore);
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }

@@ -94,6 +94,11 @@ def test_workspace_sizes(lib):
     assert lib.mc_reduce_workspace_bytes(ctypes.byref(vol)) == 7 * 8 * 8
     bad = pm.McVolume(0, 5, 7, 0, 1)
     assert lib.mc_run_workspace_bytes(ctypes.byref(bad)) == 0
+    # the Spearman analytics: z0 outside [0, nz) sizes nothing; NULL outputs are refused before any HIP call
+    assert lib.mc_pore_spearman_workspace_bytes(ctypes.byref(vol), 7) == 0
+    assert lib.mc_pore_spearman_workspace_bytes(ctypes.byref(vol), -1) == 0
+    assert lib.mc_pore_spearman(ctypes.byref(vol), None, 0, None, None, None, 0, None) == -1
+    assert b"NULL" in lib.mc_last_error()
 
 
 def _job(nx=8, ny=8, nz=8, mask=1, n=10, mu_s=0.5, g=0.7):

@@ -163,3 +163,51 @@ def test_pore_distance_degenerate_and_fullsize():
     want = oan.pore_distance(m)
     assert np.array_equal(got, want)
     print(f"256^3 phi 0.70: mean pore distance {want[m == 1].mean():.3f} voxels, max {want.max():.2f}")
+
+
+def test_pore_spearman(mask_m1):
+    banner("pore Spearman correlation per slice vs oracle (M1, ties, degenerate slices)")
+    d = dev(mask_m1)
+    F = pm.run(d, OPT, 200_000, SEED).fluence
+    Fn = F.cpu().numpy()
+    for z0 in (0, 16, 31):
+        rho, n = an.pore_spearman(d, F, z0)
+        rw, nw = oan.pore_spearman(Fn, mask_m1, z0)
+        assert np.array_equal(n.cpu().numpy(), nw)
+        r = rho.cpu().numpy()
+        assert np.array_equal(np.isnan(r), np.isnan(rw))
+        ok = ~np.isnan(rw)
+        assert np.all(np.abs(r[ok] - rw[ok]) <= 1e-12), np.abs(r[ok] - rw[ok]).max()
+    # heavy ties (quantised fluence) and slices with 0, 1 and all pore voxels
+    rng = np.random.default_rng(9)
+    m = (rng.random((6, 9, 11)) < 0.7).astype(np.uint8)
+    m[1] = 0
+    m[2] = 0
+    m[2, 4, 5] = 1
+    m[3] = 1
+    Fq = rng.integers(0, 4, size=m.shape).astype(np.int64)
+    rho, n = an.pore_spearman(dev(m), dev(Fq), 0)
+    rw, nw = oan.pore_spearman(Fq, m, 0)
+    assert np.array_equal(n.cpu().numpy(), nw)
+    r = rho.cpu().numpy()
+    assert np.array_equal(np.isnan(r), np.isnan(rw)), (r, rw)
+    ok = ~np.isnan(rw)
+    assert np.all(np.abs(r[ok] - rw[ok]) <= 1e-12)
+
+
+def test_pore_spearman_fullsize():
+    banner("pore Spearman correlation at 256^3, deep slices, vs oracle")
+    wl = inputs.WORKLOADS["M2a"]
+    m = inputs.spinodal_mask(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], wl["porosity"], seed=0)
+    d = dev(m)
+    F = pm.run(d, OPT, 2_000_000, SEED).fluence
+    z0 = 26                                   # 0.1 of the depth, as in the paper's deep cross-sections
+    rho, n = an.pore_spearman(d, F, z0)
+    rw, nw = oan.pore_spearman(F.cpu().numpy(), m, z0)
+    assert np.array_equal(n.cpu().numpy(), nw)
+    r = rho.cpu().numpy()
+    ok = ~np.isnan(rw)
+    assert np.array_equal(np.isnan(r), ~ok)
+    assert np.all(np.abs(r[ok] - rw[ok]) <= 1e-12)
+    print(f"256^3 phi 0.70, z >= {z0}: rho = {np.nanmean(rw):+.4f} +- {np.nanstd(rw, ddof=1):.4f} "
+          f"over {ok.sum()} slices")

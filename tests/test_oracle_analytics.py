@@ -3,7 +3,9 @@ itself: hand-counted chords and an independent run-length count, conservation of
 phase volume, the mean-chord ratio phi/(1 - phi) on lines with as many pore as
 solid chords, the exact per-depth decomposition phi(z) c_pore + (1 - phi(z)) c_solid
 = 1, the escape histograms against the walk's own escape channels, brute-force
-brightest deciles, and the distance transform against brute force."""
+brightest deciles, the distance transform against brute force, and the per-slice
+Spearman correlation against rank counting, the no-ties closed form
+1 - 6 sum d^2 / (n (n^2 - 1)) and its +-1 limits."""
 from __future__ import annotations
 
 import math
@@ -114,3 +116,51 @@ def test_pore_distance_brute_force():
     for seed in (5, 6):
         m = inputs.spinodal_mask(9, 7, 8, 4.0, 0.7, seed=seed)
         assert np.array_equal(an.pore_distance(m), an.pore_distance_brute(m))
+
+
+def _pearson(a, b):
+    a = a - a.mean()
+    b = b - b.mean()
+    return float((a * b).sum() / math.sqrt((a * a).sum() * (b * b).sum()))
+
+
+def test_pore_spearman_pins():
+    # no ties: the closed form on rank differences
+    rng = np.random.default_rng(8)
+    x, y = rng.permutation(30).astype(float), rng.permutation(30).astype(float)
+    n = 30
+    closed = 1 - 6 * ((x - y) ** 2).sum() / (n * (n * n - 1))
+    m = np.ones((1, 5, 6), dtype=np.uint8)
+    m[0, 0, 0] = 0                                   # one solid voxel: distances vary
+    dist = an.pore_distance(m)[0].ravel()
+    # fluence equal to a strictly increasing function of the distance -> rho = +1, decreasing -> -1
+    F = np.argsort(np.argsort(dist, kind="stable"), kind="stable").reshape(1, 5, 6) * 3 + 7
+    sel = m[0].ravel() == 1
+    # ties in the distance: Pearson of counted average ranks, whatever the fluence
+    rho_up, npore = an.pore_spearman(F, m, 0)
+    assert npore[0] == 29
+    want = _pearson(an.average_ranks_brute(F[0].ravel()[sel]), an.average_ranks_brute(dist[sel]))
+    assert math.isclose(rho_up[0], want, rel_tol=1e-12) and rho_up[0] > 0.9
+    rho_dn, _ = an.pore_spearman(-F, m, 0)
+    assert math.isclose(rho_dn[0], -want, rel_tol=1e-12)
+    assert math.isclose(_pearson(an.average_ranks_brute(x), an.average_ranks_brute(y)), closed, rel_tol=1e-12)
+    # distances without ties: a single row, solid at one end -> distance strictly increasing
+    m2 = np.ones((1, 1, 31), dtype=np.uint8)
+    m2[0, 0, 0] = 0
+    F2 = np.zeros((1, 1, 31), dtype=np.int64)
+    F2[0, 0, 1:] = x                                 # ranks of x against ranks 1..30 of the distance
+    r2, n2 = an.pore_spearman(F2, m2, 0)
+    closed2 = 1 - 6 * ((np.argsort(np.argsort(x)) - np.arange(30)) ** 2).sum() / (n * (n * n - 1))
+    assert n2[0] == 30 and math.isclose(r2[0], closed2, rel_tol=1e-12)
+    # degenerate slices: constant fluence, one pore voxel, no pore voxel
+    m3 = np.zeros((3, 2, 2), dtype=np.uint8)
+    m3[0] = 1
+    m3[0, 0, 0] = 0
+    m3[1, 1, 1] = 1
+    r3, n3 = an.pore_spearman(np.ones((3, 2, 2), dtype=np.int64), m3, 0)
+    assert list(n3) == [3, 1, 0] and np.all(np.isnan(r3))
+
+
+def test_average_ranks_against_hand_count():
+    r = an.average_ranks_brute(np.array([10, 20, 20, 5, 20]))
+    assert list(r) == [2.0, 4.0, 4.0, 1.0, 4.0]
