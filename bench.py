@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import platform
 import sys
@@ -348,6 +349,113 @@ def ch_leg(args):
     return out
 
 
+def analytics_leg(args, seed, mask_np, mask):
+    """The Sec. 3.4 analytics on the tally of one paper-model run (configuration P with
+    the paper's shell optics, 1e8 photons) over the 256^3 phi = 0.70 mask: chord
+    histograms on all three axes, the pore distance transform, the brightest-decile
+    co-localisation and the pore-phase Spearman correlation on deep slices
+    (z >= 0.1 mm = slice 69 at 1.45 um voxels), the depth-normalised phase contrast,
+    and escape-path histograms of 1e7 traced photons.  Each call timed with events on
+    torch's current stream (the one the bindings launch on), warm (second call); the
+    oracle's co-localisation and Spearman on the same tally as the CPU reference and
+    parity check."""
+    import numpy as np
+    import torch
+
+    from paper_2604_13929_amd import analytics as an
+    from paper_2604_13929_amd import photonmc as pm
+
+    def f32(x):
+        return float(np.float32(x))
+
+    a_vox, nz, phi = 1.45e-6, mask_np.shape[0], float(mask_np.mean())
+    o = dict(mu_s=f32(20118.0 * a_vox), mu_a=f32(5159.0 * a_vox), g=0.0)
+    gate = pm.time_gate_voxels(o["mu_s"], o["mu_a"], o["g"], phi, nz, 1.746)
+    opt = pm.paper_optics(o["mu_s"], o["mu_a"], o["g"], n_solid=f32(1.746), lateral=pm.LATERAL_MIRROR, gate=gate)
+    n = args.photons
+    res = pm.run(mask, opt, n, seed)
+    _, depth, _ = pm.reduce_async(mask, res)
+    F = res.fluence
+    torch.cuda.synchronize()
+    z0 = int(math.ceil(0.1e-3 / a_vox))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = fn()
+        e1.record()
+        e1.synchronize()
+        return out, e0.elapsed_time(e1)
+
+    out = {"workload": "analytics of Sec. 3.4 on the paper-model tally (256^3 phi=0.70, paper optics, 1e8 photons)",
+           "deep_slice_z0": z0, "ms": {}}
+    hists = {}
+    for axis, name in ((0, "x"), (1, "y"), (2, "z")):
+        hists[name], out["ms"][f"chords_{name}"] = timed(lambda: an.chord_histogram(mask, axis))
+    hz = hists["z"].cpu().numpy().astype(np.float64)
+    lengths = np.arange(hz.shape[1], dtype=np.float64)
+    half = nz // 2
+    out["chords_z"] = {"mean_pore": float((lengths * hz[1]).sum() / hz[1].sum()),
+                       "mean_solid": float((lengths * hz[0]).sum() / hz[0].sum()),
+                       f"plen_pore_gt_{half}": float((lengths * hz[1])[lengths > half].sum() / (lengths * hz[1]).sum())}
+    dist, out["ms"]["pore_distance"] = timed(lambda: an.pore_distance(mask))
+    voxels = mask_np.size
+    # algorithmic bytes of the transform: mask read, g written, two envelope passes read and write g,
+    # the output pass reads g and writes the FP64 distance: 1 + 4 + 2 * 8 + 12 bytes per voxel
+    edt_bytes = 33 * voxels
+    out["pore_distance_gbs"] = edt_bytes / (out["ms"]["pore_distance"] * 1e-3) / 1e9
+    dn = dist.cpu().numpy()
+    out["mean_pore_distance_voxels"] = float(dn[mask_np == 1].mean())
+    del dist
+    (kk, ks), out["ms"]["bright_colocalization"] = timed(lambda: an.bright_colocalization(mask, F, z0, 0.1))
+    frac_solid = ks.cpu().numpy() / kk.cpu().numpy()
+    out["bright_decile_solid_fraction"] = {"mean": float(frac_solid.mean()), "sd": float(frac_solid.std(ddof=1)),
+                                           "solid_volume_fraction": 1.0 - phi, "slices": int(frac_solid.size)}
+    (rho, npore), out["ms"]["pore_spearman"] = timed(lambda: an.pore_spearman(mask, F, z0))
+    r = rho.cpu().numpy()
+    out["pore_spearman"] = {"mean": float(np.nanmean(r)), "sd": float(np.nanstd(r, ddof=1)),
+                            "slices": int(np.isfinite(r).sum())}
+    pc, out["ms"]["phase_contrast"] = timed(lambda: an.phase_contrast(depth, 0))
+    out["phase_contrast"] = {k: float(v) for k, v in pc.items()}
+    m_tr = 10_000_000
+    thr = (float(nz), 0.5 * nz)
+    eh, out["ms"]["escape_paths_trace_and_bin"] = timed(
+        lambda: an.escape_paths(mask, opt, m_tr, seed, bin_width=4.0, nbins=256, thresholds=thr))
+    aw = eh["above_w"].cpu().numpy()
+    esc_w = int(eh["hist_w"].sum().item())
+    out["escape_paths"] = {"photons": m_tr, "escaped_weight_fraction": esc_w / (m_tr * pm.W1),
+                           "weight_fraction_void_path_gt_L": float(aw[0]) / esc_w if esc_w else None,
+                           "weight_fraction_void_path_gt_L2": float(aw[1]) / esc_w if esc_w else None}
+    del eh
+    log("analytics: " + ", ".join(f"{k} {v:.2f} ms" for k, v in out["ms"].items()))
+    if not args.no_cpu:
+        from oracle import analytics as oan
+        Fn = F.cpu().numpy()
+        t0 = time.perf_counter()
+        kw, sw = oan.bright_colocalization(Fn, mask_np, z0, 0.1)
+        t1 = time.perf_counter()
+        rw, nw = oan.pore_spearman(Fn, mask_np, z0)
+        t2 = time.perf_counter()
+        ok = np.isfinite(rw)
+        out["cpu_baseline"] = {"kind": "oracle", "cores": 1, "unit": "ms",
+                               "bright_colocalization_ms": (t1 - t0) * 1e3,
+                               "pore_spearman_ms": (t2 - t1) * 1e3,
+                               "sample": "the same tally and mask; numpy stable argsort per slice, scipy EDT and "
+                                         "spearmanr per slice"}
+        out["oracle_match"] = {"bright_colocalization_exact": bool(np.array_equal(ks.cpu().numpy(), sw)
+                                                                   and np.array_equal(kk.cpu().numpy(), kw)),
+                               "pore_spearman_max_abs_diff": float(np.abs(r[ok] - rw[ok]).max()),
+                               "pore_spearman_nan_pattern_equal": bool(np.array_equal(np.isfinite(r), ok)),
+                               "pore_counts_exact": bool(np.array_equal(npore.cpu().numpy(), nw))}
+        log(f"analytics oracle: decile {(t1 - t0) * 1e3:.0f} ms, spearman {(t2 - t1) * 1e3:.0f} ms, "
+            f"match {out['oracle_match']}")
+    del F, res
+    torch.cuda.empty_cache()
+    return out
+
+
 def grad_oracle_check(seed, n=100_000, B=32):
     """GPU likelihood-ratio Jacobian (FP32 transport) on the 32^3 workload against the
     oracle's FP64 likelihood-ratio bins on the same photons: z-scores with the
@@ -442,6 +550,7 @@ def main():
     ap.add_argument("--no-rows", action="store_true", help="skip the 32^3 and phi = 0.90 rows")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper boundary model rows")
     ap.add_argument("--no-ch", action="store_true", help="skip the Cahn-Hilliard generator leg")
+    ap.add_argument("--no-analytics", action="store_true", help="skip the Sec. 3.4 analytics leg")
     ap.add_argument("--ch-steps", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true",
@@ -578,6 +687,8 @@ def main():
         line["paper_boundary"] = paper_leg(args, seed, mask_np, mask)
     if not args.no_ch:
         line["spinodal_generator"] = ch_leg(args)
+    if not args.no_analytics:
+        line["analytics"] = analytics_leg(args, seed, mask_np, mask)
     if not args.no_batch:
         line["batched"] = batched_leg(args, seed)
     if not args.no_morph:

@@ -45,12 +45,11 @@ int mc_escape_path_histogram(const mc_photon_rec *rec, int64_t n, double bin_wid
 
 /* Sec. 3.4, co-localisation: for each slice z0 <= z < nz the k = ceil(frac * nx * ny)
  * voxels of highest fluence (ties to the lower linear index) and how many of them
- * are solid.  fluence: device int64[nz][ny][nx] (mc_run's tally, values < 2^53).
+ * are solid; 0 < frac <= 1, nx * ny < 2^31.
+ *   fluence  device int64[nz][ny][nx] (mc_run's tally; any int64 values)
  *   top_count, top_solid  device int64[nz - z0] (written) */
-size_t mc_bright_colocalization_workspace_bytes(const mc_volume *vol);
 int mc_bright_colocalization(const mc_volume *vol, const int64_t *fluence, int32_t z0, double frac,
-                             int64_t *top_count, int64_t *top_solid, void *workspace, size_t workspace_bytes,
-                             void *hip_stream);
+                             int64_t *top_count, int64_t *top_solid, void *hip_stream);
 
 /* Local pore size (Sec. 3.4, co-localisation): the exact Euclidean distance from
  * every pore voxel centre to the nearest solid voxel centre inside the volume (no

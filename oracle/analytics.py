@@ -98,13 +98,16 @@ def escape_path_histogram(fate: np.ndarray, w_final: np.ndarray, path_void: np.n
 
 def bright_colocalization(fluence: np.ndarray, mask: np.ndarray, z0: int, frac: float = 0.1):
     """For each slice z >= z0: (k, solid_in_top) with k = ceil(frac * N_slice) voxels of
-    highest fluence, ties to the lower index (stable sort of -F)."""
+    highest fluence, ties to the lower index (stable ascending sort of a decreasing map
+    of F).  An integer tally is ranked as integers: ~F = -F - 1 reverses the order of
+    every int64 without overflow, so no two distinct tallies compare equal."""
     nz = fluence.shape[0]
     k_all, solid_all = [], []
     for z in range(z0, nz):
-        f = np.asarray(fluence[z], dtype=np.float64).ravel()
+        f = np.asarray(fluence[z]).ravel()
         k = int(math.ceil(frac * f.size))
-        top = np.argsort(-f, kind="stable")[:k]
+        rev = ~f if np.issubdtype(f.dtype, np.integer) else -f.astype(np.float64)
+        top = np.argsort(rev, kind="stable")[:k]
         k_all.append(k)
         solid_all.append(int((np.asarray(mask[z]).ravel()[top] == 0).sum()))
     return np.array(k_all, dtype=np.int64), np.array(solid_all, dtype=np.int64)
@@ -143,7 +146,7 @@ def pore_spearman(fluence: np.ndarray, mask: np.ndarray, z0: int):
     rho, npore = [], []
     for z in range(z0, nz):
         sel = m[z].ravel() == 1
-        f = np.asarray(fluence[z], dtype=np.float64).ravel()[sel]
+        f = np.asarray(fluence[z]).ravel()[sel]        # integer tallies ranked as integers
         d = dist[z].ravel()[sel]
         npore.append(int(sel.sum()))
         if f.size < 2 or np.all(f == f[0]) or np.all(d == d[0]):

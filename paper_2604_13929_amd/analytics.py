@@ -75,9 +75,8 @@ def bright_colocalization(mask: torch.Tensor, fluence: torch.Tensor, z0: int, fr
     nz = mask.shape[0]
     k = torch.empty(nz - z0, dtype=torch.int64, device=dev)
     s = torch.empty(nz - z0, dtype=torch.int64, device=dev)
-    ws = pm.workspace(L.mc_bright_colocalization_workspace_bytes(ctypes.byref(vol)), dev)
     pm._check(L.mc_bright_colocalization(ctypes.byref(vol), _ptr(fluence.contiguous()), int(z0), float(frac),
-                                         _ptr(k), _ptr(s), _ptr(ws), ws.numel(), pm._stream(dev)),
+                                         _ptr(k), _ptr(s), pm._stream(dev)),
               "mc_bright_colocalization")
     return k, s
 

@@ -6,8 +6,8 @@
 // These are scans over the mask, the fluence tally or per-photon records, so they
 // are bound by memory traffic or launch count, not arithmetic: one thread per line
 // for the line scans (lines laid out so that neighbouring threads read
-// neighbouring bytes), global 64-bit atomics for the histograms, the shared radix
-// select for the per-slice deciles, and the separable distance transform of
+// neighbouring bytes), global 64-bit atomics for the histograms, a radix select
+// per slice in one workgroup for the deciles, and the separable distance transform of
 // Felzenszwalb & Huttenlocher (2012): a two-sided scan along x, then the lower
 // envelope of parabolas along y and along z.  The per-slice Spearman correlation
 // of fluence and pore size compacts each slice's pore voxels, sorts both keys per
@@ -26,7 +26,6 @@
 
 #include "analytics.h"
 #include "internal.hpp"
-#include "select.hpp"
 
 using namespace pmc::host;
 
@@ -127,21 +126,122 @@ __global__ void k_escape_hist(const mc_photon_rec *__restrict__ rec, long long n
     }
 }
 
-__global__ void k_fill_value(long long *p, long long n, long long v)
+// Brightest fraction of one slice per workgroup: an MSB-first radix select over
+// the order-preserving key of the int64 tally (11-bit digits, six passes over the
+// slice, histograms in LDS) finds the k-th largest key T and how many keys equal to
+// T are taken; a pass in index order then takes every key above T and the first
+// `need` keys equal to T (ties to the lower index) and counts the solid voxels
+// among them.
+constexpr int kTopThreads = 1024;
+constexpr int kTopBits = 11;
+constexpr int kTopBins = 1 << kTopBits;
+
+__device__ __forceinline__ unsigned long long tally_key(long long v) { return (unsigned long long)v ^ 0x8000000000000000ull; }
+
+// inclusive prefix sum over the workgroup's threads in thread order
+__device__ __forceinline__ unsigned int block_inclusive_scan(unsigned int v, unsigned int *wsum)
 {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        p[i] = v;
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned int u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    unsigned int before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    __syncthreads();
+    return v + before;
 }
 
-// solid voxels among the marked ones of one slice, added to *out
-__global__ void k_count_solid(const uint8_t *__restrict__ top, const uint8_t *__restrict__ mask, long long n,
-                              unsigned long long *out)
+__global__ __launch_bounds__(kTopThreads) void k_slice_top(const long long *__restrict__ F, const uint8_t *__restrict__ mask,
+                                                          long long n, int z0, long long k, long long *top_count,
+                                                          long long *top_solid)
 {
-    unsigned long long c = 0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        c += (top[i] && mask[i] == 0) ? 1ull : 0ull;
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+    __shared__ unsigned int h[kTopBins];
+    __shared__ unsigned int wsum[kTopThreads / 64];
+    __shared__ unsigned long long s_prefix;
+    __shared__ long long s_k;
+    const size_t base = (size_t)(z0 + blockIdx.x) * (size_t)n;
+    const long long *f = F + base;
+    const uint8_t *m = mask + base;
+    const int t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) {
+        s_prefix = 0ull;
+        s_k = k;
+    }
+    // digits from the top: bits 63..53, 52..42, 41..31, 30..20, 19..9, 8..0
+    for (int shift = 64 - kTopBits; shift > -kTopBits; shift -= kTopBits) {
+        const int sh = shift > 0 ? shift : 0;
+        const int bits = shift >= 0 ? kTopBits : kTopBits + shift;
+        const int nb = 1 << bits;
+        for (int i = t; i < kTopBins; i += kTopThreads) h[i] = 0u;
+        __syncthreads();
+        const unsigned long long prefix = s_prefix;
+        const long long kk = s_k;
+        const int top = sh + bits;
+        const unsigned long long hi_mask = top >= 64 ? 0ull : (~0ull << top);
+        for (long long i0 = 0; i0 < n; i0 += kTopThreads) {
+            const long long i = i0 + t;
+            int d = -1;
+            if (i < n) {
+                const unsigned long long key = tally_key(f[i]);
+                if ((key & hi_mask) == prefix) d = (int)((key >> sh) & (unsigned long long)(nb - 1));
+            }
+            // a wave whose candidates share one digit adds them with one atomic
+            const int d0 = __shfl(d, 0);
+            if (__ballot(d == d0) == ~0ull) {
+                if (lane == 0 && d0 >= 0) atomicAdd(&h[d0], 64u);
+            } else if (d >= 0) {
+                atomicAdd(&h[d], 1u);
+            }
+        }
+        __syncthreads();
+        // thread t holds digits nb-1-2t and nb-2-2t: the prefix over threads runs from the top digit down
+        const int dhi = nb - 1 - 2 * t, dlo = dhi - 1;
+        const unsigned int chi = dhi >= 0 ? h[dhi] : 0u, clo = dlo >= 0 ? h[dlo] : 0u;
+        const unsigned int incl = block_inclusive_scan(chi + clo, wsum);
+        const unsigned int excl = incl - chi - clo;
+        if ((long long)excl < kk && kk <= (long long)incl) {
+            const bool in_hi = (long long)(excl + chi) >= kk;
+            const int d = in_hi ? dhi : dlo;
+            s_prefix = prefix | ((unsigned long long)d << sh);
+            s_k = kk - (long long)(in_hi ? excl : excl + chi);
+        }
+        __syncthreads();
+    }
+    const unsigned long long T = s_prefix;
+    const long long need = s_k;
+    long long run = 0;
+    unsigned int solid = 0;
+    for (long long i0 = 0; i0 < n; i0 += kTopThreads) {
+        const long long i = i0 + t;
+        unsigned long long key = 0ull;
+        if (i < n) key = tally_key(f[i]);
+        const bool eq = i < n && key == T;
+        const unsigned long long bal = __ballot(eq);
+        if (lane == 0) wsum[wave] = (unsigned int)__popcll(bal);
+        __syncthreads();
+        long long off = run + __popcll(bal & ((1ull << lane) - 1ull));
+        long long tot = 0;
+        for (int w = 0; w < kTopThreads / 64; ++w) {
+            if (w < wave) off += wsum[w];
+            tot += wsum[w];
+        }
+        const bool take = i < n && (key > T || (eq && off < need));
+        solid += (take && m[i] == 0) ? 1u : 0u;
+        run += tot;
+        __syncthreads();
+    }
+    for (int o = 32; o > 0; o >>= 1) solid += __shfl_xor(solid, o);
+    if (lane == 0) wsum[wave] = solid;
+    __syncthreads();
+    if (t == 0) {
+        long long sum = 0;
+        for (int w = 0; w < kTopThreads / 64; ++w) sum += wsum[w];
+        top_solid[blockIdx.x] = sum;
+        top_count[blockIdx.x] = k;
+    }
 }
 
 // Distance transform, pass 1: squared distance along x to the nearest solid
@@ -503,42 +603,21 @@ int mc_escape_path_histogram(const mc_photon_rec *rec, int64_t n, double bin_wid
     return MC_OK;
 }
 
-size_t mc_bright_colocalization_workspace_bytes(const mc_volume *vol)
-{
-    clear_error();
-    if (check_volume(vol)) return 0;
-    const long long n = (long long)vol->nx * vol->ny;
-    return align256((size_t)n) + pmc::sel::workspace_bytes(n);
-}
-
 int mc_bright_colocalization(const mc_volume *vol, const int64_t *fluence, int32_t z0, double frac,
-                             int64_t *top_count, int64_t *top_solid, void *workspace, size_t workspace_bytes,
-                             void *hip_stream)
+                             int64_t *top_count, int64_t *top_solid, void *hip_stream)
 {
     clear_error();
     int rc = check_volume(vol);
     if (rc) return rc;
-    if (!fluence || !top_count || !top_solid || !workspace) return fail(MC_EINVAL, "NULL argument");
+    if (!fluence || !top_count || !top_solid) return fail(MC_EINVAL, "NULL argument");
     if (z0 < 0 || z0 >= vol->nz) return fail(MC_EINVAL, "need 0 <= z0 < nz");
     if (!(frac > 0.0 && frac <= 1.0)) return fail(MC_EINVAL, "frac must be in (0, 1]");
-    const size_t need = mc_bright_colocalization_workspace_bytes(vol);
-    if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    hipStream_t s = (hipStream_t)hip_stream;
     const long long n = (long long)vol->nx * vol->ny;
-    const long long k = (long long)ceil(frac * (double)n);
-    const int slices = vol->nz - z0;
-    uint8_t *top = (uint8_t *)workspace;
-    void *sel_ws = (char *)workspace + align256((size_t)n);
-    hipLaunchKernelGGL(k_fill_value, dim3(blocks_for(slices)), dim3(kThreads), 0, s, (long long *)top_count,
-                       (long long)slices, k);
-    hipLaunchKernelGGL(k_zero_i64, dim3(blocks_for(slices)), dim3(kThreads), 0, s, (long long *)top_solid,
-                       (long long)slices);
-    for (int z = z0; z < vol->nz; ++z) {
-        const long long *f = (const long long *)fluence + (size_t)z * n;
-        if ((rc = pmc::sel::enqueue_top<long long>(f, n, k, top, sel_ws, s))) return rc;
-        hipLaunchKernelGGL(k_count_solid, dim3(blocks_for(n)), dim3(kThreads), 0, s, top, vol->mask + (size_t)z * n, n,
-                           (unsigned long long *)(top_solid + (z - z0)));
-    }
+    if (n >= 0x7fffffffLL) return fail(MC_EINVAL, "nx * ny must stay below 2^31");
+    const long long k = std::min(n, std::max(1LL, (long long)ceil(frac * (double)n)));
+    hipLaunchKernelGGL(k_slice_top, dim3((unsigned)(vol->nz - z0)), dim3(kTopThreads), 0, (hipStream_t)hip_stream,
+                       (const long long *)fluence, vol->mask, n, (int)z0, k, (long long *)top_count,
+                       (long long *)top_solid);
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }

@@ -117,9 +117,7 @@ _SIGS = {
     "mc_phase_contrast": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "mc_escape_path_histogram": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P,
                                                 ctypes.c_int32, _P, _P, _P, _P, _P]),
-    "mc_bright_colocalization_workspace_bytes": (ctypes.c_size_t, [_P]),
-    "mc_bright_colocalization": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P, _P,
-                                                ctypes.c_size_t, _P]),
+    "mc_bright_colocalization": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P, _P]),
     "mc_pore_distance_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_pore_distance": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, _P]),
     "mc_pore_spearman_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),

@@ -136,6 +136,15 @@ def test_bright_colocalization(mask_m1):
     k, s = an.bright_colocalization(d, Fc, 0, 0.1)
     kw, sw = oan.bright_colocalization(Fc.cpu().numpy(), mask_m1, 0, 0.1)
     assert np.array_equal(s.cpu().numpy(), sw)
+    # heavy ties among negative and very large values, slices of a few tiles with a ragged tail, frac = 1
+    rng = np.random.default_rng(10)
+    m = (rng.random((5, 37, 53)) < 0.6).astype(np.uint8)
+    for lo, hi in ((-3, 4), (2 ** 62 - 5, 2 ** 62), (-(2 ** 62), 2 ** 62)):
+        Fr = rng.integers(lo, hi, size=m.shape, dtype=np.int64)
+        for z0, frac in ((0, 0.1), (2, 0.5), (4, 1.0), (1, 1e-9)):
+            k, s = an.bright_colocalization(dev(m), dev(Fr), z0, frac)
+            kw, sw = oan.bright_colocalization(Fr, m, z0, frac)
+            assert np.array_equal(k.cpu().numpy(), kw) and np.array_equal(s.cpu().numpy(), sw), (lo, z0, frac)
 
 
 @pytest.mark.parametrize("shape", [(32, 32, 32), (17, 30, 20), (9, 1, 33), (40, 5, 1)])

@@ -112,6 +112,20 @@ def test_bright_colocalization_brute_force():
         assert k[i] == kk and s[i] == sum(int(m[z].ravel()[j] == 0) for j in order)
 
 
+def test_bright_colocalization_integer_ranking():
+    """Tallies that differ by one near 2^62 (equal as float64) keep their order."""
+    m = np.zeros((1, 1, 4), dtype=np.uint8)
+    m[0, 0, 2] = 1
+    base = 2 ** 62
+    F = np.array([[[base, base, base + 1, base]]], dtype=np.int64)
+    k, s = an.bright_colocalization(F, m, 0, 0.25)
+    assert k[0] == 1 and s[0] == 0                  # the single brightest voxel is the pore voxel
+    F2 = np.array([[[-(2 ** 63), 2 ** 63 - 1, 0, -1]]], dtype=np.int64)
+    m2 = np.array([[[0, 1, 0, 0]]], dtype=np.uint8)
+    k2, s2 = an.bright_colocalization(F2, m2, 0, 0.75)
+    assert k2[0] == 3 and s2[0] == 2                # 2^63 - 1, 0, -1: the extreme minimum left out
+
+
 def test_pore_distance_brute_force():
     for seed in (5, 6):
         m = inputs.spinodal_mask(9, 7, 8, 4.0, 0.7, seed=seed)
