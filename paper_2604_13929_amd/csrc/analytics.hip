@@ -33,7 +33,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kInf = 0x3fffffff;          // "no solid voxel on this line yet" for squared distances
-constexpr long long kEdtChunk = 65536;    // lines per launch of an envelope pass
+constexpr long long kEdtChunk = 16384;    // envelope scratch slots: lines redone at once
 
 __global__ void k_zero_i64(long long *p, long long n)
 {
@@ -57,8 +57,36 @@ __device__ __forceinline__ size_t line_elem(int axis, long long l, int j, int nx
     return (size_t)l * nx + j;                                                     // l = z * ny + y
 }
 
-__global__ void k_chords(const uint8_t *__restrict__ mask, int axis, int n, long long lines, int nx, int ny,
-                         unsigned long long *hist)
+// One thread per line; the workgroup counts its chords in an LDS histogram of
+// 2 (n + 1) words and adds the non-zero bins to the global one at the end (global
+// atomics on a few hundred hot bins would serialise).  Lines whose histogram does
+// not fit in LDS go to the global-atomic variant.
+__global__ __launch_bounds__(kThreads) void k_chords(const uint8_t *__restrict__ mask, int axis, int n, long long lines,
+                                                     int nx, int ny, unsigned long long *hist)
+{
+    extern __shared__ unsigned int hs[];
+    const int nh = 2 * (n + 1);
+    for (int i = (int)threadIdx.x; i < nh; i += kThreads) hs[i] = 0u;
+    __syncthreads();
+    for (long long l = (long long)blockIdx.x * kThreads + threadIdx.x; l < lines; l += (long long)gridDim.x * kThreads) {
+        int start = 0;
+        uint8_t cur = mask[line_elem(axis, l, 0, nx, ny)];
+        for (int j = 1; j <= n; ++j) {
+            const uint8_t v = j < n ? mask[line_elem(axis, l, j, nx, ny)] : (uint8_t)(cur ^ 1u);
+            if (v != cur) {
+                atomicAdd(&hs[(cur ? 1 : 0) * (n + 1) + (j - start)], 1u);
+                start = j;
+                cur = v;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < nh; i += kThreads)
+        if (hs[i]) atomicAdd(&hist[i], (unsigned long long)hs[i]);
+}
+
+__global__ void k_chords_global(const uint8_t *__restrict__ mask, int axis, int n, long long lines, int nx, int ny,
+                                unsigned long long *hist)
 {
     const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= lines) return;
@@ -106,23 +134,74 @@ struct Thresholds {
     double t[8];
 };
 
-__global__ void k_escape_hist(const mc_photon_rec *__restrict__ rec, long long n, double width, int nbins,
-                              Thresholds th, int nthr, unsigned long long *hw, unsigned long long *hn,
-                              unsigned long long *aw, unsigned long long *an)
+__device__ __forceinline__ int path_bin(double pv, double width, int nbins)
 {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double q = floor(pv / width);
+    return q >= (double)(nbins - 1) ? nbins - 1 : (q > 0.0 ? (int)q : 0);
+}
+
+// Escape-path histograms with the bins in LDS (weights 64-bit, counts 32-bit per
+// workgroup) and the threshold sums kept per thread, then reduced per wave: one
+// global atomic per wave and threshold instead of one per photon.
+constexpr int kEscLdsBins = 2048;
+
+template <bool LDS>
+__global__ __launch_bounds__(kThreads) void k_escape_hist(const mc_photon_rec *__restrict__ rec, long long n,
+                                                          double width, int nbins, Thresholds th, int nthr,
+                                                          unsigned long long *hw, unsigned long long *hn,
+                                                          unsigned long long *aw, unsigned long long *an)
+{
+    __shared__ unsigned long long sw[LDS ? kEscLdsBins : 1];
+    __shared__ unsigned int sn[LDS ? kEscLdsBins : 1];
+    if (LDS) {
+        for (int i = (int)threadIdx.x; i < nbins; i += kThreads) {
+            sw[i] = 0ull;
+            sn[i] = 0u;
+        }
+        __syncthreads();
+    }
+    unsigned long long tw[8], tn[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tw[k] = tn[k] = 0ull;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
         const mc_photon_rec r = rec[i];
         if (r.fate != 4u && r.fate != 5u) continue;
         const double pv = r.path_void;
-        const long long b = std::min((long long)floor(pv / width), (long long)nbins - 1);
-        atomicAdd(&hw[b], (unsigned long long)r.w_final);
-        atomicAdd(&hn[b], 1ull);
-        for (int k = 0; k < nthr; ++k) {
-            if (pv > th.t[k]) {
-                atomicAdd(&aw[k], (unsigned long long)r.w_final);
-                atomicAdd(&an[k], 1ull);
-            }
+        const int b = path_bin(pv, width, nbins);
+        if (LDS) {
+            atomicAdd(&sw[b], (unsigned long long)r.w_final);
+            atomicAdd(&sn[b], 1u);
+        } else {
+            atomicAdd(&hw[b], (unsigned long long)r.w_final);
+            atomicAdd(&hn[b], 1ull);
         }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < nthr && pv > th.t[k]) {
+                tw[k] += (unsigned long long)r.w_final;
+                tn[k] += 1ull;
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k >= nthr) break;
+        unsigned long long a = tw[k], c = tn[k];
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_xor(a, o);
+            c += __shfl_xor(c, o);
+        }
+        if ((threadIdx.x & 63) == 0 && c) {
+            atomicAdd(&aw[k], a);
+            atomicAdd(&an[k], c);
+        }
+    }
+    if (LDS) {
+        __syncthreads();
+        for (int i = (int)threadIdx.x; i < nbins; i += kThreads)
+            if (sn[i]) {
+                atomicAdd(&hw[i], sw[i]);
+                atomicAdd(&hn[i], (unsigned long long)sn[i]);
+            }
     }
 }
 
@@ -245,72 +324,164 @@ __global__ __launch_bounds__(kTopThreads) void k_slice_top(const long long *__re
 }
 
 // Distance transform, pass 1: squared distance along x to the nearest solid
-// voxel of the same line (two scans), kInf where the line has none.
-__global__ void k_edt_x(const uint8_t *__restrict__ mask, int nx, long long lines, int *__restrict__ g)
+// voxel of the same line, kInf where the line has none.  One wavefront per line,
+// lane = x within a 64-voxel chunk: an inclusive max-scan across the lanes of
+// "x if solid" (carried from chunk to chunk) gives the nearest solid voxel on the
+// left, a min-scan from the right end the nearest on the right; every load and
+// store is a contiguous run of the line.
+__global__ __launch_bounds__(kThreads) void k_edt_x(const uint8_t *__restrict__ mask, int nx, long long lines,
+                                                    int *__restrict__ g)
 {
-    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= lines) return;
+    const long long l = (long long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (l >= lines) return;                        // the whole wavefront leaves together
+    const int lane = (int)(threadIdx.x & 63);
     const uint8_t *m = mask + (size_t)l * nx;
     int *o = g + (size_t)l * nx;
-    int d = kInf;
-    for (int x = 0; x < nx; ++x) {
-        d = m[x] == 0 ? 0 : (d == kInf ? kInf : d + 1);
-        o[x] = d;
+    int carry = -1;                                // nearest solid voxel at or left of the chunk start
+    for (int x0 = 0; x0 < nx; x0 += 64) {
+        const int x = x0 + lane;
+        int v = (x < nx && m[x] == 0) ? x : -1;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int u = __shfl_up(v, off);
+            if (lane >= off) v = std::max(v, u);
+        }
+        v = std::max(v, carry);
+        carry = __shfl(v, 63);
+        if (x < nx) o[x] = v;
     }
-    d = kInf;
-    for (int x = nx - 1; x >= 0; --x) {
-        d = m[x] == 0 ? 0 : (d == kInf ? kInf : d + 1);
-        const int e = std::min(o[x], d);
-        o[x] = e == kInf ? kInf : e * e;
+    constexpr int kNone = 0x7fffffff;
+    carry = kNone;                                 // nearest solid voxel at or right of the chunk end
+    for (int x0 = ((nx - 1) / 64) * 64; x0 >= 0; x0 -= 64) {
+        const int x = x0 + lane;
+        int v = (x < nx && m[x] == 0) ? x : kNone;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int u = __shfl_down(v, off);
+            if (lane + off < 64) v = std::min(v, u);
+        }
+        v = std::min(v, carry);
+        carry = __shfl(v, 0);
+        if (x < nx) {
+            const int left = o[x];
+            int d = kInf;
+            if (left >= 0) d = x - left;
+            if (v != kNone) d = std::min(d, v - x);
+            o[x] = d == kInf ? kInf : d * d;
+        }
     }
 }
 
 // Passes 2 and 3: along y (axis 1) or z (axis 2), f(q) -> min_p f(p) + (q - p)^2
-// over the line, by the lower envelope of the parabolas rooted at the finite f(p)
-// (Felzenszwalb & Huttenlocher).  One thread per line of this chunk; scratch
-// arrays laid out [k][line] so that neighbouring threads touch neighbouring words.
-// The envelope is built before any output is written, so the pass runs in place.
-__global__ void k_edt_env(int *g, int axis, int n, long long line0, long long nlines, int nx, int ny, int *sv,
-                          int *sf, double *sz)
+// over the line through q.  First one thread per voxel (neighbouring threads on
+// neighbouring x, so every load is coalesced) scans outward from q: a candidate at
+// distance r costs at least r^2, so the scan stops, exact, once r^2 reaches the best
+// value found, or at the ends of the line.  In a porous mask that is after a few
+// voxels; a voxel still open after kEdtReach steps marks its line, and the marked
+// lines are redone whole by the lower envelope of parabolas (Felzenszwalb &
+// Huttenlocher), O(n) per line, which bounds the worst case (lines far from any
+// solid voxel).  in and out are distinct buffers.
+constexpr int kEdtReach = 64;
+
+// grid: x over the voxels of one z-slice (nx * ny < 2^30 where the transform is
+// allowed), y over the slices
+template <int AXIS>
+__global__ __launch_bounds__(kThreads) void k_edt_scan(const int *__restrict__ in, int *__restrict__ out,
+                                                       uint8_t *__restrict__ open_line, int nx, int ny, int nz)
+{
+    const int n = AXIS == 1 ? ny : nz;
+    const int plane = nx * ny;
+    const long long stride = AXIS == 1 ? (long long)nx : (long long)plane;
+    const int z = (int)blockIdx.y;
+    for (int p = (int)(blockIdx.x * kThreads + threadIdx.x); p < plane; p += (int)(gridDim.x * kThreads)) {
+        const int y = p / nx, x = p - y * nx;
+        const long long i = (long long)z * plane + p;
+        const int q = AXIS == 1 ? y : z;
+        int best = in[i];
+        bool done = false;
+        for (int r = 1; r <= kEdtReach + 1; ++r) {
+            const int r2 = r * r;
+            const bool lo = q - r >= 0, hi = q + r < n;
+            if (r2 >= best || (!lo && !hi)) {
+                done = true;
+                break;
+            }
+            if (r > kEdtReach) break;
+            if (lo) {
+                const int v = in[i - r * stride];
+                if (v < kInf) best = std::min(best, v + r2);
+            }
+            if (hi) {
+                const int v = in[i + r * stride];
+                if (v < kInf) best = std::min(best, v + r2);
+            }
+        }
+        out[i] = best;
+        if (!done) open_line[AXIS == 1 ? (long long)z * nx + x : (long long)y * nx + x] = 1;
+    }
+}
+
+// list of the marked lines (order irrelevant: each is redone independently)
+__global__ void k_edt_collect(const uint8_t *__restrict__ open_line, long long lines, int *list, int *count)
+{
+    for (long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x; l < lines; l += (long long)gridDim.x * blockDim.x)
+        if (open_line[l]) list[atomicAdd(count, 1)] = (int)l;
+}
+
+__global__ void k_edt_clear(uint8_t *open_line, long long lines, int *count)
+{
+    for (long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x; l < lines; l += (long long)gridDim.x * blockDim.x)
+        open_line[l] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = 0;
+}
+
+// Lower envelope of the parabolas rooted at the finite in(p) of the listed lines,
+// one thread per line; scratch arrays laid out [k][slot] so that neighbouring
+// threads touch neighbouring words; C slots, a thread takes lines t, t + C, ...
+__global__ void k_edt_env(const int *__restrict__ in, int *__restrict__ out, int axis, int n, const int *list,
+                          const int *count, long long C, int nx, int ny, int *sv, int *sf, double *sz)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nlines) return;
-    const long long l = line0 + t;
-    const long long C = nlines;
+    if (t >= C) return;
     auto V = [&](int k) -> int & { return sv[(size_t)k * C + t]; };
     auto F = [&](int k) -> int & { return sf[(size_t)k * C + t]; };
     auto Z = [&](int k) -> double & { return sz[(size_t)k * C + t]; };
-    int k = -1;
-    for (int q = 0; q < n; ++q) {
-        const int fq = g[line_elem(axis, l, q, nx, ny)];
-        if (fq >= kInf) continue;
-        if (k < 0) {
-            k = 0;
-            V(0) = q;
-            F(0) = fq;
-            Z(0) = -INFINITY;
-            Z(1) = INFINITY;
+    const long long cnt = *count;
+    for (long long idx = t; idx < cnt; idx += C) {
+        const long long l = list[idx];
+        int k = -1;
+        for (int q = 0; q < n; ++q) {
+            const int fq = in[line_elem(axis, l, q, nx, ny)];
+            if (fq >= kInf) continue;
+            if (k < 0) {
+                k = 0;
+                V(0) = q;
+                F(0) = fq;
+                Z(0) = -INFINITY;
+                Z(1) = INFINITY;
+                continue;
+            }
+            double s;
+            for (;;) {
+                const int vk = V(k);
+                s = ((double)fq + (double)q * q - ((double)F(k) + (double)vk * vk)) / (2.0 * (q - vk));
+                if (s <= Z(k)) --k;     // Z(0) = -inf stops this at k = 0
+                else break;
+            }
+            ++k;
+            V(k) = q;
+            F(k) = fq;
+            Z(k) = s;
+            Z(k + 1) = INFINITY;
+        }
+        if (k < 0) {                    // no solid voxel reaches this line
+            for (int q = 0; q < n; ++q) out[line_elem(axis, l, q, nx, ny)] = kInf;
             continue;
         }
-        double s;
-        for (;;) {
-            const int vk = V(k);
-            s = ((double)fq + (double)q * q - ((double)F(k) + (double)vk * vk)) / (2.0 * (q - vk));
-            if (s <= Z(k)) --k;     // Z(0) = -inf stops this at k = 0
-            else break;
+        int j = 0;
+        for (int q = 0; q < n; ++q) {
+            while (Z(j + 1) < (double)q) ++j;
+            const int d = q - V(j);
+            out[line_elem(axis, l, q, nx, ny)] = d * d + F(j);
         }
-        ++k;
-        V(k) = q;
-        F(k) = fq;
-        Z(k) = s;
-        Z(k + 1) = INFINITY;
-    }
-    if (k < 0) return;              // no solid voxel reaches this line: stays kInf
-    int j = 0;
-    for (int q = 0; q < n; ++q) {
-        while (Z(j + 1) < (double)q) ++j;
-        const int d = q - V(j);
-        g[line_elem(axis, l, q, nx, ny)] = d * d + F(j);
     }
 }
 
@@ -445,35 +616,59 @@ __global__ __launch_bounds__(256) void k_rank_corr(const double *__restrict__ rf
     }
 }
 
+// distance transform scratch: two squared-distance buffers, the open-line marks
+// and list of the larger line family, the envelope's C-slot scratch
 struct EdtScratch {
-    int *g, *sv, *sf;
+    int *g, *h, *list, *count, *sv, *sf;
+    uint8_t *open;
     double *sz;
     long long C;
 };
 
-EdtScratch edt_layout(const mc_volume *vol, void *ws)
+struct EdtSizes {
+    size_t g, open, list, env_i, env_d, total;
+    long long C;
+};
+
+EdtSizes edt_sizes(const mc_volume *vol)
 {
+    EdtSizes z;
     const size_t nvox = (size_t)vol->nx * vol->ny * vol->nz;
     const int nmax = std::max(vol->ny, vol->nz);
     const long long lines = std::max((long long)vol->nx * vol->nz, (long long)vol->nx * vol->ny);
-    EdtScratch e;
-    e.C = std::min<long long>(kEdtChunk, lines);
-    char *b = (char *)ws;
-    e.g = (int *)b;
-    e.sv = (int *)(b + align256(nvox * sizeof(int)));
-    e.sf = (int *)((char *)e.sv + align256((size_t)e.C * (nmax + 1) * sizeof(int)));
-    e.sz = (double *)((char *)e.sf + align256((size_t)e.C * (nmax + 1) * sizeof(int)));
-    return e;
+    z.C = std::min<long long>(kEdtChunk, lines);
+    z.g = align256(nvox * sizeof(int));
+    z.open = align256((size_t)lines);
+    z.list = align256((size_t)lines * sizeof(int) + sizeof(int));
+    z.env_i = align256((size_t)z.C * (nmax + 1) * sizeof(int));
+    z.env_d = align256((size_t)z.C * (nmax + 2) * sizeof(double));
+    z.total = 2 * z.g + z.open + z.list + 2 * z.env_i + z.env_d;
+    return z;
 }
 
-size_t edt_bytes(const mc_volume *vol)
+size_t edt_bytes(const mc_volume *vol) { return edt_sizes(vol).total; }
+
+EdtScratch edt_layout(const mc_volume *vol, void *ws)
 {
-    const size_t nvox = (size_t)vol->nx * vol->ny * vol->nz;
-    const int nmax = std::max(vol->ny, vol->nz);
-    const long long lines = std::max((long long)vol->nx * vol->nz, (long long)vol->nx * vol->ny);
-    const size_t C = (size_t)std::min<long long>(kEdtChunk, lines);
-    return align256(nvox * sizeof(int)) + align256(C * (nmax + 1) * sizeof(int)) * 2 +
-           align256(C * (nmax + 2) * sizeof(double));
+    const EdtSizes z = edt_sizes(vol);
+    EdtScratch e;
+    char *b = (char *)ws;
+    e.C = z.C;
+    e.g = (int *)b;
+    b += z.g;
+    e.h = (int *)b;
+    b += z.g;
+    e.open = (uint8_t *)b;
+    b += z.open;
+    e.count = (int *)b;
+    e.list = e.count + 1;
+    b += z.list;
+    e.sv = (int *)b;
+    b += z.env_i;
+    e.sf = (int *)b;
+    b += z.env_i;
+    e.sz = (double *)b;
+    return e;
 }
 
 // squared distances (int, kInf where no solid voxel exists) into e.g
@@ -481,17 +676,24 @@ int enqueue_sqdist(const mc_volume *vol, const EdtScratch &e, hipStream_t s)
 {
     const int nx = vol->nx, ny = vol->ny, nz = vol->nz;
     const long long xl = (long long)ny * nz;
-    hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((xl + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, vol->mask, nx, xl,
-                       e.g);
+    const dim3 grid((unsigned)std::min<long long>(1024, ((long long)nx * ny + kThreads - 1) / kThreads), (unsigned)nz);
+    hipLaunchKernelGGL(k_edt_x, dim3((unsigned)((xl + kThreads / 64 - 1) / (kThreads / 64))), dim3(kThreads), 0, s,
+                       vol->mask, nx, xl, e.g);
+    const unsigned env_grid = (unsigned)((e.C + kThreads - 1) / kThreads);
+    // y: g -> h, z: h -> g
     for (int axis = 1; axis <= 2; ++axis) {
+        const int *in = axis == 1 ? e.g : e.h;
+        int *out = axis == 1 ? e.h : e.g;
         const int n = axis == 1 ? ny : nz;
-        if (n == 1) continue;
         const long long lines = (long long)nx * (axis == 1 ? nz : ny);
-        for (long long l0 = 0; l0 < lines; l0 += e.C) {
-            const long long cl = std::min(e.C, lines - l0);
-            hipLaunchKernelGGL(k_edt_env, dim3((unsigned)((cl + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, e.g, axis,
-                               n, l0, cl, nx, ny, e.sv, e.sf, e.sz);
-        }
+        hipLaunchKernelGGL(k_edt_clear, dim3(blocks_for(lines)), dim3(kThreads), 0, s, e.open, lines, e.count);
+        if (axis == 1)
+            hipLaunchKernelGGL(k_edt_scan<1>, grid, dim3(kThreads), 0, s, in, out, e.open, nx, ny, nz);
+        else
+            hipLaunchKernelGGL(k_edt_scan<2>, grid, dim3(kThreads), 0, s, in, out, e.open, nx, ny, nz);
+        hipLaunchKernelGGL(k_edt_collect, dim3(blocks_for(lines)), dim3(kThreads), 0, s, e.open, lines, e.list, e.count);
+        hipLaunchKernelGGL(k_edt_env, dim3(env_grid), dim3(kThreads), 0, s, in, out, axis, n, e.list, e.count, e.C, nx, ny,
+                           e.sv, e.sf, e.sz);
     }
     HIP_TRY(hipGetLastError());
     return MC_OK;
@@ -559,8 +761,15 @@ int mc_chord_histogram(const mc_volume *vol, int32_t axis, int64_t *hist, void *
     const long long lines = (long long)vol->nx * vol->ny * vol->nz / n;
     const long long nh = 2ll * (n + 1);
     hipLaunchKernelGGL(k_zero_i64, dim3(blocks_for(nh)), dim3(kThreads), 0, s, (long long *)hist, nh);
-    hipLaunchKernelGGL(k_chords, dim3((unsigned)((lines + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, vol->mask,
-                       axis, n, lines, vol->nx, vol->ny, (unsigned long long *)hist);
+    const size_t lds = sizeof(unsigned int) * (size_t)nh;
+    if (lds <= 65536) {
+        const unsigned grid = (unsigned)std::min<long long>(1024, (lines + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL(k_chords, dim3(grid), dim3(kThreads), lds, s, vol->mask, axis, n, lines, vol->nx, vol->ny,
+                           (unsigned long long *)hist);
+    } else {
+        hipLaunchKernelGGL(k_chords_global, dim3((unsigned)((lines + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                           vol->mask, axis, n, lines, vol->nx, vol->ny, (unsigned long long *)hist);
+    }
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }
@@ -595,10 +804,17 @@ int mc_escape_path_histogram(const mc_photon_rec *rec, int64_t n, double bin_wid
         hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(kThreads), 0, s, (long long *)above_w, (long long)nthr);
         hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(kThreads), 0, s, (long long *)above_n, (long long)nthr);
     }
-    if (n > 0)
-        hipLaunchKernelGGL(k_escape_hist, dim3(blocks_for(n)), dim3(kThreads), 0, s, rec, (long long)n, bin_width, nbins,
-                           th, nthr, (unsigned long long *)hist_w, (unsigned long long *)hist_n,
-                           (unsigned long long *)above_w, (unsigned long long *)above_n);
+    if (n > 0) {
+        const unsigned grid = (unsigned)std::min<long long>(1024, (n + kThreads - 1) / kThreads);
+        if (nbins <= kEscLdsBins)
+            hipLaunchKernelGGL(k_escape_hist<true>, dim3(grid), dim3(kThreads), 0, s, rec, (long long)n, bin_width, nbins,
+                               th, nthr, (unsigned long long *)hist_w, (unsigned long long *)hist_n,
+                               (unsigned long long *)above_w, (unsigned long long *)above_n);
+        else
+            hipLaunchKernelGGL(k_escape_hist<false>, dim3(grid), dim3(kThreads), 0, s, rec, (long long)n, bin_width,
+                               nbins, th, nthr, (unsigned long long *)hist_w, (unsigned long long *)hist_n,
+                               (unsigned long long *)above_w, (unsigned long long *)above_n);
+    }
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }

@@ -160,6 +160,24 @@ def test_pore_distance(shape, mask_m1):
     assert np.array_equal(got, oan.pore_distance(m))
 
 
+def test_pore_distance_far_from_solid():
+    """Pores wider than the outward scan's reach: the lines left open are redone by
+    the lower envelope (a few solid voxels in a large empty box, and one slab)."""
+    banner("pore distance with distances beyond the outward scan's reach vs scipy")
+    m = np.ones((40, 50, 60), dtype=np.uint8)
+    m[0, 0, 0] = m[39, 49, 59] = m[20, 3, 31] = 0
+    assert np.array_equal(an.pore_distance(dev(m)).cpu().numpy(), oan.pore_distance(m))
+    m2 = np.ones((70, 9, 11), dtype=np.uint8)
+    m2[0] = 0                                          # distances 1..69 along z only
+    got = an.pore_distance(dev(m2)).cpu().numpy()
+    assert np.array_equal(got, oan.pore_distance(m2)) and got.max() == 69.0
+    m3 = np.ones((3, 4, 200), dtype=np.uint8)
+    m3[:, :, 0] = 0                                    # distances 1..199 along x only
+    m3[1, 2, 150] = 0
+    got = an.pore_distance(dev(m3)).cpu().numpy()
+    assert np.array_equal(got, oan.pore_distance(m3)) and got.max() == 75.0
+
+
 def test_pore_distance_degenerate_and_fullsize():
     banner("pore distance: all solid, all pore, 256^3 vs scipy")
     z = inputs.homogeneous_mask(6, 5, 4)
