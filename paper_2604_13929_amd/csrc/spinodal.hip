@@ -360,6 +360,16 @@ enum { X_INIT = 0, X_NONLIN = 1, X_FIELD = 2 };
 // Lines along x.  X_INIT: real line -> forward transform, half spectrum out.
 // X_NONLIN: half spectrum -> inverse -> f'(phi) -> forward -> half spectrum.
 // X_FIELD: half spectrum -> inverse -> real line out.  `scale` = 1/(nx ny nz).
+//
+// Two real lines share one complex transform: lines a = 2m and b = 2m + 1 of
+// the workgroup travel as z = a + i b.  Forward, A_k = (Z_k + conj Z_(n-k)) / 2
+// and B_k = (Z_k - conj Z_(n-k)) / 2i; inverse, Z_k = A_k + i B_k over the
+// Hermitian extensions of A and B, and a, b are the real and imaginary parts of
+// the result.  The imaginary parts of bins 0 and n/2 are dropped, as a real
+// inverse transform drops them.  While loading, A_j sits at j and B_j at n - j
+// (0 < j < n/2), their real bins 0 and n/2 in the two halves of slots 0 and n/2,
+// so a pair needs exactly n slots.  `L` is the number of lines per workgroup
+// (even except in the last workgroup).
 template <int MODE, int N>
 __global__ __launch_bounds__(kThreads) void k_xpass(const double *__restrict__ rin, double2 *spec,
                                                      double *__restrict__ rout, int nx, int nlines_total, int L,
@@ -368,9 +378,11 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const double *__restrict__ r
     __shared__ double2 buf[N > 0 ? kPadElems : kLdsElems];
     __shared__ double2 tw_s[N > 0 ? kPadTw : kTwElems];
     load_twiddles<N>(tw_s, tw, nx);
-    const int hx = nx / 2 + 1, ls = N > 0 ? nx + nx / 16 : nx;   // read along the lines: no extra pad
+    double *bd = reinterpret_cast<double *>(buf);   // bd[2 p] = buf[p].x, bd[2 p + 1] = buf[p].y
+    const int hx = nx / 2 + 1, half = nx / 2, ls = N > 0 ? nx + nx / 16 : nx;
     const int line0 = (int)blockIdx.x * L;
     const int nl = min(L, nlines_total - line0);
+    const int np = (nl + 1) >> 1;
     const int tid = (int)threadIdx.x;
     const float inv_nx = 1.0f / (float)nx, inv_hx = 1.0f / (float)hx;
     if (MODE == X_INIT) {
@@ -380,48 +392,65 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const double *__restrict__ r
             nl * nx, [&](int e) { return src[e]; },
             [&](int e, double v) {
                 const int l = fdiv(e, nx, inv_nx), x = e - l * nx;
-                buf[l * ls + pidx<N>(x)] = make_double2(v, 0.0);
+                bd[2 * ((l >> 1) * ls + pidx<N>(x)) + (l & 1)] = v;
             });
+        if (nl & 1)
+            for (int x = tid; x < nx; x += kThreads) bd[2 * ((nl >> 1) * ls + pidx<N>(x)) + 1] = 0.0;
         __syncthreads();
     } else {
         const double2 *src = spec + (size_t)line0 * hx;
         gather<8, double2>(
             nl * hx, [&](int e) { return src[e]; },
             [&](int e, double2 v) {
-                const int l = fdiv(e, hx, inv_hx), x = e - l * hx;
-                buf[l * ls + pidx<N>(x)] = v;
+                const int l = fdiv(e, hx, inv_hx), j = e - l * hx;
+                const int base = (l >> 1) * ls;
+                if (j == 0 || j == half) bd[2 * (base + pidx<N>(j)) + (l & 1)] = v.x;
+                else buf[base + pidx<N>((l & 1) ? nx - j : j)] = v;
             });
-        __syncthreads();
-        // Hermitian extension: X[n - j] = conj(X[j]); the real part of the complex
-        // inverse then ignores the imaginary parts of the 0 and n/2 bins, as a
-        // real inverse transform does
-        const int ne = nx / 2 - 1;
-        const float inv_ne = 1.0f / (float)max(ne, 1);
-        for (int e = tid; e < nl * ne; e += kThreads) {
-            const int l = fdiv(e, ne, inv_ne), j = 1 + (e - l * ne);
-            const double2 v = buf[l * ls + pidx<N>(j)];
-            buf[l * ls + pidx<N>(nx - j)] = make_double2(v.x, -v.y);
+        if (nl & 1) {                                  // the last pair has no b line
+            const int base = (nl >> 1) * ls;
+            for (int j = tid; j <= half; j += kThreads) {
+                if (j == 0 || j == half) bd[2 * (base + pidx<N>(j)) + 1] = 0.0;
+                else buf[base + pidx<N>(nx - j)] = make_double2(0.0, 0.0);
+            }
         }
         __syncthreads();
-        fft_any<N>(buf, ls, nl, P, tw_s, true);
+        const int nk = half - 1;                        // bins 0 < k < n/2 of every pair
+        if (nk > 0) {
+            const float inv_nk = 1.0f / (float)nk;
+            for (int e = tid; e < np * nk; e += kThreads) {
+                const int m = fdiv(e, nk, inv_nk), k = 1 + (e - m * nk);
+                const int pa = m * ls + pidx<N>(k), pb = m * ls + pidx<N>(nx - k);
+                const double2 a = buf[pa], b = buf[pb];
+                buf[pa] = make_double2(a.x - b.y, a.y + b.x);
+                buf[pb] = make_double2(a.x + b.y, b.x - a.y);
+            }
+        }
+        __syncthreads();
+        fft_any<N>(buf, ls, np, P, tw_s, true);
         if (MODE == X_FIELD) {
             for (int e = tid; e < nl * nx; e += kThreads) {
                 const int l = fdiv(e, nx, inv_nx), x = e - l * nx;
-                rout[(size_t)(line0 + l) * nx + x] = buf[l * ls + pidx<N>(x)].x * scale;
+                rout[(size_t)(line0 + l) * nx + x] = bd[2 * ((l >> 1) * ls + pidx<N>(x)) + (l & 1)] * scale;
             }
             return;
         }
-        for (int e = tid; e < nl * nx; e += kThreads) {
-            const int l = fdiv(e, nx, inv_nx), x = e - l * nx;
-            const double phi = buf[l * ls + pidx<N>(x)].x * scale;
-            buf[l * ls + pidx<N>(x)] = make_double2(2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi), 0.0);
+        for (int e = tid; e < np * nx; e += kThreads) {
+            const int m = fdiv(e, nx, inv_nx), x = e - m * nx;
+            const int p = m * ls + pidx<N>(x);
+            const double2 z = buf[p];
+            const double a = z.x * scale, b = z.y * scale;
+            buf[p] = make_double2(2.0 * a * (1.0 - a) * (1.0 - 2.0 * a), 2.0 * b * (1.0 - b) * (1.0 - 2.0 * b));
         }
         __syncthreads();
     }
-    fft_any<N>(buf, ls, nl, P, tw_s, false);
+    fft_any<N>(buf, ls, np, P, tw_s, false);
     for (int e = tid; e < nl * hx; e += kThreads) {
-        const int l = fdiv(e, hx, inv_hx), x = e - l * hx;
-        spec[(size_t)(line0 + l) * hx + x] = buf[l * ls + pidx<N>(x)];
+        const int l = fdiv(e, hx, inv_hx), k = e - l * hx;
+        const int base = (l >> 1) * ls;
+        const double2 zk = buf[base + pidx<N>(k)], zr = buf[base + pidx<N>(k == 0 ? 0 : nx - k)];
+        spec[(size_t)(line0 + l) * hx + k] = (l & 1) ? make_double2(0.5 * (zk.y + zr.y), -0.5 * (zk.x - zr.x))
+                                                     : make_double2(0.5 * (zk.x + zr.x), 0.5 * (zk.y - zr.y));
     }
 }
 
@@ -614,7 +643,7 @@ int geometry(const mc_ch_grid *g, Geo *G)
     if (!make_plan(g->nx, &G->px) || !make_plan(g->ny, &G->py) || !make_plan(g->nz, &G->pz))
         return fail(MC_EINVAL, "every extent must be a product of powers of 2 and 3");
     G->spec_elems = (size_t)G->nz * G->ny * G->hx;
-    G->Lx = std::max(1, kLdsElems / G->nx);
+    G->Lx = 2 * std::max(1, kLdsElems / G->nx);   // two real lines per complex transform
     // column tiles: padded lines must fit the LDS buffer and the stage registers
     auto tile = [](int n) {
         const int lds = static_length(n) ? kPadElems : kColElems;
