@@ -133,6 +133,53 @@ template <> __device__ __forceinline__ void dft<4>(double2 *v, bool inv)
     v[3] = make_double2(d02.x - r.x, d02.y - r.y);
 }
 
+// radix 8: two radix-4 DFTs of the even and odd inputs, joined with w8^k
+template <> __device__ __forceinline__ void dft<8>(double2 *v, bool inv)
+{
+    constexpr double h = 0.70710678118654752440;   // sqrt(2)/2
+    const double sg = inv ? 1.0 : -1.0;
+    double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft<4>(e, inv);
+    dft<4>(o, inv);
+    const double2 t[4] = {o[0], make_double2(h * (o[1].x - sg * o[1].y), h * (o[1].y + sg * o[1].x)),
+                          make_double2(-sg * o[2].y, sg * o[2].x),
+                          make_double2(-h * (o[3].x + sg * o[3].y), h * (sg * o[3].x - o[3].y))};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = make_double2(e[k].x + t[k].x, e[k].y + t[k].y);
+        v[k + 4] = make_double2(e[k].x - t[k].x, e[k].y - t[k].y);
+    }
+}
+
+// radix 16 as 4 x 4: radix-4 DFTs over n1 of v[4 n1 + n2], twiddles w16^(n2 k1),
+// radix-4 DFTs over n2 giving X[k1 + 4 k2]
+template <> __device__ __forceinline__ void dft<16>(double2 *v, bool inv)
+{
+    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, h = 0.70710678118654752440;
+    // cos and sin of 2 pi m / 16, m = 0..9
+    constexpr double kc[10] = {1.0, c1, h, s1, 0.0, -s1, -h, -c1, -1.0, -c1};
+    constexpr double ks[10] = {0.0, s1, h, c1, 1.0, c1, h, s1, 0.0, -s1};
+    const double sg = inv ? 1.0 : -1.0;
+    double2 a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        double2 t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+        dft<4>(t, inv);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            const int m = n2 * k1;
+            a[n2][k1] = m == 0 ? t[k1] : cmul(t[k1], make_double2(kc[m], sg * ks[m]));
+        }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        double2 t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+        dft<4>(t, inv);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+}
+
 template <> __device__ __forceinline__ void dft<3>(double2 *v, bool inv)
 {
     constexpr double kS = 0.86602540378443864676;  // sqrt(3)/2
@@ -227,15 +274,20 @@ __device__ void fft_lines(double2 *buf, int ls, int nlines, const Plan &P, const
     }
 }
 
-// Compile-time plans for the common extents: the same stages as make_plan with
-// every divisor and stride a constant.
+// Compile-time plans for the common extents, every divisor and stride a
+// constant: the radix-3 stages, then the power of two 2^t in ceil(t / 4) stages
+// of radix 16, 8, 4 or 2 as even as possible (1024 = 16 8 8, 512 = 8 8 8,
+// 384 = 3 16 8, 256 = 16 16): fewer passes through LDS than radix 4.
 constexpr int c_threes(int n) { int t = 0; while (n % 3 == 0) { n /= 3; ++t; } return t; }
 constexpr int c_twos(int n) { while (n % 3 == 0) n /= 3; int t = 0; while (n % 2 == 0) { n /= 2; ++t; } return t; }
-constexpr int c_stages(int n) { return c_threes(n) + c_twos(n) / 2 + c_twos(n) % 2; }
+constexpr int c_two_stages(int n) { return (c_twos(n) + 3) / 4; }
+constexpr int c_stages(int n) { return c_threes(n) + c_two_stages(n); }
 constexpr int c_radix(int n, int s)
 {
-    const int t3 = c_threes(n), t4 = c_twos(n) / 2;
-    return s < t3 ? 3 : (s < t3 + t4 ? 4 : 2);
+    const int t3 = c_threes(n);
+    if (s < t3) return 3;
+    const int S = c_two_stages(n), t2 = c_twos(n), i = s - t3;
+    return 1 << (t2 / S + (i < t2 % S ? 1 : 0));
 }
 constexpr int c_ns(int n, int s)
 {
