@@ -39,6 +39,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kLdsElems = 4096;           // complex doubles transformed per workgroup (64 KiB)
+constexpr int kColRadixLog = 2;           // k_colpass keeps radix-4 stages (measured faster there)
 constexpr int kColElems = kLdsElems + 64; // LDS of the column passes: lines padded to n + 1
 constexpr int kMaxStages = 12;
 constexpr int kMaxN = 1024;
@@ -280,19 +281,20 @@ __device__ void fft_lines(double2 *buf, int ls, int nlines, const Plan &P, const
 // 384 = 3 16 8, 256 = 16 16): fewer passes through LDS than radix 4.
 constexpr int c_threes(int n) { int t = 0; while (n % 3 == 0) { n /= 3; ++t; } return t; }
 constexpr int c_twos(int n) { while (n % 3 == 0) n /= 3; int t = 0; while (n % 2 == 0) { n /= 2; ++t; } return t; }
-constexpr int c_two_stages(int n) { return (c_twos(n) + 3) / 4; }
-constexpr int c_stages(int n) { return c_threes(n) + c_two_stages(n); }
-constexpr int c_radix(int n, int s)
+// ML: largest radix 2^ML (4: up to 16; 2: radix 4 only)
+constexpr int c_two_stages(int n, int ML) { return (c_twos(n) + ML - 1) / ML; }
+constexpr int c_stages(int n, int ML) { return c_threes(n) + c_two_stages(n, ML); }
+constexpr int c_radix(int n, int s, int ML)
 {
     const int t3 = c_threes(n);
     if (s < t3) return 3;
-    const int S = c_two_stages(n), t2 = c_twos(n), i = s - t3;
+    const int S = c_two_stages(n, ML), t2 = c_twos(n), i = s - t3;
     return 1 << (t2 / S + (i < t2 % S ? 1 : 0));
 }
-constexpr int c_ns(int n, int s)
+constexpr int c_ns(int n, int s, int ML)
 {
     int p = 1;
-    for (int i = 0; i < s; ++i) p *= c_radix(n, i);
+    for (int i = 0; i < s; ++i) p *= c_radix(n, i, ML);
     return p;
 }
 
@@ -348,22 +350,23 @@ __device__ __forceinline__ void stage_c(double2 *buf, int ls, int nlines, const 
     __syncthreads();
 }
 
-template <int N, int S, bool INV>
+template <int N, int S, bool INV, int ML>
 __device__ __forceinline__ void fft_c(double2 *buf, int ls, int nlines, const double2 *tw)
 {
-    if constexpr (S < c_stages(N)) {
-        stage_c<c_radix(N, S), N, c_ns(N, S), INV>(buf, ls, nlines, tw);
-        fft_c<N, S + 1, INV>(buf, ls, nlines, tw);
+    if constexpr (S < c_stages(N, ML)) {
+        stage_c<c_radix(N, S, ML), N, c_ns(N, S, ML), INV>(buf, ls, nlines, tw);
+        fft_c<N, S + 1, INV, ML>(buf, ls, nlines, tw);
     }
 }
 
-// Transform dispatch: N > 0 selects the compile-time plan for that length.
-template <int N>
+// Transform dispatch: N > 0 selects the compile-time plan for that length, with
+// radices up to 2^ML.
+template <int N, int ML = 4>
 __device__ __forceinline__ void fft_any(double2 *buf, int ls, int nlines, const Plan &P, const double2 *tw, bool inv)
 {
     if constexpr (N > 0) {
-        if (inv) fft_c<N, 0, true>(buf, ls, nlines, tw);
-        else fft_c<N, 0, false>(buf, ls, nlines, tw);
+        if (inv) fft_c<N, 0, true, ML>(buf, ls, nlines, tw);
+        else fft_c<N, 0, false, ML>(buf, ls, nlines, tw);
     } else {
         fft_lines(buf, ls, nlines, P, tw, inv);
     }
@@ -548,7 +551,7 @@ __global__ __launch_bounds__(kThreads) void k_colpass(double2 *A, int ny, int hx
             buf[c * ls + pidx<N>(j)] = v;
         });
     __syncthreads();
-    fft_any<N>(buf, ls, nc, P, tw_s, inv != 0);
+    fft_any<N, kColRadixLog>(buf, ls, nc, P, tw_s, inv != 0);
     for (int e = tid; e < n * nc; e += kThreads) {
         const int j = fdiv(e, nc, inv_nc), c = e - j * nc;
         A[col_addr<AXIS>(j, p, x0 + c, ny, hx)] = buf[c * ls + pidx<N>(j)];
