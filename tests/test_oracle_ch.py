@@ -12,7 +12,8 @@ than itself:
 * the equilibrium interface phi = (1 + tanh(x / sqrt(2 kappa))) / 2 is stationary;
 * the first decomposition selects the fastest-growing wavenumber of Eq. CH,
   k* = 1 / sqrt(2 kappa) (Eq. lambda_star), not the 2-kappa form of Eq. sigma_k;
-* the radial PSD: Parseval and the peak shell of single-mode fields;
+* the radial PSD: Parseval and the peak shell of single-mode fields (shells by the
+  nearest integer of |k| N_max / 2 pi);
 * the rank threshold: exact count, order and index tie-break;
 * the stopping rule of App. A.
 """
@@ -122,7 +123,8 @@ def test_radial_psd_parseval_and_peak():
     total = phi.size * np.sum((phi - phi.mean()) ** 2)
     assert math.isclose(psd.sum(), total, rel_tol=1e-12)
     # a single mode lands in its shell
-    for m, s in (((0, 0, 5), 5), ((0, 6, 0), 8), ((2, 0, 0), 3)):
+    # (0, 3, 4): |k| N_max / 2 pi = sqrt(4^2 + 4^2) = 5.66, in shell 6 (nearest, not floor)
+    for m, s in (((0, 0, 5), 5), ((0, 6, 0), 8), ((2, 0, 0), 3), ((0, 3, 4), 6)):
         f = np.cos(2 * math.pi * (m[0] * z / nz + m[1] * y / ny + m[2] * x / nx))
         p = ch.radial_psd(ch.spectrum(f), shape)
         assert int(np.argmax(p)) == s, (m, np.argmax(p), s)

@@ -308,6 +308,36 @@ def test_roulette_is_unbiased(mask_m1):
         assert abs(a_m - b_m) < 4 * math.hypot(a_s, b_s), ch
 
 
+def test_roulette_is_unbiased_at_every_interaction(mask_m1):
+    """m = 2 and a threshold of half the launch weight put nearly every late interaction
+    through roulette; R, T and A must still match a run where roulette is rare, and the
+    roulette channel must average zero (a survival probability other than 1/m would bias
+    all of them by a large fraction of the rouletted weight)."""
+    n, B = 100_000, 32
+    hi = oracle.run(mask_m1, 0.5, 0.05, 0.7, n, seed=19, nbatch=B, fluence=False, w_roulette=0.5, roulette_m=2)
+    lo = oracle.run(mask_m1, 0.5, 0.05, 0.7, n, seed=19, nbatch=B, fluence=False, w_roulette=1e-4)
+    ich_hi, ich_lo = hi["ich"] / (n / B * W1), lo["ich"] / (n / B * W1)
+    rm, rs = batch_mean_sd(ich_hi[:, oracle.ICH.index("RR")])
+    assert abs(rm) < 4 * rs
+    for ch in ("R", "T", "A"):
+        a_m, a_s = batch_mean_sd(ich_hi[:, oracle.ICH.index(ch)])
+        b_m, b_s = batch_mean_sd(ich_lo[:, oracle.ICH.index(ch)])
+        assert abs(a_m - b_m) < 4 * math.hypot(a_s, b_s), ch
+
+
+def test_depth_bins_split_the_map_by_phase(mask_m1):
+    """The per-(phase, depth) bins are the fluence map summed over the solid and over the
+    pore voxels of each depth (two outputs accumulated separately by the walk)."""
+    n = 5000
+    r = oracle.run(mask_m1, 0.5, 0.01, 0.7, n, seed=29, depth=True)
+    F, D = r["fluence"][0], r["depth"][0]
+    solid = mask_m1 == 0
+    want_solid = np.where(solid, F, 0.0).sum(axis=(1, 2))
+    want_pore = np.where(~solid, F, 0.0).sum(axis=(1, 2))
+    assert np.allclose(D[0], want_solid, rtol=1e-12) and np.allclose(D[1], want_pore, rtol=1e-12)
+    assert D[0].sum() > 0 and D[1].sum() > 0
+
+
 def test_lateral_size_invariance():
     """Periodic lateral faces: a homogeneous slab's depth profile does not depend on Nx, Ny."""
     n, B, nz = 100_000, 16, 32
