@@ -17,7 +17,8 @@ photocatalytic aerogels", Sec. 3.4):
   co-localisation: on each deep slice z >= z0, the brightest decile of voxels by
       fluence and the fraction of it that is solid; the local pore size by a
       Euclidean distance transform of the pore phase, and, inside the pore phase of
-      each deep slice, the Spearman rank correlation of fluence with that size.
+      each deep slice, the Spearman rank correlation of fluence with that size;
+  and (Sec. 3.2, Fig. 2b) the radial power spectral density of the binary mask.
 Readings where the paper is silent (listed with their reasons in the design
 notes): chords cut by the slab faces count with their in-slab length; the
 brightest decile of a slice is its ceil(0.1 N) voxels of highest fluence with
@@ -160,3 +161,12 @@ def average_ranks_brute(x: np.ndarray) -> np.ndarray:
     """1-based ranks with ties averaged, by counting: rank_i = #{x_j < x_i} + (#{x_j == x_i} + 1) / 2."""
     x = np.asarray(x)
     return np.array([(x < v).sum() + ((x == v).sum() + 1) / 2 for v in x], dtype=np.float64)
+
+
+def mask_psd(mask: np.ndarray) -> np.ndarray:
+    """Radial PSD of the binary mask (values 0/1): the Cahn-Hilliard oracle's shell
+    sums applied to the mask's forward transform (numpy's rfftn as one step)."""
+    from oracle import cahn_hilliard as och
+
+    m = np.asarray(mask, dtype=np.float64)
+    return och.radial_psd(och.spectrum(m), m.shape)

@@ -178,3 +178,50 @@ def test_pore_spearman_pins():
 def test_average_ranks_against_hand_count():
     r = an.average_ranks_brute(np.array([10, 20, 20, 5, 20]))
     assert list(r) == [2.0, 4.0, 4.0, 1.0, 4.0]
+
+
+def test_mask_psd_stripes_closed_form():
+    """Stripes of width 6 along x (period 12 in nx = 24): the transform is nonzero only at
+    kx = 2h with odd h, where |m_hat|^2 = (ny nz)^2 * 4 / sin^2(pi h / 12); each such mode
+    lies in shell kx and is counted with its conjugate."""
+    nz, ny, nx = 6, 4, 24
+    m = np.zeros((nz, ny, nx), dtype=np.uint8)
+    m[:, :, (np.arange(nx) % 12) < 6] = 1
+    p = an.mask_psd(m)
+    want = np.zeros(nx // 2 + 1)
+    for h in (1, 3, 5):
+        want[2 * h] = 2 * (ny * nz) ** 2 * 4 / math.sin(math.pi * h / 12) ** 2
+    assert np.allclose(p, want, rtol=1e-12, atol=1e-9 * want.max())
+    s_peak = int(np.argmax(p[1:])) + 1
+    assert max(m.shape) / (2 * s_peak) == 6.0           # the dominant size is the stripe width
+
+
+def test_mask_psd_complement_invariance():
+    """m and 1 - m differ only in the mean, which the PSD excludes."""
+    m = inputs.spinodal_mask(12, 18, 24, 6.0, 0.7, seed=3)
+    assert np.allclose(an.mask_psd(m), an.mask_psd(1 - m), rtol=1e-12, atol=1e-9)
+
+
+def test_phase_contrast_hand_example():
+    """Contrasts 1, 2, 3 (solid) and 2, 1, 0.5 (pore) of three depths, and a fourth depth
+    with no light, which is skipped: means and sample standard deviations by hand."""
+    t = np.array([1.0, 1.0, 2.0, 0.0])
+    s = np.array([1.0, 2.0, 6.0, 0.0])
+    p = np.array([2.0, 1.0, 1.0, 0.0])
+    pc = an.phase_contrast(t, s, p)
+    assert pc["depths"] == 3
+    assert pc["solid_mean"] == 2.0 and math.isclose(pc["solid_sd"], 1.0, rel_tol=1e-15)
+    assert math.isclose(pc["pore_mean"], 3.5 / 3, rel_tol=1e-15)
+    dev = np.array([2.0, 1.0, 0.5]) - 3.5 / 3
+    assert math.isclose(pc["pore_sd"], math.sqrt((dev ** 2).sum() / 2), rel_tol=1e-14)
+
+
+def test_escape_histogram_hand_example():
+    """Bins are [b w, (b + 1) w), the last one open; only escaping fates (4, 5) count;
+    thresholds are strict."""
+    fate = np.array([4, 5, 4, 4, 6, 5], dtype=np.uint32)
+    w = np.array([10, 20, 30, 40, 50, 60], dtype=np.int64)
+    pv = np.array([0.4, 1.6, 2.0, 9.9, 1.0, 1.0])
+    hw, hn, aw, an_ = an.escape_path_histogram(fate, w, pv, 1.0, 4, thresholds=(1.0, 1.6))
+    assert list(hn) == [1, 2, 1, 1] and list(hw) == [10, 80, 30, 40]
+    assert list(aw) == [20 + 30 + 40, 30 + 40] and list(an_) == [3, 2]
