@@ -354,8 +354,8 @@ def analytics_leg(args, seed, mask_np, mask):
     the paper's shell optics, 1e8 photons) over the 256^3 phi = 0.70 mask: chord
     histograms on all three axes, the pore distance transform, the brightest-decile
     co-localisation and the pore-phase Spearman correlation on deep slices
-    (z >= 0.1 mm = slice 69 at 1.45 um voxels), the depth-normalised phase contrast,
-    and escape-path histograms of 1e7 traced photons.  Each call timed with events on
+    (z >= 0.1 mm = slice 69 at 1.45 um voxels), the mask's radial PSD, the
+    depth-normalised phase contrast, and escape-path histograms of 1e7 traced photons.  Each call timed with events on
     torch's current stream (the one the bindings launch on), warm (second call); the
     oracle's co-localisation and Spearman on the same tally as the CPU reference and
     parity check."""
@@ -417,6 +417,10 @@ def analytics_leg(args, seed, mask_np, mask):
     r = rho.cpu().numpy()
     out["pore_spearman"] = {"mean": float(np.nanmean(r)), "sd": float(np.nanstd(r, ddof=1)),
                             "slices": int(np.isfinite(r).sum())}
+    psd, out["ms"]["mask_psd"] = timed(lambda: an.mask_psd(mask))
+    pn = psd.cpu().numpy()
+    s_peak = int(np.argmax(pn[1:])) + 1
+    out["mask_psd"] = {"peak_shell": s_peak, "dominant_size_voxels": max(mask_np.shape) / (2.0 * s_peak)}
     pc, out["ms"]["phase_contrast"] = timed(lambda: an.phase_contrast(depth, 0))
     out["phase_contrast"] = {k: float(v) for k, v in pc.items()}
     m_tr = 10_000_000

@@ -76,6 +76,17 @@ size_t mc_pore_spearman_workspace_bytes(const mc_volume *vol, int32_t z0);
 int mc_pore_spearman(const mc_volume *vol, const int64_t *fluence, int32_t z0, double *rho, int64_t *n_pore,
                      void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* Sec. 3.2, Fig. 2b: radial power spectral density of the binary mask itself
+ * (values 0 and 1), with the shells and conventions of mc_ch_psd (spinodal.h):
+ * psd[s], s = 0 .. max(nx,ny,nz)/2, sums |m_hat_k|^2 of the unnormalised forward
+ * transform over s - 1/2 <= |k| max(nx,ny,nz) / (2 pi) < s + 1/2, the k = 0 mode
+ * excluded; the dominant pore-plus-strut size is max(nx,ny,nz) / (2 s_peak).
+ * The grid limits are those of the Cahn-Hilliard transforms: nx even, every extent
+ * a product of powers of 2 and 3 up to 1024.
+ *   psd  device double[max(nx,ny,nz)/2 + 1] (written) */
+size_t mc_mask_psd_workspace_bytes(const mc_volume *vol);
+int mc_mask_psd(const mc_volume *vol, double *psd, void *workspace, size_t workspace_bytes, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -109,3 +109,19 @@ def pore_spearman(mask: torch.Tensor, fluence: torch.Tensor, z0: int):
     pm._check(L.mc_pore_spearman(ctypes.byref(vol), _ptr(fluence.contiguous()), int(z0), _ptr(rho), _ptr(n),
                                  _ptr(ws), ws.numel(), pm._stream(dev)), "mc_pore_spearman")
     return rho, n
+
+
+def mask_psd(mask: torch.Tensor) -> torch.Tensor:
+    """float64 [max(nx,ny,nz)/2 + 1]: radial power spectral density of the binary mask
+    (shell sums of |m_hat|^2, the mean excluded); dominant size = N_max / (2 s_peak)."""
+    L = pm.load()
+    vol = pm.volume(mask)
+    dev = mask.device
+    nb = max(mask.shape) // 2 + 1
+    out = torch.empty(nb, dtype=torch.float64, device=dev)
+    need = L.mc_mask_psd_workspace_bytes(ctypes.byref(vol))
+    if need == 0:
+        raise ValueError(f"mc_mask_psd: unsupported grid {tuple(mask.shape)}: {L.mc_last_error().decode()}")
+    ws = pm.workspace(need, dev)
+    pm._check(L.mc_mask_psd(ctypes.byref(vol), _ptr(out), _ptr(ws), ws.numel(), pm._stream(dev)), "mc_mask_psd")
+    return out

@@ -26,6 +26,7 @@
 
 #include "internal.hpp"
 #include "select.hpp"
+#include "analytics.h"
 #include "spinodal.h"
 
 using namespace pmc::host;
@@ -410,9 +411,10 @@ __device__ __forceinline__ void gather(int total, Load load, Store store)
     }
 }
 
-enum { X_INIT = 0, X_NONLIN = 1, X_FIELD = 2 };
+enum { X_INIT = 0, X_NONLIN = 1, X_FIELD = 2, X_MASK = 3 };
 
-// Lines along x.  X_INIT: real line -> forward transform, half spectrum out.
+// Lines along x.  X_INIT: real line -> forward transform, half spectrum out;
+// X_MASK: the same from a uint8 mask line (0 or 1 as doubles).
 // X_NONLIN: half spectrum -> inverse -> f'(phi) -> forward -> half spectrum.
 // X_FIELD: half spectrum -> inverse -> real line out.  `scale` = 1/(nx ny nz).
 //
@@ -428,7 +430,8 @@ enum { X_INIT = 0, X_NONLIN = 1, X_FIELD = 2 };
 template <int MODE, int N>
 __global__ __launch_bounds__(kThreads) void k_xpass(const double *__restrict__ rin, double2 *spec,
                                                      double *__restrict__ rout, int nx, int nlines_total, int L,
-                                                     Plan P, const double2 *__restrict__ tw, double scale)
+                                                     Plan P, const double2 *__restrict__ tw, double scale,
+                                                     const uint8_t *__restrict__ mask_in)
 {
     __shared__ double2 buf[N > 0 ? kPadElems : kLdsElems];
     __shared__ double2 tw_s[N > 0 ? kPadTw : kTwElems];
@@ -440,11 +443,12 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const double *__restrict__ r
     const int np = (nl + 1) >> 1;
     const int tid = (int)threadIdx.x;
     const float inv_nx = 1.0f / (float)nx, inv_hx = 1.0f / (float)hx;
-    if (MODE == X_INIT) {
+    if (MODE == X_INIT || MODE == X_MASK) {
         // the block's lines are contiguous in memory
         const double *src = rin + (size_t)line0 * nx;
+        const uint8_t *msrc = mask_in + (size_t)line0 * nx;
         gather<8, double>(
-            nl * nx, [&](int e) { return src[e]; },
+            nl * nx, [&](int e) { return MODE == X_MASK ? (double)msrc[e] : src[e]; },
             [&](int e, double v) {
                 const int l = fdiv(e, nx, inv_nx), x = e - l * nx;
                 bd[2 * ((l >> 1) * ls + pidx<N>(x)) + (l & 1)] = v;
@@ -796,13 +800,14 @@ void enqueue_col(const Geo &G, int axis, double2 *A, const Ptrs &P, bool inv, hi
 }
 
 template <int MODE>
-void enqueue_x(const Geo &G, const double *rin, double2 *spec, double *rout, const Ptrs &P, hipStream_t s)
+void enqueue_x(const Geo &G, const double *rin, double2 *spec, double *rout, const Ptrs &P, hipStream_t s,
+               const uint8_t *mask_in = nullptr)
 {
     const int lines = G.nz * G.ny;
     const double scale = 1.0 / ((double)G.nx * (double)G.ny * (double)G.nz);
     with_length(G.nx, [&](auto nc) {
         hipLaunchKernelGGL((k_xpass<MODE, decltype(nc)::value>), dim3((unsigned)((lines + G.Lx - 1) / G.Lx)),
-                           dim3(kThreads), 0, s, rin, spec, rout, G.nx, lines, G.Lx, G.px, P.twx, scale);
+                           dim3(kThreads), 0, s, rin, spec, rout, G.nx, lines, G.Lx, G.px, P.twx, scale, mask_in);
     });
 }
 
@@ -930,6 +935,51 @@ int mc_ch_psd(const mc_ch_grid *g, const double *state, double *psd, void *works
     if (rc) return rc;
     const int nb = std::max(G.nx, std::max(G.ny, G.nz)) / 2 + 1;
     hipLaunchKernelGGL(k_psd_partial, dim3(kPsdBlocks), dim3(kThreads), 0, s, (const double2 *)state, G.nx, G.ny, G.nz,
+                       P.kx2, P.ky2, P.kz2, P.psd_partial, nb);
+    hipLaunchKernelGGL(k_psd_sum, dim3((nb + 255) / 256), dim3(256), 0, s, P.psd_partial, kPsdBlocks, nb, psd);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
+
+static void mask_grid(const mc_volume *vol, mc_ch_grid *g)
+{
+    memset(g, 0, sizeof *g);
+    g->nx = vol->nx;
+    g->ny = vol->ny;
+    g->nz = vol->nz;
+    g->kappa = 1.0;   // unused by the transforms
+    g->dt = 1.0;
+}
+
+size_t mc_mask_psd_workspace_bytes(const mc_volume *vol)
+{
+    clear_error();
+    if (check_volume(vol)) return 0;
+    mc_ch_grid g;
+    mask_grid(vol, &g);
+    Geo G;
+    if (geometry(&g, &G)) return 0;
+    return G.total;
+}
+
+int mc_mask_psd(const mc_volume *vol, double *psd, void *workspace, size_t workspace_bytes, void *hip_stream)
+{
+    clear_error();
+    int rc = check_volume(vol);
+    if (rc) return rc;
+    if (!psd) return fail(MC_EINVAL, "psd is NULL");
+    mc_ch_grid g;
+    mask_grid(vol, &g);
+    hipStream_t s = (hipStream_t)hip_stream;
+    Geo G;
+    Ptrs P;
+    if ((rc = prepare(&g, workspace, workspace_bytes, s, &G, &P))) return rc;
+    // forward transform of the mask into W: x (from the bytes), y, then z in place
+    enqueue_x<X_MASK>(G, nullptr, P.W, nullptr, P, s, vol->mask);
+    enqueue_col(G, 1, P.W, P, false, s);
+    if (G.nz > 1) enqueue_z<Z_INIT>(G, P.W, P, g.dt, g.kappa, false, s);
+    const int nb = std::max(G.nx, std::max(G.ny, G.nz)) / 2 + 1;
+    hipLaunchKernelGGL(k_psd_partial, dim3(kPsdBlocks), dim3(kThreads), 0, s, (const double2 *)P.W, G.nx, G.ny, G.nz,
                        P.kx2, P.ky2, P.kz2, P.psd_partial, nb);
     hipLaunchKernelGGL(k_psd_sum, dim3((nb + 255) / 256), dim3(256), 0, s, P.psd_partial, kPsdBlocks, nb, psd);
     HIP_TRY(hipGetLastError());

@@ -121,6 +121,8 @@ _SIGS = {
     "mc_pore_distance_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_pore_distance": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, _P]),
     "mc_pore_spearman_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
+    "mc_mask_psd_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "mc_mask_psd": (ctypes.c_int, [_P, _P, _P, ctypes.c_size_t, _P]),
     "mc_pore_spearman": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
     "mc_ch_generate": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_double, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),

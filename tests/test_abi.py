@@ -99,6 +99,11 @@ def test_workspace_sizes(lib):
     assert lib.mc_pore_spearman_workspace_bytes(ctypes.byref(vol), -1) == 0
     assert lib.mc_pore_spearman(ctypes.byref(vol), None, 0, None, None, None, 0, None) == -1
     assert b"NULL" in lib.mc_last_error()
+    # the mask PSD takes the transform's grid limits: nx even, factors 2 and 3 only
+    assert lib.mc_mask_psd_workspace_bytes(ctypes.byref(vol)) == 0          # nx = 9
+    ok = pm.McVolume(8, 6, 4, 0, 1)
+    assert lib.mc_mask_psd_workspace_bytes(ctypes.byref(ok)) > 0
+    assert lib.mc_mask_psd(ctypes.byref(ok), None, None, 0, None) == -1
 
 
 def _job(nx=8, ny=8, nz=8, mask=1, n=10, mu_s=0.5, g=0.7):

@@ -238,3 +238,34 @@ def test_pore_spearman_fullsize():
     assert np.all(np.abs(r[ok] - rw[ok]) <= 1e-12)
     print(f"256^3 phi 0.70, z >= {z0}: rho = {np.nanmean(rw):+.4f} +- {np.nanstd(rw, ddof=1):.4f} "
           f"over {ok.sum()} slices")
+
+
+@pytest.mark.parametrize("shape", [(6, 4, 24), (12, 18, 24), (32, 32, 32), (1, 9, 12)])
+def test_mask_psd(shape, mask_m1):
+    banner(f"mask PSD vs oracle, shape {shape}")
+    if shape == (32, 32, 32):
+        m = mask_m1
+    elif shape == (6, 4, 24):
+        m = np.zeros(shape, dtype=np.uint8)
+        m[:, :, (np.arange(24) % 12) < 6] = 1
+    else:
+        m = (np.random.default_rng(sum(shape)).random(shape) < 0.7).astype(np.uint8)
+    got = an.mask_psd(dev(m)).cpu().numpy()
+    want = oan.mask_psd(m)
+    assert got.shape == want.shape
+    assert np.all(np.abs(got - want) <= 1e-12 * want.max()), np.abs(got - want).max() / want.max()
+
+
+def test_mask_psd_fullsize_and_limits():
+    banner("mask PSD at 256^3 vs oracle; unsupported grids refused")
+    wl = inputs.WORKLOADS["M2a"]
+    m = inputs.spinodal_mask(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], wl["porosity"], seed=0)
+    got = an.mask_psd(dev(m)).cpu().numpy()
+    want = oan.mask_psd(m)
+    assert np.all(np.abs(got - want) <= 1e-12 * want.max())
+    s_peak = int(np.argmax(want[1:])) + 1
+    print(f"256^3 phi 0.70 (lambda 24): PSD peak shell {s_peak}, dominant size {256 / (2 * s_peak):.2f} voxels")
+    with pytest.raises(ValueError):
+        an.mask_psd(dev(np.ones((4, 4, 5), dtype=np.uint8)))          # odd nx
+    with pytest.raises(ValueError):
+        an.mask_psd(dev(np.ones((4, 4, 10), dtype=np.uint8)))         # factor 5
