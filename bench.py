@@ -31,6 +31,7 @@ SOURCES = ["include/photonmc.h", "paper_2604_13929_amd/csrc/batch.hip", "paper_2
            "paper_2604_13929_amd/csrc/philox.hpp", "paper_2604_13929_amd/csrc/photonmc.hip",
            "paper_2604_13929_amd/csrc/walk.hpp"]
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_walk_plain_256cube_phi070_traffic.json")
+FORMS_RECORD = os.path.join(ROOT, "profiles", "k_walk_batch_grad_counters.json")
 
 
 def source_sha256() -> str:
@@ -54,6 +55,33 @@ def recorded_traffic(photons: int):
     if rec.get("source_sha256") != source_sha256():
         return None
     return rec, rec["traffic_bytes_per_launch"] * photons / rec["photons"]
+
+
+def walk_roofline(form: str, photon_steps: int, walk_ms: float):
+    """Roofline of the batched or differentiated walk launch just timed: the algorithmic
+    HBM rate (8 B per photon-step) against 8 TB/s, and the memory-side atomic request
+    rate (requests per launch from the committed counter record of the same workload)
+    against the measured random-atomic ceiling; None for the latter when the kernel
+    sources changed since the counters were taken."""
+    achieved = photon_steps * BYTES_PER_STEP / (walk_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "algorithmic_bytes_per_step": BYTES_PER_STEP, "atomic_request_roof": None}
+    try:
+        with open(FORMS_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return out
+    if rec.get("source_sha256") != source_sha256():
+        return out
+    r = rec[form]
+    req = r["atomic_requests_per_launch"] * photon_steps / r["photon_steps"]
+    out["traffic"] = r["traffic_bytes_per_launch"] * photon_steps / r["photon_steps"]
+    out["atomic_request_roof"] = {"requests_per_launch": req, "requests_per_step": req / photon_steps,
+                                  "achieved_requests_per_s": req / (walk_ms * 1e-3),
+                                  "probe_requests_per_s": rec["probe_random_atomic64_128MiB_per_s"],
+                                  "frac": req / (walk_ms * 1e-3) / rec["probe_random_atomic64_128MiB_per_s"],
+                                  "source": os.path.relpath(FORMS_RECORD, ROOT)}
+    return out
 
 
 def log(msg):
@@ -124,7 +152,8 @@ def batched_leg(args, seed):
             "photons": n_total, "photon_steps": steps, "voxels": vox,
             "ms": t_b * 1e3, "walk_ms": min(walk), "photon_steps_per_s": steps / t_b, "photons_per_s": n_total / t_b,
             "sequential_plain_ms": t_seq * 1e3, "sequential_photon_steps_per_s": steps / t_seq,
-            "speedup_vs_sequential": t_seq / t_b, "jobs_bitwise_equal_to_plain": identical}
+            "speedup_vs_sequential": t_seq / t_b, "jobs_bitwise_equal_to_plain": identical,
+            "roofline": walk_roofline("batched", steps, min(walk))}
 
 
 def morphology_leg(args, seed):
@@ -537,7 +566,7 @@ def grad_leg(args, seed, mask):
             "workload": "plain workload, d<Phi>_3D and d<Phi>_1D (and dPhi(z)) wrt solid mu_s, mu_a, g",
             "ms": t_lr * 1e3, "walk_ms": g.walk_ms, "photon_steps_per_s": steps / t_lr, "photons_per_s": n / t_lr,
             "check_vs_crn_fd": res, "fd_relative_step": h, "subranges": B,
-            "columns": ["d_phi3d", "d_phi1d"]}
+            "columns": ["d_phi3d", "d_phi1d"], "roofline": walk_roofline("differentiated", steps, g.walk_ms)}
 
 
 def main():
