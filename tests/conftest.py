@@ -20,3 +20,12 @@ def mask_m1():
     """32^3 bicontinuous mask, lambda = 8 voxels, phi = 0.70, mask seed 0."""
     from paper_2604_13929_amd import inputs
     return inputs.spinodal_mask(32, 32, 32, 8.0, 0.70, seed=0)
+
+
+GOLDEN = os.path.join(TESTS, "golden")
+
+
+def golden(name: str):
+    """Rows of a cited text fixture under tests/golden/ ('#' lines are the citation)."""
+    import numpy as np
+    return np.atleast_2d(np.loadtxt(os.path.join(GOLDEN, name), comments="#"))

@@ -10,13 +10,14 @@ import closed_forms as cf
 import oracle
 from oracle import estimators as est
 from paper_2604_13929_amd import inputs
+from conftest import golden
 
 
 # -- the paper's printed numbers ------------------------------------------------
 def test_dilution_identity_reproduces_printed_ratios():
     """Sec. 2.8 (b) / Table S2: r = 0.5142 (phi = 0.70) and 0.5152 (phi = 0.90) give
     <Phi>_3D/<Phi>_1D = 1.5153 and 1.7739 through Eq. dilution."""
-    for phi, r, ratio in [(0.70, 0.5142, 1.5153), (0.90, 0.5152, 1.7739)]:
+    for phi, _, _, _, r, ratio in golden("dilution_identity.txt"):
         pred = 1.0 / (phi * r + (1.0 - phi))
         # r and the ratio are printed to 4 decimals: allow half a unit of each
         tol = pred ** 2 * phi * 0.5e-4 + 0.5e-4
@@ -25,27 +26,26 @@ def test_dilution_identity_reproduces_printed_ratios():
 
 def test_pore_average_reproduces_printed_values():
     """Table S2: <Phi>_pore from <Phi>_1D = phi <Phi>_pore + (1 - phi) <Phi>_3D."""
-    for phi, p3, p1, pore in [(0.70, 6.17e19, 4.07e19, 3.170e19), (0.90, 1.238e20, 6.98e19, 6.381e19)]:
+    for phi, p3, p1, pore, _, _ in golden("dilution_identity.txt"):
         assert (p1 - (1 - phi) * p3) / phi == pytest.approx(pore, rel=2e-3)
 
 
 def test_da_worked_values():
     """Sec. 2.4 with Table 1 / Table S2 parameters: L_opt = 521 / 852 um and
     <Phi>_DA = 7.73e19 / 1.266e20 photon m^-2 s^-1 at S0 = 8.27e19, L = 557 um."""
-    L, S0 = 557e-6, 8.27e19
-    assert cf.da_lopt(1548.0, 6035.0, L) == pytest.approx(521e-6, rel=1e-3)
-    assert cf.da_mean(1548.0, 6035.0, L, S0) == pytest.approx(7.73e19, rel=1e-3)
-    assert cf.da_lopt(516.0, 2012.0, L) == pytest.approx(852e-6, rel=1e-3)
-    assert cf.da_mean(516.0, 2012.0, L, S0) == pytest.approx(1.266e20, rel=1e-3)
+    for _, mua, musr, L, S0, lopt, phi_da, _, _, _ in golden("diffusion_approximation.txt"):
+        assert cf.da_lopt(mua, musr, L) == pytest.approx(lopt, rel=1e-3)
+        assert cf.da_mean(mua, musr, L, S0) == pytest.approx(phi_da, rel=1e-3)
 
 
 def test_da_parameters_table1():
     """Table 1: D = 4.40e-5 m, kappa = 5934 m^-1, kappa L = 3.30, z_b = 110.5 um."""
-    p = cf.da_params(1548.0, 6035.0)
-    assert p["D"] == pytest.approx(4.40e-5, rel=2e-3)
-    assert p["kappa"] == pytest.approx(5934.0, rel=2e-4)
-    assert p["kappa"] * 557e-6 == pytest.approx(3.30, abs=6e-3)
-    assert p["z_b"] == pytest.approx(110.5e-6, rel=1e-3)
+    _, mua, musr, L, _, _, _, D, kappa, z_b = golden("diffusion_approximation.txt")[0]
+    p = cf.da_params(mua, musr)
+    assert p["D"] == pytest.approx(D, rel=2e-3)
+    assert p["kappa"] == pytest.approx(kappa, rel=2e-4)
+    assert p["kappa"] * L == pytest.approx(3.30, abs=6e-3)
+    assert p["z_b"] == pytest.approx(z_b, rel=1e-3)
 
 
 def test_da_boundary_conditions():

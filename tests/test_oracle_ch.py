@@ -25,12 +25,14 @@ import numpy as np
 import pytest
 
 from oracle import cahn_hilliard as ch
+from conftest import golden
 
 
 def test_paper_worked_values():
-    kappa = ch.kappa_from_target(17.4 / 1.45)
-    assert round(kappa, 4) == 0.1140
-    assert round(ch.dt_from_kappa(kappa), 4) == 0.0450
+    for d_target, a_vox, kappa_printed, dt_printed in golden("cahn_hilliard_calibration.txt"):
+        kappa = ch.kappa_from_target(d_target / a_vox)
+        assert round(kappa, 4) == kappa_printed
+        assert round(ch.dt_from_kappa(kappa), 4) == dt_printed
     roots = np.sort(np.roots([12.0, -12.0, 2.0]))
     assert np.allclose(np.round(roots, 3), [0.211, 0.789])
     assert ch.f_second(0.5) == -1.0

@@ -8,14 +8,15 @@ from __future__ import annotations
 import math
 
 from paper_2604_13929_amd import photonmc as pm
+from conftest import golden
 
 A_VOX = 1.45e-6
 L = 384 * A_VOX
 
 
 def test_gate_reproduces_the_papers_values():
-    for phi, printed in ((0.70, 2.46e-10), (0.90, 8.21e-11)):
-        t = pm.time_gate_seconds(5159.0, 20118.0, phi, L, 1.746)
+    for phi, mua, musr, n_eff, nvox, a_vox, printed in golden("time_gate.txt"):
+        t = pm.time_gate_seconds(mua, musr, phi, nvox * a_vox, n_eff)
         assert math.isclose(t, printed, rel_tol=2e-3), (phi, t, printed)
 
 
