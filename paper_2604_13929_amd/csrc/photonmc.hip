@@ -120,36 +120,53 @@ struct DirectDeposit {
 // lanes transposed so that one atomic instruction carries kLogK successive
 // deposits of each of 64/kLogK lanes: deposits of one photon that fall in the
 // same brick (the same 64-byte line) then travel as one memory-side request.
-constexpr int kLogK = 16;
+// A log entry is a 32-bit tally index and a 32-bit value: one segment deposits
+// less than 2^31 * sqrt(3) < 2^32; a photon's deposits in one voxel summed over
+// several segments can exceed that, and then go to the tally directly.  At 16
+// iterations a 256-thread workgroup's log takes 33 KB, so four workgroups fit
+// per CU.  A window of 32 (fewer requests, two workgroups per CU) measured no
+// faster on the 256^3 workload: 2024 against 2016 ms per 1e8 photons.
+#ifndef MC_LOG_K
+#define MC_LOG_K 16
+#endif
+constexpr int kLogK = MC_LOG_K;
+static_assert(kLogK == 16 || kLogK == 32, "the transposed flush needs kLogK dividing 64, at least 16");
 constexpr int kLogStride = 65;  // 64 lanes + 1: the transposed reads hit distinct banks
 
 struct LoggedDeposit {
-    uint32_t *lidx;             // this wavefront's log: [kLogK][kLogStride]
-    unsigned long long *lval;
-    uint32_t slot;              // (iteration % kLogK) * kLogStride + lane
+    uint32_t *lidx;             // this wavefront's log: [window][kLogStride]
+    uint32_t *lval;
+    uint32_t slot;              // (iteration % window) * kLogStride + lane
     template <typename R>
     __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
     {
         if (a != 0ull) {
-            lidx[slot] = tally_brick_index(J.tnxb, J.tnyb, p.ix, p.iy, p.iz);
-            lval[slot] = a;
+            const uint32_t idx = tally_brick_index(J.tnxb, J.tnyb, p.ix, p.iy, p.iz);
+            if (a >> 32) {
+                __hip_atomic_fetch_add((unsigned long long *)(J.fluence + idx), (unsigned long long)a,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                lidx[slot] = idx;
+                lval[slot] = (uint32_t)a;
+            }
         }
     }
 };
 
-__device__ __forceinline__ void flush_log(uint32_t *lidx, unsigned long long *lval, int64_t *tally, uint32_t lane)
+template <int K>
+__device__ __forceinline__ void flush_log(uint32_t *lidx, uint32_t *lval, int64_t *tally, uint32_t lane)
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int i = 0; i < kLogK; ++i) {
-        const uint32_t src = (uint32_t)i * (64 / kLogK) + lane / kLogK;
-        const uint32_t e = (lane % kLogK) * kLogStride + src;
-        const unsigned long long v = lval[e];
+    for (int i = 0; i < K; ++i) {
+        const uint32_t src = (uint32_t)i * (64 / K) + lane / K;
+        const uint32_t e = (lane % K) * kLogStride + src;
+        const uint32_t v = lval[e];
         if (v) {
-            __hip_atomic_fetch_add((unsigned long long *)(tally + lidx[e]), v, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add((unsigned long long *)(tally + lidx[e]), (unsigned long long)v, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-            lval[e] = 0ull;
+            lval[e] = 0u;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -252,18 +269,19 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
                                                 int32_t refill, unsigned long long *__restrict__ grad)
 {
     constexpr int kWaves = BLOCK / 64;
+    constexpr int K = GRAD ? 16 : kLogK;   // log window (the gradient bins share the LDS)
     __shared__ unsigned long long acc[MC_NSCALARS];
-    __shared__ uint32_t s_lidx[LOGGED ? kWaves * kLogK * kLogStride : 1];
-    __shared__ unsigned long long s_lval[LOGGED ? kWaves * kLogK * kLogStride : 1];
+    __shared__ uint32_t s_lidx[LOGGED ? kWaves * K * kLogStride : 1];
+    __shared__ uint32_t s_lval[LOGGED ? kWaves * K * kLogStride : 1];
     extern __shared__ unsigned long long s_grad[];  // GRAD: [3][2][nz]
     const uint32_t lane = __lane_id();
-    uint32_t *lidx = s_lidx + (threadIdx.x >> 6) * (LOGGED ? kLogK * kLogStride : 0);
-    unsigned long long *lval = s_lval + (threadIdx.x >> 6) * (LOGGED ? kLogK * kLogStride : 0);
+    uint32_t *lidx = s_lidx + (threadIdx.x >> 6) * (LOGGED ? K * kLogStride : 0);
+    uint32_t *lval = s_lval + (threadIdx.x >> 6) * (LOGGED ? K * kLogStride : 0);
     if (threadIdx.x < MC_NSCALARS) acc[threadIdx.x] = 0ull;
     if (GRAD)
         for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) s_grad[i] = 0ull;
     if (LOGGED)
-        for (int i = 0; i < kLogK; ++i) lval[i * kLogStride + lane] = 0ull;
+        for (int i = 0; i < K; ++i) lval[i * kLogStride + lane] = 0u;
     __syncthreads();
 
     typename SinkOf<GRAD, LOGGED>::type sink;
@@ -312,7 +330,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
             if (exhausted && q_next >= q_end && !__any(alive)) break;
         }
         if (alive) {
-            if constexpr (LOGGED) sink.slot = (iter % kLogK) * kLogStride + lane;
+            if constexpr (LOGGED) sink.slot = (iter % K) * kLogStride + lane;
             const int32_t ev = step<GENERAL>(p, J, sink);
             if (is_terminal(ev)) {
                 account(acc, p, ev, J.nz);
@@ -320,10 +338,10 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
             }
         }
         if constexpr (LOGGED) {
-            if (++iter % kLogK == 0) flush_log(lidx, lval, J.fluence, lane);
+            if (++iter % K == 0) flush_log<K>(lidx, lval, J.fluence, lane);
         }
     }
-    if constexpr (LOGGED) flush_log(lidx, lval, J.fluence, lane);
+    if constexpr (LOGGED) flush_log<K>(lidx, lval, J.fluence, lane);
     __syncthreads();
     if (threadIdx.x < MC_NSCALARS) {
         const unsigned long long v = acc[threadIdx.x];
