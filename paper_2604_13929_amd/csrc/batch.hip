@@ -56,32 +56,42 @@ struct BatchTallySink {
     }
 };
 
-// Line-coalesced deposits for the batch: as the plain walk's log, with the job
-// index in the top 6 bits of each logged value (a per-visit deposit stays below
-// 2^58 Q31 units because batch jobs cap a photon at 2^26 steps).
-constexpr int kBLogK = 8;
+// Line-coalesced deposits for the batch: as the plain walk's log (8-byte
+// entries, a 16-iteration window), with the job index in the top 6 bits of the
+// 32-bit entry index, which leaves 26 bits for the word index into the job's
+// bricked tally (the batch logs only when every job's tally is that small).  A
+// value of 2^32 or more goes to the tally directly.  The window's 33 KB of LDS
+// per 256-thread workgroup, with the job table and the per-job channels,
+// still lets three workgroups share a CU.
+constexpr int kBLogK = 16;
 constexpr int kBLogStride = 65;
-constexpr int kJobShift = 58;
-constexpr unsigned long long kValMask = (1ull << kJobShift) - 1ull;
+constexpr int kJobShift = 26;
+constexpr uint32_t kIdxMask = (1u << kJobShift) - 1u;
+constexpr uint64_t kBatchLogWords = 1ull << kJobShift;   // largest tally a logged batch job may have
 
 struct BatchLoggedSink {
     uint32_t *lidx;
-    unsigned long long *lval;
+    uint32_t *lval;
     uint32_t slot;
-    unsigned long long tag;     // job << kJobShift
+    uint32_t tag;               // job << kJobShift
     template <typename R> __device__ __forceinline__ void segment(const Photon<R> &, const Job &, R, bool) {}
     template <typename R> __device__ __forceinline__ void deflect(Photon<R> &, const Job &, R) {}
     template <typename R> __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
     {
         if (a != 0ull) {
-            lidx[slot] = tally_brick_index(J.tnxb, J.tnyb, p.ix, p.iy, p.iz);
-            lval[slot] = a | tag;
+            const uint32_t idx = tally_brick_index(J.tnxb, J.tnyb, p.ix, p.iy, p.iz);
+            if (a >> 32) {
+                __hip_atomic_fetch_add((unsigned long long *)(J.fluence + idx), (unsigned long long)a,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                lidx[slot] = idx | tag;
+                lval[slot] = (uint32_t)a;
+            }
         }
     }
 };
 
-__device__ __forceinline__ void flush_batch_log(uint32_t *lidx, unsigned long long *lval, const Job *jobs,
-                                                uint32_t lane)
+__device__ __forceinline__ void flush_batch_log(uint32_t *lidx, uint32_t *lval, const Job *jobs, uint32_t lane)
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -89,12 +99,13 @@ __device__ __forceinline__ void flush_batch_log(uint32_t *lidx, unsigned long lo
     for (int i = 0; i < kBLogK; ++i) {
         const uint32_t src = (uint32_t)i * (64 / kBLogK) + lane / kBLogK;
         const uint32_t e = (lane % kBLogK) * kBLogStride + src;
-        const unsigned long long v = lval[e];
+        const uint32_t v = lval[e];
         if (v) {
-            int64_t *tally = jobs[v >> kJobShift].fluence;
-            __hip_atomic_fetch_add((unsigned long long *)(tally + lidx[e]), v & kValMask, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            lval[e] = 0ull;
+            const uint32_t w = lidx[e];
+            int64_t *tally = jobs[w >> kJobShift].fluence;
+            __hip_atomic_fetch_add((unsigned long long *)(tally + (w & kIdxMask)), (unsigned long long)v,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            lval[e] = 0u;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -141,12 +152,12 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
     __shared__ Job s_jobs[MC_MAX_BATCH_JOBS];
     __shared__ unsigned long long acc[MC_MAX_BATCH_JOBS][MC_NSCALARS];
     __shared__ uint32_t s_lidx[LOGGED ? kWaves * kBLogK * kBLogStride : 1];
-    __shared__ unsigned long long s_lval[LOGGED ? kWaves * kBLogK * kBLogStride : 1];
+    __shared__ uint32_t s_lval[LOGGED ? kWaves * kBLogK * kBLogStride : 1];
     const uint32_t lane = __lane_id();
     uint32_t *lidx = s_lidx + (threadIdx.x >> 6) * (LOGGED ? kBLogK * kBLogStride : 0);
-    unsigned long long *lval = s_lval + (threadIdx.x >> 6) * (LOGGED ? kBLogK * kBLogStride : 0);
+    uint32_t *lval = s_lval + (threadIdx.x >> 6) * (LOGGED ? kBLogK * kBLogStride : 0);
     if (LOGGED)
-        for (int i = 0; i < kBLogK; ++i) lval[i * kBLogStride + lane] = 0ull;
+        for (int i = 0; i < kBLogK; ++i) lval[i * kBLogStride + lane] = 0u;
     {
         const uint64_t *src = (const uint64_t *)jobs;
         uint64_t *dst = (uint64_t *)s_jobs;
@@ -211,7 +222,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
             const Job &J = s_jobs[job];
             if constexpr (LOGGED) {
                 sink.slot = (iter % kBLogK) * kBLogStride + lane;
-                sink.tag = (unsigned long long)job << kJobShift;
+                sink.tag = (uint32_t)job << kJobShift;
             }
             const int32_t ev = step<GENERAL>(p, J, sink);
             if (is_terminal(ev)) {
@@ -239,7 +250,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t jobs_off, bricks_off[MC_MAX_BATCH_JOBS], bins_off[MC_MAX_BATCH_JOBS], tally_off[MC_MAX_BATCH_JOBS], total;
-    bool logged;   // every job's bricked tally fits 32-bit indices
+    bool logged;   // every job's bricked tally fits the log's 26-bit indices
 };
 
 Layout layout_of(const mc_job *jobs, int32_t n)
@@ -249,7 +260,7 @@ Layout layout_of(const mc_job *jobs, int32_t n)
     L.jobs_off = off;
     off += align_up(sizeof(Job) * MC_MAX_BATCH_JOBS);
     L.logged = true;
-    for (int32_t i = 0; i < n; ++i) L.logged = L.logged && dims_of(&jobs[i].vol).logged;
+    for (int32_t i = 0; i < n; ++i) L.logged = L.logged && dims_of(&jobs[i].vol).tally_words <= kBatchLogWords;
     for (int32_t i = 0; i < n; ++i) {
         const Dims d = dims_of(&jobs[i].vol);
         L.bricks_off[i] = off;
