@@ -17,7 +17,6 @@
 
 #include <math.h>
 #include <stdint.h>
-#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -909,19 +908,15 @@ int mc_pore_spearman(const mc_volume *vol, const int64_t *fluence, int32_t z0, d
     hipLaunchKernelGGL(k_compact, dim3(nseg), dim3(256), 0, s, vol->mask, (const long long *)fluence, e.g, n_slice, z0,
                        begin, kf, kd, pos);
     HIP_TRY(hipGetLastError());
-    // the total number of pore voxels decides the sort sizes: bring it to the host
+    // the total number of pore voxels (the end of the last segment) sizes the sorts:
+    // bring that one number to the host
     long long total = 0;
     {
-        long long *h = (long long *)malloc(sizeof(long long) * nseg);
-        if (!h) return fail(MC_EINVAL, "host allocation failed");
-        const hipError_t err = hipMemcpyAsync(h, counts, sizeof(long long) * nseg, hipMemcpyDeviceToHost, s);
+        int last_end = 0;
+        const hipError_t err = hipMemcpyAsync(&last_end, end + (nseg - 1), sizeof(int), hipMemcpyDeviceToHost, s);
         const hipError_t err2 = err == hipSuccess ? hipStreamSynchronize(s) : err;
-        if (err2 != hipSuccess) {
-            free(h);
-            return fail(MC_EHIP, "reading the pore counts: %s", hipGetErrorString(err2));
-        }
-        for (int i = 0; i < nseg; ++i) total += h[i];
-        free(h);
+        if (err2 != hipSuccess) return fail(MC_EHIP, "reading the pore count: %s", hipGetErrorString(err2));
+        total = last_end;
     }
     if (total > 0) {
         size_t tmp = L.tmp_bytes;
