@@ -47,6 +47,12 @@ constexpr int kMaxN = 1024;
 constexpr int kTwElems = 768;             // LDS twiddles: n/2 for even n (w(m + n/2) = -w(m)), n for odd n <= 729
 constexpr int kPadElems = 4400;           // LDS of the compile-time lengths: lines padded by one per 16
 constexpr int kPadTw = 528;               // their twiddles: n/2 padded by one per 32
+// The x pass of the compile-time lengths takes 2048 complex values per workgroup
+// (two or more line pairs): 35 KB of LDS with the padding, 43 KB with the
+// twiddles, so three workgroups share a CU (at 1024: 2003 us against 2200 with
+// 4096 values, two workgroups per CU, and 2185 with 1024 values, one pair).
+constexpr int kXElems = 2048;
+constexpr int kXPadElems = 2200;
 
 // LDS index of element i of a line: the compile-time lengths insert one pad
 // element per 16 (and one per 32 in the twiddle table), which spreads the
@@ -433,7 +439,7 @@ __global__ __launch_bounds__(kThreads) void k_xpass(const double *__restrict__ r
                                                      Plan P, const double2 *__restrict__ tw, double scale,
                                                      const uint8_t *__restrict__ mask_in)
 {
-    __shared__ double2 buf[N > 0 ? kPadElems : kLdsElems];
+    __shared__ double2 buf[N > 0 ? kXPadElems : kLdsElems];
     __shared__ double2 tw_s[N > 0 ? kPadTw : kTwElems];
     load_twiddles<N>(tw_s, tw, nx);
     double *bd = reinterpret_cast<double *>(buf);   // bd[2 p] = buf[p].x, bd[2 p + 1] = buf[p].y
@@ -702,14 +708,18 @@ int geometry(const mc_ch_grid *g, Geo *G)
     if (!make_plan(g->nx, &G->px) || !make_plan(g->ny, &G->py) || !make_plan(g->nz, &G->pz))
         return fail(MC_EINVAL, "every extent must be a product of powers of 2 and 3");
     G->spec_elems = (size_t)G->nz * G->ny * G->hx;
-    G->Lx = 2 * std::max(1, kLdsElems / G->nx);   // two real lines per complex transform
+    // two real lines per complex transform
+    G->Lx = 2 * std::max(1, (static_length(G->nx) ? kXElems : kLdsElems) / G->nx);
     // column tiles: padded lines must fit the LDS buffer and the stage registers
-    auto tile = [](int n) {
-        const int lds = static_length(n) ? kPadElems : kColElems;
-        return std::max(1, std::min(lds / line_stride(n, true), kLdsElems / n));
+    auto tile = [](int n, int lds_static, int elems_static) {
+        const int lds = static_length(n) ? lds_static : kColElems;
+        const int elems = static_length(n) ? elems_static : kLdsElems;
+        return std::max(1, std::min(lds / line_stride(n, true), elems / n));
     };
-    G->Ty = tile(G->ny);
-    G->Tz = tile(G->nz);
+    G->Ty = tile(G->ny, kPadElems, kLdsElems);
+    // the full tile for z too: half-size z tiles (three workgroups per CU, 80-byte
+    // column runs) measured slower, 3602 against 3468 us at 384 x 1024 x 1024
+    G->Tz = tile(G->nz, kPadElems, kLdsElems);
     G->tiles_y = (G->hx + G->Ty - 1) / G->Ty;
     G->tiles_z = (G->hx + G->Tz - 1) / G->Tz;
     size_t off = 0;
