@@ -259,6 +259,34 @@ def test_bitwise_reproducible_and_tune_invariant(mask_m1):
         assert torch.equal(r.fluence, F0) and torch.equal(r.scalars, S0), t
 
 
+def test_large_per_voxel_deposits_bypass_the_log():
+    """A dense, non-absorbing solid (mu_s = 20 per voxel, g = 0) makes a photon cross
+    several voxel lengths inside one voxel at nearly full weight, so its summed deposit
+    there reaches 2^32 and goes to the tally directly instead of through the 32-bit log;
+    the tallies must still equal one atomic per visit bit for bit, and such sums must
+    occur (some voxel receives a single deposit of 2^32 or more)."""
+    banner("deposits of 2^32 or more: logged run == direct run")
+    m = dev(inputs.homogeneous_mask(12, 10, 6))
+    opt = pm.Optics(f32(20.0), 0.0, 0.0)
+    n = 3000
+    logged = pm.run(m, opt, n, SEED)
+    direct = pm.run(m, opt, n, SEED, direct=True)
+    assert torch.equal(logged.fluence, direct.fluence) and torch.equal(logged.scalars, direct.scalars)
+    # traced photons show visits whose summed deposit w * d reaches 2^32
+    recs, _ = pm.trace(m, opt, list(range(20)), 64, SEED)
+    best = 0.0
+    for ph in recs:
+        run, cur = 0.0, None
+        for rec in ph:
+            if rec["event"] < 0:
+                continue
+            v = (int(rec["ix"]), int(rec["iy"]), int(rec["iz"]))
+            run = run + float(rec["w"]) * float(rec["d"]) if v == cur else float(rec["w"]) * float(rec["d"])
+            cur = v
+            best = max(best, run)
+    assert best >= 2.0 ** 32, best
+
+
 def test_resume_split_equals_whole(mask_m1):
     banner("split run == whole run")
     d = dev(mask_m1)
