@@ -68,7 +68,8 @@ int mc_pore_distance(const mc_volume *vol, double *dist, void *workspace, size_t
  *   rho          device double[nz - z0] (written)
  *   n_pore       device int64[nz - z0]: pore voxels per slice (written)
  * Needs nx * ny * (nz - z0) < 2^31.  Unlike the other calls this one synchronises
- * the stream once: the number of pore voxels sizes the sorts.  The workspace query
+ * the stream once: the number of pore voxels sizes the sorts, and the largest
+ * fluence and squared distance fix their bit ranges.  The workspace query
  * asks the HIP runtime for the current device's sort configuration and returns 0
  * (with mc_last_error) for invalid arguments or when no device answers; the
  * workspace it sizes is for the current device. */

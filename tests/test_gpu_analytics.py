@@ -147,7 +147,9 @@ def test_bright_colocalization(mask_m1):
             assert np.array_equal(k.cpu().numpy(), kw) and np.array_equal(s.cpu().numpy(), sw), (lo, z0, frac)
 
 
-@pytest.mark.parametrize("shape", [(32, 32, 32), (17, 30, 20), (9, 1, 33), (40, 5, 1)])
+# (2100, 2, 8) and (2, 2100, 8): lines too long for an LDS tile of 8 columns, scanned
+# from global memory; the others use the LDS tiles (of 1 to 32 columns)
+@pytest.mark.parametrize("shape", [(32, 32, 32), (17, 30, 20), (9, 1, 33), (40, 5, 1), (2100, 2, 8), (2, 2100, 8)])
 def test_pore_distance(shape, mask_m1):
     banner(f"pore distance transform vs scipy, shape {shape}")
     nz, ny, nx = shape
@@ -238,6 +240,40 @@ def test_pore_spearman_fullsize():
     assert np.all(np.abs(r[ok] - rw[ok]) <= 1e-12)
     print(f"256^3 phi 0.70, z >= {z0}: rho = {np.nanmean(rw):+.4f} +- {np.nanstd(rw, ddof=1):.4f} "
           f"over {ok.sum()} slices")
+
+
+def test_pore_spearman_key_ranges():
+    banner("pore Spearman: composite-key bit ranges, the per-slice fallback, ties across slices")
+    rng = np.random.default_rng(11)
+    m = (rng.random((5, 16, 20)) < 0.6).astype(np.uint8)
+    d = dev(m)
+    tied = np.broadcast_to(rng.integers(0, 3, size=(1, 16, 20)), m.shape)   # the same values on every slice
+    cases = [
+        ("62-bit tallies on 5 slices (65 bits: per-slice sort)", rng.integers(2 ** 61, 2 ** 62, size=m.shape), 0),
+        ("62-bit tallies on 4 slices (exactly 64 composite bits)", rng.integers(2 ** 61, 2 ** 62, size=m.shape), 1),
+        ("63-bit tallies on one slice", rng.integers(2 ** 62, 2 ** 63 - 1, size=m.shape), 4),
+        ("negative tallies (per-slice sort)", rng.integers(-2 ** 40, 2 ** 40, size=m.shape), 0),
+        ("equal values on every slice", tied, 0),
+        ("all zero", np.zeros(m.shape), 0),
+    ]
+    for name, F, z0 in cases:
+        F = np.ascontiguousarray(F, dtype=np.int64)
+        rho, n = an.pore_spearman(d, dev(F), z0)
+        rw, nw = oan.pore_spearman(F, m, z0)
+        assert np.array_equal(n.cpu().numpy(), nw), name
+        r = rho.cpu().numpy()
+        assert np.array_equal(np.isnan(r), np.isnan(rw)), (name, r, rw)
+        ok = ~np.isnan(rw)
+        assert np.all(np.abs(r[ok] - rw[ok]) <= 1e-12), name
+    # pore distances beyond the counting ranks' bins (squared distances up to ~1.8e5):
+    # distances ranked by the device-wide sort
+    m2 = np.ones((2, 300, 300), dtype=np.uint8)
+    m2[0, 0, 0] = 0
+    F = rng.integers(0, 2 ** 40, size=m2.shape).astype(np.int64)
+    rho, n = an.pore_spearman(dev(m2), dev(F), 0)
+    rw, nw = oan.pore_spearman(F, m2, 0)
+    assert np.array_equal(n.cpu().numpy(), nw)
+    assert np.all(np.abs(rho.cpu().numpy() - rw) <= 1e-12), (rho, rw)
 
 
 @pytest.mark.parametrize("shape", [(6, 4, 24), (12, 18, 24), (32, 32, 32), (1, 9, 12)])
