@@ -105,32 +105,48 @@ __global__ void k_chords_global(const uint8_t *__restrict__ mask, int axis, int 
     }
 }
 
-// one thread: fixed order, exact sample variance by two passes
-__global__ void k_contrast(const double *__restrict__ depth, int nz, int z0, double *out)
+// one wavefront, sample variance by two passes: lane l takes the depths z0 + l,
+// z0 + l + 64, ...; the sums are reduced to lane 0 in a fixed order and the means
+// broadcast for the second pass
+__device__ __forceinline__ double wave_sum_to_all(double v)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double ss = 0.0, sp = 0.0;
-    int ns = 0, np = 0, nd = 0;
-    for (int z = z0; z < nz; ++z) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    return __shfl(v, 0);
+}
+
+__global__ __launch_bounds__(64) void k_contrast(const double *__restrict__ depth, int nz, int z0, double *out)
+{
+    const int lane = (int)threadIdx.x;
+    double ss = 0.0, sp = 0.0, ns = 0.0, np = 0.0, nd = 0.0;   // counts are exact in double
+    for (int z = z0 + lane; z < nz; z += 64) {
         const double t = depth[z], s = depth[nz + z], p = depth[2 * nz + z];
         if (!(t > 0.0)) continue;
-        ++nd;
-        if (isfinite(s)) { ss += s / t; ++ns; }
-        if (isfinite(p)) { sp += p / t; ++np; }
+        nd += 1.0;
+        if (isfinite(s)) { ss += s / t; ns += 1.0; }
+        if (isfinite(p)) { sp += p / t; np += 1.0; }
     }
-    const double ms = ns ? ss / ns : NAN, mp = np ? sp / np : NAN;
+    ss = wave_sum_to_all(ss);
+    sp = wave_sum_to_all(sp);
+    ns = wave_sum_to_all(ns);
+    np = wave_sum_to_all(np);
+    nd = wave_sum_to_all(nd);
+    const double ms = ns > 0.0 ? ss / ns : NAN, mp = np > 0.0 ? sp / np : NAN;
     double vs = 0.0, vp = 0.0;
-    for (int z = z0; z < nz; ++z) {
+    for (int z = z0 + lane; z < nz; z += 64) {
         const double t = depth[z], s = depth[nz + z], p = depth[2 * nz + z];
         if (!(t > 0.0)) continue;
         if (isfinite(s)) vs += (s / t - ms) * (s / t - ms);
         if (isfinite(p)) vp += (p / t - mp) * (p / t - mp);
     }
-    out[0] = ms;
-    out[1] = ns > 1 ? sqrt(vs / (ns - 1)) : 0.0;
-    out[2] = mp;
-    out[3] = np > 1 ? sqrt(vp / (np - 1)) : 0.0;
-    out[4] = (double)nd;
+    vs = wave_sum_to_all(vs);
+    vp = wave_sum_to_all(vp);
+    if (lane == 0) {
+        out[0] = ms;
+        out[1] = ns > 1.0 ? sqrt(vs / (ns - 1.0)) : 0.0;
+        out[2] = mp;
+        out[3] = np > 1.0 ? sqrt(vp / (np - 1.0)) : 0.0;
+        out[4] = nd;
+    }
 }
 
 struct Thresholds {

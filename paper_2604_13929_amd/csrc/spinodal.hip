@@ -666,13 +666,22 @@ __global__ __launch_bounds__(kThreads) void k_psd_partial(const double2 *__restr
     for (int i = (int)threadIdx.x; i < nb; i += kThreads) partial[(size_t)blockIdx.x * nb + i] = bins[i];
 }
 
-__global__ void k_psd_sum(const double *__restrict__ partial, int nblocks, int nb, double *psd)
+// one workgroup per shell: the partial sums of the shell, tree-reduced in LDS in a
+// fixed order
+__global__ __launch_bounds__(kThreads) void k_psd_sum(const double *__restrict__ partial, int nblocks, int nb,
+                                                      double *psd)
 {
-    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (s >= nb) return;
+    __shared__ double red[kThreads];
+    const int s = (int)blockIdx.x;
     double acc = 0.0;
-    for (int b = 0; b < nblocks; ++b) acc += partial[(size_t)b * nb + s];
-    psd[s] = acc;
+    for (int b = (int)threadIdx.x; b < nblocks; b += kThreads) acc += partial[(size_t)b * nb + s];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) psd[s] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -946,7 +955,7 @@ int mc_ch_psd(const mc_ch_grid *g, const double *state, double *psd, void *works
     const int nb = std::max(G.nx, std::max(G.ny, G.nz)) / 2 + 1;
     hipLaunchKernelGGL(k_psd_partial, dim3(kPsdBlocks), dim3(kThreads), 0, s, (const double2 *)state, G.nx, G.ny, G.nz,
                        P.kx2, P.ky2, P.kz2, P.psd_partial, nb);
-    hipLaunchKernelGGL(k_psd_sum, dim3((nb + 255) / 256), dim3(256), 0, s, P.psd_partial, kPsdBlocks, nb, psd);
+    hipLaunchKernelGGL(k_psd_sum, dim3(nb), dim3(kThreads), 0, s, P.psd_partial, kPsdBlocks, nb, psd);
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }
@@ -991,7 +1000,7 @@ int mc_mask_psd(const mc_volume *vol, double *psd, void *workspace, size_t works
     const int nb = std::max(G.nx, std::max(G.ny, G.nz)) / 2 + 1;
     hipLaunchKernelGGL(k_psd_partial, dim3(kPsdBlocks), dim3(kThreads), 0, s, (const double2 *)P.W, G.nx, G.ny, G.nz,
                        P.kx2, P.ky2, P.kz2, P.psd_partial, nb);
-    hipLaunchKernelGGL(k_psd_sum, dim3((nb + 255) / 256), dim3(256), 0, s, P.psd_partial, kPsdBlocks, nb, psd);
+    hipLaunchKernelGGL(k_psd_sum, dim3(nb), dim3(kThreads), 0, s, P.psd_partial, kPsdBlocks, nb, psd);
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }
