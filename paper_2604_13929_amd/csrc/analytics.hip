@@ -225,14 +225,18 @@ __global__ __launch_bounds__(kThreads) void k_escape_hist(const mc_photon_rec *_
 }
 
 // Brightest fraction of one slice per workgroup: an MSB-first radix select over
-// the order-preserving key of the int64 tally (11-bit digits, six passes over the
-// slice, histograms in LDS) finds the k-th largest key T and how many keys equal to
-// T are taken; a pass in index order then takes every key above T and the first
-// `need` keys equal to T (ties to the lower index) and counts the solid voxels
-// among them.
+// the order-preserving key of the int64 tally finds the k-th largest key T and how
+// many keys equal to T are taken; a pass in index order then takes every key above
+// T and the first `need` keys equal to T (ties to the lower index) and counts the
+// solid voxels among them.  A first pass over the slice finds the bits all its keys
+// share (their minimum and maximum), so the 11-bit digits start at the highest bit
+// that differs.  A digit pass reads the slice while more than kTopCand keys are
+// still in the running; once they fit, one pass copies them to LDS and the
+// remaining digits are resolved there.
 constexpr int kTopThreads = 1024;
 constexpr int kTopBits = 11;
 constexpr int kTopBins = 1 << kTopBits;
+constexpr int kTopCand = 6144;   // 48 KB of LDS
 
 __device__ __forceinline__ unsigned long long tally_key(long long v) { return (unsigned long long)v ^ 0x8000000000000000ull; }
 
@@ -258,40 +262,69 @@ __global__ __launch_bounds__(kTopThreads) void k_slice_top(const long long *__re
 {
     __shared__ unsigned int h[kTopBins];
     __shared__ unsigned int wsum[kTopThreads / 64];
-    __shared__ unsigned long long s_prefix;
+    __shared__ unsigned long long cand[kTopCand];
+    __shared__ unsigned long long s_prefix, s_min, s_max;
     __shared__ long long s_k;
+    __shared__ unsigned int s_count, s_ncand;
     const size_t base = (size_t)(z0 + blockIdx.x) * (size_t)n;
     const long long *f = F + base;
     const uint8_t *m = mask + base;
     const int t = (int)threadIdx.x, lane = t & 63, wave = t >> 6;
     if (t == 0) {
-        s_prefix = 0ull;
-        s_k = k;
+        s_min = ~0ull;
+        s_max = 0ull;
+        s_ncand = 0u;
     }
-    // digits from the top: bits 63..53, 52..42, 41..31, 30..20, 19..9, 8..0
-    for (int shift = 64 - kTopBits; shift > -kTopBits; shift -= kTopBits) {
-        const int sh = shift > 0 ? shift : 0;
-        const int bits = shift >= 0 ? kTopBits : kTopBits + shift;
-        const int nb = 1 << bits;
-        for (int i = t; i < kTopBins; i += kTopThreads) h[i] = 0u;
-        __syncthreads();
-        const unsigned long long prefix = s_prefix;
-        const long long kk = s_k;
-        const int top = sh + bits;
+    __syncthreads();
+    {
+        unsigned long long lo = ~0ull, hi = 0ull;
+        for (long long i = t; i < n; i += kTopThreads) {
+            const unsigned long long key = tally_key(f[i]);
+            lo = min(lo, key);
+            hi = max(hi, key);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, (unsigned long long)__shfl_xor(lo, o));
+            hi = max(hi, (unsigned long long)__shfl_xor(hi, o));
+        }
+        if (lane == 0) {
+            atomicMin(&s_min, lo);
+            atomicMax(&s_max, hi);
+        }
+    }
+    __syncthreads();
+    const unsigned long long diff = s_min ^ s_max;
+    // bits at and above `top` are resolved: they equal those of `prefix`
+    int top = diff ? 64 - __clzll((long long)diff) : 0;
+    unsigned long long prefix = top >= 64 ? 0ull : (s_min & (~0ull << top));
+    long long kk = k;
+    bool in_lds = false;
+    while (top > 0) {
+        const int bits = min(kTopBits, top), sh = top - bits, nb = 1 << bits;
         const unsigned long long hi_mask = top >= 64 ? 0ull : (~0ull << top);
-        for (long long i0 = 0; i0 < n; i0 += kTopThreads) {
-            const long long i = i0 + t;
-            int d = -1;
-            if (i < n) {
-                const unsigned long long key = tally_key(f[i]);
-                if ((key & hi_mask) == prefix) d = (int)((key >> sh) & (unsigned long long)(nb - 1));
+        for (int i = t; i < nb; i += kTopThreads) h[i] = 0u;
+        __syncthreads();
+        if (in_lds) {
+            const int nc = (int)s_ncand;
+            for (int j = t; j < nc; j += kTopThreads) {
+                const unsigned long long key = cand[j];
+                if ((key & hi_mask) == prefix) atomicAdd(&h[(key >> sh) & (unsigned long long)(nb - 1)], 1u);
             }
-            // a wave whose candidates share one digit adds them with one atomic
-            const int d0 = __shfl(d, 0);
-            if (__ballot(d == d0) == ~0ull) {
-                if (lane == 0 && d0 >= 0) atomicAdd(&h[d0], 64u);
-            } else if (d >= 0) {
-                atomicAdd(&h[d], 1u);
+        } else {
+            for (long long i0 = 0; i0 < n; i0 += kTopThreads) {
+                const long long i = i0 + t;
+                int d = -1;
+                if (i < n) {
+                    const unsigned long long key = tally_key(f[i]);
+                    if ((key & hi_mask) == prefix) d = (int)((key >> sh) & (unsigned long long)(nb - 1));
+                }
+                // a wave whose candidates share one digit adds them with one atomic
+                const int d0 = __shfl(d, 0);
+                if (__ballot(d == d0) == ~0ull) {
+                    if (lane == 0 && d0 >= 0) atomicAdd(&h[d0], 64u);
+                } else if (d >= 0) {
+                    atomicAdd(&h[d], 1u);
+                }
             }
         }
         __syncthreads();
@@ -305,11 +338,37 @@ __global__ __launch_bounds__(kTopThreads) void k_slice_top(const long long *__re
             const int d = in_hi ? dhi : dlo;
             s_prefix = prefix | ((unsigned long long)d << sh);
             s_k = kk - (long long)(in_hi ? excl : excl + chi);
+            s_count = in_hi ? chi : clo;
         }
         __syncthreads();
+        prefix = s_prefix;
+        kk = s_k;
+        top = sh;
+        if (!in_lds && top > 0 && s_count <= (unsigned int)kTopCand) {
+            // the keys still in the running fit in LDS: copy them there (any order)
+            const unsigned long long keep = ~0ull << top;
+            for (long long i0 = 0; i0 < n; i0 += kTopThreads) {
+                const long long i = i0 + t;
+                unsigned long long key = 0ull;
+                bool match = false;
+                if (i < n) {
+                    key = tally_key(f[i]);
+                    match = (key & keep) == prefix;
+                }
+                const unsigned long long bal = __ballot(match);
+                if (bal) {
+                    unsigned int at = 0u;
+                    if (lane == 0) at = atomicAdd(&s_ncand, (unsigned int)__popcll(bal));
+                    at = __shfl(at, 0);
+                    if (match) cand[at + __popcll(bal & ((1ull << lane) - 1ull))] = key;
+                }
+            }
+            in_lds = true;
+            __syncthreads();
+        }
     }
-    const unsigned long long T = s_prefix;
-    const long long need = s_k;
+    const unsigned long long T = prefix;
+    const long long need = kk;
     long long run = 0;
     unsigned int solid = 0;
     for (long long i0 = 0; i0 < n; i0 += kTopThreads) {
@@ -587,59 +646,79 @@ unsigned blocks_for(long long n) { return (unsigned)std::max<long long>(1, std::
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Pore-phase Spearman correlation (one workgroup per slice where noted).
-// Compaction of the pore voxels of slice z0 + s in index order: keys of fluence
-// and squared distance, segment offsets from a scan of the per-slice counts.
+// Pore-phase Spearman correlation.  Compaction of the pore voxels of slice z0 + s in
+// index order (keys of fluence and squared distance), in chunks of kSpChunk voxels
+// of one slice, one workgroup each; the chunks' offsets come from a scan of their
+// pore counts.  Each chunk also records the largest fluence (as unsigned: a negative
+// tally reads as 2^63 or more) and squared distance among its pore voxels, in
+// cmax[2c] and cmax[2c + 1], and k_chunk_max reduces them into stats[1] and stats[2].
 constexpr int kSpThreads = 1024;
+constexpr int kSpChunk = 8192;
 constexpr int kRankBins = 16128;   // counting ranks: prefix array of up to this many ints (63 KB of LDS)
 
-__global__ __launch_bounds__(kSpThreads) void k_slice_pore_count(const uint8_t *__restrict__ mask, long long n_slice,
-                                                                 int z0, long long *counts)
+// pore voxels of chunk c = s * cps + j: voxels [j kSpChunk, (j + 1) kSpChunk) of slice z0 + s
+__global__ __launch_bounds__(kSpThreads) void k_chunk_pore_count(const uint8_t *__restrict__ mask, long long n_slice,
+                                                                 int z0, int cps, int *counts)
 {
-    const uint8_t *m = mask + (size_t)(z0 + blockIdx.x) * n_slice;
-    long long c = 0;
-    for (long long i = threadIdx.x; i < n_slice; i += kSpThreads) c += m[i] ? 1 : 0;
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    __shared__ long long w[kSpThreads / 64];
-    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = c;
+    const int c = (int)blockIdx.x, sl = c / cps, j = c - sl * cps;
+    const long long lo = (long long)j * kSpChunk, hi = std::min(n_slice, lo + kSpChunk);
+    const uint8_t *m = mask + (size_t)(z0 + sl) * n_slice;
+    int cnt = 0;
+    for (long long i = lo + threadIdx.x; i < hi; i += kSpThreads) cnt += m[i] ? 1 : 0;
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    __shared__ int w[kSpThreads / 64];
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
-        long long sum = 0;
+        int sum = 0;
         for (int i = 0; i < kSpThreads / 64; ++i) sum += w[i];
-        counts[blockIdx.x] = sum;
+        counts[c] = sum;
     }
 }
 
-// stats[0] = the number of pore voxels over all slices; stats[1] and stats[2] are
-// cleared here and then take the largest fluence (as unsigned: a negative tally
-// reads as 2^63 or more) and the largest squared distance among them
-__global__ void k_offsets(const long long *counts, int nseg, int *begin, int *end, unsigned long long *stats)
+// One workgroup: exclusive scan of the chunk counts into coff (where each chunk's
+// pore voxels start), begin / end of every slice, and stats[0] = the number of pore
+// voxels over all slices (below 2^31).
+__global__ __launch_bounds__(kSpThreads) void k_offsets(const int *__restrict__ counts, int nchunks, int cps, int *coff,
+                                                        int *begin, int *end, unsigned long long *stats)
 {
-    if (threadIdx.x != 0) return;
-    long long run = 0;
-    for (int i = 0; i < nseg; ++i) {
-        begin[i] = (int)run;
-        run += counts[i];
-        end[i] = (int)run;
+    __shared__ unsigned int wsum[kSpThreads / 64];
+    __shared__ unsigned int s_carry;
+    if (threadIdx.x == 0) s_carry = 0u;
+    __syncthreads();
+    for (int c0 = 0; c0 < nchunks; c0 += kSpThreads) {
+        const int c = c0 + (int)threadIdx.x;
+        const unsigned int v = c < nchunks ? (unsigned int)counts[c] : 0u;
+        const unsigned int carry = s_carry;
+        const unsigned int incl = carry + block_inclusive_scan(v, wsum);
+        if (c < nchunks) {
+            coff[c] = (int)(incl - v);
+            if (c % cps == 0) begin[c / cps] = (int)(incl - v);
+            if (c % cps == cps - 1) end[c / cps] = (int)incl;
+        }
+        __syncthreads();
+        if (threadIdx.x == kSpThreads - 1) s_carry = incl;
+        __syncthreads();
     }
-    stats[0] = (unsigned long long)run;
-    stats[1] = 0ull;
-    stats[2] = 0ull;
+    if (threadIdx.x == 0) stats[0] = (unsigned long long)s_carry;
 }
 
 __global__ __launch_bounds__(kSpThreads) void k_compact(const uint8_t *__restrict__ mask, const long long *__restrict__ F,
-                                                 const int *__restrict__ g, long long n_slice, int z0,
-                                                 const int *__restrict__ begin, long long *kf, int *kd, int *pos,
-                                                 unsigned long long *stats)
+                                                        const int *__restrict__ g, long long n_slice, int z0, int cps,
+                                                        const int *__restrict__ coff, long long *kf, int *kd, int *pos,
+                                                        unsigned long long *cmax)
 {
     __shared__ int wcount[kSpThreads / 64];
-    const size_t base = (size_t)(z0 + blockIdx.x) * n_slice;
-    int run = begin[blockIdx.x];
+    __shared__ unsigned long long wmax[2][kSpThreads / 64];
+    const int c = (int)blockIdx.x, sl = c / cps, j = c - sl * cps;
+    const long long lo = (long long)j * kSpChunk, hi = std::min(n_slice, lo + kSpChunk);
+    const size_t base = (size_t)(z0 + sl) * n_slice;
+    int run = coff[c];
     const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
     unsigned long long fmax = 0ull, dmax = 0ull;
-    for (long long i0 = 0; i0 < n_slice; i0 += kSpThreads) {
+    for (long long i0 = lo; i0 < hi; i0 += kSpThreads) {
         const long long i = i0 + threadIdx.x;
-        const bool p = i < n_slice && mask[base + i] != 0;
+        const bool p = i < hi && mask[base + i] != 0;
         const unsigned long long bal = __ballot(p);
         if (lane == 0) wcount[wave] = __popcll(bal);
         __syncthreads();
@@ -666,8 +745,41 @@ __global__ __launch_bounds__(kSpThreads) void k_compact(const uint8_t *__restric
         dmax = max(dmax, (unsigned long long)__shfl_xor(dmax, o));
     }
     if (lane == 0) {
-        atomicMax(&stats[1], fmax);
-        atomicMax(&stats[2], dmax);
+        wmax[0][wave] = fmax;
+        wmax[1][wave] = dmax;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long v = 0ull;
+        for (int w = 0; w < kSpThreads / 64; ++w) v = max(v, wmax[threadIdx.x][w]);
+        cmax[2 * c + threadIdx.x] = v;
+    }
+}
+
+// stats[1], stats[2] = the largest of the chunks' maxima (one workgroup)
+__global__ __launch_bounds__(kSpThreads) void k_chunk_max(const unsigned long long *__restrict__ cmax, int nchunks,
+                                                          unsigned long long *stats)
+{
+    __shared__ unsigned long long wmax[2][kSpThreads / 64];
+    unsigned long long f = 0ull, d = 0ull;
+    for (int c = (int)threadIdx.x; c < nchunks; c += kSpThreads) {
+        f = max(f, cmax[2 * c]);
+        d = max(d, cmax[2 * c + 1]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        f = max(f, (unsigned long long)__shfl_xor(f, o));
+        d = max(d, (unsigned long long)__shfl_xor(d, o));
+    }
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    if (lane == 0) {
+        wmax[0][wave] = f;
+        wmax[1][wave] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long v = 0ull;
+        for (int w = 0; w < kSpThreads / 64; ++w) v = max(v, wmax[threadIdx.x][w]);
+        stats[1 + threadIdx.x] = v;
     }
 }
 
@@ -881,9 +993,14 @@ bool too_large(const mc_volume *vol)
     return (long long)vol->nx * vol->nx + (long long)vol->ny * vol->ny + (long long)vol->nz * vol->nz >= kInf;
 }
 
+int sp_chunks_per_slice(const mc_volume *vol)
+{
+    return (int)(((long long)vol->nx * vol->ny + kSpChunk - 1) / kSpChunk);
+}
+
 // Spearman workspace layout after the distance transform's
 struct SpLayout {
-    size_t edt, counts, begin, end, stats, kf, kd, pos, kc, kc_s, perm, rf, rd, tmp, total;
+    size_t edt, counts, coff, cmax, begin, end, stats, kf, kd, pos, kc, kc_s, perm, rf, rd, tmp, total;
     size_t tmp_bytes;
     hipError_t status;   // of rocPRIM's storage queries (they ask the runtime for the device)
 };
@@ -895,7 +1012,10 @@ SpLayout sp_layout(const mc_volume *vol, int z0, long long npore_max, hipStream_
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t at = off; off += align256(bytes); return at; };
     L.edt = take(edt_bytes(vol));
-    L.counts = take(sizeof(long long) * nseg);
+    const long long nchunks = (long long)nseg * sp_chunks_per_slice(vol);
+    L.counts = take(sizeof(int) * nchunks);
+    L.coff = take(sizeof(int) * nchunks);
+    L.cmax = take(sizeof(unsigned long long) * 2 * nchunks);
     L.begin = take(sizeof(int) * nseg);
     L.end = take(sizeof(int) * nseg);
     L.stats = take(sizeof(unsigned long long) * 3);
@@ -1080,17 +1200,22 @@ int mc_pore_spearman(const mc_volume *vol, const int64_t *fluence, int32_t z0, d
     const EdtScratch e = edt_layout(vol, b + L.edt);
     if ((rc = enqueue_sqdist(vol, e, s))) return rc;
     const int nseg = vol->nz - z0;
-    long long *counts = (long long *)(b + L.counts);
+    int *counts = (int *)(b + L.counts), *coff = (int *)(b + L.coff);
+    unsigned long long *cmax = (unsigned long long *)(b + L.cmax);
     int *begin = (int *)(b + L.begin), *end = (int *)(b + L.end);
     unsigned long long *stats = (unsigned long long *)(b + L.stats);
     long long *kf = (long long *)(b + L.kf);
     int *kd = (int *)(b + L.kd), *pos = (int *)(b + L.pos), *perm = (int *)(b + L.perm);
     unsigned long long *kc = (unsigned long long *)(b + L.kc), *kc_s = (unsigned long long *)(b + L.kc_s);
     double *rf = (double *)(b + L.rf), *rd = (double *)(b + L.rd);
-    hipLaunchKernelGGL(k_slice_pore_count, dim3(nseg), dim3(kSpThreads), 0, s, vol->mask, n_slice, z0, counts);
-    hipLaunchKernelGGL(k_offsets, dim3(1), dim3(64), 0, s, counts, nseg, begin, end, stats);
-    hipLaunchKernelGGL(k_compact, dim3(nseg), dim3(kSpThreads), 0, s, vol->mask, (const long long *)fluence, e.g, n_slice, z0,
-                       begin, kf, kd, pos, stats);
+    const int cps = sp_chunks_per_slice(vol);
+    const int nchunks = nseg * cps;
+    hipLaunchKernelGGL(k_chunk_pore_count, dim3(nchunks), dim3(kSpThreads), 0, s, vol->mask, n_slice, z0, cps, counts);
+    hipLaunchKernelGGL(k_offsets, dim3(1), dim3(kSpThreads), 0, s, (const int *)counts, nchunks, cps, coff, begin, end,
+                       stats);
+    hipLaunchKernelGGL(k_compact, dim3(nchunks), dim3(kSpThreads), 0, s, vol->mask, (const long long *)fluence, e.g,
+                       n_slice, z0, cps, (const int *)coff, kf, kd, pos, cmax);
+    hipLaunchKernelGGL(k_chunk_max, dim3(1), dim3(kSpThreads), 0, s, (const unsigned long long *)cmax, nchunks, stats);
     HIP_TRY(hipGetLastError());
     // the pore count sizes the sorts and the key maxima fix their bit ranges: bring
     // those three numbers to the host

@@ -145,6 +145,16 @@ def test_bright_colocalization(mask_m1):
             k, s = an.bright_colocalization(dev(m), dev(Fr), z0, frac)
             kw, sw = oan.bright_colocalization(Fr, m, z0, frac)
             assert np.array_equal(k.cpu().numpy(), kw) and np.array_equal(s.cpu().numpy(), sw), (lo, z0, frac)
+    # 65 536-voxel slices whose k-th key sits among tens of thousands of keys that share
+    # every digit but the last (values 0 and 1 under a few at 2^40): the select keeps
+    # reading the slice digit by digit instead of moving the candidates to LDS
+    m = (rng.random((3, 256, 256)) < 0.6).astype(np.uint8)
+    Fr = rng.integers(0, 2, size=m.shape, dtype=np.int64)
+    Fr[:, :5, :] += 2 ** 40 + rng.integers(0, 2 ** 20, size=(3, 5, 256))
+    for frac in (0.1, 0.5, 0.99):
+        k, s = an.bright_colocalization(dev(m), dev(Fr), 0, frac)
+        kw, sw = oan.bright_colocalization(Fr, m, 0, frac)
+        assert np.array_equal(k.cpu().numpy(), kw) and np.array_equal(s.cpu().numpy(), sw), frac
 
 
 # (2100, 2, 8) and (2, 2100, 8): lines too long for an LDS tile of 8 columns, scanned
