@@ -903,9 +903,10 @@ int mc_ch_steps(const mc_ch_grid *g, int32_t n_steps, double *state, void *works
     hipStream_t s = (hipStream_t)hip_stream;
     Geo G;
     Ptrs P;
-    int rc = prepare(g, workspace, workspace_bytes, s, &G, &P);
+    int rc = geometry(g, &G);
     if (rc) return rc;
     if (G.nz == 1) return fail(MC_EINVAL, "mc_ch_steps needs nz >= 2 (the step is fused with the z transform)");
+    if ((rc = prepare(g, workspace, workspace_bytes, s, &G, &P))) return rc;
     double2 *S = (double2 *)state;
     const bool timed = (flags & MC_TIMED) != 0;
     if (timed && (rc = ch_time(s, true))) return rc;

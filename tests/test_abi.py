@@ -142,3 +142,90 @@ def test_grad_rejects_deep_volume(lib):
                      None, None)
     assert rc == -1 and b"nz" in lib.mc_last_error()
     assert lib.mc_grad_workspace_bytes(ctypes.byref(vol)) > 0
+
+
+def _grid(nx=8, ny=6, nz=4, reserved=0, kappa=0.114, dt=0.045):
+    return pm.McChGrid(nx, ny, nz, reserved, kappa, dt)
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(nx=7), b"even"), (dict(nx=0), b"even"), (dict(nx=2048), b"even"), (dict(ny=0), b"ny, nz"),
+    (dict(nz=1025), b"ny, nz"), (dict(nx=10), b"powers of 2 and 3"), (dict(nz=5), b"powers of 2 and 3"),
+    (dict(reserved=1), b"reserved"), (dict(kappa=0.0), b"kappa"), (dict(dt=float("nan")), b"kappa"),
+    (dict(dt=float("inf")), b"kappa"),
+])
+def test_ch_grid_validation(lib, kw, needle):
+    """The Cahn-Hilliard grid is checked before any workspace is sized or any kernel queued."""
+    g = _grid(**kw)
+    assert lib.mc_ch_workspace_bytes(ctypes.byref(g)) == 0
+    assert needle in lib.mc_last_error()
+    assert lib.mc_ch_generate_workspace_bytes(ctypes.byref(g)) == 0
+    assert lib.mc_ch_steps(ctypes.byref(g), 1, 1, None, 0, 0, None) == -1
+    assert needle in lib.mc_last_error()
+
+
+def test_ch_entry_points_reject_bad_arguments(lib):
+    g = _grid()
+    assert lib.mc_ch_workspace_bytes(ctypes.byref(g)) > 0
+    assert lib.mc_ch_steps(ctypes.byref(g), -1, 1, None, 0, 0, None) == -1 and b"n_steps" in lib.mc_last_error()
+    assert lib.mc_ch_steps(ctypes.byref(g), 1, None, None, 0, 0, None) == -1 and b"state" in lib.mc_last_error()
+    # the step is fused with the z transform: a flat grid is refused before any device work
+    flat = _grid(nz=1)
+    assert lib.mc_ch_workspace_bytes(ctypes.byref(flat)) > 0
+    assert lib.mc_ch_steps(ctypes.byref(flat), 1, 1, None, 0, 0, None) == -1 and b"nz >= 2" in lib.mc_last_error()
+    assert lib.mc_ch_init(ctypes.byref(g), None, 1, None, 0, None) == -1 and b"NULL" in lib.mc_last_error()
+    assert lib.mc_ch_field(ctypes.byref(g), 1, None, None, 0, None) == -1
+    assert lib.mc_ch_psd(ctypes.byref(g), 1, None, None, 0, None) == -1
+    gen = lambda **k: lib.mc_ch_generate(  # noqa: E731
+        ctypes.byref(g), 1, k.get("d", 8.0), k.get("sigma", 0.1), k.get("every", 10), k.get("max", 100),
+        k.get("phi", 0.7), 1, None, None, None, None, 1, 0, None)
+    assert gen(every=0) == -1 and b"check_every" in lib.mc_last_error()
+    assert gen(max=-1) == -1 and b"max_steps" in lib.mc_last_error()
+    assert gen(phi=1.5) == -1 and b"porosity" in lib.mc_last_error()
+    assert gen(d=0.0) == -1 and b"d_target" in lib.mc_last_error()
+    assert gen(sigma=-1.0) == -1 and b"sigma" in lib.mc_last_error()
+    assert gen() == -4 and b"workspace" in lib.mc_last_error()
+    # rank binarisation
+    assert lib.mc_rank_threshold_workspace_bytes(0) == 0
+    assert lib.mc_rank_threshold_workspace_bytes(1 << 40) == 0
+    assert lib.mc_rank_threshold_workspace_bytes(1000) > 0
+    assert lib.mc_rank_threshold(1, 0, 0, 1, 1, 1 << 20, None) == -1 and b"n must" in lib.mc_last_error()
+    assert lib.mc_rank_threshold(1, 10, 11, 1, 1, 1 << 20, None) == -1 and b"n_pore" in lib.mc_last_error()
+    assert lib.mc_rank_threshold(1, 10, -1, 1, 1, 1 << 20, None) == -1 and b"n_pore" in lib.mc_last_error()
+    assert lib.mc_rank_threshold(1, 10, 5, 1, 1, 0, None) == -4
+    assert lib.mc_rank_threshold(None, 10, 5, 1, 1, 1 << 20, None) == -1
+
+
+def test_analytics_reject_bad_arguments(lib):
+    vol = pm.McVolume(8, 6, 4, 0, 1)
+    ref = ctypes.byref(vol)
+    assert lib.mc_chord_histogram(ref, 3, 1, None) == -1 and b"axis" in lib.mc_last_error()
+    assert lib.mc_chord_histogram(ref, -1, 1, None) == -1 and b"axis" in lib.mc_last_error()
+    assert lib.mc_chord_histogram(ref, 0, None, None) == -1 and b"hist" in lib.mc_last_error()
+    nomask = pm.McVolume(8, 6, 4, 0, None)
+    assert lib.mc_chord_histogram(ctypes.byref(nomask), 0, 1, None) == -1 and b"mask" in lib.mc_last_error()
+    assert lib.mc_phase_contrast(1, 4, 4, 1, None) == -1 and b"z0" in lib.mc_last_error()
+    assert lib.mc_phase_contrast(1, 0, 0, 1, None) == -1 and b"nz" in lib.mc_last_error()
+    assert lib.mc_phase_contrast(None, 4, 0, 1, None) == -1 and b"NULL" in lib.mc_last_error()
+
+    def esc(n=10, width=1.0, nbins=4, thr=None, nthr=0, above=1):
+        return lib.mc_escape_path_histogram(1, n, width, nbins, thr, nthr, 1, 1, above, above, None)
+
+    assert esc(n=-1) == -1 and b"bin_width" in lib.mc_last_error()
+    assert esc(width=0.0) == -1 and esc(width=float("inf")) == -1 and esc(nbins=0) == -1
+    assert esc(nthr=9, thr=1) == -1 and b"nthr" in lib.mc_last_error()
+    assert esc(nthr=2, thr=None) == -1 and b"thresholds" in lib.mc_last_error()
+    assert esc(nthr=2, thr=1, above=None) == -1
+
+    def top(z0=0, frac=0.1):
+        return lib.mc_bright_colocalization(ref, 1, z0, frac, 1, 1, None)
+
+    assert top(z0=4) == -1 and b"z0" in lib.mc_last_error()
+    assert top(z0=-1) == -1
+    assert top(frac=0.0) == -1 and b"frac" in lib.mc_last_error()
+    assert top(frac=1.5) == -1 and top(frac=float("nan")) == -1
+    need = lib.mc_pore_distance_workspace_bytes(ref)
+    assert need > 0
+    assert lib.mc_pore_distance(ref, 1, 1, need - 1, None) == -4 and b"workspace" in lib.mc_last_error()
+    assert lib.mc_pore_distance(ref, None, 1, need, None) == -1
+    assert lib.mc_pore_spearman(ref, 1, 4, 1, 1, 1, 1 << 20, None) == -1 and b"z0" in lib.mc_last_error()
