@@ -155,6 +155,13 @@ def test_bright_colocalization(mask_m1):
         k, s = an.bright_colocalization(dev(m), dev(Fr), 0, frac)
         kw, sw = oan.bright_colocalization(Fr, m, 0, frac)
         assert np.array_equal(k.cpu().numpy(), kw) and np.array_equal(s.cpu().numpy(), sw), frac
+    # spread 44-bit keys: one digit pass over the slice leaves a few dozen candidates,
+    # and the remaining digits are resolved in LDS
+    Fr = rng.integers(0, 2 ** 44, size=m.shape, dtype=np.int64)
+    for frac in (0.1, 0.5, 1.0):
+        k, s = an.bright_colocalization(dev(m), dev(Fr), 0, frac)
+        kw, sw = oan.bright_colocalization(Fr, m, 0, frac)
+        assert np.array_equal(k.cpu().numpy(), kw) and np.array_equal(s.cpu().numpy(), sw), frac
 
 
 # (2100, 2, 8) and (2, 2100, 8): lines too long for an LDS tile of 8 columns, scanned
