@@ -234,7 +234,7 @@ def oracle_check(mask_np, dmask, opt, m, seed, ncpu):
 
 
 def rows_leg(args, seed, field):
-    """The other workloads of the survey's measurement list, each timed on the GPU and
+    """The two other single-mask workloads, each timed on the GPU and
     (unless --no-cpu) checked against the oracle on its first photon ids: 32^3
     phi = 0.70 (all 1e5 photons) and 256^3 phi = 0.90 thresholded from the plain
     workload's field (1e8 photons)."""
