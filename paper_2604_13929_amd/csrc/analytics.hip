@@ -88,6 +88,88 @@ __global__ __launch_bounds__(kThreads) void k_chords(const uint8_t *__restrict__
         if (hs[i]) atomicAdd(&hist[i], (unsigned long long)hs[i]);
 }
 
+// The same count with the lines staged in LDS: a workgroup of kChordTile threads
+// loads kChordTile lines whole with coalesced reads (axis 0: consecutive x-lines;
+// axis 1: consecutive x at one z; axis 2: consecutive positions of the xy plane) into
+// rows of an odd number of words, one row per line, so that both the transposing
+// byte stores and the threads' row reads fall in distinct banks; each thread then
+// scans its row four voxels per LDS read.  (Splitting a row among four threads that
+// read bytes measured slower: 72-103 against 48-54 us per axis at 256^3.)
+constexpr int kChordTile = 128;
+
+__host__ __device__ inline int chord_words(int n) { return ((n + 3) / 4) | 1; }
+
+template <int AXIS>
+__global__ __launch_bounds__(kChordTile) void k_chords_tile(const uint8_t *__restrict__ mask, int n, int nx, int ny,
+                                                            int nz, unsigned long long *hist)
+{
+    extern __shared__ unsigned int hs[];             // 2 (n + 1) counters, then the tile rows
+    unsigned int *rows = hs + 2 * (n + 1);
+    uint8_t *tile = reinterpret_cast<uint8_t *>(rows);
+    const int t = (int)threadIdx.x, nh = 2 * (n + 1), words = chord_words(n), pitch = 4 * words;
+    for (int i = t; i < nh; i += kChordTile) hs[i] = 0u;
+    size_t base;
+    long long stride;
+    int w;
+    if (AXIS == 0) {
+        const long long l0 = (long long)blockIdx.x * kChordTile;
+        w = (int)std::min<long long>(kChordTile, (long long)ny * nz - l0);
+        base = (size_t)l0 * nx;
+        stride = 1;
+    } else if (AXIS == 1) {
+        const int per_z = (nx + kChordTile - 1) / kChordTile;
+        const int z = (int)blockIdx.x / per_z, x0 = ((int)blockIdx.x - z * per_z) * kChordTile;
+        w = std::min(kChordTile, nx - x0);
+        base = (size_t)z * ny * nx + x0;
+        stride = nx;
+    } else {
+        const long long l0 = (long long)blockIdx.x * kChordTile;
+        w = (int)std::min<long long>(kChordTile, (long long)nx * ny - l0);
+        base = (size_t)l0;
+        stride = (long long)nx * ny;
+    }
+    if (AXIS == 0) {
+        for (int e = t; e < w * n; e += kChordTile) {
+            const int c = e / n, j = e - c * n;
+            tile[c * pitch + j] = mask[base + e];
+        }
+    } else {
+        for (int e = t; e < n * w; e += kChordTile) {
+            const int j = e / w, c = e - j * w;
+            tile[c * pitch + j] = mask[base + j * stride + c];
+        }
+    }
+    __syncthreads();
+    if (t < w) {
+        const unsigned int *row = rows + t * words;
+        unsigned int cur = row[0] & 0xffu;
+        int start = 0;
+        for (int q = 0; 4 * q < n; ++q) {
+            const unsigned int wv = row[q];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int j = 4 * q + b;
+                const unsigned int v = (wv >> (8 * b)) & 0xffu;
+                if (j > 0 && j < n && v != cur) {
+                    atomicAdd(&hs[(cur ? 1 : 0) * (n + 1) + (j - start)], 1u);
+                    start = j;
+                    cur = v;
+                }
+            }
+        }
+        atomicAdd(&hs[(cur ? 1 : 0) * (n + 1) + (n - start)], 1u);   // the run that ends the line
+    }
+    __syncthreads();
+    for (int i = t; i < nh; i += kChordTile)
+        if (hs[i]) atomicAdd(&hist[i], (unsigned long long)hs[i]);
+}
+
+// LDS bytes of k_chords_tile for lines of n voxels
+size_t chord_tile_lds(int n)
+{
+    return sizeof(unsigned int) * (2 * ((size_t)n + 1) + (size_t)kChordTile * chord_words(n));
+}
+
 __global__ void k_chords_global(const uint8_t *__restrict__ mask, int axis, int n, long long lines, int nx, int ny,
                                 unsigned long long *hist)
 {
@@ -1064,7 +1146,21 @@ int mc_chord_histogram(const mc_volume *vol, int32_t axis, int64_t *hist, void *
     const long long nh = 2ll * (n + 1);
     hipLaunchKernelGGL(k_zero_i64, dim3(blocks_for(nh)), dim3(kThreads), 0, s, (long long *)hist, nh);
     const size_t lds = sizeof(unsigned int) * (size_t)nh;
-    if (lds <= 65536) {
+    if (chord_tile_lds(n) <= 65536) {
+        const size_t tl = chord_tile_lds(n);
+        const long long tiles = axis == 0 ? ((long long)vol->ny * vol->nz + kChordTile - 1) / kChordTile
+                              : axis == 1 ? (long long)vol->nz * ((vol->nx + kChordTile - 1) / kChordTile)
+                                          : ((long long)vol->nx * vol->ny + kChordTile - 1) / kChordTile;
+        if (axis == 0)
+            hipLaunchKernelGGL(k_chords_tile<0>, dim3((unsigned)tiles), dim3(kChordTile), tl, s, vol->mask, n, vol->nx,
+                               vol->ny, vol->nz, (unsigned long long *)hist);
+        else if (axis == 1)
+            hipLaunchKernelGGL(k_chords_tile<1>, dim3((unsigned)tiles), dim3(kChordTile), tl, s, vol->mask, n, vol->nx,
+                               vol->ny, vol->nz, (unsigned long long *)hist);
+        else
+            hipLaunchKernelGGL(k_chords_tile<2>, dim3((unsigned)tiles), dim3(kChordTile), tl, s, vol->mask, n, vol->nx,
+                               vol->ny, vol->nz, (unsigned long long *)hist);
+    } else if (lds <= 65536) {
         const unsigned grid = (unsigned)std::min<long long>(1024, (lines + kThreads - 1) / kThreads);
         hipLaunchKernelGGL(k_chords, dim3(grid), dim3(kThreads), lds, s, vol->mask, axis, n, lines, vol->nx, vol->ny,
                            (unsigned long long *)hist);

@@ -64,7 +64,9 @@ def runs_vectorised(mask: np.ndarray, np_axis: int) -> np.ndarray:
     return hist
 
 
-@pytest.mark.parametrize("shape", [(5, 7, 9), (16, 3, 11), (1, 4, 4)])
+# lines of up to a few hundred voxels are counted from LDS tiles; (2, 3, 1000) and
+# (1000, 2, 3) have x- and z-lines too long for a tile
+@pytest.mark.parametrize("shape", [(5, 7, 9), (16, 3, 11), (1, 4, 4), (3, 130, 200), (2, 3, 1000), (1000, 2, 3)])
 def test_chords_small(shape):
     banner(f"chord histograms, shape {shape}")
     nz, ny, nx = shape
@@ -81,6 +83,8 @@ def test_chords_m1_and_fullsize(mask_m1):
                               oan.chord_histogram(mask_m1, axis=2 - axis))
     wl = inputs.WORKLOADS["M2a"]
     m = inputs.spinodal_mask(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], wl["porosity"], seed=0)
+    for axis in (0, 1):
+        assert np.array_equal(an.chord_histogram(dev(m), axis).cpu().numpy(), runs_vectorised(m, 2 - axis)), axis
     h = an.chord_histogram(dev(m), 2).cpu().numpy()
     assert np.array_equal(h, runs_vectorised(m, 0))
     lengths = np.arange(h.shape[1])
