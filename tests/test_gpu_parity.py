@@ -240,6 +240,22 @@ def test_m1_fp64_transport_is_near_exact(mask_m1):
     assert np.all(np.abs(F_g - F_o) <= 1e-9 * F_o + 0.5 * 4096)
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 65535), (1, 65535, 1), (65535, 1, 1), (3, 5, 40001)])
+def test_extreme_extents_fp64_near_exact(shape):
+    """Extents at the volume limit (65 535 along one axis, one voxel across the others,
+    so the lateral wrap maps a voxel onto itself): with FP64 transport the integer
+    channels equal the oracle's and the fluence matches to quantisation."""
+    banner(f"extreme extents {shape}, FP64 transport vs oracle")
+    mask = (np.random.default_rng(sum(shape)).random(shape) < 0.7).astype(np.uint8)
+    n = 2000
+    res, summ, sc, ref, tot, e = _compare_run(mask, OPT, n, nbatch=1, rel=1e-9, fp64=True)
+    for k in ("R", "T", "A", "RR", "esc_w", "esc_n", "steps", "interactions"):
+        assert sc[k] == tot[k], k
+    F_g = res.fluence.cpu().numpy().astype(np.float64)
+    F_o = ref["fluence"][0]
+    assert np.all(np.abs(F_g - F_o) <= 1e-9 * F_o + 0.5 * 4096)
+
+
 def test_m1_globals_at_1e7(mask_m1):
     banner("M1 1e7 photons: globals within 0.5 %")
     _compare_run(mask_m1, OPT, 10_000_000, nbatch=1)
