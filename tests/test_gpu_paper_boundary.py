@@ -108,6 +108,26 @@ def test_photon_outcomes_fp64_paper_model(mask_m1):
     assert np.all(go["steps"] > 0)
 
 
+@pytest.mark.parametrize("shape", [(65535, 1, 1), (1, 1, 65535), (2, 65535, 1)])
+def test_extreme_extents_paper_model(shape):
+    """The paper model (pads, mirrors on one-voxel-wide faces, Fresnel, gate) at the
+    volume's extent limit: per-photon outcomes equal the oracle's in FP64 transport,
+    and the FP32 run closes exactly."""
+    banner(f"paper model, extreme extents {shape}, FP64 outcomes vs oracle")
+    mask = (np.random.default_rng(7 + sum(shape)).random(shape) < 0.7).astype(np.uint8)
+    opt = pm.paper_optics(**BASE, n_solid=N_SOLID, lateral=pm.LATERAL_MIRROR, gate=3000.0)
+    ids = np.arange(2000, dtype=np.uint64) + 5
+    _, go = pm.trace(dev(mask), opt, ids, 0, SEED, fp64=True)
+    _, oo = oracle.trace(mask, opt.mu_s, opt.mu_a, opt.g, ids, SEED, max_rec=0, **okw(opt))
+    clean = oo["min_gap"] > 1e-9
+    assert clean.mean() > 0.99
+    for f in ("R", "T", "A", "RR", "lost", "w_final", "fate", "steps", "interactions"):
+        assert np.array_equal(go[f][clean].astype(np.int64), oo[f][clean].astype(np.int64)), f
+    res = pm.run(dev(mask), opt, 2000, SEED)
+    sc = res.scalar_dict()
+    assert closure(sc, 2000) == 0 and sc["launched"] == 2000
+
+
 def test_fields_and_globals_paper_model(mask_m1):
     banner("paper model M1 1e5 photons FP32: per-voxel 4 sigma, globals 0.5 %")
     n, B = 100_000, 32
