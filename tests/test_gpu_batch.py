@@ -60,6 +60,23 @@ def test_batch_equals_plain_runs(small_jobs):
             assert np.array_equal(bs.depth, s.depth, equal_nan=True)
 
 
+def test_batch_with_extreme_extents_equals_plain_runs():
+    banner("batch of masks at the extent limit (65535 along one axis) == plain runs, bitwise")
+    rng = np.random.default_rng(3)
+    shapes = [(65535, 1, 1), (1, 1, 65535), (1, 65535, 2), (9, 10, 11)]
+    jobs = []
+    for i, sh in enumerate(shapes):
+        m = torch.from_numpy((rng.random(sh) < 0.7).astype(np.uint8)).cuda()
+        jobs.append(pm.BatchJob(m, pm.Optics(0.5, f32(0.01), f32(0.7)), 3000 + 100 * i, seed=20260809,
+                                stream_id=i))
+    b = pm.run_batch(jobs, tune=pm.Tune(256, 16, 256, 16))
+    torch.cuda.synchronize()
+    for k, j in enumerate(jobs):
+        r, s = _plain(j)
+        assert torch.equal(b.results[k].fluence, r.fluence), k
+        assert torch.equal(b.results[k].scalars, r.scalars), k
+
+
 def test_batch_fp64_equals_plain_fp64(small_jobs):
     banner("batch FP64 transport == plain FP64")
     b = pm.run_batch(small_jobs[:3], tune=pm.Tune(128, 8, 64, 8), fp64=True)
