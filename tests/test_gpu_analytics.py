@@ -94,6 +94,38 @@ def test_chords_m1_and_fullsize(mask_m1):
           f"ratio {st['mean_pore'] / st['mean_solid']:.3f} (phi/(1-phi) = {0.7 / 0.3:.3f})")
 
 
+@pytest.mark.parametrize("shape", [(65535, 1, 1), (1, 1, 65535), (1, 65535, 2)])
+def test_analytics_at_extreme_extents(shape):
+    """Chords, decile and (within the 32-bit squared-distance limit) distances and
+    Spearman at the volume's extent limit, against the oracle."""
+    banner(f"analytics at extreme extents {shape}")
+    rng = np.random.default_rng(sum(shape))
+    m = (rng.random(shape) < 0.7).astype(np.uint8)
+    d = dev(m)
+    for axis in (0, 1, 2):
+        assert np.array_equal(an.chord_histogram(d, axis).cpu().numpy(), oan.chord_histogram(m, axis=2 - axis)), axis
+    F = rng.integers(0, 2 ** 40, size=shape).astype(np.int64)
+    z0 = shape[0] // 2
+    k, sv = an.bright_colocalization(d, dev(F), z0, 0.1)
+    kw, sw = oan.bright_colocalization(F, m, z0, 0.1)
+    assert np.array_equal(k.cpu().numpy(), kw) and np.array_equal(sv.cpu().numpy(), sw)
+    # squared distances are 32-bit: 65535 along an axis is refused, 32767 is taken
+    with pytest.raises(pm.McError):
+        an.pore_distance(d)
+    half = tuple(min(n, 32767) for n in shape)
+    mh = np.ascontiguousarray(m[:half[0], :half[1], :half[2]])
+    mh.flat[len(mh.flat) // 3] = 0                      # at least one solid voxel
+    assert np.array_equal(an.pore_distance(dev(mh)).cpu().numpy(), oan.pore_distance(mh))
+    Fh = np.ascontiguousarray(F[:half[0], :half[1], :half[2]])
+    rho, n = an.pore_spearman(dev(mh), dev(Fh), half[0] // 2)
+    rw, nw = oan.pore_spearman(Fh, mh, half[0] // 2)
+    assert np.array_equal(n.cpu().numpy(), nw)
+    r = rho.cpu().numpy()
+    assert np.array_equal(np.isnan(r), np.isnan(rw))
+    ok = ~np.isnan(rw)
+    assert np.all(np.abs(r[ok] - rw[ok]) <= 1e-12)
+
+
 def test_phase_contrast(mask_m1):
     banner("phase contrast of a GPU run's depth profiles")
     d = dev(mask_m1)
