@@ -261,6 +261,22 @@ def test_m1_globals_at_1e7(mask_m1):
     _compare_run(mask_m1, OPT, 10_000_000, nbatch=1)
 
 
+def test_batch_spread_scales_as_inverse_sqrt_n(mask_m1):
+    """Photons are independent: the spread of phi3d over 64 disjoint photon-id batches
+    falls as 1/sqrt(N), so batches 4x larger spread half as much (the bounds are
+    about 3 sigma of a ratio of two 64-sample standard deviations)."""
+    banner("phi3d spread over 64 batches of 2000 and of 8000 photons: ratio 2")
+    d = dev(mask_m1)
+
+    def spread(m, first):
+        vals = [pm.reduce(d, pm.run(d, OPT, m, SEED, photon_begin=first + k * m))["phi3d"] for k in range(64)]
+        return float(np.std(vals, ddof=1))
+
+    s_small, s_large = spread(2000, 0), spread(8000, 1_000_000)
+    assert s_large > 0.0
+    assert 1.3 < s_small / s_large < 2.8, (s_small, s_large)
+
+
 def test_bitwise_reproducible_and_tune_invariant(mask_m1):
     banner("bitwise reproducibility across launch shapes")
     d = dev(mask_m1)

@@ -292,6 +292,21 @@ def test_collision_equals_track_length(mask_m1):
     assert abs(A.sum() / (f32(mu_a) * track.sum()) - 1.0) < 0.01
 
 
+def test_batch_spread_scales_as_inverse_sqrt_n(mask_m1):
+    """The batch spread behind every statistical check is that of independent photons:
+    with 4x the photons per batch, the spread of the per-batch phi3d halves (bounds
+    about 3 sigma of a ratio of two 32-sample standard deviations)."""
+    B = 32
+
+    def spread(n, seed):
+        r = oracle.run(mask_m1, 0.5, f32(0.01), f32(0.7), n, seed=seed, nbatch=B)
+        return np.std([est.estimators(r["fluence"][b], mask_m1, n // B)["phi3d"] for b in range(B)], ddof=1)
+
+    s_small, s_large = spread(16_000, 21), spread(64_000, 22)
+    assert s_large > 0.0
+    assert 1.2 < s_small / s_large < 3.2, (s_small, s_large)
+
+
 def test_roulette_is_unbiased(mask_m1):
     """Frequent roulette adds zero weight on average and leaves R, T unchanged in expectation."""
     n, B = 100_000, 32
