@@ -19,7 +19,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
-SUITES = ["tests/test_oracle_pins.py", "tests/test_oracle_boundary.py", "tests/test_estimators_inputs.py"]
+SUITES = ["tests/test_oracle_dda.py", "tests/test_oracle_pins.py", "tests/test_oracle_boundary.py",
+          "tests/test_estimators_inputs.py"]
 
 # (name, text in oracle.c, replacement)
 MUTANTS = [
@@ -33,6 +34,8 @@ MUTANTS = [
     ("rotation_sign", "nuy = stt * (uy * uz * cp + ux * sp) / tn + uy * ct;",
      "nuy = stt * (uy * uz * cp - ux * sp) / tn + uy * ct;"),
     ("wrap_off_by_one", "if (st->ix == nx) st->ix = 0;", "if (st->ix == nx) st->ix = 1;"),
+    ("face_tie_to_later_axis", "if (dist[1] < dist[axis]) axis = 1;", "if (dist[1] <= dist[axis]) axis = 1;"),
+    ("interaction_tie_to_face", "int interact = (s_int <= d_face);", "int interact = (s_int < d_face);"),
     ("free_path_halved", "            st->tau = -log(u_open_closed(r[2]));\n        }",
      "            st->tau = -0.5 * log(u_open_closed(r[2]));\n        }"),
     ("absorb_rounds_down", "const int64_t w_new = (int64_t)(((uint64_t)st->w * S_q + 2147483648ull) >> 32);",
