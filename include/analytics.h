@@ -54,6 +54,8 @@ int mc_bright_colocalization(const mc_volume *vol, const int64_t *fluence, int32
 /* Local pore size (Sec. 3.4, co-localisation): the exact Euclidean distance from
  * every pore voxel centre to the nearest solid voxel centre inside the volume (no
  * periodic images), 0 in the solid, +inf everywhere if there is no solid voxel.
+ * Squared distances are 32-bit integers: needs nx^2 + ny^2 + nz^2 < 2^30 - 1 (an
+ * extent up to 32 767 on one axis), MC_EINVAL otherwise.
  *   dist  device double[nz][ny][nx] (written) */
 size_t mc_pore_distance_workspace_bytes(const mc_volume *vol);
 int mc_pore_distance(const mc_volume *vol, double *dist, void *workspace, size_t workspace_bytes,
@@ -67,7 +69,8 @@ int mc_pore_distance(const mc_volume *vol, double *dist, void *workspace, size_t
  *   fluence      device int64[nz][ny][nx] (mc_run's tally)
  *   rho          device double[nz - z0] (written)
  *   n_pore       device int64[nz - z0]: pore voxels per slice (written)
- * Needs nx * ny * (nz - z0) < 2^31.  Unlike the other calls this one synchronises
+ * Needs nx * ny * (nz - z0) < 2^31 and the distance transform's extent limit.
+ * Unlike the other calls this one synchronises
  * the stream once: the number of pore voxels sizes the sorts, and the largest
  * fluence and squared distance fix their bit ranges.  The workspace query
  * asks the HIP runtime for the current device's sort configuration and returns 0
