@@ -190,6 +190,22 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
            uint64_t seed, uint32_t stream_id, int flags, int64_t *fluence, int64_t *scalars,
            void *workspace, size_t workspace_bytes, const mc_tune *tune, void *hip_stream);
 
+/*
+ * mc_run that also histograms the in-pore path of every escaping photon (fate R
+ * or T) of the run (Sec. 3.4 (c)), with the bins of mc_escape_path_histogram
+ * (analytics.h): bin b holds b * bin_width <= path < (b + 1) * bin_width, the
+ * last bin everything beyond.  The tallies are those of mc_run with the same
+ * arguments, bit for bit.
+ *   bin_width   finite, > 0 (voxels);  nbins  1 .. 512
+ *   hist_w, hist_n  device int64[nbins]: escaped Q31 weight and photon count per
+ *                   bin; zeroed first unless flags has MC_ACCUMULATE
+ * Errors as mc_run, and MC_EINVAL for NULL histograms or a bad bin_width / nbins.
+ */
+int mc_run_escape_histogram(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin,
+                            uint64_t n_photons, uint64_t seed, uint32_t stream_id, int flags, int64_t *fluence,
+                            int64_t *scalars, void *workspace, size_t workspace_bytes, const mc_tune *tune,
+                            double bin_width, int32_t nbins, int64_t *hist_w, int64_t *hist_n, void *hip_stream);
+
 /* Duration in milliseconds of the walk kernel of the last mc_run on this thread
  * that carried MC_TIMED (two HIP events recorded on its stream around the walk
  * launch only).  Waits for that walk to finish.  MC_EINVAL if none. */

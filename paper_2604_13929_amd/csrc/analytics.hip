@@ -235,12 +235,6 @@ struct Thresholds {
     double t[8];
 };
 
-__device__ __forceinline__ int path_bin(double pv, double width, int nbins)
-{
-    const double q = floor(pv / width);
-    return q >= (double)(nbins - 1) ? nbins - 1 : (q > 0.0 ? (int)q : 0);
-}
-
 // Escape-path histograms with the bins in LDS (weights 64-bit, counts 32-bit per
 // workgroup) and the threshold sums kept per thread, then reduced per wave: one
 // global atomic per wave and threshold instead of one per photon.
@@ -268,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void k_escape_hist(const mc_photon_rec *_
         const mc_photon_rec r = rec[i];
         if (r.fate != 4u && r.fate != 5u) continue;
         const double pv = r.path_void;
-        const int b = path_bin(pv, width, nbins);
+        const int b = pmc::escape_path_bin(pv, width, nbins);
         if (LDS) {
             atomicAdd(&sw[b], (unsigned long long)r.w_final);
             atomicAdd(&sn[b], 1u);

@@ -248,6 +248,16 @@ __device__ __forceinline__ void account(unsigned long long *acc, const Photon<R>
     atomicAdd(&acc[MC_S_LAUNCHED], 1ull);
 }
 
+// In-pore path histogram of the escaping photons of a walk (Sec. 3.4 (c)), kept
+// per workgroup in LDS (weights 64-bit, counts 32-bit) and added to w and n once.
+struct EscHist {
+    unsigned long long *w;    // [nbins] escaped Q31 weight
+    unsigned long long *n;    // [nbins] escaped photons
+    double width;
+    int32_t nbins;            // 1 .. kEscMaxBins
+};
+constexpr int kEscMaxBins = 512;  // 6 KB of LDS: four walk workgroups still fit per CU
+
 // ---------------------------------------------------------------------------
 // Persistent walk
 // ---------------------------------------------------------------------------
@@ -264,22 +274,29 @@ template <bool GRAD, bool LOGGED> struct SinkOf {
 
 // LOGGED: J.fluence is the bricked tally (see LoggedDeposit).  GENERAL: the
 // step that also knows the paper's boundary model (see walk.hpp).
-template <int BLOCK, typename R, bool GRAD, bool LOGGED, bool GENERAL>
+// ESC: also bin the in-pore path of every escaping photon (EscHist).
+template <int BLOCK, typename R, bool GRAD, bool LOGGED, bool GENERAL, bool ESC>
 __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long *__restrict__ queue, int32_t chunk,
-                                                int32_t refill, unsigned long long *__restrict__ grad)
+                                                int32_t refill, unsigned long long *__restrict__ grad, const EscHist eh)
 {
     constexpr int kWaves = BLOCK / 64;
     constexpr int K = GRAD ? 16 : kLogK;   // log window (the gradient bins share the LDS)
     __shared__ unsigned long long acc[MC_NSCALARS];
     __shared__ uint32_t s_lidx[LOGGED ? kWaves * K * kLogStride : 1];
     __shared__ uint32_t s_lval[LOGGED ? kWaves * K * kLogStride : 1];
-    extern __shared__ unsigned long long s_grad[];  // GRAD: [3][2][nz]
+    extern __shared__ unsigned long long s_grad[];  // GRAD: [3][2][nz]; ESC: weights [nbins], then counts
+    unsigned int *esc_n = reinterpret_cast<unsigned int *>(s_grad + (ESC ? eh.nbins : 0));
     const uint32_t lane = __lane_id();
     uint32_t *lidx = s_lidx + (threadIdx.x >> 6) * (LOGGED ? K * kLogStride : 0);
     uint32_t *lval = s_lval + (threadIdx.x >> 6) * (LOGGED ? K * kLogStride : 0);
     if (threadIdx.x < MC_NSCALARS) acc[threadIdx.x] = 0ull;
     if (GRAD)
         for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) s_grad[i] = 0ull;
+    if (ESC)
+        for (int32_t i = threadIdx.x; i < eh.nbins; i += BLOCK) {
+            s_grad[i] = 0ull;
+            esc_n[i] = 0u;
+        }
     if (LOGGED)
         for (int i = 0; i < K; ++i) lval[i * kLogStride + lane] = 0u;
     __syncthreads();
@@ -334,6 +351,11 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
             const int32_t ev = step<GENERAL>(p, J, sink);
             if (is_terminal(ev)) {
                 account(acc, p, ev, J.nz);
+                if (ESC && (ev == EV_ESC_R || ev == EV_ESC_T)) {
+                    const int b = escape_path_bin(p.l_void, eh.width, eh.nbins);
+                    atomicAdd(&s_grad[b], (unsigned long long)p.w);
+                    atomicAdd(&esc_n[b], 1u);
+                }
                 alive = false;
             }
         }
@@ -347,6 +369,12 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
         const unsigned long long v = acc[threadIdx.x];
         if (v) atomicAdd((unsigned long long *)&J.scalars[threadIdx.x], v);
     }
+    if (ESC)
+        for (int32_t i = threadIdx.x; i < eh.nbins; i += BLOCK)
+            if (esc_n[i]) {
+                atomicAdd(&eh.w[i], s_grad[i]);
+                atomicAdd(&eh.n[i], (unsigned long long)esc_n[i]);
+            }
     if (GRAD) {
         // signed block sums into (hi, lo) pairs: total = sum(hi) * 2^32 + sum(lo)
         for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) {
@@ -824,46 +852,47 @@ int enqueue_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *
     return MC_OK;
 }
 
-template <typename R, bool GRAD, bool LOGGED, bool GENERAL>
+template <typename R, bool GRAD, bool LOGGED, bool GENERAL, bool ESC>
 void enqueue_walk(int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t,
-                  unsigned long long *grad, hipStream_t s)
+                  unsigned long long *grad, const EscHist &eh, hipStream_t s)
 {
-    const size_t lds = GRAD ? (size_t)6 * J.nz * sizeof(unsigned long long) : 0;
+    const size_t lds = GRAD ? (size_t)6 * J.nz * sizeof(unsigned long long)
+                            : (ESC ? (size_t)eh.nbins * (sizeof(unsigned long long) + sizeof(unsigned int)) : 0);
     switch (block) {
     case 64:
-        hipLaunchKernelGGL((k_walk<64, R, GRAD, LOGGED, GENERAL>), dim3(blocks), dim3(64), lds, s, J, queue, t.chunk, t.refill,
-                           grad);
+        hipLaunchKernelGGL((k_walk<64, R, GRAD, LOGGED, GENERAL, ESC>), dim3(blocks), dim3(64), lds, s, J, queue, t.chunk,
+                           t.refill, grad, eh);
         break;
     case 128:
-        hipLaunchKernelGGL((k_walk<128, R, GRAD, LOGGED, GENERAL>), dim3(blocks), dim3(128), lds, s, J, queue, t.chunk,
-                           t.refill, grad);
+        hipLaunchKernelGGL((k_walk<128, R, GRAD, LOGGED, GENERAL, ESC>), dim3(blocks), dim3(128), lds, s, J, queue,
+                           t.chunk, t.refill, grad, eh);
         break;
     case 256:
-        hipLaunchKernelGGL((k_walk<256, R, GRAD, LOGGED, GENERAL>), dim3(blocks), dim3(256), lds, s, J, queue, t.chunk,
-                           t.refill, grad);
+        hipLaunchKernelGGL((k_walk<256, R, GRAD, LOGGED, GENERAL, ESC>), dim3(blocks), dim3(256), lds, s, J, queue,
+                           t.chunk, t.refill, grad, eh);
         break;
     default:
-        hipLaunchKernelGGL((k_walk<512, R, GRAD, LOGGED, GENERAL>), dim3(blocks), dim3(512), lds, s, J, queue, t.chunk,
-                           t.refill, grad);
+        hipLaunchKernelGGL((k_walk<512, R, GRAD, LOGGED, GENERAL, ESC>), dim3(blocks), dim3(512), lds, s, J, queue,
+                           t.chunk, t.refill, grad, eh);
         break;
     }
 }
 
-template <typename R, bool GRAD>
+template <typename R, bool GRAD, bool ESC>
 void enqueue_walk_dep(bool logged, int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t,
-                      unsigned long long *grad, hipStream_t s)
+                      unsigned long long *grad, const EscHist &eh, hipStream_t s)
 {
     if (J.paper) {
-        if (logged) enqueue_walk<R, GRAD, true, true>(block, blocks, J, queue, t, grad, s);
-        else enqueue_walk<R, GRAD, false, true>(block, blocks, J, queue, t, grad, s);
+        if (logged) enqueue_walk<R, GRAD, true, true, ESC>(block, blocks, J, queue, t, grad, eh, s);
+        else enqueue_walk<R, GRAD, false, true, ESC>(block, blocks, J, queue, t, grad, eh, s);
     } else {
-        if (logged) enqueue_walk<R, GRAD, true, false>(block, blocks, J, queue, t, grad, s);
-        else enqueue_walk<R, GRAD, false, false>(block, blocks, J, queue, t, grad, s);
+        if (logged) enqueue_walk<R, GRAD, true, false, ESC>(block, blocks, J, queue, t, grad, eh, s);
+        else enqueue_walk<R, GRAD, false, false, ESC>(block, blocks, J, queue, t, grad, eh, s);
     }
 }
 
 int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipStream_t s, int flags,
-                unsigned long long *grad, bool logged)
+                unsigned long long *grad, bool logged, const EscHist *esc)
 {
     DeviceInfo di;
     int rc = device_info(&di);
@@ -872,12 +901,16 @@ int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipSt
     const int blocks = std::max(1, di.cus * t.waves_per_cu / waves_per_block);
     const bool timed = (flags & MC_TIMED) != 0;
     if (timed && (rc = time_begin(s))) return rc;
+    const EscHist none = {nullptr, nullptr, 1.0, 0};
     if (grad) {
-        if (flags & MC_FP64) enqueue_walk_dep<double, true>(logged, t.block, blocks, J, queue, t, grad, s);
-        else enqueue_walk_dep<float, true>(logged, t.block, blocks, J, queue, t, grad, s);
+        if (flags & MC_FP64) enqueue_walk_dep<double, true, false>(logged, t.block, blocks, J, queue, t, grad, none, s);
+        else enqueue_walk_dep<float, true, false>(logged, t.block, blocks, J, queue, t, grad, none, s);
+    } else if (esc) {
+        if (flags & MC_FP64) enqueue_walk_dep<double, false, true>(logged, t.block, blocks, J, queue, t, nullptr, *esc, s);
+        else enqueue_walk_dep<float, false, true>(logged, t.block, blocks, J, queue, t, nullptr, *esc, s);
     } else {
-        if (flags & MC_FP64) enqueue_walk_dep<double, false>(logged, t.block, blocks, J, queue, t, nullptr, s);
-        else enqueue_walk_dep<float, false>(logged, t.block, blocks, J, queue, t, nullptr, s);
+        if (flags & MC_FP64) enqueue_walk_dep<double, false, false>(logged, t.block, blocks, J, queue, t, nullptr, none, s);
+        else enqueue_walk_dep<float, false, false>(logged, t.block, blocks, J, queue, t, nullptr, none, s);
     }
     HIP_TRY(hipGetLastError());
     if (timed && (rc = time_end(s))) return rc;
@@ -887,7 +920,7 @@ int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipSt
 // Zero the tallies (unless accumulating), pack the mask, walk, and for the
 // logged deposit path move the bricked tally into the caller's layout.
 int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws, unsigned long long *grad_bins,
-             hipStream_t s)
+             hipStream_t s, const EscHist *esc = nullptr)
 {
     const Dims d = dims_of(vol);
     const bool logged = d.logged && !(flags & MC_DIRECT_DEPOSIT);
@@ -900,13 +933,15 @@ int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws,
         if (!logged && (rc = fill(fluence, d.nvox, s))) return rc;
         if ((rc = fill(J.scalars, MC_NSCALARS, s))) return rc;
         if (grad_bins && (rc = fill((int64_t *)grad_bins, (uint64_t)12 * vol->nz, s))) return rc;
+        if (esc && (rc = fill((int64_t *)esc->w, (uint64_t)esc->nbins, s))) return rc;
+        if (esc && (rc = fill((int64_t *)esc->n, (uint64_t)esc->nbins, s))) return rc;
     }
     if (logged && (rc = fill(tally, d.tally_words, s))) return rc;
     if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
     if ((rc = pack(vol, bricks, s))) return rc;
     J.bricks = bricks;
     if (logged) J.fluence = tally;
-    if ((rc = launch_walk(J, queue, t, s, flags, grad_bins, logged))) return rc;
+    if ((rc = launch_walk(J, queue, t, s, flags, grad_bins, logged, esc))) return rc;
     if (logged) return unbrick(tally, fluence, vol, (flags & MC_ACCUMULATE) != 0, s);
     return MC_OK;
 }
@@ -990,6 +1025,29 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
     J.fluence = fluence;
     J.scalars = scalars;
     return run_walk(vol, J, flags, t, (char *)workspace, nullptr, (hipStream_t)hip_stream);
+}
+
+int mc_run_escape_histogram(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons,
+                            uint64_t seed, uint32_t stream_id, int flags, int64_t *fluence, int64_t *scalars,
+                            void *workspace, size_t workspace_bytes, const mc_tune *tune, double bin_width,
+                            int32_t nbins, int64_t *hist_w, int64_t *hist_n, void *hip_stream)
+{
+    clear_error();
+    if (!hist_w || !hist_n) return fail(MC_EINVAL, "hist_w and hist_n must be non-NULL");
+    if (nbins < 1 || nbins > kEscMaxBins) return fail(MC_EINVAL, "nbins must be in [1, %d]", kEscMaxBins);
+    if (!(bin_width > 0.0) || !isfinite(bin_width)) return fail(MC_EINVAL, "bin_width must be finite and > 0");
+    Job J;
+    int rc = make_job(vol, opt, photon_begin, n_photons, seed, stream_id, &J);
+    if (rc) return rc;
+    if (!fluence || !scalars || !workspace) return fail(MC_EINVAL, "fluence, scalars and workspace must be non-NULL");
+    const size_t need = mc_run_workspace_bytes(vol);
+    if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    const mc_tune t = resolve_tune(tune);
+    if ((rc = check_tune(t))) return rc;
+    J.fluence = fluence;
+    J.scalars = scalars;
+    const EscHist esc = {(unsigned long long *)hist_w, (unsigned long long *)hist_n, bin_width, nbins};
+    return run_walk(vol, J, flags, t, (char *)workspace, nullptr, (hipStream_t)hip_stream, &esc);
 }
 
 int mc_walk_elapsed_ms(float *ms)

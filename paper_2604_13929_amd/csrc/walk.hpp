@@ -46,6 +46,15 @@ enum : int32_t {
 
 __host__ __device__ __forceinline__ bool is_terminal(int32_t ev) { return ev >= EV_ESC_R && ev <= EV_GATED; }
 
+// Bin of an escaping photon's in-pore path pv (Sec. 3.4 (c)): b * width <= pv <
+// (b + 1) * width, the last bin everything beyond.  The walk's own histogram and
+// the binning of traced records both use this one definition.
+__device__ __forceinline__ int escape_path_bin(double pv, double width, int nbins)
+{
+    const double q = floor(pv / width);
+    return q >= (double)(nbins - 1) ? nbins - 1 : (q > 0.0 ? (int)q : 0);
+}
+
 // Per-job constants.  Everything integer that decides an outcome is computed
 // on the host in FP64 (survival factor, roulette threshold and odds).
 struct Job {

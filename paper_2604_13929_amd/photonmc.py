@@ -87,6 +87,9 @@ _SIGS = {
     "mc_run_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_run": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                               ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P, _P]),
+    "mc_run_escape_histogram": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                               ctypes.c_uint32, ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P,
+                                               ctypes.c_double, ctypes.c_int32, _P, _P, _P]),
     "mc_walk_elapsed_ms": (ctypes.c_int, [_P]),
     "mc_reduce_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_reduce": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -242,6 +245,8 @@ class RunResult:
     fluence: torch.Tensor
     scalars: torch.Tensor
     walk_ms: float | None = None
+    escape_hist_w: torch.Tensor | None = None   # int64[nbins] with escape_bins
+    escape_hist_n: torch.Tensor | None = None
 
     def scalar_dict(self) -> dict:
         s = self.scalars.cpu().tolist()
@@ -263,8 +268,10 @@ def workspace(nbytes: int, device) -> torch.Tensor:
 
 def run(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_begin: int = 0, stream_id: int = 0,
         accumulate: RunResult | None = None, tune: Tune | None = None, timed: bool = False,
-        fp64: bool = False, direct: bool = False) -> RunResult:
-    """mc_run on the current stream of the mask's device (fp64: the FP64 reference transport)."""
+        fp64: bool = False, direct: bool = False, escape_bins: tuple[float, int] | None = None) -> RunResult:
+    """mc_run on the current stream of the mask's device (fp64: the FP64 reference transport).
+    escape_bins = (bin_width, nbins): mc_run_escape_histogram, which also bins the
+    in-pore path of the escaping photons into res.escape_hist_w / escape_hist_n."""
     L = load()
     vol = volume(mask)
     dev = mask.device
@@ -284,9 +291,23 @@ def run(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_be
     ws = workspace(nbytes, dev)
     opt = optics.c()
     t = tune.c() if tune is not None else None
-    _check(L.mc_run(ctypes.byref(vol), ctypes.byref(opt), photon_begin, n_photons, seed, stream_id, flags,
-                    res.fluence.data_ptr(), res.scalars.data_ptr(), ws.data_ptr(), ws.numel(),
-                    ctypes.byref(t) if t is not None else None, _stream(dev)), "mc_run")
+    tref = ctypes.byref(t) if t is not None else None
+    if escape_bins is None:
+        _check(L.mc_run(ctypes.byref(vol), ctypes.byref(opt), photon_begin, n_photons, seed, stream_id, flags,
+                        res.fluence.data_ptr(), res.scalars.data_ptr(), ws.data_ptr(), ws.numel(), tref,
+                        _stream(dev)), "mc_run")
+    else:
+        width, nbins = float(escape_bins[0]), int(escape_bins[1])
+        if res.escape_hist_w is None or res.escape_hist_w.numel() != nbins:
+            if accumulate is not None:
+                raise ValueError("accumulate needs a result that carries histograms of the same nbins")
+            res.escape_hist_w = torch.empty(nbins, dtype=torch.int64, device=dev)
+            res.escape_hist_n = torch.empty(nbins, dtype=torch.int64, device=dev)
+        _check(L.mc_run_escape_histogram(ctypes.byref(vol), ctypes.byref(opt), photon_begin, n_photons, seed,
+                                         stream_id, flags, res.fluence.data_ptr(), res.scalars.data_ptr(),
+                                         ws.data_ptr(), ws.numel(), tref, width, nbins,
+                                         res.escape_hist_w.data_ptr(), res.escape_hist_n.data_ptr(), _stream(dev)),
+               "mc_run_escape_histogram")
     res._ws = ws  # keep the workspace alive with the queued work
     if timed:
         ms = ctypes.c_float(0.0)

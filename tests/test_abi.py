@@ -229,3 +229,21 @@ def test_analytics_reject_bad_arguments(lib):
     assert lib.mc_pore_distance(ref, 1, 1, need - 1, None) == -4 and b"workspace" in lib.mc_last_error()
     assert lib.mc_pore_distance(ref, None, 1, need, None) == -1
     assert lib.mc_pore_spearman(ref, 1, 4, 1, 1, 1, 1 << 20, None) == -1 and b"z0" in lib.mc_last_error()
+
+
+def test_escape_histogram_run_rejects_bad_arguments(lib):
+    vol = pm.McVolume(8, 8, 8, 0, 1)
+    opt = pm.McOptics(0.5, 0.01, 0.7, 1e-4, 10, 0.0, 0, 0)
+
+    def call(width=1.0, nbins=16, hw=1, hn=1):
+        return lib.mc_run_escape_histogram(ctypes.byref(vol), ctypes.byref(opt), 0, 10, 1, 0, 0, 1, 1, 1, 1 << 30,
+                                           None, width, nbins, hw, hn, None)
+
+    assert call(nbins=0) == -1 and b"nbins" in lib.mc_last_error()
+    assert call(nbins=513) == -1 and b"nbins" in lib.mc_last_error()
+    assert call(width=0.0) == -1 and b"bin_width" in lib.mc_last_error()
+    assert call(width=float("inf")) == -1 and call(width=float("nan")) == -1
+    assert call(hw=None) == -1 and call(hn=None) == -1 and b"hist" in lib.mc_last_error()
+    bad = pm.McOptics(0.5, 0.01, 1.0, 1e-4, 10, 0.0, 0, 0)
+    assert lib.mc_run_escape_histogram(ctypes.byref(vol), ctypes.byref(bad), 0, 10, 1, 0, 0, 1, 1, 1, 1 << 30, None,
+                                       1.0, 16, 1, 1, None) == -1 and b"|g|" in lib.mc_last_error()

@@ -159,6 +159,29 @@ def test_escape_paths(mask_m1):
     assert aw[0] == run["esc_w_gtL"] and an_[0] == run["esc_n_gtL"]
 
 
+@pytest.mark.parametrize("model,fp64", [("plain", False), ("paper", False), ("plain", True)])
+def test_walk_escape_histogram_equals_traced_records(mask_m1, model, fp64):
+    """mc_run_escape_histogram: the tallies are mc_run's bit for bit, and the histogram
+    is that of the same photons' traced records, bin for bin; halves accumulate to the whole."""
+    banner(f"escape histogram kept by the walk ({model}, fp64={fp64}) vs traced records")
+    opt = OPT if model == "plain" else pm.paper_optics(0.5, f32(0.01), f32(0.7), n_solid=f32(1.746),
+                                                       lateral=pm.LATERAL_MIRROR, gate=400.0)
+    d = dev(mask_m1)
+    n, width, nbins = 200_000, 1.5, 96
+    plain = pm.run(d, opt, n, SEED, fp64=fp64)
+    res = pm.run(d, opt, n, SEED, fp64=fp64, escape_bins=(width, nbins))
+    assert torch.equal(res.fluence, plain.fluence) and torch.equal(res.scalars, plain.scalars)
+    traced = an.escape_paths(d, opt, n, SEED, bin_width=width, nbins=nbins, fp64=fp64)
+    assert torch.equal(res.escape_hist_w, traced["hist_w"]) and torch.equal(res.escape_hist_n, traced["hist_n"])
+    sc = res.scalar_dict()
+    assert int(res.escape_hist_w.sum()) == sc["esc_w"] and int(res.escape_hist_n.sum()) == sc["esc_n"]
+    assert int(res.escape_hist_n[-1]) > 0                       # the overflow bin is in use
+    half = pm.run(d, opt, n // 2, SEED, fp64=fp64, escape_bins=(width, nbins))
+    pm.run(d, opt, n - n // 2, SEED, photon_begin=n // 2, fp64=fp64, accumulate=half, escape_bins=(width, nbins))
+    assert torch.equal(half.escape_hist_w, res.escape_hist_w) and torch.equal(half.escape_hist_n, res.escape_hist_n)
+    assert torch.equal(half.fluence, res.fluence)
+
+
 def test_bright_colocalization(mask_m1):
     banner("brightest-decile co-localisation per slice vs oracle")
     d = dev(mask_m1)
