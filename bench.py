@@ -384,7 +384,8 @@ def analytics_leg(args, seed, mask_np, mask):
     histograms on all three axes, the pore distance transform, the brightest-decile
     co-localisation and the pore-phase Spearman correlation on deep slices
     (z >= 0.1 mm = slice 69 at 1.45 um voxels), the mask's radial PSD, the
-    depth-normalised phase contrast, and escape-path histograms of 1e7 traced photons.  Each call timed with events on
+    depth-normalised phase contrast, and escape-path histograms: kept by the run's own walk
+    over all its photons, and from 1e7 traced photons.  Each call timed with events on
     torch's current stream (the one the bindings launch on), warm (second call); the
     oracle's co-localisation and Spearman on the same tally as the CPU reference and
     parity check."""
@@ -402,7 +403,8 @@ def analytics_leg(args, seed, mask_np, mask):
     gate = pm.time_gate_voxels(o["mu_s"], o["mu_a"], o["g"], phi, nz, 1.746)
     opt = pm.paper_optics(o["mu_s"], o["mu_a"], o["g"], n_solid=f32(1.746), lateral=pm.LATERAL_MIRROR, gate=gate)
     n = args.photons
-    res = pm.run(mask, opt, n, seed)
+    esc_width, esc_bins = 4.0, 256
+    res = pm.run(mask, opt, n, seed, escape_bins=(esc_width, esc_bins), timed=True)
     _, depth, _ = pm.reduce_async(mask, res)
     F = res.fluence
     torch.cuda.synchronize()
@@ -462,7 +464,16 @@ def analytics_leg(args, seed, mask_np, mask):
                            "weight_fraction_void_path_gt_L": float(aw[0]) / esc_w if esc_w else None,
                            "weight_fraction_void_path_gt_L2": float(aw[1]) / esc_w if esc_w else None}
     del eh
+    # the same histogram over all n photons, kept by the walk that made the tally
+    hw = res.escape_hist_w.cpu().numpy().astype(np.float64)
+    esc_all = hw.sum()
+    lo_l, lo_l2 = int(nz / esc_width), int(0.5 * nz / esc_width)
+    out["escape_paths_run"] = {"photons": n, "walk_ms_with_histogram": res.walk_ms, "bin_width": esc_width,
+                               "nbins": esc_bins, "escaped_weight_fraction": esc_all / (n * pm.W1),
+                               "weight_fraction_void_path_ge_L": float(hw[lo_l:].sum() / esc_all) if esc_all else None,
+                               "weight_fraction_void_path_ge_L2": float(hw[lo_l2:].sum() / esc_all) if esc_all else None}
     log("analytics: " + ", ".join(f"{k} {v:.2f} ms" for k, v in out["ms"].items()))
+    log(f"analytics: walk with the escape histogram {res.walk_ms:.1f} ms for {n} photons")
     if not args.no_cpu:
         from oracle import analytics as oan
         Fn = F.cpu().numpy()
