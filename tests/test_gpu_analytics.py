@@ -162,7 +162,8 @@ def test_escape_paths(mask_m1):
 @pytest.mark.parametrize("model,fp64", [("plain", False), ("paper", False), ("plain", True)])
 def test_walk_escape_histogram_equals_traced_records(mask_m1, model, fp64):
     """mc_run_escape_histogram: the tallies are mc_run's bit for bit, and the histogram
-    is that of the same photons' traced records, bin for bin; halves accumulate to the whole."""
+    is that of the same photons' traced records, bin for bin, for every workgroup size;
+    halves accumulate to the whole."""
     banner(f"escape histogram kept by the walk ({model}, fp64={fp64}) vs traced records")
     opt = OPT if model == "plain" else pm.paper_optics(0.5, f32(0.01), f32(0.7), n_solid=f32(1.746),
                                                        lateral=pm.LATERAL_MIRROR, gate=400.0)
@@ -176,6 +177,9 @@ def test_walk_escape_histogram_equals_traced_records(mask_m1, model, fp64):
     sc = res.scalar_dict()
     assert int(res.escape_hist_w.sum()) == sc["esc_w"] and int(res.escape_hist_n.sum()) == sc["esc_n"]
     assert int(res.escape_hist_n[-1]) > 0                       # the overflow bin is in use
+    for tune in (pm.Tune(64, 8, 7, 1), pm.Tune(128, 16, 256, 16), pm.Tune(512, 16, 1024, 32)):
+        other = pm.run(d, opt, n, SEED, fp64=fp64, escape_bins=(width, nbins), tune=tune)
+        assert torch.equal(other.escape_hist_w, res.escape_hist_w) and torch.equal(other.fluence, res.fluence), tune
     half = pm.run(d, opt, n // 2, SEED, fp64=fp64, escape_bins=(width, nbins))
     pm.run(d, opt, n - n // 2, SEED, photon_begin=n // 2, fp64=fp64, accumulate=half, escape_bins=(width, nbins))
     assert torch.equal(half.escape_hist_w, res.escape_hist_w) and torch.equal(half.escape_hist_n, res.escape_hist_n)
