@@ -247,3 +247,14 @@ def test_escape_histogram_run_rejects_bad_arguments(lib):
     bad = pm.McOptics(0.5, 0.01, 1.0, 1e-4, 10, 0.0, 0, 0)
     assert lib.mc_run_escape_histogram(ctypes.byref(vol), ctypes.byref(bad), 0, 10, 1, 0, 0, 1, 1, 1, 1 << 30, None,
                                        1.0, 16, 1, 1, None) == -1 and b"|g|" in lib.mc_last_error()
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the HIP library the binding raises: there is no CPU fallback."""
+    import subprocess
+    import sys
+    code = ("from paper_2604_13929_amd import photonmc as pm\n"
+            f"pm.load({str(tmp_path / 'libphotonmc.so')!r})\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "is not built" in r.stderr and "no fallback" in r.stderr
