@@ -284,17 +284,18 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
     __shared__ unsigned long long acc[MC_NSCALARS];
     __shared__ uint32_t s_lidx[LOGGED ? kWaves * K * kLogStride : 1];
     __shared__ uint32_t s_lval[LOGGED ? kWaves * K * kLogStride : 1];
-    extern __shared__ unsigned long long s_grad[];  // GRAD: [3][2][nz]; ESC: weights [nbins], then counts
-    unsigned int *esc_n = reinterpret_cast<unsigned int *>(s_grad + (ESC ? eh.nbins : 0));
+    extern __shared__ unsigned long long s_dyn[];   // GRAD: bins [3][2][nz]; ESC: weights [nbins], then counts
+    unsigned long long *esc_w = s_dyn;
+    unsigned int *esc_n = reinterpret_cast<unsigned int *>(s_dyn + (ESC ? eh.nbins : 0));
     const uint32_t lane = __lane_id();
     uint32_t *lidx = s_lidx + (threadIdx.x >> 6) * (LOGGED ? K * kLogStride : 0);
     uint32_t *lval = s_lval + (threadIdx.x >> 6) * (LOGGED ? K * kLogStride : 0);
     if (threadIdx.x < MC_NSCALARS) acc[threadIdx.x] = 0ull;
     if (GRAD)
-        for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) s_grad[i] = 0ull;
+        for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) s_dyn[i] = 0ull;
     if (ESC)
         for (int32_t i = threadIdx.x; i < eh.nbins; i += BLOCK) {
-            s_grad[i] = 0ull;
+            esc_w[i] = 0ull;
             esc_n[i] = 0u;
         }
     if (LOGGED)
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
         sink.lval = lval;
     }
     if constexpr (GRAD) {
-        sink.bins = s_grad;
+        sink.bins = s_dyn;
         sink.nz = J.nz;
         sink.inv_mu_s = J.mu_s > 0.0 ? 1.0 / J.mu_s : 0.0;
     }
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
                 account(acc, p, ev, J.nz);
                 if (ESC && (ev == EV_ESC_R || ev == EV_ESC_T)) {
                     const int b = escape_path_bin(p.l_void, eh.width, eh.nbins);
-                    atomicAdd(&s_grad[b], (unsigned long long)p.w);
+                    atomicAdd(&esc_w[b], (unsigned long long)p.w);
                     atomicAdd(&esc_n[b], 1u);
                 }
                 alive = false;
@@ -372,13 +373,13 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
     if (ESC)
         for (int32_t i = threadIdx.x; i < eh.nbins; i += BLOCK)
             if (esc_n[i]) {
-                atomicAdd(&eh.w[i], s_grad[i]);
+                atomicAdd(&eh.w[i], esc_w[i]);
                 atomicAdd(&eh.n[i], (unsigned long long)esc_n[i]);
             }
     if (GRAD) {
         // signed block sums into (hi, lo) pairs: total = sum(hi) * 2^32 + sum(lo)
         for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) {
-            const long long v = (long long)s_grad[i];
+            const long long v = (long long)s_dyn[i];
             if (v) {
                 atomicAdd(&grad[2 * i], (unsigned long long)(v >> 32));
                 atomicAdd(&grad[2 * i + 1], (unsigned long long)v & 0xFFFFFFFFull);
