@@ -1,6 +1,6 @@
 /*
  * analytics.h -- C ABI of the morphology and fluence analytics of "Three-
- * dimensional photon transport in spinodal photocatalytic aerogels" (Sec. 3.4),
+ * dimensional photon transport in spinodal photocatalytic aerogels" (Sec. 3.5),
  * part of libphotonmc.so.  Conventions as in photonmc.h: caller-owned device
  * buffers, asynchronous on the given HIP stream, status 0 ok / < 0 error with
  * mc_last_error().  Volumes are mc_volume masks (1 = pore, 0 = solid).
@@ -17,13 +17,13 @@
 extern "C" {
 #endif
 
-/* Sec. 3.4 (a): chord-length histogram along one axis (0 = x, 1 = y, 2 = z; the
+/* Sec. 3.5 (a): chord-length histogram along one axis (0 = x, 1 = y, 2 = z; the
  * paper uses the beam axis z).  A chord is a maximal run of voxels of one phase on
  * a line; chords cut by the faces count with their in-volume length.
  *   hist  device int64[2][n_axis + 1]: hist[phase][len], phase 0 solid, 1 pore (written). */
 int mc_chord_histogram(const mc_volume *vol, int32_t axis, int64_t *hist, void *hip_stream);
 
-/* Sec. 3.4 (b): depth-normalised phase contrast from mc_reduce's depth[3][nz]
+/* Sec. 3.5 (b): depth-normalised phase contrast from mc_reduce's depth[3][nz]
  * (lateral mean, solid mean, pore mean per depth): c_solid(z) = solid / lateral
  * mean and c_pore(z) likewise over z0 <= z < nz, skipping depths whose lateral
  * mean is not positive or that lack the phase.
@@ -31,7 +31,7 @@ int mc_chord_histogram(const mc_volume *vol, int32_t axis, int64_t *hist, void *
  *        depths with a positive lateral mean. */
 int mc_phase_contrast(const double *depth, int32_t nz, int32_t z0, double *out, void *hip_stream);
 
-/* Sec. 3.4 (c): in-pore path of escaping photons (fate 4 or 5) from per-photon
+/* Sec. 3.5 (c): in-pore path of escaping photons (fate 4 or 5) from per-photon
  * outcome records (mc_trace with max_steps = 0): bin b of width bin_width holds
  * b * bin_width <= path < (b + 1) * bin_width, the last bin everything beyond.
  *   rec         device mc_photon_rec[n]
@@ -43,7 +43,7 @@ int mc_escape_path_histogram(const mc_photon_rec *rec, int64_t n, double bin_wid
                              const double *thresholds, int32_t nthr, int64_t *hist_w, int64_t *hist_n,
                              int64_t *above_w, int64_t *above_n, void *hip_stream);
 
-/* Sec. 3.4, co-localisation: for each slice z0 <= z < nz the k = ceil(frac * nx * ny)
+/* Sec. 3.5, co-localisation: for each slice z0 <= z < nz the k = ceil(frac * nx * ny)
  * voxels of highest fluence (ties to the lower linear index) and how many of them
  * are solid; 0 < frac <= 1, nx * ny < 2^31.
  *   fluence  device int64[nz][ny][nx] (mc_run's tally; any int64 values)
@@ -51,7 +51,7 @@ int mc_escape_path_histogram(const mc_photon_rec *rec, int64_t n, double bin_wid
 int mc_bright_colocalization(const mc_volume *vol, const int64_t *fluence, int32_t z0, double frac,
                              int64_t *top_count, int64_t *top_solid, void *hip_stream);
 
-/* Local pore size (Sec. 3.4, co-localisation): the exact Euclidean distance from
+/* Local pore size (Sec. 3.5, co-localisation): the exact Euclidean distance from
  * every pore voxel centre to the nearest solid voxel centre inside the volume (no
  * periodic images), 0 in the solid, +inf everywhere if there is no solid voxel.
  * Squared distances are 32-bit integers: needs nx^2 + ny^2 + nz^2 < 2^30 - 1 (an
@@ -61,7 +61,7 @@ size_t mc_pore_distance_workspace_bytes(const mc_volume *vol);
 int mc_pore_distance(const mc_volume *vol, double *dist, void *workspace, size_t workspace_bytes,
                      void *hip_stream);
 
-/* Sec. 3.4, co-localisation: Spearman rank correlation, per slice z0 <= z < nz, between
+/* Sec. 3.5, co-localisation: Spearman rank correlation, per slice z0 <= z < nz, between
  * the fluence and the local pore size (the distance of mc_pore_distance) over the
  * pore voxels of that slice.  Ties take the average of their ranks; rho is the
  * Pearson correlation of the two rank vectors, NaN where a slice has fewer than two
@@ -80,7 +80,7 @@ size_t mc_pore_spearman_workspace_bytes(const mc_volume *vol, int32_t z0);
 int mc_pore_spearman(const mc_volume *vol, const int64_t *fluence, int32_t z0, double *rho, int64_t *n_pore,
                      void *workspace, size_t workspace_bytes, void *hip_stream);
 
-/* Sec. 3.2, Fig. 2b: radial power spectral density of the binary mask itself
+/* Sec. 3.1, Fig. 2b: radial power spectral density of the binary mask itself
  * (values 0 and 1), with the shells and conventions of mc_ch_psd (spinodal.h):
  * psd[s], s = 0 .. max(nx,ny,nz)/2, sums |m_hat_k|^2 of the unnormalised forward
  * transform over s - 1/2 <= |k| max(nx,ny,nz) / (2 pi) < s + 1/2, the k = 0 mode

@@ -13,7 +13,7 @@
  *   - Sec. 2.6 (Fluence estimators): solid-weighted <Phi>_3D (Eq. Phi_MC3D),
  *     volume average <Phi>_1D (Eq. Phi_MC1D), pore average and the contrast
  *     ratio r (Eq. r_def), and the identity of Eq. dilution;
- *   - Sec. 2.8 (c): in-pore path length of every escaping photon.
+ *   - Sec. 3.5 (c): in-pore path length of every escaping photon.
  * Two boundary models (mc_optics.boundary):
  *   - MC_BOUNDARY_PLAIN: lateral faces periodic, refractive index 1 everywhere,
  *     photons start on the z = 0 face and escape when they cross z = 0 or z = Nz;
@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define MC_ABI_VERSION 2
+#define MC_ABI_VERSION 3
 
 /* status codes */
 #define MC_OK 0
@@ -117,7 +117,8 @@ enum {
     MC_Q_MEAN_VOID_PATH,   /* escaped-weight-weighted mean in-pore path, voxels */
     MC_Q_STEPS_PER_PHOTON,
     MC_Q_INTERACTIONS_PER_PHOTON,
-    MC_Q_STATUS,           /* 0, or MC_EOVERFLOW if a voxel tally reached 2^62 */
+    MC_Q_STATUS,           /* MC_EOVERFLOW if a voxel tally reached 2^62, else MC_WARN_LOST if weight
+                              was stopped by the step / path cap (scalar MC_S_LOST > 0), else 0 */
     MC_Q_N_SOLID,          /* solid voxel count */
     MC_Q_LAUNCHED,         /* photons the tallies hold */
     MC_Q_GATED,            /* weight fraction stopped by the time gate */
@@ -165,6 +166,8 @@ typedef struct {
     int32_t waves_per_cu;  /* resident waves per compute unit the grid is sized for */
     int32_t chunk;         /* photons a wavefront takes from the queue at once */
     int32_t refill;        /* refill a wavefront once this many of its lanes are idle */
+    int32_t defer;         /* run a wavefront's interactions once this many of its lanes wait at an
+                              interaction point (or no lane can advance); 1: at once; at most 64 */
 } mc_tune;
 
 /* Fill *t with the library defaults. */
@@ -192,7 +195,7 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
 
 /*
  * mc_run that also histograms the in-pore path of every escaping photon (fate R
- * or T) of the run (Sec. 3.4 (c)), with the bins of mc_escape_path_histogram
+ * or T) of the run (Sec. 3.5 (c)), with the bins of mc_escape_path_histogram
  * (analytics.h): bin b holds b * bin_width <= path < (b + 1) * bin_width, the
  * last bin everything beyond.  The tallies are those of mc_run with the same
  * arguments, bit for bit.
@@ -220,8 +223,12 @@ size_t mc_reduce_workspace_bytes(const mc_volume *vol);
  *   summary  device double[MC_NSUMMARY]
  *   depth    device double[3][nz]: Phi/S0 lateral mean, solid mean, pore mean per
  *            depth (NaN where a layer has no voxel of that phase); may be NULL
- * The photon count is the tallies' own MC_S_LAUNCHED.  A voxel tally >= 2^62
- * sets summary[MC_Q_STATUS] = MC_EOVERFLOW.
+ * The photon count is the tallies' own MC_S_LAUNCHED.  The outcome of the run is
+ * known only on the device, so the reduction writes it to summary[MC_Q_STATUS]:
+ * MC_EOVERFLOW when a voxel tally reached 2^62 (the estimators are then invalid),
+ * otherwise MC_WARN_LOST when weight was stopped by the step or path cap (the
+ * estimators then miss that weight's further path), otherwise MC_OK.  The return
+ * value covers only the arguments and the launch.
  */
 int mc_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scalars, double *summary,
               double *depth, void *workspace, size_t workspace_bytes, void *hip_stream);
@@ -294,17 +301,21 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
              mc_photon_rec *outcome, void *workspace, size_t workspace_bytes, void *hip_stream);
 
 /*
- * Roofline probe (measurement only, not part of the walk): n_ops random 64-bit
- * scatter operations over a device table of n_entries int64 (a power of two),
- * spread over 16 waves per compute unit.  mode 0: device-scope atomic add (what
- * the walk's fluence deposit does); 1: workgroup-scope atomic add; 2: plain
- * store; 3: device-scope 32-bit atomic add; 4: device-scope atomic add with the
- * 64 lanes of a wavefront on 64 consecutive entries; 5, 6, 7: device-scope atomic
- * add with groups of 16, 8, 4 lanes on 16, 8, 4 consecutive entries of a random
- * aligned block (128, 64, 32 bytes).  The table's contents afterwards are
- * meaningless.
+ * Roofline probe (measurement only, not part of the walk): n_ops random scatter
+ * operations over a device table of n_entries int64 (a power of two, >= 64), spread
+ * over waves_per_cu resident waves per compute unit (0: 16; else a multiple of 4 in
+ * [4, 32]).  mode 0: device-scope 64-bit atomic add (what the walk's fluence
+ * deposit does); 1: workgroup-scope 64-bit atomic add; 2: plain 64-bit store;
+ * 3: device-scope 32-bit atomic add; 4: 64-bit atomic add with the 64 lanes of a
+ * wavefront on 64 consecutive entries; 5, 6, 7: 64-bit atomic add with groups of
+ * 16, 8, 4 lanes on 16, 8, 4 consecutive entries of a random aligned block (128, 64,
+ * 32 bytes); 8: mode 0 returning the old value; 9: mode 3 returning the old value;
+ * 10, 11: 32-bit atomic add with groups of 16 lanes on the 16 words of a random
+ * 64-byte line, without / with the old value returned; 12: mode 6 returning the old
+ * value.  The table's contents afterwards are meaningless.
  */
-int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mode, void *hip_stream);
+int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mode, int waves_per_cu,
+                     void *hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Batched runs: many volumes of uneven size, porosity and optics in one
@@ -362,6 +373,62 @@ int mc_batch_graph_create(const mc_job *jobs, int32_t n_jobs, int flags, const m
                           size_t workspace_bytes, mc_graph *out);
 int mc_graph_launch(mc_graph graph, void *hip_stream);
 int mc_graph_destroy(mc_graph graph);
+
+/* ---------------------------------------------------------------------------
+ * The paper's reference model and comparison metrics.  The host functions take
+ * host pointers and return at once; mc_rms_w is a kernel on the stream.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Time gate of Eq. tend (Sec. 2.5, "Photon budget, time gate and statistics"):
+ *   t_end = max(5 n_eff / (mu_a c), 6 L^2 / D_phys),
+ *   D_phys = (c / n_eff) / (3 (mu_a,eff + mu_s,eff')),
+ * with the effective-medium scaling of Eq. EMA_scaling, mu_eff = (1 - porosity) mu,
+ * and the reduced scattering coefficient mu_s' = mu_s (1 - g).
+ *   mu_s, mu_a  solid (shell) coefficients per unit length, >= 0;  |g| < 1
+ *   porosity    in [0, 1];  thickness L > 0 in the same length unit
+ *   n_eff >= 1; c > 0, the speed of light in length per time unit
+ *   t_end       host double: the gate in time units, +inf when mu_a = 0 (the first
+ *               term is then unbounded).  With c = 1 and voxel units it is c t_end
+ *               in voxels, the optical path limit that mc_optics.gate takes.
+ * Host function.  Errors: MC_EINVAL for a NULL pointer or an argument out of range.
+ */
+int mc_time_gate(double mu_s, double mu_a, double g, double porosity, double thickness, double n_eff, double c,
+                 double *t_end);
+
+/*
+ * Collimated-source diffusion approximation (Sec. 2.4: Eq. DA_total with the
+ * particular solution of Eq. DA_diff_eq, the constants of Eq. Cpm for the
+ * extrapolated boundaries Phi_diff(-z_b) = Phi_diff(L + z_b) = 0, Eq. Phi_diff, and
+ * Eq. Lopt_DA) on a slab of nz voxel layers, in voxel units with S0 = 1:
+ *   effective coefficients (Eq. EMA_scaling)  mu_a,eff = (1 - porosity) mu_a,
+ *   mu_s,eff' = (1 - porosity) mu_s (1 - g);  D = 1 / (3 (mu_a,eff + mu_s,eff')),
+ *   kappa = sqrt(mu_a,eff / D), mu_t = mu_a,eff + mu_s,eff', z_b = (2/3) / mu_s,eff',
+ *   L = nz.
+ *   profile  host double[nz] or NULL: the mean of Phi_DA / S0 over depth [z, z + 1)
+ *            of layer z (each term of Eq. DA_total integrated in closed form), the
+ *            quantity a depth profile of mc_reduce estimates
+ *   l_opt    host double or NULL: L_opt of Eq. Lopt_DA in voxels, the integral over
+ *            [0, L], i.e. the sum of the profile (so <Phi>_DA / S0 = l_opt / nz)
+ * Host function.  Errors: MC_EINVAL for nz < 1, |g| >= 1, porosity outside [0, 1),
+ * effective coefficients that are not finite and > 0, kappa = mu_t (the particular
+ * solution is degenerate), kappa (L + 2 z_b) > 700 (sinh overflows), or both
+ * outputs NULL.
+ */
+int mc_da_profile(double mu_s, double mu_a, double g, double porosity, int32_t nz, double *profile, double *l_opt);
+
+/*
+ * Discrepancy between a depth profile p and a reference q (Sec. 2.7, Eq. RMSw, and
+ * the two variants of App. B / Table S1), over the depths where q is finite and
+ * positive and p is finite:
+ *   out[0]  RMS_w = [sum_z q (p - q)^2 / q^2 / sum_z q]^(1/2)      (Eq. RMSw)
+ *   out[1]  unweighted: [mean_z ((p - q) / q)^2]^(1/2)
+ *   out[2]  log-ratio: [mean_z ln(p / q)^2]^(1/2), over those depths where p > 0 too
+ * profile, reference  device double[n], n >= 1;  out  device double[3] (NaN where
+ * no depth qualifies).  Fractions, not percent.  Sums in a fixed order: the result
+ * is reproducible.  Errors: MC_EINVAL (NULL argument, n < 1), MC_EHIP.
+ */
+int mc_rms_w(const double *profile, const double *reference, int32_t n, double *out, void *hip_stream);
 
 /* Text for a status code. */
 const char *mc_strerror(int status);

@@ -3,7 +3,7 @@
  * generator, part of libphotonmc.so.
  *
  * It integrates the Cahn-Hilliard equation of "Three-dimensional photon
- * transport in spinodal photocatalytic aerogels" (Sec. 2.3, Eq. CH) with the
+ * transport in spinodal photocatalytic aerogels" (Sec. 2.2, Eq. CH) with the
  * double well f(phi) = phi^2 (1 - phi)^2 and unit mobility by the semi-implicit
  * Fourier spectral step of Eq. CH_spectral,
  *     phihat^{n+1}_k = (phihat^n_k - dt k^2 [f'(phi^n)]^_k) / (1 + dt kappa k^4),
@@ -40,6 +40,23 @@ typedef struct {
     double kappa;          /* gradient coefficient kappa_CH, voxel units (Eq. kappa_cal), > 0 */
     double dt;             /* time step, dimensionless CH units (App. A), > 0 */
 } mc_ch_grid;
+
+/* The grid constants for a target dominant size d_target (voxels, > 0):
+ * kappa_CH = (1/2) (d_target / (8 pi))^2 (Eq. kappa_cal) and the time step of App. A,
+ * dt = min(0.5 / (kappa_CH k_max^4), 1) with k_max = pi per voxel.  Writes g->kappa
+ * and g->dt of a host struct (the extents are left as they are).  Host function.
+ * MC_EINVAL for a NULL grid or a d_target that is not finite and > 0. */
+int mc_ch_grid_from_target(double d_target, mc_ch_grid *g);
+
+/* App. A's dominant structural size from a radial PSD (mc_ch_psd, or mc_mask_psd of
+ * analytics.h): the peak shell s_peak, the first s >= 1 holding the largest psd[s]
+ * (shell 0 is the mean, excluded), and size = n_max / (2 s_peak) voxels, half the
+ * peak wavelength (one pore and one strut per period).
+ *   psd         device double[n_bins], n_bins >= 2;  n_max = max(nx, ny, nz) >= 1
+ *   peak_shell  device int32 or NULL;  size  device double or NULL (not both NULL)
+ * Asynchronous on the stream.  MC_EINVAL, MC_EHIP. */
+int mc_psd_peak(const double *psd, int32_t n_bins, int32_t n_max, int32_t *peak_shell, double *size,
+                void *hip_stream);
 
 /* Device workspace of the mc_ch_* calls: one spectrum-sized work array plus
  * transform tables and reduction space.  0 when the grid is invalid. */

@@ -149,7 +149,7 @@ def run(mask, mu_s, mu_a, g, n_photons, seed, photon_begin=0, stream_id=0, nthre
     P, m = make_problem(mask, mu_s, mu_a, g, seed, stream_id, **kw)
     nz, ny, nx = m.shape
     if nthreads is None:
-        nthreads = os.cpu_count() or 1
+        nthreads = len(os.sched_getaffinity(0)) or 1
     out = {}
     F = np.zeros((nbatch, nz, ny, nx), dtype=np.float64) if fluence else None
     G = np.zeros((nbatch, 3, 2, nz), dtype=np.float64) if grad else None

@@ -1,10 +1,10 @@
-"""FP64 / integer oracle of the morphology and fluence analytics of Sec. 3.4.
+"""FP64 / integer oracle of the morphology and fluence analytics of Sec. 3.5.
 
 TEST INFRASTRUCTURE ONLY: the tests and the benchmark's CPU baseline use it; the
 product library never imports it and it never imports the product.
 
 What it follows (paper: "Three-dimensional photon transport in spinodal
-photocatalytic aerogels", Sec. 3.4):
+photocatalytic aerogels", Sec. 3.5):
   (a) chord-length distributions of the binary mask along a chosen axis (the beam
       axis z in the paper): every maximal run of consecutive voxels of one phase on
       a line is a chord; mean chords and length-weighted tail fractions
@@ -18,7 +18,7 @@ photocatalytic aerogels", Sec. 3.4):
       fluence and the fraction of it that is solid; the local pore size by a
       Euclidean distance transform of the pore phase, and, inside the pore phase of
       each deep slice, the Spearman rank correlation of fluence with that size;
-  and (Sec. 3.2, Fig. 2b) the radial power spectral density of the binary mask.
+  and (Sec. 3.1, Fig. 2b) the radial power spectral density of the binary mask.
 Readings where the paper is silent (listed with their reasons in the design
 notes): chords cut by the slab faces count with their in-slab length; the
 brightest decile of a slice is its ceil(0.1 N) voxels of highest fluence with

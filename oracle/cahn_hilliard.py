@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: the tests and the benchmark's CPU baseline use it; the
 product library never imports it and it never imports the product.
 
 What it follows (paper: "Three-dimensional photon transport in spinodal
-photocatalytic aerogels", Sec. 2.3 and App. A):
+photocatalytic aerogels", Sec. 2.2 and App. A):
   - Eq. CH with the double well f(phi) = phi^2 (1 - phi)^2, mobility M = 1;
   - Eq. CH_spectral, the semi-implicit Fourier spectral step
         phihat^{n+1}_k = (phihat^n_k - dt k^2 [f'(phi^n)]^_k) / (1 + dt kappa k^4),

@@ -14,7 +14,8 @@ from the definitions:
 * phase-resolved depth profiles as in App. B (Post-processing) and Fig. 4b;
 * front/back ratio Phi(0)/Phi(L) as in Table S2, and L_opt = <Phi>_1D L / S0 as
   in the caption of Table 4;
-* the fluence-weighted relative RMS deviation of Sec. 2.7, Eq. RMSw.
+* the fluence-weighted relative RMS deviation of Sec. 2.7, Eq. RMSw, and the
+  unweighted and log-ratio variants reported beside it in Table S1 (App. B).
 """
 from __future__ import annotations
 
@@ -58,14 +59,30 @@ def estimators(F: np.ndarray, mask: np.ndarray, n_photons: int) -> dict:
     return out
 
 
-def rms_w(profile: np.ndarray, reference: np.ndarray) -> float:
-    """Eq. RMSw with the reference profile as weights and denominator."""
+def _rms_depths(profile, reference):
+    """The depths a relative deviation is defined at: reference finite and positive,
+    profile finite (reading of the sums over z in Eq. RMSw)."""
     p = np.asarray(profile, dtype=np.float64)
     q = np.asarray(reference, dtype=np.float64)
+    ok = np.isfinite(q) & (q > 0) & np.isfinite(p)
+    return p[ok], q[ok]
+
+
+def rms_w(profile: np.ndarray, reference: np.ndarray) -> float:
+    """Eq. RMSw with the reference profile as weights and denominator."""
+    p, q = _rms_depths(profile, reference)
     return float(np.sqrt((q * (p - q) ** 2 / q ** 2).sum() / q.sum()))
 
 
 def rms_unweighted(profile: np.ndarray, reference: np.ndarray) -> float:
-    p = np.asarray(profile, dtype=np.float64)
-    q = np.asarray(reference, dtype=np.float64)
+    """Table S1's unweighted variant: the weights of Eq. RMSw set to one."""
+    p, q = _rms_depths(profile, reference)
     return float(np.sqrt((((p - q) / q) ** 2).mean()))
+
+
+def rms_log(profile: np.ndarray, reference: np.ndarray) -> float:
+    """Table S1's log variant: the RMS of ln(Phi_MC / Phi_DA), over the depths where
+    the profile is positive too."""
+    p, q = _rms_depths(profile, reference)
+    ok = p > 0
+    return float(np.sqrt((np.log(p[ok] / q[ok]) ** 2).mean()))

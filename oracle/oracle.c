@@ -18,7 +18,7 @@
  *     from the escape records, so R + T + A = 1 is a measurement (Eq. RTA,
  *     Eq. closure).
  *   - App. B (Monte Carlo solver configuration): source, tallies, fixed seed.
- *   - Sec. 2.8 / Fig. 4c (per-photon path statistics): cumulative in-pore path
+ *   - Sec. 3.5 (c) / Fig. 4c (per-photon path statistics): cumulative in-pore path
  *     of every escaping photon, and the weight fraction whose in-pore path
  *     exceeds the slab thickness L.
  *
@@ -344,7 +344,11 @@ static int step(const orc_problem *P, uint64_t photon, orc_state *st, orc_sink *
             double ga = fabs(dist[a] - d_face);
             if (ga < gap) gap = ga;
         }
-    /* time gate: the optical path may reach, not pass, the gate */
+    /* Time gate of Eq. tend.  A photon's time of flight is its optical path over
+     * c, t = sum(n_i d_i) / c (light moves at c/n in a medium of index n), so the
+     * condition t <= t_end reads sum(n d) <= c t_end = gate, written here on the
+     * optical path after this segment.  Reading: the photon may reach the gate
+     * but not pass it; the segment that would pass it is cut where t = t_end. */
     int gated = 0;
     if (paper && isfinite(P->gate)) {
         const double gg = fabs(st->l_opt + n_here * d - P->gate) / n_here;

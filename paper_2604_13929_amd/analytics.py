@@ -41,7 +41,7 @@ def phase_contrast(depth: torch.Tensor, z0: int = 0) -> dict:
 
 def escape_paths(mask: torch.Tensor, optics: pm.Optics, n_photons: int, seed: int, bin_width: float, nbins: int,
                  thresholds=(), photon_begin: int = 0, stream_id: int = 0, fp64: bool = False) -> dict:
-    """Sec. 3.4 (c): per-photon outcomes of photons [begin, begin + n) (mc_trace with no
+    """Sec. 3.5 (c): per-photon outcomes of photons [begin, begin + n) (mc_trace with no
     step records, on the device) binned by the in-pore path of the escaping ones."""
     L = pm.load()
     vol = pm.volume(mask)

@@ -1,4 +1,4 @@
-// analytics.hip -- morphology and fluence analytics of Sec. 3.4: chord-length
+// analytics.hip -- morphology and fluence analytics of Sec. 3.5: chord-length
 // histograms, depth-normalised phase contrast, escape-path histograms, the
 // brightest-decile co-localisation per slice, the exact Euclidean distance
 // transform of the pore phase, and the per-slice Spearman correlation of fluence

@@ -139,14 +139,15 @@ __device__ __forceinline__ void account_job(unsigned long long *acc, const Photo
 }
 
 // Same queue discipline as the plain walk: a wavefront-private range of queue
-// positions refilled by one atomic, idle lanes refilled together, exit once
-// the queue is exhausted and no lane is alive.
+// positions refilled by one atomic, idle lanes refilled together, interactions
+// run together once `defer` lanes wait at one (or no lane can advance), exit
+// once the queue is exhausted and no lane is alive.
 // LOGGED: every job's fluence pointer is its bricked tally.  GENERAL: some job
 // uses the paper's boundary model (each job's own flags select its physics).
 template <int BLOCK, typename R, bool LOGGED, bool GENERAL>
 __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jobs, int32_t n_jobs,
                                                       unsigned long long *__restrict__ queue, int32_t chunk,
-                                                      int32_t refill)
+                                                      int32_t refill, int32_t defer)
 {
     constexpr int kWaves = BLOCK / 64;
     __shared__ Job s_jobs[MC_MAX_BATCH_JOBS];
@@ -177,6 +178,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
     Photon<R> p;
     int32_t job = 0;
     bool alive = false;
+    bool waiting = false;   // alive, at an interaction point, interaction not yet run
     uint64_t q_next = 0, q_end = 0;
     bool exhausted = false;
     uint32_t iter = 0;
@@ -218,16 +220,35 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
             }
             if (exhausted && q_next >= q_end && !__any(alive)) break;
         }
-        if (alive) {
+        // this iteration's log slot: a lane flushes at most once per iteration
+        if constexpr (LOGGED) {
+            sink.slot = (iter % kBLogK) * kBLogStride + lane;
+            sink.tag = (uint32_t)job << kJobShift;
+        }
+        if (alive && !waiting) {
             const Job &J = s_jobs[job];
-            if constexpr (LOGGED) {
-                sink.slot = (iter % kBLogK) * kBLogStride + lane;
-                sink.tag = (uint32_t)job << kJobShift;
+            const int32_t ev = advance<GENERAL>(p, J, sink);
+            if (ev == EV_AT_INTERACTION) {
+                waiting = true;
+            } else {
+                const int32_t fin = finish(p, J, sink, ev);
+                if (is_terminal(fin)) {
+                    account_job(acc[job], p, fin, J.nz);
+                    alive = false;
+                }
             }
-            const int32_t ev = step<GENERAL>(p, J, sink);
-            if (is_terminal(ev)) {
-                account_job(acc[job], p, ev, J.nz);
-                alive = false;
+        }
+        const uint64_t wait_mask = __ballot(waiting);
+        if (wait_mask != 0ull &&
+            (__popcll(wait_mask) >= defer || __ballot(alive && !waiting) == 0ull)) {
+            if (waiting) {
+                const Job &J = s_jobs[job];
+                const int32_t fin = finish(p, J, sink, interact(p, J, sink));
+                waiting = false;
+                if (is_terminal(fin)) {
+                    account_job(acc[job], p, fin, J.nz);
+                    alive = false;
+                }
             }
         }
         if constexpr (LOGGED) {
@@ -336,19 +357,19 @@ void enqueue_batch_walk(int block, int blocks, const Job *table, int32_t n, unsi
     switch (block) {
     case 64:
         hipLaunchKernelGGL((k_walk_batch<64, R, LOGGED, GENERAL>), dim3(blocks), dim3(64), 0, s, table, n, queue, t.chunk,
-                           t.refill);
+                           t.refill, t.defer);
         break;
     case 128:
         hipLaunchKernelGGL((k_walk_batch<128, R, LOGGED, GENERAL>), dim3(blocks), dim3(128), 0, s, table, n, queue, t.chunk,
-                           t.refill);
+                           t.refill, t.defer);
         break;
     case 256:
         hipLaunchKernelGGL((k_walk_batch<256, R, LOGGED, GENERAL>), dim3(blocks), dim3(256), 0, s, table, n, queue, t.chunk,
-                           t.refill);
+                           t.refill, t.defer);
         break;
     default:
         hipLaunchKernelGGL((k_walk_batch<512, R, LOGGED, GENERAL>), dim3(blocks), dim3(512), 0, s, table, n, queue, t.chunk,
-                           t.refill);
+                           t.refill, t.defer);
         break;
     }
 }
@@ -439,8 +460,8 @@ int enqueue_batch(const mc_job *jobs, const Prepared &P, char *ws, const mc_tune
 }
 
 // ---------------------------------------------------------------------------
-// Autotuner: coordinate descent over waves per CU, block size, chunk and
-// refill threshold, each trial a timed walk over a scaled-down copy of the
+// Autotuner: coordinate descent over waves per CU, block size, chunk, refill
+// threshold and interaction deferral, each trial a timed walk over a scaled-down copy of the
 // batch (every job keeps at least one photon).  Results never depend on the
 // launch shape, so tuning only changes speed.
 // ---------------------------------------------------------------------------
@@ -469,7 +490,8 @@ bool cache_get(const std::string &key, mc_tune *t)
     while (fgets(line, sizeof line, f)) {
         char k[400];
         mc_tune r;
-        if (sscanf(line, "%399s %d %d %d %d", k, &r.block, &r.waves_per_cu, &r.chunk, &r.refill) == 5 && key == k &&
+        if (sscanf(line, "%399s %d %d %d %d %d", k, &r.block, &r.waves_per_cu, &r.chunk, &r.refill, &r.defer) == 6 &&
+            key == k &&
             check_tune(r) == MC_OK) {
             *t = r;  // the last entry for a key wins
             found = true;
@@ -486,7 +508,7 @@ void cache_put(const std::string &key, const mc_tune &t)
     if (path.empty()) return;
     FILE *f = fopen(path.c_str(), "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d\n", key.c_str(), t.block, t.waves_per_cu, t.chunk, t.refill);
+    fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), t.block, t.waves_per_cu, t.chunk, t.refill, t.defer);
     fclose(f);
 }
 
@@ -565,6 +587,11 @@ int tune_descent(const std::function<int(const mc_tune &)> &enqueue, hipStream_t
     for (int rf : {1, 8, 16, 32, 48}) {
         mc_tune c = best;
         c.refill = rf;
+        if ((rc = consider(c))) return rc;
+    }
+    for (int df : {1, 8, 16, 24, 32, 40, 48}) {
+        mc_tune c = best;
+        c.defer = df;
         if ((rc = consider(c))) return rc;
     }
     clear_error();

@@ -6,6 +6,8 @@
 #include "photonmc.h"
 #include "walk.hpp"
 
+struct EscHist;  // the escape-path histogram of a walk (photonmc.hip)
+
 namespace pmc {
 namespace host {
 
@@ -47,6 +49,10 @@ int check_tune(const mc_tune &t);
 int fill(int64_t *p, uint64_t n, hipStream_t s);
 int pack(const mc_volume *vol, uint64_t *bricks, hipStream_t s);
 int unbrick(const int64_t *tally, int64_t *fluence, const mc_volume *vol, bool accumulate, hipStream_t s);
+// zero (unless accumulating), pack, walk and move the staged tally into the caller's
+// fluence, with the queue, packed mask and staging tally in the workspace ws
+int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws, unsigned long long *grad_bins,
+             hipStream_t s, const EscHist *esc = nullptr);
 int enqueue_reduce(const mc_volume *vol, const int64_t *fluence, const int64_t *scalars, double *summary,
                    double *depth, unsigned long long *bins, hipStream_t s);
 

@@ -248,7 +248,7 @@ __device__ __forceinline__ void account(unsigned long long *acc, const Photon<R>
     atomicAdd(&acc[MC_S_LAUNCHED], 1ull);
 }
 
-// In-pore path histogram of the escaping photons of a walk (Sec. 3.4 (c)), kept
+// In-pore path histogram of the escaping photons of a walk (Sec. 3.5 (c)), kept
 // per workgroup in LDS (weights 64-bit, counts 32-bit) and added to w and n once.
 struct EscHist {
     unsigned long long *w;    // [nbins] escaped Q31 weight
@@ -264,9 +264,14 @@ constexpr int kEscMaxBins = 512;  // 6 KB of LDS: four walk workgroups still fit
 // Each wavefront owns a private range [q_next, q_end) of queue positions and
 // takes `chunk` more with one atomic when it runs dry.  Idle lanes are refilled
 // together once at least `refill` of them are idle (or all are), so launches
-// run converged.  A wavefront exits when the queue is exhausted, its range is
-// empty and none of its lanes is alive; every photon terminates (escape,
-// weight 0, roulette, or the step cap), so every wavefront exits.
+// run converged.  A lane whose segment ends at an interaction point waits there
+// until `defer` lanes of its wavefront wait (or no lane can advance); then the
+// waiting lanes run their interactions together, so that code runs with many
+// lanes active instead of a few in every iteration.  A photon's own sequence of
+// steps is the same either way.  A wavefront exits when the queue is exhausted,
+// its range is empty and none of its lanes is alive; every photon terminates
+// (escape, weight 0, roulette, or the step cap), and a waiting lane is served
+// at the latest once no lane can advance, so every wavefront exits.
 template <bool GRAD, bool LOGGED> struct SinkOf {
     using Deposit = typename std::conditional<LOGGED, LoggedDeposit, DirectDeposit>::type;
     using type = typename std::conditional<GRAD, GradSink<Deposit>, TallySink<Deposit>>::type;
@@ -277,7 +282,8 @@ template <bool GRAD, bool LOGGED> struct SinkOf {
 // ESC: also bin the in-pore path of every escaping photon (EscHist).
 template <int BLOCK, typename R, bool GRAD, bool LOGGED, bool GENERAL, bool ESC>
 __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long *__restrict__ queue, int32_t chunk,
-                                                int32_t refill, unsigned long long *__restrict__ grad, const EscHist eh)
+                                                int32_t refill, int32_t defer, unsigned long long *__restrict__ grad,
+                                                const EscHist eh)
 {
     constexpr int kWaves = BLOCK / 64;
     constexpr int K = GRAD ? 16 : kLogK;   // log window (the gradient bins share the LDS)
@@ -314,10 +320,21 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
     }
     Photon<R> p;
     bool alive = false;
+    bool waiting = false;   // alive, at an interaction point, interaction not yet run
     uint64_t q_next = 0, q_end = 0;
     bool exhausted = false;
     const uint64_t total = J.n_photons;
     uint32_t iter = 0;
+
+    auto retire = [&](int32_t ev) {
+        account(acc, p, ev, J.nz);
+        if (ESC && (ev == EV_ESC_R || ev == EV_ESC_T)) {
+            const int b = escape_path_bin(p.l_void, eh.width, eh.nbins);
+            atomicAdd(&esc_w[b], (unsigned long long)p.w);
+            atomicAdd(&esc_n[b], 1u);
+        }
+        alive = false;
+    };
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -347,17 +364,25 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
             }
             if (exhausted && q_next >= q_end && !__any(alive)) break;
         }
-        if (alive) {
-            if constexpr (LOGGED) sink.slot = (iter % K) * kLogStride + lane;
-            const int32_t ev = step<GENERAL>(p, J, sink);
-            if (is_terminal(ev)) {
-                account(acc, p, ev, J.nz);
-                if (ESC && (ev == EV_ESC_R || ev == EV_ESC_T)) {
-                    const int b = escape_path_bin(p.l_void, eh.width, eh.nbins);
-                    atomicAdd(&esc_w[b], (unsigned long long)p.w);
-                    atomicAdd(&esc_n[b], 1u);
-                }
-                alive = false;
+        // this iteration's log slot: a lane flushes at most once per iteration (an
+        // advance that reaches an interaction point flushes nothing)
+        if constexpr (LOGGED) sink.slot = (iter % K) * kLogStride + lane;
+        if (alive && !waiting) {
+            const int32_t ev = advance<GENERAL>(p, J, sink);
+            if (ev == EV_AT_INTERACTION) {
+                waiting = true;
+            } else {
+                const int32_t fin = finish(p, J, sink, ev);
+                if (is_terminal(fin)) retire(fin);
+            }
+        }
+        const uint64_t wait_mask = __ballot(waiting);
+        if (wait_mask != 0ull &&
+            (__popcll(wait_mask) >= defer || __ballot(alive && !waiting) == 0ull)) {
+            if (waiting) {
+                const int32_t fin = finish(p, J, sink, interact(p, J, sink));
+                waiting = false;
+                if (is_terminal(fin)) retire(fin);
             }
         }
         if constexpr (LOGGED) {
@@ -570,7 +595,9 @@ __global__ void k_finalize(const unsigned long long *__restrict__ bins, const in
     q[MC_Q_MEAN_VOID_PATH] = S[MC_S_ESC_W] ? void_path / (double)S[MC_S_ESC_W] : nan;
     q[MC_Q_STEPS_PER_PHOTON] = (double)S[MC_S_STEPS] / n_ph;
     q[MC_Q_INTERACTIONS_PER_PHOTON] = (double)S[MC_S_INTERACTIONS] / n_ph;
-    q[MC_Q_STATUS] = mx >= (1ull << 62) ? (double)MC_EOVERFLOW : 0.0;
+    // an overflowing voxel tally makes the run invalid; weight stopped by the step or
+    // path cap leaves it valid but incomplete
+    q[MC_Q_STATUS] = mx >= (1ull << 62) ? (double)MC_EOVERFLOW : (S[MC_S_LOST] > 0 ? (double)MC_WARN_LOST : 0.0);
     q[MC_Q_N_SOLID] = (double)n_s;
     q[MC_Q_LAUNCHED] = n_ph;
     q[MC_Q_GATED] = (double)S[MC_S_GATED] / launched_w;
@@ -628,6 +655,7 @@ __global__ __launch_bounds__(256) void k_probe(unsigned long long *__restrict__ 
 {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t wave = t >> 6, lane = t & 63;
+    unsigned long long sink = 0;   // the returning modes use what the atomics return
     for (uint64_t i = 0; i < per_thread; ++i) {
         const uint64_t a = mix64(t * per_thread + i) & mask;
         if (MODE == 0) {
@@ -644,14 +672,36 @@ __global__ __launch_bounds__(256) void k_probe(unsigned long long *__restrict__ 
             // the 64 lanes of a wavefront hit 64 consecutive slots of one random block
             const uint64_t blk = mix64(wave * per_thread + i) & (mask & ~63ull);
             __hip_atomic_fetch_add(table + blk + lane, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        } else if (MODE >= 5 && MODE <= 7) {
             // groups of G lanes hit G consecutive slots (G * 8 bytes) of a random aligned block
             constexpr uint64_t G = MODE == 5 ? 16 : (MODE == 6 ? 8 : 4);
             const uint64_t grp = (t >> (MODE == 5 ? 4 : (MODE == 6 ? 3 : 2)));
             const uint64_t blk = mix64(grp * per_thread + i) & (mask & ~(G - 1));
             __hip_atomic_fetch_add(table + blk + (lane & (G - 1)), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (MODE == 8) {
+            // 64-bit atomic add returning the old value, random slot
+            sink += __hip_atomic_fetch_add(table + a, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (MODE == 9) {
+            // 32-bit atomic add returning the old value, random slot
+            unsigned int *t32 = (unsigned int *)table;
+            sink += __hip_atomic_fetch_add(t32 + ((a << 1) | (i & 1)), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (MODE == 10 || MODE == 11) {
+            // groups of 16 lanes on the 16 consecutive 32-bit slots of a random 64-byte line,
+            // without (10) or with (11) the old value returned
+            unsigned int *t32 = (unsigned int *)table;
+            const uint64_t blk = mix64((t >> 4) * per_thread + i) & (mask & ~7ull);
+            unsigned int *p32 = t32 + 2 * blk + (lane & 15);
+            if (MODE == 10) __hip_atomic_fetch_add(p32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else sink += __hip_atomic_fetch_add(p32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // groups of 8 lanes on one random 64-byte line, 64-bit, the old value returned
+            const uint64_t blk = mix64((t >> 3) * per_thread + i) & (mask & ~7ull);
+            sink += __hip_atomic_fetch_add(table + blk + (lane & 7), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+    // never true for the counts these modes add (the sums stay far below 2^64 - 1); it keeps
+    // the returned values live
+    if (sink == ~0ull) table[0] = sink;
 }
 
 // ---------------------------------------------------------------------------
@@ -784,6 +834,7 @@ mc_tune resolve_tune(const mc_tune *t)
         if (t->waves_per_cu > 0) r.waves_per_cu = t->waves_per_cu;
         if (t->chunk > 0) r.chunk = t->chunk;
         if (t->refill > 0) r.refill = t->refill;
+        if (t->defer > 0) r.defer = t->defer;
     }
     return r;
 }
@@ -792,8 +843,10 @@ int check_tune(const mc_tune &t)
 {
     if (t.block != 64 && t.block != 128 && t.block != 256 && t.block != 512)
         return fail(MC_EINVAL, "tune: block size %d not one of 64, 128, 256, 512", t.block);
-    if (t.chunk < 1 || t.refill < 1 || t.refill > 64 || t.waves_per_cu < 1 || t.waves_per_cu > 32)
-        return fail(MC_EINVAL, "tune out of range (chunk >= 1, refill in [1, 64], waves_per_cu in [1, 32])");
+    if (t.chunk < 1 || t.refill < 1 || t.refill > 64 || t.waves_per_cu < 1 || t.waves_per_cu > 32 || t.defer < 1 ||
+        t.defer > 64)
+        return fail(MC_EINVAL,
+                    "tune out of range (chunk >= 1, refill and defer in [1, 64], waves_per_cu in [1, 32])");
     return MC_OK;
 }
 
@@ -862,19 +915,19 @@ void enqueue_walk(int block, int blocks, const Job &J, unsigned long long *queue
     switch (block) {
     case 64:
         hipLaunchKernelGGL((k_walk<64, R, GRAD, LOGGED, GENERAL, ESC>), dim3(blocks), dim3(64), lds, s, J, queue, t.chunk,
-                           t.refill, grad, eh);
+                           t.refill, t.defer, grad, eh);
         break;
     case 128:
         hipLaunchKernelGGL((k_walk<128, R, GRAD, LOGGED, GENERAL, ESC>), dim3(blocks), dim3(128), lds, s, J, queue,
-                           t.chunk, t.refill, grad, eh);
+                           t.chunk, t.refill, t.defer, grad, eh);
         break;
     case 256:
         hipLaunchKernelGGL((k_walk<256, R, GRAD, LOGGED, GENERAL, ESC>), dim3(blocks), dim3(256), lds, s, J, queue,
-                           t.chunk, t.refill, grad, eh);
+                           t.chunk, t.refill, t.defer, grad, eh);
         break;
     default:
         hipLaunchKernelGGL((k_walk<512, R, GRAD, LOGGED, GENERAL, ESC>), dim3(blocks), dim3(512), lds, s, J, queue,
-                           t.chunk, t.refill, grad, eh);
+                           t.chunk, t.refill, t.defer, grad, eh);
         break;
     }
 }
@@ -921,7 +974,7 @@ int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipSt
 // Zero the tallies (unless accumulating), pack the mask, walk, and for the
 // logged deposit path move the bricked tally into the caller's layout.
 int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws, unsigned long long *grad_bins,
-             hipStream_t s, const EscHist *esc = nullptr)
+             hipStream_t s, const EscHist *esc)
 {
     const Dims d = dims_of(vol);
     const bool logged = d.logged && !(flags & MC_DIRECT_DEPOSIT);
@@ -1002,6 +1055,7 @@ void mc_tune_default(mc_tune *t)
     t->waves_per_cu = 16;
     t->chunk = 256;
     t->refill = 16;
+    t->defer = 1;
 }
 
 size_t mc_run_workspace_bytes(const mc_volume *vol)
@@ -1152,29 +1206,40 @@ int mc_grad(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, u
     return MC_OK;
 }
 
-int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mode, void *hip_stream)
+int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mode, int waves_per_cu,
+                     void *hip_stream)
 {
     clear_error();
-    if (!table || n_entries == 0 || (n_entries & (n_entries - 1)) != 0)
-        return fail(MC_EINVAL, "table must be non-NULL with a power-of-two entry count");
-    if (mode < 0 || mode > 7) return fail(MC_EINVAL, "mode must be in [0, 7]");
-    if (mode == 4 && n_entries < 64) return fail(MC_EINVAL, "mode 4 needs at least 64 entries");
+    if (!table || n_entries < 64 || (n_entries & (n_entries - 1)) != 0)
+        return fail(MC_EINVAL, "table must be non-NULL with a power-of-two entry count >= 64");
+    if (mode < 0 || mode > 12) return fail(MC_EINVAL, "mode must be in [0, 12]");
+    if (waves_per_cu == 0) waves_per_cu = 16;
+    if (waves_per_cu < 4 || waves_per_cu > 32 || waves_per_cu % 4)
+        return fail(MC_EINVAL, "waves_per_cu must be 0 (16) or a multiple of 4 in [4, 32]");
     DeviceInfo di;
     int rc = device_info(&di);
     if (rc) return rc;
-    const uint64_t threads = (uint64_t)di.cus * 16 * 64;
+    const uint64_t threads = (uint64_t)di.cus * (uint64_t)waves_per_cu * 64;
     const uint64_t per_thread = std::max<uint64_t>(1, n_ops / threads);
     const unsigned blocks = (unsigned)(threads / 256);
     hipStream_t s = (hipStream_t)hip_stream;
     unsigned long long *t = (unsigned long long *)table;
-    if (mode == 0) hipLaunchKernelGGL(k_probe<0>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
-    else if (mode == 1) hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
-    else if (mode == 2) hipLaunchKernelGGL(k_probe<2>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
-    else if (mode == 3) hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
-    else if (mode == 4) hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
-    else if (mode == 5) hipLaunchKernelGGL(k_probe<5>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
-    else if (mode == 6) hipLaunchKernelGGL(k_probe<6>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
-    else hipLaunchKernelGGL(k_probe<7>, dim3(blocks), dim3(256), 0, s, t, n_entries - 1, per_thread);
+    const uint64_t m = n_entries - 1;
+    switch (mode) {
+    case 0: hipLaunchKernelGGL(k_probe<0>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 1: hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 2: hipLaunchKernelGGL(k_probe<2>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 3: hipLaunchKernelGGL(k_probe<3>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 4: hipLaunchKernelGGL(k_probe<4>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 5: hipLaunchKernelGGL(k_probe<5>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 6: hipLaunchKernelGGL(k_probe<6>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 7: hipLaunchKernelGGL(k_probe<7>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 8: hipLaunchKernelGGL(k_probe<8>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 9: hipLaunchKernelGGL(k_probe<9>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 10: hipLaunchKernelGGL(k_probe<10>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    case 11: hipLaunchKernelGGL(k_probe<11>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    default: hipLaunchKernelGGL(k_probe<12>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
+    }
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }

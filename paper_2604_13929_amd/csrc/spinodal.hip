@@ -1,4 +1,4 @@
-// spinodal.hip -- Cahn-Hilliard spinodal mask generator (Sec. 2.3, Eq. CH,
+// spinodal.hip -- Cahn-Hilliard spinodal mask generator (Sec. 2.2, Eq. CH,
 // Eq. CH_spectral; App. A): the semi-implicit Fourier spectral step in FP64,
 // the radial power spectral density of the stopping rule, and the exact rank
 // binarisation.
@@ -863,7 +863,56 @@ size_t rank_ws_bytes(int64_t n) { return pmc::sel::workspace_bytes((long long)n)
 
 }  // namespace
 
+// App. A's dominant structural size from a radial PSD (reading: half the peak
+// wavelength, one pore and one strut per period): the first shell s >= 1 holding
+// the largest value, and n_max / (2 s).
+__host__ __device__ inline int psd_peak_shell(const double *psd, int n_bins)
+{
+    int peak = 1;
+    for (int i = 2; i < n_bins; ++i)
+        if (psd[i] > psd[peak]) peak = i;
+    return peak;
+}
+
+__host__ __device__ inline double dominant_size(int n_max, int peak) { return (double)n_max / (2.0 * peak); }
+
+__global__ void k_psd_peak(const double *__restrict__ psd, int32_t n_bins, int32_t n_max, int32_t *__restrict__ peak,
+                           double *__restrict__ size)
+{
+    if (threadIdx.x != 0) return;
+    const int s = psd_peak_shell(psd, n_bins);
+    if (peak) *peak = s;
+    if (size) *size = dominant_size(n_max, s);
+}
+
 extern "C" {
+
+int mc_ch_grid_from_target(double d_target, mc_ch_grid *g)
+{
+    clear_error();
+    if (!g) return fail(MC_EINVAL, "grid is NULL");
+    if (!(d_target > 0.0) || !isfinite(d_target)) return fail(MC_EINVAL, "d_target must be finite and > 0");
+    // Eq. kappa_cal
+    const double pi = 3.141592653589793;
+    const double r = d_target / (8.0 * pi);
+    g->kappa = 0.5 * r * r;
+    // App. A: the explicit nonlinear term bounds the step, dt = min(0.5 / (kappa k_max^4), 1), k_max = pi
+    const double k2 = pi * pi;
+    const double dt = 0.5 / (g->kappa * k2 * k2);
+    g->dt = dt < 1.0 ? dt : 1.0;
+    return MC_OK;
+}
+
+int mc_psd_peak(const double *psd, int32_t n_bins, int32_t n_max, int32_t *peak_shell, double *size, void *hip_stream)
+{
+    clear_error();
+    if (!psd || (!peak_shell && !size)) return fail(MC_EINVAL, "NULL argument");
+    if (n_bins < 2) return fail(MC_EINVAL, "n_bins must be >= 2 (shell 0 is the mean)");
+    if (n_max < 1) return fail(MC_EINVAL, "n_max must be >= 1");
+    hipLaunchKernelGGL(k_psd_peak, dim3(1), dim3(64), 0, (hipStream_t)hip_stream, psd, n_bins, n_max, peak_shell, size);
+    HIP_TRY(hipGetLastError());
+    return MC_OK;
+}
 
 size_t mc_ch_workspace_bytes(const mc_ch_grid *g)
 {
@@ -1078,10 +1127,7 @@ int mc_ch_generate(const mc_ch_grid *g, const double *phi0, double d_target, dou
         if ((rc = mc_ch_psd(g, state, psd, workspace, G.total, hip_stream))) return rc;
         HIP_TRY(hipMemcpyAsync(host_psd, psd, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        int peak = 1;
-        for (int i = 2; i < nb; ++i)
-            if (host_psd[i] > host_psd[peak]) peak = i;
-        size = (double)nmax / (2.0 * peak);
+        size = dominant_size(nmax, psd_peak_shell(host_psd, nb));
         if (size >= d_target - 0.5 * sigma && size <= d_target + 0.5 * sigma) break;
     }
     if (steps_taken) *steps_taken = done;

@@ -46,7 +46,7 @@ enum : int32_t {
 
 __host__ __device__ __forceinline__ bool is_terminal(int32_t ev) { return ev >= EV_ESC_R && ev <= EV_GATED; }
 
-// Bin of an escaping photon's in-pore path pv (Sec. 3.4 (c)): b * width <= pv <
+// Bin of an escaping photon's in-pore path pv (Sec. 3.5 (c)): b * width <= pv <
 // (b + 1) * width, the last bin everything beyond.  The walk's own histogram and
 // the binning of traced records both use this one definition.
 __device__ __forceinline__ int escape_path_bin(double pv, double width, int nbins)
@@ -91,6 +91,7 @@ struct Photon {
     int32_t ix, iy, iz;
     R fx, fy, fz;
     R ux, uy, uz;
+    R iux, iuy, iuz;          // 1/|u| per axis (+inf where u = 0), kept with the direction
     double s_rem;             // remaining free path, in solid path length
     double l_void, l_tot;     // path inside pores, total path
     double score_g;           // sum of d ln p_HG / dg over the deflections so far (gradient walk)
@@ -118,6 +119,18 @@ template <typename R> __device__ __forceinline__ R clamp01(R x) { return fmin(fm
 template <typename R> __device__ __forceinline__ R u01(uint32_t r) { return (R)(r >> 8) * (R)0x1.0p-24; }
 // 1/|u| per axis, +inf on an axis the photon does not move along
 template <typename R> __device__ __forceinline__ R inv_abs(R u) { return u != (R)0 ? (R)1 / fabs(u) : r_inf<R>(); }
+
+// The face distances divide by |u| every step; the quotients are computed once per
+// direction (at launch, deflection and refraction) and kept in the photon state.
+template <typename R> __device__ __forceinline__ void set_direction(Photon<R> &p, R ux, R uy, R uz)
+{
+    p.ux = ux;
+    p.uy = uy;
+    p.uz = uz;
+    p.iux = inv_abs(ux);
+    p.iuy = inv_abs(uy);
+    p.iuz = inv_abs(uz);
+}
 
 __device__ __forceinline__ uint32_t brick_of(const Job &J, int32_t ix, int32_t iy, int32_t iz)
 {
@@ -183,18 +196,15 @@ __device__ __forceinline__ void launch(Photon<R> &p, const Job &J, uint32_t pid)
     p.fx = (R)(uint32_t)(X & 0xFFFFFFu) * (R)0x1.0p-24;
     p.fy = (R)(uint32_t)(Y & 0xFFFFFFu) * (R)0x1.0p-24;
     p.fz = (R)0;
-    p.ux = (R)0;
-    p.uy = (R)0;
-    p.uz = (R)1;
     if (J.source == 1) {
         const U4 s = philox4x32_10(U4{0u, pid, J.stream_id, 1u}, J.key0, J.key1);
         const R ct = r_sqrt(u01<R>(s.x));
         const R st = r_sqrt(fmax((R)0, ((R)1 - ct) * ((R)1 + ct)));
         R sp, cp;
         r_sincospi((R)2 * u01<R>(s.y), &sp, &cp);
-        p.ux = st * cp;
-        p.uy = st * sp;
-        p.uz = ct;
+        set_direction(p, st * cp, st * sp, ct);
+    } else {
+        set_direction(p, (R)0, (R)0, (R)1);
     }
     p.s_rem = free_path(J, r.z);
     p.l_void = 0.0;
@@ -253,9 +263,7 @@ __device__ __forceinline__ R scatter(Photon<R> &p, const Job &J, uint32_t r0, ui
         nz = -st * cp * tn + uz * ct;
     }
     const R inrm = (R)1 / r_sqrt(nx * nx + ny * ny + nz * nz);
-    p.ux = nx * inrm;
-    p.uy = ny * inrm;
-    p.uz = nz * inrm;
+    set_direction(p, nx * inrm, ny * inrm, nz * inrm);
     return ct;
 }
 
@@ -294,17 +302,25 @@ __device__ __forceinline__ R fresnel_uniform(Photon<R> &p, const Job &J)
     return u01<R>(w);
 }
 
-// One photon-step: a segment inside the current voxel that ends at a face, an
-// interaction or an escape (and, in the GENERAL walk, a reflection or the time
-// gate).  Returns the event.  The Sink receives every segment (deposits and
-// gradient scores are taken only inside the slab), the flushed per-voxel
-// deposits and the deflection cosines.
+// An event a walk kernel sees between advance() and interact(): the photon stands
+// at an interaction point, its interaction not yet drawn.  Never recorded.
+constexpr int32_t EV_AT_INTERACTION = 13;
+
+// One photon-step is advance() and, when the segment ends at an interaction point,
+// interact(), then finish().  step() runs them back to back; the walk kernels may
+// run a lane's interact() some iterations after its advance() (the lane waits
+// meanwhile), which changes nothing in the photon's history.
+//
+// advance(): the segment inside the current voxel up to a face, an interaction
+// point or an escape (and, in the GENERAL walk, a reflection or the time gate).
+// The Sink receives every segment (deposits and gradient scores are taken only
+// inside the slab) and the flushed per-voxel deposits.
 template <bool GENERAL, typename R, class Sink>
-__device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
+__device__ __forceinline__ int32_t advance(Photon<R> &p, const Job &J, Sink &sink)
 {
-    const R dx = p.ux != (R)0 ? (p.ux > (R)0 ? (R)1 - p.fx : p.fx) * inv_abs(p.ux) : r_inf<R>();
-    const R dy = p.uy != (R)0 ? (p.uy > (R)0 ? (R)1 - p.fy : p.fy) * inv_abs(p.uy) : r_inf<R>();
-    const R dz = p.uz != (R)0 ? (p.uz > (R)0 ? (R)1 - p.fz : p.fz) * inv_abs(p.uz) : r_inf<R>();
+    const R dx = p.ux != (R)0 ? (p.ux > (R)0 ? (R)1 - p.fx : p.fx) * p.iux : r_inf<R>();
+    const R dy = p.uy != (R)0 ? (p.uy > (R)0 ? (R)1 - p.fy : p.fy) * p.iuy : r_inf<R>();
+    const R dz = p.uz != (R)0 ? (p.uz > (R)0 ? (R)1 - p.fz : p.fz) * p.iuz : r_inf<R>();
     int32_t axis = 0;
     R d_face = dx;
     R ua = p.ux;              // direction component normal to the face reached
@@ -338,57 +354,33 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
     p.steps += 1u;
 
     int32_t ev;
-    if (GENERAL && gated) {
+    if ((GENERAL && gated) || interact) {
         p.fx = clamp01(p.fx + p.ux * d);
         p.fy = clamp01(p.fy + p.uy * d);
         p.fz = clamp01(p.fz + p.uz * d);
-        ev = EV_GATED;
-    } else if (interact) {
-        p.fx = clamp01(p.fx + p.ux * d);
-        p.fy = clamp01(p.fy + p.uy * d);
-        p.fz = clamp01(p.fz + p.uz * d);
-        p.k += 1u;
-        const U4 r = philox4x32_10(U4{p.k, p.pid, J.stream_id, 0u}, J.key0, J.key1);
-        // implicit capture on the integer weight, round half up
-        const uint32_t w_new = (uint32_t)(((uint64_t)p.w * J.s_q + 0x80000000ull) >> 32);
-        p.absorbed += (uint64_t)(p.w - w_new);
-        p.w = w_new;
-        if (w_new == 0u) {
-            ev = EV_DEAD_ABSORB;
-        } else {
-            const R ct = scatter(p, J, r.x, r.y);
-            sink.deflect(p, J, ct);
-            ev = EV_SCATTER;
-            if (p.w < J.w_th) {
-                if ((r.w >> 8) < J.t_m) {
-                    p.rr -= (int64_t)(J.m - 1u) * (int64_t)p.w;
-                    p.w *= J.m;
-                } else {
-                    p.rr += (int64_t)p.w;
-                    ev = EV_DEAD_ROULETTE;
-                }
-            }
-            p.s_rem = free_path(J, r.z);
-        }
+        ev = (GENERAL && gated) ? EV_GATED : EV_AT_INTERACTION;
     } else if constexpr (!GENERAL) {
-        if (axis != 0) p.fx = clamp01(p.fx + p.ux * d);
-        if (axis != 1) p.fy = clamp01(p.fy + p.uy * d);
-        if (axis != 2) p.fz = clamp01(p.fz + p.uz * d);
+        // the two other axes advance; the face axis is set on the face the photon enters
+        // (every component written with a value select, so no lane branches on the axis)
+        const R ax = clamp01(p.fx + p.ux * d), ay = clamp01(p.fy + p.uy * d), az = clamp01(p.fz + p.uz * d);
+        const bool up = ua > (R)0;
+        const R enter = up ? (R)0 : (R)1;
+        p.fx = axis == 0 ? enter : ax;
+        p.fy = axis == 1 ? enter : ay;
+        p.fz = axis == 2 ? enter : az;
         sink.flush(J, p, p.acc);
         p.acc = 0ull;
+        const int32_t sgn = up ? 1 : -1;
+        const int32_t jx = p.ix + sgn, jy = p.iy + sgn;
+        // lateral faces are periodic
+        const int32_t wx = jx == J.nx ? 0 : (jx < 0 ? J.nx - 1 : jx);
+        const int32_t wy = jy == J.ny ? 0 : (jy < 0 ? J.ny - 1 : jy);
+        p.ix = axis == 0 ? wx : p.ix;
+        p.iy = axis == 1 ? wy : p.iy;
+        p.iz = axis == 2 ? p.iz + sgn : p.iz;
         ev = axis;
-        if (axis == 0) {
-            if (p.ux > (R)0) { p.fx = (R)0; p.ix = (p.ix + 1 == J.nx) ? 0 : p.ix + 1; }
-            else             { p.fx = (R)1; p.ix = (p.ix == 0) ? J.nx - 1 : p.ix - 1; }
-        } else if (axis == 1) {
-            if (p.uy > (R)0) { p.fy = (R)0; p.iy = (p.iy + 1 == J.ny) ? 0 : p.iy + 1; }
-            else             { p.fy = (R)1; p.iy = (p.iy == 0) ? J.ny - 1 : p.iy - 1; }
-        } else {
-            if (p.uz > (R)0) { p.fz = (R)0; p.iz += 1; }
-            else             { p.fz = (R)1; p.iz -= 1; }
-            if (p.iz < 0) ev = EV_ESC_R;
-            else if (p.iz >= J.nz) ev = EV_ESC_T;
-        }
+        if (p.iz < 0) ev = EV_ESC_R;
+        else if (p.iz >= J.nz) ev = EV_ESC_T;
         if (!is_terminal(ev)) lookup<false>(p, J);
     } else {
         if (axis != 0) p.fx = clamp01(p.fx + p.ux * d);
@@ -430,16 +422,15 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
                 reflect = true;
             } else {
                 const R eta = n1 / n2;
-                p.ux = axis == 0 ? (R)sgn * ct : eta * p.ux;
-                p.uy = axis == 1 ? (R)sgn * ct : eta * p.uy;
-                p.uz = axis == 2 ? (R)sgn * ct : eta * p.uz;
+                set_direction(p, axis == 0 ? (R)sgn * ct : eta * p.ux, axis == 1 ? (R)sgn * ct : eta * p.uy,
+                              axis == 2 ? (R)sgn * ct : eta * p.uz);
             }
         }
         // Every component is written with a value select: stores chosen by axis would
         // be merged into one store through a selected address, which keeps the photon
         // state in memory.
         if (reflect) {
-            // stay in this voxel on the face, normal component reversed
+            // stay in this voxel on the face, normal component reversed (|u| unchanged)
             const R face = sgn > 0 ? (R)1 : (R)0;
             p.ux = axis == 0 ? -p.ux : p.ux;
             p.uy = axis == 1 ? -p.uy : p.uy;
@@ -468,13 +459,58 @@ __device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
             }
         }
     }
+    return ev;
+}
+
+// interact(): the interaction at the point advance() stopped at, with Philox block k
+// of the photon: implicit capture on the integer weight, Henyey-Greenstein
+// deflection (the Sink sees the cosine), Russian roulette, the next free path.
+template <typename R, class Sink>
+__device__ __forceinline__ int32_t interact(Photon<R> &p, const Job &J, Sink &sink)
+{
+    p.k += 1u;
+    const U4 r = philox4x32_10(U4{p.k, p.pid, J.stream_id, 0u}, J.key0, J.key1);
+    // implicit capture on the integer weight, round half up
+    const uint32_t w_new = (uint32_t)(((uint64_t)p.w * J.s_q + 0x80000000ull) >> 32);
+    p.absorbed += (uint64_t)(p.w - w_new);
+    p.w = w_new;
+    if (w_new == 0u) return EV_DEAD_ABSORB;
+    const R ct = scatter(p, J, r.x, r.y);
+    sink.deflect(p, J, ct);
+    int32_t ev = EV_SCATTER;
+    if (p.w < J.w_th) {
+        if ((r.w >> 8) < J.t_m) {
+            p.rr -= (int64_t)(J.m - 1u) * (int64_t)p.w;
+            p.w *= J.m;
+        } else {
+            p.rr += (int64_t)p.w;
+            ev = EV_DEAD_ROULETTE;
+        }
+    }
+    p.s_rem = free_path(J, r.z);
+    return ev;
+}
+
+// finish(): the step and path caps, and the deposit a photon that ends inside a
+// voxel (absorbed, roulette, cap, gate) leaves there.
+template <typename R, class Sink>
+__device__ __forceinline__ int32_t finish(Photon<R> &p, const Job &J, Sink &sink, int32_t ev)
+{
     if (!is_terminal(ev) && (p.steps >= J.max_steps || p.l_tot > (double)J.path_cap)) ev = EV_LOST;
     if (is_terminal(ev) && p.acc != 0ull) {
-        // photon ends inside a voxel (absorbed, roulette, cap, gate): flush what it left there
         sink.flush(J, p, p.acc);
         p.acc = 0ull;
     }
     return ev;
+}
+
+// One whole photon-step.  Returns the event.
+template <bool GENERAL, typename R, class Sink>
+__device__ __forceinline__ int32_t step(Photon<R> &p, const Job &J, Sink &sink)
+{
+    int32_t ev = advance<GENERAL>(p, J, sink);
+    if (ev == EV_AT_INTERACTION) ev = interact(p, J, sink);
+    return finish(p, J, sink, ev);
 }
 
 }  // namespace pmc

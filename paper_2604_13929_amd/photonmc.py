@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import warnings
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -57,7 +58,7 @@ class McChGrid(ctypes.Structure):
 
 class McTune(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("refill", ctypes.c_int32)]
+                ("refill", ctypes.c_int32), ("defer", ctypes.c_int32)]
 
 
 class McJob(ctypes.Structure):
@@ -93,7 +94,7 @@ _SIGS = {
     "mc_walk_elapsed_ms": (ctypes.c_int, [_P]),
     "mc_reduce_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_reduce": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
-    "mc_probe_scatter": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, _P]),
+    "mc_probe_scatter": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _P]),
     "mc_grad_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_grad": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
@@ -129,15 +130,37 @@ _SIGS = {
     "mc_pore_spearman": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P]),
     "mc_ch_generate": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_double, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "mc_ch_grid_from_target": (ctypes.c_int, [ctypes.c_double, _P]),
+    "mc_psd_peak": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    # the paper's reference model and comparison metrics
+    "mc_time_gate": (ctypes.c_int, [ctypes.c_double] * 7 + [_P]),
+    "mc_da_profile": (ctypes.c_int, [ctypes.c_double] * 4 + [ctypes.c_int32, _P, _P]),
+    "mc_rms_w": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
 }
 
 _lib = None
+
+
+MC_OK, MC_WARN_LOST, MC_EOVERFLOW = 0, 1, -2
 
 
 class McError(RuntimeError):
     def __init__(self, status: int, where: str, message: str):
         super().__init__(f"{where}: status {status}: {message}")
         self.status = status
+
+
+class McLostWeightWarning(UserWarning):
+    """Some weight was stopped by the step or path cap (summary status MC_WARN_LOST)."""
+
+
+def _summary_status(status: float, where: str):
+    """Act on summary[MC_Q_STATUS] as the reduction wrote it."""
+    st = int(status)
+    if st < 0:
+        raise McError(st, where, load().mc_strerror(st).decode())
+    if st == MC_WARN_LOST:
+        warnings.warn(f"{where}: {load().mc_strerror(st).decode()}", McLostWeightWarning, stacklevel=3)
 
 
 def load(path: str = LIB_PATH):
@@ -211,21 +234,31 @@ def paper_optics(mu_s: float, mu_a: float, g: float, n_solid: float = 1.746, lat
 
 def time_gate_seconds(mu_a: float, mu_s_red: float, porosity: float, thickness: float, n_eff: float,
                       c: float = SPEED_OF_LIGHT) -> float:
-    """Eq. tend: t_end = max(5 n_eff / (mu_a c), 6 L^2 / D_phys) with
-    D_phys = (c / n_eff) / (3 (mu_a,eff + mu_s,eff')) and the effective-medium
-    scaling of Eq. EMA_scaling, mu_eff = (1 - phi) mu.  SI units (1/m, m, s);
-    mu_a and mu_s_red are the solid (shell) coefficients."""
-    mu_a_eff = mu_a * (1.0 - porosity)
-    mus_eff = mu_s_red * (1.0 - porosity)
-    d_phys = (c / n_eff) / (3.0 * (mu_a_eff + mus_eff))
-    absorb = 5.0 * n_eff / (mu_a * c) if mu_a > 0 else float("inf")
-    return max(absorb, 6.0 * thickness ** 2 / d_phys)
+    """mc_time_gate (Eq. tend) for solid (shell) coefficients mu_a and mu_s' in SI
+    units (1/m, m, s): t_end in seconds."""
+    out = ctypes.c_double(0.0)
+    _check(load().mc_time_gate(float(mu_s_red), float(mu_a), 0.0, float(porosity), float(thickness), float(n_eff),
+                               float(c), ctypes.byref(out)), "mc_time_gate")
+    return out.value
 
 
 def time_gate_voxels(mu_s: float, mu_a: float, g: float, porosity: float, nz: int, n_eff: float) -> float:
-    """The same gate as an optical path c t_end in voxel lengths, for coefficients per
-    voxel and a slab of nz voxels: max(5 n / mu_a, 18 n nz^2 (1 - phi)(mu_a + mu_s (1 - g)))."""
-    return time_gate_seconds(mu_a, mu_s * (1.0 - g), porosity, float(nz), n_eff, c=1.0)
+    """mc_time_gate with c = 1 for solid coefficients per voxel and a slab of nz voxels:
+    the optical path limit c t_end in voxels (what Optics.gate takes)."""
+    out = ctypes.c_double(0.0)
+    _check(load().mc_time_gate(float(mu_s), float(mu_a), float(g), float(porosity), float(nz), float(n_eff), 1.0,
+                               ctypes.byref(out)), "mc_time_gate")
+    return out.value
+
+
+def da_profile(mu_s: float, mu_a: float, g: float, porosity: float, nz: int):
+    """mc_da_profile (Sec. 2.4): the collimated-source diffusion approximation's
+    Phi/S0 averaged over each of nz voxel layers, and L_opt in voxels."""
+    prof = np.empty(int(nz), dtype=np.float64)
+    l_opt = ctypes.c_double(0.0)
+    _check(load().mc_da_profile(float(mu_s), float(mu_a), float(g), float(porosity), int(nz),
+                                prof.ctypes.data_as(ctypes.c_void_p), ctypes.byref(l_opt)), "mc_da_profile")
+    return prof, l_opt.value
 
 
 @dataclass
@@ -234,9 +267,10 @@ class Tune:
     waves_per_cu: int = 0
     chunk: int = 0
     refill: int = 0
+    defer: int = 0
 
     def c(self) -> McTune:
-        return McTune(self.block, self.waves_per_cu, self.chunk, self.refill)
+        return McTune(self.block, self.waves_per_cu, self.chunk, self.refill, self.defer)
 
 
 @dataclass
@@ -346,8 +380,7 @@ def reduce(mask: torch.Tensor, res: RunResult) -> Summary:
     d = depth.cpu().numpy()
     del ws
     vals = {name: float(s[i]) for i, name in enumerate(SUMMARY)}
-    if vals["status"] != 0:
-        raise McError(int(vals["status"]), "mc_reduce", "a voxel tally reached 2^62")
+    _summary_status(vals["status"], "mc_reduce")
     return Summary(vals, d[0], d[1], d[2])
 
 
@@ -370,16 +403,19 @@ def trace(mask: torch.Tensor, optics: Optics, photon_ids, max_steps: int, seed: 
     return r, o
 
 
-def probe_scatter(table: torch.Tensor, n_ops: int, mode: int = 0) -> float:
-    """Time mc_probe_scatter on the current stream; returns operations per second."""
+def probe_scatter(table: torch.Tensor, n_ops: int, mode: int = 0, waves_per_cu: int = 16) -> float:
+    """Time mc_probe_scatter on the current stream (HIP events on that stream);
+    returns operations per second."""
     L = load()
     dev = table.device
+    stream = torch.cuda.current_stream(dev)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    _check(L.mc_probe_scatter(table.data_ptr(), table.numel(), n_ops, mode, _stream(dev)), "mc_probe_scatter")
-    stop.record()
+    start.record(stream)
+    _check(L.mc_probe_scatter(table.data_ptr(), table.numel(), n_ops, mode, waves_per_cu, _stream(dev)),
+           "mc_probe_scatter")
+    stop.record(stream)
     stop.synchronize()
-    threads = torch.cuda.get_device_properties(dev).multi_processor_count * 16 * 64
+    threads = torch.cuda.get_device_properties(dev).multi_processor_count * waves_per_cu * 64
     done = max(1, n_ops // threads) * threads
     return done / (start.elapsed_time(stop) * 1e-3)
 
@@ -434,6 +470,7 @@ class Batch:
         q = self.summaries[i].cpu().numpy()
         d = self.depths[i].cpu().numpy()
         vals = {name: float(q[k]) for k, name in enumerate(SUMMARY)}
+        _summary_status(vals["status"], f"mc_run_batch job {i}")
         return Summary(vals, d[0], d[1], d[2])
 
 
@@ -459,7 +496,7 @@ def autotune_batch(jobs: list[BatchJob], fp64: bool = False) -> Tune:
     out = McTune()
     _check(L.mc_autotune_batch(ctypes.byref(b.c_jobs), len(jobs), MC_FP64 if fp64 else 0, b.ws.data_ptr(),
                                b.ws.numel(), ctypes.byref(out), _stream(b.device)), "mc_autotune_batch")
-    return Tune(out.block, out.waves_per_cu, out.chunk, out.refill)
+    return Tune(out.block, out.waves_per_cu, out.chunk, out.refill, out.defer)
 
 
 class BatchGraph:
@@ -549,6 +586,7 @@ class PhiFn(torch.autograd.Function):
         base = Optics(float(mu_s), float(mu_a), float(g))
         r = run(mask, base, n_photons, seed, stream_id=stream_id, fp64=fp64)
         q, d, ws = reduce_async(mask, r)
+        _summary_status(float(q[SUMMARY.index("status")].item()), "PhiFn")
         ctx.save_for_backward(mu_s, mu_a, g)
         ctx.cfg = (mask, base, n_photons, seed, stream_id, fp64)
         return (q[SUMMARY.index("phi3d")].clone(), q[SUMMARY.index("phi1d")].clone(), d[0].clone())
@@ -563,9 +601,17 @@ class PhiFn(torch.autograd.Function):
         return (out[0].to(mu_s.dtype), out[1].to(mu_a.dtype), out[2].to(g.dtype), None, None, None, None, None)
 
 
-def rms_w(profile, reference) -> float:
-    """Fluence-weighted relative RMS deviation of a depth profile from a reference
-    (the paper's discrepancy metric, Sec. 2.7): host FP64 on two short profiles."""
-    p = np.asarray(profile, dtype=np.float64)
-    q = np.asarray(reference, dtype=np.float64)
-    return float(np.sqrt(np.sum(q * ((p - q) / q) ** 2) / np.sum(q)))
+def rms_w(profile, reference, device="cuda:0") -> dict:
+    """mc_rms_w (Sec. 2.7, Eq. RMSw, and Table S1's variants) of a depth profile
+    against a reference, on the GPU: {"weighted", "unweighted", "log"}, fractions."""
+    dev = torch.device(device)
+    p = torch.as_tensor(np.asarray(profile.cpu() if torch.is_tensor(profile) else profile, dtype=np.float64),
+                        device=dev).contiguous()
+    q = torch.as_tensor(np.asarray(reference.cpu() if torch.is_tensor(reference) else reference, dtype=np.float64),
+                        device=dev).contiguous()
+    if p.shape != q.shape or p.dim() != 1:
+        raise ValueError("profile and reference must be 1-D arrays of one length")
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    _check(load().mc_rms_w(p.data_ptr(), q.data_ptr(), int(p.numel()), out.data_ptr(), _stream(dev)), "mc_rms_w")
+    w, u, lg = out.cpu().tolist()
+    return {"weighted": w, "unweighted": u, "log": lg}

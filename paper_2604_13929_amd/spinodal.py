@@ -6,22 +6,11 @@ The spectrum is a complex128 tensor [nz, ny, nx//2 + 1] (numpy.fft.rfftn layout)
 from __future__ import annotations
 
 import ctypes
-import math
 from dataclasses import dataclass
 
 import torch
 
 from . import photonmc as pm
-
-
-def kappa_from_target(d_target_voxels: float) -> float:
-    """Eq. kappa_cal: kappa_CH = (1/2) (d_target / (8 pi))^2, voxel units."""
-    return 0.5 * (d_target_voxels / (8.0 * math.pi)) ** 2
-
-
-def dt_from_kappa(kappa: float) -> float:
-    """App. A: dt = min(0.5 / (kappa k_max^4), 1) with k_max = pi per voxel."""
-    return min(0.5 / (kappa * math.pi ** 4), 1.0)
 
 
 @dataclass
@@ -42,6 +31,14 @@ class Grid:
     @property
     def n_bins(self) -> int:
         return max(self.nx, self.ny, self.nz) // 2 + 1
+
+
+def grid_from_target(nx: int, ny: int, nz: int, d_target_voxels: float) -> Grid:
+    """A grid whose kappa_CH (Eq. kappa_cal) and dt (App. A) come from
+    mc_ch_grid_from_target for a target dominant size in voxels."""
+    g = pm.McChGrid(nx, ny, nz, 0, 0.0, 0.0)
+    pm._check(pm.load().mc_ch_grid_from_target(float(d_target_voxels), ctypes.byref(g)), "mc_ch_grid_from_target")
+    return Grid(nx, ny, nz, g.kappa, g.dt)
 
 
 def _ptr(t: torch.Tensor):
@@ -103,10 +100,22 @@ def psd(state: torch.Tensor, grid: Grid, ws: torch.Tensor | None = None) -> torc
     return out
 
 
+def psd_peak(p: torch.Tensor, n_max: int):
+    """mc_psd_peak: (peak shell, dominant size in voxels) of a radial PSD on the GPU."""
+    L = pm.load()
+    if not p.is_cuda:
+        raise ValueError("psd must be a device tensor")
+    q = p.to(torch.float64).contiguous()
+    shell = torch.empty(1, dtype=torch.int32, device=q.device)
+    size = torch.empty(1, dtype=torch.float64, device=q.device)
+    pm._check(L.mc_psd_peak(_ptr(q), int(q.numel()), int(n_max), _ptr(shell), _ptr(size), pm._stream(q.device)),
+              "mc_psd_peak")
+    return int(shell.item()), float(size.item())
+
+
 def dominant_size(p: torch.Tensor, grid: Grid) -> float:
-    """max(nx, ny, nz) / (2 s_peak): the size the stopping rule tests."""
-    s = int(torch.argmax(p[1:]).item()) + 1
-    return max(grid.nx, grid.ny, grid.nz) / (2.0 * s)
+    """The size App. A's stopping rule tests (mc_psd_peak)."""
+    return psd_peak(p, max(grid.nx, grid.ny, grid.nz))[1]
 
 
 def rank_threshold(f: torch.Tensor, porosity: float | None = None, n_pore: int | None = None) -> torch.Tensor:

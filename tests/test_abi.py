@@ -41,7 +41,8 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_layouts(lib):
-    assert lib.mc_abi_version() == 2
+    assert lib.mc_abi_version() == 3
+    assert lib.mc_sizeof(b"mc_tune") == ctypes.sizeof(pm.McTune) == 20
     assert lib.mc_sizeof(b"mc_volume") == 24
     assert lib.mc_sizeof(b"mc_optics") == ctypes.sizeof(pm.McOptics) == 56
     assert lib.mc_sizeof(b"mc_trace_rec") == pm.TRACE_DTYPE.itemsize == 88
@@ -84,6 +85,7 @@ def test_run_rejects_bad_arguments(lib, kw, needle):
 def test_run_rejects_bad_tune(lib):
     assert _call_run(lib, tune=pm.McTune(96, 0, 0, 0)) == -1 and b"block" in lib.mc_last_error()
     assert _call_run(lib, tune=pm.McTune(0, 0, 0, 65)) == -1 and b"refill" in lib.mc_last_error()
+    assert _call_run(lib, tune=pm.McTune(0, 0, 0, 0, 65)) == -1 and b"defer" in lib.mc_last_error()
 
 
 def test_workspace_sizes(lib):

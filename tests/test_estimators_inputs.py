@@ -12,10 +12,12 @@ from oracle import estimators as est
 from paper_2604_13929_amd import inputs
 from conftest import golden
 
+f32 = lambda x: float(np.float32(x))  # noqa: E731
+
 
 # -- the paper's printed numbers ------------------------------------------------
 def test_dilution_identity_reproduces_printed_ratios():
-    """Sec. 2.8 (b) / Table S2: r = 0.5142 (phi = 0.70) and 0.5152 (phi = 0.90) give
+    """Sec. 3.5 (b) / Table S2: r = 0.5142 (phi = 0.70) and 0.5152 (phi = 0.90) give
     <Phi>_3D/<Phi>_1D = 1.5153 and 1.7739 through Eq. dilution."""
     for phi, _, _, _, r, ratio in golden("dilution_identity.txt"):
         pred = 1.0 / (phi * r + (1.0 - phi))
@@ -70,11 +72,80 @@ def test_identity_holds_on_tallies(mask_m1):
     assert np.nansum(e["depth"]) / mask_m1.shape[0] == pytest.approx(e["phi1d"], rel=1e-12)
 
 
+def test_front_back_and_l_opt_on_a_hand_built_tally():
+    """Table S2's front/back ratio Phi(0)/Phi(L) and Table 4's L_opt = <Phi>_1D L / S0 on
+    a tally built by hand: layer z of an nx x ny x nz map (all extents different) holds
+    (z + 1) (1 + x + 2y) units, so the lateral mean of layer z is (z + 1) times the
+    mean of (1 + x + 2y) and every quantity follows by hand."""
+    nx, ny, nz, n = 5, 3, 7, 1000
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    F = ((z + 1) * (1 + x + 2 * y)).astype(np.float64) * est.W1
+    e = est.estimators(F, np.zeros((nz, ny, nx), np.uint8), n)
+    lat = (1 + np.arange(nx)[None, :] + 2 * np.arange(ny)[:, None]).mean()      # = 1 + 2 + 2 = 5
+    assert lat == 5.0
+    norm = nx * ny / n                                   # Phi/S0 per unit of F / W1
+    assert e["depth"] == pytest.approx(norm * lat * np.arange(1, nz + 1), rel=1e-15)
+    assert e["front_back"] == pytest.approx(1.0 / nz, rel=1e-15)
+    # <Phi>_1D = norm * lat * mean(z + 1) = norm * 5 * (nz + 1) / 2; L_opt multiplies by nz
+    assert e["phi1d"] == pytest.approx(norm * lat * (nz + 1) / 2.0, rel=1e-15)
+    assert e["L_opt"] == pytest.approx(norm * lat * (nz + 1) / 2.0 * nz, rel=1e-15)
+    # a last layer without fluence has no finite front/back ratio
+    F[-1] = 0.0
+    assert est.estimators(F, np.zeros((nz, ny, nx), np.uint8), n)["front_back"] == float("inf")
+
+
+def test_l_opt_of_an_all_pore_slab_is_its_thickness():
+    """An all-pore slab is crossed straight: every launched photon deposits one voxel
+    length in every layer, so each layer's lateral mean of Phi/S0 is 1 (the columns
+    share the photons unevenly, their mean does not depend on it), <Phi>_1D = 1,
+    L_opt = Nz and the front/back ratio is exactly 1, for any lateral size."""
+    for nx, ny, nz in ((5, 3, 7), (1, 1, 13), (9, 4, 2)):
+        m = np.ones((nz, ny, nx), dtype=np.uint8)
+        n = 3000
+        r = oracle.run(m, 0.5, 0.01, 0.7, n, seed=11)
+        e = est.estimators(r["fluence"][0], m, n)
+        assert e["phi1d"] == pytest.approx(1.0, rel=1e-14) and e["front_back"] == 1.0
+        assert e["L_opt"] == pytest.approx(float(nz), rel=1e-14)
+        assert np.all(e["depth"] == e["depth"][0]) and e["depth"][0] == pytest.approx(1.0, rel=1e-14)
+
+
+def test_front_back_of_a_pure_absorber_slab():
+    """Beer-Lambert in an all-solid, non-scattering slab: layer z holds
+    e^{-mu_a z} (1 - e^{-mu_a}) / mu_a, so Phi(0)/Phi(Nz - 1) = e^{mu_a (Nz - 1)};
+    the oracle's ratio agrees within 4 sigma of 32 photon batches."""
+    nz, mu_a, n, B = 10, f32(0.1), 64_000, 32
+    m = np.zeros((nz, 2, 3), dtype=np.uint8)
+    r = oracle.run(m, 0.0, mu_a, 0.0, n, seed=5, nbatch=B)
+    per_b = np.array([est.estimators(r["fluence"][b], m, n // B)["front_back"] for b in range(B)])
+    whole = est.estimators(r["fluence"].sum(axis=0), m, n)
+    want = math.exp(mu_a * (nz - 1))
+    assert abs(whole["front_back"] - want) <= 4 * per_b.std(ddof=1) / math.sqrt(B)
+    assert whole["L_opt"] == pytest.approx(whole["phi1d"] * nz, rel=1e-15)
+    assert whole["phi1d"] * nz == pytest.approx((1 - math.exp(-mu_a * nz)) / mu_a, rel=2e-2)
+
+
 def test_rms_w_definition():
     q = np.array([4.0, 2.0, 1.0])
     p = q * np.array([1.1, 0.8, 1.0])
     want = math.sqrt((4 * 0.01 + 2 * 0.04 + 0) / 7.0)
     assert est.rms_w(p, q) == pytest.approx(want, rel=1e-14)
+
+
+def test_rms_variants_by_hand():
+    """Table S1's variants on profiles whose deviations are known: a profile e^{+-0.1}
+    times the reference has log-ratio RMS 0.1 exactly; relative deviations of 0.1,
+    -0.2 and 0 give an unweighted RMS of sqrt(0.05 / 3); depths with a zero or
+    infinite reference and a NaN profile value are left out of every variant, and a
+    non-positive profile value only out of the log variant."""
+    q = np.array([3.0, 1.5, 0.25, 8.0])
+    p = q * np.exp(np.array([0.1, -0.1, 0.1, -0.1]))
+    assert est.rms_log(p, q) == pytest.approx(0.1, rel=1e-14)
+    q = np.array([4.0, 2.0, 1.0, 0.0, np.inf, 5.0])
+    p = np.array([4.4, 1.6, 1.0, 7.0, 1.0, np.nan])
+    assert est.rms_unweighted(p, q) == pytest.approx(math.sqrt(0.05 / 3), rel=1e-14)
+    assert est.rms_w(p, q) == pytest.approx(math.sqrt((4 * 0.01 + 2 * 0.04) / 7.0), rel=1e-14)
+    p2 = np.array([4.4, -1.0, 1.0])
+    assert est.rms_log(p2, q[:3]) == pytest.approx(math.sqrt((math.log(1.1) ** 2 + 0.0) / 2), rel=1e-14)
 
 
 # -- input generators ----------------------------------------------------------------

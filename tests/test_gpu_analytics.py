@@ -1,4 +1,4 @@
-"""Analytics of Sec. 3.4 on the GPU (include/analytics.h) against the oracle
+"""Analytics of Sec. 3.5 on the GPU (include/analytics.h) against the oracle
 (oracle/analytics.py), through the C ABI:
 
 * chord histograms bit-exact on every axis (small masks, M1, and at 256^3 against

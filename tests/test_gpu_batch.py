@@ -1,12 +1,19 @@
-"""Batched multi-mask launch: job k of a batch equals a plain run of job k, bit for
-bit, for any launch shape; the captured graph replays the same bits; the reduction
-of every job equals mc_reduce on that job; the autotuner returns a usable shape."""
+"""Batched multi-mask launch: every job of a batch against the FP64 oracle on the
+same photons (jobs spanning the 64-job workload's sizes, porosities and optics, with
+stream ids and photon ranges other than 0); job k of a batch equals a plain run of
+job k, bit for bit, for any launch shape; the captured graph replays the same bits;
+the reduction of every job equals mc_reduce on that job; the autotuner returns a
+usable shape."""
 from __future__ import annotations
+
+import math
 
 import numpy as np
 import pytest
 import torch
 
+import oracle
+from oracle import estimators as est
 from paper_2604_13929_amd import inputs
 from paper_2604_13929_amd import photonmc as pm
 
@@ -39,6 +46,117 @@ def small_jobs():
     return jobs
 
 
+W1 = 2 ** 31
+# the largest rounding 4096 segments' deposits can add up to (each rounded to a whole tally unit)
+ROUNDING_4096 = 0.5 * 4096
+
+
+@pytest.fixture(scope="module")
+def oracle_jobs():
+    """Six jobs at the corners of the 64-job workload's ranges (phi 0.5 / 0.9, solid mu_s
+    0.2 / 1.0, mu_a 0.005 / 0.05, g 0.5 / 0.9) and one in the middle, on ragged cubes of
+    16 to 48 voxels, each with its own stream id and a photon range that does not start
+    at 0."""
+    spec = [(16, 16, 16, 0.5, 0.2, 0.005, 0.5, 3, 1000),
+            (48, 48, 48, 0.9, 1.0, 0.05, 0.9, 7, 123_456),
+            (37, 29, 23, 0.5, 1.0, 0.005, 0.9, 11, 5),
+            (24, 40, 47, 0.9, 0.2, 0.05, 0.5, 13, 999_999),
+            (45, 20, 31, 0.6, 0.45, 0.01, 0.8, 42, 77),
+            (33, 33, 33, 0.7, 0.6, 0.0275, 0.7, 63, 2 ** 31)]
+    jobs = []
+    for i, (nx, ny, nz, phi, mus, mua, g, sid, begin) in enumerate(spec):
+        m = inputs.spinodal_mask(nx, ny, nz, 8.0, phi, seed=200 + i)
+        jobs.append((m, pm.BatchJob(torch.from_numpy(m).cuda(), pm.Optics(f32(mus), f32(mua), f32(g)), 60_000,
+                                    seed=20260809, stream_id=sid, photon_begin=begin)))
+    return jobs
+
+
+def _oracle_of(m, j: pm.BatchJob, nbatch):
+    o = j.optics
+    return oracle.run(m, o.mu_s, o.mu_a, o.g, j.n_photons, j.seed, photon_begin=j.photon_begin,
+                      stream_id=j.stream_id, nbatch=nbatch)
+
+
+def test_batch_jobs_match_oracle(oracle_jobs):
+    """FP32 batch: per job, the globals within 0.5 %, R/T/A within 0.5 % of the launched
+    weight, steps within 0.1 %, and every voxel within 4 sigma of the oracle's spread
+    over 32 photon batches (voxels the oracle never reached must be exactly 0)."""
+    banner("batch of 6 (FP32) vs the FP64 oracle, job by job")
+    b = pm.run_batch([j for _, j in oracle_jobs], tune=pm.Tune(256, 16, 256, 16))
+    torch.cuda.synchronize()
+    for k, (m, j) in enumerate(oracle_jobs):
+        n = j.n_photons
+        ref = _oracle_of(m, j, 32)
+        tot = oracle.totals(ref)
+        Fb = ref["fluence"]
+        F_o = Fb.sum(axis=0)
+        e = est.estimators(F_o, m, n)
+        s = b.summary(k)
+        sc = b.results[k].scalar_dict()
+        assert sc["launched"] == n and s["closure_exact"] == 1.0 and sc["lost"] == 0, k
+        for key in ("phi3d", "phi1d", "phi_pore", "r", "L_opt"):
+            assert abs(s[key] - e[key]) <= 5e-3 * abs(e[key]), (k, key, s[key], e[key])
+        for key in ("R", "T", "A"):
+            assert abs(sc[key] - tot[key]) <= 5e-3 * n * W1, (k, key)
+        assert abs(sc["steps"] - tot["steps"]) <= 1e-3 * tot["steps"], k
+        F_g = b.results[k].fluence.cpu().numpy().astype(np.float64)
+        sd = Fb.std(axis=0, ddof=1) * math.sqrt(Fb.shape[0])
+        on = sd > 0
+        assert np.all(np.abs(F_g - F_o)[on] <= 4 * sd[on]), k
+        assert np.all(F_g[~on] == F_o[~on]), k
+        print(f"job {k}: phi3d {s['phi3d']:.6f} (oracle {e['phi3d']:.6f}), steps {sc['steps']} "
+              f"(oracle {tot['steps']})")
+
+
+def test_batch_fp64_jobs_equal_oracle(oracle_jobs):
+    """FP64 transport in the batch: every integer channel of every job equals the
+    oracle's, and the fluence equals it up to the per-segment rounding of deposits in
+    at least 99.9 % of the voxels.  The rest may differ by FP64 trajectory drift: over
+    a walk of hundreds of steps the rounding of two FP64 evaluations of the same steps
+    grows through shallow face crossings (one photon of job 2, mu_s 1.0, g 0.9, reached
+    3e-6 voxel after 700 steps without changing a decision), which moves that much
+    track length between neighbouring voxels: bounded here by 1e-6 of the voxel's
+    tally."""
+    banner("batch of 6 (FP64 transport) vs the FP64 oracle: integer channels exact")
+    b = pm.run_batch([j for _, j in oracle_jobs], tune=pm.Tune(128, 8, 64, 8), fp64=True)
+    torch.cuda.synchronize()
+    for k, (m, j) in enumerate(oracle_jobs):
+        ref = _oracle_of(m, j, 1)
+        tot = oracle.totals(ref)
+        sc = b.results[k].scalar_dict()
+        for key in ("R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_n", "esc_n_gtL", "steps",
+                    "interactions"):
+            assert sc[key] == tot[key], (k, key, sc[key], tot[key])
+        F_g = b.results[k].fluence.cpu().numpy().astype(np.float64)
+        F_o = ref["fluence"][0]
+        diff = np.abs(F_g - F_o)
+        bad = diff > 1e-9 * F_o + ROUNDING_4096
+        if bad.any():
+            _report_fluence_mismatch(m, j, F_g, F_o, bad)
+        assert bad.mean() <= 1e-3, k
+        assert np.all(diff <= 1e-6 * F_o + ROUNDING_4096), k
+
+
+def _report_fluence_mismatch(m, j, F_g, F_o, bad):
+    """Print what names the failing voxels and the photons whose outcomes differ."""
+    idx = np.argwhere(bad)
+    print(f"{len(idx)} voxels outside the rounding bound; worst:", flush=True)
+    diff = np.abs(F_g - F_o)
+    for z, y, x in idx[np.argsort(-diff[bad])][:8]:
+        print(f"  (z {z}, y {y}, x {x}) pore {m[z, y, x]}: gpu {F_g[z, y, x]:.6e} oracle {F_o[z, y, x]:.6e} "
+              f"diff {F_g[z, y, x] - F_o[z, y, x]:.6e}", flush=True)
+    ids = np.arange(j.photon_begin, j.photon_begin + j.n_photons, dtype=np.uint64)
+    _, go = pm.trace(j.mask, j.optics, ids, 0, j.seed, stream_id=j.stream_id, fp64=True)
+    o = j.optics
+    _, oo = oracle.trace(m, o.mu_s, o.mu_a, o.g, ids, j.seed, max_rec=0, stream_id=j.stream_id)
+    diff_ph = np.zeros(len(ids), dtype=bool)
+    for f in ("fate", "steps", "interactions", "A", "w_final"):
+        diff_ph |= go[f].astype(np.int64) != oo[f].astype(np.int64)
+    diff_ph |= np.abs(go["path_void"] - oo["path_void"]) > 1e-6
+    print(f"{diff_ph.sum()} photons end differently; first: {ids[diff_ph][:5]}, "
+          f"oracle min_gap there {oo['min_gap'][diff_ph][:5]}", flush=True)
+
+
 def _plain(j: pm.BatchJob, fp64=False):
     r = pm.run(j.mask, j.optics, j.n_photons, j.seed, photon_begin=j.photon_begin, stream_id=j.stream_id, fp64=fp64)
     return r, pm.reduce(j.mask, r)
@@ -47,7 +165,8 @@ def _plain(j: pm.BatchJob, fp64=False):
 def test_batch_equals_plain_runs(small_jobs):
     banner("batch of 6 == 6 plain runs, bitwise, several launch shapes")
     plains = [_plain(j) for j in small_jobs]
-    for tune in (pm.Tune(256, 16, 256, 16), pm.Tune(64, 4, 7, 1), pm.Tune(512, 32, 4096, 64)):
+    for tune in (pm.Tune(256, 16, 256, 16), pm.Tune(64, 4, 7, 1), pm.Tune(512, 32, 4096, 64),
+                 pm.Tune(256, 16, 256, 16, 1), pm.Tune(128, 8, 64, 8, 64)):
         b = pm.run_batch(small_jobs, tune=tune)
         torch.cuda.synchronize()
         for k, (r, s) in enumerate(plains):

@@ -29,8 +29,9 @@ from paper_2604_13929_amd import photonmc as pm
 from paper_2604_13929_amd import spinodal as sp
 
 pytestmark = pytest.mark.gpu
-KAPPA = sp.kappa_from_target(17.4 / 1.45)
-DT = sp.dt_from_kappa(KAPPA)
+# the paper's constants, kappa_CH = 0.1140 and dt = 0.0450 (Eq. kappa_cal, App. A), as the oracle computes them
+KAPPA = och.kappa_from_target(17.4 / 1.45)
+DT = och.dt_from_kappa(KAPPA)
 
 
 def banner(msg):
@@ -109,7 +110,11 @@ def test_psd_matches_oracle():
     want = och.radial_psd(st.cpu().numpy(), shape)
     assert got.shape == want.shape
     assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * want.max())
-    assert sp.dominant_size(torch.from_numpy(got), g) == och.dominant_size(want, shape)
+    assert sp.dominant_size(torch.from_numpy(got).cuda(), g) == och.dominant_size(want, shape)
+    # mc_psd_peak on the oracle's own PSD and on PSDs with ties and a single shell
+    for p, n_max in ((want, max(shape)), (np.array([9.0, 1.0, 3.0, 3.0, 2.0]), 8), (np.array([5.0, 0.5]), 2)):
+        s_peak, size = sp.psd_peak(torch.from_numpy(p).cuda(), n_max)
+        assert s_peak == int(np.argmax(p[1:])) + 1 and size == och.dominant_size(p, (n_max,))
 
 
 @pytest.mark.parametrize("n", [1, 7, 4096, 4097, 100_003])

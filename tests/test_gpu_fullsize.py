@@ -5,6 +5,8 @@ times (library default launch shape, FP32 transport):
   (exact integer energy closure, no lost weight, the dilution identity on the
   tallies, collision = track-length absorption within 4 sigma of 16 photon
   sub-ranges, the sub-ranges summing bitwise to the whole run);
+* the global estimators of the first 1e7 photons (256^3 at phi = 0.70 and 0.90)
+  against the oracle on the same photons, within 0.5 %;
 * sampled outputs the oracle computes one by one: a 20 000-photon sub-range taken
   from the middle of the 1e8 id range (globals and phase-resolved depth sums
   against the oracle on the same ids), and FP64-transport trajectories of sampled
@@ -116,6 +118,44 @@ def test_m2a_full_run_properties(m2a):
     assert torch.equal(acc.fluence, whole.fluence) and torch.equal(acc.scalars, whole.scalars)
 
 
+def _globals_at_1e7(d, mask_np, name):
+    """The first 1e7 photon ids of the workload on the GPU (FP32 transport, default launch
+    shape) and in the oracle (FP64, every host core): the global estimators within 0.5 %,
+    R, T, A within 0.5 % of the launched weight, steps within 0.1 %."""
+    n = 10_000_000
+    r = pm.run(d, OPT, n, SEED)
+    s = pm.reduce(d, r)
+    sc = r.scalar_dict()
+    ref = oracle.run(mask_np, OPT.mu_s, OPT.mu_a, OPT.g, n, SEED)
+    tot = oracle.totals(ref)
+    e = est.estimators(ref["fluence"][0], mask_np, n)
+    err = {k: abs(s[k] - e[k]) / abs(e[k]) for k in ("phi3d", "phi1d", "phi_pore", "r", "ratio", "L_opt",
+                                                      "front_back")}
+    err.update({k: abs(sc[k] - tot[k]) / (n * W1) for k in ("R", "T", "A")})
+    err["steps"] = abs(sc["steps"] - tot["steps"]) / tot["steps"]
+    print(f"{name} at 1e7 photons, relative errors against the oracle: "
+          + ", ".join(f"{k} {v:.2e}" for k, v in err.items()), flush=True)
+    for k in ("phi3d", "phi1d", "phi_pore", "r", "ratio", "L_opt", "R", "T", "A"):
+        assert err[k] < 5e-3, (k, err[k])
+    assert err["front_back"] < 2e-2
+    assert err["steps"] < 1e-3
+    assert s["closure_exact"] == 1.0 and sc["lost"] == 0
+
+
+def test_m2a_globals_at_1e7_match_oracle(m2a):
+    banner("256^3 phi 0.70: first 1e7 photons, GPU vs oracle globals (oracle ~1 min on the host)")
+    mask_np, d = m2a
+    _globals_at_1e7(d, mask_np, "M2a")
+
+
+def test_m2b_globals_at_1e7_match_oracle():
+    banner("256^3 phi 0.90: first 1e7 photons, GPU vs oracle globals (oracle ~1 min on the host)")
+    wl = inputs.WORKLOADS["M2b"]
+    field = inputs.cahn_field(wl["nx"], wl["ny"], wl["nz"], wl["wavelength"], 0)
+    m9 = inputs.rank_threshold(field, 0.90)
+    _globals_at_1e7(torch.from_numpy(m9).cuda(), m9, "M2b")
+
+
 def test_m2a_sampled_subrange_matches_oracle(m2a):
     banner("256^3 phi 0.70: 20 000 photons from the middle of the id range vs oracle")
     mask_np, d = m2a
@@ -167,8 +207,18 @@ def test_morphology_control_m3_vs_h3():
     sm = pm.reduce(d3, pm.run(d3, OPT, n, SEED))
     sh = pm.reduce(dh, pm.run(dh, opt_h, n, SEED))
     rms = est.rms_w(sm.depth, sh.depth)
-    print(f"RMS_w(M3 vs H3) = {rms:.4f}; P_w(void > L) = {sm['Pw_void_gtL']:.4f}, "
-          f"P_n = {sm['Pn_void_gtL']:.4f}, mean void path {sm['mean_void_path']:.1f}")
+    lib = pm.rms_w(sm.depth, sh.depth)
+    assert lib["weighted"] == pytest.approx(rms, rel=1e-12)
+    assert lib["unweighted"] == pytest.approx(est.rms_unweighted(sm.depth, sh.depth), rel=1e-12)
+    assert lib["log"] == pytest.approx(est.rms_log(sm.depth, sh.depth), rel=1e-12)
+    # both against the collimated diffusion approximation of the same effective medium
+    da, _ = pm.da_profile(OPT.mu_s, OPT.mu_a, OPT.g, phi, wl["nz"])
+    m3_da, h3_da = pm.rms_w(sm.depth, da), pm.rms_w(sh.depth, da)
+    assert m3_da["weighted"] == pytest.approx(est.rms_w(sm.depth, da), rel=1e-12)
+    print(f"RMS_w(M3 vs H3) = {rms:.4f}; vs DA: M3 {m3_da}, H3 {h3_da}; P_w(void > L) = "
+          f"{sm['Pw_void_gtL']:.4f}, P_n = {sm['Pn_void_gtL']:.4f}, mean void path {sm['mean_void_path']:.1f}")
     assert 0.0 < rms < 10.0
+    # the homogeneous slab is much closer to the DA than the spinodal mask (Table S1's ordering)
+    assert h3_da["weighted"] < m3_da["weighted"]
     assert sh["Pw_void_gtL"] == 0.0 and sh["mean_void_path"] == 0.0
     assert 0.0 < sm["Pw_void_gtL"] < 1.0

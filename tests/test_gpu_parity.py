@@ -68,9 +68,13 @@ def test_all_pore_exact():
 
 
 def _compare_trajectories(g, o, tol, tie):
-    """Accumulated agreement of GPU and oracle trajectories, step by step, up to the
-    first step the oracle marks as a near tie (gap < tie).  Returns the per-photon
-    maximum deviation (position offsets, direction, segment length)."""
+    """Accumulated agreement of GPU and oracle trajectories, step by step: same voxels,
+    integer weights, interaction counts and events, and every photon's maximum
+    deviation (position offsets, direction, segment length) below tol.  A photon is
+    followed up to the first step whose decision the oracle logs as close (its gap
+    between competing distances below tie, or below ten times the deviation the photon
+    has accumulated so far): from there the two may legitimately take different
+    branches.  Returns the per-photon maximum deviations."""
     worst = np.zeros(g.shape[0])
     for i in range(g.shape[0]):
         mx = 0.0
@@ -82,13 +86,17 @@ def _compare_trajectories(g, o, tol, tie):
             if (a["ix"], a["iy"], a["iz"]) != (b["ix"], b["iy"], b["iz"]):
                 mx = np.inf
                 break
-            for c in ("fx", "fy", "fz", "ux", "uy", "uz", "d"):
+            # the state at the start of the step
+            for c in ("fx", "fy", "fz", "ux", "uy", "uz"):
                 mx = max(mx, abs(float(a[c]) - float(b[c])))
             assert int(a["w"]) == int(b["w"]) and int(a["k"]) == int(b["k"]), (i, j)
-            if b["tie_gap"] < tie:
-                break  # later steps may take the other branch of the tie
+            if b["tie_gap"] < max(tie, 10.0 * mx):
+                break  # this step's decision may go the other way on either side
+            # the decision: segment length and how the step ended
+            mx = max(mx, abs(float(a["d"]) - float(b["d"])))
             assert a["event"] == b["event"], (i, j, a["event"], b["event"])
         worst[i] = mx
+        assert mx < tol, (i, mx, tol)
     return worst
 
 
@@ -143,10 +151,27 @@ def test_trajectories_fp32_transport_stepwise(mask_m1):
             worst_step = max(worst_step, dev_)
             steps += 1
     assert steps > 50_000
-    acc = _compare_trajectories(g, o, tol=np.inf, tie=1e-4)
-    print(f"fp32: {steps} steps checked, worst single-step deviation {worst_step:.2e}; accumulated deviation "
-          f"over 64 steps, quantiles 50/90/99 %: {np.quantile(acc, [0.5, 0.9, 0.99])}")
+    print(f"fp32: {steps} steps checked, worst single-step deviation {worst_step:.2e}")
     assert worst_step < 2e-6
+
+
+def test_trajectories_fp32_transport_accumulated(mask_m1):
+    """FP32 transport followed without restarts: the first 64 steps of every photon
+    against the oracle's FP64 trajectory (same voxels, events, integer weights up to the
+    oracle's first near tie, gap < 1e-4).  FP32 direction rounding (~1e-7) is amplified
+    by 1/|u_axis| at every shallow face crossing, so the 1e-5 bound of the FP64 transport
+    does not hold for every photon; the claim asserted for FP32 is the measured one:
+    the median photon stays within 1e-5 voxel, 90 % within 1e-4, every photon within
+    1e-2, and no photon changes voxel sequence before a decision closer than its deviation."""
+    banner("FP32 trajectories M1, 2000 photons x 64 steps (accumulated)")
+    ids = np.arange(2000, dtype=np.uint64) * 7 + 3
+    g, _ = pm.trace(dev(mask_m1), OPT, ids, 64, SEED)
+    o, _ = oracle.trace(mask_m1, OPT.mu_s, OPT.mu_a, OPT.g, ids, SEED, max_rec=64)
+    acc = _compare_trajectories(g, o, tol=1e-2, tie=1e-4)
+    q = np.quantile(acc, [0.5, 0.9, 0.99, 1.0])
+    print(f"fp32 accumulated deviation over 64 steps, quantiles 50/90/99/100 %: {q}; "
+          f"within 1e-5: {(acc < 1e-5).mean():.3f}")
+    assert q[0] < 1e-5 and q[1] < 1e-4
 
 
 def test_photon_outcomes_fp64_match_oracle(mask_m1):
@@ -200,6 +225,11 @@ def _compare_run(mask, opt, n, nbatch=32, seed=SEED, tune=None, rel=5e-3, fp64=F
         assert abs(sc[k] - tot[k]) <= rel * n * W1, (k, sc[k], tot[k])
     assert abs(sc["steps"] - tot["steps"]) <= 1e-3 * tot["steps"]
     assert summ["porosity"] == mask.mean()
+    # Table S2's front/back ratio and Table 4's L_opt, from the same depth profile
+    if np.isfinite(e["front_back"]):
+        assert abs(summ["front_back"] - e["front_back"]) <= 2 * rel * abs(e["front_back"]), \
+            (summ["front_back"], e["front_back"])
+    assert abs(summ["L_opt"] - e["L_opt"]) <= rel * abs(e["L_opt"])
     if np.isfinite(summ["ratio"]):
         assert summ["ratio"] == pytest.approx(summ["identity_rhs"], rel=1e-12)
     assert summ["identity_rhs"] == pytest.approx(e["identity_rhs"], rel=rel) or not np.isfinite(e["identity_rhs"])
@@ -283,7 +313,8 @@ def test_bitwise_reproducible_and_tune_invariant(mask_m1):
     n = 200_000
     base = pm.run(d, OPT, n, SEED)
     F0, S0 = base.fluence.clone(), base.scalars.clone()
-    for t in (None, pm.Tune(64, 8, 32, 1), pm.Tune(512, 4, 1024, 64), pm.Tune(128, 32, 7, 33)):
+    for t in (None, pm.Tune(64, 8, 32, 1), pm.Tune(512, 4, 1024, 64), pm.Tune(128, 32, 7, 33),
+              pm.Tune(256, 16, 256, 16, 1), pm.Tune(256, 16, 256, 16, 64), pm.Tune(64, 4, 3, 2, 7)):
         r = pm.run(d, OPT, n, SEED, tune=t)
         assert torch.equal(r.fluence, F0) and torch.equal(r.scalars, S0), t
         # the deposit path (line-coalesced log or one atomic per visit) changes nothing either
@@ -363,6 +394,31 @@ def test_edge_cases(case):
         assert sc["R"] == oo["R"][0] and sc["T"] == oo["T"][0] and sc["A"] == oo["A"][0]
         return
     _compare_run(mask, opt, n, nbatch=8, rel=rel)
+
+
+def test_lost_weight_is_reported(mask_m1):
+    """A step cap that stops photons: the lost weight equals the oracle's (FP64 transport,
+    exact integers), closure stays exact, and the reduction reports MC_WARN_LOST, which
+    the binding raises as a warning."""
+    banner("step cap 40: lost weight, MC_WARN_LOST")
+    opt = pm.Optics(0.5, f32(0.01), f32(0.7), max_steps=40)
+    n = 20_000
+    d = dev(mask_m1)
+    res = pm.run(d, opt, n, SEED, fp64=True)
+    sc = res.scalar_dict()
+    ref = oracle.run(mask_m1, opt.mu_s, opt.mu_a, opt.g, n, SEED, max_steps=40, fluence=False)
+    tot = oracle.totals(ref)
+    assert sc["lost"] > 0 and closure(sc, n) == 0
+    for k in ("R", "T", "A", "RR", "lost", "steps"):
+        assert sc[k] == tot[k], k
+    with pytest.warns(pm.McLostWeightWarning):
+        summ = pm.reduce(d, res)
+    assert summ["status"] == pm.MC_WARN_LOST and summ["lost"] == sc["lost"] / (n * W1)
+    # without the cap nothing is lost and the status is clean
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("error", pm.McLostWeightWarning)
+        assert pm.reduce(d, pm.run(d, OPT, n, SEED))["status"] == 0
 
 
 def test_reduce_overflow_flag(mask_m1):

@@ -3,7 +3,7 @@ than itself:
 
 * the paper's worked values: kappa_CH = 0.1140 for d_target = 17.4 um at 1.45 um
   voxels (Eq. kappa_cal), dt = 0.0450 (App. A), the spinodal interval
-  (0.211, 0.789) and |f''(0.5)| = 1 (Sec. 2.3);
+  (0.211, 0.789) and |f''(0.5)| = 1 (Sec. 2.2);
 * exact conservation of the mean (the k = 0 mode of Eq. CH_spectral is untouched);
 * the discrete linear growth factor of a single small Fourier mode around the
   spinodal centre, (1 + dt k^2) / (1 + dt kappa k^4) per step, on each axis and a

@@ -59,6 +59,7 @@ MUTANTS = [
 # (name, file under oracle/, text, replacement, pin suites)
 CH = ["tests/test_oracle_ch.py"]
 AN = ["tests/test_oracle_analytics.py"]
+ES = ["tests/test_estimators_inputs.py"]
 PY_MUTANTS = [
     ("f_prime_sign", "cahn_hilliard.py", "return 2.0 * phi * (1.0 - phi) * (1.0 - 2.0 * phi)",
      "return 2.0 * phi * (1.0 - phi) * (2.0 * phi - 1.0)", CH),
@@ -81,6 +82,16 @@ PY_MUTANTS = [
     ("spearman_is_pearson", "analytics.py", "stats.spearmanr(f, d).statistic", "stats.pearsonr(f, d).statistic", AN),
     ("mask_psd_of_complement_mean", "analytics.py", "m = np.asarray(mask, dtype=np.float64)",
      "m = np.asarray(mask, dtype=np.float64) * 2.0", AN),
+    ("front_back_second_layer", "estimators.py", 'out["front_back"] = depth[0] / depth[-1]',
+     'out["front_back"] = depth[1] / depth[-1]', ES),
+    ("front_back_penultimate_layer", "estimators.py", 'out["front_back"] = depth[0] / depth[-1]',
+     'out["front_back"] = depth[0] / depth[-2]', ES),
+    ("l_opt_lateral_axis", "estimators.py", 'out["L_opt"] = out["phi1d"] * nz', 'out["L_opt"] = out["phi1d"] * nx', ES),
+    ("rms_log_unsquared", "estimators.py", "np.log(p[ok] / q[ok]) ** 2", "np.abs(np.log(p[ok] / q[ok]))", ES),
+    ("rms_depths_keep_zero_reference", "estimators.py", "ok = np.isfinite(q) & (q > 0) & np.isfinite(p)",
+     "ok = np.isfinite(q) & (q >= 0) & np.isfinite(p)", ES),
+    ("rms_w_unweighted", "estimators.py", "np.sqrt((q * (p - q) ** 2 / q ** 2).sum() / q.sum())",
+     "np.sqrt(((p - q) ** 2 / q ** 2).mean())", ES),
 ]
 
 

@@ -1,4 +1,4 @@
-"""The time gate of Eq. tend (host arithmetic of the binding) against the paper's
+"""The time gate of Eq. tend (mc_time_gate in the library) against the paper's
 printed values: t_end = 2.46e-10 s at phi = 0.70 and 8.21e-11 s at phi = 0.90
 (Sec. 2.5, "Photon budget, time gate and statistics"), from the shell values of
 Table 2 (mu_a = 5159 1/m, mu_s' = 20118 1/m, n_eff = 1.746) and the slab of
