@@ -194,6 +194,31 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
            void *workspace, size_t workspace_bytes, const mc_tune *tune, void *hip_stream);
 
 /*
+ * mc_run for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same walk
+ * and the same tallies, bit for bit, with no workspace argument.  The queue counter
+ * and the packed mask live in a fixed scratch array of 16 MiB + 256 bytes that the
+ * library holds on every GPU it runs on until the process ends; the call
+ * allocates nothing.  The fluence is deposited with one atomic per voxel visit straight into
+ * the caller's tally (MC_DIRECT_DEPOSIT), since the line-coalesced log would need a
+ * scratch tally as large as the fluence, so it runs slower than mc_run.
+ *   limit   the mask's 4x4x4 bricks, ceil(nx/4) ceil(ny/4) ceil(nz/4), at most
+ *           mc_run_noalloc_max_bricks() = 2^21 (e.g. 512 x 512 x 512 voxels);
+ *           larger volumes: MC_ENOSPACE, nothing enqueued
+ *   flags   MC_ACCUMULATE, MC_FP64 (MC_DIRECT_DEPOSIT is implied); MC_TIMED is
+ *           refused (its events would be allocated)
+ * Every call on one GPU uses that GPU's one scratch array (each call clears the
+ * queue counter and repacks the mask first), so calls that overlap on one GPU, on
+ * any streams, race and give wrong results: serialise them.  Other arguments and
+ * errors as mc_run.
+ */
+int mc_run_noalloc(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons,
+                   uint64_t seed, uint32_t stream_id, int flags, int64_t *fluence, int64_t *scalars,
+                   const mc_tune *tune, void *hip_stream);
+/* The largest brick count mc_run_noalloc accepts. */
+size_t mc_run_noalloc_max_bricks(void);
+
+/*
  * mc_run that also histograms the in-pore path of every escaping photon (fate R
  * or T) of the run (Sec. 3.5 (c)), with the bins of mc_escape_path_histogram
  * (analytics.h): bin b holds b * bin_width <= path < (b + 1) * bin_width, the

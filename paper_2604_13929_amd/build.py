@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libphotonmc.so")
 SOURCES = [os.path.join(CSRC, "photonmc.hip"), os.path.join(CSRC, "batch.hip"), os.path.join(CSRC, "spinodal.hip"),
-           os.path.join(CSRC, "analytics.hip"), os.path.join(CSRC, "metrics.hip")]
+           os.path.join(CSRC, "analytics.hip"), os.path.join(CSRC, "metrics.hip"),
+           os.path.join(CSRC, "noalloc.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("philox.hpp", "walk.hpp", "internal.hpp", "select.hpp")] + [
     os.path.join(INCLUDE, "photonmc.h"), os.path.join(INCLUDE, "spinodal.h"), os.path.join(INCLUDE, "analytics.h")]
 

@@ -91,6 +91,9 @@ _SIGS = {
     "mc_run_escape_histogram": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                                ctypes.c_uint32, ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P,
                                                ctypes.c_double, ctypes.c_int32, _P, _P, _P]),
+    "mc_run_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                      ctypes.c_int, _P, _P, _P, _P]),
+    "mc_run_noalloc_max_bricks": (ctypes.c_size_t, []),
     "mc_walk_elapsed_ms": (ctypes.c_int, [_P]),
     "mc_reduce_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_reduce": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -347,6 +350,30 @@ def run(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_be
         ms = ctypes.c_float(0.0)
         _check(L.mc_walk_elapsed_ms(ctypes.byref(ms)), "mc_walk_elapsed_ms")
         res.walk_ms = float(ms.value)
+    return res
+
+
+def run_noalloc(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_begin: int = 0,
+                stream_id: int = 0, accumulate: RunResult | None = None, tune: Tune | None = None,
+                fp64: bool = False) -> RunResult:
+    """mc_run_noalloc on the current stream: mc_run's tallies with no workspace (the
+    library's fixed per-GPU scratch; calls on one GPU must not overlap)."""
+    L = load()
+    vol = volume(mask)
+    dev = mask.device
+    if accumulate is None:
+        res = RunResult(torch.empty(tuple(mask.shape), dtype=torch.int64, device=dev),
+                        torch.empty(NSCALARS, dtype=torch.int64, device=dev))
+        flags = 0
+    else:
+        res, flags = accumulate, MC_ACCUMULATE
+    if fp64:
+        flags |= MC_FP64
+    opt = optics.c()
+    t = tune.c() if tune is not None else None
+    _check(L.mc_run_noalloc(ctypes.byref(vol), ctypes.byref(opt), photon_begin, n_photons, seed, stream_id, flags,
+                            res.fluence.data_ptr(), res.scalars.data_ptr(), ctypes.byref(t) if t is not None else None,
+                            _stream(dev)), "mc_run_noalloc")
     return res
 
 
