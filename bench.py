@@ -61,7 +61,7 @@ def walk_roofline(form: str, photon_steps: int, walk_ms: float):
     """Roofline of the batched or differentiated walk launch just timed: the algorithmic
     HBM rate (8 B per photon-step) against 8 TB/s, and the memory-side atomic request
     rate (requests per launch from the committed counter record of the same workload)
-    against the measured random-atomic ceiling; None for the latter when the kernel
+    against the measured ceiling for those requests; None for the latter when the kernel
     sources changed since the counters were taken."""
     achieved = photon_steps * BYTES_PER_STEP / (walk_ms * 1e-3) / 1e9
     out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -78,8 +78,8 @@ def walk_roofline(form: str, photon_steps: int, walk_ms: float):
     out["traffic"] = r["traffic_bytes_per_launch"] * photon_steps / r["photon_steps"]
     out["atomic_request_roof"] = {"requests_per_launch": req, "requests_per_step": req / photon_steps,
                                   "achieved_requests_per_s": req / (walk_ms * 1e-3),
-                                  "probe_requests_per_s": rec["probe_random_atomic64_128MiB_per_s"],
-                                  "frac": req / (walk_ms * 1e-3) / rec["probe_random_atomic64_128MiB_per_s"],
+                                  "ceiling_requests_per_s": rec["request_ceiling_per_s"],
+                                  "frac": req / (walk_ms * 1e-3) / rec["request_ceiling_per_s"],
                                   "source": os.path.relpath(FORMS_RECORD, ROOT)}
     return out
 
@@ -781,13 +781,14 @@ def main():
     if tr is not None:
         rec, traffic = tr
         line["roofline"]["traffic"] = traffic
-        # the binding limit: memory-side atomic requests (64-byte granules), measured by the scatter probe
+        # the binding limit: memory-side atomic requests (64-byte lines), against the rate the scatter
+        # probe measures for the walk's kind of request
         req = rec["atomic_requests_per_launch"] * n / rec["photons"]
         line["atomic_request_roof"] = {
             "requests_per_launch": req, "requests_per_step": req / steps_per_run,
             "achieved_requests_per_s": req / (walk_avg_ms * 1e-3),
-            "probe_requests_per_s": rec["probe_random_atomic64_128MiB_per_s"],
-            "frac": req / (walk_avg_ms * 1e-3) / rec["probe_random_atomic64_128MiB_per_s"],
+            "ceiling_requests_per_s": rec["request_ceiling_per_s"], "ceiling": rec["request_ceiling_source"],
+            "frac": req / (walk_avg_ms * 1e-3) / rec["request_ceiling_per_s"],
             "source": os.path.relpath(TRAFFIC_RECORD, ROOT)}
 
     if not args.no_rows:

@@ -37,7 +37,9 @@
  *   - Status: 0 ok, > 0 warning, < 0 error.  No entry point throws.  On error
  *     nothing is enqueued and mc_last_error() (thread-local) explains why.
  *   - Weights are integers in units of 2^-31 of a launched photon (Q31).  The
- *     fluence tally is int64, in Q31 weight x voxel length.  Integer atomics
+ *     fluence tally is int64, in Q31 weight x voxel length; each track segment's
+ *     deposit w d is rounded to a whole multiple of MC_DEPOSIT_QUANTUM Q31 units
+ *     (2^-23 of a launched photon x voxel) before it is added.  Integer atomics
  *     make every result independent of scheduling: a run is bitwise
  *     reproducible and a run split into photon ranges sums to the whole.
  *   - Coordinates: voxel (x, y, z), x fastest; z = 0 is the illuminated face.
@@ -67,7 +69,10 @@ extern "C" {
 #define MC_TIMED 2          /* time the walk kernel with HIP events on the run's stream (mc_walk_elapsed_ms) */
 #define MC_FP64 4           /* geometry and scattering in FP64 instead of FP32 (reference transport) */
 #define MC_DIRECT_DEPOSIT 8 /* one atomic per voxel visit into the caller's tally, not the line-coalesced
-                               deposit log (the log is used when the bricked tally has <= 2^32 words) */
+                               deposit log into a staging tally of uint32 words (the log is used when that
+                               staging tally, 2 x 2 x 4 voxels per 64-byte line, has <= 2^32 words) */
+
+#define MC_DEPOSIT_QUANTUM 256 /* Q31 units: every tally value is a multiple of it */
 
 /* Scalar tally channels: int64 words in a caller-owned device array of
  * MC_NSCALARS entries.  Weight channels are Q31.  For every run

@@ -53,7 +53,7 @@ REC_DTYPE = np.dtype([("ix", "<i4"), ("iy", "<i4"), ("iz", "<i4"), ("event", "<i
 PHOTON_DTYPE = np.dtype([("R", "<i8"), ("T", "<i8"), ("A", "<i8"), ("RR", "<i8"), ("lost", "<i8"),
                          ("w_final", "<i8"), ("steps", "<u8"), ("interactions", "<u8"),
                          ("path_void", "<f8"), ("path_solid", "<f8"), ("min_gap", "<f8"),
-                         ("fate", "<i4"), ("pad", "<i4")])
+                         ("max_visit", "<f8"), ("fate", "<i4"), ("pad", "<i4")])
 
 
 STATE_DTYPE = np.dtype([("ix", "<i8"), ("iy", "<i8"), ("iz", "<i8"),

@@ -166,6 +166,8 @@ typedef struct {
     uint64_t steps, interactions;
     double path_void, path_solid;
     double min_gap;              /* smallest tie gap over the whole walk (see orc_rec) */
+    double max_visit;            /* largest weight x path deposited between two face crossings (one
+                                    stay in a voxel), weight units 2^-31 x voxel: a diagnostic output */
     int32_t fate;                /* final event */
     int32_t pad;
 } orc_photon;
@@ -583,10 +585,15 @@ static void walk(const orc_problem *P, uint64_t photon, orc_sink *S)
     memset(&me, 0, sizeof me);
     me.min_gap = INFINITY;
     int event;
+    double visit = 0.0;   /* deposited during the current stay in a voxel */
     for (;;) {
         double gap;
+        const double w0 = (double)st.w, path0 = st.l_void + st.l_solid;
         event = step(P, photon, &st, S, &me, &gap);
         if (gap < me.min_gap) me.min_gap = gap;
+        visit += w0 * ((st.l_void + st.l_solid) - path0);
+        if (visit > me.max_visit) me.max_visit = visit;
+        if (event == EV_FACE_X || event == EV_FACE_Y || event == EV_FACE_Z) visit = 0.0;
         if (terminal(event)) break;
     }
     S->sums->ich[ORC_STEPS] += (int64_t)st.steps;

@@ -51,23 +51,24 @@ struct BatchTallySink {
     template <typename R> __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
     {
         if (a != 0ull)
-            __hip_atomic_fetch_add((unsigned long long *)(J.fluence + voxel_index(J, p)), (unsigned long long)a,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add((unsigned long long *)(J.fluence + voxel_index(J, p)),
+                                   (unsigned long long)a << kDepositShift, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
 
 // Line-coalesced deposits for the batch: as the plain walk's log (8-byte
-// entries, a 16-iteration window), with the job index in the top 6 bits of the
-// 32-bit entry index, which leaves 26 bits for the word index into the job's
-// bricked tally (the batch logs only when every job's tally is that small).  A
-// value of 2^32 or more goes to the tally directly.  The window's 33 KB of LDS
-// per 256-thread workgroup, with the job table and the per-job channels,
-// still lets three workgroups share a CU.
+// entries, a 16-iteration window, uint32 staging words in lines of 2x2x4 voxels,
+// carries of wrapped words into the job's int64 tally), with the job index in the
+// top 6 bits of the 32-bit entry index, which leaves 26 bits for the word index
+// into the job's staging tally (the batch logs only when every job's staging
+// tally is that small).  A deposit of 2^32 quanta or more goes to the job's tally
+// directly.  The window's 33 KB of LDS per 256-thread workgroup, with the job
+// table and the per-job channels, still lets three workgroups share a CU.
 constexpr int kBLogK = 16;
 constexpr int kBLogStride = 65;
 constexpr int kJobShift = 26;
 constexpr uint32_t kIdxMask = (1u << kJobShift) - 1u;
-constexpr uint64_t kBatchLogWords = 1ull << kJobShift;   // largest tally a logged batch job may have
+constexpr uint64_t kBatchLogWords = 1ull << kJobShift;   // largest staging tally a logged batch job may have
 
 struct BatchLoggedSink {
     uint32_t *lidx;
@@ -79,12 +80,12 @@ struct BatchLoggedSink {
     template <typename R> __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
     {
         if (a != 0ull) {
-            const uint32_t idx = tally_brick_index(J.tnxb, J.tnyb, p.ix, p.iy, p.iz);
             if (a >> 32) {
-                __hip_atomic_fetch_add((unsigned long long *)(J.fluence + idx), (unsigned long long)a,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add((unsigned long long *)(J.fluence + voxel_index(J, p)),
+                                       (unsigned long long)a << kDepositShift, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                lidx[slot] = idx | tag;
+                lidx[slot] = stage_index(J.lnx, J.lny, p.ix, p.iy, p.iz) | tag;
                 lval[slot] = (uint32_t)a;
             }
         }
@@ -95,17 +96,37 @@ __device__ __forceinline__ void flush_batch_log(uint32_t *lidx, uint32_t *lval, 
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    // in two halves, each issuing its adds before it looks at what they returned
 #pragma unroll
-    for (int i = 0; i < kBLogK; ++i) {
-        const uint32_t src = (uint32_t)i * (64 / kBLogK) + lane / kBLogK;
-        const uint32_t e = (lane % kBLogK) * kBLogStride + src;
-        const uint32_t v = lval[e];
-        if (v) {
-            const uint32_t w = lidx[e];
-            int64_t *tally = jobs[w >> kJobShift].fluence;
-            __hip_atomic_fetch_add((unsigned long long *)(tally + (w & kIdxMask)), (unsigned long long)v,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            lval[e] = 0u;
+    for (int h = 0; h < kBLogK; h += kBLogK / 2) {
+        uint32_t old[kBLogK / 2];
+#pragma unroll
+        for (int i = 0; i < kBLogK / 2; ++i) {
+            const uint32_t src = (uint32_t)(h + i) * (64 / kBLogK) + lane / kBLogK;
+            const uint32_t e = (lane % kBLogK) * kBLogStride + src;
+            const uint32_t v = lval[e];
+            old[i] = 0u;
+            if (v) {
+                const uint32_t w = lidx[e];
+                old[i] = __hip_atomic_fetch_add(jobs[w >> kJobShift].stage + (w & kIdxMask), v, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kBLogK / 2; ++i) {
+            const uint32_t src = (uint32_t)(h + i) * (64 / kBLogK) + lane / kBLogK;
+            const uint32_t e = (lane % kBLogK) * kBLogStride + src;
+            const uint32_t v = lval[e];
+            if (v) {
+                if (old[i] > 0xFFFFFFFFu - v) {
+                    // the word wrapped: its lost 2^32 quanta go to the voxel's int64 word
+                    const uint32_t w = lidx[e];
+                    const Job &J = jobs[w >> kJobShift];
+                    __hip_atomic_fetch_add((unsigned long long *)(J.fluence + stage_voxel(J, w & kIdxMask)),
+                                           1ull << (32 + kDepositShift), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                lval[e] = 0u;
+            }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -270,8 +291,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t jobs_off, bricks_off[MC_MAX_BATCH_JOBS], bins_off[MC_MAX_BATCH_JOBS], tally_off[MC_MAX_BATCH_JOBS], total;
-    bool logged;   // every job's bricked tally fits the log's 26-bit indices
+    size_t jobs_off, bricks_off[MC_MAX_BATCH_JOBS], bins_off[MC_MAX_BATCH_JOBS], stage_off[MC_MAX_BATCH_JOBS], total;
+    bool logged;   // every job's staging tally fits the log's 26-bit indices
 };
 
 Layout layout_of(const mc_job *jobs, int32_t n)
@@ -281,15 +302,15 @@ Layout layout_of(const mc_job *jobs, int32_t n)
     L.jobs_off = off;
     off += align_up(sizeof(Job) * MC_MAX_BATCH_JOBS);
     L.logged = true;
-    for (int32_t i = 0; i < n; ++i) L.logged = L.logged && dims_of(&jobs[i].vol).tally_words <= kBatchLogWords;
+    for (int32_t i = 0; i < n; ++i) L.logged = L.logged && dims_of(&jobs[i].vol).stage_words <= kBatchLogWords;
     for (int32_t i = 0; i < n; ++i) {
         const Dims d = dims_of(&jobs[i].vol);
         L.bricks_off[i] = off;
         off += align_up(d.nbricks * sizeof(uint64_t));
         L.bins_off[i] = off;
         off += align_up((size_t)jobs[i].vol.nz * kBinW * sizeof(uint64_t));
-        L.tally_off[i] = off;
-        if (L.logged) off += align_up(d.tally_words * sizeof(int64_t));
+        L.stage_off[i] = off;
+        if (L.logged) off += align_up(d.stage_words * sizeof(uint32_t));
     }
     L.total = off;
     return L;
@@ -340,7 +361,8 @@ int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, Prepared *
         if (!jb.fluence || !jb.scalars) return fail(MC_EINVAL, "job %d: fluence and scalars must be non-NULL", i);
         if (J.max_steps > (1u << 26)) return fail(MC_EINVAL, "job %d: batch jobs allow max_steps <= 2^26", i);
         J.bricks = (const uint64_t *)(ws + P->L.bricks_off[i]);
-        J.fluence = P->L.logged ? (int64_t *)(ws + P->L.tally_off[i]) : jb.fluence;
+        J.fluence = jb.fluence;
+        J.stage = P->L.logged ? (uint32_t *)(ws + P->L.stage_off[i]) : nullptr;
         J.scalars = jb.scalars;
         J.queue_begin = q;
         q += jb.n_photons;
@@ -432,10 +454,11 @@ int enqueue_batch(const mc_job *jobs, const Prepared &P, char *ws, const mc_tune
         const mc_job &jb = jobs[i];
         const Dims d = dims_of(&jb.vol);
         if (!jb.accumulate) {
-            if (!P.L.logged && (rc = fill(jb.fluence, d.nvox, s))) return rc;
+            if ((rc = fill(jb.fluence, d.nvox, s))) return rc;
             if ((rc = fill(jb.scalars, MC_NSCALARS, s))) return rc;
         }
-        if (P.L.logged && (rc = fill((int64_t *)(ws + P.L.tally_off[i]), d.tally_words, s))) return rc;
+        // the staging words as int64 pairs: a line is 16 words, so the count is even
+        if (P.L.logged && (rc = fill((int64_t *)(ws + P.L.stage_off[i]), d.stage_words / 2, s))) return rc;
         if ((rc = pack(&jb.vol, (uint64_t *)(ws + P.L.bricks_off[i]), s))) return rc;
     }
     const bool timed = (flags & MC_TIMED) != 0;
@@ -445,8 +468,7 @@ int enqueue_batch(const mc_job *jobs, const Prepared &P, char *ws, const mc_tune
     if (P.L.logged) {
         for (int32_t i = 0; i < n; ++i) {
             const mc_job &jb = jobs[i];
-            if ((rc = unbrick((const int64_t *)(ws + P.L.tally_off[i]), jb.fluence, &jb.vol, jb.accumulate != 0, s)))
-                return rc;
+            if ((rc = unstage((const uint32_t *)(ws + P.L.stage_off[i]), jb.fluence, &jb.vol, s))) return rc;
         }
     }
     for (int32_t i = 0; i < n; ++i) {

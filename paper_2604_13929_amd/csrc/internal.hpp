@@ -26,12 +26,12 @@ constexpr int kBinW = 8;              // int64 words per depth bin of the reduct
 struct Dims {
     int32_t nxb, nyb, nzb;       // 4x4x4 mask bricks
     uint64_t nbricks, nvox;
-    int32_t tnxb, tnyb, tnzb;    // 2x2x2 tally bricks
-    uint64_t tally_words;        // int64 words of the bricked tally
-    bool logged;                 // the bricked tally fits 32-bit indices
+    int32_t lnx, lny, lnz;       // staging lines of 2x2x4 voxels
+    uint64_t stage_words;        // uint32 words of the staging tally
+    bool logged;                 // the staging tally fits 32-bit indices
 };
 size_t run_workspace_bytes(const Dims &d);
-size_t tally_offset(const Dims &d);
+size_t stage_offset(const Dims &d);
 Dims dims_of(const mc_volume *v);
 int check_volume(const mc_volume *v);
 int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, uint64_t n_photons, uint64_t seed,
@@ -48,7 +48,7 @@ int check_tune(const mc_tune &t);
 // asynchronous building blocks on a stream
 int fill(int64_t *p, uint64_t n, hipStream_t s);
 int pack(const mc_volume *vol, uint64_t *bricks, hipStream_t s);
-int unbrick(const int64_t *tally, int64_t *fluence, const mc_volume *vol, bool accumulate, hipStream_t s);
+int unstage(const uint32_t *stage, int64_t *fluence, const mc_volume *vol, hipStream_t s);
 // zero (unless accumulating), pack, walk and move the staged tally into the caller's
 // fluence, with the queue, packed mask and staging tally in the workspace ws
 int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws, unsigned long long *grad_bins,

@@ -86,46 +86,53 @@ __global__ void k_pack(const uint8_t *__restrict__ mask, int32_t nx, int32_t ny,
     bricks[b] = bits;
 }
 
-// Bricked tally -> the caller's [nz][ny][nx] tally (assign, or add when accumulating).
-__global__ void k_unbrick(const int64_t *__restrict__ T, int64_t *__restrict__ F, int32_t nx, int32_t ny, int32_t nz,
-                          int32_t tnxb, int32_t tnyb, int32_t accumulate)
+// Staged quanta -> the caller's [nz][ny][nx] tally in Q31 units: F += S << shift.
+// The walk has already added there what the staging words could not hold (whole
+// 2^32-quanta carries and deposits of 2^32 quanta or more).
+__global__ void k_unstage(const uint32_t *__restrict__ S, int64_t *__restrict__ F, int32_t nx, int32_t ny, int32_t nz,
+                          int32_t lnx, int32_t lny)
 {
     const uint64_t n = (uint64_t)nx * ny * nz;
     for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x) {
         const int32_t x = (int32_t)(v % (uint64_t)nx);
         const int32_t y = (int32_t)((v / (uint64_t)nx) % (uint64_t)ny);
         const int32_t z = (int32_t)(v / ((uint64_t)nx * ny));
-        const int64_t t = T[tally_brick_index(tnxb, tnyb, x, y, z)];
-        F[v] = accumulate ? F[v] + t : t;
+        F[v] += (int64_t)S[stage_index(lnx, lny, x, y, z)] << kDepositShift;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Sinks: where a step's side effects go
 // ---------------------------------------------------------------------------
-// Fluence deposits straight to the caller's [nz][ny][nx] tally, one device-scope
-// atomic per voxel visit.
+// Fluence deposits straight to the caller's [nz][ny][nx] tally (Q31 units), one
+// device-scope atomic per voxel visit.
 struct DirectDeposit {
     template <typename R>
     __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
     {
         if (a != 0ull)
-            __hip_atomic_fetch_add((unsigned long long *)(J.fluence + voxel_index(J, p)), (unsigned long long)a,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add((unsigned long long *)(J.fluence + voxel_index(J, p)),
+                                   (unsigned long long)a << kDepositShift, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
 
-// Fluence deposits logged in LDS, one slot per lane and iteration, into a tally
-// of 2x2x2 bricks; every kLogK iterations the wavefront issues the log with
-// lanes transposed so that one atomic instruction carries kLogK successive
-// deposits of each of 64/kLogK lanes: deposits of one photon that fall in the
-// same brick (the same 64-byte line) then travel as one memory-side request.
-// A log entry is a 32-bit tally index and a 32-bit value: one segment deposits
-// less than 2^31 * sqrt(3) < 2^32; a photon's deposits in one voxel summed over
-// several segments can exceed that, and then go to the tally directly.  At 16
-// iterations a 256-thread workgroup's log takes 33 KB, so four workgroups fit
-// per CU.  A window of 32 (fewer requests, two workgroups per CU) measured no
-// faster on the 256^3 workload: 2024 against 2016 ms per 1e8 photons.
+// Fluence deposits logged in LDS, one slot per lane and iteration, for a staging
+// tally of uint32 quanta in lines of 2x2x4 voxels (16 words, one 64-byte line);
+// every kLogK iterations the wavefront issues the log with lanes transposed so
+// that one atomic instruction carries kLogK successive deposits of each of
+// 64/kLogK lanes: deposits of one photon that fall in the same line travel as one
+// memory-side request.  A line holds twice the voxels a line of int64 words would
+// (0.40 against 0.48 requests per photon-step over oracle trajectories of the
+// 256^3 workload), and 16-lane groups of 32-bit atomics on one line run at
+// 26.5 G requests/s against 23.7 for 8-lane groups of 64-bit atomics.
+// A word cannot hold a voxel's sum: the flush reads back each word's previous
+// value and, where an add wrapped it past 2^32, adds the lost 2^32 quanta to the
+// caller's int64 tally, so the total stays exact (a quantum of 2^8 Q31 units makes
+// that about one carry per 2000 photon-steps).  A log entry is a 32-bit word
+// index and a 32-bit value; a photon's deposit in one voxel of 2^32 quanta or more
+// (512 voxel lengths at full weight) goes to the int64 tally directly.  At 16
+// iterations a 256-thread workgroup's log takes 33 KB, so four workgroups fit per
+// CU.
 #ifndef MC_LOG_K
 #define MC_LOG_K 16
 #endif
@@ -141,32 +148,52 @@ struct LoggedDeposit {
     __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
     {
         if (a != 0ull) {
-            const uint32_t idx = tally_brick_index(J.tnxb, J.tnyb, p.ix, p.iy, p.iz);
             if (a >> 32) {
-                __hip_atomic_fetch_add((unsigned long long *)(J.fluence + idx), (unsigned long long)a,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add((unsigned long long *)(J.fluence + voxel_index(J, p)),
+                                       (unsigned long long)a << kDepositShift, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                lidx[slot] = idx;
+                lidx[slot] = stage_index(J.lnx, J.lny, p.ix, p.iy, p.iz);
                 lval[slot] = (uint32_t)a;
             }
         }
     }
 };
 
+// The carry of a staging word that wrapped: 2^32 quanta into the voxel's int64 word.
+__device__ __forceinline__ void stage_carry(const Job &J, uint32_t idx)
+{
+    __hip_atomic_fetch_add((unsigned long long *)(J.fluence + stage_voxel(J, idx)), 1ull << (32 + kDepositShift),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int K>
-__device__ __forceinline__ void flush_log(uint32_t *lidx, uint32_t *lval, int64_t *tally, uint32_t lane)
+__device__ __forceinline__ void flush_log(uint32_t *lidx, uint32_t *lval, const Job &J, uint32_t lane)
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    // in two halves, each issuing its adds before it looks at what they returned
+    // (half the returned words live at a time keeps the walk within 128 VGPRs)
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const uint32_t src = (uint32_t)i * (64 / K) + lane / K;
-        const uint32_t e = (lane % K) * kLogStride + src;
-        const uint32_t v = lval[e];
-        if (v) {
-            __hip_atomic_fetch_add((unsigned long long *)(tally + lidx[e]), (unsigned long long)v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            lval[e] = 0u;
+    for (int h = 0; h < K; h += K / 2) {
+        uint32_t old[K / 2];
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i) {
+            const uint32_t src = (uint32_t)(h + i) * (64 / K) + lane / K;
+            const uint32_t e = (lane % K) * kLogStride + src;
+            const uint32_t v = lval[e];
+            old[i] = 0u;
+            if (v) old[i] = __hip_atomic_fetch_add(J.stage + lidx[e], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i) {
+            const uint32_t src = (uint32_t)(h + i) * (64 / K) + lane / K;
+            const uint32_t e = (lane % K) * kLogStride + src;
+            const uint32_t v = lval[e];
+            if (v) {
+                if (old[i] > 0xFFFFFFFFu - v) stage_carry(J, lidx[e]);
+                lval[e] = 0u;
+            }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -277,7 +304,7 @@ template <bool GRAD, bool LOGGED> struct SinkOf {
     using type = typename std::conditional<GRAD, GradSink<Deposit>, TallySink<Deposit>>::type;
 };
 
-// LOGGED: J.fluence is the bricked tally (see LoggedDeposit).  GENERAL: the
+// LOGGED: deposits go through the log into J.stage (see LoggedDeposit).  GENERAL: the
 // step that also knows the paper's boundary model (see walk.hpp).
 // ESC: also bin the in-pore path of every escaping photon (EscHist).
 template <int BLOCK, typename R, bool GRAD, bool LOGGED, bool GENERAL, bool ESC>
@@ -386,10 +413,10 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
             }
         }
         if constexpr (LOGGED) {
-            if (++iter % K == 0) flush_log<K>(lidx, lval, J.fluence, lane);
+            if (++iter % K == 0) flush_log<K>(lidx, lval, J, lane);
         }
     }
-    if constexpr (LOGGED) flush_log<K>(lidx, lval, J.fluence, lane);
+    if constexpr (LOGGED) flush_log<K>(lidx, lval, J, lane);
     __syncthreads();
     if (threadIdx.x < MC_NSCALARS) {
         const unsigned long long v = acc[threadIdx.x];
@@ -718,21 +745,21 @@ Dims dims_of(const mc_volume *v)
     d.nzb = (v->nz + 3) / 4;
     d.nbricks = (uint64_t)d.nxb * d.nyb * d.nzb;
     d.nvox = (uint64_t)v->nx * v->ny * v->nz;
-    d.tnxb = (v->nx + 1) / 2;
-    d.tnyb = (v->ny + 1) / 2;
-    d.tnzb = (v->nz + 1) / 2;
-    d.tally_words = (uint64_t)d.tnxb * d.tnyb * d.tnzb * 8;
-    d.logged = d.tally_words <= (1ull << 32);
+    d.lnx = (v->nx + 1) / 2;
+    d.lny = (v->ny + 1) / 2;
+    d.lnz = (v->nz + 3) / 4;
+    d.stage_words = (uint64_t)d.lnx * d.lny * d.lnz * 16;
+    d.logged = d.stage_words <= (1ull << 32);
     return d;
 }
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-size_t tally_offset(const Dims &d) { return kHeaderBytes + align256(d.nbricks * sizeof(uint64_t)); }
+size_t stage_offset(const Dims &d) { return kHeaderBytes + align256(d.nbricks * sizeof(uint64_t)); }
 
 size_t run_workspace_bytes(const Dims &d)
 {
-    return tally_offset(d) + (d.logged ? align256(d.tally_words * sizeof(int64_t)) : 0);
+    return stage_offset(d) + (d.logged ? align256(d.stage_words * sizeof(uint32_t)) : 0);
 }
 
 int check_volume(const mc_volume *v)
@@ -785,8 +812,8 @@ int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, 
     J->nz = vol->nz;
     J->nxb = d.nxb;
     J->nyb = d.nyb;
-    J->tnxb = d.tnxb;
-    J->tnyb = d.tnyb;
+    J->lnx = d.lnx;
+    J->lny = d.lny;
     const double mu_s = opt->mu_s, mu_a = opt->mu_a, mu_t = mu_s + mu_a;
     J->mu_t = mu_t;
     J->mu_s = mu_s;
@@ -972,7 +999,7 @@ int launch_walk(const Job &J, unsigned long long *queue, const mc_tune &t, hipSt
 }
 
 // Zero the tallies (unless accumulating), pack the mask, walk, and for the
-// logged deposit path move the bricked tally into the caller's layout.
+// logged deposit path add the staged quanta to the caller's tally.
 int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws, unsigned long long *grad_bins,
              hipStream_t s, const EscHist *esc)
 {
@@ -980,32 +1007,32 @@ int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws,
     const bool logged = d.logged && !(flags & MC_DIRECT_DEPOSIT);
     unsigned long long *queue = (unsigned long long *)ws;
     uint64_t *bricks = (uint64_t *)(ws + kHeaderBytes);
-    int64_t *tally = (int64_t *)(ws + tally_offset(d));
-    int64_t *fluence = J.fluence;
+    uint32_t *stage = (uint32_t *)(ws + stage_offset(d));
     int rc;
     if (!(flags & MC_ACCUMULATE)) {
-        if (!logged && (rc = fill(fluence, d.nvox, s))) return rc;
+        if ((rc = fill(J.fluence, d.nvox, s))) return rc;
         if ((rc = fill(J.scalars, MC_NSCALARS, s))) return rc;
         if (grad_bins && (rc = fill((int64_t *)grad_bins, (uint64_t)12 * vol->nz, s))) return rc;
         if (esc && (rc = fill((int64_t *)esc->w, (uint64_t)esc->nbins, s))) return rc;
         if (esc && (rc = fill((int64_t *)esc->n, (uint64_t)esc->nbins, s))) return rc;
     }
-    if (logged && (rc = fill(tally, d.tally_words, s))) return rc;
+    // the staging words as int64 pairs: a line is 16 words, so the count is even
+    if (logged && (rc = fill((int64_t *)stage, d.stage_words / 2, s))) return rc;
     if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
     if ((rc = pack(vol, bricks, s))) return rc;
     J.bricks = bricks;
-    if (logged) J.fluence = tally;
+    J.stage = logged ? stage : nullptr;
     if ((rc = launch_walk(J, queue, t, s, flags, grad_bins, logged, esc))) return rc;
-    if (logged) return unbrick(tally, fluence, vol, (flags & MC_ACCUMULATE) != 0, s);
+    if (logged) return unstage(stage, J.fluence, vol, s);
     return MC_OK;
 }
 
-int unbrick(const int64_t *tally, int64_t *fluence, const mc_volume *vol, bool accumulate, hipStream_t s)
+int unstage(const uint32_t *stage, int64_t *fluence, const mc_volume *vol, hipStream_t s)
 {
     const Dims d = dims_of(vol);
     const uint64_t blocks = std::min<uint64_t>((d.nvox + 255) / 256, 16384);
-    hipLaunchKernelGGL(k_unbrick, dim3((unsigned)blocks), dim3(256), 0, s, tally, fluence, vol->nx, vol->ny, vol->nz,
-                       d.tnxb, d.tnyb, accumulate ? 1 : 0);
+    hipLaunchKernelGGL(k_unstage, dim3((unsigned)blocks), dim3(256), 0, s, stage, fluence, vol->nx, vol->ny, vol->nz,
+                       d.lnx, d.lny);
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }
@@ -1055,7 +1082,7 @@ void mc_tune_default(mc_tune *t)
     t->waves_per_cu = 16;
     t->chunk = 256;
     t->refill = 16;
-    t->defer = 1;
+    t->defer = 4;
 }
 
 size_t mc_run_workspace_bytes(const mc_volume *vol)

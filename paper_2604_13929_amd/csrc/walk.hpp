@@ -60,10 +60,11 @@ __device__ __forceinline__ int escape_path_bin(double pv, double width, int nbin
 struct Job {
     const uint64_t *bricks;   // 4x4x4 bit bricks, 1 = pore
     int64_t *fluence;         // [nz][ny][nx]
+    uint32_t *stage;          // staging tally of the logged deposits (lines of 2x2x4 words), or NULL
     int64_t *scalars;         // [MC_NSCALARS]
     int32_t nx, ny, nz;
     int32_t nxb, nyb;         // bricks along x and y
-    int32_t tnxb, tnyb;       // 2x2x2 tally bricks along x and y (logged deposits)
+    int32_t lnx, lny;         // staging lines along x and y
     double mu_t;              // mu_s + mu_a of the solid, summed in FP64 on the host
     double mu_s;              // mu_s of the solid (the gradient walk's score)
     float g;
@@ -98,7 +99,7 @@ struct Photon {
     uint32_t w, k, steps, pid;
     uint64_t absorbed;        // weight absorbed by this photon so far
     int64_t rr;               // roulette balance of this photon
-    uint64_t acc;             // deposit in the current voxel not yet flushed
+    uint64_t acc;             // deposit in the current voxel not yet flushed, in quanta
     uint32_t brick;           // index of the cached brick
     uint32_t solid;           // current voxel is solid
     uint64_t bits;            // cached brick
@@ -166,12 +167,30 @@ __device__ __forceinline__ uint64_t voxel_index(const Job &J, const Photon<R> &p
     return ((uint64_t)p.iz * (uint64_t)J.ny + (uint64_t)p.iy) * (uint64_t)J.nx + (uint64_t)p.ix;
 }
 
-// Index in a tally stored as 2x2x2 bricks of int64, one brick per 64-byte line,
-// so that successive deposits of a photon tend to share a line.
-__device__ __forceinline__ uint32_t tally_brick_index(int32_t tnxb, int32_t tnyb, int32_t ix, int32_t iy, int32_t iz)
+// A segment's track-length deposit w d is rounded to a whole number of quanta of
+// 2^kDepositShift Q31 weight x voxel (2^-23 of a launched photon x voxel); the
+// tallies hold Q31 units, so every tally value is a multiple of the quantum.
+constexpr int kDepositShift = 8;
+
+// Index in the staging tally of the logged deposits: uint32 words in lines of
+// 2 x 2 x 4 voxels (x, y, z), one line = 16 words = one 64-byte memory-side atomic
+// request, so that successive deposits of a photon tend to share a line.
+__host__ __device__ __forceinline__ uint32_t stage_index(int32_t lnx, int32_t lny, int32_t ix, int32_t iy, int32_t iz)
 {
-    const uint32_t b = ((uint32_t)(iz >> 1) * (uint32_t)tnyb + (uint32_t)(iy >> 1)) * (uint32_t)tnxb + (uint32_t)(ix >> 1);
-    return (b << 3) | ((uint32_t)(iz & 1) << 2) | ((uint32_t)(iy & 1) << 1) | (uint32_t)(ix & 1);
+    const uint32_t line = ((uint32_t)(iz >> 2) * (uint32_t)lny + (uint32_t)(iy >> 1)) * (uint32_t)lnx + (uint32_t)(ix >> 1);
+    return (line << 4) | ((uint32_t)(iz & 3) << 2) | ((uint32_t)(iy & 1) << 1) | (uint32_t)(ix & 1);
+}
+
+// The voxel, as an index of the [nz][ny][nx] tally, of a staging word.
+__device__ __forceinline__ uint64_t stage_voxel(const Job &J, uint32_t idx)
+{
+    const uint32_t line = idx >> 4, off = idx & 15u;
+    const uint32_t t = line / (uint32_t)J.lnx;
+    const uint64_t x = (uint64_t)(line - t * (uint32_t)J.lnx) * 2 + (off & 1u);
+    const uint32_t bz = t / (uint32_t)J.lny;
+    const uint64_t y = (uint64_t)(t - bz * (uint32_t)J.lny) * 2 + ((off >> 1) & 1u);
+    const uint64_t z = (uint64_t)bz * 4 + (off >> 2);
+    return (z * (uint64_t)J.ny + y) * (uint64_t)J.nx + x;
 }
 
 __device__ __forceinline__ double free_path(const Job &J, uint32_t r)
@@ -344,8 +363,8 @@ __device__ __forceinline__ int32_t advance(Photon<R> &p, const Job &J, Sink &sin
 
     sink.segment(p, J, d, solid);
     if (in_slab) {
-        // track-length deposit, quantised per segment, accumulated while in this voxel
-        p.acc += r_to_u64((R)p.w * d);
+        // track-length deposit, rounded to whole quanta per segment, accumulated while in this voxel
+        p.acc += r_to_u64((R)p.w * d * (R)(1.0 / (1 << kDepositShift)));
         if (solid) p.s_rem = fmax(p.s_rem - (double)d, 0.0);
         else p.l_void += (double)d;
         p.l_tot += (double)d;

@@ -22,6 +22,8 @@ MC_ACCUMULATE = 1
 MC_TIMED = 2
 MC_FP64 = 4
 MC_DIRECT_DEPOSIT = 8
+#: Q31 units per deposit quantum: each segment's deposit is rounded to a multiple of it
+DEPOSIT_QUANTUM = 256
 NSCALARS = 16
 NSUMMARY = 32
 SCALARS = ["R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_w_void_path_lo", "esc_n", "esc_n_gtL",

@@ -90,9 +90,10 @@ def test_run_rejects_bad_tune(lib):
 
 def test_workspace_sizes(lib):
     vol = pm.McVolume(9, 5, 7, 0, 1)
-    # header + one uint64 per 4x4x4 mask brick (3 x 2 x 2 bricks, padded to 256 bytes) + the tally in
-    # 2x2x2 bricks of int64 (5 x 3 x 4 bricks)
-    assert lib.mc_run_workspace_bytes(ctypes.byref(vol)) == 256 + 256 + 5 * 3 * 4 * 8 * 8
+    # header + one uint64 per 4x4x4 mask brick (3 x 2 x 2 bricks, padded to 256 bytes) + the staging
+    # tally in lines of 2x2x4 uint32 words (5 x 3 x 2 lines of 16 words, padded to 256 bytes)
+    assert lib.mc_run_workspace_bytes(ctypes.byref(vol)) == 256 + 256 + 2048
+    assert 5 * 3 * 2 * 16 * 4 == 1920
     assert lib.mc_reduce_workspace_bytes(ctypes.byref(vol)) == 7 * 8 * 8
     bad = pm.McVolume(0, 5, 7, 0, 1)
     assert lib.mc_run_workspace_bytes(ctypes.byref(bad)) == 0

@@ -47,8 +47,8 @@ def small_jobs():
 
 
 W1 = 2 ** 31
-# the largest rounding 4096 segments' deposits can add up to (each rounded to a whole tally unit)
-ROUNDING_4096 = 0.5 * 4096
+# the largest rounding 4096 segments' deposits can add up to (each rounded to a whole deposit quantum)
+ROUNDING_4096 = 0.5 * pm.DEPOSIT_QUANTUM * 4096
 
 
 @pytest.fixture(scope="module")
@@ -258,14 +258,14 @@ def test_autotune_returns_usable_shape(small_jobs, tmp_path, monkeypatch):
 
 
 def test_oversize_job_takes_the_direct_path():
-    """A job whose bricked tally exceeds the log's 26-bit indices (here 512 x 512 x 258
+    """A job whose staging tally exceeds the log's 26-bit indices (here 512 x 512 x 258
     voxels) sends the whole batch through one atomic per voxel visit; every job must
     still equal its plain run (which logs) bit for bit."""
     banner("batch with a 512x512x258 job (direct deposits) == plain runs")
     g = torch.Generator(device="cuda").manual_seed(5)
     big = (torch.rand((258, 512, 512), generator=g, device="cuda") < 0.7).to(torch.uint8)
     small = torch.from_numpy(inputs.spinodal_mask(16, 16, 16, 8.0, 0.7, seed=3)).cuda()
-    assert ((258 + 1) // 2) * 256 * 256 * 8 > 2 ** 26          # more tally words than a log index holds
+    assert ((258 + 3) // 4) * 256 * 256 * 16 > 2 ** 26         # more staging words than a log index holds
     jobs = [pm.BatchJob(big, pm.Optics(f32(0.5), f32(0.01), f32(0.7)), 20000, seed=20260809, stream_id=0),
             pm.BatchJob(small, pm.Optics(f32(0.8), f32(0.02), f32(0.6)), 5000, seed=20260809, stream_id=1)]
     b = pm.run_batch(jobs, tune=pm.Tune(256, 16, 256, 16))

@@ -258,16 +258,22 @@ def test_m1_fields_and_globals(mask_m1):
     assert abs(sc["esc_w_void_path"] - tot["esc_w_void_path"]) <= 5e-3 * tot["esc_w_void_path"]
 
 
+# FP64 transport: the estimators differ from the oracle's only by the rounding of each segment's
+# deposit to a whole quantum (at most half a quantum, 128 Q31 units, against the 2^29 or more a
+# photon of weight above 1/4 deposits over half a voxel length)
+FP64_REL = 2e-7
+
+
 def test_m1_fp64_transport_is_near_exact(mask_m1):
     banner("M1 1e5 photons, FP64 transport: integer channels exact, fluence to quantisation")
     n = 100_000
-    res, summ, sc, ref, tot, e = _compare_run(mask_m1, OPT, n, nbatch=1, rel=1e-9, fp64=True)
+    res, summ, sc, ref, tot, e = _compare_run(mask_m1, OPT, n, nbatch=1, rel=FP64_REL, fp64=True)
     for k in ("R", "T", "A", "RR", "esc_w", "esc_w_gtL", "esc_n", "esc_n_gtL", "steps", "interactions"):
         assert sc[k] == tot[k], k
     F_g = res.fluence.cpu().numpy().astype(np.float64)
     F_o = ref["fluence"][0]
-    # GPU deposits are rounded to whole Q31 units per segment; nothing else differs
-    assert np.all(np.abs(F_g - F_o) <= 1e-9 * F_o + 0.5 * 4096)
+    # GPU deposits are rounded to whole deposit quanta per segment; nothing else differs
+    assert np.all(np.abs(F_g - F_o) <= 1e-9 * F_o + 0.5 * pm.DEPOSIT_QUANTUM * 4096)
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 65535), (1, 65535, 1), (65535, 1, 1), (3, 5, 40001)])
@@ -278,12 +284,12 @@ def test_extreme_extents_fp64_near_exact(shape):
     banner(f"extreme extents {shape}, FP64 transport vs oracle")
     mask = (np.random.default_rng(sum(shape)).random(shape) < 0.7).astype(np.uint8)
     n = 2000
-    res, summ, sc, ref, tot, e = _compare_run(mask, OPT, n, nbatch=1, rel=1e-9, fp64=True)
+    res, summ, sc, ref, tot, e = _compare_run(mask, OPT, n, nbatch=1, rel=FP64_REL, fp64=True)
     for k in ("R", "T", "A", "RR", "esc_w", "esc_n", "steps", "interactions"):
         assert sc[k] == tot[k], k
     F_g = res.fluence.cpu().numpy().astype(np.float64)
     F_o = ref["fluence"][0]
-    assert np.all(np.abs(F_g - F_o) <= 1e-9 * F_o + 0.5 * 4096)
+    assert np.all(np.abs(F_g - F_o) <= 1e-9 * F_o + 0.5 * pm.DEPOSIT_QUANTUM * 4096)
 
 
 def test_m1_globals_at_1e7(mask_m1):
@@ -323,31 +329,25 @@ def test_bitwise_reproducible_and_tune_invariant(mask_m1):
 
 
 def test_large_per_voxel_deposits_bypass_the_log():
-    """A dense, non-absorbing solid (mu_s = 20 per voxel, g = 0) makes a photon cross
-    several voxel lengths inside one voxel at nearly full weight, so its summed deposit
-    there reaches 2^32 and goes to the tally directly instead of through the 32-bit log;
-    the tallies must still equal one atomic per visit bit for bit, and such sums must
-    occur (some voxel receives a single deposit of 2^32 or more)."""
-    banner("deposits of 2^32 or more: logged run == direct run")
-    m = dev(inputs.homogeneous_mask(12, 10, 6))
-    opt = pm.Optics(f32(20.0), 0.0, 0.0)
-    n = 3000
-    logged = pm.run(m, opt, n, SEED)
-    direct = pm.run(m, opt, n, SEED, direct=True)
-    assert torch.equal(logged.fluence, direct.fluence) and torch.equal(logged.scalars, direct.scalars)
-    # traced photons show visits whose summed deposit w * d reaches 2^32
-    recs, _ = pm.trace(m, opt, list(range(20)), 64, SEED)
-    best = 0.0
-    for ph in recs:
-        run, cur = 0.0, None
-        for rec in ph:
-            if rec["event"] < 0:
-                continue
-            v = (int(rec["ix"]), int(rec["iy"]), int(rec["iz"]))
-            run = run + float(rec["w"]) * float(rec["d"]) if v == cur else float(rec["w"]) * float(rec["d"])
-            cur = v
-            best = max(best, run)
-    assert best >= 2.0 ** 32, best
+    """A dense, non-absorbing solid (mu_s = 3000 per voxel, g = 0, a 3x3x3 slab) keeps some
+    photons scattering inside one voxel for thousands of voxel lengths, so their deposit
+    in one stay reaches 2^32 quanta (2^40 Q31, 512 voxel lengths at full weight) and goes
+    to the int64 tally directly instead of through the 32-bit log; the tallies must still
+    equal one atomic per visit bit for bit.  The oracle shows such stays occur for these
+    photons (its largest single-stay deposit per photon)."""
+    banner("deposits of 2^32 quanta or more in one stay: logged run == direct run")
+    m = inputs.homogeneous_mask(3, 3, 3)
+    opt = pm.Optics(f32(3000.0), 0.0, 0.0)
+    n = 8000
+    d = dev(m)
+    for fp64 in (False, True):
+        logged = pm.run(d, opt, n, SEED, fp64=fp64)
+        direct = pm.run(d, opt, n, SEED, fp64=fp64, direct=True)
+        assert torch.equal(logged.fluence, direct.fluence) and torch.equal(logged.scalars, direct.scalars), fp64
+    _, oo = oracle.trace(m, opt.mu_s, opt.mu_a, opt.g, np.arange(n, dtype=np.uint64), SEED, max_rec=0)
+    big = int((oo["max_visit"] >= 2.0 ** 32 * pm.DEPOSIT_QUANTUM).sum())
+    print(f"{big} of {n} photons deposit 2^32 quanta or more in one stay", flush=True)
+    assert big >= 3
 
 
 def test_resume_split_equals_whole(mask_m1):
