@@ -119,7 +119,11 @@ def batched_leg(args, seed):
     n_total = sum(j.n_photons for j in jobs)
     vox = sum(j.mask.numel() for j in jobs)
     log(f"batch: 64 masks ({vox / 1e6:.0f} Mvoxels, {n_total / 1e6:.0f} M photons) built in {time.time() - t0:.1f}s")
-    b = pm.run_batch(jobs)           # warm-up; autotunes the launch shape on a cache miss
+    t0 = time.perf_counter()
+    tuned = pm.autotune_batch(jobs)  # timed trials on a scaled-down copy; also stored in the tune cache
+    t_tune = time.perf_counter() - t0
+    log(f"batch autotune: {tuned} in {t_tune:.1f}s")
+    b = pm.run_batch(jobs)           # warm-up, with the cached shape
     torch.cuda.synchronize()
     log("batch warm-up done")
     times, walk = [], []
@@ -134,6 +138,22 @@ def batched_leg(args, seed):
         log(f"batch step {i}: {times[-1] * 1e3:.0f} ms (walk {b.walk_ms:.0f} ms)")
     steps = sum(int(r.scalars[pm.SCALARS.index("steps")].item()) for r in b.results)
     batch_scalars = [r.scalars.clone() for r in b.results]
+    del b
+    torch.cuda.synchronize()
+    # the library's default launch shape on the same batch
+    b = pm.run_batch(jobs, tune=pm.Tune(), timed=True)
+    torch.cuda.synchronize()
+    walk_default = b.walk_ms
+    del b
+    # the same batch keeping every job's escape-path histogram (Sec. 3.5 (c)) in the walk
+    bins = [(4.0, 256)] * len(jobs)
+    b = pm.run_batch(jobs, timed=True, escape_bins=bins)
+    torch.cuda.synchronize()
+    walk_esc = b.walk_ms
+    esc_ok = all(int(r.escape_hist_n.sum()) == int(r.scalars[pm.SCALARS.index("esc_n")])
+                 and int(r.escape_hist_w.sum()) == int(r.scalars[pm.SCALARS.index("esc_w")])
+                 and torch.equal(r.scalars, c) for r, c in zip(b.results, batch_scalars))
+    log(f"batch walk: default shape {walk_default:.0f} ms, with escape histograms {walk_esc:.0f} ms")
     del b
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -157,6 +177,10 @@ def batched_leg(args, seed):
             "ms": t_b * 1e3, "walk_ms": min(walk), "photon_steps_per_s": steps / t_b, "photons_per_s": n_total / t_b,
             "sequential_plain_ms": t_seq * 1e3, "sequential_photon_steps_per_s": steps / t_seq,
             "speedup_vs_sequential": t_seq / t_b, "jobs_bitwise_equal_to_plain": identical,
+            "autotuned_shape": {"block": tuned.block, "waves_per_cu": tuned.waves_per_cu, "chunk": tuned.chunk,
+                                "refill": tuned.refill, "defer": tuned.defer, "tuning_s": t_tune},
+            "walk_ms_default_shape": walk_default,
+            "walk_ms_with_escape_histograms": walk_esc, "escape_histograms_consistent": esc_ok,
             "roofline": walk_roofline("batched", steps, min(walk))}
 
 
@@ -656,6 +680,8 @@ def main():
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--scatter-probe", action="store_true",
                     help="only measure random 64-bit scatter / atomic throughput (the deposit roofline)")
+    ap.add_argument("--hot-probe", action="store_true",
+                    help="only measure atomic throughput onto few addresses (64 to 262144 table entries)")
     args = ap.parse_args()
     if args.scatter_probe:
         import torch
@@ -683,6 +709,23 @@ def main():
             out[key] = pm.probe_scatter(t, 1 << 30, mode, w)
             log(f"{mib:5d} MiB {w:2d} waves/CU {names[mode]:36s} {out[key] / 1e9:8.2f} G ops/s")
         print(json.dumps({"scatter_probe_ops_per_s": out}))
+        return
+    if args.hot_probe:
+        import torch
+
+        from paper_2604_13929_amd import photonmc as pm
+        pm.load()
+        out = {}
+        names = {0: "atomic64_device", 8: "atomic64_device_return", 3: "atomic32_device"}
+        for entries in (64, 512, 4096, 32768, 262144):
+            t = torch.zeros(entries, dtype=torch.int64, device="cuda:0")
+            for mode in names:
+                pm.probe_scatter(t, 1 << 20, mode, 16)
+                key = f"{names[mode]}_{entries}entries"
+                out[key] = pm.probe_scatter(t, 1 << 26, mode, 16)
+                log(f"{entries:7d} entries ({entries * 8 // 64:5d} lines) {names[mode]:24s} "
+                    f"{out[key] / 1e9:8.3f} G ops/s")
+        print(json.dumps({"hot_probe_ops_per_s": out}))
         return
     if args.copy_probe:
         import torch

@@ -385,6 +385,35 @@ size_t mc_batch_workspace_bytes(const mc_job *jobs, int32_t n_jobs);
 int mc_run_batch(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune, void *workspace,
                  size_t workspace_bytes, void *hip_stream);
 
+/* The in-pore path histogram of one batch job's escaping photons (Sec. 3.5 (c)),
+ * with the bins of mc_run_escape_histogram. */
+typedef struct {
+    double bin_width;      /* finite, > 0 (voxels) */
+    int32_t nbins;         /* 1 .. 512; the last bin takes every longer path */
+    int32_t reserved;      /* must be 0 */
+    int64_t *hist_w;       /* device int64[nbins]: escaped Q31 weight per bin; NULL: no histogram for this job */
+    int64_t *hist_n;       /* device int64[nbins]: escaped photons per bin */
+} mc_escape_bins;
+
+/*
+ * mc_run_batch that also histograms, per job, the in-pore path of every escaping
+ * photon (fate R or T) over the whole run (Sec. 3.5 (c)), so that no per-photon
+ * record is needed.  bins: host array [n_jobs], entry i for jobs[i]; a job whose
+ * hist_w is NULL keeps no histogram.  A job's histogram is zeroed first unless
+ * the job accumulates.  Job k's tallies are those of mc_run_batch and its
+ * histogram equals, bin for bin, mc_run_escape_histogram of job k alone, for any
+ * launch shape.  The walk adds each escaping photon into one of 16 copies of
+ * its job's bins in the workspace (a workgroup's copy by its index, so that the
+ * few bins most photons fall in are not one hot address), and a kernel after
+ * the walk adds the copies into hist_w / hist_n.  tune NULL: as mc_run_batch.  Errors as
+ * mc_run_batch, and MC_EINVAL for a NULL bins array, a histogram entry with
+ * hist_n NULL, a nonzero reserved field or a bad bin_width / nbins (the message
+ * names the job).
+ */
+int mc_run_batch_escape_histogram(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune,
+                                  const mc_escape_bins *bins, void *workspace, size_t workspace_bytes,
+                                  void *hip_stream);
+
 /*
  * Find a fast launch shape for this batch by timed trials on a scaled-down copy
  * of it (about 2^22 photons per trial; coordinate descent over waves per CU,
@@ -467,7 +496,7 @@ const char *mc_last_error(void);
 /* Library ABI version (MC_ABI_VERSION). */
 int mc_abi_version(void);
 /* sizeof one of the ABI structs by name ("mc_volume", "mc_optics", "mc_tune",
- * "mc_trace_rec", "mc_photon_rec", "mc_job"), 0 for an unknown name; lets a
+ * "mc_trace_rec", "mc_photon_rec", "mc_job", "mc_escape_bins"), 0 for an unknown name; lets a
  * binding check its layouts. */
 size_t mc_sizeof(const char *type_name);
 

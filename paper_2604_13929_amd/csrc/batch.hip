@@ -45,6 +45,54 @@ __global__ void k_write_jobs(JobPack pack, Job *__restrict__ dst, int32_t count)
     for (int32_t i = threadIdx.x; i < count * w; i += blockDim.x) d[i] = src[i];
 }
 
+// The escape-path histogram of one job (table order), NULL w: none.  Read only
+// when a photon escapes, so it stays in global memory, not in the LDS job table.
+// The walk adds into kEscReplicas copies in the workspace, a workgroup's copy
+// chosen by its index: a batch runs its jobs longest first, so at any time most
+// of the chip's escapes go to a few bins of one job, and one 64-byte line takes
+// only ~1e8 atomics per second at the memory side.  k_esc_fold adds the copies
+// into the caller's bins after the walk.
+constexpr int kEscReplicas = 16;
+struct BatchEsc {
+    unsigned long long *w;    // [nbins] escaped Q31 weight (the caller's)
+    unsigned long long *n;    // [nbins] escaped photons (the caller's)
+    unsigned long long *rw;   // [kEscReplicas][kEscMaxBins] copies of w (workspace)
+    unsigned long long *rn;   // [kEscReplicas][kEscMaxBins] copies of n (workspace)
+    double width;
+    int32_t nbins;
+    int32_t pad;
+};
+static_assert(sizeof(BatchEsc) % 8 == 0, "histogram table is written in 8-byte words");
+constexpr size_t kEscReplicaWords = 2ull * kEscReplicas * kEscMaxBins;   // per job: copies of w and n
+
+struct EscPack {
+    BatchEsc e[16];
+};
+
+__global__ void k_write_esc(EscPack pack, BatchEsc *__restrict__ dst, int32_t count)
+{
+    const int32_t w = (int32_t)(sizeof(BatchEsc) / 8);
+    const uint64_t *src = (const uint64_t *)pack.e;
+    uint64_t *d = (uint64_t *)dst;
+    for (int32_t i = threadIdx.x; i < count * w; i += blockDim.x) d[i] = src[i];
+}
+
+// One workgroup per job: bin b of the caller's histogram += the sum of its copies.
+__global__ __launch_bounds__(256) void k_esc_fold(const BatchEsc *__restrict__ esc)
+{
+    const BatchEsc e = esc[blockIdx.x];
+    if (e.w == nullptr) return;
+    for (int32_t b = threadIdx.x; b < e.nbins; b += blockDim.x) {
+        unsigned long long sw = 0ull, sn = 0ull;
+        for (int r = 0; r < kEscReplicas; ++r) {
+            sw += e.rw[(size_t)r * kEscMaxBins + b];
+            sn += e.rn[(size_t)r * kEscMaxBins + b];
+        }
+        e.w[b] += sw;
+        e.n[b] += sn;
+    }
+}
+
 struct BatchTallySink {
     template <typename R> __device__ __forceinline__ void segment(const Photon<R> &, const Job &, R, bool) {}
     template <typename R> __device__ __forceinline__ void deflect(Photon<R> &, const Job &, R) {}
@@ -163,12 +211,14 @@ __device__ __forceinline__ void account_job(unsigned long long *acc, const Photo
 // positions refilled by one atomic, idle lanes refilled together, interactions
 // run together once `defer` lanes wait at one (or no lane can advance), exit
 // once the queue is exhausted and no lane is alive.
-// LOGGED: every job's fluence pointer is its bricked tally.  GENERAL: some job
-// uses the paper's boundary model (each job's own flags select its physics).
+// LOGGED: deposits go through the log into each job's staging tally.  GENERAL:
+// some job uses the paper's boundary model (each job's own flags select its
+// physics).  esc: per-job escape-path histograms (Sec. 3.5 (c)), or NULL.
 template <int BLOCK, typename R, bool LOGGED, bool GENERAL>
 __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jobs, int32_t n_jobs,
                                                       unsigned long long *__restrict__ queue, int32_t chunk,
-                                                      int32_t refill, int32_t defer)
+                                                      int32_t refill, int32_t defer,
+                                                      const BatchEsc *__restrict__ esc)
 {
     constexpr int kWaves = BLOCK / 64;
     __shared__ Job s_jobs[MC_MAX_BATCH_JOBS];
@@ -203,6 +253,20 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
     uint64_t q_next = 0, q_end = 0;
     bool exhausted = false;
     uint32_t iter = 0;
+
+    auto retire = [&](int32_t ev, int32_t nz) {
+        account_job(acc[job], p, ev, nz);
+        if (esc != nullptr && (ev == EV_ESC_R || ev == EV_ESC_T)) {
+            const BatchEsc &e = esc[job];
+            if (e.w != nullptr) {
+                const size_t b = (size_t)(blockIdx.x % kEscReplicas) * kEscMaxBins +
+                                 (size_t)escape_path_bin(p.l_void, e.width, e.nbins);
+                __hip_atomic_fetch_add(e.rw + b, (unsigned long long)p.w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(e.rn + b, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        alive = false;
+    };
 
     for (;;) {
         const uint64_t idle = __ballot(!alive);
@@ -253,10 +317,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
                 waiting = true;
             } else {
                 const int32_t fin = finish(p, J, sink, ev);
-                if (is_terminal(fin)) {
-                    account_job(acc[job], p, fin, J.nz);
-                    alive = false;
-                }
+                if (is_terminal(fin)) retire(fin, J.nz);
             }
         }
         const uint64_t wait_mask = __ballot(waiting);
@@ -266,10 +327,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
                 const Job &J = s_jobs[job];
                 const int32_t fin = finish(p, J, sink, interact(p, J, sink));
                 waiting = false;
-                if (is_terminal(fin)) {
-                    account_job(acc[job], p, fin, J.nz);
-                    alive = false;
-                }
+                if (is_terminal(fin)) retire(fin, J.nz);
             }
         }
         if constexpr (LOGGED) {
@@ -291,7 +349,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t jobs_off, bricks_off[MC_MAX_BATCH_JOBS], bins_off[MC_MAX_BATCH_JOBS], stage_off[MC_MAX_BATCH_JOBS], total;
+    size_t jobs_off, esc_off, bricks_off[MC_MAX_BATCH_JOBS], bins_off[MC_MAX_BATCH_JOBS],
+        stage_off[MC_MAX_BATCH_JOBS], esc_rep_off[MC_MAX_BATCH_JOBS], total;
     bool logged;   // every job's staging tally fits the log's 26-bit indices
 };
 
@@ -301,6 +360,8 @@ Layout layout_of(const mc_job *jobs, int32_t n)
     size_t off = kHeaderBytes;
     L.jobs_off = off;
     off += align_up(sizeof(Job) * MC_MAX_BATCH_JOBS);
+    L.esc_off = off;
+    off += align_up(sizeof(BatchEsc) * MC_MAX_BATCH_JOBS);
     L.logged = true;
     for (int32_t i = 0; i < n; ++i) L.logged = L.logged && dims_of(&jobs[i].vol).stage_words <= kBatchLogWords;
     for (int32_t i = 0; i < n; ++i) {
@@ -311,6 +372,8 @@ Layout layout_of(const mc_job *jobs, int32_t n)
         off += align_up((size_t)jobs[i].vol.nz * kBinW * sizeof(uint64_t));
         L.stage_off[i] = off;
         if (L.logged) off += align_up(d.stage_words * sizeof(uint32_t));
+        L.esc_rep_off[i] = off;
+        off += align_up(kEscReplicaWords * sizeof(uint64_t));
     }
     L.total = off;
     return L;
@@ -374,24 +437,24 @@ int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, Prepared *
 
 template <typename R, bool LOGGED, bool GENERAL>
 void enqueue_batch_walk(int block, int blocks, const Job *table, int32_t n, unsigned long long *queue,
-                        const mc_tune &t, hipStream_t s)
+                        const mc_tune &t, const BatchEsc *esc, hipStream_t s)
 {
     switch (block) {
     case 64:
         hipLaunchKernelGGL((k_walk_batch<64, R, LOGGED, GENERAL>), dim3(blocks), dim3(64), 0, s, table, n, queue, t.chunk,
-                           t.refill, t.defer);
+                           t.refill, t.defer, esc);
         break;
     case 128:
         hipLaunchKernelGGL((k_walk_batch<128, R, LOGGED, GENERAL>), dim3(blocks), dim3(128), 0, s, table, n, queue, t.chunk,
-                           t.refill, t.defer);
+                           t.refill, t.defer, esc);
         break;
     case 256:
         hipLaunchKernelGGL((k_walk_batch<256, R, LOGGED, GENERAL>), dim3(blocks), dim3(256), 0, s, table, n, queue, t.chunk,
-                           t.refill, t.defer);
+                           t.refill, t.defer, esc);
         break;
     default:
         hipLaunchKernelGGL((k_walk_batch<512, R, LOGGED, GENERAL>), dim3(blocks), dim3(512), 0, s, table, n, queue, t.chunk,
-                           t.refill, t.defer);
+                           t.refill, t.defer, esc);
         break;
     }
 }
@@ -411,8 +474,9 @@ int enqueue_table(const Prepared &P, char *ws, hipStream_t s)
     return MC_OK;
 }
 
-// The walk alone (table written, tallies zeroed and masks packed beforehand).
-int enqueue_walk_only(const Prepared &P, char *ws, const mc_tune &t, int flags, hipStream_t s)
+// The walk alone (table written, tallies zeroed and masks packed beforehand);
+// with_esc: the histogram table in the workspace is written and in use.
+int enqueue_walk_only(const Prepared &P, char *ws, const mc_tune &t, int flags, hipStream_t s, bool with_esc = false)
 {
     DeviceInfo di;
     int rc = device_info(&di);
@@ -420,36 +484,76 @@ int enqueue_walk_only(const Prepared &P, char *ws, const mc_tune &t, int flags, 
     if ((rc = fill((int64_t *)ws, kHeaderBytes / 8, s))) return rc;
     const int blocks = std::max(1, di.cus * t.waves_per_cu / (t.block / 64));
     const Job *table = (const Job *)(ws + P.L.jobs_off);
+    const BatchEsc *esc = with_esc ? (const BatchEsc *)(ws + P.L.esc_off) : nullptr;
     unsigned long long *queue = (unsigned long long *)ws;
     const int32_t n = (int32_t)P.table.size();
     const bool f64 = (flags & MC_FP64) != 0;
     if (P.general) {
         if (P.L.logged) {
-            if (f64) enqueue_batch_walk<double, true, true>(t.block, blocks, table, n, queue, t, s);
-            else enqueue_batch_walk<float, true, true>(t.block, blocks, table, n, queue, t, s);
+            if (f64) enqueue_batch_walk<double, true, true>(t.block, blocks, table, n, queue, t, esc, s);
+            else enqueue_batch_walk<float, true, true>(t.block, blocks, table, n, queue, t, esc, s);
         } else {
-            if (f64) enqueue_batch_walk<double, false, true>(t.block, blocks, table, n, queue, t, s);
-            else enqueue_batch_walk<float, false, true>(t.block, blocks, table, n, queue, t, s);
+            if (f64) enqueue_batch_walk<double, false, true>(t.block, blocks, table, n, queue, t, esc, s);
+            else enqueue_batch_walk<float, false, true>(t.block, blocks, table, n, queue, t, esc, s);
         }
     } else {
         if (P.L.logged) {
-            if (f64) enqueue_batch_walk<double, true, false>(t.block, blocks, table, n, queue, t, s);
-            else enqueue_batch_walk<float, true, false>(t.block, blocks, table, n, queue, t, s);
+            if (f64) enqueue_batch_walk<double, true, false>(t.block, blocks, table, n, queue, t, esc, s);
+            else enqueue_batch_walk<float, true, false>(t.block, blocks, table, n, queue, t, esc, s);
         } else {
-            if (f64) enqueue_batch_walk<double, false, false>(t.block, blocks, table, n, queue, t, s);
-            else enqueue_batch_walk<float, false, false>(t.block, blocks, table, n, queue, t, s);
+            if (f64) enqueue_batch_walk<double, false, false>(t.block, blocks, table, n, queue, t, esc, s);
+            else enqueue_batch_walk<float, false, false>(t.block, blocks, table, n, queue, t, esc, s);
         }
     }
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }
 
+// The histogram table in queue order, from the caller's per-job bins (validated).
+int enqueue_esc_table(const Prepared &P, const mc_escape_bins *bins, char *ws, hipStream_t s)
+{
+    BatchEsc *dst = (BatchEsc *)(ws + P.L.esc_off);
+    const int32_t n = (int32_t)P.table.size();
+    for (int32_t i = 0; i < n; i += 16) {
+        EscPack pack;
+        memset(&pack, 0, sizeof pack);
+        const int32_t c = std::min(16, n - i);
+        for (int32_t k = 0; k < c; ++k) {
+            const int32_t job = P.order[i + k];
+            const mc_escape_bins &b = bins[job];
+            if (!b.hist_w) continue;
+            unsigned long long *rep = (unsigned long long *)(ws + P.L.esc_rep_off[job]);
+            pack.e[k].w = (unsigned long long *)b.hist_w;
+            pack.e[k].n = (unsigned long long *)b.hist_n;
+            pack.e[k].rw = rep;
+            pack.e[k].rn = rep + (size_t)kEscReplicas * kEscMaxBins;
+            pack.e[k].width = b.bin_width;
+            pack.e[k].nbins = b.nbins;
+        }
+        hipLaunchKernelGGL(k_write_esc, dim3(1), dim3(256), 0, s, pack, dst + i, c);
+        HIP_TRY(hipGetLastError());
+    }
+    return MC_OK;
+}
+
 // The whole batched step: table, zeroed tallies, packed masks, one walk, reductions.
-int enqueue_batch(const mc_job *jobs, const Prepared &P, char *ws, const mc_tune &t, int flags, hipStream_t s)
+// bins: per-job escape-path histograms (caller's job order, validated), or NULL.
+int enqueue_batch(const mc_job *jobs, const Prepared &P, char *ws, const mc_tune &t, int flags, hipStream_t s,
+                  const mc_escape_bins *bins = nullptr)
 {
     int rc = enqueue_table(P, ws, s);
     if (rc) return rc;
     const int32_t n = (int32_t)P.table.size();
+    if (bins) {
+        if ((rc = enqueue_esc_table(P, bins, ws, s))) return rc;
+        for (int32_t i = 0; i < n; ++i) {
+            if (!bins[i].hist_w) continue;
+            if ((rc = fill((int64_t *)(ws + P.L.esc_rep_off[i]), kEscReplicaWords, s))) return rc;
+            if (jobs[i].accumulate) continue;
+            if ((rc = fill(bins[i].hist_w, (uint64_t)bins[i].nbins, s))) return rc;
+            if ((rc = fill(bins[i].hist_n, (uint64_t)bins[i].nbins, s))) return rc;
+        }
+    }
     for (int32_t i = 0; i < n; ++i) {
         const mc_job &jb = jobs[i];
         const Dims d = dims_of(&jb.vol);
@@ -463,8 +567,12 @@ int enqueue_batch(const mc_job *jobs, const Prepared &P, char *ws, const mc_tune
     }
     const bool timed = (flags & MC_TIMED) != 0;
     if (timed && (rc = time_begin(s))) return rc;
-    if ((rc = enqueue_walk_only(P, ws, t, flags, s))) return rc;
+    if ((rc = enqueue_walk_only(P, ws, t, flags, s, bins != nullptr))) return rc;
     if (timed && (rc = time_end(s))) return rc;
+    if (bins) {
+        hipLaunchKernelGGL(k_esc_fold, dim3(n), dim3(256), 0, s, (const BatchEsc *)(ws + P.L.esc_off));
+        HIP_TRY(hipGetLastError());
+    }
     if (P.L.logged) {
         for (int32_t i = 0; i < n; ++i) {
             const mc_job &jb = jobs[i];
@@ -686,10 +794,13 @@ int mc_autotune_batch(const mc_job *jobs, int32_t n_jobs, int flags, void *works
     return MC_OK;
 }
 
-int mc_run_batch(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune, void *workspace,
-                 size_t workspace_bytes, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+int run_batch(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune, void *workspace,
+              size_t workspace_bytes, void *hip_stream, const mc_escape_bins *bins)
 {
-    clear_error();
     Prepared P;
     int rc = prepare(jobs, n_jobs, (char *)workspace, workspace_bytes, &P);
     if (rc) return rc;
@@ -705,7 +816,39 @@ int mc_run_batch(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *t
         }
     }
     if ((rc = check_tune(t))) return rc;
-    return enqueue_batch(jobs, P, (char *)workspace, t, flags, s);
+    return enqueue_batch(jobs, P, (char *)workspace, t, flags, s, bins);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mc_run_batch(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune, void *workspace,
+                 size_t workspace_bytes, void *hip_stream)
+{
+    clear_error();
+    return run_batch(jobs, n_jobs, flags, tune, workspace, workspace_bytes, hip_stream, nullptr);
+}
+
+int mc_run_batch_escape_histogram(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune,
+                                  const mc_escape_bins *bins, void *workspace, size_t workspace_bytes,
+                                  void *hip_stream)
+{
+    clear_error();
+    if (!bins) return fail(MC_EINVAL, "bins is NULL");
+    if (jobs && n_jobs >= 1 && n_jobs <= MC_MAX_BATCH_JOBS) {
+        for (int32_t i = 0; i < n_jobs; ++i) {
+            const mc_escape_bins &b = bins[i];
+            if (b.reserved != 0) return fail(MC_EINVAL, "job %d: bins.reserved must be 0", i);
+            if (!b.hist_w) continue;
+            if (!b.hist_n) return fail(MC_EINVAL, "job %d: hist_n is NULL while hist_w is not", i);
+            if (b.nbins < 1 || b.nbins > kEscMaxBins)
+                return fail(MC_EINVAL, "job %d: nbins must be in [1, %d]", i, kEscMaxBins);
+            if (!(b.bin_width > 0.0) || !isfinite(b.bin_width))
+                return fail(MC_EINVAL, "job %d: bin_width must be finite and > 0", i);
+        }
+    }
+    return run_batch(jobs, n_jobs, flags, tune, workspace, workspace_bytes, hip_stream, bins);
 }
 
 int mc_batch_graph_create(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune, void *workspace,

@@ -22,6 +22,7 @@ void clear_error();
 
 constexpr size_t kHeaderBytes = 256;  // queue counter(s) at the start of a run workspace
 constexpr int kBinW = 8;              // int64 words per depth bin of the reduction
+constexpr int kEscMaxBins = 512;      // escape-path bins; 6 KB of LDS leaves four walk workgroups per CU
 
 struct Dims {
     int32_t nxb, nyb, nzb;       // 4x4x4 mask bricks

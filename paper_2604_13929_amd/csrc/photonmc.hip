@@ -283,7 +283,6 @@ struct EscHist {
     double width;
     int32_t nbins;            // 1 .. kEscMaxBins
 };
-constexpr int kEscMaxBins = 512;  // 6 KB of LDS: four walk workgroups still fit per CU
 
 // ---------------------------------------------------------------------------
 // Persistent walk
@@ -1057,6 +1056,7 @@ size_t mc_sizeof(const char *type_name)
     if (!strcmp(type_name, "mc_trace_rec")) return sizeof(mc_trace_rec);
     if (!strcmp(type_name, "mc_photon_rec")) return sizeof(mc_photon_rec);
     if (!strcmp(type_name, "mc_job")) return sizeof(mc_job);
+    if (!strcmp(type_name, "mc_escape_bins")) return sizeof(mc_escape_bins);
     return 0;
 }
 

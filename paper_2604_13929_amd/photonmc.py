@@ -70,6 +70,11 @@ class McJob(ctypes.Structure):
                 ("summary", ctypes.c_void_p), ("depth", ctypes.c_void_p)]
 
 
+class McEscapeBins(ctypes.Structure):
+    _fields_ = [("bin_width", ctypes.c_double), ("nbins", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("hist_w", ctypes.c_void_p), ("hist_n", ctypes.c_void_p)]
+
+
 MAX_BATCH_JOBS = 64
 
 TRACE_DTYPE = np.dtype([("fx", "<f8"), ("fy", "<f8"), ("fz", "<f8"), ("ux", "<f8"), ("uy", "<f8"), ("uz", "<f8"),
@@ -105,6 +110,8 @@ _SIGS = {
                                ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
     "mc_batch_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
     "mc_run_batch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, _P, _P, ctypes.c_size_t, _P]),
+    "mc_run_batch_escape_histogram": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, _P, _P, _P,
+                                                     ctypes.c_size_t, _P]),
     "mc_autotune_batch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, _P, ctypes.c_size_t, _P, _P]),
     "mc_batch_graph_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, _P, _P, ctypes.c_size_t, _P]),
     "mc_graph_launch": (ctypes.c_int, [_P, _P]),
@@ -472,6 +479,7 @@ class Batch:
         self.device = dev
         self.results: list[RunResult] = []
         self.summaries, self.depths = [], []
+        self.c_bins = None
         arr = (McJob * len(jobs))()
         for i, j in enumerate(jobs):
             vol = volume(j.mask)
@@ -495,6 +503,27 @@ class Batch:
             raise McError(-1, "mc_batch_workspace_bytes", "invalid batch")
         self.ws = workspace(nbytes, dev)
 
+    def attach_escape_bins(self, escape_bins: list, accumulate_into: "Batch | None" = None):
+        """Per-job escape-path histograms: escape_bins[i] = (bin_width, nbins) or None.
+        The tensors land in self.results[i].escape_hist_w / escape_hist_n."""
+        if len(escape_bins) != len(self.jobs):
+            raise ValueError("escape_bins needs one entry (or None) per job")
+        arr = (McEscapeBins * len(self.jobs))()
+        for i, eb in enumerate(escape_bins):
+            r = self.results[i]
+            if eb is None:
+                arr[i] = McEscapeBins(1.0, 1, 0, None, None)
+                continue
+            width, nbins = float(eb[0]), int(eb[1])
+            if accumulate_into is not None:
+                if r.escape_hist_w is None or r.escape_hist_w.numel() != nbins:
+                    raise ValueError(f"job {i}: accumulate needs a result that carries histograms of the same nbins")
+            else:
+                r.escape_hist_w = torch.empty(max(nbins, 1), dtype=torch.int64, device=self.device)
+                r.escape_hist_n = torch.empty(max(nbins, 1), dtype=torch.int64, device=self.device)
+            arr[i] = McEscapeBins(width, nbins, 0, r.escape_hist_w.data_ptr(), r.escape_hist_n.data_ptr())
+        self.c_bins = arr
+
     def summary(self, i: int) -> Summary:
         q = self.summaries[i].cpu().numpy()
         d = self.depths[i].cpu().numpy()
@@ -504,14 +533,24 @@ class Batch:
 
 
 def run_batch(jobs: list[BatchJob], tune: Tune | None = None, fp64: bool = False, timed: bool = False,
-              accumulate_into: Batch | None = None) -> Batch:
-    """mc_run_batch on the current stream; tune None: the cached (or autotuned) launch shape."""
+              accumulate_into: Batch | None = None, escape_bins: list | None = None) -> Batch:
+    """mc_run_batch on the current stream; tune None: the cached (or autotuned) launch shape.
+    escape_bins: one (bin_width, nbins) or None per job: mc_run_batch_escape_histogram,
+    which also bins each job's escaping photons by in-pore path into
+    batch.results[i].escape_hist_w / escape_hist_n."""
     L = load()
     b = Batch(jobs, accumulate_into)
     flags = (MC_FP64 if fp64 else 0) | (MC_TIMED if timed else 0)
     t = tune.c() if tune is not None else None
-    _check(L.mc_run_batch(ctypes.byref(b.c_jobs), len(jobs), flags, ctypes.byref(t) if t is not None else None,
-                          b.ws.data_ptr(), b.ws.numel(), _stream(b.device)), "mc_run_batch")
+    tref = ctypes.byref(t) if t is not None else None
+    if escape_bins is None:
+        _check(L.mc_run_batch(ctypes.byref(b.c_jobs), len(jobs), flags, tref, b.ws.data_ptr(), b.ws.numel(),
+                              _stream(b.device)), "mc_run_batch")
+    else:
+        b.attach_escape_bins(escape_bins, accumulate_into)
+        _check(L.mc_run_batch_escape_histogram(ctypes.byref(b.c_jobs), len(jobs), flags, tref,
+                                               ctypes.byref(b.c_bins), b.ws.data_ptr(), b.ws.numel(),
+                                               _stream(b.device)), "mc_run_batch_escape_histogram")
     if timed:
         ms = ctypes.c_float(0.0)
         _check(L.mc_walk_elapsed_ms(ctypes.byref(ms)), "mc_walk_elapsed_ms")

@@ -47,6 +47,8 @@ def test_abi_version_and_layouts(lib):
     assert lib.mc_sizeof(b"mc_optics") == ctypes.sizeof(pm.McOptics) == 56
     assert lib.mc_sizeof(b"mc_trace_rec") == pm.TRACE_DTYPE.itemsize == 88
     assert lib.mc_sizeof(b"mc_photon_rec") == pm.PHOTON_DTYPE.itemsize == 72
+    assert lib.mc_sizeof(b"mc_job") == ctypes.sizeof(pm.McJob)
+    assert lib.mc_sizeof(b"mc_escape_bins") == ctypes.sizeof(pm.McEscapeBins) == 32
     assert lib.mc_sizeof(b"nonsense") == 0
 
 
@@ -250,6 +252,30 @@ def test_escape_histogram_run_rejects_bad_arguments(lib):
     bad = pm.McOptics(0.5, 0.01, 1.0, 1e-4, 10, 0.0, 0, 0)
     assert lib.mc_run_escape_histogram(ctypes.byref(vol), ctypes.byref(bad), 0, 10, 1, 0, 0, 1, 1, 1, 1 << 30, None,
                                        1.0, 16, 1, 1, None) == -1 and b"|g|" in lib.mc_last_error()
+
+
+def test_batch_escape_histogram_rejects_bad_arguments(lib):
+    jobs = (pm.McJob * 2)(_job(), _job())
+    ws = lib.mc_batch_workspace_bytes(ctypes.byref(jobs), 2)
+    tune = ctypes.byref(pm.McTune(256, 8, 64, 8, 4))
+
+    def call(b0, b1=pm.McEscapeBins(1.0, 1, 0, None, None), batch=jobs):
+        bins = (pm.McEscapeBins * 2)(b0, b1)
+        return lib.mc_run_batch_escape_histogram(ctypes.byref(batch), 2, 0, tune, ctypes.byref(bins), 1, ws, None)
+
+    assert lib.mc_run_batch_escape_histogram(ctypes.byref(jobs), 2, 0, tune, None, 1, ws, None) == -1
+    assert b"bins" in lib.mc_last_error()
+    assert call(pm.McEscapeBins(1.0, 0, 0, 1, 1)) == -1 and b"job 0" in lib.mc_last_error()
+    assert b"nbins" in lib.mc_last_error()
+    assert call(pm.McEscapeBins(1.0, 16, 0, None, None), pm.McEscapeBins(1.0, 513, 0, 1, 1)) == -1
+    assert b"job 1" in lib.mc_last_error() and b"nbins" in lib.mc_last_error()
+    for w in (0.0, -1.0, float("inf"), float("nan")):
+        assert call(pm.McEscapeBins(w, 16, 0, 1, 1)) == -1 and b"bin_width" in lib.mc_last_error()
+    assert call(pm.McEscapeBins(1.0, 16, 0, 1, None)) == -1 and b"hist_n" in lib.mc_last_error()
+    assert call(pm.McEscapeBins(1.0, 16, 7, None, None)) == -1 and b"reserved" in lib.mc_last_error()
+    # the jobs are validated as by mc_run_batch
+    bad = (pm.McJob * 2)(_job(), _job(g=1.5))
+    assert call(pm.McEscapeBins(1.0, 16, 0, 1, 1), batch=bad) == -1 and b"job 1" in lib.mc_last_error()
 
 
 def test_missing_library_fails_loudly(tmp_path):

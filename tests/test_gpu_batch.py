@@ -3,7 +3,8 @@ same photons (jobs spanning the 64-job workload's sizes, porosities and optics, 
 stream ids and photon ranges other than 0); job k of a batch equals a plain run of
 job k, bit for bit, for any launch shape; the captured graph replays the same bits;
 the reduction of every job equals mc_reduce on that job; the autotuner returns a
-usable shape."""
+usable shape; the per-job escape-path histograms (Sec. 3.5 (c)) equal single runs'
+and the oracle's."""
 from __future__ import annotations
 
 import math
@@ -13,6 +14,7 @@ import pytest
 import torch
 
 import oracle
+from oracle import analytics as oan
 from oracle import estimators as est
 from paper_2604_13929_amd import inputs
 from paper_2604_13929_amd import photonmc as pm
@@ -276,3 +278,101 @@ def test_oversize_job_takes_the_direct_path():
         assert torch.equal(b.results[k].scalars, r.scalars), k
     del b, big
     torch.cuda.empty_cache()
+
+
+# job 1 (5000 photons) bins paths of 4 voxels and more into its last bin; job 3 has one photon
+ESC_BINS = [(1.5, 96), (0.25, 16), None, (0.5, 512), (3.0, 1), (1.5, 96)]
+
+
+def _esc_jobs(small_jobs):
+    """Five plain jobs of the small batch and one under the paper boundary model."""
+    paper = pm.BatchJob(small_jobs[5].mask, pm.paper_optics(0.5, f32(0.01), f32(0.7), n_solid=f32(1.746),
+                                                            lateral=pm.LATERAL_MIRROR, gate=400.0),
+                        20000, seed=20260809, stream_id=9, photon_begin=11)
+    return small_jobs[:5] + [paper]
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_batch_escape_histograms_equal_single_runs(small_jobs, fp64):
+    """Each job's escape-path histogram kept by the batched walk equals that of
+    mc_run_escape_histogram of the job alone, bin for bin, for several launch shapes;
+    the tallies are those of mc_run_batch; a job without bins keeps none."""
+    banner(f"batched escape-path histograms == single-run histograms (fp64={fp64})")
+    jobs = _esc_jobs(small_jobs)
+    base = pm.run_batch(jobs, tune=pm.Tune(256, 16, 256, 16), fp64=fp64)
+    singles = {}
+    for k, j in enumerate(jobs):
+        if ESC_BINS[k] is not None:
+            singles[k] = pm.run(j.mask, j.optics, j.n_photons, j.seed, photon_begin=j.photon_begin,
+                                stream_id=j.stream_id, fp64=fp64, escape_bins=ESC_BINS[k])
+    for tune in (pm.Tune(256, 16, 256, 16), pm.Tune(64, 4, 7, 1, 1), pm.Tune(512, 32, 4096, 64, 32)):
+        b = pm.run_batch(jobs, tune=tune, fp64=fp64, escape_bins=ESC_BINS)
+        torch.cuda.synchronize()
+        for k in range(len(jobs)):
+            r = b.results[k]
+            assert torch.equal(r.fluence, base.results[k].fluence), (tune, k)
+            assert torch.equal(r.scalars, base.results[k].scalars), (tune, k)
+            if ESC_BINS[k] is None:
+                assert r.escape_hist_w is None
+                continue
+            assert torch.equal(r.escape_hist_w, singles[k].escape_hist_w), (tune, k)
+            assert torch.equal(r.escape_hist_n, singles[k].escape_hist_n), (tune, k)
+            sc = r.scalar_dict()
+            assert int(r.escape_hist_w.sum()) == sc["esc_w"] and int(r.escape_hist_n.sum()) == sc["esc_n"], k
+    # the single-bin job holds every escape in its one bin; job 1 uses its overflow bin
+    assert int(b.results[4].escape_hist_n[0]) == b.results[4].scalar_dict()["esc_n"] > 0
+    assert int(b.results[1].escape_hist_n[-1]) > 0
+
+
+def test_batch_escape_histogram_fp64_equals_oracle(small_jobs):
+    """FP64 batch: a job's histogram equals the one the oracle's per-photon outcomes
+    (fate, final Q31 weight, in-pore path) give, bin for bin."""
+    banner("batched FP64 escape-path histogram == oracle per-photon outcomes, binned")
+    jobs = _esc_jobs(small_jobs)
+    b = pm.run_batch(jobs, tune=pm.Tune(256, 16, 256, 16), fp64=True, escape_bins=ESC_BINS)
+    torch.cuda.synchronize()
+    for k in (0, 1, 5):
+        j = jobs[k]
+        o = j.optics
+        m = j.mask.cpu().numpy()
+        ids = np.arange(j.photon_begin, j.photon_begin + j.n_photons, dtype=np.uint64)
+        kw = dict(w_roulette=o.w_roulette, roulette_m=o.roulette_m, source=o.source, boundary=o.boundary,
+                  lateral=o.lateral, n_solid=o.n_solid if o.n_solid else 1.0,
+                  gate=o.gate if o.gate > 0 else float("inf"))
+        _, summ = oracle.trace(m, o.mu_s, o.mu_a, o.g, ids, j.seed, max_rec=1, stream_id=j.stream_id, **kw)
+        width, nbins = ESC_BINS[k]
+        hw, hn, _, _ = oan.escape_path_histogram(summ["fate"], summ["w_final"], summ["path_void"], width, nbins)
+        gw, gn = b.results[k].escape_hist_w.cpu().numpy(), b.results[k].escape_hist_n.cpu().numpy()
+        # FP64 paths agree to ~1e-6 voxel after long walks; a path that close to a bin edge may bin either way
+        q = summ["path_void"] / width
+        esc = (summ["fate"] == 4) | (summ["fate"] == 5)
+        near = int((esc & (np.abs(q - np.round(q)) < 1e-5) & (q > 0.5) & (q < nbins - 0.5)).sum())
+        assert gn.sum() == hn.sum() and gw.sum() == hw.sum(), k
+        assert np.abs(gn - hn).sum() <= 2 * near, (k, near)
+        if near == 0:
+            assert np.array_equal(gn, hn) and np.array_equal(gw, hw), k
+
+
+def test_batch_escape_histograms_accumulate(small_jobs):
+    """Two photon halves of a batch, the second accumulating, give the whole
+    batch's histograms and tallies."""
+    banner("batched escape-path histograms: two halves accumulate to the whole")
+    jobs = _esc_jobs(small_jobs)
+    whole = pm.run_batch(jobs, tune=pm.Tune(256, 8, 128, 16), escape_bins=ESC_BINS)
+    first = [pm.BatchJob(j.mask, j.optics, max(1, j.n_photons // 2), j.seed, j.stream_id, j.photon_begin, False)
+             for j in jobs]
+    second = [pm.BatchJob(j.mask, j.optics, j.n_photons - f.n_photons, j.seed, j.stream_id,
+                          j.photon_begin + f.n_photons, False) for j, f in zip(jobs, first)]
+    keep = [i for i, s in enumerate(second) if s.n_photons > 0]
+    part = pm.run_batch(first, tune=pm.Tune(256, 8, 128, 16), escape_bins=ESC_BINS)
+    sub = pm.Batch.__new__(pm.Batch)
+    sub.results = [part.results[i] for i in keep]
+    pm.run_batch([second[i] for i in keep], tune=pm.Tune(64, 16, 32, 4), accumulate_into=sub,
+                 escape_bins=[ESC_BINS[i] for i in keep])
+    torch.cuda.synchronize()
+    for k in range(len(jobs)):
+        assert torch.equal(part.results[k].fluence, whole.results[k].fluence), k
+        assert torch.equal(part.results[k].scalars, whole.results[k].scalars), k
+        if ESC_BINS[k] is not None:
+            assert torch.equal(part.results[k].escape_hist_w, whole.results[k].escape_hist_w), k
+            assert torch.equal(part.results[k].escape_hist_n, whole.results[k].escape_hist_n), k
