@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define MC_ABI_VERSION 3
+#define MC_ABI_VERSION 4
 
 /* status codes */
 #define MC_OK 0
@@ -73,6 +73,7 @@ extern "C" {
                                staging tally, 2 x 2 x 4 voxels per 64-byte line, has <= 2^32 words) */
 
 #define MC_DEPOSIT_QUANTUM 256 /* Q31 units: every tally value is a multiple of it */
+#define MC_GRAD_FIXED_BITS 20  /* mc_grad's score bins count units of 2^-20 Q31 weight x voxel */
 
 /* Scalar tally channels: int64 words in a caller-owned device array of
  * MC_NSCALARS entries.  Weight channels are Q31.  For every run
@@ -282,7 +283,7 @@ size_t mc_grad_workspace_bytes(const mc_volume *vol);
  * score bins, then optionally the reduction and the Jacobian:
  *   grad_bins  device int64[3][2][nz][2]: (mu_s, mu_a, g) x (solid, pore) x depth x
  *              (hi, lo); value = hi * 2^32 + lo (lo summed as unsigned) in units of
- *              2^-16 Q31 weight x voxel
+ *              2^-MC_GRAD_FIXED_BITS Q31 weight x voxel
  *   jac        device double[3][2 + nz] or NULL: d<Phi>_3D, d<Phi>_1D, dPhi(z)/S0
  *              with respect to mu_s, mu_a, g (per voxel units)
  *   summary, depth  as mc_reduce, or NULL

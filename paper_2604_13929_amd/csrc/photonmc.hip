@@ -212,9 +212,44 @@ struct TallySink : Deposit {
 // S_mua = -l_solid and S_g = sum_i d ln p_HG(cos_i)/dg.  A segment of length d
 // starting with those scores adds w (S d - [solid] d^2/2) to the mu_s and mu_a
 // bins (the d^2/2 is the survival inside the segment) and w S_g d to the g bin,
-// per (parameter, phase, depth), in fixed point 2^-16 of a Q31 weight x voxel.
-// Roulette decisions carry no score: survival 1/m with weight x m is unbiased.
-constexpr double kGradScale = 0x1.0p-16;
+// per (parameter, phase, depth), in fixed point 2^-MC_GRAD_FIXED_BITS of a Q31
+// weight x voxel, each segment's value rounded to nearest.  Roulette decisions
+// carry no score: survival 1/m with weight x m is unbiased.
+constexpr double kGradScale = 1.0 / (double)(1ll << MC_GRAD_FIXED_BITS);
+
+// The block keeps its score bins in LDS as int32 words (half the space of int64
+// bins: four 256-thread walk workgroups still fit per CU at nz = 256) and moves a
+// word to the global (hi, lo) int64 pairs before it can overflow.  A value of
+// magnitude >= kGradDirect goes to the global pair directly; any other is added
+// to its word, and a lane whose add leaves the word at magnitude >= kGradSpill
+// swaps the word for 0 and adds what it took to the global pair.  A lane that
+// sees the threshold swaps before its next add, so at most one add per thread of
+// the block lands on a word between its crossing and the swap: |word| < kGradSpill
+// + 512 * kGradDirect = 2^28 + 2^30.  Every transfer is exact, so the totals are
+// the integer sums of the segments' fixed-point values whatever the order.  The
+// global pairs are few (6 nz, a hot address each), so the direct path must stay
+// rare: at 2^-20 a value reaches 2^21 only where (w / 2^31) |S| d reaches 1024
+// voxels, while under implicit capture (w / 2^31) l_solid peaks at 1 / (e mu_a),
+// 37 voxels at mu_a = 0.01.
+constexpr long long kGradDirect = 1ll << 21;
+constexpr int kGradSpill = 1 << 28;
+
+__device__ __forceinline__ void grad_global_add(unsigned long long *grad, int32_t i, long long v)
+{
+    atomicAdd(&grad[2 * i], (unsigned long long)(v >> 32));
+    atomicAdd(&grad[2 * i + 1], (unsigned long long)v & 0xFFFFFFFFull);
+}
+
+__device__ __forceinline__ void grad_bin_add(int *bins, unsigned long long *grad, int32_t i, long long v)
+{
+    if (v == 0) return;
+    if (v >= kGradDirect || v <= -kGradDirect) {
+        grad_global_add(grad, i, v);
+        return;
+    }
+    const long long nv = (long long)atomicAdd(&bins[i], (int)v) + v;
+    if (nv >= kGradSpill || nv <= -kGradSpill) grad_global_add(grad, i, (long long)atomicExch(&bins[i], 0));
+}
 
 __device__ __forceinline__ double hg_score(double ct, double g)
 {
@@ -223,7 +258,8 @@ __device__ __forceinline__ double hg_score(double ct, double g)
 
 template <class Deposit>
 struct GradSink : Deposit {
-    unsigned long long *bins;  // LDS [3][2][nz]
+    int *bins;                 // LDS [3][2][nz] int32 words
+    unsigned long long *grad;  // global [3][2][nz] (hi, lo) pairs
     int32_t nz;
     double inv_mu_s;           // 1/mu_s, 0 when mu_s = 0
     template <typename R>
@@ -237,9 +273,9 @@ struct GradSink : Deposit {
         const long long vs = __double2ll_rn(sw * (((double)p.k * inv_mu_s - ls) * dd - sq));
         const long long va = __double2ll_rn(sw * (-ls * dd - sq));
         const long long vg = __double2ll_rn(sw * (p.score_g * dd));
-        if (vs) atomicAdd(&bins[base], (unsigned long long)vs);
-        if (va) atomicAdd(&bins[2 * nz + base], (unsigned long long)va);
-        if (vg) atomicAdd(&bins[4 * nz + base], (unsigned long long)vg);
+        grad_bin_add(bins, grad, base, vs);
+        grad_bin_add(bins, grad, 2 * nz + base, va);
+        grad_bin_add(bins, grad, 4 * nz + base, vg);
     }
     template <typename R> __device__ __forceinline__ void deflect(Photon<R> &p, const Job &J, R ct)
     {
@@ -316,15 +352,16 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
     __shared__ unsigned long long acc[MC_NSCALARS];
     __shared__ uint32_t s_lidx[LOGGED ? kWaves * K * kLogStride : 1];
     __shared__ uint32_t s_lval[LOGGED ? kWaves * K * kLogStride : 1];
-    extern __shared__ unsigned long long s_dyn[];   // GRAD: bins [3][2][nz]; ESC: weights [nbins], then counts
+    extern __shared__ unsigned long long s_dyn[];   // GRAD: int32 bins [3][2][nz]; ESC: weights [nbins], then counts
     unsigned long long *esc_w = s_dyn;
     unsigned int *esc_n = reinterpret_cast<unsigned int *>(s_dyn + (ESC ? eh.nbins : 0));
     const uint32_t lane = __lane_id();
     uint32_t *lidx = s_lidx + (threadIdx.x >> 6) * (LOGGED ? K * kLogStride : 0);
     uint32_t *lval = s_lval + (threadIdx.x >> 6) * (LOGGED ? K * kLogStride : 0);
     if (threadIdx.x < MC_NSCALARS) acc[threadIdx.x] = 0ull;
+    int *gbins = reinterpret_cast<int *>(s_dyn);
     if (GRAD)
-        for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) s_dyn[i] = 0ull;
+        for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) gbins[i] = 0;
     if (ESC)
         for (int32_t i = threadIdx.x; i < eh.nbins; i += BLOCK) {
             esc_w[i] = 0ull;
@@ -340,7 +377,8 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
         sink.lval = lval;
     }
     if constexpr (GRAD) {
-        sink.bins = s_dyn;
+        sink.bins = gbins;
+        sink.grad = grad;
         sink.nz = J.nz;
         sink.inv_mu_s = J.mu_s > 0.0 ? 1.0 / J.mu_s : 0.0;
     }
@@ -428,13 +466,10 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
                 atomicAdd(&eh.n[i], (unsigned long long)esc_n[i]);
             }
     if (GRAD) {
-        // signed block sums into (hi, lo) pairs: total = sum(hi) * 2^32 + sum(lo)
+        // what the words still hold, signed, into the (hi, lo) pairs: total = sum(hi) * 2^32 + sum(lo)
         for (int32_t i = threadIdx.x; i < 6 * J.nz; i += BLOCK) {
-            const long long v = (long long)s_dyn[i];
-            if (v) {
-                atomicAdd(&grad[2 * i], (unsigned long long)(v >> 32));
-                atomicAdd(&grad[2 * i + 1], (unsigned long long)v & 0xFFFFFFFFull);
-            }
+            const long long v = (long long)gbins[i];
+            if (v) grad_global_add(grad, i, v);
         }
     }
 }
@@ -641,7 +676,7 @@ __global__ void k_grad_finalize(const unsigned long long *__restrict__ grad, con
                                 double *__restrict__ jac)
 {
     const double face = (double)nx * (double)ny;
-    const double norm = face / ((double)S[MC_S_LAUNCHED] * 2147483648.0) / 0x1.0p-16;
+    const double norm = face / ((double)S[MC_S_LAUNCHED] * 2147483648.0) / kGradScale;
     const int32_t row = 2 + nz;
     for (int32_t i = threadIdx.x; i < 3 * nz; i += blockDim.x) {
         const int32_t p = i / nz, z = i % nz;
@@ -936,7 +971,7 @@ template <typename R, bool GRAD, bool LOGGED, bool GENERAL, bool ESC>
 void enqueue_walk(int block, int blocks, const Job &J, unsigned long long *queue, const mc_tune &t,
                   unsigned long long *grad, const EscHist &eh, hipStream_t s)
 {
-    const size_t lds = GRAD ? (size_t)6 * J.nz * sizeof(unsigned long long)
+    const size_t lds = GRAD ? (size_t)6 * J.nz * sizeof(int)
                             : (ESC ? (size_t)eh.nbins * (sizeof(unsigned long long) + sizeof(unsigned int)) : 0);
     switch (block) {
     case 64:

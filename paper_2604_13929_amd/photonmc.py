@@ -23,7 +23,9 @@ MC_TIMED = 2
 MC_FP64 = 4
 MC_DIRECT_DEPOSIT = 8
 #: Q31 units per deposit quantum: each segment's deposit is rounded to a multiple of it
+ABI_VERSION = 4
 DEPOSIT_QUANTUM = 256
+GRAD_FIXED_BITS = 20        # score bins in units of 2^-20 Q31 weight x voxel
 NSCALARS = 16
 NSUMMARY = 32
 SCALARS = ["R", "T", "A", "RR", "lost", "esc_w", "esc_w_gtL", "esc_w_void_path_lo", "esc_n", "esc_n_gtL",
@@ -153,7 +155,7 @@ _SIGS = {
 _lib = None
 
 
-MC_OK, MC_WARN_LOST, MC_EOVERFLOW = 0, 1, -2
+MC_OK, MC_WARN_LOST, MC_EINVAL, MC_EOVERFLOW, MC_EHIP, MC_ENOSPACE = 0, 1, -1, -2, -3, -4
 
 
 class McError(RuntimeError):
@@ -188,8 +190,11 @@ def load(path: str = LIB_PATH):
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
+    if L.mc_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"ABI mismatch: {path} is version {L.mc_abi_version()}, the binding {ABI_VERSION}; "
+                           "rebuild the library")
     for name, size in (("mc_volume", ctypes.sizeof(McVolume)), ("mc_optics", ctypes.sizeof(McOptics)),
-                       ("mc_job", ctypes.sizeof(McJob)),
+                       ("mc_job", ctypes.sizeof(McJob)), ("mc_escape_bins", ctypes.sizeof(McEscapeBins)),
                        ("mc_tune", ctypes.sizeof(McTune)), ("mc_trace_rec", TRACE_DTYPE.itemsize),
                        ("mc_photon_rec", PHOTON_DTYPE.itemsize), ("mc_ch_grid", ctypes.sizeof(McChGrid))):
         if L.mc_sizeof(name.encode()) != size:
@@ -604,7 +609,7 @@ class GradResult:
     depth: torch.Tensor           # float64 [3, nz]
 
     def bins_value(self) -> np.ndarray:
-        """Exact bin values (hi * 2^32 + lo) as float64 [3, 2, nz], units 2^-16 Q31 weight x voxel."""
+        """Exact bin values (hi * 2^32 + lo) as float64 [3, 2, nz], units 2^-GRAD_FIXED_BITS Q31 weight x voxel."""
         b = self.bins.cpu().numpy()
         hi = b[..., 0].astype(np.float64)
         lo = b[..., 1].view(np.uint64).astype(np.float64)

@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version_and_layouts(lib):
-    assert lib.mc_abi_version() == 3
+    assert lib.mc_abi_version() == 4
     assert lib.mc_sizeof(b"mc_tune") == ctypes.sizeof(pm.McTune) == 20
     assert lib.mc_sizeof(b"mc_volume") == 24
     assert lib.mc_sizeof(b"mc_optics") == ctypes.sizeof(pm.McOptics) == 56
@@ -50,6 +50,19 @@ def test_abi_version_and_layouts(lib):
     assert lib.mc_sizeof(b"mc_job") == ctypes.sizeof(pm.McJob)
     assert lib.mc_sizeof(b"mc_escape_bins") == ctypes.sizeof(pm.McEscapeBins) == 32
     assert lib.mc_sizeof(b"nonsense") == 0
+
+
+def test_header_constants_match_the_binding():
+    """The #define constants the binding repeats are the header's."""
+    text = open(HEADERS[0]).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"^#define (MC_[A-Z0-9_]+) \(?(-?\d+)\)?", text, re.M)}
+    assert defs["MC_ABI_VERSION"] == pm.ABI_VERSION
+    assert defs["MC_DEPOSIT_QUANTUM"] == pm.DEPOSIT_QUANTUM
+    assert defs["MC_GRAD_FIXED_BITS"] == pm.GRAD_FIXED_BITS
+    assert defs["MC_MAX_BATCH_JOBS"] == pm.MAX_BATCH_JOBS
+    for name in ("MC_ACCUMULATE", "MC_TIMED", "MC_FP64", "MC_DIRECT_DEPOSIT", "MC_OK", "MC_WARN_LOST",
+                 "MC_EINVAL", "MC_EOVERFLOW", "MC_EHIP", "MC_ENOSPACE"):
+        assert defs[name] == getattr(pm, name), name
 
 
 def test_strerror(lib):

@@ -41,7 +41,19 @@ def dev(mask):
 def norm_bins(g: pm.GradResult, mask, n):
     """Score bins as d(sum of Phi/S0 over the voxels of a (phase, depth) cell)."""
     nz, ny, nx = mask.shape
-    return g.bins_value() * 2.0 ** 16 * (nx * ny) / (n * W1)
+    return g.bins_value() * 2.0 ** pm.GRAD_FIXED_BITS * (nx * ny) / (n * W1)
+
+
+def rounding_bound(g: pm.GradResult, mask, n):
+    """Six standard deviations of the fixed-point rounding in a bin, in norm_bins units:
+    the walk rounds each segment's value to the nearest unit (an error uniform in half a
+    unit either way, independent between segments), and a bin holds at most the run's
+    photon-steps of them, so the error's standard deviation is at most sqrt(steps / 12)
+    units.  The oracle sums the same values unrounded in FP64."""
+    nz, ny, nx = mask.shape
+    steps = g.run.scalar_dict()["steps"]
+    unit = 2.0 ** pm.GRAD_FIXED_BITS * (nx * ny) / (n * W1)
+    return 6.0 * math.sqrt(steps / 12.0) * unit
 
 
 def test_grad_walk_forward_equals_run(mask_m1):
@@ -64,7 +76,7 @@ def test_grad_bins_fp64_match_oracle(mask_m1):
     got = norm_bins(g, mask_m1, n)
     want = ref["grad"][0] * (nx * ny) / (n * W1)
     scale = np.abs(want).max(axis=-1, keepdims=True)
-    assert np.all(np.abs(got - want) <= 1e-6 * scale + 1e-9), np.abs(got - want).max()
+    assert np.all(np.abs(got - want) <= 1e-6 * scale + rounding_bound(g, mask_m1, n)), np.abs(got - want).max()
 
 
 def test_grad_fp32_within_oracle_error(mask_m1):
@@ -147,3 +159,63 @@ def test_autograd_function_contracts_jacobian(mask_m1):
     assert torch.allclose(got, want, rtol=1e-12, atol=0)
     s = pm.reduce(d, pm.run(d, OPT, 20_000, SEED))
     assert phi3d.item() == s["phi3d"]
+
+
+def _exact_bins(g: pm.GradResult) -> np.ndarray:
+    """The score bins' exact integer totals, sum(hi) * 2^32 + sum(lo), as Python ints."""
+    b = g.bins.cpu().numpy()
+    hi = b[..., 0].astype(object)
+    lo = b[..., 1].view(np.uint64).astype(object)
+    return hi * (1 << 32) + lo
+
+
+def test_grad_bins_exact_across_launch_shapes_with_large_scores():
+    """Long low-loss paths (solid mu_s 0.05, mu_a 1e-4, 40 % pores, 256 voxels deep) give
+    per-segment score values far above the size the workgroup's int32 LDS words take
+    directly, and push those words to their spill threshold many times; the bins' exact
+    integer totals are the same for every launch shape (they are sums of the same
+    per-segment fixed-point values, whatever path each value takes)."""
+    banner("grad bins with large scores: exact integer totals across launch shapes")
+    mask = inputs.spinodal_mask(32, 32, 256, 12.0, 0.4, seed=11)
+    d = dev(mask)
+    opt = pm.Optics(f32(0.05), f32(1e-4), f32(0.7))
+    n = 20_000
+    ref_bins = None
+    for tune in (pm.Tune(), pm.Tune(64, 8, 7, 1, 1), pm.Tune(512, 16, 1024, 32, 16), pm.Tune(128, 32, 64, 8, 64),
+                 pm.Tune(256, 4, 32, 16, 4)):
+        g = pm.grad(d, opt, n, SEED, tune=tune)
+        torch.cuda.synchronize()
+        exact = _exact_bins(g)
+        if ref_bins is None:
+            ref_bins = exact
+            # the mu_a bins are sums of -w l_solid d over long paths: far beyond one int32 word
+            assert max(abs(int(v)) for v in exact[1].ravel()) > (1 << 33)
+        else:
+            assert np.array_equal(exact, ref_bins), tune
+
+
+def test_grad_with_large_scores_matches_oracle():
+    """A thin mostly-solid slab (16 x 16 x 96, 30 % pores) with forward scattering and
+    little absorption (mu_s 0.1, mu_a 1e-4, g 0.9): the mu_s and mu_a scores of
+    full-weight photons deep in the slab (k / mu_s - l_solid and l_solid of tens of
+    voxels) give per-segment values of 2^20 and more, the ones that bypass the LDS
+    words.  The FP32 Jacobian lies within 4 sigma of the oracle's batch error; the FP64
+    transport's Jacobian equals the oracle's on the same photons to 1e-4 (a near-tie
+    decision that sends one photon of 2e5 elsewhere moves an entry by ~1e-5)."""
+    banner("grad with large scores: FP32 within 4 sigma, FP64 to 1e-4 of the oracle")
+    mask = inputs.spinodal_mask(16, 16, 96, 8.0, 0.3, seed=12)
+    opt = pm.Optics(f32(0.1), f32(1e-4), f32(0.9))
+    n, B = 200_000, 32
+    d = dev(mask)
+    ref = oracle.run(mask, opt.mu_s, opt.mu_a, opt.g, n, SEED, nbatch=B, grad=True, fluence=False)
+    nz, ny, nx = mask.shape
+    solid = (mask == 0)
+    per_b = ref["grad"] * (nx * ny) / (n / B * W1)                 # [B, 3, 2, nz]
+    d3 = per_b[:, :, 0, :].sum(-1) / solid.sum()
+    d1 = per_b.sum(axis=(2, 3)) / mask.size
+    jac = pm.grad(d, opt, n, SEED).jac.cpu().numpy()
+    jac64 = pm.grad(d, opt, n, SEED, fp64=True).jac.cpu().numpy()
+    for col, arr in ((0, d3), (1, d1)):
+        m, sd = arr.mean(0), arr.std(0, ddof=1) / math.sqrt(B)
+        assert np.all(np.abs(jac[:, col] - m) < 4 * sd + 1e-12), (col, jac[:, col], m, sd)
+        assert np.all(np.abs(jac64[:, col] - m) <= 1e-4 * np.abs(m) + 1e-12), (col, jac64[:, col], m)
