@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "philox.hpp"
 
 namespace pmc {
@@ -118,8 +120,18 @@ __device__ __forceinline__ uint64_t r_to_u64(double x) { return __double2ull_rn(
 template <typename R> __device__ __forceinline__ R r_inf() { return (R)kInf; }
 template <typename R> __device__ __forceinline__ R clamp01(R x) { return fmin(fmax(x, (R)0), (R)1); }
 template <typename R> __device__ __forceinline__ R u01(uint32_t r) { return (R)(r >> 8) * (R)0x1.0p-24; }
+// 1/x: the hardware reciprocal in the FP32 transport (within 1 ulp), the correctly
+// rounded quotient in the FP64 reference transport
+__device__ __forceinline__ float r_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double r_rcp(double x) { return 1.0 / x; }
+// a/b: a times the hardware reciprocal in FP32, the correctly rounded quotient in FP64
+__device__ __forceinline__ float r_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double r_div(double a, double b) { return a / b; }
+// 1/sqrt(x): the hardware reciprocal square root in FP32 (within 1 ulp)
+__device__ __forceinline__ float r_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double r_rsqrt(double x) { return 1.0 / sqrt(x); }
 // 1/|u| per axis, +inf on an axis the photon does not move along
-template <typename R> __device__ __forceinline__ R inv_abs(R u) { return u != (R)0 ? (R)1 / fabs(u) : r_inf<R>(); }
+template <typename R> __device__ __forceinline__ R inv_abs(R u) { return u != (R)0 ? r_rcp(fabs(u)) : r_inf<R>(); }
 
 // The face distances divide by |u| every step; the quotients are computed once per
 // direction (at launch, deflection and refraction) and kept in the photon state.
@@ -193,11 +205,20 @@ __device__ __forceinline__ uint64_t stage_voxel(const Job &J, uint32_t idx)
     return (z * (uint64_t)J.ny + y) * (uint64_t)J.nx + x;
 }
 
+template <typename R>
 __device__ __forceinline__ double free_path(const Job &J, uint32_t r)
 {
-    // tau = -ln U, U in (0,1]; the interaction lies tau / mu_t into the solid
-    const double u = (double)((r >> 8) + 1u) * 0x1.0p-24;
-    return J.mu_t > 0.0 ? -log(u) / J.mu_t : (double)kInf;
+    // tau = -ln U, U in (0,1]; the interaction lies tau / mu_t into the solid.  The
+    // FP32 transport takes the logarithm and the quotient in FP32 (the remaining path
+    // is then kept in FP64 as it is consumed); the FP64 transport takes both in FP64.
+    if (!(J.mu_t > 0.0)) return (double)kInf;
+    if constexpr (std::is_same<R, float>::value) {
+        const float u = (float)((r >> 8) + 1u) * 0x1.0p-24f;
+        return (double)(-logf(u) * r_rcp((float)J.mu_t));
+    } else {
+        const double u = (double)((r >> 8) + 1u) * 0x1.0p-24;
+        return -log(u) / J.mu_t;
+    }
 }
 
 // Launch photon `pid` (Philox block k = 0): uniform position on the z = 0 face
@@ -225,7 +246,7 @@ __device__ __forceinline__ void launch(Photon<R> &p, const Job &J, uint32_t pid)
     } else {
         set_direction(p, (R)0, (R)0, (R)1);
     }
-    p.s_rem = free_path(J, r.z);
+    p.s_rem = free_path<R>(J, r.z);
     p.l_void = 0.0;
     p.l_tot = 0.0;
     p.score_g = 0.0;
@@ -255,10 +276,10 @@ __device__ __forceinline__ R scatter(Photon<R> &p, const Job &J, uint32_t r0, ui
     R ct, st2;
     if (g != (R)0) {
         const R den = (R)1 - g + (R)2 * g * xi;
-        const R t = ((R)1 - g * g) / den;
-        ct = ((R)1 + g * g - t * t) / ((R)2 * g);
-        const R om = ((R)1 - g) * ((R)1 - xi) * (t + (R)1 - g) / den;
-        const R op = ((R)1 + g) * xi * ((R)1 + g + t) / den;
+        const R t = r_div((R)1 - g * g, den);
+        ct = r_div((R)1 + g * g - t * t, (R)2 * g);
+        const R om = r_div(((R)1 - g) * ((R)1 - xi) * (t + (R)1 - g), den);
+        const R op = r_div(((R)1 + g) * xi * ((R)1 + g + t), den);
         st2 = om * op;
     } else {
         ct = (R)2 * xi - (R)1;
@@ -276,12 +297,12 @@ __device__ __forceinline__ R scatter(Photon<R> &p, const Job &J, uint32_t r0, ui
         ny = st * sp;
         nz = (uz >= (R)0 ? ct : -ct);
     } else {
-        const R it = (R)1 / tn;
+        const R it = r_rcp(tn);
         nx = st * (ux * uz * cp - uy * sp) * it + ux * ct;
         ny = st * (uy * uz * cp + ux * sp) * it + uy * ct;
         nz = -st * cp * tn + uz * ct;
     }
-    const R inrm = (R)1 / r_sqrt(nx * nx + ny * ny + nz * nz);
+    const R inrm = r_rsqrt(nx * nx + ny * ny + nz * nz);
     set_direction(p, nx * inrm, ny * inrm, nz * inrm);
     return ct;
 }
@@ -289,18 +310,28 @@ __device__ __forceinline__ R scatter(Photon<R> &p, const Job &J, uint32_t r0, ui
 // Unpolarised Fresnel reflectance from index n1 into n2 at incidence cosine ci:
 // the mean of the s and p power coefficients.  Returns 1 on total internal
 // reflection; otherwise *ct is the cosine of the refracted direction.
+// The FP32 transport forms both quotients from one reciprocal of the product of
+// their denominators.
 template <typename R>
 __device__ __forceinline__ R fresnel(R n1, R n2, R ci, R *ct)
 {
-    const R eta = n1 / n2;
+    const R eta = r_div(n1, n2);
     const R st2 = eta * eta * ((R)1 - ci * ci);
     if (st2 >= (R)1) {
         *ct = (R)0;
         return (R)1;
     }
     const R c = r_sqrt((R)1 - st2);
-    const R rs = (n1 * ci - n2 * c) / (n1 * ci + n2 * c);
-    const R rp = (n1 * c - n2 * ci) / (n1 * c + n2 * ci);
+    R rs, rp;
+    if constexpr (std::is_same<R, float>::value) {
+        const R ds = n1 * ci + n2 * c, dp = n1 * c + n2 * ci;
+        const R inv = r_rcp(ds * dp);
+        rs = (n1 * ci - n2 * c) * dp * inv;
+        rp = (n1 * c - n2 * ci) * ds * inv;
+    } else {
+        rs = (n1 * ci - n2 * c) / (n1 * ci + n2 * c);
+        rp = (n1 * c - n2 * ci) / (n1 * c + n2 * ci);
+    }
     *ct = c;
     return (R)0.5 * (rs * rs + rp * rp);
 }
@@ -440,7 +471,7 @@ __device__ __forceinline__ int32_t advance(Photon<R> &p, const Job &J, Sink &sin
             if (rf >= (R)1 || fresnel_uniform(p, J) < rf) {
                 reflect = true;
             } else {
-                const R eta = n1 / n2;
+                const R eta = r_div(n1, n2);
                 set_direction(p, axis == 0 ? (R)sgn * ct : eta * p.ux, axis == 1 ? (R)sgn * ct : eta * p.uy,
                               axis == 2 ? (R)sgn * ct : eta * p.uz);
             }
@@ -506,7 +537,7 @@ __device__ __forceinline__ int32_t interact(Photon<R> &p, const Job &J, Sink &si
             ev = EV_DEAD_ROULETTE;
         }
     }
-    p.s_rem = free_path(J, r.z);
+    p.s_rem = free_path<R>(J, r.z);
     return ev;
 }
 
