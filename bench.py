@@ -57,6 +57,34 @@ def recorded_traffic(photons: int):
     return rec, rec["traffic_bytes_per_launch"] * photons / rec["photons"]
 
 
+def plain_roofs(rec: dict, photons: int, photon_steps: int, walk_ms: float):
+    """The plain walk's roofs for a launch of ``photons`` photons and ``photon_steps`` steps
+    that took ``walk_ms``, from its committed counter record (same sources): the HBM-side
+    bytes of the launch; the memory-side atomic request rate against the probe's ceiling
+    for the walk's kind of request (the binding limit); and the VALU, at 4 cycles per
+    wave64 instruction on each of the 1024 SIMDs at the clock the record's GRBM cycles and
+    kernel time give (an estimate: FP64 and quarter-rate instructions take longer)."""
+    scale = photons / rec["photons"]
+    t = walk_ms * 1e-3
+    traffic = rec["traffic_bytes_per_launch"] * scale
+    req = rec["atomic_requests_per_launch"] * scale
+    atomic = {"requests_per_launch": req, "requests_per_step": req / photon_steps,
+              "achieved_requests_per_s": req / t,
+              "ceiling_requests_per_s": rec["request_ceiling_per_s"], "ceiling": rec["request_ceiling_source"],
+              "frac": req / t / rec["request_ceiling_per_s"],
+              "source": os.path.relpath(TRAFFIC_RECORD, ROOT)}
+    v = rec["valu"]
+    clock = v["GRBM_GUI_ACTIVE"] / 8 / (rec["kernel_trace_avg_ms"] * 1e-3)   # one XCD's cycles per second
+    simd_cycles = v["SQ_ACTIVE_INST_VALU"] * scale * 4 / 1024                 # VALU cycles per SIMD
+    valu = {"instructions_per_step": v["SQ_INSTS_VALU"] / rec["photon_steps"],
+            "thread_utilisation": v["thread_utilisation"],
+            "roof_photon_steps_per_s": photon_steps / (simd_cycles / clock),
+            "achieved_photon_steps_per_s": photon_steps / t,
+            "frac": simd_cycles / (clock * t), "clock_hz": clock,
+            "source": os.path.relpath(TRAFFIC_RECORD, ROOT)}
+    return traffic, atomic, valu
+
+
 def walk_roofline(form: str, photon_steps: int, walk_ms: float):
     """Roofline of the batched or differentiated walk launch just timed: the algorithmic
     HBM rate (8 B per photon-step) against 8 TB/s, and the memory-side atomic request
@@ -839,17 +867,9 @@ def main():
 
     tr = recorded_traffic(n)
     if tr is not None:
-        rec, traffic = tr
+        rec, _ = tr
+        traffic, line["atomic_request_roof"], line["valu_roof"] = plain_roofs(rec, n, steps_per_run, walk_avg_ms)
         line["roofline"]["traffic"] = traffic
-        # the binding limit: memory-side atomic requests (64-byte lines), against the rate the scatter
-        # probe measures for the walk's kind of request
-        req = rec["atomic_requests_per_launch"] * n / rec["photons"]
-        line["atomic_request_roof"] = {
-            "requests_per_launch": req, "requests_per_step": req / steps_per_run,
-            "achieved_requests_per_s": req / (walk_avg_ms * 1e-3),
-            "ceiling_requests_per_s": rec["request_ceiling_per_s"], "ceiling": rec["request_ceiling_source"],
-            "frac": req / (walk_avg_ms * 1e-3) / rec["request_ceiling_per_s"],
-            "source": os.path.relpath(TRAFFIC_RECORD, ROOT)}
 
     if not args.no_rows:
         line["rows"] = rows_leg(args, seed, field)
