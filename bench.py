@@ -836,6 +836,17 @@ def main():
     photons_per_s = n * args.steps / t_el
     walk_avg_ms = float(np.mean(walk_ms))
     achieved_gbs = steps_per_run * BYTES_PER_STEP / (walk_avg_ms * 1e-3) / 1e9
+    del res, outs
+    # the same workload once through the FP64 reference transport (outside the timed steps)
+    r64 = pm.run(mask, opt, n, seed, timed=True, fp64=True, tune=tune)
+    s64 = pm.reduce(mask, r64)
+    fp64_leg = {"walk_ms": r64.walk_ms, "photon_steps": int(s64["steps_per_photon"] * n),
+                "photon_steps_per_s": s64["steps_per_photon"] * n / (r64.walk_ms * 1e-3),
+                "walk_time_vs_fp32": r64.walk_ms / walk_avg_ms,
+                "relative_difference_vs_fp32": {k: abs(s64[k] - summary[k]) / abs(summary[k])
+                                                for k in ("phi3d", "phi1d", "r", "R", "T", "A")}}
+    log(f"FP64 transport: walk {r64.walk_ms:.1f} ms ({r64.walk_ms / walk_avg_ms:.2f}x the FP32 walk)")
+    del r64
     line = {
         "metric": METRIC,
         "value": steps_per_s,
@@ -858,6 +869,7 @@ def main():
                      "note": "uint8 mask, pinned host memory to HBM, once per run, not in the timed steps"},
         "walk_ms_avg": walk_avg_ms,
         "walk_ms_median": float(np.median(walk_ms)),
+        "fp64_transport": fp64_leg,
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_walk", "algorithmic_bytes_per_step": BYTES_PER_STEP},
