@@ -1,6 +1,6 @@
 """bench.py's host-side helpers, without a GPU: the roofs it derives from the committed
-counter records, the guard that drops a record whose kernel sources changed, and the
-check of every oracle comparison against the stated tolerances."""
+counter records, the guard that drops a record whose kernel sources changed, the check of
+every oracle comparison against the stated tolerances, and the paper's context ratios."""
 from __future__ import annotations
 
 import json
@@ -80,3 +80,14 @@ def test_oracle_tolerance_failures():
     assert any(f.startswith("plain.steps") for f in fails)
     assert any(f.startswith("M1.phi3d") for f in fails)
     assert any(f.startswith("morphology_M3.r") for f in fails)
+
+
+def test_paper_context_reports_both_sides():
+    line = {"results": {"ratio": 0.96}, "rows": {"M2b_256cube_phi090": {"phi3d": 1.3, "phi1d": 1.4}},
+            "paper_boundary": {"paper_optics": {"ratio": 1.48}}}
+    c = bench.paper_context(line)["ratio_phi3d_over_phi1d"]
+    assert (c["paper_phi070"], c["paper_phi090"]) == (1.515, 1.774)
+    assert c["this_run"] == {"plain_model_phi070": 0.96, "plain_model_phi090": pytest.approx(1.3 / 1.4),
+                             "paper_model_paper_optics_phi070": 1.48}
+    assert bench.paper_context({"results": {"ratio": 1.0}})["ratio_phi3d_over_phi1d"]["this_run"] == \
+        {"plain_model_phi070": 1.0}
