@@ -70,7 +70,11 @@ extern "C" {
 #define MC_FP64 4           /* geometry and scattering in FP64 instead of FP32 (reference transport) */
 #define MC_DIRECT_DEPOSIT 8 /* one atomic per voxel visit into the caller's tally, not the line-coalesced
                                deposit log into a staging tally of uint32 words (the log is used when that
-                               staging tally, 2 x 2 x 4 voxels per 64-byte line, has <= 2^32 words) */
+                               staging tally has <= 2^32 words) */
+#define MC_LINE_STAGING 16  /* stage the logged deposits in one table of 2 x 2 x 4-voxel lines even where
+                               the three tables of 4 x 4-voxel planes fit (the workspace sizes allow for
+                               the planes; the two layouts give identical tallies); for mc_run_batch,
+                               in every job */
 
 #define MC_DEPOSIT_QUANTUM 256 /* Q31 units: every tally value is a multiple of it */
 #define MC_GRAD_FIXED_BITS 20  /* mc_grad's score bins count units of 2^-20 Q31 weight x voxel */

@@ -105,8 +105,8 @@ struct BatchTallySink {
 };
 
 // Line-coalesced deposits for the batch: as the plain walk's log (8-byte
-// entries, a 16-iteration window, uint32 staging words in lines of 2x2x4 voxels,
-// carries of wrapped words into the job's int64 tally), with the job index in the
+// entries, a 16-iteration window, uint32 staging words in each job's own layout,
+// planes or lines, carries of wrapped words into the job's int64 tally), with the job index in the
 // top 6 bits of the 32-bit entry index, which leaves 26 bits for the word index
 // into the job's staging tally (the batch logs only when every job's staging
 // tally is that small).  A deposit of 2^32 quanta or more goes to the job's tally
@@ -133,7 +133,7 @@ struct BatchLoggedSink {
                                        (unsigned long long)a << kDepositShift, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                lidx[slot] = stage_index(J.lnx, J.lny, p.ix, p.iy, p.iz) | tag;
+                lidx[slot] = stage_word(J, p) | tag;
                 lval[slot] = (uint32_t)a;
             }
         }
@@ -352,6 +352,7 @@ struct Layout {
     size_t jobs_off, esc_off, bricks_off[MC_MAX_BATCH_JOBS], bins_off[MC_MAX_BATCH_JOBS],
         stage_off[MC_MAX_BATCH_JOBS], esc_rep_off[MC_MAX_BATCH_JOBS], total;
     bool logged;   // every job's staging tally fits the log's 26-bit indices
+    bool planes[MC_MAX_BATCH_JOBS];   // the job's staging tally may take the plane layout
 };
 
 Layout layout_of(const mc_job *jobs, int32_t n)
@@ -363,15 +364,16 @@ Layout layout_of(const mc_job *jobs, int32_t n)
     L.esc_off = off;
     off += align_up(sizeof(BatchEsc) * MC_MAX_BATCH_JOBS);
     L.logged = true;
-    for (int32_t i = 0; i < n; ++i) L.logged = L.logged && dims_of(&jobs[i].vol).stage_words <= kBatchLogWords;
+    for (int32_t i = 0; i < n; ++i) L.logged = L.logged && dims_of(&jobs[i].vol).line_words <= kBatchLogWords;
     for (int32_t i = 0; i < n; ++i) {
         const Dims d = dims_of(&jobs[i].vol);
+        L.planes[i] = d.planes && d.stage_words <= kBatchLogWords;
         L.bricks_off[i] = off;
         off += align_up(d.nbricks * sizeof(uint64_t));
         L.bins_off[i] = off;
         off += align_up((size_t)jobs[i].vol.nz * kBinW * sizeof(uint64_t));
         L.stage_off[i] = off;
-        if (L.logged) off += align_up(d.stage_words * sizeof(uint32_t));
+        if (L.logged) off += align_up((L.planes[i] ? d.stage_words : d.line_words) * sizeof(uint32_t));
         L.esc_rep_off[i] = off;
         off += align_up(kEscReplicaWords * sizeof(uint64_t));
     }
@@ -386,9 +388,11 @@ struct Prepared {
     Layout L;
     uint64_t total_photons = 0;
     bool general = false;         // some job uses the paper boundary model
+    bool planes[MC_MAX_BATCH_JOBS] = {};   // caller's job index -> staged in the plane layout
 };
 
-int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, Prepared *P)
+// MC_LINE_STAGING in flags keeps every job's staging tally in the line layout.
+int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, int flags, Prepared *P)
 {
     if (!jobs || n < 1 || n > MC_MAX_BATCH_JOBS)
         return fail(MC_EINVAL, "a batch holds 1 to %d jobs (got %d)", MC_MAX_BATCH_JOBS, n);
@@ -426,6 +430,8 @@ int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, Prepared *
         J.bricks = (const uint64_t *)(ws + P->L.bricks_off[i]);
         J.fluence = jb.fluence;
         J.stage = P->L.logged ? (uint32_t *)(ws + P->L.stage_off[i]) : nullptr;
+        J.stage_planes = P->L.logged && P->L.planes[i] && !(flags & MC_LINE_STAGING);
+        P->planes[i] = J.stage_planes != 0;
         J.scalars = jb.scalars;
         J.queue_begin = q;
         q += jb.n_photons;
@@ -562,7 +568,9 @@ int enqueue_batch(const mc_job *jobs, const Prepared &P, char *ws, const mc_tune
             if ((rc = fill(jb.scalars, MC_NSCALARS, s))) return rc;
         }
         // the staging words as int64 pairs: a line is 16 words, so the count is even
-        if (P.L.logged && (rc = fill((int64_t *)(ws + P.L.stage_off[i]), d.stage_words / 2, s))) return rc;
+        if (P.L.logged &&
+            (rc = fill((int64_t *)(ws + P.L.stage_off[i]), (P.planes[i] ? d.stage_words : d.line_words) / 2, s)))
+            return rc;
         if ((rc = pack(&jb.vol, (uint64_t *)(ws + P.L.bricks_off[i]), s))) return rc;
     }
     const bool timed = (flags & MC_TIMED) != 0;
@@ -576,7 +584,8 @@ int enqueue_batch(const mc_job *jobs, const Prepared &P, char *ws, const mc_tune
     if (P.L.logged) {
         for (int32_t i = 0; i < n; ++i) {
             const mc_job &jb = jobs[i];
-            if ((rc = unstage((const uint32_t *)(ws + P.L.stage_off[i]), jb.fluence, &jb.vol, s))) return rc;
+            if ((rc = unstage((const uint32_t *)(ws + P.L.stage_off[i]), jb.fluence, &jb.vol, P.planes[i], s)))
+                return rc;
         }
     }
     for (int32_t i = 0; i < n; ++i) {
@@ -785,7 +794,7 @@ int mc_autotune_batch(const mc_job *jobs, int32_t n_jobs, int flags, void *works
     clear_error();
     if (!out) return fail(MC_EINVAL, "out is NULL");
     Prepared P;
-    int rc = prepare(jobs, n_jobs, (char *)workspace, workspace_bytes, &P);
+    int rc = prepare(jobs, n_jobs, (char *)workspace, workspace_bytes, flags, &P);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     const std::string key = shape_key("batch", P, flags);
@@ -802,7 +811,7 @@ int run_batch(const mc_job *jobs, int32_t n_jobs, int flags, const mc_tune *tune
               size_t workspace_bytes, void *hip_stream, const mc_escape_bins *bins)
 {
     Prepared P;
-    int rc = prepare(jobs, n_jobs, (char *)workspace, workspace_bytes, &P);
+    int rc = prepare(jobs, n_jobs, (char *)workspace, workspace_bytes, flags, &P);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     mc_tune t;
@@ -858,7 +867,7 @@ int mc_batch_graph_create(const mc_job *jobs, int32_t n_jobs, int flags, const m
     if (!out) return fail(MC_EINVAL, "out is NULL");
     if (flags & MC_TIMED) return fail(MC_EINVAL, "MC_TIMED cannot be captured; time the graph launch instead");
     Prepared P;
-    int rc = prepare(jobs, n_jobs, (char *)workspace, workspace_bytes, &P);
+    int rc = prepare(jobs, n_jobs, (char *)workspace, workspace_bytes, flags, &P);
     if (rc) return rc;
     const mc_tune t = resolve_tune(tune);
     if ((rc = check_tune(t))) return rc;

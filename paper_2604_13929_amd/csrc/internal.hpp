@@ -23,12 +23,22 @@ void clear_error();
 constexpr size_t kHeaderBytes = 256;  // queue counter(s) at the start of a run workspace
 constexpr int kBinW = 8;              // int64 words per depth bin of the reduction
 constexpr int kEscMaxBins = 512;      // escape-path bins; 6 KB of LDS leaves four walk workgroups per CU
+// The single-run walk stages its deposits in the plane layout (three tables) where
+// those fit in this many bytes, else in the line layout (one table).  Memory-side
+// atomics keep their full rate while the tally stays within the 256 MiB
+// Infinity Cache.
+#ifndef MC_PLANE_STAGE_MAX_BYTES
+#define MC_PLANE_STAGE_MAX_BYTES (192ull << 20)
+#endif
+constexpr uint64_t kPlaneStageMaxBytes = MC_PLANE_STAGE_MAX_BYTES;
 
 struct Dims {
     int32_t nxb, nyb, nzb;       // 4x4x4 mask bricks
     uint64_t nbricks, nvox;
-    int32_t lnx, lny, lnz;       // staging lines of 2x2x4 voxels
-    uint64_t stage_words;        // uint32 words of the staging tally
+    int32_t lnx, lny, lnz;       // staging lines of 2x2x4 voxels (line layout)
+    uint64_t line_words;         // uint32 words of the line layout
+    bool planes;                 // the single-run walk stages in the plane layout
+    uint64_t stage_words;        // uint32 words of the single-run walk's staging tally
     bool logged;                 // the staging tally fits 32-bit indices
 };
 size_t run_workspace_bytes(const Dims &d);
@@ -49,7 +59,7 @@ int check_tune(const mc_tune &t);
 // asynchronous building blocks on a stream
 int fill(int64_t *p, uint64_t n, hipStream_t s);
 int pack(const mc_volume *vol, uint64_t *bricks, hipStream_t s);
-int unstage(const uint32_t *stage, int64_t *fluence, const mc_volume *vol, hipStream_t s);
+int unstage(const uint32_t *stage, int64_t *fluence, const mc_volume *vol, bool planes, hipStream_t s);
 // zero (unless accumulating), pack, walk and move the staged tally into the caller's
 // fluence, with the queue, packed mask and staging tally in the workspace ws
 int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws, unsigned long long *grad_bins,

@@ -90,14 +90,20 @@ __global__ void k_pack(const uint8_t *__restrict__ mask, int32_t nx, int32_t ny,
 // The walk has already added there what the staging words could not hold (whole
 // 2^32-quanta carries and deposits of 2^32 quanta or more).
 __global__ void k_unstage(const uint32_t *__restrict__ S, int64_t *__restrict__ F, int32_t nx, int32_t ny, int32_t nz,
-                          int32_t lnx, int32_t lny)
+                          int32_t lnx, int32_t lny, int32_t planes)
 {
     const uint64_t n = (uint64_t)nx * ny * nz;
+    const PlaneDims P = plane_dims(nx, ny, nz);
     for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x) {
         const int32_t x = (int32_t)(v % (uint64_t)nx);
         const int32_t y = (int32_t)((v / (uint64_t)nx) % (uint64_t)ny);
         const int32_t z = (int32_t)(v / ((uint64_t)nx * ny));
-        F[v] += (int64_t)S[stage_index(lnx, lny, x, y, z)] << kDepositShift;
+        if (planes)
+            F[v] += (int64_t)((uint64_t)S[plane_index(P, nx, ny, 0u, x, y, z)] + S[plane_index(P, nx, ny, 1u, x, y, z)] +
+                              S[plane_index(P, nx, ny, 2u, x, y, z)])
+                    << kDepositShift;
+        else
+            F[v] += (int64_t)S[stage_index(lnx, lny, x, y, z)] << kDepositShift;
     }
 }
 
@@ -117,11 +123,12 @@ struct DirectDeposit {
 };
 
 // Fluence deposits logged in LDS, one slot per lane and iteration, for a staging
-// tally of uint32 quanta in lines of 2x2x4 voxels (16 words, one 64-byte line);
+// tally of uint32 quanta in lines of 16 words (one 64-byte line): the plane layout
+// where its three tables fit (see stage_word), else lines of 2x2x4 voxels;
 // every kLogK iterations the wavefront issues the log with lanes transposed so
 // that one atomic instruction carries kLogK successive deposits of each of
 // 64/kLogK lanes: deposits of one photon that fall in the same line travel as one
-// memory-side request.  A line holds twice the voxels a line of int64 words would
+// memory-side request.  A 2x2x4 line holds twice the voxels a line of int64 words would
 // (0.40 against 0.48 requests per photon-step over oracle trajectories of the
 // 256^3 workload), and 16-lane groups of 32-bit atomics on one line run at
 // 26.5 G requests/s against 23.7 for 8-lane groups of 64-bit atomics.
@@ -153,7 +160,7 @@ struct LoggedDeposit {
                                        (unsigned long long)a << kDepositShift, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                lidx[slot] = stage_index(J.lnx, J.lny, p.ix, p.iy, p.iz);
+                lidx[slot] = stage_word(J, p);
                 lval[slot] = (uint32_t)a;
             }
         }
@@ -782,7 +789,10 @@ Dims dims_of(const mc_volume *v)
     d.lnx = (v->nx + 1) / 2;
     d.lny = (v->ny + 1) / 2;
     d.lnz = (v->nz + 3) / 4;
-    d.stage_words = (uint64_t)d.lnx * d.lny * d.lnz * 16;
+    d.line_words = (uint64_t)d.lnx * d.lny * d.lnz * 16;
+    const uint64_t plane_words = plane_dims(v->nx, v->ny, v->nz).words;
+    d.planes = plane_words * sizeof(uint32_t) <= kPlaneStageMaxBytes;
+    d.stage_words = d.planes ? plane_words : d.line_words;
     d.logged = d.stage_words <= (1ull << 32);
     return d;
 }
@@ -1051,22 +1061,24 @@ int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws,
         if (esc && (rc = fill((int64_t *)esc->n, (uint64_t)esc->nbins, s))) return rc;
     }
     // the staging words as int64 pairs: a line is 16 words, so the count is even
-    if (logged && (rc = fill((int64_t *)stage, d.stage_words / 2, s))) return rc;
+    const bool planes = d.planes && !(flags & MC_LINE_STAGING);
+    if (logged && (rc = fill((int64_t *)stage, (planes ? d.stage_words : d.line_words) / 2, s))) return rc;
     if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
     if ((rc = pack(vol, bricks, s))) return rc;
     J.bricks = bricks;
     J.stage = logged ? stage : nullptr;
+    J.stage_planes = logged && planes;
     if ((rc = launch_walk(J, queue, t, s, flags, grad_bins, logged, esc))) return rc;
-    if (logged) return unstage(stage, J.fluence, vol, s);
+    if (logged) return unstage(stage, J.fluence, vol, planes, s);
     return MC_OK;
 }
 
-int unstage(const uint32_t *stage, int64_t *fluence, const mc_volume *vol, hipStream_t s)
+int unstage(const uint32_t *stage, int64_t *fluence, const mc_volume *vol, bool planes, hipStream_t s)
 {
     const Dims d = dims_of(vol);
     const uint64_t blocks = std::min<uint64_t>((d.nvox + 255) / 256, 16384);
     hipLaunchKernelGGL(k_unstage, dim3((unsigned)blocks), dim3(256), 0, s, stage, fluence, vol->nx, vol->ny, vol->nz,
-                       d.lnx, d.lny);
+                       d.lnx, d.lny, (int32_t)planes);
     HIP_TRY(hipGetLastError());
     return MC_OK;
 }

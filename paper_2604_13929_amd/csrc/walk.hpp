@@ -66,7 +66,8 @@ struct Job {
     int64_t *scalars;         // [MC_NSCALARS]
     int32_t nx, ny, nz;
     int32_t nxb, nyb;         // bricks along x and y
-    int32_t lnx, lny;         // staging lines along x and y
+    int32_t lnx, lny;         // staging lines along x and y (line layout)
+    int32_t stage_planes;     // 1: the staging tally is in the plane layout
     double mu_t;              // mu_s + mu_a of the solid, summed in FP64 on the host
     double mu_s;              // mu_s of the solid (the gradient walk's score)
     float g;
@@ -193,9 +194,97 @@ __host__ __device__ __forceinline__ uint32_t stage_index(int32_t lnx, int32_t ln
     return (line << 4) | ((uint32_t)(iz & 3) << 2) | ((uint32_t)(iy & 1) << 1) | (uint32_t)(ix & 1);
 }
 
-// The voxel, as an index of the [nz][ny][nx] tally, of a staging word.
-__device__ __forceinline__ uint64_t stage_voxel(const Job &J, uint32_t idx)
+// Plane layout of the staging tally: three tables whose lines are 4 x 4 voxels
+// one voxel thin, across x (table 0: 1 x 4 x 4), across y (table 1: 4 x 1 x 4)
+// and across z (table 2: 4 x 4 x 1), each padded to whole lines along its
+// 4-voxel axes.  A deposit goes into the table across the axis of the photon's
+// smallest direction component, so that the line extends along the two axes
+// the photon moves along most: over oracle trajectories of the 256^3 workload
+// this gives 0.375 requests per photon-step against 0.401 for the one table of
+// 2 x 2 x 4 lines.  A voxel's total is the sum of its three words.
+struct PlaneDims {
+    uint32_t px, py, pz;      // 4-voxel groups along x, y, z
+    uint32_t off1, off2;      // first words of tables 1 and 2
+    uint64_t words;           // words of the three tables
+};
+
+__host__ __device__ __forceinline__ PlaneDims plane_dims(int32_t nx, int32_t ny, int32_t nz)
 {
+    PlaneDims P;
+    P.px = ((uint32_t)nx + 3u) >> 2;
+    P.py = ((uint32_t)ny + 3u) >> 2;
+    P.pz = ((uint32_t)nz + 3u) >> 2;
+    const uint64_t t0 = (uint64_t)nx * P.py * P.pz * 16, t1 = (uint64_t)P.px * ny * P.pz * 16;
+    P.off1 = (uint32_t)t0;
+    P.off2 = (uint32_t)(t0 + t1);
+    P.words = t0 + t1 + (uint64_t)P.px * P.py * nz * 16;
+    return P;
+}
+
+// Word of voxel (ix, iy, iz) in plane table t; valid where P.words <= 2^32.
+__host__ __device__ __forceinline__ uint32_t plane_index(const PlaneDims &P, int32_t nx, int32_t ny, uint32_t t,
+                                                         int32_t ix, int32_t iy, int32_t iz)
+{
+    const uint32_t x = (uint32_t)ix, y = (uint32_t)iy, z = (uint32_t)iz;
+    const uint32_t zh = t == 2u ? z : z >> 2;
+    const uint32_t yh = t == 1u ? y : y >> 2;
+    const uint32_t xh = t == 0u ? x : x >> 2;
+    const uint32_t ly = t == 1u ? (uint32_t)ny : P.py;
+    const uint32_t lx = t == 0u ? (uint32_t)nx : P.px;
+    const uint32_t hi = t == 2u ? (y & 3u) : (z & 3u);
+    const uint32_t lo = t == 0u ? (y & 3u) : (x & 3u);
+    const uint32_t first = t == 0u ? 0u : (t == 1u ? P.off1 : P.off2);
+    return first + ((((zh * ly + yh) * lx + xh)) << 4) + (hi << 2) + lo;
+}
+
+// The plane table of a deposit: the one across the axis of the smallest |u|.
+template <typename R>
+__device__ __forceinline__ uint32_t plane_table(R ux, R uy, R uz)
+{
+    const R ax = fabs(ux), ay = fabs(uy), az = fabs(uz);
+    return (ax <= ay && ax <= az) ? 0u : (ay <= az ? 1u : 2u);
+}
+
+// The staging word of a photon's deposit in its current voxel.
+template <typename R>
+__device__ __forceinline__ uint32_t stage_word(const Job &J, const Photon<R> &p)
+{
+    if (J.stage_planes)
+        return plane_index(plane_dims(J.nx, J.ny, J.nz), J.nx, J.ny, plane_table(p.ux, p.uy, p.uz), p.ix, p.iy, p.iz);
+    return stage_index(J.lnx, J.lny, p.ix, p.iy, p.iz);
+}
+
+// The voxel, as an index of the [nz][ny][nx] tally, of a plane-layout word.
+__host__ __device__ __forceinline__ uint64_t plane_voxel(const Job &J, uint32_t idx)
+{
+    const PlaneDims P = plane_dims(J.nx, J.ny, J.nz);
+    const uint32_t t = idx < P.off1 ? 0u : (idx < P.off2 ? 1u : 2u);
+    const uint32_t r = idx - (t == 0u ? 0u : (t == 1u ? P.off1 : P.off2));
+    const uint32_t line = r >> 4, hi = (r >> 2) & 3u, lo = r & 3u;
+    uint64_t x, y, z;
+    if (t == 0u) {
+        const uint32_t q = line / (uint32_t)J.nx;
+        x = line - q * (uint32_t)J.nx;
+        y = (uint64_t)(q % P.py) * 4 + lo;
+        z = (uint64_t)(q / P.py) * 4 + hi;
+    } else if (t == 1u) {
+        const uint32_t q = line / P.px;
+        x = (uint64_t)(line - q * P.px) * 4 + lo;
+        y = q % (uint32_t)J.ny;
+        z = (uint64_t)(q / (uint32_t)J.ny) * 4 + hi;
+    } else {
+        const uint32_t q = line / P.px;
+        x = (uint64_t)(line - q * P.px) * 4 + lo;
+        y = (uint64_t)(q % P.py) * 4 + hi;
+        z = q / P.py;
+    }
+    return (z * (uint64_t)J.ny + y) * (uint64_t)J.nx + x;
+}
+
+// The voxel, as an index of the [nz][ny][nx] tally, of a staging word.
+__host__ __device__ __forceinline__ uint64_t stage_voxel(const Job &J, uint32_t idx)
+{
+    if (J.stage_planes) return plane_voxel(J, idx);
     const uint32_t line = idx >> 4, off = idx & 15u;
     const uint32_t t = line / (uint32_t)J.lnx;
     const uint64_t x = (uint64_t)(line - t * (uint32_t)J.lnx) * 2 + (off & 1u);

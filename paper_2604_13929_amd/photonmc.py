@@ -22,6 +22,7 @@ MC_ACCUMULATE = 1
 MC_TIMED = 2
 MC_FP64 = 4
 MC_DIRECT_DEPOSIT = 8
+MC_LINE_STAGING = 16
 #: Q31 units per deposit quantum: each segment's deposit is rounded to a multiple of it
 ABI_VERSION = 4
 DEPOSIT_QUANTUM = 256
@@ -319,8 +320,10 @@ def workspace(nbytes: int, device) -> torch.Tensor:
 
 def run(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_begin: int = 0, stream_id: int = 0,
         accumulate: RunResult | None = None, tune: Tune | None = None, timed: bool = False,
-        fp64: bool = False, direct: bool = False, escape_bins: tuple[float, int] | None = None) -> RunResult:
-    """mc_run on the current stream of the mask's device (fp64: the FP64 reference transport).
+        fp64: bool = False, direct: bool = False, escape_bins: tuple[float, int] | None = None,
+        line_staging: bool = False) -> RunResult:
+    """mc_run on the current stream of the mask's device (fp64: the FP64 reference transport;
+    direct: MC_DIRECT_DEPOSIT; line_staging: MC_LINE_STAGING).
     escape_bins = (bin_width, nbins): mc_run_escape_histogram, which also bins the
     in-pore path of the escaping photons into res.escape_hist_w / escape_hist_n."""
     L = load()
@@ -338,6 +341,8 @@ def run(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_be
         flags |= MC_FP64
     if direct:
         flags |= MC_DIRECT_DEPOSIT
+    if line_staging:
+        flags |= MC_LINE_STAGING
     nbytes = L.mc_run_workspace_bytes(ctypes.byref(vol))
     ws = workspace(nbytes, dev)
     opt = optics.c()
@@ -538,14 +543,15 @@ class Batch:
 
 
 def run_batch(jobs: list[BatchJob], tune: Tune | None = None, fp64: bool = False, timed: bool = False,
-              accumulate_into: Batch | None = None, escape_bins: list | None = None) -> Batch:
+              accumulate_into: Batch | None = None, escape_bins: list | None = None,
+              line_staging: bool = False) -> Batch:
     """mc_run_batch on the current stream; tune None: the cached (or autotuned) launch shape.
     escape_bins: one (bin_width, nbins) or None per job: mc_run_batch_escape_histogram,
     which also bins each job's escaping photons by in-pore path into
-    batch.results[i].escape_hist_w / escape_hist_n."""
+    batch.results[i].escape_hist_w / escape_hist_n.  line_staging: MC_LINE_STAGING."""
     L = load()
     b = Batch(jobs, accumulate_into)
-    flags = (MC_FP64 if fp64 else 0) | (MC_TIMED if timed else 0)
+    flags = (MC_FP64 if fp64 else 0) | (MC_TIMED if timed else 0) | (MC_LINE_STAGING if line_staging else 0)
     t = tune.c() if tune is not None else None
     tref = ctypes.byref(t) if t is not None else None
     if escape_bins is None:
@@ -617,8 +623,8 @@ class GradResult:
 
 
 def grad(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_begin: int = 0, stream_id: int = 0,
-         fp64: bool = False, timed: bool = False, tune: Tune | None = None) -> GradResult:
-    """mc_grad on the current stream."""
+         fp64: bool = False, timed: bool = False, tune: Tune | None = None, line_staging: bool = False) -> GradResult:
+    """mc_grad on the current stream (line_staging: MC_LINE_STAGING)."""
     L = load()
     vol = volume(mask)
     dev = mask.device
@@ -632,7 +638,7 @@ def grad(mask: torch.Tensor, optics: Optics, n_photons: int, seed: int, photon_b
     ws = workspace(L.mc_grad_workspace_bytes(ctypes.byref(vol)), dev)
     opt = optics.c()
     t = tune.c() if tune is not None else None
-    flags = (MC_FP64 if fp64 else 0) | (MC_TIMED if timed else 0)
+    flags = (MC_FP64 if fp64 else 0) | (MC_TIMED if timed else 0) | (MC_LINE_STAGING if line_staging else 0)
     _check(L.mc_grad(ctypes.byref(vol), ctypes.byref(opt), photon_begin, n_photons, seed, stream_id, flags,
                      run_.fluence.data_ptr(), run_.scalars.data_ptr(), bins.data_ptr(), jac.data_ptr(),
                      summary.data_ptr(), depth.data_ptr(), ws.data_ptr(), ws.numel(),

@@ -60,7 +60,7 @@ def test_header_constants_match_the_binding():
     assert defs["MC_DEPOSIT_QUANTUM"] == pm.DEPOSIT_QUANTUM
     assert defs["MC_GRAD_FIXED_BITS"] == pm.GRAD_FIXED_BITS
     assert defs["MC_MAX_BATCH_JOBS"] == pm.MAX_BATCH_JOBS
-    for name in ("MC_ACCUMULATE", "MC_TIMED", "MC_FP64", "MC_DIRECT_DEPOSIT", "MC_OK", "MC_WARN_LOST",
+    for name in ("MC_ACCUMULATE", "MC_TIMED", "MC_FP64", "MC_DIRECT_DEPOSIT", "MC_LINE_STAGING", "MC_OK", "MC_WARN_LOST",
                  "MC_EINVAL", "MC_EOVERFLOW", "MC_EHIP", "MC_ENOSPACE"):
         assert defs[name] == getattr(pm, name), name
 
@@ -106,9 +106,16 @@ def test_run_rejects_bad_tune(lib):
 def test_workspace_sizes(lib):
     vol = pm.McVolume(9, 5, 7, 0, 1)
     # header + one uint64 per 4x4x4 mask brick (3 x 2 x 2 bricks, padded to 256 bytes) + the staging
-    # tally in lines of 2x2x4 uint32 words (5 x 3 x 2 lines of 16 words, padded to 256 bytes)
-    assert lib.mc_run_workspace_bytes(ctypes.byref(vol)) == 256 + 256 + 2048
-    assert 5 * 3 * 2 * 16 * 4 == 1920
+    # tally in the plane layout: lines of 4 x 4 uint32 words one voxel thin across x (9 x 2 x 2 lines),
+    # across y (3 x 5 x 2) and across z (3 x 2 x 7), 16 words each
+    assert lib.mc_run_workspace_bytes(ctypes.byref(vol)) == 256 + 256 + (9 * 2 * 2 + 3 * 5 * 2 + 3 * 2 * 7) * 16 * 4
+    # 512 x 512 x 256: the three plane tables (768 MiB) exceed 192 MiB, so the line layout of 2 x 2 x 4
+    # voxels (256 x 256 x 64 lines of 16 words); 128 x 128 x 64 mask bricks
+    big = pm.McVolume(512, 512, 256, 0, 1)
+    assert lib.mc_run_workspace_bytes(ctypes.byref(big)) == 256 + 128 * 128 * 64 * 8 + 256 * 256 * 64 * 16 * 4
+    # 256^3: the plane layout, three tables of 2^24 words
+    cube = pm.McVolume(256, 256, 256, 0, 1)
+    assert lib.mc_run_workspace_bytes(ctypes.byref(cube)) == 256 + 64 ** 3 * 8 + 3 * (1 << 24) * 4
     assert lib.mc_reduce_workspace_bytes(ctypes.byref(vol)) == 7 * 8 * 8
     bad = pm.McVolume(0, 5, 7, 0, 1)
     assert lib.mc_run_workspace_bytes(ctypes.byref(bad)) == 0

@@ -179,6 +179,14 @@ def test_batch_equals_plain_runs(small_jobs):
                 a, c = bs[key], s[key]
                 assert (a == c) or (np.isnan(a) and np.isnan(c)), (k, key)
             assert np.array_equal(bs.depth, s.depth, equal_nan=True)
+    # every job staged in the line layout instead of the plane layout: the same bits
+    for fp64 in (False, True):
+        b = pm.run_batch(small_jobs, tune=pm.Tune(256, 16, 256, 16), fp64=fp64, line_staging=True)
+        torch.cuda.synchronize()
+        for k, j in enumerate(small_jobs):
+            r = plains[k][0] if not fp64 else _plain(j, fp64=True)[0]
+            assert torch.equal(b.results[k].fluence, r.fluence), ("lines", fp64, k)
+            assert torch.equal(b.results[k].scalars, r.scalars), ("lines", fp64, k)
 
 
 def test_batch_with_extreme_extents_equals_plain_runs():

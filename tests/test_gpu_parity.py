@@ -328,6 +328,35 @@ def test_bitwise_reproducible_and_tune_invariant(mask_m1):
         assert torch.equal(r.fluence, F0) and torch.equal(r.scalars, S0), t
 
 
+def test_staging_layouts_agree_bitwise():
+    """The plane layout (three tables of 4 x 4-voxel planes, chosen per deposit by the
+    photon's direction), the line layout (one table of 2 x 2 x 4-voxel lines) and one
+    atomic per visit give the same tallies bit for bit, on a ragged volume whose sides
+    are no multiple of 4: FP32 and FP64 transport, the paper's boundary model, the
+    escape-path histogram run and the gradient walk."""
+    banner("staging layouts: planes == lines == direct, 37 x 29 x 23")
+    m = inputs.spinodal_mask(37, 29, 23, 12.0, 0.6, seed=5)
+    d = dev(m)
+    n = 60_000
+    paper = pm.paper_optics(0.5, f32(0.01), f32(0.7), n_solid=f32(1.746), lateral=pm.LATERAL_MIRROR, gate=300.0)
+    for opt in (OPT, paper):
+        for fp64 in (False, True):
+            runs = [pm.run(d, opt, n, SEED, stream_id=3, fp64=fp64, line_staging=ls, direct=di)
+                    for ls, di in ((False, False), (True, False), (False, True))]
+            for r in runs[1:]:
+                assert torch.equal(r.fluence, runs[0].fluence) and torch.equal(r.scalars, runs[0].scalars), fp64
+            assert int(runs[0].fluence.max()) > 0
+    h = [pm.run(d, OPT, n, SEED, escape_bins=(2.0, 64), line_staging=ls) for ls in (False, True)]
+    assert torch.equal(h[0].fluence, h[1].fluence) and torch.equal(h[0].escape_hist_w, h[1].escape_hist_w)
+    g = [pm.grad(d, OPT, n, SEED, line_staging=ls) for ls in (False, True)]
+    assert torch.equal(g[0].run.fluence, g[1].run.fluence)
+
+    def exact(gr):   # the score bins' integer totals, hi * 2^32 + lo (their split into words may differ)
+        b = gr.bins.cpu().numpy().reshape(-1, 2)
+        return [int(hi) * 2 ** 32 + int(lo) for hi, lo in zip(b[:, 0], b[:, 1].view(np.uint64))]
+    assert exact(g[0]) == exact(g[1])
+
+
 def test_large_per_voxel_deposits_bypass_the_log():
     """A dense, non-absorbing solid (mu_s = 3000 per voxel, g = 0, a 3x3x3 slab) keeps some
     photons scattering inside one voxel for thousands of voxel lengths, so their deposit
@@ -341,9 +370,11 @@ def test_large_per_voxel_deposits_bypass_the_log():
     n = 8000
     d = dev(m)
     for fp64 in (False, True):
-        logged = pm.run(d, opt, n, SEED, fp64=fp64)
         direct = pm.run(d, opt, n, SEED, fp64=fp64, direct=True)
-        assert torch.equal(logged.fluence, direct.fluence) and torch.equal(logged.scalars, direct.scalars), fp64
+        for lines in (False, True):
+            logged = pm.run(d, opt, n, SEED, fp64=fp64, line_staging=lines)
+            assert torch.equal(logged.fluence, direct.fluence) and torch.equal(logged.scalars, direct.scalars), \
+                (fp64, lines)
     _, oo = oracle.trace(m, opt.mu_s, opt.mu_a, opt.g, np.arange(n, dtype=np.uint64), SEED, max_rec=0)
     big = int((oo["max_visit"] >= 2.0 ** 32 * pm.DEPOSIT_QUANTUM).sum())
     print(f"{big} of {n} photons deposit 2^32 quanta or more in one stay", flush=True)
