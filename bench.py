@@ -722,10 +722,11 @@ def main():
                  6: "atomic64_device_8lane_64B", 7: "atomic64_device_4lane_32B", 8: "atomic64_device_return",
                  9: "atomic32_device_return", 10: "atomic32_device_16lane_64B",
                  11: "atomic32_device_16lane_64B_return", 12: "atomic64_device_8lane_64B_return"}
-        # every mode at 16 waves per CU on four table sizes, the walk's request kinds also at 64 MiB
-        # (the staging tally of the 256^3 workload), then the occupancy sweep at 128 MiB
+        # every mode at 16 waves per CU on four table sizes, the walk's request kinds also at 64, 192
+        # and 256 MiB (the staging tallies of the 256^3 workload in lines and in planes, and of the
+        # 512x512x256 volumes), then the occupancy sweep at 128 MiB
         plan = [(mib, mode, 16) for mib in (2, 128, 512, 2048) for mode in names]
-        plan += [(64, mode, 16) for mode in (0, 3, 6, 10, 11)]
+        plan += [(mib, mode, 16) for mib in (64, 192, 256) for mode in (0, 3, 6, 10, 11)]
         plan += [(128, mode, w) for w in (4, 8, 24, 32) for mode in (0, 3, 6, 8, 9, 10, 11, 12)]
         tables = {}
         for mib, mode, w in plan:

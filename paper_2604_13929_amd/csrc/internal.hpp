@@ -23,10 +23,10 @@ void clear_error();
 constexpr size_t kHeaderBytes = 256;  // queue counter(s) at the start of a run workspace
 constexpr int kBinW = 8;              // int64 words per depth bin of the reduction
 constexpr int kEscMaxBins = 512;      // escape-path bins; 6 KB of LDS leaves four walk workgroups per CU
-// The single-run walk stages its deposits in the plane layout (three tables) where
-// those fit in this many bytes, else in the line layout (one table).  Memory-side
-// atomics keep their full rate while the tally stays within the 256 MiB
-// Infinity Cache.
+// A walk stages its deposits in the plane layout (three tables) where those fit in
+// this many bytes, else in the line layout (one table): tripled, the 256^3 tally
+// stays within the 256 MiB Infinity Cache, beyond which memory-side atomics slow
+// down.
 #ifndef MC_PLANE_STAGE_MAX_BYTES
 #define MC_PLANE_STAGE_MAX_BYTES (192ull << 20)
 #endif
