@@ -337,7 +337,7 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
 
 /*
  * Roofline probe (measurement only, not part of the walk): n_ops random scatter
- * operations over a device table of n_entries int64 (a power of two, >= 64), spread
+ * operations over a device table of n_entries int64 (a multiple of 64), spread
  * over waves_per_cu resident waves per compute unit (0: 16; else a multiple of 4 in
  * [4, 32]).  mode 0: device-scope 64-bit atomic add (what the walk's fluence
  * deposit does); 1: workgroup-scope 64-bit atomic add; 2: plain 64-bit store;

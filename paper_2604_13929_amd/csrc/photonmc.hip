@@ -706,8 +706,9 @@ __global__ void k_grad_finalize(const unsigned long long *__restrict__ grad, con
 
 // ---------------------------------------------------------------------------
 // Roofline probe: random 64-bit scatter-adds, the walk's deposit pattern
-// without the walk.  Addresses come from a 64-bit mixer of (thread, i); the
-// table size is a power of two.
+// without the walk.  Addresses come from a 64-bit mixer of (thread, i), scaled
+// to the table (a multiple of 64 entries) by the high half of a 64 x 64-bit
+// product.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t mix64(uint64_t x)
 {
@@ -718,14 +719,17 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x)
     return x ^ (x >> 31);
 }
 
+// A uniform pick in [0, units) from 64 random bits.
+__device__ __forceinline__ uint64_t pick(uint64_t x, uint64_t units) { return __umul64hi(x, units); }
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_probe(unsigned long long *__restrict__ table, uint64_t mask, uint64_t per_thread)
+__global__ __launch_bounds__(256) void k_probe(unsigned long long *__restrict__ table, uint64_t n, uint64_t per_thread)
 {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t wave = t >> 6, lane = t & 63;
     unsigned long long sink = 0;   // the returning modes use what the atomics return
     for (uint64_t i = 0; i < per_thread; ++i) {
-        const uint64_t a = mix64(t * per_thread + i) & mask;
+        const uint64_t a = pick(mix64(t * per_thread + i), n);
         if (MODE == 0) {
             __hip_atomic_fetch_add(table + a, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else if (MODE == 1) {
@@ -738,13 +742,13 @@ __global__ __launch_bounds__(256) void k_probe(unsigned long long *__restrict__ 
             __hip_atomic_fetch_add(t32 + ((a << 1) | (i & 1)), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else if (MODE == 4) {
             // the 64 lanes of a wavefront hit 64 consecutive slots of one random block
-            const uint64_t blk = mix64(wave * per_thread + i) & (mask & ~63ull);
+            const uint64_t blk = pick(mix64(wave * per_thread + i), n / 64) * 64;
             __hip_atomic_fetch_add(table + blk + lane, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else if (MODE >= 5 && MODE <= 7) {
             // groups of G lanes hit G consecutive slots (G * 8 bytes) of a random aligned block
             constexpr uint64_t G = MODE == 5 ? 16 : (MODE == 6 ? 8 : 4);
             const uint64_t grp = (t >> (MODE == 5 ? 4 : (MODE == 6 ? 3 : 2)));
-            const uint64_t blk = mix64(grp * per_thread + i) & (mask & ~(G - 1));
+            const uint64_t blk = pick(mix64(grp * per_thread + i), n / G) * G;
             __hip_atomic_fetch_add(table + blk + (lane & (G - 1)), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else if (MODE == 8) {
             // 64-bit atomic add returning the old value, random slot
@@ -757,13 +761,13 @@ __global__ __launch_bounds__(256) void k_probe(unsigned long long *__restrict__ 
             // groups of 16 lanes on the 16 consecutive 32-bit slots of a random 64-byte line,
             // without (10) or with (11) the old value returned
             unsigned int *t32 = (unsigned int *)table;
-            const uint64_t blk = mix64((t >> 4) * per_thread + i) & (mask & ~7ull);
+            const uint64_t blk = pick(mix64((t >> 4) * per_thread + i), n / 8) * 8;
             unsigned int *p32 = t32 + 2 * blk + (lane & 15);
             if (MODE == 10) __hip_atomic_fetch_add(p32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             else sink += __hip_atomic_fetch_add(p32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             // groups of 8 lanes on one random 64-byte line, 64-bit, the old value returned
-            const uint64_t blk = mix64((t >> 3) * per_thread + i) & (mask & ~7ull);
+            const uint64_t blk = pick(mix64((t >> 3) * per_thread + i), n / 8) * 8;
             sink += __hip_atomic_fetch_add(table + blk + (lane & 7), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -1284,8 +1288,8 @@ int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mod
                      void *hip_stream)
 {
     clear_error();
-    if (!table || n_entries < 64 || (n_entries & (n_entries - 1)) != 0)
-        return fail(MC_EINVAL, "table must be non-NULL with a power-of-two entry count >= 64");
+    if (!table || n_entries < 64 || n_entries % 64 != 0)
+        return fail(MC_EINVAL, "table must be non-NULL with an entry count that is a multiple of 64");
     if (mode < 0 || mode > 12) return fail(MC_EINVAL, "mode must be in [0, 12]");
     if (waves_per_cu == 0) waves_per_cu = 16;
     if (waves_per_cu < 4 || waves_per_cu > 32 || waves_per_cu % 4)
@@ -1298,7 +1302,7 @@ int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mod
     const unsigned blocks = (unsigned)(threads / 256);
     hipStream_t s = (hipStream_t)hip_stream;
     unsigned long long *t = (unsigned long long *)table;
-    const uint64_t m = n_entries - 1;
+    const uint64_t m = n_entries;
     switch (mode) {
     case 0: hipLaunchKernelGGL(k_probe<0>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;
     case 1: hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(256), 0, s, t, m, per_thread); break;

@@ -298,6 +298,15 @@ def test_batch_escape_histogram_rejects_bad_arguments(lib):
     assert call(pm.McEscapeBins(1.0, 16, 0, 1, 1), batch=bad) == -1 and b"job 1" in lib.mc_last_error()
 
 
+def test_scatter_probe_rejects_bad_arguments(lib):
+    # refused before any HIP call: the table pointer is never touched
+    cases = [(None, 64, 0, 16, b"multiple of 64"), (1, 100, 0, 16, b"multiple of 64"), (1, 32, 0, 16, b"multiple of 64"),
+             (1, 192 << 17, 13, 16, b"mode"), (1, 192 << 17, 10, 6, b"waves_per_cu"), (1, 64, -1, 0, b"mode")]
+    for table, n, mode, w, needle in cases:
+        assert lib.mc_probe_scatter(table, n, 1 << 20, mode, w, None) == -1, (table, n, mode, w)
+        assert needle in lib.mc_last_error(), (table, n, mode, w)
+
+
 def test_missing_library_fails_loudly(tmp_path):
     """Without the HIP library the binding raises: there is no CPU fallback."""
     import subprocess
