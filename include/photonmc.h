@@ -421,8 +421,10 @@ int mc_run_batch_escape_histogram(const mc_job *jobs, int32_t n_jobs, int flags,
 
 /*
  * Find a fast launch shape for this batch by timed trials on a scaled-down copy
- * of it (about 2^22 photons per trial; coordinate descent over waves per CU,
- * block size, chunk and refill), store it in the tune cache and return it.
+ * of it (about 2^23 photons per trial; coordinate descent from the default shape
+ * over waves per CU, block size, chunk, refill and defer, a candidate taken only
+ * when over 1 % faster, and the result kept only if it beats the default again in
+ * two more trials), store it in the tune cache and return it.
  * Synchronises the stream.  Overwrites the jobs' tallies with meaningless
  * values (MC_EINVAL if a job accumulates).
  */

@@ -862,6 +862,9 @@ int make_job(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, 
     J->nyb = d.nyb;
     J->lnx = d.lnx;
     J->lny = d.lny;
+    const PlaneDims pd = plane_dims(vol->nx, vol->ny, vol->nz);
+    J->stage_off1 = pd.off1;
+    J->stage_off2 = pd.off2;
     const double mu_s = opt->mu_s, mu_a = opt->mu_a, mu_t = mu_s + mu_a;
     J->mu_t = mu_t;
     J->mu_s = mu_s;

@@ -68,6 +68,8 @@ struct Job {
     int32_t nxb, nyb;         // bricks along x and y
     int32_t lnx, lny;         // staging lines along x and y (line layout)
     int32_t stage_planes;     // 1: the staging tally is in the plane layout
+    uint32_t stage_off1;      // plane layout: first words of tables 1 and 2
+    uint32_t stage_off2;
     double mu_t;              // mu_s + mu_a of the solid, summed in FP64 on the host
     double mu_s;              // mu_s of the solid (the gradient walk's score)
     float g;
@@ -245,19 +247,33 @@ __device__ __forceinline__ uint32_t plane_table(R ux, R uy, R uz)
     return (ax <= ay && ax <= az) ? 0u : (ay <= az ? 1u : 2u);
 }
 
+// The plane layout's dimensions from a job: the table offsets are stored in it
+// (the batch reads its jobs from LDS, per lane).
+__host__ __device__ __forceinline__ PlaneDims plane_dims_of(const Job &J)
+{
+    PlaneDims P;
+    P.px = ((uint32_t)J.nx + 3u) >> 2;
+    P.py = ((uint32_t)J.ny + 3u) >> 2;
+    P.pz = ((uint32_t)J.nz + 3u) >> 2;
+    P.off1 = J.stage_off1;
+    P.off2 = J.stage_off2;
+    P.words = 0;   // unused here
+    return P;
+}
+
 // The staging word of a photon's deposit in its current voxel.
 template <typename R>
 __device__ __forceinline__ uint32_t stage_word(const Job &J, const Photon<R> &p)
 {
     if (J.stage_planes)
-        return plane_index(plane_dims(J.nx, J.ny, J.nz), J.nx, J.ny, plane_table(p.ux, p.uy, p.uz), p.ix, p.iy, p.iz);
+        return plane_index(plane_dims_of(J), J.nx, J.ny, plane_table(p.ux, p.uy, p.uz), p.ix, p.iy, p.iz);
     return stage_index(J.lnx, J.lny, p.ix, p.iy, p.iz);
 }
 
 // The voxel, as an index of the [nz][ny][nx] tally, of a plane-layout word.
 __host__ __device__ __forceinline__ uint64_t plane_voxel(const Job &J, uint32_t idx)
 {
-    const PlaneDims P = plane_dims(J.nx, J.ny, J.nz);
+    const PlaneDims P = plane_dims_of(J);
     const uint32_t t = idx < P.off1 ? 0u : (idx < P.off2 ? 1u : 2u);
     const uint32_t r = idx - (t == 0u ? 0u : (t == 1u ? P.off1 : P.off2));
     const uint32_t line = r >> 4, hi = (r >> 2) & 3u, lo = r & 3u;

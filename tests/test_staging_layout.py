@@ -29,6 +29,7 @@ static int check(int nx, int ny, int nz)
     J.lnx = (nx + 1) / 2; J.lny = (ny + 1) / 2;
     const int lnz = (nz + 3) / 4;
     const PlaneDims P = plane_dims(nx, ny, nz);
+    J.stage_off1 = P.off1; J.stage_off2 = P.off2;   // as the host fills a job
     if (P.words % 16 || P.off1 % 16 || P.off2 % 16) { printf("tables not whole lines\n"); return 1; }
     const uint64_t first[4] = {0, P.off1, P.off2, P.words};
     // plane layout
