@@ -288,6 +288,29 @@ def test_oversize_job_takes_the_direct_path():
     torch.cuda.empty_cache()
 
 
+def test_batch_mixes_plane_and_line_layouts():
+    """A job whose three plane tables exceed 192 MiB (384 x 384 x 360 voxels: 3 x 53 M words) but
+    whose line-layout tally fits the log's 26-bit indices stages in lines, beside jobs staged in
+    planes, in one logged launch; every job equals its plain run bit for bit."""
+    banner("batch mixing a line-layout job (384x384x360) with plane-layout jobs == plain runs")
+    g = torch.Generator(device="cuda").manual_seed(6)
+    big = (torch.rand((360, 384, 384), generator=g, device="cuda") < 0.7).to(torch.uint8)
+    assert 3 * 384 * 384 * 360 * 4 > 192 * 2 ** 20          # planes do not fit
+    assert 192 * 192 * 90 * 16 <= 2 ** 26                    # lines fit a log index
+    small = [torch.from_numpy(inputs.spinodal_mask(n, n + 3, n - 2, 8.0, 0.7, seed=7 + n)).cuda() for n in (17, 30)]
+    jobs = [pm.BatchJob(small[0], pm.Optics(f32(0.8), f32(0.02), f32(0.6)), 6000, seed=20260809, stream_id=1),
+            pm.BatchJob(big, pm.Optics(f32(0.5), f32(0.01), f32(0.7)), 20000, seed=20260809, stream_id=0),
+            pm.BatchJob(small[1], pm.Optics(f32(0.4), f32(0.005), f32(0.9)), 9000, seed=20260809, stream_id=2)]
+    b = pm.run_batch(jobs, tune=pm.Tune(256, 16, 256, 16))
+    torch.cuda.synchronize()
+    for k, j in enumerate(jobs):
+        r, _ = _plain(j)
+        assert torch.equal(b.results[k].fluence, r.fluence), k
+        assert torch.equal(b.results[k].scalars, r.scalars), k
+    del b, big
+    torch.cuda.empty_cache()
+
+
 # job 1 (5000 photons) bins paths of 4 voxels and more into its last bin; job 3 has one photon
 ESC_BINS = [(1.5, 96), (0.25, 16), None, (0.5, 512), (3.0, 1), (1.5, 96)]
 
