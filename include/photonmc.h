@@ -67,14 +67,16 @@ extern "C" {
 /* flags */
 #define MC_ACCUMULATE 1     /* add to the tallies instead of zeroing them first */
 #define MC_TIMED 2          /* time the walk kernel with HIP events on the run's stream (mc_walk_elapsed_ms) */
-#define MC_FP64 4           /* geometry and scattering in FP64 instead of FP32 (reference transport) */
+#define MC_FP64 4           /* geometry and scattering in FP64 instead of FP32 (reference transport); its
+                               walk is bound by the VALU, so it stages deposits in the line layout, whose
+                               index costs less VALU work than the plane layout's */
 #define MC_DIRECT_DEPOSIT 8 /* one atomic per voxel visit into the caller's tally, not the line-coalesced
                                deposit log into a staging tally of uint32 words (the log is used when that
                                staging tally has <= 2^32 words) */
 #define MC_LINE_STAGING 16  /* stage the logged deposits in one table of 2 x 2 x 4-voxel lines even where
                                the three tables of 4 x 4-voxel planes fit (the workspace sizes allow for
                                the planes; the two layouts give identical tallies); for mc_run_batch,
-                               in every job */
+                               in every job.  Implied by MC_FP64. */
 
 #define MC_DEPOSIT_QUANTUM 256 /* Q31 units: every tally value is a multiple of it */
 #define MC_GRAD_FIXED_BITS 20  /* mc_grad's score bins count units of 2^-20 Q31 weight x voxel */

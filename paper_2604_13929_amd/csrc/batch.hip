@@ -391,7 +391,7 @@ struct Prepared {
     bool planes[MC_MAX_BATCH_JOBS] = {};   // caller's job index -> staged in the plane layout
 };
 
-// MC_LINE_STAGING in flags keeps every job's staging tally in the line layout.
+// MC_LINE_STAGING or MC_FP64 in flags keeps every job's staging tally in the line layout.
 int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, int flags, Prepared *P)
 {
     if (!jobs || n < 1 || n > MC_MAX_BATCH_JOBS)
@@ -430,7 +430,7 @@ int prepare(const mc_job *jobs, int32_t n, char *ws, size_t ws_bytes, int flags,
         J.bricks = (const uint64_t *)(ws + P->L.bricks_off[i]);
         J.fluence = jb.fluence;
         J.stage = P->L.logged ? (uint32_t *)(ws + P->L.stage_off[i]) : nullptr;
-        J.stage_planes = P->L.logged && P->L.planes[i] && !(flags & MC_LINE_STAGING);
+        J.stage_planes = P->L.logged && P->L.planes[i] && !(flags & (MC_LINE_STAGING | MC_FP64));
         P->planes[i] = J.stage_planes != 0;
         J.scalars = jb.scalars;
         J.queue_begin = q;

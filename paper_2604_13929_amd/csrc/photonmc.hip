@@ -1068,7 +1068,7 @@ int run_walk(const mc_volume *vol, Job J, int flags, const mc_tune &t, char *ws,
         if (esc && (rc = fill((int64_t *)esc->n, (uint64_t)esc->nbins, s))) return rc;
     }
     // the staging words as int64 pairs: a line is 16 words, so the count is even
-    const bool planes = d.planes && !(flags & MC_LINE_STAGING);
+    const bool planes = d.planes && !(flags & (MC_LINE_STAGING | MC_FP64));
     if (logged && (rc = fill((int64_t *)stage, (planes ? d.stage_words : d.line_words) / 2, s))) return rc;
     if ((rc = fill((int64_t *)queue, kHeaderBytes / 8, s))) return rc;
     if ((rc = pack(vol, bricks, s))) return rc;

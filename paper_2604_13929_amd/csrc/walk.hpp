@@ -62,7 +62,7 @@ __device__ __forceinline__ int escape_path_bin(double pv, double width, int nbin
 struct Job {
     const uint64_t *bricks;   // 4x4x4 bit bricks, 1 = pore
     int64_t *fluence;         // [nz][ny][nx]
-    uint32_t *stage;          // staging tally of the logged deposits (lines of 2x2x4 words), or NULL
+    uint32_t *stage;          // staging tally of the logged deposits (plane or line layout), or NULL
     int64_t *scalars;         // [MC_NSCALARS]
     int32_t nx, ny, nz;
     int32_t nxb, nyb;         // bricks along x and y

@@ -332,8 +332,9 @@ def test_staging_layouts_agree_bitwise():
     """The plane layout (three tables of 4 x 4-voxel planes, chosen per deposit by the
     photon's direction), the line layout (one table of 2 x 2 x 4-voxel lines) and one
     atomic per visit give the same tallies bit for bit, on a ragged volume whose sides
-    are no multiple of 4: FP32 and FP64 transport, the paper's boundary model, the
-    escape-path histogram run and the gradient walk."""
+    are no multiple of 4: FP32 transport (the FP64 transport always stages in lines,
+    here against one atomic per visit), the paper's boundary model, the escape-path
+    histogram run and the gradient walk."""
     banner("staging layouts: planes == lines == direct, 37 x 29 x 23")
     m = inputs.spinodal_mask(37, 29, 23, 12.0, 0.6, seed=5)
     d = dev(m)
