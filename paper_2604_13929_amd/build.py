@@ -32,18 +32,32 @@ def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def build_library(verbose: bool = False) -> str:
-    """Compile the library (always; the caller decides when)."""
-    cmd = [hipcc(), *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *SOURCES, "-o", LIB + ".tmp"]
+def _run(cmd: list[str]) -> str:
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = "packed-fp32-ops"
     errs = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if noise not in l)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + errs)
-    if verbose and errs.strip():
-        print(errs)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    return errs
+
+
+def build_library(verbose: bool = False, out: str = LIB, defines: tuple[str, ...] = ()) -> str:
+    """Compile the library (always; the caller decides when): each source to an object
+    in parallel under ``_build/``, then one link."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(ROOT, "_build", os.path.basename(out) + ".obj")
+    os.makedirs(objdir, exist_ok=True)
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"] + [f"-D{d}" for d in defines]
+    objs = [os.path.join(objdir, os.path.splitext(os.path.basename(src))[0] + ".o") for src in SOURCES]
+    cmds = [[hipcc(), *flags, f"-I{INCLUDE}", f"-I{CSRC}", "-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+        msgs = list(ex.map(_run, cmds))
+    msgs.append(_run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", out + ".tmp"]))
+    if verbose and any(m.strip() for m in msgs):
+        print("\n".join(m for m in msgs if m.strip()))
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

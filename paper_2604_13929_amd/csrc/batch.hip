@@ -105,15 +105,22 @@ struct BatchTallySink {
 };
 
 // Line-coalesced deposits for the batch: as the plain walk's log (8-byte
-// entries, a 16-iteration window, uint32 staging words in each job's own layout,
-// planes or lines, carries of wrapped words into the job's int64 tally), with the job index in the
-// top 6 bits of the 32-bit entry index, which leaves 26 bits for the word index
-// into the job's staging tally (the batch logs only when every job's staging
-// tally is that small).  A deposit of 2^32 quanta or more goes to the job's tally
-// directly.  The window's 33 KB of LDS per 256-thread workgroup, with the job
-// table and the per-job channels, still lets three workgroups share a CU.
+// entries, 16 slots per lane, issued transposed once some lane has filled its
+// slots, the run of entries in the line a photon still deposits into held back,
+// uint32 staging words in each job's own layout, planes or lines, carries of
+// wrapped words into the job's int64 tally), with the job index in the top 6 bits
+// of the 32-bit entry index, which leaves 26 bits for the word index into the
+// job's staging tally (the batch logs only when every job's staging tally is that
+// small).  A deposit of 2^31 quanta or more goes to the job's tally directly.  The
+// log's 33 KB of LDS per 256-thread workgroup, with the job table and the per-job
+// channels, still lets three workgroups share a CU.
 constexpr int kBLogK = 16;
 constexpr int kBLogStride = 65;
+#ifndef MC_LOG_HOLD
+#define MC_LOG_HOLD 6
+#endif
+constexpr int kBLogHold = MC_LOG_HOLD;
+constexpr uint32_t kBNoLine = 0xFFFFFFFFu;
 constexpr int kJobShift = 26;
 constexpr uint32_t kIdxMask = (1u << kJobShift) - 1u;
 constexpr uint64_t kBatchLogWords = 1ull << kJobShift;   // largest staging tally a logged batch job may have
@@ -121,27 +128,36 @@ constexpr uint64_t kBatchLogWords = 1ull << kJobShift;   // largest staging tall
 struct BatchLoggedSink {
     uint32_t *lidx;
     uint32_t *lval;
-    uint32_t slot;
+    uint32_t lane;
+    uint32_t head, count;       // this lane's ring of kBLogK slots
     uint32_t tag;               // job << kJobShift
     template <typename R> __device__ __forceinline__ void segment(const Photon<R> &, const Job &, R, bool) {}
     template <typename R> __device__ __forceinline__ void deflect(Photon<R> &, const Job &, R) {}
     template <typename R> __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
     {
         if (a != 0ull) {
-            if (a >> 32) {
+            if (a >> 31) {
                 __hip_atomic_fetch_add((unsigned long long *)(J.fluence + voxel_index(J, p)),
                                        (unsigned long long)a << kDepositShift, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                lidx[slot] = stage_word(J, p) | tag;
-                lval[slot] = (uint32_t)a;
+                const uint32_t s = log_slot<kBLogStride, kBLogK>(lane, head, count);
+                lidx[s] = stage_word(J, p) | tag;
+                lval[s] = (uint32_t)a;
+                ++count;
             }
         }
     }
 };
 
-__device__ __forceinline__ void flush_batch_log(uint32_t *lidx, uint32_t *lval, const Job *jobs, uint32_t lane)
+// Issue the wavefront's log; HOLD: the newest run of each lane's log that lies in
+// `line` (job bits included; kBNoLine: none) stays as the lane's ring.  The FP64
+// transport holds nothing.
+template <bool HOLD>
+__device__ __forceinline__ void flush_batch_log(uint32_t *lidx, uint32_t *lval, const Job *jobs, uint32_t lane,
+                                                uint32_t line, uint32_t &head, uint32_t &count)
 {
+    const uint32_t held = HOLD ? log_mark_run<kBLogStride, kBLogK, kBLogHold>(lidx, lval, lane, head, count, line) : 0u;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     // in two halves, each issuing its adds before it looks at what they returned
@@ -154,7 +170,7 @@ __device__ __forceinline__ void flush_batch_log(uint32_t *lidx, uint32_t *lval, 
             const uint32_t e = (lane % kBLogK) * kBLogStride + src;
             const uint32_t v = lval[e];
             old[i] = 0u;
-            if (v) {
+            if (v != 0u && (!HOLD || v < kLogHeld)) {
                 const uint32_t w = lidx[e];
                 old[i] = __hip_atomic_fetch_add(jobs[w >> kJobShift].stage + (w & kIdxMask), v, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
@@ -165,7 +181,7 @@ __device__ __forceinline__ void flush_batch_log(uint32_t *lidx, uint32_t *lval, 
             const uint32_t src = (uint32_t)(h + i) * (64 / kBLogK) + lane / kBLogK;
             const uint32_t e = (lane % kBLogK) * kBLogStride + src;
             const uint32_t v = lval[e];
-            if (v) {
+            if (v != 0u && (!HOLD || v < kLogHeld)) {
                 if (old[i] > 0xFFFFFFFFu - v) {
                     // the word wrapped: its lost 2^32 quanta go to the voxel's int64 word
                     const uint32_t w = lidx[e];
@@ -176,6 +192,14 @@ __device__ __forceinline__ void flush_batch_log(uint32_t *lidx, uint32_t *lval, 
                 lval[e] = 0u;
             }
         }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (HOLD) {
+        log_keep_run<kBLogStride, kBLogK, kBLogHold>(lval, lane, head, count, held);
+    } else {
+        head = 0u;
+        count = 0u;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -221,6 +245,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
                                                       const BatchEsc *__restrict__ esc)
 {
     constexpr int kWaves = BLOCK / 64;
+    constexpr bool kFP32 = std::is_same<R, float>::value;
     __shared__ Job s_jobs[MC_MAX_BATCH_JOBS];
     __shared__ unsigned long long acc[MC_MAX_BATCH_JOBS][MC_NSCALARS];
     __shared__ uint32_t s_lidx[LOGGED ? kWaves * kBLogK * kBLogStride : 1];
@@ -245,6 +270,9 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
     if constexpr (LOGGED) {
         sink.lidx = lidx;
         sink.lval = lval;
+        sink.lane = lane;
+        sink.head = 0u;
+        sink.count = 0u;
     }
     Photon<R> p;
     int32_t job = 0;
@@ -252,7 +280,6 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
     bool waiting = false;   // alive, at an interaction point, interaction not yet run
     uint64_t q_next = 0, q_end = 0;
     bool exhausted = false;
-    uint32_t iter = 0;
 
     auto retire = [&](int32_t ev, int32_t nz) {
         account_job(acc[job], p, ev, nz);
@@ -305,11 +332,7 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
             }
             if (exhausted && q_next >= q_end && !__any(alive)) break;
         }
-        // this iteration's log slot: a lane flushes at most once per iteration
-        if constexpr (LOGGED) {
-            sink.slot = (iter % kBLogK) * kBLogStride + lane;
-            sink.tag = (uint32_t)job << kJobShift;
-        }
+        if constexpr (LOGGED) sink.tag = (uint32_t)job << kJobShift;
         if (alive && !waiting) {
             const Job &J = s_jobs[job];
             const int32_t ev = advance<GENERAL>(p, J, sink);
@@ -330,11 +353,16 @@ __global__ __launch_bounds__(BLOCK) void k_walk_batch(const Job *__restrict__ jo
                 if (is_terminal(fin)) retire(fin, J.nz);
             }
         }
+        // a lane logs at most one deposit per iteration, so issue the log once some
+        // lane has filled it
         if constexpr (LOGGED) {
-            if (++iter % kBLogK == 0) flush_batch_log(lidx, lval, s_jobs, lane);
+            if (__ballot(sink.count >= (uint32_t)kBLogK) != 0ull)
+                flush_batch_log<kFP32>(lidx, lval, s_jobs, lane,
+                                       alive ? (stage_word(s_jobs[job], p) | sink.tag) >> 4 : kBNoLine, sink.head,
+                                       sink.count);
         }
     }
-    if constexpr (LOGGED) flush_batch_log(lidx, lval, s_jobs, lane);
+    if constexpr (LOGGED) flush_batch_log<kFP32>(lidx, lval, s_jobs, lane, kBNoLine, sink.head, sink.count);
     __syncthreads();
     for (int32_t i = threadIdx.x; i < n_jobs * MC_NSCALARS; i += BLOCK) {
         const unsigned long long v = acc[i / MC_NSCALARS][i % MC_NSCALARS];

@@ -88,7 +88,7 @@ __global__ void k_pack(const uint8_t *__restrict__ mask, int32_t nx, int32_t ny,
 
 // Staged quanta -> the caller's [nz][ny][nx] tally in Q31 units: F += S << shift.
 // The walk has already added there what the staging words could not hold (whole
-// 2^32-quanta carries and deposits of 2^32 quanta or more).
+// 2^32-quanta carries and deposits of 2^31 quanta or more).
 __global__ void k_unstage(const uint32_t *__restrict__ S, int64_t *__restrict__ F, int32_t nx, int32_t ny, int32_t nz,
                           int32_t lnx, int32_t lny, int32_t planes)
 {
@@ -122,46 +122,61 @@ struct DirectDeposit {
     }
 };
 
-// Fluence deposits logged in LDS, one slot per lane and iteration, for a staging
-// tally of uint32 quanta in lines of 16 words (one 64-byte line): the plane layout
-// where its three tables fit (see stage_word), else lines of 2x2x4 voxels;
-// every kLogK iterations the wavefront issues the log with lanes transposed so
-// that one atomic instruction carries kLogK successive deposits of each of
-// 64/kLogK lanes: deposits of one photon that fall in the same line travel as one
-// memory-side request.  A 2x2x4 line holds twice the voxels a line of int64 words would
-// (0.40 against 0.48 requests per photon-step over oracle trajectories of the
-// 256^3 workload), and 16-lane groups of 32-bit atomics on one line run at
+// Fluence deposits logged in LDS for a staging tally of uint32 quanta in lines of
+// 16 words (one 64-byte line): the plane layout where its three tables fit (see
+// stage_word), else lines of 2x2x4 voxels.  Each lane appends its deposits to its
+// own kLogK slots; once some lane has filled them, the wavefront issues the log
+// with lanes transposed, so that one atomic instruction carries the kLogK slots of
+// each of 64/kLogK lanes: deposits of one photon that fall in the same line travel
+// as one memory-side request.  A 2x2x4 line holds twice the voxels a line of int64
+// words would (0.40 against 0.48 requests per photon-step over oracle trajectories
+// of the 256^3 workload), and 16-lane groups of 32-bit atomics on one line run at
 // 26.5 G requests/s against 23.7 for 8-lane groups of 64-bit atomics.
+// A flush would cut the run of deposits a photon is still making into one line in
+// two requests.  So the newest entries of a lane's log that lie in the line of its
+// current voxel (its next deposit's line, unless an interaction turns it to
+// another plane table), up to kLogHold of them, are held back: they stay in the
+// lane's ring of slots and go out with the deposits that follow them.
 // A word cannot hold a voxel's sum: the flush reads back each word's previous
 // value and, where an add wrapped it past 2^32, adds the lost 2^32 quanta to the
 // caller's int64 tally, so the total stays exact (a quantum of 2^8 Q31 units makes
 // that about one carry per 2000 photon-steps).  A log entry is a 32-bit word
-// index and a 32-bit value; a photon's deposit in one voxel of 2^32 quanta or more
-// (512 voxel lengths at full weight) goes to the int64 tally directly.  At 16
-// iterations a 256-thread workgroup's log takes 33 KB, so four workgroups fit per
-// CU.
+// index and a value below 2^31 (its top bit marks a held entry); a photon's
+// deposit in one voxel of 2^31 quanta or more (256 voxel lengths at full weight)
+// goes to the int64 tally directly.  At 16 slots a 256-thread workgroup's log
+// takes 33 KB, so four workgroups fit per CU.
 #ifndef MC_LOG_K
 #define MC_LOG_K 16
 #endif
+#ifndef MC_LOG_HOLD
+#define MC_LOG_HOLD 6
+#endif
 constexpr int kLogK = MC_LOG_K;
+constexpr int kLogHold = MC_LOG_HOLD;   // 0: no entries held back
 static_assert(kLogK == 16 || kLogK == 32, "the transposed flush needs kLogK dividing 64, at least 16");
+static_assert(kLogHold >= 0 && kLogHold < kLogK, "a lane must keep a free slot after a flush");
 constexpr int kLogStride = 65;  // 64 lanes + 1: the transposed reads hit distinct banks
+constexpr uint32_t kNoLine = 0xFFFFFFFFu;
 
-struct LoggedDeposit {
-    uint32_t *lidx;             // this wavefront's log: [window][kLogStride]
+template <int kLogSlots>
+struct LoggedDepositK {
+    uint32_t *lidx;             // this wavefront's log: [slot][kLogStride]
     uint32_t *lval;
-    uint32_t slot;              // (iteration % window) * kLogStride + lane
+    uint32_t lane;
+    uint32_t head, count;       // this lane's ring of kLogSlots slots
     template <typename R>
     __device__ __forceinline__ void flush(const Job &J, const Photon<R> &p, uint64_t a)
     {
         if (a != 0ull) {
-            if (a >> 32) {
+            if (a >> 31) {
                 __hip_atomic_fetch_add((unsigned long long *)(J.fluence + voxel_index(J, p)),
                                        (unsigned long long)a << kDepositShift, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                lidx[slot] = stage_word(J, p);
-                lval[slot] = (uint32_t)a;
+                const uint32_t s = log_slot<kLogStride, kLogSlots>(lane, head, count);
+                lidx[s] = stage_word(J, p);
+                lval[s] = (uint32_t)a;
+                ++count;
             }
         }
     }
@@ -174,9 +189,17 @@ __device__ __forceinline__ void stage_carry(const Job &J, uint32_t idx)
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int K>
-__device__ __forceinline__ void flush_log(uint32_t *lidx, uint32_t *lval, const Job &J, uint32_t lane)
+// Issue the wavefront's log.  HOLD: each lane first marks the newest run of entries
+// in its log that lies in `line` (kNoLine: none), the issue skips them, and they
+// stay as the lane's whole ring.  The FP64 transport, bound by its VALU, holds
+// nothing.
+template <int K, bool HOLD>
+__device__ __forceinline__ void flush_log(uint32_t *lidx, uint32_t *lval, const Job &J, uint32_t lane,
+                                          uint32_t line, uint32_t &head, uint32_t &count)
 {
+    constexpr bool kHold = HOLD && kLogHold > 0;
+    const uint32_t held =
+        kHold ? log_mark_run<kLogStride, K, (kHold ? kLogHold : 1)>(lidx, lval, lane, head, count, line) : 0u;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     // in two halves, each issuing its adds before it looks at what they returned
@@ -190,18 +213,27 @@ __device__ __forceinline__ void flush_log(uint32_t *lidx, uint32_t *lval, const 
             const uint32_t e = (lane % K) * kLogStride + src;
             const uint32_t v = lval[e];
             old[i] = 0u;
-            if (v) old[i] = __hip_atomic_fetch_add(J.stage + lidx[e], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v != 0u && (!kHold || v < kLogHeld))
+                old[i] = __hip_atomic_fetch_add(J.stage + lidx[e], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
 #pragma unroll
         for (int i = 0; i < K / 2; ++i) {
             const uint32_t src = (uint32_t)(h + i) * (64 / K) + lane / K;
             const uint32_t e = (lane % K) * kLogStride + src;
             const uint32_t v = lval[e];
-            if (v) {
+            if (v != 0u && (!kHold || v < kLogHeld)) {
                 if (old[i] > 0xFFFFFFFFu - v) stage_carry(J, lidx[e]);
                 lval[e] = 0u;
             }
         }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (kHold) {
+        log_keep_run<kLogStride, K, (kHold ? kLogHold : 1)>(lval, lane, head, count, held);
+    } else {
+        head = 0u;
+        count = 0u;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -342,11 +374,11 @@ struct EscHist {
 // (escape, weight 0, roulette, or the step cap), and a waiting lane is served
 // at the latest once no lane can advance, so every wavefront exits.
 template <bool GRAD, bool LOGGED> struct SinkOf {
-    using Deposit = typename std::conditional<LOGGED, LoggedDeposit, DirectDeposit>::type;
+    using Deposit = typename std::conditional<LOGGED, LoggedDepositK<GRAD ? 16 : kLogK>, DirectDeposit>::type;
     using type = typename std::conditional<GRAD, GradSink<Deposit>, TallySink<Deposit>>::type;
 };
 
-// LOGGED: deposits go through the log into J.stage (see LoggedDeposit).  GENERAL: the
+// LOGGED: deposits go through the log into J.stage (see LoggedDepositK).  GENERAL: the
 // step that also knows the paper's boundary model (see walk.hpp).
 // ESC: also bin the in-pore path of every escaping photon (EscHist).
 template <int BLOCK, typename R, bool GRAD, bool LOGGED, bool GENERAL, bool ESC>
@@ -355,7 +387,8 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
                                                 const EscHist eh)
 {
     constexpr int kWaves = BLOCK / 64;
-    constexpr int K = GRAD ? 16 : kLogK;   // log window (the gradient bins share the LDS)
+    constexpr int K = GRAD ? 16 : kLogK;   // log slots per lane (the gradient bins share the LDS)
+    constexpr bool kFP32 = std::is_same<R, float>::value;
     __shared__ unsigned long long acc[MC_NSCALARS];
     __shared__ uint32_t s_lidx[LOGGED ? kWaves * K * kLogStride : 1];
     __shared__ uint32_t s_lval[LOGGED ? kWaves * K * kLogStride : 1];
@@ -382,6 +415,9 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
     if constexpr (LOGGED) {
         sink.lidx = lidx;
         sink.lval = lval;
+        sink.lane = lane;
+        sink.head = 0u;
+        sink.count = 0u;
     }
     if constexpr (GRAD) {
         sink.bins = gbins;
@@ -395,7 +431,6 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
     uint64_t q_next = 0, q_end = 0;
     bool exhausted = false;
     const uint64_t total = J.n_photons;
-    uint32_t iter = 0;
 
     auto retire = [&](int32_t ev) {
         account(acc, p, ev, J.nz);
@@ -435,9 +470,6 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
             }
             if (exhausted && q_next >= q_end && !__any(alive)) break;
         }
-        // this iteration's log slot: a lane flushes at most once per iteration (an
-        // advance that reaches an interaction point flushes nothing)
-        if constexpr (LOGGED) sink.slot = (iter % K) * kLogStride + lane;
         if (alive && !waiting) {
             const int32_t ev = advance<GENERAL>(p, J, sink);
             if (ev == EV_AT_INTERACTION) {
@@ -456,11 +488,15 @@ __global__ __launch_bounds__(BLOCK) void k_walk(const Job J, unsigned long long 
                 if (is_terminal(fin)) retire(fin);
             }
         }
+        // a lane logs at most one deposit per iteration (an advance that reaches an
+        // interaction point logs none), so issue the log once some lane has filled it
         if constexpr (LOGGED) {
-            if (++iter % K == 0) flush_log<K>(lidx, lval, J, lane);
+            if (__ballot(sink.count >= (uint32_t)K) != 0ull)
+                flush_log<K, kFP32>(lidx, lval, J, lane, alive ? stage_word(J, p) >> 4 : kNoLine, sink.head,
+                                    sink.count);
         }
     }
-    if constexpr (LOGGED) flush_log<K>(lidx, lval, J, lane);
+    if constexpr (LOGGED) flush_log<K, kFP32>(lidx, lval, J, lane, kNoLine, sink.head, sink.count);
     __syncthreads();
     if (threadIdx.x < MC_NSCALARS) {
         const unsigned long long v = acc[threadIdx.x];

@@ -310,6 +310,54 @@ __host__ __device__ __forceinline__ uint64_t stage_voxel(const Job &J, uint32_t 
     return (z * (uint64_t)J.ny + y) * (uint64_t)J.nx + x;
 }
 
+// The walks' deposit logs (LDS, one per wavefront): slot s of lane l is element
+// s * STRIDE + l of two arrays, a staging word index and a value.  A lane's slots
+// form a ring of K: its entries, oldest first, sit in slots (head + j) mod K for
+// j < count.  A logged value is below 2^31: the top bit marks an entry held back
+// from the next issue.
+constexpr uint32_t kLogHeld = 0x80000000u;
+
+// The slot of a lane's next entry.
+template <int STRIDE, int K>
+__device__ __forceinline__ uint32_t log_slot(uint32_t lane, uint32_t head, uint32_t count)
+{
+    return ((head + count) & (uint32_t)(K - 1)) * STRIDE + lane;
+}
+
+// Mark the newest entries of this lane's log that lie in `line` (the staging line of
+// its next deposit; kNoLine-like values match nothing), at most CAP of them, stopping
+// at the first that does not; returns how many.
+template <int STRIDE, int K, int CAP>
+__device__ __forceinline__ uint32_t log_mark_run(const uint32_t *lidx, uint32_t *lval, uint32_t lane, uint32_t head,
+                                                 uint32_t count, uint32_t line)
+{
+    uint32_t n = 0;
+    bool run = true;
+#pragma unroll
+    for (int k = 0; k < CAP; ++k) {
+        const uint32_t e = ((head + count - 1u - (uint32_t)k) & (uint32_t)(K - 1)) * STRIDE + lane;
+        run = run && (uint32_t)k < count && (lidx[e] >> 4) == line;
+        if (run) {
+            lval[e] |= kLogHeld;
+            ++n;
+        }
+    }
+    return n;
+}
+
+// After an issue that skipped them: unmark this lane's n held entries (the newest n
+// of its count) and make them the whole ring.
+template <int STRIDE, int K, int CAP>
+__device__ __forceinline__ void log_keep_run(uint32_t *lval, uint32_t lane, uint32_t &head, uint32_t &count,
+                                             uint32_t n)
+{
+#pragma unroll
+    for (int k = 0; k < CAP; ++k)
+        if ((uint32_t)k < n) lval[((head + count - 1u - (uint32_t)k) & (uint32_t)(K - 1)) * STRIDE + lane] &= ~kLogHeld;
+    head = (head + count - n) & (uint32_t)(K - 1);
+    count = n;
+}
+
 template <typename R>
 __device__ __forceinline__ double free_path(const Job &J, uint32_t r)
 {

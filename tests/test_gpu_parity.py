@@ -361,14 +361,14 @@ def test_staging_layouts_agree_bitwise():
 def test_large_per_voxel_deposits_bypass_the_log():
     """A dense, non-absorbing solid (mu_s = 3000 per voxel, g = 0, a 3x3x3 slab) keeps some
     photons scattering inside one voxel for hundreds of voxel lengths, so their deposit
-    in one stay reaches 2^32 quanta (2^40 Q31, 512 voxel lengths at full weight) and goes
-    to the int64 tally directly instead of through the 32-bit log; the tallies must still
-    equal one atomic per visit bit for bit.  The oracle shows such stays occur for these
-    photons (its largest single-stay deposit per photon).  A photon stops after 2^21 steps
-    (a stay of 512 voxel lengths is 1.5e6 steps), and each wavefront takes two photons, so
+    in one stay reaches 2^31 quanta (2^39 Q31, 256 voxel lengths at full weight) and goes
+    to the int64 tally directly instead of through the log, whose values stay below 2^31;
+    the tallies must still equal one atomic per visit bit for bit.  The oracle shows such
+    stays occur for these photons (its largest single-stay deposit per photon).  A photon
+    stops after 2^21 steps (a stay of 256 voxel lengths is 7.7e5 steps), and each wavefront takes two photons, so
     a run lasts about as long as its longest photon: the 2^24 default cap let one lane
     walk for tens of seconds."""
-    banner("deposits of 2^32 quanta or more in one stay: logged run == direct run")
+    banner("deposits of 2^31 quanta or more in one stay: logged run == direct run")
     m = inputs.homogeneous_mask(3, 3, 3)
     cap = 1 << 21
     opt = pm.Optics(f32(3000.0), 0.0, 0.0, max_steps=cap)
@@ -385,8 +385,8 @@ def test_large_per_voxel_deposits_bypass_the_log():
         print(f"[gpu]   fp64={fp64}: logged == direct", flush=True)
     _, oo = oracle.trace(m, opt.mu_s, opt.mu_a, opt.g, np.arange(n, dtype=np.uint64), SEED, max_rec=0,
                          max_steps=cap)
-    big = int((oo["max_visit"] >= 2.0 ** 32 * pm.DEPOSIT_QUANTUM).sum())
-    print(f"{big} of {n} photons deposit 2^32 quanta or more in one stay", flush=True)
+    big = int((oo["max_visit"] >= 2.0 ** 31 * pm.DEPOSIT_QUANTUM).sum())
+    print(f"{big} of {n} photons deposit 2^31 quanta or more in one stay", flush=True)
     assert big >= 3
 
 
