@@ -179,10 +179,13 @@ typedef struct {
     int32_t chunk;         /* photons a wavefront takes from the queue at once */
     int32_t refill;        /* refill a wavefront once this many of its lanes are idle */
     int32_t defer;         /* run a wavefront's interactions once this many of its lanes wait at an
-                              interaction point (or no lane can advance); 1: at once; at most 64 */
+                              interaction point (or no lane can advance); 1: at once; at most 64.
+                              Default 4 for the plain walk; 8 for the gradient walk and for the paper's
+                              boundary model, whose walks are bound by their VALU rather than by
+                              their deposit requests */
 } mc_tune;
 
-/* Fill *t with the library defaults. */
+/* Fill *t with the library defaults (those of the plain walk). */
 void mc_tune_default(mc_tune *t);
 
 /* Workspace (device bytes) an mc_run on this volume needs. */
@@ -423,7 +426,7 @@ int mc_run_batch_escape_histogram(const mc_job *jobs, int32_t n_jobs, int flags,
 
 /*
  * Find a fast launch shape for this batch by timed trials on a scaled-down copy
- * of it (about 2^23 photons per trial; coordinate descent from the default shape
+ * of it (about 2^25 photons per trial; coordinate descent from the default shape
  * over waves per CU, block size, chunk, refill and defer, a candidate taken only
  * when over 1 % faster, and the result kept only if it beats the default again in
  * two more trials), store it in the tune cache and return it.

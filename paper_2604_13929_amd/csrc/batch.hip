@@ -799,8 +799,9 @@ int autotune_prepared(const mc_job *jobs, const Prepared &P, char *ws, int flags
     for (size_t i = 0; i < P.table.size(); ++i)
         if (jobs[i].accumulate)
             return fail(MC_EINVAL, "job %zu accumulates: tuning trials would add to its tallies; pass a tune", i);
-    // trials of about 2^23 photons in total
-    const double fraction = std::min(1.0, 8388608.0 / (double)P.total_photons);
+    // trials of about 2^25 photons in total: long enough that the tail of a launch and
+    // the spread between trials do not decide the shape
+    const double fraction = std::min(1.0, 33554432.0 / (double)P.total_photons);
     Prepared S = scaled(P, fraction);
     int rc = enqueue_table(S, ws, s);
     if (rc) return rc;

@@ -939,10 +939,11 @@ int device_info(DeviceInfo *out)
     return MC_OK;
 }
 
-mc_tune resolve_tune(const mc_tune *t)
+mc_tune resolve_tune(const mc_tune *t, int32_t defer_default)
 {
     mc_tune r;
     mc_tune_default(&r);
+    if (defer_default > 0) r.defer = defer_default;
     if (t) {
         if (t->block > 0) r.block = t->block;
         if (t->waves_per_cu > 0) r.waves_per_cu = t->waves_per_cu;
@@ -1192,7 +1193,7 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
     if (!fluence || !scalars || !workspace) return fail(MC_EINVAL, "fluence, scalars and workspace must be non-NULL");
     const size_t need = mc_run_workspace_bytes(vol);
     if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    const mc_tune t = resolve_tune(tune);
+    const mc_tune t = resolve_tune(tune, J.paper ? kDeferVALUBound : 0);
     if ((rc = check_tune(t))) return rc;
     J.fluence = fluence;
     J.scalars = scalars;
@@ -1214,7 +1215,7 @@ int mc_run_escape_histogram(const mc_volume *vol, const mc_optics *opt, uint64_t
     if (!fluence || !scalars || !workspace) return fail(MC_EINVAL, "fluence, scalars and workspace must be non-NULL");
     const size_t need = mc_run_workspace_bytes(vol);
     if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    const mc_tune t = resolve_tune(tune);
+    const mc_tune t = resolve_tune(tune, J.paper ? kDeferVALUBound : 0);
     if ((rc = check_tune(t))) return rc;
     J.fluence = fluence;
     J.scalars = scalars;
@@ -1303,7 +1304,7 @@ int mc_grad(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, u
         return fail(MC_EINVAL, "fluence, scalars, grad_bins and workspace must be non-NULL");
     const size_t need = mc_grad_workspace_bytes(vol);
     if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    const mc_tune t = resolve_tune(tune);
+    const mc_tune t = resolve_tune(tune, kDeferVALUBound);
     if ((rc = check_tune(t))) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     char *ws = (char *)workspace;
