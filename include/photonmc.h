@@ -357,6 +357,16 @@ int mc_trace(const mc_volume *vol, const mc_optics *opt, const uint64_t *photon_
 int mc_probe_scatter(int64_t *table, uint64_t n_entries, uint64_t n_ops, int mode, int waves_per_cu,
                      void *hip_stream);
 
+/*
+ * Accuracy of the FP32 transport's hardware functions on the inputs the walk
+ * gives them (the interaction step of Sec. 2.5 / App. B: the azimuth's sine and
+ * cosine, the square roots of the deflection, the free path's logarithm), over all
+ * 2^24 uniforms, against FP64.  max_err: device double[4], written with the
+ * largest absolute sine error, absolute cosine error, relative logarithm error and
+ * relative square-root error.  Asynchronous on the stream.
+ */
+int mc_probe_math(double *max_err, void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Batched runs: many volumes of uneven size, porosity and optics in one
  * persistent launch.  Every job draws its own Philox streams (seed, stream_id),

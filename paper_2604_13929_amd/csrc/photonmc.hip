@@ -758,6 +758,36 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x)
 // A uniform pick in [0, units) from 64 random bits.
 __device__ __forceinline__ uint64_t pick(uint64_t x, uint64_t units) { return __umul64hi(x, units); }
 
+// The FP32 transport's square root, sine and cosine of a turn, and logarithm over
+// all 2^24 uniforms the walk draws (u = i 2^-24 for the turn and the square root,
+// (i + 1) 2^-24 for the logarithm), against FP64: the largest absolute sine and
+// cosine errors and relative logarithm and square-root errors, as the bit
+// patterns of non-negative doubles (ordered as integers), maxima over the grid.
+__global__ __launch_bounds__(256) void k_probe_math(unsigned long long *__restrict__ out)
+{
+    __shared__ double m[4][256];
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;   // the grid is exactly 2^24 threads
+    const float u = (float)i * 0x1.0p-24f, v = (float)(i + 1u) * 0x1.0p-24f;
+    float sf, cf;
+    r_sincos_turn(u, &sf, &cf);
+    double sd, cd;
+    r_sincos_turn((double)u, &sd, &cd);
+    const double ld = log((double)v), qd = sqrt((double)u);
+    double e[4];
+    e[0] = fabs((double)sf - sd);
+    e[1] = fabs((double)cf - cd);
+    e[2] = v < 1.0f ? fabs((double)r_log_unit(v) - ld) / fabs(ld) : fabs((double)r_log_unit(v));
+    e[3] = i ? fabs((double)r_sqrt(u) - qd) / qd : fabs((double)r_sqrt(u));
+    for (int j = 0; j < 4; ++j) m[j][threadIdx.x] = e[j];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < (unsigned)st)
+            for (int j = 0; j < 4; ++j) m[j][threadIdx.x] = fmax(m[j][threadIdx.x], m[j][threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) atomicMax(&out[threadIdx.x], (unsigned long long)__double_as_longlong(m[threadIdx.x][0]));
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_probe(unsigned long long *__restrict__ table, uint64_t n, uint64_t per_thread)
 {
@@ -1321,6 +1351,18 @@ int mc_grad(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, u
                            scalars, vol->nx, vol->ny, vol->nz, jac);
         HIP_TRY(hipGetLastError());
     }
+    return MC_OK;
+}
+
+int mc_probe_math(double *max_err, void *hip_stream)
+{
+    clear_error();
+    if (!max_err) return fail(MC_EINVAL, "max_err is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc = fill((int64_t *)max_err, 4, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_probe_math, dim3(1u << 16), dim3(256), 0, s, (unsigned long long *)max_err);
+    HIP_TRY(hipGetLastError());
     return MC_OK;
 }
 

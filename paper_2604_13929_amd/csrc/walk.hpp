@@ -128,6 +128,9 @@ __device__ __forceinline__ void r_sincos_turn(float u, float *s, float *c)
     *c = __builtin_amdgcn_cosf(u);
 }
 __device__ __forceinline__ void r_sincos_turn(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
+// ln u for u in (0, 1]
+__device__ __forceinline__ float r_log_unit(float u) { return __builtin_amdgcn_logf(u) * 0.693147180559945309f; }
+__device__ __forceinline__ double r_log_unit(double u) { return log(u); }
 __device__ __forceinline__ uint64_t r_to_u64(float x) { return __float2ull_rn(x); }
 __device__ __forceinline__ uint64_t r_to_u64(double x) { return __double2ull_rn(x); }
 template <typename R> __device__ __forceinline__ R r_inf() { return (R)kInf; }
@@ -377,10 +380,10 @@ __device__ __forceinline__ double free_path(const Job &J, uint32_t r)
     if (!(J.mu_t > 0.0)) return (double)kInf;
     if constexpr (std::is_same<R, float>::value) {
         const float u = (float)((r >> 8) + 1u) * 0x1.0p-24f;
-        return (double)(-(__builtin_amdgcn_logf(u) * 0.693147180559945309f) * r_rcp((float)J.mu_t));
+        return (double)(-r_log_unit(u) * r_rcp((float)J.mu_t));
     } else {
         const double u = (double)((r >> 8) + 1u) * 0x1.0p-24;
-        return -log(u) / J.mu_t;
+        return -r_log_unit(u) / J.mu_t;
     }
 }
 

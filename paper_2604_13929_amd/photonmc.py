@@ -108,6 +108,7 @@ _SIGS = {
     "mc_reduce_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_reduce": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "mc_probe_scatter": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _P]),
+    "mc_probe_math": (ctypes.c_int, [_P, _P]),
     "mc_grad_workspace_bytes": (ctypes.c_size_t, [_P]),
     "mc_grad": (ctypes.c_int, [_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]),
@@ -464,6 +465,16 @@ def probe_scatter(table: torch.Tensor, n_ops: int, mode: int = 0, waves_per_cu: 
     threads = torch.cuda.get_device_properties(dev).multi_processor_count * waves_per_cu * 64
     done = max(1, n_ops // threads) * threads
     return done / (start.elapsed_time(stop) * 1e-3)
+
+
+def probe_math(device: str | torch.device = "cuda:0") -> dict:
+    """mc_probe_math: the largest errors of the FP32 transport's hardware sine,
+    cosine (absolute), logarithm and square root (relative) over all 2^24 uniforms,
+    against FP64."""
+    L = load()
+    out = torch.empty(4, dtype=torch.float64, device=device)
+    _check(L.mc_probe_math(out.data_ptr(), _stream(out.device)), "mc_probe_math")
+    return dict(zip(("sin", "cos", "log", "sqrt"), out.cpu().tolist()))
 
 
 @dataclass

@@ -307,6 +307,10 @@ def test_scatter_probe_rejects_bad_arguments(lib):
         assert needle in lib.mc_last_error(), (table, n, mode, w)
 
 
+def test_math_probe_rejects_a_null_output(lib):
+    assert lib.mc_probe_math(None, None) == -1 and b"max_err" in lib.mc_last_error()
+
+
 def test_missing_library_fails_loudly(tmp_path):
     """Without the HIP library the binding raises: there is no CPU fallback."""
     import subprocess

@@ -111,6 +111,18 @@ def test_trajectories_fp64_transport_match_oracle(mask_m1):
     assert np.all(worst < 1e-5)
 
 
+def test_fp32_transport_functions_accuracy():
+    """The FP32 transport's hardware sine and cosine of a turn, logarithm and square
+    root, on every one of the 2^24 uniforms the walk draws, against FP64: within a
+    few FP32 ulps of 1 (2^-23 = 1.19e-7), so that a step restarted from the GPU's own
+    state stays within the stepwise bound the trajectory tests assert."""
+    banner("FP32 transport functions: hardware sin/cos/log/sqrt against FP64 on all 2^24 uniforms")
+    e = pm.probe_math()
+    print(f"[gpu] max errors: {e}", flush=True)
+    assert e["sin"] < 2.5e-7 and e["cos"] < 2.5e-7, e
+    assert e["log"] < 3e-7 and e["sqrt"] < 2e-7, e
+
+
 def test_trajectories_fp32_transport_stepwise(mask_m1):
     """FP32 transport: every one of the first 64 steps, restarted in the oracle from the
     GPU's own state at the start of the step, lands within 1e-5 voxel of the GPU's next
