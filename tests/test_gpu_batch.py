@@ -110,6 +110,56 @@ def test_batch_jobs_match_oracle(oracle_jobs):
               f"(oracle {tot['steps']})")
 
 
+def test_batch_paper_model_jobs_match_oracle():
+    """Jobs under the paper's boundary model in one FP32 batch (air pads, solid index
+    1.746 with Fresnel faces; lateral mirrors with a time gate of 300 voxels, periodic
+    faces with none), next to a plain job: per job, the globals (gated fraction
+    included) within 0.5 %, R/T/A within 0.5 % of the launched weight, steps within
+    0.1 %, and every voxel within 4 sigma of the oracle's spread over 32 photon batches."""
+    banner("batch mixing paper-model and plain jobs (FP32) vs the FP64 oracle, job by job")
+    spec = [(24, 20, 28, 0.7, 0.5, 0.01, 0.7, pm.LATERAL_MIRROR, 300.0, 5, 11),
+            (32, 16, 20, 0.6, 0.3, 0.02, 0.8, pm.LATERAL_PERIODIC, 0.0, 9, 4_321),
+            (20, 20, 20, 0.8, 0.8, 0.03, 0.6, None, 0.0, 17, 0)]
+    jobs = []
+    for i, (nx, ny, nz, phi, mus, mua, g, lateral, gate, sid, begin) in enumerate(spec):
+        m = inputs.spinodal_mask(nx, ny, nz, 8.0, phi, seed=300 + i)
+        if lateral is None:
+            opt = pm.Optics(f32(mus), f32(mua), f32(g))
+        else:
+            opt = pm.paper_optics(f32(mus), f32(mua), f32(g), n_solid=f32(1.746), lateral=lateral, gate=gate)
+        jobs.append((m, pm.BatchJob(torch.from_numpy(m).cuda(), opt, 40_000, seed=20260809, stream_id=sid,
+                                    photon_begin=begin)))
+    b = pm.run_batch([j for _, j in jobs], tune=pm.Tune(256, 16, 64, 8, 8))
+    torch.cuda.synchronize()
+    for k, (m, j) in enumerate(jobs):
+        o, n = j.optics, j.n_photons
+        kw = dict(boundary=o.boundary, lateral=o.lateral, n_solid=o.n_solid if o.n_solid else 1.0,
+                  gate=o.gate if o.gate > 0 else float("inf"))
+        ref = oracle.run(m, o.mu_s, o.mu_a, o.g, n, j.seed, photon_begin=j.photon_begin, stream_id=j.stream_id,
+                         nbatch=32, **kw)
+        tot = oracle.totals(ref)
+        Fb = ref["fluence"]
+        F_o = Fb.sum(axis=0)
+        e = est.estimators(F_o, m, n)
+        s = b.summary(k)
+        sc = b.results[k].scalar_dict()
+        assert sc["launched"] == n and s["closure_exact"] == 1.0 and sc["lost"] == 0, k
+        for key in ("phi3d", "phi1d", "phi_pore", "r"):
+            assert abs(s[key] - e[key]) <= 5e-3 * abs(e[key]), (k, key, s[key], e[key])
+        for key in ("R", "T", "A", "gated"):
+            assert abs(sc[key] - tot[key]) <= 5e-3 * n * W1, (k, key, sc[key], tot[key])
+        assert abs(sc["steps"] - tot["steps"]) <= 1e-3 * tot["steps"], k
+        if o.gate > 0:
+            assert tot["gated"] > 0, k                     # the gate cuts some photons
+        F_g = b.results[k].fluence.cpu().numpy().astype(np.float64)
+        sd = Fb.std(axis=0, ddof=1) * math.sqrt(Fb.shape[0])
+        on = sd > 0
+        assert np.all(np.abs(F_g - F_o)[on] <= 4 * sd[on]), k
+        assert np.all(F_g[~on] == F_o[~on]), k
+        print(f"job {k}: phi3d {s['phi3d']:.6f} (oracle {e['phi3d']:.6f}), gated {sc['gated'] / (n * W1):.4f} "
+              f"(oracle {tot['gated'] / (n * W1):.4f})", flush=True)
+
+
 def test_batch_fp64_jobs_equal_oracle(oracle_jobs):
     """FP64 transport in the batch: every integer channel of every job equals the
     oracle's, and the fluence equals it up to the per-segment rounding of deposits in
