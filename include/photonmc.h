@@ -180,9 +180,9 @@ typedef struct {
     int32_t refill;        /* refill a wavefront once this many of its lanes are idle */
     int32_t defer;         /* run a wavefront's interactions once this many of its lanes wait at an
                               interaction point (or no lane can advance); 1: at once; at most 64.
-                              Default 4 for the plain walk; 8 for the gradient walk and for the paper's
-                              boundary model, whose walks are bound by their VALU rather than by
-                              their deposit requests */
+                              Default 4 for the plain walk; 8 for the gradient walk, the paper's
+                              boundary model and the FP64 transport, whose walks are bound by their
+                              VALU rather than by their deposit requests */
 } mc_tune;
 
 /* Fill *t with the library defaults (those of the plain walk). */

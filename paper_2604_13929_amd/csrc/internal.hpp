@@ -56,8 +56,8 @@ int device_info(DeviceInfo *out);
 // The launch shape: the caller's fields where > 0, else the defaults, with defer_default
 // (when > 0) in place of the plain walk's default defer.
 mc_tune resolve_tune(const mc_tune *t, int32_t defer_default = 0);
-// The default defer of a walk: the gradient walk and the paper's boundary model are bound
-// by their VALU and run their interactions in larger groups.
+// The default defer of a walk: the gradient walk, the paper's boundary model and the FP64
+// transport are bound by their VALU and run their interactions in larger groups.
 constexpr int32_t kDeferVALUBound = 8;
 int check_tune(const mc_tune &t);
 

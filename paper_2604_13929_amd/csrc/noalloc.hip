@@ -60,7 +60,7 @@ int mc_run_noalloc(const mc_volume *vol, const mc_optics *opt, uint64_t photon_b
     if (d.nbricks > mc_run_noalloc_max_bricks())
         return fail(MC_ENOSPACE, "volume needs %llu mask bricks of 4x4x4 voxels; the fixed scratch holds %zu",
                     (unsigned long long)d.nbricks, mc_run_noalloc_max_bricks());
-    const mc_tune t = resolve_tune(tune, J.paper ? kDeferVALUBound : 0);
+    const mc_tune t = resolve_tune(tune, (J.paper || (flags & MC_FP64)) ? kDeferVALUBound : 0);
     if ((rc = check_tune(t))) return rc;
     void *ws = nullptr;
     if ((rc = scratch_address(&ws))) return rc;

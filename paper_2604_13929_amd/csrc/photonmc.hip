@@ -1223,7 +1223,7 @@ int mc_run(const mc_volume *vol, const mc_optics *opt, uint64_t photon_begin, ui
     if (!fluence || !scalars || !workspace) return fail(MC_EINVAL, "fluence, scalars and workspace must be non-NULL");
     const size_t need = mc_run_workspace_bytes(vol);
     if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    const mc_tune t = resolve_tune(tune, J.paper ? kDeferVALUBound : 0);
+    const mc_tune t = resolve_tune(tune, (J.paper || (flags & MC_FP64)) ? kDeferVALUBound : 0);
     if ((rc = check_tune(t))) return rc;
     J.fluence = fluence;
     J.scalars = scalars;
@@ -1245,7 +1245,7 @@ int mc_run_escape_histogram(const mc_volume *vol, const mc_optics *opt, uint64_t
     if (!fluence || !scalars || !workspace) return fail(MC_EINVAL, "fluence, scalars and workspace must be non-NULL");
     const size_t need = mc_run_workspace_bytes(vol);
     if (workspace_bytes < need) return fail(MC_ENOSPACE, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
-    const mc_tune t = resolve_tune(tune, J.paper ? kDeferVALUBound : 0);
+    const mc_tune t = resolve_tune(tune, (J.paper || (flags & MC_FP64)) ? kDeferVALUBound : 0);
     if ((rc = check_tune(t))) return rc;
     J.fluence = fluence;
     J.scalars = scalars;
