@@ -118,6 +118,21 @@ def test_m2a_full_run_properties(m2a):
     assert torch.equal(acc.fluence, whole.fluence) and torch.equal(acc.scalars, whole.scalars)
 
 
+def test_m2a_full_run_logged_equals_direct(m2a):
+    """At the benchmark's size and launch shape (256^3 phi 0.70, 1e8 photons, default
+    shape), the tally the walk stages through its deposit log (plane tables, held runs)
+    and the one-table line layout both equal one atomic per voxel visit, bit for bit."""
+    banner("256^3 phi 0.70, 1e8 photons: logged (planes) == logged (lines) == one atomic per visit")
+    _, d = m2a
+    n = 100_000_000
+    planes = pm.run(d, OPT, n, SEED)
+    direct = pm.run(d, OPT, n, SEED, direct=True)
+    assert torch.equal(planes.fluence, direct.fluence) and torch.equal(planes.scalars, direct.scalars)
+    del direct
+    lines = pm.run(d, OPT, n, SEED, line_staging=True)
+    assert torch.equal(planes.fluence, lines.fluence) and torch.equal(planes.scalars, lines.scalars)
+
+
 def _globals_at_1e7(d, mask_np, name):
     """The first 1e7 photon ids of the workload on the GPU (FP32 transport, default launch
     shape) and in the oracle (FP64, every host core): the global estimators within 0.5 %,
